@@ -1,0 +1,491 @@
+"""FP64 CPU oracle of the lattice-Boltzmann plasma-wakefield step.
+
+TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct definition that the GPU
+path is checked against.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark may import it; the product path never does.  It shares no code with the GPU path.
+
+What is computed follows G. Parise et al., "Lattice Boltzmann simulations of Plasma Wakefield
+Acceleration" (arXiv:2201.05473):
+
+  * cold-fluid plasma electrons, Sec. II, Eq. (2) (cold-fluid equations) rewritten in the
+    axisymmetric conservative form Eq. (3) with A = (n, n p_z, n p_r), u = c beta and the
+    Lorentz source F of Eq. (4);
+  * Maxwell's equations Eq. (5) on a Yee (FDTD) grid, with J_e = n beta_e and J_b = n_b beta_b;
+  * one D2Q9 lattice per transported scalar A (end of Sec. III), each evolved with the discrete
+    Boltzmann equation Eq. (6), the BGK collision Eq. (7), moments Eq. (8), the equilibrium
+    Eq. (9), the source Eq. (10), the diffusivity Eq. (12) and the axisymmetric target Eq. (13);
+  * boundary populations set to the equilibrium of the boundary moments, Eq. (14), with axis
+    symmetry and free flux (Sec. II, paragraph after Eq. (4));
+  * the moving window (Sec. II, end).
+
+Normalised units: t omega_p, x k_p, n / n_0, p / (m_e c), e E / (m_e c omega_p), e B / (m_e omega_p),
+c = 1.  In these units the electron momentum equation reads dp/dt = -(E + beta x B), Ampere's law
+dE/dt = curl B + n_e beta_e + n_b beta_b and Faraday's law dB/dt = -curl E.
+
+Readings of the paper (where it is silent, garbled or inconsistent; each is listed in the design doc):
+
+  R1  Eq. (9) is printed with coefficients 1/3, 1/18, 1/6; its zeroth and first moments then do
+      not reproduce Eq. (8).  The standard D2Q9 form with c_s^2 = 1/3 is used:
+      f_eq_i = w_i A (1 + 3 xi.u + 4.5 (xi.u)^2 - 1.5 u.u), consistent with Eq. (12).
+  R2  Faraday's law is printed as dB/dt = +curl E; the standard -curl E is used.
+  R4  The D2Q9 table (Fig. 2) is missing; the standard set and weights are used (XI, W below).
+  R5  Eq. (6) adds S_i per step while Eq. (10) defines S_i = w_i F with F a rate; the source per
+      step is w_i F dt (lattice units, dt_lattice = 1, tau dimensionless).
+  R6  The lattice advects with u* = beta * (c dt / dz), which is below c_s = 1/sqrt(3).
+  R7  The advecting velocity of all three lattices is beta_e computed from the moments of the
+      n and n p lattices (beta = p / gamma, p = A_1,2 / A_0); first moments are not used.
+  R8  (beta x B)_z = beta_r B_theta and (beta x B)_r = -beta_z B_theta (axisymmetric TM fields).
+  R9  The same scalar operator of Eq. (13) is used for all three lattices.
+  R10 The axisymmetric source is F_cyl = -A beta_r / r + D (dA/dr) / r, with dA/dr a central
+      difference of the previous step's post-collision moments.
+  R11 Ghost (boundary) populations are f_eq of ghost moments: axis mirror with parity (+, +, -),
+      copy of the adjacent cell at the outer and rear edges, unperturbed plasma at rest at the
+      window front (copy when the window is off).  Corners compose the z rule then the r rule.
+  R12 Radially half-shifted Yee grid: E_z at (i+1/2, j), E_r at (i, r=(j+1) dr), B_theta at
+      (i+1/2, r=(j+1) dr); E at integer times, B at half-integer times.
+  R13 The fluid is kicked with E^n and B^n = (B^{n-1/2} + B^{n+1/2}) / 2; the next Ampere update
+      uses the post-kick current (symplectic Euler coupling).
+  R15 The window moves one cell every m = 1/(c dt/dz) steps; the new front column is plasma at
+      rest at the background density with E = B = 0.
+  R17 Fields use zero-gradient ghosts at the outer, rear and front edges; E_r and B_theta vanish
+      on the axis.
+  R19 Where A_0 <= n_floor the momentum, velocity, current and Lorentz force are zero.
+  R23 Ramp shapes: linear n0 clamp((z - z_p)/L, 0, 1) and tanh n0 (1 + tanh(2 (z - z_p)/L - 1)) / 2.
+
+State after k completed steps (k = 0 is the initial state):
+    g  [3][9][nr][nz]   post-collision populations of step k-1 (raw values, not deviations)
+    M  [3][nr][nz]      their moments A*_k = A_k + dt F_k of step k-1
+    Ez [nr][nz]         E_z^{k-1} at (z_i + dz/2, r_j)
+    Er [nr][nz]         E_r^{k-1} at (z_i, (j+1) dr)
+    B  [nr][nz]         B_theta^{k-1/2} at (z_i + dz/2, (j+1) dr)
+    k, s                step count and window shift count; z_i = (s + i) dz, r_j = (j + 1/2) dr
+
+One step k -> k+1:
+    1  Ampere   E^k = E^{k-1} + dt (curl B^{k-1/2} + J*_face(M) + J_b(t_{k-1/2}))
+    2  Faraday  B^{k+1/2} = B^{k-1/2} - dt curl E^k
+    3  fluid    pull-stream, moments, fields at the site, Lorentz + axisymmetric source, BGK
+    4  window   shift by one cell when (k+1) is a multiple of m
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+DT = torch.float64
+
+# D2Q9 velocity set (xi_z, xi_r) and weights (R4; Fig. 2 of the paper is not available).
+XI = ((0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1))
+W = (4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0)
+# Mirror parity of (n, n p_z, n p_r) across the axis r = 0 (R11).
+PARITY = (1.0, 1.0, -1.0)
+
+
+def _t(x):
+    return x if isinstance(x, torch.Tensor) else torch.tensor(float(x), dtype=DT)
+
+
+class Params:
+    """Run parameters and the quantities derived from them.
+
+    The four parameters that gradients are taken with respect to (n0, ramp_len, sigma_r, nb)
+    are held as 0-dim float64 tensors, so autograd can differentiate the whole run."""
+
+    def __init__(self, cfg: dict, theta: dict | None = None):
+        self.nz, self.nr = int(cfg["nz"]), int(cfg["nr"])
+        self.h = float(cfg["dz"])
+        if abs(float(cfg["dr"]) - self.h) > 1e-12 * self.h:
+            raise ValueError("the lattice needs dz == dr")
+        self.lam = float(cfg["c_dt_over_dz"])
+        self.dt = self.lam * self.h
+        self.tau = float(cfg["tau"])
+        if not self.tau > 0.5:
+            raise ValueError("tau must exceed 1/2")
+        # Eq. (12) in lattice units, converted to normalised units: D = (tau - 1/2)/3 dz^2/dt.
+        self.D = (self.tau - 0.5) / 3.0 * self.h * self.h / self.dt
+        self.window = bool(cfg.get("moving_window", 0))
+        per = int(cfg.get("periodic", 0))
+        self.per_z, self.per_r = bool(per & 1), bool(per & 2)
+        self.fields_on = bool(cfg.get("fields_on", 1))
+        self.cyl_on = bool(cfg.get("cyl_on", 1))
+        if self.per_r and (self.fields_on or self.cyl_on):
+            raise ValueError("periodic r needs fields_on = 0 and cyl_on = 0")
+        if self.per_z and self.window:
+            raise ValueError("periodic z and the moving window exclude each other")
+        self.m = 0
+        if self.window:
+            self.m = int(round(1.0 / self.lam))
+            if abs(self.m * self.lam - 1.0) > 1e-9:
+                raise ValueError("the moving window needs 1/(c dt/dz) to be an integer")
+        self.ramp_kind = int(cfg.get("ramp_kind", 0))
+        self.ramp_start = float(cfg.get("ramp_start", 0.0))
+        self.sigma_z = float(cfg.get("sigma_z", 1.0))
+        self.zd0 = float(cfg.get("zd0", 0.0))
+        self.n_floor = float(cfg.get("n_floor", 1e-10))
+        theta = theta or {}
+        self.n0 = _t(theta.get("n0", cfg.get("n0", 1.0)))
+        self.ramp_len = _t(theta.get("ramp_len", cfg.get("ramp_len", 1.0)))
+        self.sigma_r = _t(theta.get("sigma_r", cfg.get("sigma_r", 1.0)))
+        self.nb = _t(theta.get("nb", cfg.get("nb", 0.0)))
+        # grid index vectors: j down the rows, i along the columns
+        self.jj = torch.arange(self.nr, dtype=DT)[:, None]
+        self.ii = torch.arange(self.nz, dtype=DT)[None, :]
+        self.r = (self.jj + 0.5) * self.h            # fluid rows and E_z rows
+        self.r_edge = (self.jj + 1.0) * self.h       # E_r and B_theta rows
+
+
+# ---------------------------------------------------------------------------------------------
+# Plasma profile and driver (Sec. IV set-up; ramp shapes are reading R23)
+# ---------------------------------------------------------------------------------------------
+
+def n_background(z, P: Params):
+    """Unperturbed plasma (ion) density at lab positions z."""
+    z = _t(z) if not isinstance(z, torch.Tensor) else z
+    if P.ramp_kind == 0:
+        return P.n0 * torch.ones_like(z)
+    x = (z - P.ramp_start) / P.ramp_len
+    if P.ramp_kind == 1:
+        return P.n0 * torch.clamp(x, 0.0, 1.0)
+    if P.ramp_kind == 2:
+        return P.n0 * 0.5 * (1.0 + torch.tanh(2.0 * x - 1.0))
+    raise ValueError("unknown ramp kind")
+
+
+def driver_density(z, r, t: float, P: Params):
+    """Rigid bi-Gaussian driver moving at c: n_b exp(-(z - z_d(t))^2/2 sz^2 - r^2/2 sr^2)."""
+    zd = P.zd0 + t
+    return P.nb * torch.exp(-(z - zd) ** 2 / (2.0 * P.sigma_z ** 2)) \
+        * torch.exp(-r ** 2 / (2.0 * P.sigma_r ** 2))
+
+
+def gauss_field(z, t: float, P: Params):
+    """Radial field of the driver alone from the discrete Gauss law (vacuum, E_z = 0).
+
+    Finite-volume form of (1/r) d(r E_r)/dr = -n_b on the rows j: E_r at r = (j+1) dr is
+    -(dr / (j+1)) * sum_{j' <= j} (j' + 1/2) n_b(r_j').  For beta_b = 1, B_theta = E_r."""
+    nb = driver_density(z, P.r, t, P)
+    cum = torch.cumsum((P.jj + 0.5) * nb, dim=0)
+    return -P.h * cum / (P.jj + 1.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Lattice pieces: equilibrium Eq. (9) (reading R1), velocity from moments (R7, R19)
+# ---------------------------------------------------------------------------------------------
+
+def equilibrium(A, uz, ur):
+    """Eq. (9) with the standard D2Q9 coefficients: [9][...] populations of scalar A at velocity u."""
+    usq = uz * uz + ur * ur
+    out = []
+    for (xz, xr), w in zip(XI, W):
+        cu = xz * uz + xr * ur
+        out.append(w * A * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq))
+    return torch.stack(out)
+
+
+def velocity(M, P: Params):
+    """beta_e = p / sqrt(1 + p^2), p = (A_1, A_2) / A_0 (Eq. (2) third line); zero where A_0 <= floor."""
+    n = M[0]
+    live = n > P.n_floor
+    safe = torch.where(live, n, torch.ones_like(n))
+    pz = torch.where(live, M[1] / safe, torch.zeros_like(n))
+    pr = torch.where(live, M[2] / safe, torch.zeros_like(n))
+    gam = torch.sqrt(1.0 + pz * pz + pr * pr)
+    return pz / gam, pr / gam, live
+
+
+def current(M, P: Params):
+    """Electron current J_e = n_e beta_e of Eq. (5) (sign absorbed as in the paper)."""
+    bz, br, _ = velocity(M, P)
+    return M[0] * bz, M[0] * br
+
+
+# ---------------------------------------------------------------------------------------------
+# Ghost ring (R11, R17)
+# ---------------------------------------------------------------------------------------------
+
+def padded_moments(M, P: Params, s: int):
+    """Moments on the ring i in [-1, nz], j in [-1, nr]: shape [3][nr+2][nz+2]."""
+    nr = P.nr
+    if P.per_z:
+        rear, front = M[:, :, -1:], M[:, :, :1]
+    else:
+        rear = M[:, :, :1]
+        if P.window:
+            zf = _t((s + P.nz) * P.h)
+            nf = n_background(zf, P)
+            col = torch.zeros(3, nr, 1, dtype=DT)
+            front = torch.cat([nf * torch.ones(1, nr, 1, dtype=DT), col[1:]], dim=0)
+        else:
+            front = M[:, :, -1:]
+    Mz = torch.cat([rear, M, front], dim=2)
+    if P.per_r:
+        below, above = Mz[:, -1:, :], Mz[:, :1, :]
+    else:
+        par = torch.tensor(PARITY, dtype=DT)[:, None, None]
+        below, above = Mz[:, :1, :] * par, Mz[:, -1:, :]
+    return torch.cat([below, Mz, above], dim=1)
+
+
+def padded_populations(g, Mp, P: Params):
+    """Populations on the ring [3][9][nr+2][nz+2]: the interior is g; a ghost position that is a
+    periodic image copies the wrapped populations, any other ghost is f_eq of the ghost moments
+    (Eq. (14))."""
+    bz, br, _ = velocity(Mp, P)
+    uz, ur = P.lam * bz, P.lam * br
+    gp = torch.stack([equilibrium(Mp[k], uz, ur) for k in range(3)])
+    gp = gp.clone()
+    gp[:, :, 1:-1, 1:-1] = g
+    if P.per_z:
+        gp[:, :, 1:-1, 0] = g[:, :, :, -1]
+        gp[:, :, 1:-1, -1] = g[:, :, :, 0]
+    if P.per_r:
+        gp[:, :, 0, 1:-1] = g[:, :, -1, :]
+        gp[:, :, -1, 1:-1] = g[:, :, 0, :]
+    if P.per_z and P.per_r:
+        gp[:, :, 0, 0] = g[:, :, -1, -1]
+        gp[:, :, 0, -1] = g[:, :, -1, 0]
+        gp[:, :, -1, 0] = g[:, :, 0, -1]
+        gp[:, :, -1, -1] = g[:, :, 0, 0]
+    return gp
+
+
+def _left(X, P: Params):
+    """X at column i-1: periodic wrap or zero-gradient copy at the rear edge."""
+    if P.per_z:
+        return torch.roll(X, 1, dims=-1)
+    return torch.cat([X[..., :1], X[..., :-1]], dim=-1)
+
+
+def _right(X, P: Params):
+    """X at column i+1: periodic wrap or zero-gradient copy at the front edge."""
+    if P.per_z:
+        return torch.roll(X, -1, dims=-1)
+    return torch.cat([X[..., 1:], X[..., -1:]], dim=-1)
+
+
+def _below_axis_zero(X):
+    """X at row j-1 with X = 0 below the first row (E_r and B_theta vanish on the axis)."""
+    return torch.cat([torch.zeros_like(X[:1]), X[:-1]], dim=0)
+
+
+def _above_copy(X):
+    """X at row j+1 with a zero-gradient copy beyond the outer edge."""
+    return torch.cat([X[1:], X[-1:]], dim=0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Field update: Eq. (5), Yee scheme (R2, R12, R13, R17)
+# ---------------------------------------------------------------------------------------------
+
+def field_update(Ez, Er, B, Mp, k: int, s: int, P: Params):
+    """Ampere then Faraday: returns (E_z^k, E_r^k, B^{k+1/2}) from (E^{k-1}, B^{k-1/2}, A*^{k-1})."""
+    h, dt = P.h, P.dt
+    jj = P.jj
+    # (curl B)_z = (1/r) d(r B)/dr at E_z points; the r = 0 edge flux vanishes.
+    curl_z = ((jj + 1.0) * B - jj * _below_axis_zero(B)) / ((jj + 0.5) * h)
+    # (curl B)_r = -dB/dz at E_r points
+    curl_r = -(B - _left(B, P)) / h
+    Jz, Jr = current(Mp, P)
+    Jz_face = 0.5 * (Jz[1:-1, 1:-1] + Jz[1:-1, 2:])
+    Jr_face = 0.5 * (Jr[1:-1, 1:-1] + Jr[2:, 1:-1])
+    zE = (s + P.ii + 0.5) * h
+    Jb = driver_density(zE, P.r, (k - 0.5) * dt, P)
+    Ez1 = Ez + dt * (curl_z + Jz_face + Jb)
+    Er1 = Er + dt * (curl_r + Jr_face)
+    # dB_theta/dt = dE_z/dr - dE_r/dz
+    B1 = B + dt * ((_above_copy(Ez1) - Ez1) / h - (_right(Er1, P) - Er1) / h)
+    return Ez1, Er1, B1
+
+
+def fields_at_sites(Ez1, Er1, B0, B1, P: Params):
+    """E^k and B^k = (B^{k-1/2} + B^{k+1/2})/2 averaged onto the fluid sites (R12, R13)."""
+    Ebar_z = 0.5 * (_left(Ez1, P) + Ez1)
+    Ebar_r = 0.5 * (_below_axis_zero(Er1) + Er1)
+    Bs = B0 + B1
+    Bs_l = _left(Bs, P)
+    Bbar = (Bs + Bs_l + _below_axis_zero(Bs) + _below_axis_zero(Bs_l)) / 8.0
+    return Ebar_z, Ebar_r, Bbar
+
+
+# ---------------------------------------------------------------------------------------------
+# Fluid update: Eqs. (6)-(10), (13), (14)
+# ---------------------------------------------------------------------------------------------
+
+def fluid_update(g, Mp, Ebar_z, Ebar_r, Bbar, P: Params):
+    """One collide-stream step of the three lattices; returns (g', A*)."""
+    nz, nr = P.nz, P.nr
+    gp = padded_populations(g, Mp, P)
+    # Eq. (6) in pull form: f_i(x) = g_i(x - xi_i)
+    f = torch.stack([torch.stack([gp[kk, q, 1 - xr:1 - xr + nr, 1 - xz:1 - xz + nz]
+                                  for q, (xz, xr) in enumerate(XI)]) for kk in range(3)])
+    A = f.sum(dim=1)                                    # Eq. (8), zeroth moments
+    bz, br, live = velocity(A, P)
+    uz, ur = P.lam * bz, P.lam * br                      # R6
+    n = A[0]
+    zero = torch.zeros_like(n)
+    # Eq. (4): F = -e n (E + c beta x B); R8 for the cross product
+    Fz = -(Ebar_z + br * Bbar)
+    Fr = -(Ebar_r - bz * Bbar)
+    F = [zero, torch.where(live, n * Fz, zero), torch.where(live, n * Fr, zero)]
+    if P.cyl_on:
+        # Eq. (13): -A u_r / r + D (dA/dr) / r, with the lagged radial gradient (R10)
+        dAdr = (Mp[:, 2:, 1:-1] - Mp[:, :-2, 1:-1]) / (2.0 * P.h)
+        F = [F[kk] - A[kk] * br / P.r + P.D * dAdr[kk] / P.r for kk in range(3)]
+    w = torch.tensor(W, dtype=DT)[:, None, None]
+    gnew, Mnew = [], []
+    for kk in range(3):
+        feq = equilibrium(A[kk], uz, ur)
+        # Eq. (7) BGK relaxation plus the source of Eq. (10) per step (R5)
+        gnew.append(f[kk] - (f[kk] - feq) / P.tau + w * P.dt * F[kk])
+        Mnew.append(A[kk] + P.dt * F[kk])
+    return torch.stack(gnew), torch.stack(Mnew)
+
+
+# ---------------------------------------------------------------------------------------------
+# State, step, run
+# ---------------------------------------------------------------------------------------------
+
+class State:
+    __slots__ = ("g", "M", "Ez", "Er", "B", "k", "s")
+
+    def __init__(self, g, M, Ez, Er, B, k=0, s=0):
+        self.g, self.M, self.Ez, self.Er, self.B, self.k, self.s = g, M, Ez, Er, B, k, s
+
+    def clone(self):
+        return State(self.g.clone(), self.M.clone(), self.Ez.clone(), self.Er.clone(),
+                     self.B.clone(), self.k, self.s)
+
+
+def initial_state(P: Params, n_pert=None, p_init=None) -> State:
+    """Plasma at its local equilibrium with density n_bg(z)(1 + n_pert) and momentum p_init,
+    the driver's discrete Gauss field E_r^{-1} at t = -dt and B^{-1/2} at t = -dt/2, E_z = 0."""
+    z = P.ii * P.h
+    nbg = n_background(z, P) * torch.ones(P.nr, 1, dtype=DT)
+    n = nbg if n_pert is None else nbg * (1.0 + torch.as_tensor(n_pert, dtype=DT))
+    if p_init is None:
+        A1 = torch.zeros_like(n)
+        A2 = torch.zeros_like(n)
+    else:
+        p = torch.as_tensor(p_init, dtype=DT)
+        A1, A2 = n * p[0], n * p[1]
+    M = torch.stack([n, A1, A2])
+    bz, br, _ = velocity(M, P)
+    g = torch.stack([equilibrium(M[kk], P.lam * bz, P.lam * br) for kk in range(3)])
+    zeros = torch.zeros(P.nr, P.nz, dtype=DT)
+    if P.fields_on:
+        Er = gauss_field(z, -P.dt, P)
+        B = gauss_field(z + 0.5 * P.h, -0.5 * P.dt, P)
+    else:
+        Er, B = zeros.clone(), zeros.clone()
+    return State(g, M, zeros.clone(), Er, B, 0, 0)
+
+
+def shift_due(k: int, P: Params) -> bool:
+    """Whether the window moves at the end of step k (R15)."""
+    return P.window and (k + 1) % P.m == 0
+
+
+def step(S: State, P: Params) -> State:
+    """Advance the state by one step (module docstring, steps 1-4)."""
+    Mp = padded_moments(S.M, P, S.s)
+    if P.fields_on:
+        Ez1, Er1, B1 = field_update(S.Ez, S.Er, S.B, Mp, S.k, S.s, P)
+        Ebz, Ebr, Bb = fields_at_sites(Ez1, Er1, S.B, B1, P)
+    else:
+        Ez1, Er1, B1 = S.Ez, S.Er, S.B
+        Ebz = Ebr = Bb = torch.zeros(P.nr, P.nz, dtype=DT)
+    g1, M1 = fluid_update(S.g, Mp, Ebz, Ebr, Bb, P)
+    s = S.s
+    if shift_due(S.k, P):
+        nf = n_background(_t((s + P.nz) * P.h), P)
+        w = torch.tensor(W, dtype=DT)[:, None, None]
+        fresh_g = torch.zeros(3, 9, P.nr, 1, dtype=DT)
+        fresh_g = torch.cat([(w * nf * torch.ones(1, P.nr, 1, dtype=DT))[None],
+                             fresh_g[1:]], dim=0)
+        fresh_M = torch.cat([nf * torch.ones(1, P.nr, 1, dtype=DT),
+                             torch.zeros(2, P.nr, 1, dtype=DT)], dim=0)
+        zc = torch.zeros(P.nr, 1, dtype=DT)
+        g1 = torch.cat([g1[..., 1:], fresh_g], dim=-1)
+        M1 = torch.cat([M1[..., 1:], fresh_M], dim=-1)
+        Ez1 = torch.cat([Ez1[:, 1:], zc], dim=-1)
+        Er1 = torch.cat([Er1[:, 1:], zc], dim=-1)
+        B1 = torch.cat([B1[:, 1:], zc], dim=-1)
+        s += 1
+    return State(g1, M1, Ez1, Er1, B1, S.k + 1, s)
+
+
+def run(cfg: dict, nsteps: int, n_pert=None, p_init=None, theta=None, callback=None):
+    """Initial state plus nsteps steps; returns (final state, Params)."""
+    P = Params(cfg, theta)
+    S = initial_state(P, n_pert, p_init)
+    for _ in range(nsteps):
+        S = step(S, P)
+        if callback is not None:
+            callback(S, P)
+    return S, P
+
+
+# ---------------------------------------------------------------------------------------------
+# Outputs and diagnostics
+# ---------------------------------------------------------------------------------------------
+
+def moments_out(S: State, P: Params):
+    """[3][nr][nz]: n, J_z, J_r of the last step's post-collision moments."""
+    Jz, Jr = current(S.M, P)
+    return torch.stack([S.M[0], Jz, Jr])
+
+
+def fields_out(S: State):
+    """[3][nr][nz]: E_z, E_r, B_theta of the state."""
+    return torch.stack([S.Ez, S.Er, S.B])
+
+
+def gauss_residual(S: State, P: Params):
+    """div_h E - (n_i - n_e - n_b) at the fluid sites with i >= 1 (reading R18): E^{k-1}, the
+    electron density A*_0, ions at n_bg(z), driver at t_{k-1}."""
+    h = P.h
+    jj = P.jj
+    div = (S.Ez - _left(S.Ez, P)) / h \
+        + ((jj + 1.0) * S.Er - jj * _below_axis_zero(S.Er)) / ((jj + 0.5) * h)
+    z = (S.s + P.ii) * h
+    rho = n_background(z, P) - S.M[0] - driver_density(z, P.r, (S.k - 1) * P.dt, P)
+    return (div - rho)[:, 1:]
+
+
+def diagnostics(S: State, P: Params) -> dict:
+    """FP64 sums: electron charge in the window, field energy, max |Gauss residual|,
+    max |u*| (lattice units) and whether any state value is non-finite."""
+    h = P.h
+    vol = 2.0 * math.pi * P.r * h * h
+    charge = (vol * S.M[0]).sum()
+    energy = 0.5 * (2.0 * math.pi * h * h * (P.r * S.Ez ** 2 + P.r_edge * S.Er ** 2
+                                             + P.r_edge * S.B ** 2)).sum()
+    bz, br, _ = velocity(S.M, P)
+    umax = P.lam * torch.sqrt(bz * bz + br * br).max()
+    G = gauss_residual(S, P)
+    finite = all(bool(torch.isfinite(x).all()) for x in (S.M, S.Ez, S.Er, S.B))
+    return dict(charge=float(charge), field_energy=float(energy),
+                gauss_max=float(G.abs().max()) if G.numel() else 0.0,
+                umax=float(umax), nonfinite=int(not finite), step=S.k, shifts=S.s)
+
+
+def objective(S: State, P: Params, z_behind: float):
+    """Witness objective: E_z on the first row, linearly interpolated in z at z_d - z_behind,
+    where z_d is the driver centre at the time level of the state's E (t_{k-1})."""
+    zstar = P.zd0 + (S.k - 1) * P.dt - z_behind
+    x = zstar / P.h - S.s - 0.5
+    i0 = int(math.floor(x))
+    if not (0 <= i0 < P.nz - 1):
+        raise ValueError("witness position outside the window")
+    w = x - i0
+    return (1.0 - w) * S.Ez[0, i0] + w * S.Ez[0, i0 + 1]
+
+
+def rel_err(x, ref) -> float:
+    """Max-norm error relative to the max-norm of the reference (reading R24)."""
+    x = torch.as_tensor(x, dtype=DT)
+    ref = torch.as_tensor(ref, dtype=DT)
+    den = float(ref.abs().max())
+    num = float((x - ref).abs().max())
+    return num / den if den > 0 else num

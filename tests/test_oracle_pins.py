@@ -1,0 +1,441 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the pin it implements; together they are chosen so that a plausible mistake in
+the oracle (a coefficient, a sign, an index, a time level, a boundary rule) fails at least one.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import lbm_oracle as O
+from oracle import scalar_ref as SR
+from oracle import units as U
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+F64 = torch.float64
+
+
+def _run(cfg, nsteps, n_pert=None, p_init=None):
+    P = O.Params(cfg)
+    S = O.initial_state(P, n_pert, p_init)
+    for _ in range(nsteps):
+        S = O.step(S, P)
+    return S, P
+
+
+# ---------------------------------------------------------------------------------------------
+# P_eq: equilibrium moments (Eq. (8), Eq. (9) under reading R1, D2Q9 set R4)
+# ---------------------------------------------------------------------------------------------
+
+def test_equilibrium_moments():
+    g = torch.Generator().manual_seed(0)
+    A = torch.rand(200, generator=g, dtype=F64) * 3
+    uz = (torch.rand(200, generator=g, dtype=F64) - 0.5) * 0.4
+    ur = (torch.rand(200, generator=g, dtype=F64) - 0.5) * 0.4
+    f = O.equilibrium(A, uz, ur)
+    xz = torch.tensor([x[0] for x in O.XI], dtype=F64)[:, None]
+    xr = torch.tensor([x[1] for x in O.XI], dtype=F64)[:, None]
+    assert torch.allclose(f.sum(0), A, rtol=0, atol=1e-14)
+    assert torch.allclose((xz * f).sum(0), A * uz, rtol=0, atol=1e-14)
+    assert torch.allclose((xr * f).sum(0), A * ur, rtol=0, atol=1e-14)
+    # second moments A (c_s^2 I + u u) with c_s^2 = 1/3 (consistent with Eq. (12))
+    assert torch.allclose((xz * xz * f).sum(0), A * (1 / 3 + uz * uz), rtol=0, atol=1e-14)
+    assert torch.allclose((xr * xr * f).sum(0), A * (1 / 3 + ur * ur), rtol=0, atol=1e-14)
+    assert torch.allclose((xz * xr * f).sum(0), A * uz * ur, rtol=0, atol=1e-14)
+    assert abs(sum(O.W) - 1.0) < 1e-15
+
+
+def test_printed_equilibrium_coefficients_violate_moments():
+    """Reading R1: Eq. (9) as printed (1/3, 1/18, 1/6) does not return A u as its first moment,
+    contradicting Eq. (8); this is why the standard coefficients are used."""
+    A, uz = 1.0, 0.1
+    f = [w * A * (1 + xz * uz / 3 + (xz * uz) ** 2 / 18 - uz * uz / 6) for (xz, _), w in zip(O.XI, O.W)]
+    first = sum(xz * fi for (xz, _), fi in zip(O.XI, f))
+    assert abs(first - A * uz) > 0.5 * A * uz
+
+
+# ---------------------------------------------------------------------------------------------
+# P_brute: vectorised oracle vs the scalar per-site loop
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [
+    dict(),
+    dict(moving_window=1),
+    dict(periodic=1),
+    dict(periodic=3, fields_on=0, cyl_on=0),
+    dict(ramp_kind=2, ramp_start=0.1, ramp_len=0.2, moving_window=1),
+    dict(ramp_kind=1, ramp_start=0.3, ramp_len=0.3, n_floor=1e-3),
+])
+def test_brute_force_agreement(variant):
+    cfg = wl.config(None, nz=8, nr=4, dz=0.1, dr=0.1, nb=0.3, sigma_z=0.2, sigma_r=0.15, zd0=0.4,
+                    noise_amp=0.05, seed=3, **variant)
+    P = O.Params(cfg)
+    S = O.initial_state(P, wl.density_perturbation(cfg), wl.random_momentum(cfg, 0.3, seed=2))
+    G = SR.Grid(cfg)
+    st = SR.from_tensors(S)
+    for _ in range(7):
+        S = O.step(S, P)
+        st = SR.step(G, st)
+    for a, b in zip(st[:5], (S.g, S.M, S.Ez, S.Er, S.B)):
+        assert float((torch.tensor(a, dtype=F64) - b).abs().max()) < 1e-14
+    assert (st[5], st[6]) == (S.k, S.s)
+
+
+# ---------------------------------------------------------------------------------------------
+# P_rest: a uniform plasma at rest with no driver is a fixed point (ghosts, axis, window)
+# ---------------------------------------------------------------------------------------------
+
+def test_rest_is_fixed_point():
+    cfg = wl.config(None, nz=32, nr=12, moving_window=1, n0=1.0, nb=0.0)
+    P = O.Params(cfg)
+    S0 = O.initial_state(P)
+    S = S0
+    for _ in range(12):
+        S = O.step(S, P)
+    assert S.s == 2
+    assert float((S.g - S0.g).abs().max()) < 1e-15
+    assert float((S.M - S0.M).abs().max()) < 1e-15
+    for X in (S.Ez, S.Er, S.B):
+        assert float(X.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------------------------------
+# P_mass: per-site post-collision moments, and global conservation when streaming is a permutation
+# ---------------------------------------------------------------------------------------------
+
+def test_post_collision_populations_sum_to_moments():
+    cfg = wl.config(None, nz=24, nr=10, nb=0.2, sigma_z=0.3, sigma_r=0.3, zd0=0.6, noise_amp=0.01,
+                    seed=4, moving_window=1)
+    S, _ = _run(cfg, 9, wl.density_perturbation(cfg), wl.random_momentum(cfg, 0.1))
+    assert float((S.g.sum(1) - S.M).abs().max()) < 1e-14
+
+
+def test_global_conservation_periodic():
+    cfg = wl.config(None, nz=20, nr=14, periodic=3, fields_on=0, cyl_on=0, noise_amp=0.2, seed=9)
+    P = O.Params(cfg)
+    S = O.initial_state(P, wl.density_perturbation(cfg), wl.random_momentum(cfg, 0.2, seed=5))
+    tot0 = S.M.sum(dim=(1, 2))
+    for _ in range(60):
+        S = O.step(S, P)
+    tot = S.M.sum(dim=(1, 2))
+    assert float((tot - tot0).abs().max()) < 1e-12 * float(tot0[0])
+    # and the density actually moved (the test is not vacuous)
+    assert float((S.M[0] - O.initial_state(P, wl.density_perturbation(cfg)).M[0]).abs().max()) > 1e-3
+
+
+# ---------------------------------------------------------------------------------------------
+# P_k0: uniform cold plasma oscillation, exact discrete map of the symplectic coupling
+# (Eqs. (4), (5), R2, R5, R8, R13)
+# ---------------------------------------------------------------------------------------------
+
+def test_plasma_oscillation_exact_map():
+    """p' = p - h E, E' = E + h beta(p'): with E^{-1} = 0 and p = eps the stored E^{k-1} after k
+    steps is eps sin(k theta) / sqrt(1 - h^2/4), theta = 2 asin(h/2) (relativistic terms O(eps^2))."""
+    cfg = wl.config(None, nz=16, nr=8, dz=0.05, dr=0.05, periodic=1, nb=0.0, tau=0.8)
+    eps = 1e-6
+    P = O.Params(cfg)
+    S = O.initial_state(P, None, wl.uniform_momentum(cfg, pz=eps))
+    h = P.dt
+    th = 2 * math.asin(h / 2)
+    worst = 0.0
+    for _ in range(400):
+        S = O.step(S, P)
+        ref = eps * math.sin(S.k * th) / math.sqrt(1 - h * h / 4)
+        worst = max(worst, float((S.Ez - ref).abs().max()) / eps)
+    assert worst < 1e-10
+    assert float(S.Er.abs().max()) < 1e-20 and float(S.M[2].abs().max()) < 1e-20
+
+
+# ---------------------------------------------------------------------------------------------
+# P_k: momentum diffusion with field coupling (Eq. (11) with D of Eq. (12))
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tau", [0.8, 1.2])
+def test_momentum_diffusion_wave(tau):
+    """p_z = eps sin(kz): continuum solution E_z = (eps/w) exp(-D k^2 t/2) sin(w t) sin(kz),
+    w = sqrt(1 - D^2 k^4/4); discretisation errors O((k dz)^2) and O(dt)."""
+    cfg = wl.config(None, nz=64, nr=4, dz=0.05, dr=0.05, periodic=1, nb=0.0, tau=tau)
+    eps = 1e-6
+    S, P = _run(cfg, 600, None, wl.sine_momentum_z(cfg, eps, 1))
+    kk = 2 * math.pi / (64 * 0.05)
+    om = math.sqrt(1 - P.D ** 2 * kk ** 4 / 4)
+    z = (torch.arange(64, dtype=F64) + 0.5) * 0.05
+    t = (S.k - 0.5) * P.dt
+    ref = eps / om * math.exp(-P.D * kk * kk * t / 2) * math.sin(om * t) * torch.sin(kk * z)
+    assert float((S.Ez[0] - ref).abs().max()) < 0.02 * float(ref.abs().max())
+
+
+# ---------------------------------------------------------------------------------------------
+# P_D: diffusivity of Eq. (12) from the variance growth of a bump (Cartesian, fields off)
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tau", [0.6, 0.8])
+def test_diffusivity(tau):
+    n = 96
+    cfg = wl.config(None, nz=n, nr=n, dz=0.05, dr=0.05, periodic=3, fields_on=0, cyl_on=0,
+                    nb=0.0, tau=tau)
+    P = O.Params(cfg)
+    zc, rc = 48 * 0.05, 48.5 * 0.05
+    S = O.initial_state(P, wl.gaussian_bump(cfg, 0.1, 0.2, 0.2, zc=zc, rc=rc))
+    z = torch.arange(n, dtype=F64) * 0.05
+    r = (torch.arange(n, dtype=F64) + 0.5) * 0.05
+
+    def variances(S):
+        d = S.M[0] - 1.0
+        m0 = d.sum()
+        return float((d * (z[None, :] - zc) ** 2).sum() / m0), float((d * (r[:, None] - rc) ** 2).sum() / m0)
+
+    snaps = {}
+    for k in range(1, 201):
+        S = O.step(S, P)
+        if k in (50, 200):
+            snaps[k] = variances(S)
+    span = 150 * P.dt
+    Dz = (snaps[200][0] - snaps[50][0]) / (2 * span)
+    Dr = (snaps[200][1] - snaps[50][1]) / (2 * span)
+    assert abs(Dz / P.D - 1) < 1e-6 and abs(Dr / P.D - 1) < 1e-6
+
+
+# ---------------------------------------------------------------------------------------------
+# P_cyl: axisymmetric diffusion term of Eq. (13) (reading R10)
+# ---------------------------------------------------------------------------------------------
+
+def test_cylindrical_diffusion():
+    """Radial Gaussian, uniform in z: delta n = a (s0^2/s^2) exp(-r^2/2 s^2), s^2 = s0^2 + 2 D t."""
+    cfg = wl.config(None, nz=4, nr=64, dz=0.05, dr=0.05, periodic=1, fields_on=0, cyl_on=1,
+                    nb=0.0, tau=0.8)
+    s0, a = 0.3, 0.1
+    S, P = _run(cfg, 300, wl.gaussian_bump(cfg, a, None, s0))
+    r = (torch.arange(64, dtype=F64) + 0.5) * 0.05
+    s2 = s0 * s0 + 2 * P.D * S.k * P.dt
+    ref = a * (s0 * s0 / s2) * torch.exp(-r * r / (2 * s2))
+    assert float((S.M[0, :, 0] - 1.0 - ref).abs().max()) < 0.01 * a
+    # without the cylindrical term the same run is the 1D (slab) solution, far from the reference
+    cfg0 = dict(cfg, cyl_on=0)
+    S0, _ = _run(cfg0, 300, wl.gaussian_bump(cfg0, a, None, s0))
+    assert float((S0.M[0, :, 0] - 1.0 - ref).abs().max()) > 0.05 * a
+
+
+def test_radial_flow_continuity():
+    """Uniform density with p_r = eps r: dn/dt = -(1/r) d(r n u_r)/dr = -2 eps away from the axis
+    (Eq. (3)); half of it comes from the -A u_r / r source."""
+    for cyl, rate in ((1, -2.0), (0, -1.0)):
+        cfg = wl.config(None, nz=4, nr=32, dz=0.05, dr=0.05, periodic=1, fields_on=0, cyl_on=cyl,
+                        nb=0.0, tau=0.8)
+        eps = 1e-4
+        S, P = _run(cfg, 20, None, wl.linear_radial_momentum(cfg, eps))
+        d = (S.M[0, 4:16, 0] - 1.0) / (S.k * P.dt) / eps
+        assert float((d - rate).abs().max()) < 0.01 * abs(rate)
+
+
+def test_axis_mirror_equivalence():
+    """Axis rule R11: a slab that is mirror-symmetric about r = 0 (n, n p_z even, n p_r odd), run
+    Cartesian and periodic over 2 nr rows, equals the half domain with the axis ghost after one
+    step from equilibrium (the ghost equilibrium then equals the mirrored population exactly)."""
+    nr, nz = 6, 10
+    half = wl.config(None, nz=nz, nr=nr, dz=0.1, dr=0.1, periodic=1, fields_on=0, cyl_on=0, nb=0.0)
+    rng = np.random.default_rng(3)
+    n_h = 0.2 * (rng.random((nr, nz)) - 0.5)
+    p_h = 0.2 * (rng.random((2, nr, nz)) - 0.5)
+    full = dict(half, nr=2 * nr, periodic=3)
+    n_f = np.concatenate([n_h[::-1], n_h])
+    p_f = np.concatenate([p_h[:, ::-1], p_h], axis=1)
+    p_f[1, :nr] *= -1.0
+    Sh, _ = _run(half, 1, n_h, p_h)
+    Sf, _ = _run(full, 1, n_f, p_f)
+    # rows below nr - 1 (the outer edge of the half domain reaches only its last row in one step)
+    assert float((Sh.M[:, :-1] - Sf.M[:, nr:-1]).abs().max()) < 1e-15
+    assert float((Sh.g[:, :, :-1] - Sf.g[:, :, nr:-1]).abs().max()) < 1e-15
+
+
+# ---------------------------------------------------------------------------------------------
+# P_divcurl: Yee operators incl. the axis (R12): div_h curl_h = 0
+# ---------------------------------------------------------------------------------------------
+
+def test_div_curl_identity():
+    cfg = wl.config(None, nz=20, nr=10, dz=0.1, dr=0.1, nb=0.0, periodic=1)
+    P = O.Params(cfg)
+    g = torch.Generator().manual_seed(1)
+    Ez, Er, B = (torch.randn(P.nr, P.nz, generator=g, dtype=F64) for _ in range(3))
+    M = torch.stack([1 + 0.1 * torch.randn(P.nr, P.nz, generator=g, dtype=F64),
+                     0.3 * torch.randn(P.nr, P.nz, generator=g, dtype=F64),
+                     0.3 * torch.randn(P.nr, P.nz, generator=g, dtype=F64)])
+    Mp = O.padded_moments(M, P, 0)
+    Ez1, Er1, _ = O.field_update(Ez, Er, B, Mp, 0, 0, P)
+    h, jj = P.h, P.jj
+
+    def div(Ez, Er):
+        return (Ez - torch.roll(Ez, 1, -1)) / h + \
+            ((jj + 1) * Er - jj * torch.cat([torch.zeros(1, P.nz, dtype=F64), Er[:-1]])) / ((jj + 0.5) * h)
+
+    Jz, Jr = O.current(Mp, P)
+    Jzf = 0.5 * (Jz[1:-1, 1:-1] + Jz[1:-1, 2:])
+    Jrf = 0.5 * (Jr[1:-1, 1:-1] + Jr[2:, 1:-1])
+    lhs = (div(Ez1, Er1) - div(Ez, Er)) / P.dt
+    rhs = div(Jzf, Jrf)
+    assert float((lhs - rhs).abs().max()) < 1e-10 * float(B.abs().max() / h)
+
+
+# ---------------------------------------------------------------------------------------------
+# P_vac: driver field in vacuum moves rigidly at c (Faraday sign R2, J_b, window kinematics)
+# ---------------------------------------------------------------------------------------------
+
+def test_vacuum_driver_field():
+    cfg = wl.config(None, nz=128, nr=48, dz=0.05, dr=0.05, moving_window=1, n0=0.0, nb=0.1,
+                    sigma_z=0.5, sigma_r=0.5, zd0=3.2, tau=0.8)
+    S, P = _run(cfg, 300)
+    z = (S.s + P.ii) * P.h
+    assert S.s == 60
+    assert O.rel_err(S.Er, O.gauss_field(z, (S.k - 1) * P.dt, P)) < 5e-3
+    assert O.rel_err(S.B, O.gauss_field(z + 0.5 * P.h, (S.k - 0.5) * P.dt, P)) < 5e-3
+    assert float(S.Ez.abs().max()) < 5e-3 * float(S.Er.abs().max())
+    assert float(S.M.abs().max()) == 0.0
+
+
+def test_comoving_fluid_cancels_radial_force():
+    """Lorentz force (Eq. (4), R8): in the driver's field (B_theta = E_r at beta_b = 1) a tenuous
+    fluid moving with beta_z -> 1 feels -(E_r - beta_z B_theta) = -(1 - beta_z) E_r; a fluid at
+    rest feels -E_r.  A sign error in the magnetic term would give (1 + beta_z) instead."""
+    out = {}
+    for pz in (0.0, 10.0):
+        cfg = wl.config(None, nz=96, nr=32, dz=0.05, dr=0.05, moving_window=1, n0=1e-9,
+                        n_floor=1e-15, nb=0.1, sigma_z=0.5, sigma_r=0.4, zd0=96 * 0.05 - 2.4)
+        S, P = _run(cfg, 100, None, wl.uniform_momentum(cfg, pz=pz))
+        i = int((P.zd0 + (S.k - 1) * P.dt) / P.h - S.s)
+        out[pz] = float((S.M[2] / S.M[0])[2:8, i].abs().max())
+    beta = 10 / math.sqrt(101)
+    assert out[0.0] > 1e-3
+    assert out[10.0] / out[0.0] < 3 * (1 - beta)
+
+
+# ---------------------------------------------------------------------------------------------
+# Initial state: discrete Gauss law (R18), perturbation, window
+# ---------------------------------------------------------------------------------------------
+
+def test_initial_gauss_law_exact():
+    cfg = wl.config("C1", noise_amp=0.0)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    G = O.gauss_residual(S, P)
+    assert float(G.abs().max()) < 1e-15
+    # the driver's field is really there
+    assert float(S.Er.abs().max()) > 1e-3
+
+
+def test_initial_perturbation_applied():
+    cfg = wl.config("C1")
+    P = O.Params(cfg)
+    pert = wl.density_perturbation(cfg)
+    S = O.initial_state(P, pert)
+    assert np.allclose(S.M[0].numpy(), 1.0 + pert, rtol=0, atol=1e-15)
+    assert np.abs(pert).max() <= 1e-6 and np.abs(pert).max() > 0.9e-6
+
+
+def test_ramp_profiles():
+    for kind in (1, 2):
+        cfg = wl.config(None, ramp_kind=kind, ramp_start=2.0, ramp_len=4.0, n0=1.5)
+        P = O.Params(cfg)
+        z = torch.tensor([0.0, 2.0, 4.0, 6.0, 100.0], dtype=F64)
+        n = O.n_background(z, P)
+        assert abs(float(n[2]) - 0.75) < 1e-15           # half density mid-ramp
+        assert abs(float(n[4]) - 1.5) < 1e-12            # plateau
+        assert float(n[0]) < 0.1 and float(n[1]) < 0.3   # (near) vacuum before the ramp
+        assert bool((n[1:] >= n[:-1]).all())
+    P = O.Params(wl.config(None, ramp_kind=1, ramp_start=2.0, ramp_len=4.0, n0=1.5))
+    assert float(O.n_background(torch.tensor(2.0, dtype=F64), P)) == 0.0
+
+
+def test_window_equals_fixed_domain():
+    """R15: a run with the moving window equals, column for column in the lab frame, a run on a
+    longer fixed domain, away from the rear edge (uniform plasma ahead, so the fresh columns are
+    what the fixed run holds there)."""
+    base = dict(dz=0.05, dr=0.05, nb=0.05, sigma_z=0.3, sigma_r=0.4, ramp_kind=0, tau=0.8)
+    cA = wl.config(None, nz=96, nr=24, moving_window=1, zd0=96 * 0.05 - 3.0, **base)
+    cB = wl.config(None, nz=116, nr=24, moving_window=0, zd0=96 * 0.05 - 3.0, **base)
+    SA, _ = _run(cA, 40)
+    SB, _ = _run(cB, 40)
+    s, lo = SA.s, 42
+    assert s == 8
+    for name in ("g", "M", "Ez", "Er", "B"):
+        a = getattr(SA, name)[..., lo:]
+        b = getattr(SB, name)[..., s + lo:s + 96]
+        assert float((a - b).abs().max()) <= 1e-14 * max(float(b.abs().max()), 1e-300)
+
+
+def test_objective_interpolates_witness_position():
+    cfg = wl.config(None, nz=64, nr=8, moving_window=1, zd0=2.5)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    S.k, S.s = 23, 4
+    zE = (S.s + P.ii + 0.5) * P.h
+    S.Ez = (0.3 * zE + 0.1) * torch.ones(P.nr, 1, dtype=F64)
+    zstar = P.zd0 + (S.k - 1) * P.dt - 1.0
+    assert abs(float(O.objective(S, P, 1.0)) - (0.3 * zstar + 0.1)) < 1e-14
+
+
+# ---------------------------------------------------------------------------------------------
+# P_lin: linear wake of a weak Gaussian driver (physics check, not parity)
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_linear_wake_closed_form():
+    """Cold-fluid linear theory: E_z(xi, r) = n_b R(r) int_xi^inf cos(x - xi) exp(-x^2/2 sz^2) dx,
+    R(r) = int_0^inf r' I0(r<) K0(r>) exp(-r'^2/2 sr^2) dr'.
+
+    The driver starts in vacuum and enters the plasma through a tanh ramp (a driver switched on
+    inside the plasma, or a short entrance, launches a forward-moving transient that travels with
+    it and only slowly falls behind); after 32 plasma periods of propagation at small diffusivity
+    the wake behind the driver is compared on the first two rows."""
+    from scipy import integrate, special
+    h, nz, nr = 0.1, 160, 48
+    zd0 = nz * h - 4.0
+    cfg = wl.config("C1", noise_amp=0.0, tau=0.51, nz=nz, nr=nr, dz=h, dr=h, moving_window=1,
+                    zd0=zd0, ramp_kind=2, ramp_start=zd0 + 2.0, ramp_len=2.0)
+    S, P = _run(cfg, 1600)
+    sz = sr = 0.5
+
+    def R_of(r):
+        f = lambda rp: rp * special.i0(min(r, rp)) * special.k0(max(r, rp)) * math.exp(-rp * rp / (2 * sr * sr))
+        return integrate.quad(f, 0, r, limit=200)[0] + integrate.quad(f, r, 12 * sr, limit=200)[0]
+
+    zd = P.zd0 + (S.k - 1) * P.dt
+    for j in (0, 5):
+        Rr = R_of((j + 0.5) * h)
+        amp = 0.01 * Rr * math.sqrt(2 * math.pi) * sz * math.exp(-sz * sz / 2)
+        worst = 0.0
+        for i in range(P.nz):
+            xi = (S.s + i + 0.5) * P.h - zd
+            if -3.0 <= xi <= 1.0:
+                ref = 0.01 * Rr * integrate.quad(
+                    lambda x: math.cos(x - xi) * math.exp(-x * x / (2 * sz * sz)), xi, 12 * sz, limit=200)[0]
+                worst = max(worst, abs(float(S.Ez[j, i]) - ref))
+        assert worst < 0.05 * amp
+
+
+# ---------------------------------------------------------------------------------------------
+# P_units: values printed in the paper (golden fixtures)
+# ---------------------------------------------------------------------------------------------
+
+def test_normalized_charge_reproduces_paper():
+    with open(os.path.join(GOLDEN, "paper_setup.json")) as fh:
+        g = json.load(fh)
+    sz, sx = g["sigma_z_um"] * 1e-6, g["sigma_xy_um"] * 1e-6
+    for q_nC, qt in zip(g["charges_nC"], g["qtilde"]):
+        alpha = U.peak_density_ratio(q_nC * 1e-9, sx, sx, sz, g["n0_cm3"])
+        assert abs(U.normalized_charge(alpha, sx, sx, sz, g["n0_cm3"]) / qt - 1) < 5e-3
+    kp = U.plasma_wavenumber(g["n0_cm3"])
+    # the paper's grid in normalised units: k_p dz ~ 0.0047 and c dt / dz ~ 0.176
+    assert abs(kp * g["dz_um"] * 1e-6 - 0.0047) < 1e-4
+    assert abs(U.C_LIGHT * g["dt_fs"] * 1e-15 / (g["dz_um"] * 1e-6) - 0.1763) < 1e-3
+
+
+def test_table1_gain_column():
+    with open(os.path.join(GOLDEN, "table1.json")) as fh:
+        t = json.load(fh)
+    for f, l, gain in zip(t["fct_ks"], t["lbm_ks"], t["gain_percent"]):
+        assert abs(U.gain_percent(f, l) - gain) < 0.01
