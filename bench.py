@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X lattice-Boltzmann plasma-wakefield step.
+
+One "step" is one time step of the whole hot path (field update, pull-stream, moments, forces,
+collision, window shift) over the whole lattice: one launch of the fused kernel.  The headline
+workload is C2: 2048 x 512 sites, dz = 0.02, FP32 storage, linear entrance ramp, n_b/n0 = 0.1
+driver, moving window, 10,000 steps.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & HBM GB/s FP32 vs FP64 at stated Ez error; adjoint/forward time ratio"
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2201_05473_amd/csrc/lbm_kernels.hip", "paper_2201_05473_amd/csrc/lbm_internal.h")
+
+
+def bytes_per_site(storage: int) -> int:
+    """Algorithmic HBM bytes per site and step of the fused kernel: 27 populations read and
+    written, and the auxiliary planes (3 moments, E_z, E_r, B_theta) read and written once."""
+    s_pop = {0: 8, 1: 4, 2: 2}[storage]
+    s_aux = 8 if storage == 0 else 4
+    return 2 * 27 * s_pop + 2 * 6 * s_aux
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, storage: int):
+    """Counter-measured HBM bytes per launch from profiles/traffic.json, if it was taken on the
+    current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    e = t.get("entries", {}).get(f"{workload}:{storage}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def time_run(cfg: dict, steps: int, warmup: int):
+    """Run warmup + steps; return (seconds of the timed steps, lattice).  The timed region is
+    bracketed by synchronisations and measured with HIP events on the library's stream."""
+    import torch
+
+    from paper_2201_05473_amd import Lattice
+    lat = Lattice(cfg)
+    if warmup:
+        lat.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(lat.stream)
+    lat.step(steps)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_s = ev0.elapsed_time(ev1) / 1e3
+    return wall, ev_s, lat
+
+
+def rel_err(a, b) -> float:
+    den = float(b.abs().max())
+    return float((a - b).abs().max()) / den if den > 0 else float((a - b).abs().max())
+
+
+def cpu_baseline(sample_steps: int = 1) -> dict:
+    """The FP64 oracle, as it stands, on the host cores: C2 at full size for sample_steps steps."""
+    import torch
+
+    import workloads as wl
+    from oracle import lbm_oracle as O
+    cfg = wl.config("C2", storage=0)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    S = O.step(S, P)   # untimed first step (allocator warm-up)
+    t0 = time.perf_counter()
+    for _ in range(sample_steps):
+        S = O.step(S, P)
+    dt = time.perf_counter() - t0
+    return {"value": P.nz * P.nr * sample_steps / dt / 1e6, "unit": "MLUPS",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"C2 2048x512 FP64 oracle (torch CPU), {sample_steps} step(s) after one untimed step"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="headline FP32 run only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU decomposition is described in DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+
+    import workloads as wl
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+
+    cfg = wl.config("C2")
+    sites = cfg["nz"] * cfg["nr"]
+    steps, warmup = args.steps, args.warmup
+
+    # headline: FP32 storage
+    wall, ev_s, lat32 = time_run(cfg, steps, warmup)
+    mlups = sites * steps / wall / 1e6
+    kern_s = ev_s / steps
+    bps = bytes_per_site(wl.F32)
+    achieved = bps * sites / kern_s / 1e9
+    traffic = measured_traffic("C2", wl.F32)
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C2: 2048x512 (z,r), dz=dr=0.02/k_p, c dt/dz=0.2, tau=0.8, FP32 "
+                               "populations, linear entrance ramp 10/k_p, driver n_b/n0=0.1 "
+                               "sigma_z=1 sigma_r=0.5, moving window",
+                   "sites": sites, "lattice_LUPS_factor": 3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic, "bytes_per_site": bps,
+                     "kernel": "lbm::step_kernel<1>", "kernel_avg_us": kern_s * 1e6},
+    }
+
+    if not args.no_extra:
+        modes = {}
+        # FP64 and FP16 at the same workload and step count, with the FP32/FP16 error vs FP64
+        ref_f = lat32.fields()
+        ref_m = lat32.moments()
+        lat32.close()
+        res = {}
+        for storage, name in ((wl.F64, "f64"), (wl.F16, "f16")):
+            w, e, lat = time_run(dict(cfg, storage=storage), steps, warmup)
+            res[name] = (w, e, lat.fields(), lat.moments())
+            lat.close()
+        f64_f, f64_m = res["f64"][2], res["f64"][3]
+        for name, storage, w, e, fl, mo in (
+                ("f32", wl.F32, wall, ev_s, ref_f, ref_m),
+                ("f64", wl.F64, *res["f64"]),
+                ("f16", wl.F16, *res["f16"])):
+            b = bytes_per_site(storage)
+            modes[name] = {
+                "MLUPS": sites * steps / w / 1e6,
+                "alg_GBps": b * sites / (e / steps) / 1e9,
+                "bytes_per_site": b,
+                "err_vs_f64": None if name == "f64" else {
+                    "Ez": rel_err(fl[0], f64_f[0]), "Er": rel_err(fl[1], f64_f[1]),
+                    "n": rel_err(mo[0], f64_m[0])},
+            }
+        out["modes_C2"] = modes
+        # HBM-scale: C3 lattice (4096 x 1024) per storage, 1000 steps
+        c3 = {}
+        for storage, name in ((wl.F32, "f32"), (wl.F64, "f64"), (wl.F16, "f16")):
+            ccfg = wl.config("C3", storage=storage)
+            n3 = ccfg["nz"] * ccfg["nr"]
+            w, e, lat = time_run(ccfg, 1000, 50)
+            lat.close()
+            b = bytes_per_site(storage)
+            c3[name] = {"MLUPS": n3 * 1000 / w / 1e6, "alg_GBps": b * n3 / (e / 1000) / 1e9,
+                        "frac_of_peak": b * n3 / (e / 1000) / 1e9 / PEAK_HBM_GBS}
+        out["modes_C3"] = c3
+        out["adjoint_forward_ratio"] = None
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

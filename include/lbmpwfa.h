@@ -1,0 +1,161 @@
+/*
+ * lbmpwfa.h -- C ABI of the MI355X lattice-Boltzmann plasma-wakefield step.
+ *
+ * The library advances the plasma-electron fluid of G. Parise et al., "Lattice Boltzmann
+ * simulations of Plasma Wakefield Acceleration" (arXiv:2201.05473) on an axisymmetric (z, r)
+ * grid: three D2Q9 BGK lattices for A = (n, n p_z, n p_r) (Sec. III, Eqs. (6)-(14)) coupled to
+ * Maxwell's equations on a Yee grid (Sec. II, Eq. (5)), driven by a rigid bi-Gaussian electron
+ * bunch moving at c, on a window that moves with the driver (Sec. II, last paragraph).
+ *
+ * Units are normalised plasma units: t omega_p, x k_p, n / n_0, p / (m_e c),
+ * e E / (m_e c omega_p), e B / (m_e omega_p), c = 1.
+ *
+ * Grid and layout.  Fluid sites (i, j), i in [0, nz) along z, j in [0, nr) along r, at
+ * z_i = (s + i) dz (s = window shift count) and r_j = (j + 1/2) dr.  E_z lives at (z_i + dz/2, r_j),
+ * E_r at (z_i, (j + 1) dr), B_theta at (z_i + dz/2, (j + 1) dr).  Every array that crosses this
+ * ABI is row-major [component][nr][nz] with z fastest and no padding.
+ *
+ * Memory and streams.  The caller owns every buffer: one device workspace of at least
+ * lbm_workspace_bytes() bytes (the library never allocates device memory), the HIP stream
+ * (hipStream_t passed as void*, NULL = default stream), and all output buffers.  Calls are
+ * stream-ordered; only calls that return data to host memory synchronise the stream.
+ *
+ * Errors.  Every call returns LBM_OK or a negative LBM_E* code and records a message readable
+ * with lbm_last_error() on the same thread.  No call throws across the ABI.  A context is
+ * used by one host thread at a time.
+ */
+#ifndef LBMPWFA_H
+#define LBMPWFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid configuration or argument */
+  LBM_ENOMEM = -2,    /* workspace smaller than required */
+  LBM_EHIP = -3,      /* a HIP runtime call failed */
+  LBM_EUNSTABLE = -4, /* a stability check found a non-finite value */
+  LBM_ESTATE = -5     /* call out of order (e.g. NULL or destroyed context) */
+};
+
+/* Storage precision of the populations.  F64: populations, fields and arithmetic in FP64.
+ * F32: populations and fields in FP32, FP32 arithmetic.  F16: populations in FP16, fields and
+ * arithmetic in FP32.  The density lattice is stored as the deviation from the rest equilibrium
+ * w_i n_bg(z); diagnostics are always accumulated in FP64. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+
+/* Run configuration.  Physical meaning (normalised units):
+ *   nz, nr        grid size (both >= 3)
+ *   dz, dr        cell size; must be equal (the D2Q9 lattice is square)
+ *   c_dt_over_dz  c dt / dz, in (0, 1/sqrt(3)); keeps the lattice velocity below c_s and the
+ *                 Yee scheme stable.  With moving_window it must be 1/m for an integer m
+ *   tau           BGK relaxation time in lattice units, > 1/2; D = (tau - 1/2)/3 dz^2/dt (Eq. (12))
+ *   storage       LBM_F64, LBM_F32 or LBM_F16
+ *   moving_window 1: shift the window one cell every m = 1/(c dt/dz) steps
+ *   periodic      bit 0: periodic in z (excludes moving_window); bit 1: periodic in r
+ *                 (requires fields_on = 0 and cyl_on = 0)
+ *   fields_on     1: Maxwell update and Lorentz force; 0: fields stay zero
+ *   cyl_on        1: axisymmetric source terms of Eq. (13)
+ *   n0, ramp_kind, ramp_start, ramp_len
+ *                 background density n_bg(z): 0 uniform n0; 1 linear n0 clamp((z-z_p)/L, 0, 1);
+ *                 2 tanh n0 (1 + tanh(2 (z-z_p)/L - 1)) / 2; z_p = ramp_start, L = ramp_len > 0
+ *   nb, sigma_z, sigma_r, zd0
+ *                 driver density n_b exp(-(z - zd0 - t)^2 / 2 sigma_z^2 - r^2 / 2 sigma_r^2)
+ *   n_floor       densities at or below it carry no momentum, current or force
+ *   check_every   > 0: every that many steps lbm_step synchronises and checks for non-finite
+ *                 values (LBM_EUNSTABLE); 0: no checks */
+typedef struct {
+  int32_t nz, nr;
+  double dz, dr, c_dt_over_dz, tau;
+  int32_t storage;
+  int32_t moving_window, periodic, fields_on, cyl_on;
+  double n0;
+  int32_t ramp_kind;
+  double ramp_start, ramp_len;
+  double nb, sigma_z, sigma_r, zd0;
+  double n_floor;
+  int32_t check_every;
+} lbm_config;
+
+/* FP64 diagnostics of the current state (all sums over the window):
+ *   charge        sum 2 pi r_j dz dr n          (electron number in the window)
+ *   field_energy  1/2 sum 2 pi dz dr (r E_z^2 + r_edge E_r^2 + r_edge B^2)
+ *   gauss_max     max over sites with i >= 1 of |div_h E - (n_bg - n - n_b)|
+ *   umax          max lattice speed |u*| = (c dt/dz) |beta|
+ *   nonfinite     number of non-finite values among the moments and fields */
+typedef struct {
+  double charge, field_energy, gauss_max, umax;
+  int64_t step, shifts;
+  int32_t nonfinite, reserved;
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Device workspace needed by a configuration (bytes).  LBM_EINVAL for an invalid config. */
+int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
+
+/* Create a context and set the initial state (Sec. II/III set-up, R16 and R18 readings):
+ * populations at the local equilibrium of density n_bg(z_i) (1 + n_pert[j][i]) and momentum
+ * p_init[c][j][i] (c = 0: p_z, 1: p_r); E_z = 0; E_r and B_theta = the driver's discrete Gauss
+ * field at t = -dt and t = -dt/2.  n_pert (host, [nr][nz]) and p_init (host, [2][nr][nz]) may
+ * be NULL (zero).  workspace: device pointer, 256-byte aligned, ws_bytes >= lbm_workspace_bytes.
+ * The workspace must stay valid until lbm_destroy.  Synchronises the stream. */
+int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init,
+             void* workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
+
+/* Advance nsteps >= 0 steps.  One step (Eqs. (5)-(10), (13), (14)): Ampere with the previous
+ * step's post-kick current and the driver current, Faraday, pull-stream of the 27 populations,
+ * moments, Lorentz and axisymmetric sources, BGK collision, window shift when due.  Stream-
+ * ordered and asynchronous unless cfg.check_every > 0. */
+int lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Moments of the last step's post-collision state, [3][nr][nz]: n, J_z = n beta_z,
+ * J_r = n beta_r.  dtype LBM_F64 or LBM_F32.  dst on the device (stream-ordered) or on the host
+ * (synchronising). */
+int lbm_moments(lbm_ctx* ctx, void* dst, int32_t dtype, int32_t dst_on_device);
+
+/* Fields of the state, [3][nr][nz]: E_z at t_{k-1}, E_r at t_{k-1}, B_theta at t_{k-1/2} after k
+ * steps, on their staggered positions.  dtype and placement as lbm_moments. */
+int lbm_fields(lbm_ctx* ctx, void* dst, int32_t dtype, int32_t dst_on_device);
+
+/* Full state in FP64 on the host: [27][nr][nz] populations (lattice-major, raw values, not
+ * deviations), [3][nr][nz] post-collision moments, [3][nr][nz] E_z, E_r, B_theta; the step and
+ * shift counters go to *step and *shifts (may be NULL).  dst holds 33 nr nz doubles.
+ * Synchronising.  Used for checkpoints and checks. */
+int lbm_get_state(lbm_ctx* ctx, double* dst, int64_t* step, int64_t* shifts);
+
+/* Restore a state written by lbm_get_state (same layout, host memory) together with its step
+ * and shift counters.  Values are rounded to the storage precision.  Synchronising. */
+int lbm_set_state(lbm_ctx* ctx, const double* src, int64_t step, int64_t shifts);
+
+/* Checkpoint in the native storage format, for bit-exact resume:
+ * a 64-byte header (magic, storage, nz, nr, step, shift count) followed by the active
+ * population, moment and field buffers as stored.  lbm_checkpoint_bytes gives its size.
+ * dst/src may be host or device memory (flag); both calls synchronise the stream.  lbm_load
+ * returns LBM_EINVAL if the checkpoint was written for another grid or storage precision. */
+int lbm_checkpoint_bytes(lbm_ctx* ctx, size_t* bytes);
+int lbm_save(lbm_ctx* ctx, void* dst, int32_t dst_on_device);
+int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);
+
+/* FP64 diagnostics of the current state (deterministic two-pass reduction).  Synchronising. */
+int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
+
+/* Step and window-shift counters of the state. */
+int lbm_counters(lbm_ctx* ctx, int64_t* step, int64_t* shifts);
+
+/* Release the context (not the caller's workspace). */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until the next call. */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMPWFA_H */

@@ -1,0 +1,272 @@
+"""ctypes binding of liblbmpwfa (include/lbmpwfa.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP kernels.  torch
+provides the device workspace (a uint8 tensor) and the stream handle.  The functions named
+``lbm_*`` mirror the C entry points one to one; ``Lattice`` is a small convenience owner of a
+context and its workspace.  If the library is missing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_F64, LBM_F32, LBM_F16 = 0, 1, 2
+_STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbmpwfa.so")
+
+c_int32, c_int64, c_double, c_size_t, c_void_p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                                  ctypes.c_size_t, ctypes.c_void_p)
+
+
+class LbmConfig(ctypes.Structure):
+    _fields_ = [
+        ("nz", c_int32), ("nr", c_int32),
+        ("dz", c_double), ("dr", c_double), ("c_dt_over_dz", c_double), ("tau", c_double),
+        ("storage", c_int32),
+        ("moving_window", c_int32), ("periodic", c_int32), ("fields_on", c_int32), ("cyl_on", c_int32),
+        ("n0", c_double),
+        ("ramp_kind", c_int32),
+        ("ramp_start", c_double), ("ramp_len", c_double),
+        ("nb", c_double), ("sigma_z", c_double), ("sigma_r", c_double), ("zd0", c_double),
+        ("n_floor", c_double),
+        ("check_every", c_int32),
+    ]
+
+
+class LbmDiag(ctypes.Structure):
+    _fields_ = [
+        ("charge", c_double), ("field_energy", c_double), ("gauss_max", c_double), ("umax", c_double),
+        ("step", c_int64), ("shifts", c_int64), ("nonfinite", c_int32), ("reserved", c_int32),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblbmpwfa error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load the HIP library (once).  Raises OSError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise OSError(f"{p} not found: build it with paper_2201_05473_amd/build.py (no fallback exists)")
+    lib = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    sig = {
+        "lbm_workspace_bytes": (c_int32, [P(LbmConfig), P(c_size_t)]),
+        "lbm_init": (c_int32, [P(LbmConfig), c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)]),
+        "lbm_step": (c_int32, [c_void_p, c_int64]),
+        "lbm_moments": (c_int32, [c_void_p, c_void_p, c_int32, c_int32]),
+        "lbm_fields": (c_int32, [c_void_p, c_void_p, c_int32, c_int32]),
+        "lbm_get_state": (c_int32, [c_void_p, c_void_p, P(c_int64), P(c_int64)]),
+        "lbm_set_state": (c_int32, [c_void_p, c_void_p, c_int64, c_int64]),
+        "lbm_diagnostics": (c_int32, [c_void_p, P(LbmDiag)]),
+        "lbm_checkpoint_bytes": (c_int32, [c_void_p, P(c_size_t)]),
+        "lbm_save": (c_int32, [c_void_p, c_void_p, c_int32]),
+        "lbm_load": (c_int32, [c_void_p, c_void_p, c_int32]),
+        "lbm_counters": (c_int32, [c_void_p, P(c_int64), P(c_int64)]),
+        "lbm_destroy": (c_int32, [c_void_p]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != LBM_OK:
+        raise LbmError(rc, lbm_last_error())
+
+
+def make_config(cfg: dict) -> LbmConfig:
+    """C configuration struct from a workload dictionary (extra keys are ignored)."""
+    c = LbmConfig()
+    for name, ctype in LbmConfig._fields_:
+        v = cfg[name]
+        if name == "storage" and isinstance(v, str):
+            v = _STORAGE[v]
+        setattr(c, name, int(v) if ctype is c_int32 else float(v))
+    return c
+
+
+# --- one-to-one wrappers of the C entry points ----------------------------------------------
+
+def lbm_last_error() -> str:
+    return load_library().lbm_last_error().decode()
+
+
+def lbm_workspace_bytes(cfg: dict | LbmConfig) -> int:
+    c = cfg if isinstance(cfg, LbmConfig) else make_config(cfg)
+    n = c_size_t(0)
+    _check(load_library().lbm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_init(cfg: dict | LbmConfig, n_pert, p_init, workspace_ptr: int, ws_bytes: int,
+             stream_handle: int) -> int:
+    c = cfg if isinstance(cfg, LbmConfig) else make_config(cfg)
+    npert = None if n_pert is None else np.ascontiguousarray(n_pert, dtype=np.float64)
+    pinit = None if p_init is None else np.ascontiguousarray(p_init, dtype=np.float64)
+    if npert is not None and npert.shape != (c.nr, c.nz):
+        raise ValueError(f"n_pert must have shape {(c.nr, c.nz)}")
+    if pinit is not None and pinit.shape != (2, c.nr, c.nz):
+        raise ValueError(f"p_init must have shape {(2, c.nr, c.nz)}")
+    ctx = c_void_p(0)
+    _check(load_library().lbm_init(
+        ctypes.byref(c),
+        None if npert is None else npert.ctypes.data_as(c_void_p),
+        None if pinit is None else pinit.ctypes.data_as(c_void_p),
+        c_void_p(workspace_ptr), c_size_t(ws_bytes), c_void_p(stream_handle), ctypes.byref(ctx)))
+    return ctx.value
+
+
+def lbm_step(ctx: int, nsteps: int):
+    _check(load_library().lbm_step(c_void_p(ctx), c_int64(nsteps)))
+
+
+def lbm_moments(ctx: int, dst_ptr: int, dtype: int, on_device: bool):
+    _check(load_library().lbm_moments(c_void_p(ctx), c_void_p(dst_ptr), dtype, int(on_device)))
+
+
+def lbm_fields(ctx: int, dst_ptr: int, dtype: int, on_device: bool):
+    _check(load_library().lbm_fields(c_void_p(ctx), c_void_p(dst_ptr), dtype, int(on_device)))
+
+
+def lbm_get_state(ctx: int, nz: int, nr: int):
+    out = np.empty((33, nr, nz), dtype=np.float64)
+    k, s = c_int64(0), c_int64(0)
+    _check(load_library().lbm_get_state(c_void_p(ctx), out.ctypes.data_as(c_void_p), ctypes.byref(k),
+                                        ctypes.byref(s)))
+    return out, k.value, s.value
+
+
+def lbm_set_state(ctx: int, state, step: int, shifts: int):
+    src = np.ascontiguousarray(state, dtype=np.float64)
+    _check(load_library().lbm_set_state(c_void_p(ctx), src.ctypes.data_as(c_void_p), c_int64(step),
+                                        c_int64(shifts)))
+
+
+def lbm_diagnostics(ctx: int) -> dict:
+    d = LbmDiag()
+    _check(load_library().lbm_diagnostics(c_void_p(ctx), ctypes.byref(d)))
+    return {name: getattr(d, name) for name, _ in LbmDiag._fields_ if name != "reserved"}
+
+
+def lbm_checkpoint_bytes(ctx: int) -> int:
+    n = c_size_t(0)
+    _check(load_library().lbm_checkpoint_bytes(c_void_p(ctx), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_save(ctx: int, dst_ptr: int, on_device: bool):
+    _check(load_library().lbm_save(c_void_p(ctx), c_void_p(dst_ptr), int(on_device)))
+
+
+def lbm_load(ctx: int, src_ptr: int, on_device: bool):
+    _check(load_library().lbm_load(c_void_p(ctx), c_void_p(src_ptr), int(on_device)))
+
+
+def lbm_counters(ctx: int):
+    k, s = c_int64(0), c_int64(0)
+    _check(load_library().lbm_counters(c_void_p(ctx), ctypes.byref(k), ctypes.byref(s)))
+    return k.value, s.value
+
+
+def lbm_destroy(ctx: int):
+    _check(load_library().lbm_destroy(c_void_p(ctx)))
+
+
+# --- convenience owner ------------------------------------------------------------------------
+
+class Lattice:
+    """A context plus its device workspace (a torch uint8 tensor) on one GPU and stream."""
+
+    def __init__(self, cfg: dict, n_pert=None, p_init=None, device="cuda", stream=None):
+        import torch
+        load_library()
+        self.cfg = dict(cfg)
+        self.nz, self.nr = int(cfg["nz"]), int(cfg["nr"])
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws_bytes = lbm_workspace_bytes(cfg)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ctx = lbm_init(cfg, n_pert, p_init, self.ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+
+    def step(self, nsteps: int = 1):
+        lbm_step(self.ctx, nsteps)
+
+    def _out3(self, fn, dtype):
+        import torch
+        dt = torch.float64 if dtype == torch.float64 else torch.float32
+        out = torch.empty((3, self.nr, self.nz), dtype=dt, device=self.device)
+        fn(self.ctx, out.data_ptr(), LBM_F64 if dt == torch.float64 else LBM_F32, True)
+        return out
+
+    def moments(self, dtype=None):
+        """[3][nr][nz] device tensor: n, J_z, J_r (stream-ordered)."""
+        import torch
+        return self._out3(lbm_moments, dtype or torch.float64)
+
+    def fields(self, dtype=None):
+        """[3][nr][nz] device tensor: E_z, E_r, B_theta (stream-ordered)."""
+        import torch
+        return self._out3(lbm_fields, dtype or torch.float64)
+
+    def state(self):
+        """(state [33][nr][nz] float64 numpy, step, shifts); synchronising."""
+        return lbm_get_state(self.ctx, self.nz, self.nr)
+
+    def set_state(self, state, step: int, shifts: int):
+        lbm_set_state(self.ctx, state, step, shifts)
+
+    def save(self, on_device: bool = False):
+        """Native-format checkpoint: a uint8 numpy array (host) or torch tensor (device)."""
+        import torch
+        n = lbm_checkpoint_bytes(self.ctx)
+        if on_device:
+            buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+            lbm_save(self.ctx, buf.data_ptr(), True)
+        else:
+            buf = np.empty(n, dtype=np.uint8)
+            lbm_save(self.ctx, buf.ctypes.data, False)
+        return buf
+
+    def load(self, buf):
+        if isinstance(buf, np.ndarray):
+            lbm_load(self.ctx, buf.ctypes.data, False)
+        else:
+            lbm_load(self.ctx, buf.data_ptr(), True)
+
+    def diagnostics(self) -> dict:
+        return lbm_diagnostics(self.ctx)
+
+    def counters(self):
+        return lbm_counters(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,442 @@
+// Host runtime and C ABI of liblbmpwfa (see include/lbmpwfa.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbmpwfa.h"
+#include "lbm_internal.h"
+
+using lbm::Physics;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_CHECK(expr, what)                    \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t pop_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+size_t aux_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+// Validate a configuration; on success fill the derived physics.
+int validate(const lbm_config* c, Physics* p) {
+  if (!c) return fail(LBM_EINVAL, "config is NULL");
+  if (c->nz < 3 || c->nr < 3) return fail(LBM_EINVAL, "nz and nr must be >= 3 (got %d, %d)", c->nz, c->nr);
+  if ((long long)c->nz * c->nr > (1LL << 31) / 32)
+    return fail(LBM_EINVAL, "grid too large (%d x %d)", c->nz, c->nr);
+  if (!(c->dz > 0.0) || !std::isfinite(c->dz)) return fail(LBM_EINVAL, "dz must be positive");
+  if (std::fabs(c->dr - c->dz) > 1e-12 * c->dz) return fail(LBM_EINVAL, "dz and dr must be equal");
+  const double lam = c->c_dt_over_dz;
+  if (!(lam > 0.0) || !(lam < 1.0 / std::sqrt(3.0)))
+    return fail(LBM_EINVAL, "c_dt_over_dz must lie in (0, 1/sqrt(3)) (got %g)", lam);
+  if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_EINVAL, "tau must exceed 1/2 (got %g)", c->tau);
+  if (c->storage != LBM_F64 && c->storage != LBM_F32 && c->storage != LBM_F16)
+    return fail(LBM_EINVAL, "unknown storage %d", c->storage);
+  if (c->periodic < 0 || c->periodic > 3) return fail(LBM_EINVAL, "periodic must be in [0, 3]");
+  const int per_z = c->periodic & 1, per_r = (c->periodic >> 1) & 1;
+  if (per_z && c->moving_window) return fail(LBM_EINVAL, "periodic z excludes the moving window");
+  if (per_r && (c->fields_on || c->cyl_on))
+    return fail(LBM_EINVAL, "periodic r needs fields_on = 0 and cyl_on = 0");
+  int m = 0;
+  if (c->moving_window) {
+    m = (int)std::lround(1.0 / lam);
+    if (m < 1 || std::fabs(m * lam - 1.0) > 1e-9)
+      return fail(LBM_EINVAL, "the moving window needs 1/(c dt/dz) to be an integer (got %g)", 1.0 / lam);
+  }
+  if (c->ramp_kind < 0 || c->ramp_kind > 2) return fail(LBM_EINVAL, "unknown ramp_kind %d", c->ramp_kind);
+  if (c->ramp_kind != 0 && !(c->ramp_len > 0.0)) return fail(LBM_EINVAL, "ramp_len must be positive");
+  if (!std::isfinite(c->n0) || c->n0 < 0.0) return fail(LBM_EINVAL, "n0 must be finite and >= 0");
+  if (!std::isfinite(c->nb)) return fail(LBM_EINVAL, "nb must be finite");
+  if (c->nb != 0.0 && !(c->sigma_z > 0.0 && c->sigma_r > 0.0))
+    return fail(LBM_EINVAL, "driver sizes must be positive");
+  if (!(c->n_floor >= 0.0)) return fail(LBM_EINVAL, "n_floor must be >= 0");
+  if (c->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+  if (p) {
+    Physics& q = *p;
+    std::memset(&q, 0, sizeof q);
+    q.nz = c->nz;
+    q.nr = c->nr;
+    q.pitch = (int)round_up((size_t)c->nz, lbm::PITCH_ALIGN);
+    q.plane = (long long)q.nr * q.pitch;
+    q.h = c->dz;
+    q.lam = lam;
+    q.dt = lam * c->dz;
+    q.tau = c->tau;
+    q.D = (c->tau - 0.5) / 3.0 * c->dz * c->dz / q.dt;   // Eq. (12) in normalised units
+    q.n_floor = c->n_floor;
+    q.n0 = c->n0;
+    q.ramp_start = c->ramp_start;
+    q.ramp_len = c->ramp_kind ? c->ramp_len : 1.0;
+    q.ramp_kind = c->ramp_kind;
+    q.nb = c->nb;
+    q.sigma_z = c->nb != 0.0 ? c->sigma_z : 1.0;
+    q.sigma_r = c->nb != 0.0 ? c->sigma_r : 1.0;
+    q.zd0 = c->zd0;
+    q.window = c->moving_window ? 1 : 0;
+    q.m = m;
+    q.per_z = per_z;
+    q.per_r = per_r;
+    q.fields_on = c->fields_on ? 1 : 0;
+    q.cyl_on = c->cyl_on ? 1 : 0;
+  }
+  return LBM_OK;
+}
+
+// Workspace layout: two population buffers, two moment buffers, two field buffers, and the
+// reduction scratch, each 256-byte aligned.
+struct Layout {
+  size_t g[2], M[2], E[2], partials, out, total;
+};
+
+Layout layout(const Physics& p, int storage) {
+  Layout L;
+  const size_t plane = (size_t)p.plane;
+  const size_t gb = round_up(27 * plane * pop_bytes(storage), 256);
+  const size_t mb = round_up(3 * plane * aux_bytes(storage), 256);
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b) { L.g[b] = off; off += gb; }
+  for (int b = 0; b < 2; ++b) { L.M[b] = off; off += mb; }
+  for (int b = 0; b < 2; ++b) { L.E[b] = off; off += mb; }
+  L.partials = off;
+  off += round_up((size_t)lbm::diag_blocks(p) * 8 * sizeof(double), 256);
+  L.out = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_config cfg;
+  Physics p;
+  int storage;
+  char* ws;
+  Layout L;
+  int cur;
+  long long k, s;
+  hipStream_t stream;
+  void* g(int b) { return ws + L.g[b]; }
+  void* M(int b) { return ws + L.M[b]; }
+  void* E(int b) { return ws + L.E[b]; }
+  double* partials() { return (double*)(ws + L.partials); }
+  double* red_out() { return (double*)(ws + L.out); }
+  // Scratch for host transfers: the inactive population buffer (free between steps).
+  void* staging() { return g(1 - cur); }
+  size_t staging_bytes() const { return L.g[1] - L.g[0]; }
+};
+
+namespace {
+
+int run_check(lbm_ctx* c) {
+  HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur),
+                                    c->partials(), c->red_out(), c->stream),
+            "diagnostics launch");
+  double out[8];
+  HIP_CHECK(hipMemcpyAsync(out, c->red_out(), sizeof out, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  if (out[4] != 0.0 || !std::isfinite(out[3]))
+    return fail(LBM_EUNSTABLE, "non-finite state after step %lld", c->k);
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
+  Physics p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  *bytes = layout(p, cfg->storage).total;
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init, void* workspace,
+             size_t ws_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Physics p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  if ((uintptr_t)workspace % 256 != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = layout(p, cfg->storage);
+  if (ws_bytes < L.total)
+    return fail(LBM_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  lbm_ctx* c = new (std::nothrow) lbm_ctx;
+  if (!c) return fail(LBM_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->p = p;
+  c->storage = cfg->storage;
+  c->ws = (char*)workspace;
+  c->L = L;
+  c->cur = 0;
+  c->k = 0;
+  c->s = 0;
+  c->stream = (hipStream_t)hip_stream;
+  auto bail = [&](int code) { delete c; return code; };
+  hipError_t e = hipMemsetAsync(workspace, 0, L.total, c->stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "workspace clear"));
+  // Upload the perturbation arrays into the inactive population buffer.
+  const size_t plane_u = (size_t)p.nr * p.nz;
+  double* stage = (double*)c->staging();
+  const double* d_pert = nullptr;
+  const double* d_pinit = nullptr;
+  if (3 * plane_u * sizeof(double) > c->staging_bytes()) return bail(fail(LBM_ENOMEM, "staging too small"));
+  if (n_pert) {
+    e = hipMemcpyAsync(stage, n_pert, plane_u * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload n_pert"));
+    d_pert = stage;
+  }
+  if (p_init) {
+    e = hipMemcpyAsync(stage + plane_u, p_init, 2 * plane_u * sizeof(double), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload p_init"));
+    d_pinit = stage + plane_u;
+  }
+  e = lbm::launch_init_fluid(c->storage, p, d_pert, d_pinit, c->g(0), c->M(0), c->stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "init fluid launch"));
+  e = lbm::launch_init_fields(c->storage, p, c->E(0), c->stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "init fields launch"));
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "init synchronise"));
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  for (int64_t n = 0; n < nsteps; ++n) {
+    lbm::StepArgs a;
+    a.p = c->p;
+    a.k = c->k;
+    a.s = c->s;
+    a.shift = (c->p.window && (c->k + 1) % c->p.m == 0) ? 1 : 0;
+    a.g_in = c->g(c->cur);
+    a.g_out = c->g(1 - c->cur);
+    a.M_in = c->M(c->cur);
+    a.M_out = c->M(1 - c->cur);
+    a.E_in = c->E(c->cur);
+    a.E_out = c->E(1 - c->cur);
+    HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "step launch");
+    c->cur ^= 1;
+    c->k += 1;
+    c->s += a.shift;
+    if (c->cfg.check_every > 0 && c->k % c->cfg.check_every == 0) {
+      int rc = run_check(c);
+      if (rc) return rc;
+    }
+  }
+  return LBM_OK;
+}
+
+static int output3(lbm_ctx* c, void* dst, int32_t dtype, int32_t on_device, bool moments) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  const int f64 = dtype == LBM_F64;
+  const size_t nbytes = 3 * (size_t)c->p.nr * c->p.nz * (f64 ? 8 : 4);
+  void* target = on_device ? dst : c->staging();
+  hipError_t e = moments
+      ? lbm::launch_moments_out(c->storage, c->p, c->s, c->M(c->cur), target, f64, c->stream)
+      : lbm::launch_fields_out(c->storage, c->p, c->E(c->cur), target, f64, c->stream);
+  HIP_CHECK(e, "output launch");
+  if (!on_device) {
+    HIP_CHECK(hipMemcpyAsync(dst, target, nbytes, hipMemcpyDeviceToHost, c->stream), "download");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, void* dst, int32_t dtype, int32_t dst_on_device) {
+  return output3(c, dst, dtype, dst_on_device, true);
+}
+
+int lbm_fields(lbm_ctx* c, void* dst, int32_t dtype, int32_t dst_on_device) {
+  return output3(c, dst, dtype, dst_on_device, false);
+}
+
+int lbm_get_state(lbm_ctx* c, double* dst, int64_t* step, int64_t* shifts) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+  const size_t pl = (size_t)c->p.nr * c->p.nz;
+  double* stage = (double*)c->staging();
+  for (int comp = 0; comp < 33; ++comp) {
+    HIP_CHECK(lbm::launch_state_get(c->storage, c->p, c->s, c->g(c->cur), c->M(c->cur), c->E(c->cur),
+                                    comp, stage, c->stream),
+              "state launch");
+    HIP_CHECK(hipMemcpyAsync(dst + comp * pl, stage, pl * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream),
+              "download");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  }
+  if (step) *step = c->k;
+  if (shifts) *shifts = c->s;
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const double* src, int64_t step, int64_t shifts) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!src) return fail(LBM_EINVAL, "src is NULL");
+  if (step < 0 || shifts < 0) return fail(LBM_EINVAL, "counters must be >= 0");
+  const size_t pl = (size_t)c->p.nr * c->p.nz;
+  double* stage = (double*)c->staging();
+  for (int comp = 0; comp < 33; ++comp) {
+    HIP_CHECK(hipMemcpyAsync(stage, src + comp * pl, pl * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream),
+              "upload");
+    HIP_CHECK(lbm::launch_state_set(c->storage, c->p, shifts, c->g(c->cur), c->M(c->cur), c->E(c->cur),
+                                    comp, stage, c->stream),
+              "state launch");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  }
+  c->k = step;
+  c->s = shifts;
+  return LBM_OK;
+}
+
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int32_t storage, nz, nr, pitch;
+  int64_t step, shifts;
+  char pad[24];
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '1'};
+
+size_t region_bytes(const lbm_ctx* c, int which) {
+  const size_t plane = (size_t)c->p.plane;
+  return which == 0 ? 27 * plane * pop_bytes(c->storage) : 3 * plane * aux_bytes(c->storage);
+}
+}  // namespace
+
+int lbm_checkpoint_bytes(lbm_ctx* c, size_t* bytes) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + 2 * region_bytes(c, 1);
+  return LBM_OK;
+}
+
+int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kMagic, 8);
+  h.storage = c->storage;
+  h.nz = c->p.nz;
+  h.nr = c->p.nr;
+  h.pitch = c->p.pitch;
+  h.step = c->k;
+  h.shifts = c->s;
+  char* d = (char*)dst;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (on_device) {
+    HIP_CHECK(hipMemcpyAsync(d, &h, sizeof h, hipMemcpyHostToDevice, c->stream), "save header");
+  } else {
+    std::memcpy(d, &h, sizeof h);
+  }
+  size_t off = sizeof h;
+  const void* src[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  for (int r = 0; r < 3; ++r) {
+    const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
+    HIP_CHECK(hipMemcpyAsync(d + off, src[r], nb, kind, c->stream), "save copy");
+    off += nb;
+  }
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  return LBM_OK;
+}
+
+int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!src) return fail(LBM_EINVAL, "src is NULL");
+  CkptHeader h;
+  const char* s = (const char*)src;
+  if (on_device) {
+    HIP_CHECK(hipMemcpyAsync(&h, s, sizeof h, hipMemcpyDeviceToHost, c->stream), "load header");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  } else {
+    std::memcpy(&h, s, sizeof h);
+  }
+  if (std::memcmp(h.magic, kMagic, 8) != 0) return fail(LBM_EINVAL, "not an lbmpwfa checkpoint");
+  if (h.storage != c->storage || h.nz != c->p.nz || h.nr != c->p.nr || h.pitch != c->p.pitch)
+    return fail(LBM_EINVAL, "checkpoint is for another grid or storage precision");
+  if (h.step < 0 || h.shifts < 0) return fail(LBM_EINVAL, "corrupt checkpoint counters");
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  size_t off = sizeof h;
+  void* dstp[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  for (int r = 0; r < 3; ++r) {
+    const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
+    HIP_CHECK(hipMemcpyAsync(dstp[r], s + off, nb, kind, c->stream), "load copy");
+    off += nb;
+  }
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  c->k = h.step;
+  c->s = h.shifts;
+  return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur),
+                                    c->partials(), c->red_out(), c->stream),
+            "diagnostics launch");
+  double r[8];
+  HIP_CHECK(hipMemcpyAsync(r, c->red_out(), sizeof r, hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  out->charge = r[0];
+  out->field_energy = r[1];
+  out->gauss_max = r[2];
+  out->umax = r[3];
+  out->nonfinite = (int32_t)r[4];
+  out->reserved = 0;
+  out->step = c->k;
+  out->shifts = c->s;
+  return LBM_OK;
+}
+
+int lbm_counters(lbm_ctx* c, int64_t* step, int64_t* shifts) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (step) *step = c->k;
+  if (shifts) *shifts = c->s;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  delete c;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

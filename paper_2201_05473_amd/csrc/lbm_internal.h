@@ -1,0 +1,65 @@
+// Internal declarations shared by the kernels and the host runtime of liblbmpwfa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Tile of the fused step kernel: TZ sites along z (one wavefront) by TR rows.
+constexpr int TZ = 64;
+constexpr int TR = 4;
+constexpr int NTHREADS = TZ * TR;
+// Row pitch of every plane, in elements (keeps every row start 256-byte aligned in FP32).
+constexpr int PITCH_ALIGN = 64;
+// Blocks of the diagnostic reduction.
+constexpr int RED_THREADS = 256;
+
+// Physical and grid parameters of a run (fixed for a context).
+struct Physics {
+  int nz, nr, pitch;
+  long long plane;          // nr * pitch elements
+  double h, dt, lam, tau, D, n_floor;
+  double n0, ramp_start, ramp_len;
+  int ramp_kind;
+  double nb, sigma_z, sigma_r, zd0;
+  int window, m, per_z, per_r, fields_on, cyl_on;
+};
+
+// One launch of the fused step: physics + time counters + buffers.
+struct StepArgs {
+  Physics p;
+  long long k;      // index of the step being taken (state holds k completed steps)
+  long long s;      // window shift count before this step
+  int shift;        // 1 if the window moves at the end of this step
+  const void* g_in;
+  void* g_out;
+  const void* M_in;
+  void* M_out;
+  const void* E_in;  // [3 planes] E_z, E_r, B_theta
+  void* E_out;
+};
+
+// Launchers (defined in lbm_kernels.hip).  storage: 0 F64, 1 F32, 2 F16.
+hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st);
+hipError_t launch_init_fluid(int storage, const Physics& p, const double* n_pert,
+                             const double* p_init, void* g, void* M, hipStream_t st);
+hipError_t launch_init_fields(int storage, const Physics& p, void* E, hipStream_t st);
+hipError_t launch_moments_out(int storage, const Physics& p, long long s, const void* M,
+                              void* dst, int dst_f64, hipStream_t st);
+hipError_t launch_fields_out(int storage, const Physics& p, const void* E, void* dst,
+                             int dst_f64, hipStream_t st);
+// One plane of the FP64 state view: component c in [0, 33) (27 populations, 3 moments,
+// 3 fields) written unpadded to dst[nr][nz].
+hipError_t launch_state_get(int storage, const Physics& p, long long s, const void* g,
+                            const void* M, const void* E, int c, double* dst, hipStream_t st);
+hipError_t launch_state_set(int storage, const Physics& p, long long s, void* g, void* M,
+                            void* E, int c, const double* src, hipStream_t st);
+// Diagnostics: partials[nblocks][8] then a single-block final pass into out[8].
+int diag_blocks(const Physics& p);
+hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
+                              const void* M, const void* E, double* partials, double* out,
+                              hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,700 @@
+// HIP kernels (gfx950) of the lattice-Boltzmann plasma-wakefield step.
+//
+// One launch per time step: the fused kernel first advances the Yee fields of its tile (plus a
+// one-cell halo, recomputed from LDS) and then performs the pull-stream / BGK collision of the
+// three D2Q9 lattices of its sites.  Notation and step order follow the paper (Parise et al.,
+// arXiv:2201.05473): Eq. (5) for the fields, Eqs. (6)-(10), (13), (14) for the lattices; the
+// readings where the paper is silent are stated at each use.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------------------------------
+// Precision modes: population storage S, arithmetic C, auxiliary (moments, fields) storage A.
+// ------------------------------------------------------------------------------------------
+template <int ST> struct Mode;
+template <> struct Mode<0> { using S = double; using C = double; using A = double; };
+template <> struct Mode<1> { using S = float;  using C = float;  using A = float;  };
+template <> struct Mode<2> { using S = __half; using C = float;  using A = float;  };
+
+__device__ __forceinline__ double ldv(double x) { return x; }
+__device__ __forceinline__ float ldv(float x) { return x; }
+__device__ __forceinline__ float ldv(__half x) { return __half2float(x); }
+__device__ __forceinline__ void stv(double* p, double v) { *p = v; }
+__device__ __forceinline__ void stv(float* p, float v) { *p = v; }
+__device__ __forceinline__ void stv(float* p, double v) { *p = (float)v; }
+__device__ __forceinline__ void stv(__half* p, float v) { *p = __float2half_rn(v); }
+__device__ __forceinline__ void stv(__half* p, double v) { *p = __float2half_rn((float)v); }
+
+__device__ __forceinline__ float msqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double msqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float mexp(float x) { return expf(x); }
+__device__ __forceinline__ double mexp(double x) { return exp(x); }
+
+// D2Q9 velocity set (xi_z, xi_r) and weights; the paper's table (Fig. 2) is not in its text,
+// the standard set is used.  Order: rest, +z, +r, -z, -r, (+z,+r), (-z,+r), (-z,-r), (+z,-r).
+__host__ __device__ constexpr int XZ(int q) {
+  return (q == 1 || q == 5 || q == 8) ? 1 : ((q == 3 || q == 6 || q == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int XR(int q) {
+  return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
+}
+template <typename C> __host__ __device__ constexpr C WQ(int q) {
+  return q == 0 ? C(4) / C(9) : (q < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+// Background (ion) density n_bg(z): uniform, linear ramp or tanh ramp (always FP64).
+__device__ __forceinline__ double nbg(const Physics& p, double z) {
+  if (p.ramp_kind == 0) return p.n0;
+  const double x = (z - p.ramp_start) / p.ramp_len;
+  if (p.ramp_kind == 1) return p.n0 * fmin(fmax(x, 0.0), 1.0);
+  return p.n0 * 0.5 * (1.0 + tanh(2.0 * x - 1.0));
+}
+
+// Rigid bi-Gaussian driver moving at c, evaluated in arithmetic type C.
+template <typename C>
+__device__ __forceinline__ C driver(const Physics& p, double z, double r, double t) {
+  const C dz = (C)(z - (p.zd0 + t));
+  const C rr = (C)r;
+  return (C)p.nb * mexp(-(dz * dz) / (C)(2.0 * p.sigma_z * p.sigma_z)) *
+         mexp(-(rr * rr) / (C)(2.0 * p.sigma_r * p.sigma_r));
+}
+
+// beta = p / gamma from the moments (Eq. (2), third line); zero at or below the density floor.
+template <typename C>
+__device__ __forceinline__ bool velocity(C n, C a1, C a2, C floor_, C& bz, C& br) {
+  if (!(n > floor_)) { bz = C(0); br = C(0); return false; }
+  const C pz = a1 / n, pr = a2 / n;
+  const C ig = C(1) / msqrt(C(1) + pz * pz + pr * pr);
+  bz = pz * ig;
+  br = pr * ig;
+  return true;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// XCD-aware block -> tile map: consecutive tiles go to the same XCD (blocks are dispatched
+// round-robin over the 8 XCDs), so halo and pull neighbours share an L2.  A bijection.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = nblocks / 8, rem = nblocks % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// ------------------------------------------------------------------------------------------
+// The fused step kernel.
+// ------------------------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
+  using S = typename Mode<ST>::S;
+  using C = typename Mode<ST>::C;
+  using A = typename Mode<ST>::A;
+  const Physics& p = a.p;
+  constexpr int MZ = TZ + 2, MR = TR + 2;    // moments:  cols i0-1..i0+TZ,   rows j0-1..j0+TR
+  constexpr int BZ = TZ + 3, BR = TR + 3;    // B^{k-1/2}: cols i0-2..i0+TZ,  rows j0-2..j0+TR
+  constexpr int EZZ = TZ + 1, EZR = TR + 2;  // E_z:      cols i0-1..i0+TZ-1, rows j0-1..j0+TR
+  constexpr int ERZ = TZ + 2, ERR = TR + 1;  // E_r:      cols i0-1..i0+TZ,   rows j0-1..j0+TR-1
+  constexpr int BNZ = TZ + 1, BNR = TR + 1;  // B^{k+1/2}: cols i0-1..i0+TZ-1, rows j0-1..j0+TR-1
+  __shared__ C sM[3][MR][MZ];
+  __shared__ C sJ[2][MR][MZ];
+  __shared__ C sBo[BR][BZ];
+  __shared__ C sEz[EZR][EZZ];
+  __shared__ C sEr[ERR][ERZ];
+  __shared__ C sBn[BNR][BNZ];
+  __shared__ double sN[MZ];
+
+  const int nz = p.nz, nr = p.nr, pitch = p.pitch;
+  const long long plane = p.plane;
+  const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
+  const int tile = xcd_tile(blockIdx.x, gx * gy);
+  const int o0 = (tile % gx) * TZ;
+  const int i0 = o0 + a.shift;  // logical (pre-shift) column of the first site
+  const int j0 = (tile / gx) * TR;
+  const int tid = threadIdx.x;
+  const int tx = tid % TZ, ty = tid / TZ;
+  const double h = p.h, dt = p.dt;
+  const C hc = (C)h, dtc = (C)dt;
+  const A* Min = (const A*)a.M_in;
+  const A* Ein = (const A*)a.E_in;
+
+  // --- background density of the tile's columns (lab position of the physical column) ------
+  for (int t = tid; t < MZ; t += NTHREADS) {
+    const int i = i0 - 1 + t;
+    const int ci = p.per_z ? wrapi(i, nz) : i;
+    sN[t] = nbg(p, (double)(a.s + ci) * h);
+  }
+  __syncthreads();
+
+  // --- moments with the ghost ring (R11: z rule, then r rule) and their current J = n beta ---
+  for (int t = tid; t < MR * MZ; t += NTHREADS) {
+    const int bb = t / MZ, aa = t % MZ;
+    const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+    int ci;
+    bool fresh = false;
+    if (p.per_z) {
+      ci = wrapi(i, nz);
+    } else if (i < 0) {
+      ci = 0;                                   // rear: copy of the first column
+    } else if (i >= nz) {
+      ci = nz - 1;                              // front: copy of the last column ...
+      fresh = p.window && i == nz;              // ... or plasma at rest with the window
+    } else {
+      ci = i;
+    }
+    int rj;
+    C sg = C(1);
+    if (p.per_r) {
+      rj = wrapi(j, nr);
+    } else if (j < 0) {
+      rj = 0;
+      sg = C(-1);                               // axis mirror: n p_r is odd
+    } else {
+      rj = j < nr ? j : nr - 1;                 // outer: copy of the last row
+    }
+    // sM[0] holds the density moment as the deviation from n_bg of this LDS column; a ghost
+    // copied from column ci carries the difference of the two columns' n_bg
+    C d0, m1, m2;
+    if (fresh) {
+      d0 = C(0);
+      m1 = C(0);
+      m2 = C(0);
+    } else {
+      const long long off = (long long)rj * pitch + ci;
+      d0 = (C)Min[off];
+      if (!p.per_z && ci != i) d0 += (C)(sN[ci - (i0 - 1)] - sN[aa]);
+      m1 = (C)Min[plane + off];
+      m2 = sg * (C)Min[2 * plane + off];
+    }
+    sM[0][bb][aa] = d0;
+    sM[1][bb][aa] = m1;
+    sM[2][bb][aa] = m2;
+    if (p.fields_on) {
+      const C m0 = (C)sN[aa] + d0;
+      C bz, br;
+      velocity<C>(m0, m1, m2, (C)p.n_floor, bz, br);
+      sJ[0][bb][aa] = m0 * bz;
+      sJ[1][bb][aa] = m0 * br;
+    }
+  }
+
+  if (p.fields_on) {
+    // --- load B^{k-1/2}, E^{k-1} (ghosts: B = 0 on the axis, zero-gradient elsewhere) -------
+    for (int t = tid; t < BR * BZ; t += NTHREADS) {
+      const int bb = t / BZ, aa = t % BZ;
+      const int i = i0 - 2 + aa, j = j0 - 2 + bb;
+      C v = C(0);
+      if (j >= 0) {
+        const int rj = j < nr ? j : nr - 1;
+        const int ci = p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1));
+        v = (C)Ein[2 * plane + (long long)rj * pitch + ci];
+      }
+      sBo[bb][aa] = v;
+    }
+    for (int t = tid; t < EZR * EZZ; t += NTHREADS) {
+      const int bb = t / EZZ, aa = t % EZZ;
+      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+      const int rj = j < 0 ? 0 : (j < nr ? j : nr - 1);
+      const int ci = p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1));
+      sEz[bb][aa] = (C)Ein[(long long)rj * pitch + ci];
+    }
+    for (int t = tid; t < ERR * ERZ; t += NTHREADS) {
+      const int bb = t / ERZ, aa = t % ERZ;
+      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+      const int rj = j < 0 ? 0 : (j < nr ? j : nr - 1);
+      const int ci = p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1));
+      sEr[bb][aa] = (C)Ein[plane + (long long)rj * pitch + ci];
+    }
+    __syncthreads();
+
+    // --- Ampere, Eq. (5): E^k = E^{k-1} + dt (curl B^{k-1/2} + J*_face + J_b(t_{k-1/2})) ------
+    const double tb = ((double)a.k - 0.5) * dt;
+    for (int t = tid; t < EZR * EZZ; t += NTHREADS) {
+      const int bb = t / EZZ, aa = t % EZZ;
+      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+      if ((p.per_z || (i >= 0 && i < nz)) && j >= 0 && j < nr) {
+        // (1/r) d(r B)/dr between the edges r = j dr and (j+1) dr; the axis flux vanishes
+        // ((j+1) B_j - j B_{j-1}) written as B_j + j (B_j - B_{j-1}): same value, no large
+        // cancellation at large j in reduced precision
+        const C bj = sBo[bb + 1][aa + 1];
+        const C curl = (bj + (C)j * (bj - sBo[bb][aa + 1])) / ((C)(j + 0.5) * hc);
+        const C jf = C(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
+        const int ci = p.per_z ? wrapi(i, nz) : i;
+        const C jb = driver<C>(p, ((double)(a.s + ci) + 0.5) * h, (j + 0.5) * h, tb);
+        sEz[bb][aa] = sEz[bb][aa] + dtc * (curl + jf + jb);
+      }
+    }
+    for (int t = tid; t < ERR * ERZ; t += NTHREADS) {
+      const int bb = t / ERZ, aa = t % ERZ;
+      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+      if ((p.per_z || (i >= 0 && i < nz)) && j >= 0 && j < nr) {
+        const C curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) / hc;   // -dB/dz
+        const C jf = C(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
+        sEr[bb][aa] = sEr[bb][aa] + dtc * (curl + jf);
+      }
+    }
+    __syncthreads();
+    // ghosts of E^k (R17), z rule first: rear E_z copy, front E_r copy ...
+    if (!p.per_z) {
+      if (i0 == 0)
+        for (int bb = tid; bb < EZR; bb += NTHREADS) sEz[bb][0] = sEz[bb][1];
+      const int af = nz - (i0 - 1);   // LDS column of i = nz
+      if (af >= 1 && af < ERZ)
+        for (int bb = tid; bb < ERR; bb += NTHREADS) sEr[bb][af] = sEr[bb][af - 1];
+    }
+    __syncthreads();
+    // ... then the r rule: outer E_z copy, E_r = 0 on the axis
+    {
+      const int bo = nr - (j0 - 1);   // LDS row of j = nr
+      if (bo >= 1 && bo < EZR)
+        for (int aa = tid; aa < EZZ; aa += NTHREADS) sEz[bo][aa] = sEz[bo - 1][aa];
+    }
+    if (j0 == 0)
+      for (int aa = tid; aa < ERZ; aa += NTHREADS) sEr[0][aa] = C(0);
+    __syncthreads();
+
+    // --- Faraday, Eq. (5) with reading R2: B^{k+1/2} = B^{k-1/2} + dt (dE_z/dr - dE_r/dz) -----
+    for (int t = tid; t < BNR * BNZ; t += NTHREADS) {
+      const int bb = t / BNZ, aa = t % BNZ;
+      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+      C v = C(0);
+      if ((p.per_z || (i >= 0 && i < nz)) && j >= 0 && j < nr) {
+        const C dez = (sEz[bb + 1][aa] - sEz[bb][aa]) / hc;
+        const C der = (sEr[bb][aa + 1] - sEr[bb][aa]) / hc;
+        v = sBo[bb + 1][aa + 1] + dtc * (dez - der);
+      }
+      sBn[bb][aa] = v;
+    }
+    __syncthreads();
+    if (!p.per_z && i0 == 0)
+      for (int bb = tid; bb < BNR; bb += NTHREADS) sBn[bb][0] = sBn[bb][1];   // rear copy
+    __syncthreads();
+  } else {
+    __syncthreads();
+  }
+
+  // --- fluid phase: one site per thread -----------------------------------------------------
+  const int o = o0 + tx;       // output column (post-shift)
+  const int i = i0 + tx;       // logical column (pre-shift)
+  const int j = j0 + ty;
+  if (o >= nz || j >= nr) return;   // no barrier below this point
+  const long long oo = (long long)j * pitch + o;
+  S* gout = (S*)a.g_out;
+  A* Mout = (A*)a.M_out;
+  A* Eout = (A*)a.E_out;
+
+  if (a.shift && i == nz) {
+    // new front column of the moved window (R15): plasma at rest at n_bg, no fields
+    for (int c = 0; c < 27; ++c) stv(gout + c * plane + oo, C(0));
+    stv(Mout + oo, C(0));
+    stv(Mout + plane + oo, C(0));
+    stv(Mout + 2 * plane + oo, C(0));
+    stv(Eout + oo, C(0));
+    stv(Eout + plane + oo, C(0));
+    stv(Eout + 2 * plane + oo, C(0));
+    return;
+  }
+
+  const S* gin = (const S*)a.g_in;
+  const double nref_d = sN[tx + 1];
+  const C nref = (C)nref_d;
+
+  // Eq. (6), pull form: f_q(x) = g_q(x - xi_q); ghost sources are f_eq of the ghost moments
+  // (Eq. (14), R11).  Lattice 0 is carried as the deviation from w_q n_bg(z_i).
+  C f0[9], f1[9], f2[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int si = i - XZ(q), sj = j - XR(q);
+    const bool oz = si < 0 || si >= nz, orr = sj < 0 || sj >= nr;
+    const C w = WQ<C>(q);
+    if ((oz && !p.per_z) || (orr && !p.per_r)) {
+      const int ga = tx + 1 - XZ(q), gb = ty + 1 - XR(q);
+      const C dg = sM[0][gb][ga] + (C)(sN[ga] - nref_d);   // ghost density minus n_bg(z_i)
+      const C m0 = nref + dg, m1 = sM[1][gb][ga], m2 = sM[2][gb][ga];
+      C bz, br;
+      velocity<C>(m0, m1, m2, (C)p.n_floor, bz, br);
+      const C uz = (C)p.lam * bz, ur = (C)p.lam * br;
+      const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+      const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * (uz * uz + ur * ur);
+      f0[q] = w * (dg + m0 * Q);
+      f1[q] = w * m1 * (C(1) + Q);
+      f2[q] = w * m2 * (C(1) + Q);
+    } else {
+      const int pi = oz ? wrapi(si, nz) : si;
+      const int pj = orr ? wrapi(sj, nr) : sj;
+      const long long off = (long long)pj * pitch + pi;
+      const C dn = (C)(sN[tx + 1 - XZ(q)] - nref_d);
+      f0[q] = ldv(gin[q * plane + off]) + w * dn;
+      f1[q] = ldv(gin[(9 + q) * plane + off]);
+      f2[q] = ldv(gin[(18 + q) * plane + off]);
+    }
+  }
+
+  // Eq. (8): zeroth moments; beta_e from the n and n p lattices (R7), floor R19
+  C dA0 = C(0), A1 = C(0), A2 = C(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    dA0 += f0[q];
+    A1 += f1[q];
+    A2 += f2[q];
+  }
+  const C A0 = nref + dA0;
+  C bz, br;
+  const bool live = velocity<C>(A0, A1, A2, (C)p.n_floor, bz, br);
+  const C uz = (C)p.lam * bz, ur = (C)p.lam * br;   // R6
+  const C usq = uz * uz + ur * ur;
+
+  // fields at the site (R12, R13): E^k averaged, B^k = (B^{k-1/2} + B^{k+1/2}) / 2 averaged
+  C Ebz = C(0), Ebr = C(0), Bb = C(0);
+  if (p.fields_on) {
+    Ebz = C(0.5) * (sEz[ty + 1][tx] + sEz[ty + 1][tx + 1]);
+    Ebr = C(0.5) * (sEr[ty][tx + 1] + sEr[ty + 1][tx + 1]);
+    Bb = (sBo[ty + 2][tx + 2] + sBo[ty + 2][tx + 1] + sBo[ty + 1][tx + 2] + sBo[ty + 1][tx + 1] +
+          sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * C(0.125);
+  }
+
+  // Eq. (4): F = -n (E + beta x B), (beta x B)_z = beta_r B, (beta x B)_r = -beta_z B (R8)
+  C F0 = C(0), F1 = C(0), F2 = C(0);
+  if (live) {
+    F1 = A0 * (-(Ebz + br * Bb));
+    F2 = A0 * (-(Ebr - bz * Bb));
+  }
+  if (p.cyl_on) {
+    // Eq. (13): -A u_r / r + D (dA/dr) / r, gradient of the previous step's moments (R10)
+    const C rj = (C)((j + 0.5) * h);
+    const C Dc = (C)p.D, i2h = C(1) / (C(2) * hc);
+    F0 += -A0 * br / rj + Dc * ((sM[0][ty + 2][tx + 1] - sM[0][ty][tx + 1]) * i2h) / rj;
+    F1 += -A1 * br / rj + Dc * ((sM[1][ty + 2][tx + 1] - sM[1][ty][tx + 1]) * i2h) / rj;
+    F2 += -A2 * br / rj + Dc * ((sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1]) * i2h) / rj;
+  }
+
+  // Eqs. (7), (9), (10): BGK toward the equilibrium (coefficients R1) plus w_q dt F (R5)
+  const C itau = (C)(1.0 / p.tau);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const C w = WQ<C>(q);
+    const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+    const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
+    const C e0 = w * (dA0 + A0 * Q);
+    const C e1 = w * A1 * (C(1) + Q);
+    const C e2 = w * A2 * (C(1) + Q);
+    const C wdt = w * dtc;
+    stv(gout + q * plane + oo, f0[q] - (f0[q] - e0) * itau + wdt * F0);
+    stv(gout + (9 + q) * plane + oo, f1[q] - (f1[q] - e1) * itau + wdt * F1);
+    stv(gout + (18 + q) * plane + oo, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+  }
+  stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
+  stv(Mout + plane + oo, A1 + dtc * F1);
+  stv(Mout + 2 * plane + oo, A2 + dtc * F2);
+
+  if (p.fields_on) {
+    stv(Eout + oo, sEz[ty + 1][tx + 1]);
+    stv(Eout + plane + oo, sEr[ty + 1][tx + 1]);
+    stv(Eout + 2 * plane + oo, sBn[ty + 1][tx + 1]);
+  } else {
+    const long long io = (long long)j * pitch + i;
+    stv(Eout + oo, (C)Ein[io]);
+    stv(Eout + plane + oo, (C)Ein[plane + io]);
+    stv(Eout + 2 * plane + oo, (C)Ein[2 * plane + io]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Initial state (FP64 arithmetic, rounded to the storage precision).
+// ------------------------------------------------------------------------------------------
+template <int ST>
+__global__ void init_fluid_kernel(Physics p, const double* n_pert, const double* p_init,
+                                  void* gv, void* Mv) {
+  using S = typename Mode<ST>::S;
+  using A = typename Mode<ST>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= p.nz || j >= p.nr) return;
+  const long long u = (long long)j * p.nz + i;
+  const long long oo = (long long)j * p.pitch + i;
+  const double nb = nbg(p, (double)i * p.h);
+  const double n = n_pert ? nb * (1.0 + n_pert[u]) : nb;
+  const double a1 = p_init ? n * p_init[u] : 0.0;
+  const double a2 = p_init ? n * p_init[(long long)p.nr * p.nz + u] : 0.0;
+  double bz, br;
+  velocity<double>(n, a1, a2, p.n_floor, bz, br);
+  const double uz = p.lam * bz, ur = p.lam * br;
+  S* g = (S*)gv;
+  A* M = (A*)Mv;
+  for (int q = 0; q < 9; ++q) {
+    const double w = WQ<double>(q);
+    const double cu = XZ(q) * uz + XR(q) * ur;
+    const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
+    stv(g + q * p.plane + oo, w * ((n - nb) + n * Q));
+    stv(g + (9 + q) * p.plane + oo, w * a1 * (1.0 + Q));
+    stv(g + (18 + q) * p.plane + oo, w * a2 * (1.0 + Q));
+  }
+  stv(M + oo, n - nb);
+  stv(M + p.plane + oo, a1);
+  stv(M + 2 * p.plane + oo, a2);
+}
+
+// Driver field from the discrete Gauss law: E_r^{-1} at (z_i, t = -dt), B^{-1/2} at
+// (z_i + dz/2, t = -dt/2); E_z = 0.  One thread per column, serial cumulative sum over rows.
+template <int ST>
+__global__ void init_fields_kernel(Physics p, void* Ev) {
+  using A = typename Mode<ST>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.nz) return;
+  A* E = (A*)Ev;
+  double ce = 0.0, cb = 0.0;
+  const double z = (double)i * p.h;
+  for (int j = 0; j < p.nr; ++j) {
+    const long long oo = (long long)j * p.pitch + i;
+    double er = 0.0, b = 0.0;
+    if (p.fields_on) {
+      const double r = (j + 0.5) * p.h;
+      ce += (j + 0.5) * driver<double>(p, z, r, -p.dt);
+      cb += (j + 0.5) * driver<double>(p, z + 0.5 * p.h, r, -0.5 * p.dt);
+      er = -p.h * ce / (j + 1.0);
+      b = -p.h * cb / (j + 1.0);
+    }
+    stv(E + oo, 0.0);
+    stv(E + p.plane + oo, er);
+    stv(E + 2 * p.plane + oo, b);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Outputs, state view, diagnostics
+// ------------------------------------------------------------------------------------------
+template <int ST>
+__global__ void moments_out_kernel(Physics p, long long s, const void* Mv, void* dst, int dst_f64) {
+  using A = typename Mode<ST>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= p.nz || j >= p.nr) return;
+  const A* M = (const A*)Mv;
+  const long long oo = (long long)j * p.pitch + i;
+  const double n = (double)M[oo] + nbg(p, (double)(s + i) * p.h);
+  const double a1 = (double)M[p.plane + oo], a2 = (double)M[2 * p.plane + oo];
+  double bz, br;
+  velocity<double>(n, a1, a2, p.n_floor, bz, br);
+  const long long u = (long long)j * p.nz + i, pl = (long long)p.nr * p.nz;
+  const double v[3] = {n, n * bz, n * br};
+  for (int c = 0; c < 3; ++c) {
+    if (dst_f64) ((double*)dst)[c * pl + u] = v[c];
+    else ((float*)dst)[c * pl + u] = (float)v[c];
+  }
+}
+
+template <int ST>
+__global__ void fields_out_kernel(Physics p, const void* Ev, void* dst, int dst_f64) {
+  using A = typename Mode<ST>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= p.nz || j >= p.nr) return;
+  const A* E = (const A*)Ev;
+  const long long oo = (long long)j * p.pitch + i;
+  const long long u = (long long)j * p.nz + i, pl = (long long)p.nr * p.nz;
+  for (int c = 0; c < 3; ++c) {
+    const double v = (double)E[c * p.plane + oo];
+    if (dst_f64) ((double*)dst)[c * pl + u] = v;
+    else ((float*)dst)[c * pl + u] = (float)v;
+  }
+}
+
+template <int ST>
+__global__ void state_get_kernel(Physics p, long long s, const void* gv, const void* Mv,
+                                 const void* Ev, int c, double* dst) {
+  using S = typename Mode<ST>::S;
+  using A = typename Mode<ST>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= p.nz || j >= p.nr) return;
+  const long long oo = (long long)j * p.pitch + i;
+  double v;
+  if (c < 27) {
+    v = (double)ldv(((const S*)gv)[c * p.plane + oo]);
+    if (c < 9) v += WQ<double>(c) * nbg(p, (double)(s + i) * p.h);
+  } else if (c < 30) {
+    v = (double)((const A*)Mv)[(c - 27) * p.plane + oo];
+    if (c == 27) v += nbg(p, (double)(s + i) * p.h);
+  } else {
+    v = (double)((const A*)Ev)[(c - 30) * p.plane + oo];
+  }
+  dst[(long long)j * p.nz + i] = v;
+}
+
+template <int ST>
+__global__ void state_set_kernel(Physics p, long long s, void* gv, void* Mv, void* Ev, int c,
+                                 const double* src) {
+  using S = typename Mode<ST>::S;
+  using A = typename Mode<ST>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= p.nz || j >= p.nr) return;
+  const long long oo = (long long)j * p.pitch + i;
+  double v = src[(long long)j * p.nz + i];
+  if (c < 27) {
+    if (c < 9) v -= WQ<double>(c) * nbg(p, (double)(s + i) * p.h);
+    stv(((S*)gv) + c * p.plane + oo, v);
+  } else if (c < 30) {
+    if (c == 27) v -= nbg(p, (double)(s + i) * p.h);
+    stv(((A*)Mv) + (c - 27) * p.plane + oo, v);
+  } else {
+    stv(((A*)Ev) + (c - 30) * p.plane + oo, v);
+  }
+}
+
+// Wavefront-then-block reduction of 5 FP64 quantities: 0 sum charge, 1 sum energy,
+// 2 max |Gauss residual|, 3 max |u*|, 4 sum of non-finite counts.
+__device__ __forceinline__ void block_reduce5(double v[5], double* out) {
+  __shared__ double sred[RED_THREADS / 64][5];
+  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+  for (int off = 32; off > 0; off >>= 1) {
+    v[0] += __shfl_down(v[0], off, 64);
+    v[1] += __shfl_down(v[1], off, 64);
+    v[2] = fmax(v[2], __shfl_down(v[2], off, 64));
+    v[3] = fmax(v[3], __shfl_down(v[3], off, 64));
+    v[4] += __shfl_down(v[4], off, 64);
+  }
+  if (lane == 0)
+    for (int c = 0; c < 5; ++c) sred[wid][c] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < RED_THREADS / 64; ++w) {
+      r[0] += sred[w][0];
+      r[1] += sred[w][1];
+      r[2] = fmax(r[2], sred[w][2]);
+      r[3] = fmax(r[3], sred[w][3]);
+      r[4] += sred[w][4];
+    }
+    for (int c = 0; c < 5; ++c) out[c] = r[c];
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, long long k,
+                                                                  long long s, const void* Mv,
+                                                                  const void* Ev,
+                                                                  double* partials) {
+  using A = typename Mode<ST>::A;
+  const long long n = (long long)p.nz * p.nr;
+  const long long u = (long long)blockIdx.x * RED_THREADS + threadIdx.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (u < n) {
+    const int i = (int)(u % p.nz), j = (int)(u / p.nz);
+    const A* M = (const A*)Mv;
+    const A* E = (const A*)Ev;
+    const long long oo = (long long)j * p.pitch + i;
+    const double h = p.h, r = (j + 0.5) * h, re = (j + 1.0) * h;
+    const double z = (double)(s + i) * h;
+    const double nb0 = nbg(p, z);
+    const double m0 = (double)M[oo] + nb0, m1 = M[p.plane + oo], m2 = M[2 * p.plane + oo];
+    const double ez = E[oo], er = E[p.plane + oo], b = E[2 * p.plane + oo];
+    const double twopi = 6.283185307179586;
+    v[0] = twopi * r * h * h * m0;
+    v[1] = 0.5 * twopi * h * h * (r * ez * ez + re * er * er + re * b * b);
+    if (i >= 1) {
+      const double ezl = E[oo - 1];
+      const double erb = j > 0 ? (double)E[p.plane + oo - p.pitch] : 0.0;
+      const double div = (ez - ezl) / h + ((j + 1.0) * er - j * erb) / ((j + 0.5) * h);
+      const double rho = nb0 - m0 - driver<double>(p, z, r, ((double)k - 1.0) * p.dt);
+      v[2] = fabs(div - rho);
+    }
+    double bz, br;
+    velocity<double>(m0, m1, m2, p.n_floor, bz, br);
+    v[3] = p.lam * sqrt(bz * bz + br * br);
+    const double vals[6] = {(double)M[oo], m1, m2, ez, er, b};
+    for (int c = 0; c < 6; ++c) v[4] += isfinite(vals[c]) ? 0.0 : 1.0;
+  }
+  block_reduce5(v, partials + (long long)blockIdx.x * 8);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void diag_final_kernel(const double* partials,
+                                                                int nblocks, double* out) {
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
+    const double* q = partials + (long long)b * 8;
+    v[0] += q[0];
+    v[1] += q[1];
+    v[2] = fmax(v[2], q[2]);
+    v[3] = fmax(v[3], q[3]);
+    v[4] += q[4];
+  }
+  block_reduce5(v, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+#define LBM_DISPATCH(storage, KERNEL, GRID, BLOCK, STREAM, ...)                      \
+  do {                                                                               \
+    if ((storage) == 0) KERNEL<0><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);    \
+    else if ((storage) == 1) KERNEL<1><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__); \
+    else KERNEL<2><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);                   \
+  } while (0)
+
+static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
+
+hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
+  const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
+  LBM_DISPATCH(storage, step_kernel, dim3(gx * gy), dim3(NTHREADS), st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_fluid(int storage, const Physics& p, const double* n_pert,
+                             const double* p_init, void* g, void* M, hipStream_t st) {
+  LBM_DISPATCH(storage, init_fluid_kernel, site_grid(p), dim3(256), st, p, n_pert, p_init, g, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_fields(int storage, const Physics& p, void* E, hipStream_t st) {
+  LBM_DISPATCH(storage, init_fields_kernel, dim3((p.nz + 255) / 256), dim3(256), st, p, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_out(int storage, const Physics& p, long long s, const void* M,
+                              void* dst, int dst_f64, hipStream_t st) {
+  LBM_DISPATCH(storage, moments_out_kernel, site_grid(p), dim3(256), st, p, s, M, dst, dst_f64);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields_out(int storage, const Physics& p, const void* E, void* dst,
+                             int dst_f64, hipStream_t st) {
+  LBM_DISPATCH(storage, fields_out_kernel, site_grid(p), dim3(256), st, p, E, dst, dst_f64);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_get(int storage, const Physics& p, long long s, const void* g,
+                            const void* M, const void* E, int c, double* dst, hipStream_t st) {
+  LBM_DISPATCH(storage, state_get_kernel, site_grid(p), dim3(256), st, p, s, g, M, E, c, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_set(int storage, const Physics& p, long long s, void* g, void* M,
+                            void* E, int c, const double* src, hipStream_t st) {
+  LBM_DISPATCH(storage, state_set_kernel, site_grid(p), dim3(256), st, p, s, g, M, E, c, src);
+  return hipGetLastError();
+}
+
+int diag_blocks(const Physics& p) {
+  const long long n = (long long)p.nz * p.nr;
+  return (int)((n + RED_THREADS - 1) / RED_THREADS);
+}
+
+hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
+                              const void* M, const void* E, double* partials, double* out,
+                              hipStream_t st) {
+  const int nb = diag_blocks(p);
+  LBM_DISPATCH(storage, diag_partial_kernel, dim3(nb), dim3(RED_THREADS), st, p, k, s, M, E,
+               partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  diag_final_kernel<<<1, RED_THREADS, 0, st>>>(partials, nb, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+FP64 storage must match to 1e-10 relative (max-norm per state component).  FP32 and FP16
+storage are compared with the tolerances stated at each test.  Grids are chosen to span several
+64 x 4 tiles with ragged tails in both directions.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import lbm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2201_05473_amd import load_library
+    load_library()
+
+
+def oracle_state(S, P):
+    return np.concatenate([S.g.reshape(27, P.nr, P.nz).numpy(), S.M.numpy(),
+                           np.stack([S.Ez.numpy(), S.Er.numpy(), S.B.numpy()])])
+
+
+# Components that share a physical scale: density populations, momentum populations (n p_z and
+# n p_r lattices), density moment, momentum moments, and the three fields.  Errors are taken
+# relative to the largest reference value of the group, so that a component that is exactly zero
+# up to round-off in the reference (e.g. E_z right after the Gauss-consistent initial state,
+# where the discrete curl of B cancels the driver current) does not make the norm ill-posed.
+GROUPS = [range(0, 9), range(9, 27), range(27, 28), range(28, 30), range(30, 33)]
+
+
+def comp_errors(st, ref):
+    errs = np.zeros(ref.shape[0])
+    if ref.shape[0] != 33:
+        groups = [range(ref.shape[0])]
+    else:
+        groups = GROUPS
+    for g in groups:
+        den = max(np.abs(ref[c]).max() for c in g)
+        for c in g:
+            num = np.abs(st[c] - ref[c]).max()
+            errs[c] = num / den if den > 0 else num
+    return errs
+
+
+def run_gpu(cfg, nsteps, n_pert=None, p_init=None):
+    from paper_2201_05473_amd import Lattice
+    lat = Lattice(cfg, n_pert, p_init)
+    lat.step(nsteps)
+    return lat
+
+
+VARIANTS = {
+    "plain": dict(),
+    "window": dict(moving_window=1),
+    "periodic_z": dict(periodic=1),
+    "periodic_zr_cartesian": dict(periodic=3, fields_on=0, cyl_on=0),
+    "tanh_window": dict(ramp_kind=2, ramp_start=3.0, ramp_len=2.0, moving_window=1),
+    "linear_vacuum_floor": dict(ramp_kind=1, ramp_start=4.5, ramp_len=1.5, moving_window=1, n_floor=1e-8),
+    "fields_off": dict(fields_on=0),
+    "cartesian": dict(cyl_on=0, moving_window=1),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_fp64_parity_variants(name):
+    cfg = wl.config(None, nz=150, nr=13, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3,
+                    zd0=5.0, noise_amp=1e-3, seed=11, storage=wl.F64, **VARIANTS[name])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=3)
+    print(f"[fp64 parity] {name} 150x13, 27 steps", flush=True)
+    lat = run_gpu(cfg, 27, pert, pinit)
+    st, k, s = lat.state()
+    S, P = O.run(cfg, 27, pert, pinit)
+    assert (k, s) == (S.k, S.s)
+    errs = comp_errors(st, oracle_state(S, P))
+    assert errs.max() < TOL64, (errs.argmax(), errs.max())
+
+
+def test_fp64_parity_c1_full_run():
+    """C1 (256 x 64, tau 0.8, weak driver, +-1e-6 noise), all 500 steps, every state value."""
+    cfg = wl.config("C1")
+    pert = wl.density_perturbation(cfg)
+    print("[fp64 parity] C1 256x64, 500 steps", flush=True)
+    lat = run_gpu(cfg, cfg["nsteps"], pert)
+    st, k, s = lat.state()
+    S, P = O.run(cfg, cfg["nsteps"], pert)
+    errs = comp_errors(st, oracle_state(S, P))
+    assert errs.max() < TOL64, (errs.argmax(), errs.max())
+    # outputs through lbm_moments / lbm_fields, device and host placement, FP64 and FP32
+    from paper_2201_05473_amd import LBM_F32, LBM_F64, lbm_fields, lbm_moments
+    mom = lat.moments().cpu().numpy()
+    fld = lat.fields().cpu().numpy()
+    ref_m = O.moments_out(S, P).numpy()
+    ref_f = O.fields_out(S).numpy()
+    assert comp_errors(mom, ref_m).max() < TOL64
+    assert comp_errors(fld, ref_f).max() < TOL64   # [3] arrays: one group each
+    host = np.empty((3, P.nr, P.nz), dtype=np.float32)
+    lbm_moments(lat.ctx, host.ctypes.data, LBM_F32, False)
+    assert comp_errors(host, ref_m).max() < 1e-6
+    host64 = np.empty((3, P.nr, P.nz), dtype=np.float64)
+    lbm_fields(lat.ctx, host64.ctypes.data, LBM_F64, False)
+    assert comp_errors(host64, ref_f).max() < TOL64
+
+
+def test_diagnostics_match_oracle():
+    cfg = wl.config(None, nz=150, nr=13, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3,
+                    zd0=5.0, noise_amp=1e-3, seed=11, storage=wl.F64, moving_window=1,
+                    ramp_kind=2, ramp_start=3.0, ramp_len=2.0)
+    pert = wl.density_perturbation(cfg)
+    lat = run_gpu(cfg, 23, pert)
+    d = lat.diagnostics()
+    S, P = O.run(cfg, 23, pert)
+    r = O.diagnostics(S, P)
+    for key in ("charge", "field_energy", "gauss_max", "umax"):
+        assert abs(d[key] - r[key]) <= 1e-10 * abs(r[key]), key
+    assert (d["step"], d["shifts"], d["nonfinite"]) == (r["step"], r["shifts"], 0)
+
+
+def test_initial_state_gauss_exact_on_gpu():
+    cfg = wl.config("C1", noise_amp=0.0)
+    lat = run_gpu(cfg, 0)
+    d = lat.diagnostics()
+    assert d["gauss_max"] < 1e-14
+    S, P = O.run(cfg, 0)
+    st, _, _ = lat.state()
+    assert comp_errors(st, oracle_state(S, P)).max() < 1e-13
+
+
+def test_checkpoint_resume_is_exact():
+    """lbm_save / lbm_load (native format, host and device buffers): 10 + 10 steps through a
+    restored context equal 20 continuous steps bit for bit; lbm_get_state / lbm_set_state (FP64
+    view) round-trips to round-off."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config(None, nz=100, nr=10, nb=0.2, sigma_z=0.3, sigma_r=0.3, zd0=3.0,
+                    moving_window=1, storage=wl.F64, noise_amp=1e-4, seed=2)
+    pert = wl.density_perturbation(cfg)
+    a = run_gpu(cfg, 20, pert)
+    sa, ka, sa_s = a.state()
+    b = run_gpu(cfg, 10, pert)
+    for on_device in (False, True):
+        ck = b.save(on_device)
+        c = Lattice(cfg)
+        c.load(ck)
+        c.step(10)
+        sc, kc, sc_s = c.state()
+        assert (ka, sa_s) == (kc, sc_s)
+        assert np.array_equal(sa, sc)
+        c.close()
+    st, k, s = b.state()
+    d = Lattice(cfg)
+    d.set_state(st, k, s)
+    sd, kd, sd_s = d.state()
+    assert (kd, sd_s) == (k, s)
+    assert comp_errors(sd, st).max() < 1e-15
+    # a checkpoint of another precision is rejected
+    from paper_2201_05473_amd import LBM_EINVAL, LbmError
+    e32 = Lattice(dict(cfg, storage=wl.F32))
+    with pytest.raises(LbmError) as ei:
+        e32.load(b.save(False))
+    assert ei.value.code == LBM_EINVAL
+
+
+def test_nonfinite_state_is_reported():
+    """Failure detection forced from the host: a NaN planted in one population is caught by the
+    periodic check and lbm_step returns LBM_EUNSTABLE."""
+    from paper_2201_05473_amd import LBM_EUNSTABLE, LbmError, Lattice
+    cfg = wl.config(None, nz=64, nr=8, storage=wl.F32, check_every=2)
+    lat = Lattice(cfg)
+    st, k, s = lat.state()
+    st[5, 3, 10] = np.nan
+    lat.set_state(st, k, s)
+    with pytest.raises(LbmError) as ei:
+        lat.step(4)
+    assert ei.value.code == LBM_EUNSTABLE
+    assert lat.diagnostics()["nonfinite"] > 0
+
+
+def test_fp32_fp16_parity_c2_copy():
+    """C2's 512 x 128 copy with the plasma already around the driver (so that a wake exists and
+    E_z is not a near-cancellation residual), FP32 and FP16 storage against the FP64 oracle
+    after 400 steps: max-norm relative error of n, E_z, E_r."""
+    cfg64 = wl.config("C2s")
+    cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
+    S, P = O.run(cfg64, 400)
+    ref = {"n": S.M[0].numpy(), "Ez": S.Ez.numpy(), "Er": S.Er.numpy()}
+    tol = {wl.F32: 1e-5, wl.F16: 5e-3}
+    errs_all = {}
+    for storage in (wl.F32, wl.F16):
+        cfg = dict(cfg64, storage=storage)
+        print(f"[reduced precision] C2s storage={storage} 400 steps", flush=True)
+        lat = run_gpu(cfg, 400)
+        st, _, _ = lat.state()
+        errs_all[storage] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
+                             "Er": O.rel_err(st[31], ref["Er"])}
+        print(storage, errs_all[storage], flush=True)
+        lat.close()
+    for storage, errs in errs_all.items():
+        assert max(errs.values()) < tol[storage], (storage, errs)
+
+
+def test_full_size_c2_single_steps():
+    """C2 at full size (2048 x 512, the benchmark's launch configuration): one step from the
+    initial state, and one window-shift step (both sides start from their own initial state with
+    the step counter set to 4).  FP64 matches the oracle to 1e-10, FP32 to 1e-6."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C2", storage=wl.F64)
+    for k0 in (0, 4):
+        P = O.Params(cfg)
+        S = O.initial_state(P)
+        S.k = k0
+        S = O.step(S, P)
+        ref = oracle_state(S, P)
+        for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6)):
+            print(f"[full size] C2 k0={k0} storage={storage}", flush=True)
+            lat = Lattice(dict(cfg, storage=storage))
+            st0, _, _ = lat.state()
+            lat.set_state(st0, k0, 0)
+            lat.step(1)
+            st, k, s = lat.state()
+            assert (k, s) == (S.k, S.s)
+            errs = comp_errors(st, ref)
+            if storage == wl.F64:
+                assert errs.max() < tol, (errs.argmax(), errs.max())
+            else:
+                assert errs[27:].max() < tol, errs[27:]
+            lat.close()
+
+
+def test_periodic_conservation_at_full_size():
+    """Property at any size: with periodic z and r, Cartesian and no fields, the global charge
+    is conserved by the step (streaming is a permutation), here at 2048 x 512 in FP64."""
+    cfg = wl.config(None, nz=2048, nr=512, dz=0.02, dr=0.02, periodic=3, fields_on=0, cyl_on=0,
+                    storage=wl.F64, noise_amp=0.1, seed=4)
+    pert = wl.density_perturbation(cfg)
+    lat = run_gpu(cfg, 0, pert, wl.random_momentum(cfg, 0.1, seed=8))
+    st0, _, _ = lat.state()
+    lat.step(50)
+    st1, _, _ = lat.state()
+    for c in (27, 28, 29):
+        assert abs(st1[c].sum() - st0[c].sum()) <= 1e-12 * np.abs(st0[27]).sum()
+    assert np.abs(st1[27] - st0[27]).max() > 1e-4
