@@ -107,6 +107,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline FP32 run only")
+    ap.add_argument("--profile", action="store_true",
+                    help="for rocprofv3: the headline FP32 run only, then a plain 1 GiB device copy "
+                         "(the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--storage", choices=("f64", "f32", "f16"), default="f32",
+                    help="population storage of the --profile run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
@@ -123,6 +128,19 @@ def main():
     cfg = wl.config("C2")
     sites = cfg["nz"] * cfg["nr"]
     steps, warmup = args.steps, args.warmup
+
+    if args.profile:
+        storage = {"f64": wl.F64, "f32": wl.F32, "f16": wl.F16}[args.storage]
+        wall, ev_s, lat = time_run(dict(cfg, storage=storage), steps, warmup)
+        lat.close()
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": True, "storage": args.storage, "steps": steps,
+                          "kernel_avg_us": ev_s / steps * 1e6, "copy_bytes_each_way": a.numel() * 4}))
+        return
 
     # headline: FP32 storage
     wall, ev_s, lat32 = time_run(cfg, steps, warmup)
@@ -141,7 +159,8 @@ def main():
                    "sites": sites, "lattice_LUPS_factor": 3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "bytes_per_site": bps,
+                     "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "alg_bytes_per_launch": bps * sites, "bytes_per_site": bps,
                      "kernel": "lbm::step_kernel<1>", "kernel_avg_us": kern_s * 1e6},
     }
 
