@@ -62,6 +62,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise OSError(f"{p} not found: build it with paper_2201_05473_amd/build.py (no fallback exists)")
+    # torch first: the library then binds to the HIP runtime torch has loaded, so that torch's
+    # device memory and stream handles are valid in it (one runtime per process)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(p)
     P = ctypes.POINTER
     sig = {

@@ -64,11 +64,15 @@ __device__ __forceinline__ C driver(const Physics& p, double z, double r, double
 }
 
 // beta = p / gamma from the moments (Eq. (2), third line); zero at or below the density floor.
+__device__ __forceinline__ float mrsqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double mrsqrt(double x) { return 1.0 / sqrt(x); }
+
 template <typename C>
 __device__ __forceinline__ bool velocity(C n, C a1, C a2, C floor_, C& bz, C& br) {
   if (!(n > floor_)) { bz = C(0); br = C(0); return false; }
-  const C pz = a1 / n, pr = a2 / n;
-  const C ig = C(1) / msqrt(C(1) + pz * pz + pr * pr);
+  const C in = C(1) / n;
+  const C pz = a1 * in, pr = a2 * in;
+  const C ig = mrsqrt(C(1) + pz * pz + pr * pr);
   bz = pz * ig;
   br = pr * ig;
   return true;
@@ -89,8 +93,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 
 // ------------------------------------------------------------------------------------------
 // The fused step kernel.
+//
+// Memory schedule: every thread first issues its share of the halo loads (moments, B^{k-1/2},
+// E^{k-1}) and then its 27 population loads, all from clamped in-range addresses so that every
+// thread issues the same number of loads.  Vector-memory counters retire in order, so the field
+// phase can wait for the halo loads alone while the population loads stay in flight across the
+// LDS barriers (which only wait for LDS traffic).
 // ------------------------------------------------------------------------------------------
-template <int ST>
+template <int ST, bool FIELDS>
 __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using S = typename Mode<ST>::S;
   using C = typename Mode<ST>::C;
@@ -101,6 +111,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   constexpr int EZZ = TZ + 1, EZR = TR + 2;  // E_z:      cols i0-1..i0+TZ-1, rows j0-1..j0+TR
   constexpr int ERZ = TZ + 2, ERR = TR + 1;  // E_r:      cols i0-1..i0+TZ,   rows j0-1..j0+TR-1
   constexpr int BNZ = TZ + 1, BNR = TR + 1;  // B^{k+1/2}: cols i0-1..i0+TZ-1, rows j0-1..j0+TR-1
+  constexpr int NM = MR * MZ, NB = BR * BZ, NEZ = EZR * EZZ, NER = ERR * ERZ;
+  constexpr int SM = (NM + NTHREADS - 1) / NTHREADS, SB = (NB + NTHREADS - 1) / NTHREADS;
+  constexpr int SEZ = (NEZ + NTHREADS - 1) / NTHREADS, SER = (NER + NTHREADS - 1) / NTHREADS;
   __shared__ C sM[3][MR][MZ];
   __shared__ C sJ[2][MR][MZ];
   __shared__ C sBo[BR][BZ];
@@ -108,6 +121,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   __shared__ C sEr[ERR][ERZ];
   __shared__ C sBn[BNR][BNZ];
   __shared__ double sN[MZ];
+  __shared__ C sDz[EZZ];   // exp(-(z - z_d)^2 / 2 sigma_z^2) at the E_z columns
+  __shared__ C sDr[EZR];   // n_b exp(-r^2 / 2 sigma_r^2) at the fluid / E_z rows
+  __shared__ C sIr[EZR];   // 1 / r_j at the fluid / E_z rows
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
@@ -122,124 +138,170 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   const C hc = (C)h, dtc = (C)dt;
   const A* Min = (const A*)a.M_in;
   const A* Ein = (const A*)a.E_in;
+  const S* gin = (const S*)a.g_in;
 
-  // --- background density of the tile's columns (lab position of the physical column) ------
+  // Column of a logical position after the z rule for copies (rear copy, front copy, wrap) and
+  // row after the r rule (axis mirror row 0, outer copy, wrap); always in range.
+  auto zcol = [&](int i) { return p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1)); };
+  auto rrow = [&](int j) { return p.per_r ? wrapi(j, nr) : (j < 0 ? 0 : (j < nr ? j : nr - 1)); };
+  // plane bases (uniform) + 32-bit in-plane offsets (a plane holds fewer than 2^31 elements)
+  const A* M0p = Min;
+  const A* M1p = Min + plane;
+  const A* M2p = Min + 2 * plane;
+  const A* Ezp = Ein;
+  const A* Erp = Ein + plane;
+  const A* Bp = Ein + 2 * plane;
+
+  // --- 1. halo loads into registers --------------------------------------------------------
+  A hm[SM][3];
+  A hb[SB], hez[SEZ], her[SER];
+#pragma unroll
+  for (int s = 0; s < SM; ++s) {
+    const int t = min(tid + s * NTHREADS, NM - 1);
+    const int off = rrow(j0 - 1 + t / MZ) * pitch + zcol(i0 - 1 + t % MZ);
+    hm[s][0] = M0p[off];
+    hm[s][1] = M1p[off];
+    hm[s][2] = M2p[off];
+  }
+  if (FIELDS) {
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int t = min(tid + s * NTHREADS, NB - 1);
+      hb[s] = Bp[rrow(j0 - 2 + t / BZ) * pitch + zcol(i0 - 2 + t % BZ)];
+    }
+#pragma unroll
+    for (int s = 0; s < SEZ; ++s) {
+      const int t = min(tid + s * NTHREADS, NEZ - 1);
+      hez[s] = Ezp[rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ)];
+    }
+#pragma unroll
+    for (int s = 0; s < SER; ++s) {
+      const int t = min(tid + s * NTHREADS, NER - 1);
+      her[s] = Erp[rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ)];
+    }
+  }
+
+  // --- 2. population loads (Eq. (6), pull form f_q(x) = g_q(x - xi_q)) ----------------------
+  const int o = o0 + tx;       // output column (post-shift)
+  const int i = i0 + tx;       // logical column (pre-shift)
+  const int j = j0 + ty;
+  const bool site_ok = o < nz && j < nr;
+  const bool fresh_site = site_ok && a.shift && i == nz;
+  const bool active = site_ok && !fresh_site;
+  S r0[9], r1[9], r2[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    // ghost sources are replaced below; their (in-range) load is discarded
+    const int off = rrow(j - XR(q)) * pitch + zcol(i - XZ(q));
+    r0[q] = (gin + q * plane)[off];
+    r1[q] = (gin + (9 + q) * plane)[off];
+    r2[q] = (gin + (18 + q) * plane)[off];
+  }
+
+  // --- 3. per-column and per-row factors of the tile --------------------------------------
+  // background density at the lab position of the physical column
   for (int t = tid; t < MZ; t += NTHREADS) {
-    const int i = i0 - 1 + t;
-    const int ci = p.per_z ? wrapi(i, nz) : i;
-    sN[t] = nbg(p, (double)(a.s + ci) * h);
+    const int ii = i0 - 1 + t;
+    sN[t] = nbg(p, (double)(a.s + (p.per_z ? wrapi(ii, nz) : ii)) * h);
+  }
+  // the driver density factorises into a column and a row factor
+  const double tb = ((double)a.k - 0.5) * dt;
+  if (FIELDS) {
+    for (int t = tid; t < EZZ; t += NTHREADS) {
+      const int ii = i0 - 1 + t;
+      const int ci = p.per_z ? wrapi(ii, nz) : ii;
+      const C dz = (C)(((double)(a.s + ci) + 0.5) * h - (p.zd0 + tb));
+      sDz[t] = mexp(-(dz * dz) / (C)(2.0 * p.sigma_z * p.sigma_z));
+    }
+  }
+  for (int t = tid; t < EZR; t += NTHREADS) {
+    const double r = (j0 - 1 + t + 0.5) * h;
+    const C rr = (C)r;
+    sDr[t] = (C)p.nb * mexp(-(rr * rr) / (C)(2.0 * p.sigma_r * p.sigma_r));
+    sIr[t] = C(1) / rr;
   }
   __syncthreads();
 
-  // --- moments with the ghost ring (R11: z rule, then r rule) and their current J = n beta ---
-  for (int t = tid; t < MR * MZ; t += NTHREADS) {
-    const int bb = t / MZ, aa = t % MZ;
-    const int i = i0 - 1 + aa, j = j0 - 1 + bb;
-    int ci;
-    bool fresh = false;
-    if (p.per_z) {
-      ci = wrapi(i, nz);
-    } else if (i < 0) {
-      ci = 0;                                   // rear: copy of the first column
-    } else if (i >= nz) {
-      ci = nz - 1;                              // front: copy of the last column ...
-      fresh = p.window && i == nz;              // ... or plasma at rest with the window
-    } else {
-      ci = i;
-    }
-    int rj;
-    C sg = C(1);
-    if (p.per_r) {
-      rj = wrapi(j, nr);
-    } else if (j < 0) {
-      rj = 0;
-      sg = C(-1);                               // axis mirror: n p_r is odd
-    } else {
-      rj = j < nr ? j : nr - 1;                 // outer: copy of the last row
-    }
-    // sM[0] holds the density moment as the deviation from n_bg of this LDS column; a ghost
-    // copied from column ci carries the difference of the two columns' n_bg
-    C d0, m1, m2;
-    if (fresh) {
-      d0 = C(0);
-      m1 = C(0);
-      m2 = C(0);
-    } else {
-      const long long off = (long long)rj * pitch + ci;
-      d0 = (C)Min[off];
-      if (!p.per_z && ci != i) d0 += (C)(sN[ci - (i0 - 1)] - sN[aa]);
-      m1 = (C)Min[plane + off];
-      m2 = sg * (C)Min[2 * plane + off];
-    }
-    sM[0][bb][aa] = d0;
-    sM[1][bb][aa] = m1;
-    sM[2][bb][aa] = m2;
-    if (p.fields_on) {
-      const C m0 = (C)sN[aa] + d0;
-      C bz, br;
-      velocity<C>(m0, m1, m2, (C)p.n_floor, bz, br);
-      sJ[0][bb][aa] = m0 * bz;
-      sJ[1][bb][aa] = m0 * br;
+  // --- 4. moments with the ghost ring (z rule, then r rule) and their current J = n beta ----
+  // sM[0] holds the density moment as the deviation from n_bg of this LDS column; a ghost
+  // copied from another column carries the difference of the two columns' n_bg.
+#pragma unroll
+  for (int s = 0; s < SM; ++s) {
+    const int t = tid + s * NTHREADS;
+    if (t < NM) {
+      const int bb = t / MZ, aa = t % MZ;
+      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
+      const bool fresh = !p.per_z && p.window && ii == nz;   // window front: plasma at rest
+      C d0 = (C)hm[s][0], m1 = (C)hm[s][1], m2 = (C)hm[s][2];
+      if (fresh) {
+        d0 = C(0);
+        m1 = C(0);
+        m2 = C(0);
+      } else if (!p.per_z && (ii < 0 || ii >= nz)) {
+        // the copied column lies inside this LDS tile (the ghost borders it)
+        d0 += (C)(sN[zcol(ii) - (i0 - 1)] - sN[aa]);
+      }
+      if (!p.per_r && jj < 0) m2 = -m2;                     // axis mirror: n p_r is odd
+      sM[0][bb][aa] = d0;
+      sM[1][bb][aa] = m1;
+      sM[2][bb][aa] = m2;
+      if (FIELDS) {
+        const C m0 = (C)sN[aa] + d0;
+        C bz, br;
+        velocity<C>(m0, m1, m2, (C)p.n_floor, bz, br);
+        sJ[0][bb][aa] = m0 * bz;
+        sJ[1][bb][aa] = m0 * br;
+      }
     }
   }
 
-  if (p.fields_on) {
-    // --- load B^{k-1/2}, E^{k-1} (ghosts: B = 0 on the axis, zero-gradient elsewhere) -------
-    for (int t = tid; t < BR * BZ; t += NTHREADS) {
-      const int bb = t / BZ, aa = t % BZ;
-      const int i = i0 - 2 + aa, j = j0 - 2 + bb;
-      C v = C(0);
-      if (j >= 0) {
-        const int rj = j < nr ? j : nr - 1;
-        const int ci = p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1));
-        v = (C)Ein[2 * plane + (long long)rj * pitch + ci];
-      }
-      sBo[bb][aa] = v;
+  if (FIELDS) {
+    // --- 5. B^{k-1/2}, E^{k-1} into LDS (ghosts: B = 0 on the axis, zero-gradient elsewhere) --
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int t = tid + s * NTHREADS;
+      if (t < NB) sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? C(0) : (C)hb[s];
     }
-    for (int t = tid; t < EZR * EZZ; t += NTHREADS) {
-      const int bb = t / EZZ, aa = t % EZZ;
-      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
-      const int rj = j < 0 ? 0 : (j < nr ? j : nr - 1);
-      const int ci = p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1));
-      sEz[bb][aa] = (C)Ein[(long long)rj * pitch + ci];
+#pragma unroll
+    for (int s = 0; s < SEZ; ++s) {
+      const int t = tid + s * NTHREADS;
+      if (t < NEZ) sEz[t / EZZ][t % EZZ] = (C)hez[s];
     }
-    for (int t = tid; t < ERR * ERZ; t += NTHREADS) {
-      const int bb = t / ERZ, aa = t % ERZ;
-      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
-      const int rj = j < 0 ? 0 : (j < nr ? j : nr - 1);
-      const int ci = p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1));
-      sEr[bb][aa] = (C)Ein[plane + (long long)rj * pitch + ci];
+#pragma unroll
+    for (int s = 0; s < SER; ++s) {
+      const int t = tid + s * NTHREADS;
+      if (t < NER) sEr[t / ERZ][t % ERZ] = (C)her[s];
     }
     __syncthreads();
 
-    // --- Ampere, Eq. (5): E^k = E^{k-1} + dt (curl B^{k-1/2} + J*_face + J_b(t_{k-1/2})) ------
-    const double tb = ((double)a.k - 0.5) * dt;
-    for (int t = tid; t < EZR * EZZ; t += NTHREADS) {
+    // --- 6. Ampere, Eq. (5): E^k = E^{k-1} + dt (curl B^{k-1/2} + J*_face + J_b(t_{k-1/2})) ----
+    const C ih = C(1) / hc;
+    for (int t = tid; t < NEZ; t += NTHREADS) {
       const int bb = t / EZZ, aa = t % EZZ;
-      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
-      if ((p.per_z || (i >= 0 && i < nz)) && j >= 0 && j < nr) {
-        // (1/r) d(r B)/dr between the edges r = j dr and (j+1) dr; the axis flux vanishes
-        // ((j+1) B_j - j B_{j-1}) written as B_j + j (B_j - B_{j-1}): same value, no large
-        // cancellation at large j in reduced precision
+      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
+      if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
+        // (1/r) d(r B)/dr = ((j+1) B_j - j B_{j-1}) / r_j with r_j = (j + 1/2) dr, written as
+        // (B_j + j (B_j - B_{j-1})) / r_j: same value, no large cancellation at large j in
+        // reduced precision; the axis flux (j = 0) vanishes
         const C bj = sBo[bb + 1][aa + 1];
-        const C curl = (bj + (C)j * (bj - sBo[bb][aa + 1])) / ((C)(j + 0.5) * hc);
+        const C curl = (bj + (C)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
         const C jf = C(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
-        const int ci = p.per_z ? wrapi(i, nz) : i;
-        const C jb = driver<C>(p, ((double)(a.s + ci) + 0.5) * h, (j + 0.5) * h, tb);
+        const C jb = sDz[aa] * sDr[bb];
         sEz[bb][aa] = sEz[bb][aa] + dtc * (curl + jf + jb);
       }
     }
-    for (int t = tid; t < ERR * ERZ; t += NTHREADS) {
+    for (int t = tid; t < NER; t += NTHREADS) {
       const int bb = t / ERZ, aa = t % ERZ;
-      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
-      if ((p.per_z || (i >= 0 && i < nz)) && j >= 0 && j < nr) {
-        const C curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) / hc;   // -dB/dz
+      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
+      if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
+        const C curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) * ih;   // -dB/dz
         const C jf = C(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
         sEr[bb][aa] = sEr[bb][aa] + dtc * (curl + jf);
       }
     }
     __syncthreads();
-    // ghosts of E^k (R17), z rule first: rear E_z copy, front E_r copy ...
+    // ghosts of E^k (zero-gradient fields, E_r = 0 on the axis), z rule first: rear E_z copy,
+    // front E_r copy ...
     if (!p.per_z) {
       if (i0 == 0)
         for (int bb = tid; bb < EZR; bb += NTHREADS) sEz[bb][0] = sEz[bb][1];
@@ -258,14 +320,14 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       for (int aa = tid; aa < ERZ; aa += NTHREADS) sEr[0][aa] = C(0);
     __syncthreads();
 
-    // --- Faraday, Eq. (5) with reading R2: B^{k+1/2} = B^{k-1/2} + dt (dE_z/dr - dE_r/dz) -----
+    // --- 7. Faraday, Eq. (5) with the standard sign: B^{k+1/2} = B^{k-1/2} + dt (dE_z/dr - dE_r/dz)
     for (int t = tid; t < BNR * BNZ; t += NTHREADS) {
       const int bb = t / BNZ, aa = t % BNZ;
-      const int i = i0 - 1 + aa, j = j0 - 1 + bb;
+      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
       C v = C(0);
-      if ((p.per_z || (i >= 0 && i < nz)) && j >= 0 && j < nr) {
-        const C dez = (sEz[bb + 1][aa] - sEz[bb][aa]) / hc;
-        const C der = (sEr[bb][aa + 1] - sEr[bb][aa]) / hc;
+      if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
+        const C dez = (sEz[bb + 1][aa] - sEz[bb][aa]) * ih;
+        const C der = (sEr[bb][aa + 1] - sEr[bb][aa]) * ih;
         v = sBo[bb + 1][aa + 1] + dtc * (dez - der);
       }
       sBn[bb][aa] = v;
@@ -278,18 +340,16 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     __syncthreads();
   }
 
-  // --- fluid phase: one site per thread -----------------------------------------------------
-  const int o = o0 + tx;       // output column (post-shift)
-  const int i = i0 + tx;       // logical column (pre-shift)
-  const int j = j0 + ty;
-  if (o >= nz || j >= nr) return;   // no barrier below this point
-  const long long oo = (long long)j * pitch + o;
+  // --- 8. fluid phase: one site per thread ------------------------------------------------
+  if (!site_ok) return;   // no barrier below this point
+  const int oo32 = j * pitch + o;
+  const long long oo = oo32;
   S* gout = (S*)a.g_out;
   A* Mout = (A*)a.M_out;
   A* Eout = (A*)a.E_out;
 
-  if (a.shift && i == nz) {
-    // new front column of the moved window (R15): plasma at rest at n_bg, no fields
+  if (fresh_site) {
+    // new front column of the moved window: plasma at rest at n_bg, no fields
     for (int c = 0; c < 27; ++c) stv(gout + c * plane + oo, C(0));
     stv(Mout + oo, C(0));
     stv(Mout + plane + oo, C(0));
@@ -300,12 +360,12 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     return;
   }
 
-  const S* gin = (const S*)a.g_in;
   const double nref_d = sN[tx + 1];
   const C nref = (C)nref_d;
 
-  // Eq. (6), pull form: f_q(x) = g_q(x - xi_q); ghost sources are f_eq of the ghost moments
-  // (Eq. (14), R11).  Lattice 0 is carried as the deviation from w_q n_bg(z_i).
+  // Ghost sources take f_eq of the ghost moments (Eq. (14): boundary populations at the
+  // equilibrium of the boundary values).  Lattice 0 is carried as the deviation from
+  // w_q n_bg(z_i).
   C f0[9], f1[9], f2[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -325,17 +385,14 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       f1[q] = w * m1 * (C(1) + Q);
       f2[q] = w * m2 * (C(1) + Q);
     } else {
-      const int pi = oz ? wrapi(si, nz) : si;
-      const int pj = orr ? wrapi(sj, nr) : sj;
-      const long long off = (long long)pj * pitch + pi;
       const C dn = (C)(sN[tx + 1 - XZ(q)] - nref_d);
-      f0[q] = ldv(gin[q * plane + off]) + w * dn;
-      f1[q] = ldv(gin[(9 + q) * plane + off]);
-      f2[q] = ldv(gin[(18 + q) * plane + off]);
+      f0[q] = ldv(r0[q]) + w * dn;
+      f1[q] = ldv(r1[q]);
+      f2[q] = ldv(r2[q]);
     }
   }
 
-  // Eq. (8): zeroth moments; beta_e from the n and n p lattices (R7), floor R19
+  // Eq. (8): zeroth moments; the advecting velocity is beta_e from the n and n p lattices
   C dA0 = C(0), A1 = C(0), A2 = C(0);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -346,34 +403,34 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   const C A0 = nref + dA0;
   C bz, br;
   const bool live = velocity<C>(A0, A1, A2, (C)p.n_floor, bz, br);
-  const C uz = (C)p.lam * bz, ur = (C)p.lam * br;   // R6
+  const C uz = (C)p.lam * bz, ur = (C)p.lam * br;   // lattice velocity u* = beta c dt/dz
   const C usq = uz * uz + ur * ur;
 
-  // fields at the site (R12, R13): E^k averaged, B^k = (B^{k-1/2} + B^{k+1/2}) / 2 averaged
+  // fields at the site: E^k averaged, B^k = (B^{k-1/2} + B^{k+1/2}) / 2 averaged
   C Ebz = C(0), Ebr = C(0), Bb = C(0);
-  if (p.fields_on) {
+  if (FIELDS) {
     Ebz = C(0.5) * (sEz[ty + 1][tx] + sEz[ty + 1][tx + 1]);
     Ebr = C(0.5) * (sEr[ty][tx + 1] + sEr[ty + 1][tx + 1]);
     Bb = (sBo[ty + 2][tx + 2] + sBo[ty + 2][tx + 1] + sBo[ty + 1][tx + 2] + sBo[ty + 1][tx + 1] +
           sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * C(0.125);
   }
 
-  // Eq. (4): F = -n (E + beta x B), (beta x B)_z = beta_r B, (beta x B)_r = -beta_z B (R8)
+  // Eq. (4): F = -n (E + beta x B), (beta x B)_z = beta_r B, (beta x B)_r = -beta_z B
   C F0 = C(0), F1 = C(0), F2 = C(0);
   if (live) {
     F1 = A0 * (-(Ebz + br * Bb));
     F2 = A0 * (-(Ebr - bz * Bb));
   }
   if (p.cyl_on) {
-    // Eq. (13): -A u_r / r + D (dA/dr) / r, gradient of the previous step's moments (R10)
-    const C rj = (C)((j + 0.5) * h);
-    const C Dc = (C)p.D, i2h = C(1) / (C(2) * hc);
-    F0 += -A0 * br / rj + Dc * ((sM[0][ty + 2][tx + 1] - sM[0][ty][tx + 1]) * i2h) / rj;
-    F1 += -A1 * br / rj + Dc * ((sM[1][ty + 2][tx + 1] - sM[1][ty][tx + 1]) * i2h) / rj;
-    F2 += -A2 * br / rj + Dc * ((sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1]) * i2h) / rj;
+    // Eq. (13): -A u_r / r + D (dA/dr) / r, gradient of the previous step's moments
+    const C ir = sIr[ty + 1];
+    const C Dc = (C)p.D * C(0.5) / hc;
+    F0 += (-A0 * br + Dc * (sM[0][ty + 2][tx + 1] - sM[0][ty][tx + 1])) * ir;
+    F1 += (-A1 * br + Dc * (sM[1][ty + 2][tx + 1] - sM[1][ty][tx + 1])) * ir;
+    F2 += (-A2 * br + Dc * (sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1])) * ir;
   }
 
-  // Eqs. (7), (9), (10): BGK toward the equilibrium (coefficients R1) plus w_q dt F (R5)
+  // Eqs. (7), (9), (10): BGK toward the equilibrium (standard D2Q9 coefficients) plus w_q dt F
   const C itau = (C)(1.0 / p.tau);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -384,15 +441,15 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     const C e1 = w * A1 * (C(1) + Q);
     const C e2 = w * A2 * (C(1) + Q);
     const C wdt = w * dtc;
-    stv(gout + q * plane + oo, f0[q] - (f0[q] - e0) * itau + wdt * F0);
-    stv(gout + (9 + q) * plane + oo, f1[q] - (f1[q] - e1) * itau + wdt * F1);
-    stv(gout + (18 + q) * plane + oo, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+    stv(gout + q * plane + oo32, f0[q] - (f0[q] - e0) * itau + wdt * F0);
+    stv(gout + (9 + q) * plane + oo32, f1[q] - (f1[q] - e1) * itau + wdt * F1);
+    stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
   }
   stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
   stv(Mout + plane + oo, A1 + dtc * F1);
   stv(Mout + 2 * plane + oo, A2 + dtc * F2);
 
-  if (p.fields_on) {
+  if (FIELDS) {
     stv(Eout + oo, sEz[ty + 1][tx + 1]);
     stv(Eout + plane + oo, sEr[ty + 1][tx + 1]);
     stv(Eout + 2 * plane + oo, sBn[ty + 1][tx + 1]);
@@ -639,9 +696,18 @@ __global__ __launch_bounds__(RED_THREADS) void diag_final_kernel(const double* p
 
 static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
 
+template <int ST>
+static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
+  if (a.p.fields_on) step_kernel<ST, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else step_kernel<ST, false><<<grid, dim3(NTHREADS), 0, st>>>(a);
+}
+
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
   const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
-  LBM_DISPATCH(storage, step_kernel, dim3(gx * gy), dim3(NTHREADS), st, a);
+  const dim3 grid(gx * gy);
+  if (storage == 0) launch_step_t<0>(a, grid, st);
+  else if (storage == 1) launch_step_t<1>(a, grid, st);
+  else launch_step_t<2>(a, grid, st);
   return hipGetLastError();
 }
 
