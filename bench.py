@@ -165,35 +165,38 @@ def main():
     }
 
     if not args.no_extra:
-        modes = {}
-        # FP64 and FP16 at the same workload and step count, with the FP32/FP16 error vs FP64
+        # the other storage / arithmetic modes at the same workload and step count, with the
+        # max-norm error of E_z, E_r and n against the FP64 run
         ref_f = lat32.fields()
         ref_m = lat32.moments()
         lat32.close()
-        res = {}
-        for storage, name in ((wl.F64, "f64"), (wl.F16, "f16")):
-            w, e, lat = time_run(dict(cfg, storage=storage), steps, warmup)
-            res[name] = (w, e, lat.fields(), lat.moments())
+        runs = {"f32": (wl.F32, 0, wall, ev_s, ref_f, ref_m)}
+        for name, storage, m64 in (("f64", wl.F64, 0), ("f32_fp64math", wl.F32, 1),
+                                   ("f16", wl.F16, 0)):
+            w, e, lat = time_run(dict(cfg, storage=storage, fp64_math=m64), steps, warmup)
+            runs[name] = (storage, m64, w, e, lat.fields(), lat.moments())
             lat.close()
-        f64_f, f64_m = res["f64"][2], res["f64"][3]
-        for name, storage, w, e, fl, mo in (
-                ("f32", wl.F32, wall, ev_s, ref_f, ref_m),
-                ("f64", wl.F64, *res["f64"]),
-                ("f16", wl.F16, *res["f16"])):
+        f64_f, f64_m = runs["f64"][4], runs["f64"][5]
+        modes = {}
+        for name, (storage, m64, w, e, fl, mo) in runs.items():
             b = bytes_per_site(storage)
             modes[name] = {
+                "storage": {0: "f64", 1: "f32", 2: "f16"}[storage],
+                "arithmetic": "f64" if (storage == 0 or m64) else "f32",
                 "MLUPS": sites * steps / w / 1e6,
                 "alg_GBps": b * sites / (e / steps) / 1e9,
+                "frac_of_peak": b * sites / (e / steps) / 1e9 / PEAK_HBM_GBS,
                 "bytes_per_site": b,
                 "err_vs_f64": None if name == "f64" else {
                     "Ez": rel_err(fl[0], f64_f[0]), "Er": rel_err(fl[1], f64_f[1]),
                     "n": rel_err(mo[0], f64_m[0])},
             }
         out["modes_C2"] = modes
-        # HBM-scale: C3 lattice (4096 x 1024) per storage, 1000 steps
+        # HBM-scale lattice (C3, 4096 x 1024, working set well above the 256 MB Infinity Cache)
         c3 = {}
-        for storage, name in ((wl.F32, "f32"), (wl.F64, "f64"), (wl.F16, "f16")):
-            ccfg = wl.config("C3", storage=storage)
+        for name, storage, m64 in (("f32", wl.F32, 0), ("f32_fp64math", wl.F32, 1),
+                                   ("f64", wl.F64, 0), ("f16", wl.F16, 0)):
+            ccfg = wl.config("C3", storage=storage, fp64_math=m64)
             n3 = ccfg["nz"] * ccfg["nr"]
             w, e, lat = time_run(ccfg, 1000, 50)
             lat.close()

@@ -68,7 +68,9 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
  *                 driver density n_b exp(-(z - zd0 - t)^2 / 2 sigma_z^2 - r^2 / 2 sigma_r^2)
  *   n_floor       densities at or below it carry no momentum, current or force
  *   check_every   > 0: every that many steps lbm_step synchronises and checks for non-finite
- *                 values (LBM_EUNSTABLE); 0: no checks */
+ *                 values (LBM_EUNSTABLE); 0: no checks
+ *   fp64_math     1: FP64 arithmetic in the step for FP32 / FP16 storage (storage unchanged);
+ *                 0: arithmetic in FP32.  Ignored for LBM_F64 (always FP64). */
 typedef struct {
   int32_t nz, nr;
   double dz, dr, c_dt_over_dz, tau;
@@ -80,6 +82,7 @@ typedef struct {
   double nb, sigma_z, sigma_r, zd0;
   double n_floor;
   int32_t check_every;
+  int32_t fp64_math;
 } lbm_config;
 
 /* FP64 diagnostics of the current state (all sums over the window):

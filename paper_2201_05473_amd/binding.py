@@ -35,6 +35,7 @@ class LbmConfig(ctypes.Structure):
         ("nb", c_double), ("sigma_z", c_double), ("sigma_r", c_double), ("zd0", c_double),
         ("n_floor", c_double),
         ("check_every", c_int32),
+        ("fp64_math", c_int32),
     ]
 
 

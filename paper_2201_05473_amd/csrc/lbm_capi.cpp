@@ -75,6 +75,7 @@ int validate(const lbm_config* c, Physics* p) {
     return fail(LBM_EINVAL, "driver sizes must be positive");
   if (!(c->n_floor >= 0.0)) return fail(LBM_EINVAL, "n_floor must be >= 0");
   if (c->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+  if (c->fp64_math != 0 && c->fp64_math != 1) return fail(LBM_EINVAL, "fp64_math must be 0 or 1");
   if (p) {
     Physics& q = *p;
     std::memset(&q, 0, sizeof q);
@@ -102,6 +103,7 @@ int validate(const lbm_config* c, Physics* p) {
     q.per_r = per_r;
     q.fields_on = c->fields_on ? 1 : 0;
     q.cyl_on = c->cyl_on ? 1 : 0;
+    q.fp64_math = c->fp64_math;
   }
   return LBM_OK;
 }

@@ -25,6 +25,7 @@ struct Physics {
   int ramp_kind;
   double nb, sigma_z, sigma_r, zd0;
   int window, m, per_z, per_r, fields_on, cyl_on;
+  int fp64_math;            // FP64 arithmetic for FP32 / FP16 storage
 };
 
 // One launch of the fused step: physics + time counters + buffers.

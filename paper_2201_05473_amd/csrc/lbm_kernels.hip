@@ -15,10 +15,16 @@ namespace lbm {
 // ------------------------------------------------------------------------------------------
 // Precision modes: population storage S, arithmetic C, auxiliary (moments, fields) storage A.
 // ------------------------------------------------------------------------------------------
-template <int ST> struct Mode;
-template <> struct Mode<0> { using S = double; using C = double; using A = double; };
-template <> struct Mode<1> { using S = float;  using C = float;  using A = float;  };
-template <> struct Mode<2> { using S = __half; using C = float;  using A = float;  };
+// C: arithmetic of the fluid phase; CF: arithmetic of the field phase and of the moment halo
+// (LDS tiles).  M64 selects FP64 arithmetic for FP32 / FP16 storage: FP64 vector FMAs issue at
+// the FP32 rate here (packed FP32 is not used), so exact-in-FP64 collision sums cost little in
+// this memory-bound kernel, while FP32 collision sums leak ~1e-8 of mass per site and step.
+template <int ST, bool M64> struct Mode;
+template <bool M64> struct Mode<0, M64> { using S = double; using C = double; using A = double; using CF = double; };
+template <> struct Mode<1, false> { using S = float;  using C = float;  using A = float;  using CF = float; };
+template <> struct Mode<1, true>  { using S = float;  using C = double; using A = float;  using CF = double; };
+template <> struct Mode<2, false> { using S = __half; using C = float;  using A = float;  using CF = float; };
+template <> struct Mode<2, true>  { using S = __half; using C = double; using A = float;  using CF = double; };
 
 __device__ __forceinline__ double ldv(double x) { return x; }
 __device__ __forceinline__ float ldv(float x) { return x; }
@@ -100,11 +106,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // phase can wait for the halo loads alone while the population loads stay in flight across the
 // LDS barriers (which only wait for LDS traffic).
 // ------------------------------------------------------------------------------------------
-template <int ST, bool FIELDS>
+template <int ST, bool FIELDS, bool M64>
 __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
-  using S = typename Mode<ST>::S;
-  using C = typename Mode<ST>::C;
-  using A = typename Mode<ST>::A;
+  using S = typename Mode<ST, M64>::S;
+  using C = typename Mode<ST, M64>::C;
+  using A = typename Mode<ST, M64>::A;
+  using CF = typename Mode<ST, M64>::CF;
   const Physics& p = a.p;
   constexpr int MZ = TZ + 2, MR = TR + 2;    // moments:  cols i0-1..i0+TZ,   rows j0-1..j0+TR
   constexpr int BZ = TZ + 3, BR = TR + 3;    // B^{k-1/2}: cols i0-2..i0+TZ,  rows j0-2..j0+TR
@@ -114,16 +121,16 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   constexpr int NM = MR * MZ, NB = BR * BZ, NEZ = EZR * EZZ, NER = ERR * ERZ;
   constexpr int SM = (NM + NTHREADS - 1) / NTHREADS, SB = (NB + NTHREADS - 1) / NTHREADS;
   constexpr int SEZ = (NEZ + NTHREADS - 1) / NTHREADS, SER = (NER + NTHREADS - 1) / NTHREADS;
-  __shared__ C sM[3][MR][MZ];
-  __shared__ C sJ[2][MR][MZ];
-  __shared__ C sBo[BR][BZ];
-  __shared__ C sEz[EZR][EZZ];
-  __shared__ C sEr[ERR][ERZ];
-  __shared__ C sBn[BNR][BNZ];
+  __shared__ CF sM[3][MR][MZ];
+  __shared__ CF sJ[2][MR][MZ];
+  __shared__ CF sBo[BR][BZ];
+  __shared__ CF sEz[EZR][EZZ];
+  __shared__ CF sEr[ERR][ERZ];
+  __shared__ CF sBn[BNR][BNZ];
   __shared__ double sN[MZ];
-  __shared__ C sDz[EZZ];   // exp(-(z - z_d)^2 / 2 sigma_z^2) at the E_z columns
-  __shared__ C sDr[EZR];   // n_b exp(-r^2 / 2 sigma_r^2) at the fluid / E_z rows
-  __shared__ C sIr[EZR];   // 1 / r_j at the fluid / E_z rows
+  __shared__ CF sDz[EZZ];   // exp(-(z - z_d)^2 / 2 sigma_z^2) at the E_z columns
+  __shared__ CF sDr[EZR];   // n_b exp(-r^2 / 2 sigma_r^2) at the fluid / E_z rows
+  __shared__ CF sIr[EZR];   // 1 / r_j at the fluid / E_z rows
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
@@ -136,6 +143,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   const int tx = tid % TZ, ty = tid / TZ;
   const double h = p.h, dt = p.dt;
   const C hc = (C)h, dtc = (C)dt;
+  const CF hf = (CF)h, dtf = (CF)dt;
   const A* Min = (const A*)a.M_in;
   const A* Ein = (const A*)a.E_in;
   const S* gin = (const S*)a.g_in;
@@ -210,15 +218,15 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     for (int t = tid; t < EZZ; t += NTHREADS) {
       const int ii = i0 - 1 + t;
       const int ci = p.per_z ? wrapi(ii, nz) : ii;
-      const C dz = (C)(((double)(a.s + ci) + 0.5) * h - (p.zd0 + tb));
-      sDz[t] = mexp(-(dz * dz) / (C)(2.0 * p.sigma_z * p.sigma_z));
+      const CF dz = (CF)(((double)(a.s + ci) + 0.5) * h - (p.zd0 + tb));
+      sDz[t] = mexp(-(dz * dz) / (CF)(2.0 * p.sigma_z * p.sigma_z));
     }
   }
   for (int t = tid; t < EZR; t += NTHREADS) {
     const double r = (j0 - 1 + t + 0.5) * h;
-    const C rr = (C)r;
-    sDr[t] = (C)p.nb * mexp(-(rr * rr) / (C)(2.0 * p.sigma_r * p.sigma_r));
-    sIr[t] = C(1) / rr;
+    const CF rr = (CF)r;
+    sDr[t] = (CF)p.nb * mexp(-(rr * rr) / (CF)(2.0 * p.sigma_r * p.sigma_r));
+    sIr[t] = CF(1) / rr;
   }
   __syncthreads();
 
@@ -232,23 +240,23 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       const int bb = t / MZ, aa = t % MZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
       const bool fresh = !p.per_z && p.window && ii == nz;   // window front: plasma at rest
-      C d0 = (C)hm[s][0], m1 = (C)hm[s][1], m2 = (C)hm[s][2];
+      CF d0 = (CF)hm[s][0], m1 = (CF)hm[s][1], m2 = (CF)hm[s][2];
       if (fresh) {
-        d0 = C(0);
-        m1 = C(0);
-        m2 = C(0);
+        d0 = CF(0);
+        m1 = CF(0);
+        m2 = CF(0);
       } else if (!p.per_z && (ii < 0 || ii >= nz)) {
         // the copied column lies inside this LDS tile (the ghost borders it)
-        d0 += (C)(sN[zcol(ii) - (i0 - 1)] - sN[aa]);
+        d0 += (CF)(sN[zcol(ii) - (i0 - 1)] - sN[aa]);
       }
       if (!p.per_r && jj < 0) m2 = -m2;                     // axis mirror: n p_r is odd
       sM[0][bb][aa] = d0;
       sM[1][bb][aa] = m1;
       sM[2][bb][aa] = m2;
       if (FIELDS) {
-        const C m0 = (C)sN[aa] + d0;
-        C bz, br;
-        velocity<C>(m0, m1, m2, (C)p.n_floor, bz, br);
+        const CF m0 = (CF)sN[aa] + d0;
+        CF bz, br;
+        velocity<CF>(m0, m1, m2, (CF)p.n_floor, bz, br);
         sJ[0][bb][aa] = m0 * bz;
         sJ[1][bb][aa] = m0 * br;
       }
@@ -260,22 +268,22 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       const int t = tid + s * NTHREADS;
-      if (t < NB) sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? C(0) : (C)hb[s];
+      if (t < NB) sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? CF(0) : (CF)hb[s];
     }
 #pragma unroll
     for (int s = 0; s < SEZ; ++s) {
       const int t = tid + s * NTHREADS;
-      if (t < NEZ) sEz[t / EZZ][t % EZZ] = (C)hez[s];
+      if (t < NEZ) sEz[t / EZZ][t % EZZ] = (CF)hez[s];
     }
 #pragma unroll
     for (int s = 0; s < SER; ++s) {
       const int t = tid + s * NTHREADS;
-      if (t < NER) sEr[t / ERZ][t % ERZ] = (C)her[s];
+      if (t < NER) sEr[t / ERZ][t % ERZ] = (CF)her[s];
     }
     __syncthreads();
 
     // --- 6. Ampere, Eq. (5): E^k = E^{k-1} + dt (curl B^{k-1/2} + J*_face + J_b(t_{k-1/2})) ----
-    const C ih = C(1) / hc;
+    const CF ih = CF(1) / hf;
     for (int t = tid; t < NEZ; t += NTHREADS) {
       const int bb = t / EZZ, aa = t % EZZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
@@ -283,20 +291,20 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
         // (1/r) d(r B)/dr = ((j+1) B_j - j B_{j-1}) / r_j with r_j = (j + 1/2) dr, written as
         // (B_j + j (B_j - B_{j-1})) / r_j: same value, no large cancellation at large j in
         // reduced precision; the axis flux (j = 0) vanishes
-        const C bj = sBo[bb + 1][aa + 1];
-        const C curl = (bj + (C)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
-        const C jf = C(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
-        const C jb = sDz[aa] * sDr[bb];
-        sEz[bb][aa] = sEz[bb][aa] + dtc * (curl + jf + jb);
+        const CF bj = sBo[bb + 1][aa + 1];
+        const CF curl = (bj + (CF)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
+        const CF jf = CF(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
+        const CF jb = sDz[aa] * sDr[bb];
+        sEz[bb][aa] = sEz[bb][aa] + dtf * (curl + jf + jb);
       }
     }
     for (int t = tid; t < NER; t += NTHREADS) {
       const int bb = t / ERZ, aa = t % ERZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
       if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
-        const C curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) * ih;   // -dB/dz
-        const C jf = C(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
-        sEr[bb][aa] = sEr[bb][aa] + dtc * (curl + jf);
+        const CF curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) * ih;   // -dB/dz
+        const CF jf = CF(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
+        sEr[bb][aa] = sEr[bb][aa] + dtf * (curl + jf);
       }
     }
     __syncthreads();
@@ -317,18 +325,18 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
         for (int aa = tid; aa < EZZ; aa += NTHREADS) sEz[bo][aa] = sEz[bo - 1][aa];
     }
     if (j0 == 0)
-      for (int aa = tid; aa < ERZ; aa += NTHREADS) sEr[0][aa] = C(0);
+      for (int aa = tid; aa < ERZ; aa += NTHREADS) sEr[0][aa] = CF(0);
     __syncthreads();
 
     // --- 7. Faraday, Eq. (5) with the standard sign: B^{k+1/2} = B^{k-1/2} + dt (dE_z/dr - dE_r/dz)
     for (int t = tid; t < BNR * BNZ; t += NTHREADS) {
       const int bb = t / BNZ, aa = t % BNZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
-      C v = C(0);
+      CF v = CF(0);
       if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
-        const C dez = (sEz[bb + 1][aa] - sEz[bb][aa]) * ih;
-        const C der = (sEr[bb][aa + 1] - sEr[bb][aa]) * ih;
-        v = sBo[bb + 1][aa + 1] + dtc * (dez - der);
+        const CF dez = (sEz[bb + 1][aa] - sEz[bb][aa]) * ih;
+        const CF der = (sEr[bb][aa + 1] - sEr[bb][aa]) * ih;
+        v = sBo[bb + 1][aa + 1] + dtf * (dez - der);
       }
       sBn[bb][aa] = v;
     }
@@ -374,8 +382,8 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     const C w = WQ<C>(q);
     if ((oz && !p.per_z) || (orr && !p.per_r)) {
       const int ga = tx + 1 - XZ(q), gb = ty + 1 - XR(q);
-      const C dg = sM[0][gb][ga] + (C)(sN[ga] - nref_d);   // ghost density minus n_bg(z_i)
-      const C m0 = nref + dg, m1 = sM[1][gb][ga], m2 = sM[2][gb][ga];
+      const C dg = (C)sM[0][gb][ga] + (C)(sN[ga] - nref_d);   // ghost density minus n_bg(z_i)
+      const C m0 = nref + dg, m1 = (C)sM[1][gb][ga], m2 = (C)sM[2][gb][ga];
       C bz, br;
       velocity<C>(m0, m1, m2, (C)p.n_floor, bz, br);
       const C uz = (C)p.lam * bz, ur = (C)p.lam * br;
@@ -409,10 +417,10 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   // fields at the site: E^k averaged, B^k = (B^{k-1/2} + B^{k+1/2}) / 2 averaged
   C Ebz = C(0), Ebr = C(0), Bb = C(0);
   if (FIELDS) {
-    Ebz = C(0.5) * (sEz[ty + 1][tx] + sEz[ty + 1][tx + 1]);
-    Ebr = C(0.5) * (sEr[ty][tx + 1] + sEr[ty + 1][tx + 1]);
-    Bb = (sBo[ty + 2][tx + 2] + sBo[ty + 2][tx + 1] + sBo[ty + 1][tx + 2] + sBo[ty + 1][tx + 1] +
-          sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * C(0.125);
+    Ebz = (C)(CF(0.5) * (sEz[ty + 1][tx] + sEz[ty + 1][tx + 1]));
+    Ebr = (C)(CF(0.5) * (sEr[ty][tx + 1] + sEr[ty + 1][tx + 1]));
+    Bb = (C)((sBo[ty + 2][tx + 2] + sBo[ty + 2][tx + 1] + sBo[ty + 1][tx + 2] + sBo[ty + 1][tx + 1] +
+              sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * CF(0.125));
   }
 
   // Eq. (4): F = -n (E + beta x B), (beta x B)_z = beta_r B, (beta x B)_r = -beta_z B
@@ -423,11 +431,11 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   }
   if (p.cyl_on) {
     // Eq. (13): -A u_r / r + D (dA/dr) / r, gradient of the previous step's moments
-    const C ir = sIr[ty + 1];
+    const C ir = (C)sIr[ty + 1];
     const C Dc = (C)p.D * C(0.5) / hc;
-    F0 += (-A0 * br + Dc * (sM[0][ty + 2][tx + 1] - sM[0][ty][tx + 1])) * ir;
-    F1 += (-A1 * br + Dc * (sM[1][ty + 2][tx + 1] - sM[1][ty][tx + 1])) * ir;
-    F2 += (-A2 * br + Dc * (sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1])) * ir;
+    F0 += (-A0 * br + Dc * (C)(sM[0][ty + 2][tx + 1] - sM[0][ty][tx + 1])) * ir;
+    F1 += (-A1 * br + Dc * (C)(sM[1][ty + 2][tx + 1] - sM[1][ty][tx + 1])) * ir;
+    F2 += (-A2 * br + Dc * (C)(sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1])) * ir;
   }
 
   // Eqs. (7), (9), (10): BGK toward the equilibrium (standard D2Q9 coefficients) plus w_q dt F
@@ -450,9 +458,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   stv(Mout + 2 * plane + oo, A2 + dtc * F2);
 
   if (FIELDS) {
-    stv(Eout + oo, sEz[ty + 1][tx + 1]);
-    stv(Eout + plane + oo, sEr[ty + 1][tx + 1]);
-    stv(Eout + 2 * plane + oo, sBn[ty + 1][tx + 1]);
+    stv(Eout + oo, (A)sEz[ty + 1][tx + 1]);
+    stv(Eout + plane + oo, (A)sEr[ty + 1][tx + 1]);
+    stv(Eout + 2 * plane + oo, (A)sBn[ty + 1][tx + 1]);
   } else {
     const long long io = (long long)j * pitch + i;
     stv(Eout + oo, (C)Ein[io]);
@@ -467,8 +475,8 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 template <int ST>
 __global__ void init_fluid_kernel(Physics p, const double* n_pert, const double* p_init,
                                   void* gv, void* Mv) {
-  using S = typename Mode<ST>::S;
-  using A = typename Mode<ST>::A;
+  using S = typename Mode<ST, false>::S;
+  using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
@@ -500,7 +508,7 @@ __global__ void init_fluid_kernel(Physics p, const double* n_pert, const double*
 // (z_i + dz/2, t = -dt/2); E_z = 0.  One thread per column, serial cumulative sum over rows.
 template <int ST>
 __global__ void init_fields_kernel(Physics p, void* Ev) {
-  using A = typename Mode<ST>::A;
+  using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.nz) return;
   A* E = (A*)Ev;
@@ -527,7 +535,7 @@ __global__ void init_fields_kernel(Physics p, void* Ev) {
 // ------------------------------------------------------------------------------------------
 template <int ST>
 __global__ void moments_out_kernel(Physics p, long long s, const void* Mv, void* dst, int dst_f64) {
-  using A = typename Mode<ST>::A;
+  using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
@@ -547,7 +555,7 @@ __global__ void moments_out_kernel(Physics p, long long s, const void* Mv, void*
 
 template <int ST>
 __global__ void fields_out_kernel(Physics p, const void* Ev, void* dst, int dst_f64) {
-  using A = typename Mode<ST>::A;
+  using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
@@ -564,8 +572,8 @@ __global__ void fields_out_kernel(Physics p, const void* Ev, void* dst, int dst_
 template <int ST>
 __global__ void state_get_kernel(Physics p, long long s, const void* gv, const void* Mv,
                                  const void* Ev, int c, double* dst) {
-  using S = typename Mode<ST>::S;
-  using A = typename Mode<ST>::A;
+  using S = typename Mode<ST, false>::S;
+  using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
@@ -586,8 +594,8 @@ __global__ void state_get_kernel(Physics p, long long s, const void* gv, const v
 template <int ST>
 __global__ void state_set_kernel(Physics p, long long s, void* gv, void* Mv, void* Ev, int c,
                                  const double* src) {
-  using S = typename Mode<ST>::S;
-  using A = typename Mode<ST>::A;
+  using S = typename Mode<ST, false>::S;
+  using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
@@ -637,7 +645,7 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
                                                                   long long s, const void* Mv,
                                                                   const void* Ev,
                                                                   double* partials) {
-  using A = typename Mode<ST>::A;
+  using A = typename Mode<ST, false>::A;
   const long long n = (long long)p.nz * p.nr;
   const long long u = (long long)blockIdx.x * RED_THREADS + threadIdx.x;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -696,18 +704,20 @@ __global__ __launch_bounds__(RED_THREADS) void diag_final_kernel(const double* p
 
 static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
 
-template <int ST>
+template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
-  if (a.p.fields_on) step_kernel<ST, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else step_kernel<ST, false><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  if (a.p.fields_on) step_kernel<ST, true, M64><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else step_kernel<ST, false, M64><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
   const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
   const dim3 grid(gx * gy);
-  if (storage == 0) launch_step_t<0>(a, grid, st);
-  else if (storage == 1) launch_step_t<1>(a, grid, st);
-  else launch_step_t<2>(a, grid, st);
+  if (storage == 0) launch_step_t<0, false>(a, grid, st);
+  else if (storage == 1 && a.p.fp64_math) launch_step_t<1, true>(a, grid, st);
+  else if (storage == 1) launch_step_t<1, false>(a, grid, st);
+  else if (a.p.fp64_math) launch_step_t<2, true>(a, grid, st);
+  else launch_step_t<2, false>(a, grid, st);
   return hipGetLastError();
 }
 

@@ -194,19 +194,27 @@ def test_fp32_fp16_parity_c2_copy():
     cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
     S, P = O.run(cfg64, 400)
     ref = {"n": S.M[0].numpy(), "Ez": S.Ez.numpy(), "Er": S.Er.numpy()}
-    tol = {wl.F32: 1e-5, wl.F16: 5e-3}
+    # (storage, FP64 arithmetic) -> tolerance per quantity.  FP32 storage: the 1e-5 bound on
+    # density and E_z; with FP64 arithmetic the collision conserves mass to FP64 round-off and
+    # the density error drops below 1e-7 (E_z stays limited by the FP32 storage of the fields).
+    # FP16 storage: 5e-3 (11-bit significand of the stored deviations).
+    tol = {(wl.F32, 0): {"n": 1e-5, "Ez": 1e-5, "Er": 1e-5},
+           (wl.F32, 1): {"n": 1e-7, "Ez": 1e-5, "Er": 1e-5},
+           (wl.F16, 0): {"n": 5e-3, "Ez": 5e-3, "Er": 5e-3},
+           (wl.F16, 1): {"n": 5e-3, "Ez": 5e-3, "Er": 5e-3}}
     errs_all = {}
-    for storage in (wl.F32, wl.F16):
-        cfg = dict(cfg64, storage=storage)
-        print(f"[reduced precision] C2s storage={storage} 400 steps", flush=True)
+    for (storage, m64) in tol:
+        cfg = dict(cfg64, storage=storage, fp64_math=m64)
+        print(f"[reduced precision] C2s storage={storage} fp64_math={m64} 400 steps", flush=True)
         lat = run_gpu(cfg, 400)
         st, _, _ = lat.state()
-        errs_all[storage] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
-                             "Er": O.rel_err(st[31], ref["Er"])}
-        print(storage, errs_all[storage], flush=True)
+        errs_all[(storage, m64)] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
+                                    "Er": O.rel_err(st[31], ref["Er"])}
+        print(storage, m64, errs_all[(storage, m64)], flush=True)
         lat.close()
-    for storage, errs in errs_all.items():
-        assert max(errs.values()) < tol[storage], (storage, errs)
+    for key, errs in errs_all.items():
+        for q, e in errs.items():
+            assert e < tol[key][q], (key, q, errs)
 
 
 def test_full_size_c2_single_steps():

@@ -34,14 +34,14 @@ CONFIG_FIELDS = (
     "nz", "nr", "dz", "dr", "c_dt_over_dz", "tau", "storage",
     "moving_window", "periodic", "fields_on", "cyl_on",
     "n0", "ramp_kind", "ramp_start", "ramp_len",
-    "nb", "sigma_z", "sigma_r", "zd0", "n_floor", "check_every",
+    "nb", "sigma_z", "sigma_r", "zd0", "n_floor", "check_every", "fp64_math",
 )
 
 _BASE = dict(
     nz=64, nr=16, dz=0.05, dr=0.05, c_dt_over_dz=0.2, tau=0.8, storage=F64,
     moving_window=0, periodic=0, fields_on=1, cyl_on=1,
     n0=1.0, ramp_kind=0, ramp_start=0.0, ramp_len=1.0,
-    nb=0.0, sigma_z=0.5, sigma_r=0.5, zd0=0.0, n_floor=1e-10, check_every=0,
+    nb=0.0, sigma_z=0.5, sigma_r=0.5, zd0=0.0, n_floor=1e-10, check_every=0, fp64_math=0,
     # workload-level fields (not part of the C struct)
     noise_amp=0.0, seed=0, nsteps=1, z_behind=4.0,
 )
