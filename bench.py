@@ -21,7 +21,8 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & HBM GB/s FP32 vs FP64 at stated Ez error; adjoint/forward time ratio"
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2201_05473_amd/csrc/lbm_kernels.hip", "paper_2201_05473_amd/csrc/lbm_internal.h")
+KERNEL_SOURCES = ("paper_2201_05473_amd/csrc/lbm_kernels.hip", "paper_2201_05473_amd/csrc/lbm_device.h",
+                  "paper_2201_05473_amd/csrc/lbm_internal.h")
 
 
 def bytes_per_site(storage: int) -> int:

@@ -145,6 +145,43 @@ int lbm_checkpoint_bytes(lbm_ctx* ctx, size_t* bytes);
 int lbm_save(lbm_ctx* ctx, void* dst, int32_t dst_on_device);
 int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);
 
+/* ---------------------------------------------------------------------------------------------
+ * Adjoint (differentiation of the step; not part of the paper's method).
+ *
+ * theta = (ramp_len, n0, sigma_r, nb).  The objective J is the witness field: E_z of the state
+ * on row obj->row, linearly interpolated in z at z_d(t_{N-1}) - obj->z_behind after N steps
+ * (the time level of E in the state).  All adjoint arithmetic and adjoint variables are FP64;
+ * the forward states are used in their storage precision.  Adjoint variables use the layout of
+ * lbm_get_state: [27][nr][nz] populations, [3][nr][nz] moments, [3][nr][nz] E_z, E_r, B_theta.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct { double z_behind; int32_t row; } lbm_objective;
+
+/* Device scratch of lbm_vjp_step / lbm_vjp_init (bytes). */
+int lbm_vjp_workspace_bytes(const lbm_config* cfg, size_t* bytes);
+
+/* Vector-Jacobian product of one step at the current state x^k: lam_out = (dPhi/dx^k)^T lam_next
+ * and grad[4] = (dPhi/dtheta)^T lam_next, where x^{k+1} = Phi(x^k; theta) is the next step.
+ * lam_next and lam_out are host arrays in the lbm_get_state layout.  The state is unchanged.
+ * Periodic dimensions need at least 5 cells.  Synchronising. */
+int lbm_vjp_step(lbm_ctx* ctx, void* adj_ws, size_t adj_bytes, const double* lam_next,
+                 double* lam_out, double grad[4]);
+
+/* theta partials of the initial state: grad[4] = (dx^0/dtheta)^T lam0.  The context must hold
+ * its initial state (step 0).  Synchronising. */
+int lbm_vjp_init(lbm_ctx* ctx, void* adj_ws, size_t adj_bytes, const double* lam0, double grad[4]);
+
+/* Device workspace of lbm_adjoint for nsteps steps with a checkpoint every ckpt_every steps. */
+int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t ckpt_every,
+                                size_t* bytes);
+
+/* Objective and its gradient dJ/d(ramp_len, n0, sigma_r, nb) over nsteps steps from the
+ * initial state.  The context must be at step 0.  Forward pass with a stored checkpoint every
+ * ckpt_every steps, then segment by segment in reverse: recompute the segment's states from its
+ * checkpoint and run the reverse steps.  On return the context holds the state after nsteps.
+ * Synchronising. */
+int lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every,
+                void* adj_ws, size_t adj_bytes, double* J, double grad[4]);
+
 /* FP64 diagnostics of the current state (deterministic two-pass reduction).  Synchronising. */
 int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 

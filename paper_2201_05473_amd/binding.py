@@ -46,6 +46,10 @@ class LbmDiag(ctypes.Structure):
     ]
 
 
+class LbmObjective(ctypes.Structure):
+    _fields_ = [("z_behind", c_double), ("row", c_int32)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"liblbmpwfa error {code}: {msg}")
@@ -81,6 +85,12 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "lbm_save": (c_int32, [c_void_p, c_void_p, c_int32]),
         "lbm_load": (c_int32, [c_void_p, c_void_p, c_int32]),
         "lbm_counters": (c_int32, [c_void_p, P(c_int64), P(c_int64)]),
+        "lbm_vjp_workspace_bytes": (c_int32, [P(LbmConfig), P(c_size_t)]),
+        "lbm_vjp_step": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+        "lbm_vjp_init": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
+        "lbm_adjoint_workspace_bytes": (c_int32, [P(LbmConfig), c_int64, c_int32, P(c_size_t)]),
+        "lbm_adjoint": (c_int32, [c_void_p, P(LbmObjective), c_int64, c_int32, c_void_p, c_size_t,
+                                  P(c_double), c_void_p]),
         "lbm_destroy": (c_int32, [c_void_p]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -185,6 +195,54 @@ def lbm_load(ctx: int, src_ptr: int, on_device: bool):
     _check(load_library().lbm_load(c_void_p(ctx), c_void_p(src_ptr), int(on_device)))
 
 
+def lbm_vjp_workspace_bytes(cfg: dict | LbmConfig) -> int:
+    c = cfg if isinstance(cfg, LbmConfig) else make_config(cfg)
+    n = c_size_t(0)
+    _check(load_library().lbm_vjp_workspace_bytes(ctypes.byref(c), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_vjp_step(ctx: int, ws_ptr: int, ws_bytes: int, lam_next, nz: int, nr: int):
+    src = np.ascontiguousarray(lam_next, dtype=np.float64)
+    if src.shape != (33, nr, nz):
+        raise ValueError(f"lam_next must have shape {(33, nr, nz)}")
+    out = np.empty((33, nr, nz), dtype=np.float64)
+    grad = np.zeros(4, dtype=np.float64)
+    _check(load_library().lbm_vjp_step(c_void_p(ctx), c_void_p(ws_ptr), c_size_t(ws_bytes),
+                                       src.ctypes.data_as(c_void_p), out.ctypes.data_as(c_void_p),
+                                       grad.ctypes.data_as(c_void_p)))
+    return out, grad
+
+
+def lbm_vjp_init(ctx: int, ws_ptr: int, ws_bytes: int, lam0, nz: int, nr: int):
+    src = np.ascontiguousarray(lam0, dtype=np.float64)
+    if src.shape != (33, nr, nz):
+        raise ValueError(f"lam0 must have shape {(33, nr, nz)}")
+    grad = np.zeros(4, dtype=np.float64)
+    _check(load_library().lbm_vjp_init(c_void_p(ctx), c_void_p(ws_ptr), c_size_t(ws_bytes),
+                                       src.ctypes.data_as(c_void_p), grad.ctypes.data_as(c_void_p)))
+    return grad
+
+
+def lbm_adjoint_workspace_bytes(cfg: dict | LbmConfig, nsteps: int, ckpt_every: int) -> int:
+    c = cfg if isinstance(cfg, LbmConfig) else make_config(cfg)
+    n = c_size_t(0)
+    _check(load_library().lbm_adjoint_workspace_bytes(ctypes.byref(c), c_int64(nsteps), c_int32(ckpt_every),
+                                                      ctypes.byref(n)))
+    return n.value
+
+
+def lbm_adjoint(ctx: int, z_behind: float, row: int, nsteps: int, ckpt_every: int, ws_ptr: int,
+                ws_bytes: int):
+    obj = LbmObjective(float(z_behind), int(row))
+    J = c_double(0.0)
+    grad = np.zeros(4, dtype=np.float64)
+    _check(load_library().lbm_adjoint(c_void_p(ctx), ctypes.byref(obj), c_int64(nsteps), c_int32(ckpt_every),
+                                      c_void_p(ws_ptr), c_size_t(ws_bytes), ctypes.byref(J),
+                                      grad.ctypes.data_as(c_void_p)))
+    return J.value, grad
+
+
 def lbm_counters(ctx: int):
     k, s = c_int64(0), c_int64(0)
     _check(load_library().lbm_counters(c_void_p(ctx), ctypes.byref(k), ctypes.byref(s)))
@@ -260,6 +318,32 @@ class Lattice:
 
     def diagnostics(self) -> dict:
         return lbm_diagnostics(self.ctx)
+
+    def _scratch(self, nbytes: int):
+        import torch
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        return buf, (buf.data_ptr() + 255) // 256 * 256
+
+    def vjp_step(self, lam_next):
+        """(lambda^k, theta partials) of the step from the current state, for lambda^{k+1}."""
+        nbytes = lbm_vjp_workspace_bytes(self.cfg)
+        buf, ptr = self._scratch(nbytes)
+        return lbm_vjp_step(self.ctx, ptr, nbytes, lam_next, self.nz, self.nr)
+
+    def vjp_init(self, lam0):
+        """theta partials of the initial state for lambda^0 (the context must be at step 0)."""
+        nbytes = lbm_vjp_workspace_bytes(self.cfg)
+        buf, ptr = self._scratch(nbytes)
+        return lbm_vjp_init(self.ctx, ptr, nbytes, lam0, self.nz, self.nr)
+
+    def adjoint(self, nsteps: int, ckpt_every: int | None = None, z_behind: float = 4.0, row: int = 0):
+        """(J, dJ/d(ramp_len, n0, sigma_r, nb)) of the witness field after nsteps steps from the
+        initial state; checkpoints every ckpt_every steps (default: about sqrt(nsteps))."""
+        if ckpt_every is None:
+            ckpt_every = max(1, int(round(nsteps ** 0.5)))
+        nbytes = lbm_adjoint_workspace_bytes(self.cfg, nsteps, ckpt_every)
+        buf, ptr = self._scratch(nbytes)
+        return lbm_adjoint(self.ctx, z_behind, row, nsteps, ckpt_every, ptr, nbytes)
 
     def counters(self):
         return lbm_counters(self.ctx)

@@ -1,6 +1,7 @@
 // Host runtime and C ABI of liblbmpwfa (see include/lbmpwfa.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -423,6 +424,259 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   out->reserved = 0;
   out->step = c->k;
   out->shifts = c->s;
+  return LBM_OK;
+}
+
+// --------------------------------------------------------------------------------------------
+// Adjoint
+// --------------------------------------------------------------------------------------------
+namespace {
+
+struct AdjLayout {
+  size_t lamA, lamB, work, partials, grad, vjp_total;
+};
+
+AdjLayout adj_layout(const Physics& p) {
+  AdjLayout L;
+  const size_t plane_d = (size_t)p.plane * sizeof(double);
+  size_t off = 0;
+  L.lamA = off; off += round_up(33 * plane_d, 256);
+  L.lamB = off; off += round_up(33 * plane_d, 256);
+  L.work = off; off += round_up(11 * plane_d, 256);
+  L.partials = off; off += round_up((size_t)lbm::adjoint_partial_blocks(p) * 4 * sizeof(double), 256);
+  L.grad = off; off += 256;
+  L.vjp_total = off;
+  return L;
+}
+
+// bytes of one stored state in the native layout (populations, moments, fields)
+size_t state_bytes(const Physics& p, int storage) {
+  const size_t plane = (size_t)p.plane;
+  return round_up(27 * plane * pop_bytes(storage), 256) + 2 * round_up(3 * plane * aux_bytes(storage), 256);
+}
+
+struct StateView {
+  void* g;
+  void* M;
+  void* E;
+};
+
+StateView state_at(char* base, const Physics& p, int storage) {
+  const size_t plane = (size_t)p.plane;
+  const size_t gb = round_up(27 * plane * pop_bytes(storage), 256);
+  const size_t mb = round_up(3 * plane * aux_bytes(storage), 256);
+  return StateView{base, base + gb, base + gb + mb};
+}
+
+int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!ws) return fail(LBM_EINVAL, "adjoint workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (bytes < need) return fail(LBM_ENOMEM, "adjoint workspace too small: %zu < %zu bytes", bytes, need);
+  if ((c->p.per_z && c->p.nz < 5) || (c->p.per_r && c->p.nr < 5))
+    return fail(LBM_EINVAL, "the adjoint needs at least 5 cells along periodic dimensions");
+  return LBM_OK;
+}
+
+// host [33][nr][nz] <-> device [33][nr][pitch] (FP64)
+hipError_t upload_lam(const Physics& p, double* dst, const double* src, hipStream_t st) {
+  return hipMemcpy2DAsync(dst, (size_t)p.pitch * sizeof(double), src, (size_t)p.nz * sizeof(double),
+                          (size_t)p.nz * sizeof(double), (size_t)33 * p.nr, hipMemcpyHostToDevice, st);
+}
+hipError_t download_lam(const Physics& p, double* dst, const double* src, hipStream_t st) {
+  return hipMemcpy2DAsync(dst, (size_t)p.nz * sizeof(double), src, (size_t)p.pitch * sizeof(double),
+                          (size_t)p.nz * sizeof(double), (size_t)33 * p.nr, hipMemcpyDeviceToHost, st);
+}
+
+lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, long long k, const double* lam_next, double* lam,
+                      char* ws, const AdjLayout& L) {
+  lbm::AdjArgs a;
+  a.p = c->p;
+  a.k = k;
+  a.s = c->p.window ? k / c->p.m : 0;
+  a.shift = (c->p.window && (k + 1) % c->p.m == 0) ? 1 : 0;
+  a.g = x.g;
+  a.M = x.M;
+  a.E = x.E;
+  a.lam_next = lam_next;
+  a.lam = lam;
+  a.work = (double*)(ws + L.work);
+  a.partials = (double*)(ws + L.partials);
+  return a;
+}
+
+}  // namespace
+
+int lbm_vjp_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
+  Physics p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  *bytes = adj_layout(p).vjp_total;
+  return LBM_OK;
+}
+
+int lbm_vjp_step(lbm_ctx* c, void* ws, size_t bytes, const double* lam_next, double* lam_out, double grad[4]) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  const AdjLayout L = adj_layout(c->p);
+  int rc = adj_check(c, ws, bytes, L.vjp_total);
+  if (rc) return rc;
+  if (!lam_next || !lam_out || !grad) return fail(LBM_EINVAL, "NULL argument");
+  char* w = (char*)ws;
+  double* lamA = (double*)(w + L.lamA);
+  double* lamB = (double*)(w + L.lamB);
+  double* gacc = (double*)(w + L.grad);
+  HIP_CHECK(hipMemsetAsync(w, 0, L.vjp_total, c->stream), "clear");
+  HIP_CHECK(upload_lam(c->p, lamA, lam_next, c->stream), "upload");
+  const StateView x{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  const lbm::AdjArgs a = adj_args(c, x, c->k, lamA, lamB, w, L);
+  if (a.s != c->s) return fail(LBM_ESTATE, "shift count does not match the step count");
+  HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, gacc, c->stream), "adjoint launch");
+  HIP_CHECK(download_lam(c->p, lam_out, lamB, c->stream), "download");
+  HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  return LBM_OK;
+}
+
+int lbm_vjp_init(lbm_ctx* c, void* ws, size_t bytes, const double* lam0, double grad[4]) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  const AdjLayout L = adj_layout(c->p);
+  int rc = adj_check(c, ws, bytes, L.vjp_total);
+  if (rc) return rc;
+  if (!lam0 || !grad) return fail(LBM_EINVAL, "NULL argument");
+  if (c->k != 0) return fail(LBM_ESTATE, "lbm_vjp_init needs the initial state (step 0)");
+  char* w = (char*)ws;
+  double* lamA = (double*)(w + L.lamA);
+  double* gacc = (double*)(w + L.grad);
+  HIP_CHECK(hipMemsetAsync(w, 0, L.vjp_total, c->stream), "clear");
+  HIP_CHECK(upload_lam(c->p, lamA, lam0, c->stream), "upload");
+  const StateView x{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  const lbm::AdjArgs a = adj_args(c, x, 0, lamA, nullptr, w, L);
+  HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, gacc, c->stream), "adjoint init launch");
+  HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  return LBM_OK;
+}
+
+int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t ckpt_every, size_t* bytes) {
+  Physics p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  if (nsteps < 1 || ckpt_every < 1) return fail(LBM_EINVAL, "nsteps and ckpt_every must be >= 1");
+  const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+  const size_t sb = state_bytes(p, cfg->storage);
+  const int64_t seglen = ckpt_every < nsteps ? ckpt_every : nsteps;
+  *bytes = adj_layout(p).vjp_total + (size_t)nseg * sb + (size_t)seglen * sb;
+  return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every, void* ws,
+                size_t bytes, double* J, double grad[4]) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!obj || !J || !grad) return fail(LBM_EINVAL, "NULL argument");
+  if (nsteps < 1 || ckpt_every < 1) return fail(LBM_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if (c->k != 0) return fail(LBM_ESTATE, "lbm_adjoint needs the context at its initial state (step 0)");
+  size_t need;
+  int rc = lbm_adjoint_workspace_bytes(&c->cfg, nsteps, ckpt_every, &need);
+  if (rc) return rc;
+  rc = adj_check(c, ws, bytes, need);
+  if (rc) return rc;
+  const Physics& p = c->p;
+  if (obj->row < 0 || obj->row >= p.nr) return fail(LBM_EINVAL, "objective row out of range");
+  // witness position after nsteps: E^{N-1} at z_d(t_{N-1}) - z_behind
+  const long long sN = p.window ? nsteps / p.m : 0;
+  const double zstar = p.zd0 + (double)(nsteps - 1) * p.dt - obj->z_behind;
+  const double xw = zstar / p.h - (double)sN - 0.5;
+  const long long iw = (long long)std::floor(xw);
+  if (iw < 0 || iw >= p.nz - 1) return fail(LBM_EINVAL, "witness position outside the window");
+  const double ww = xw - (double)iw;
+
+  const AdjLayout L = adj_layout(p);
+  const size_t sb = state_bytes(p, c->storage);
+  const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+  char* w = (char*)ws;
+  char* ckpt = w + L.vjp_total;
+  char* seg = ckpt + (size_t)nseg * sb;
+  double* lam[2] = {(double*)(w + L.lamA), (double*)(w + L.lamB)};
+  double* gacc = (double*)(w + L.grad);
+  const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
+  const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
+  auto copy_state = [&](const StateView& dst, const StateView& src) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst.g, src.g, gbytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.M, src.M, mbytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.E, src.E, mbytes, hipMemcpyDeviceToDevice, c->stream);
+    return e;
+  };
+
+  // forward pass with checkpoints
+  for (int64_t sgi = 0; sgi < nseg; ++sgi) {
+    const StateView cur{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+    HIP_CHECK(copy_state(state_at(ckpt + (size_t)sgi * sb, p, c->storage), cur), "checkpoint");
+    const int64_t len = std::min<int64_t>(ckpt_every, nsteps - sgi * ckpt_every);
+    rc = lbm_step(c, len);
+    if (rc) return rc;
+  }
+  // objective
+  {
+    const size_t ab = aux_bytes(c->storage);
+    const char* ez = (const char*)c->E(c->cur) + ((size_t)obj->row * p.pitch + (size_t)iw) * ab;
+    double e0, e1;
+    if (ab == 8) {
+      double v[2];
+      HIP_CHECK(hipMemcpyAsync(v, ez, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "objective");
+      HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+      e0 = v[0]; e1 = v[1];
+    } else {
+      float v[2];
+      HIP_CHECK(hipMemcpyAsync(v, ez, 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream), "objective");
+      HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+      e0 = v[0]; e1 = v[1];
+    }
+    *J = (1.0 - ww) * e0 + ww * e1;
+  }
+  // seed lambda^N = dJ/dx^N
+  HIP_CHECK(hipMemsetAsync(w, 0, L.vjp_total, c->stream), "clear");
+  const double seedv[2] = {1.0 - ww, ww};
+  HIP_CHECK(hipMemcpyAsync(lam[0] + 30 * (size_t)p.plane + (size_t)obj->row * p.pitch + iw, seedv,
+                           2 * sizeof(double), hipMemcpyHostToDevice, c->stream),
+            "seed");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  int cur = 0;
+  // reverse sweep, segment by segment
+  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int64_t k0 = sgi * ckpt_every;
+    const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
+    HIP_CHECK(copy_state(state_at(seg, p, c->storage), state_at(ckpt + (size_t)sgi * sb, p, c->storage)),
+              "restore");
+    for (int64_t t = 0; t + 1 < len; ++t) {
+      const StateView xi = state_at(seg + (size_t)t * sb, p, c->storage);
+      const StateView xo = state_at(seg + (size_t)(t + 1) * sb, p, c->storage);
+      lbm::StepArgs a;
+      a.p = p;
+      a.k = k0 + t;
+      a.s = p.window ? a.k / p.m : 0;
+      a.shift = (p.window && (a.k + 1) % p.m == 0) ? 1 : 0;
+      a.g_in = xi.g; a.g_out = xo.g;
+      a.M_in = xi.M; a.M_out = xo.M;
+      a.E_in = xi.E; a.E_out = xo.E;
+      HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "recompute launch");
+    }
+    for (int64_t t = len - 1; t >= 0; --t) {
+      const StateView x = state_at(seg + (size_t)t * sb, p, c->storage);
+      const lbm::AdjArgs a = adj_args(c, x, k0 + t, lam[cur], lam[1 - cur], w, L);
+      HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, gacc, c->stream), "adjoint launch");
+      cur ^= 1;
+    }
+  }
+  // initial state
+  {
+    const StateView x0 = state_at(ckpt, p, c->storage);
+    const lbm::AdjArgs a = adj_args(c, x0, 0, lam[cur], nullptr, w, L);
+    HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, gacc, c->stream), "adjoint init launch");
+  }
+  HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   return LBM_OK;
 }
 

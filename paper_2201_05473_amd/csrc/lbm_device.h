@@ -1,0 +1,96 @@
+// Device helpers shared by the forward and adjoint kernels of liblbmpwfa (gfx950).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------------------------------
+// Precision modes: population storage S, arithmetic C, auxiliary (moments, fields) storage A.
+// ------------------------------------------------------------------------------------------
+// C: arithmetic of the fluid phase; CF: arithmetic of the field phase and of the moment halo
+// (LDS tiles).  M64 selects FP64 arithmetic for FP32 / FP16 storage: FP64 vector FMAs issue at
+// the FP32 rate here (packed FP32 is not used), so exact-in-FP64 collision sums cost little in
+// this memory-bound kernel, while FP32 collision sums leak ~1e-8 of mass per site and step.
+template <int ST, bool M64> struct Mode;
+template <bool M64> struct Mode<0, M64> { using S = double; using C = double; using A = double; using CF = double; };
+template <> struct Mode<1, false> { using S = float;  using C = float;  using A = float;  using CF = float; };
+template <> struct Mode<1, true>  { using S = float;  using C = double; using A = float;  using CF = double; };
+template <> struct Mode<2, false> { using S = __half; using C = float;  using A = float;  using CF = float; };
+template <> struct Mode<2, true>  { using S = __half; using C = double; using A = float;  using CF = double; };
+
+__device__ __forceinline__ double ldv(double x) { return x; }
+__device__ __forceinline__ float ldv(float x) { return x; }
+__device__ __forceinline__ float ldv(__half x) { return __half2float(x); }
+__device__ __forceinline__ void stv(double* p, double v) { *p = v; }
+__device__ __forceinline__ void stv(float* p, float v) { *p = v; }
+__device__ __forceinline__ void stv(float* p, double v) { *p = (float)v; }
+__device__ __forceinline__ void stv(__half* p, float v) { *p = __float2half_rn(v); }
+__device__ __forceinline__ void stv(__half* p, double v) { *p = __float2half_rn((float)v); }
+
+__device__ __forceinline__ float msqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double msqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float mexp(float x) { return expf(x); }
+__device__ __forceinline__ double mexp(double x) { return exp(x); }
+
+// D2Q9 velocity set (xi_z, xi_r) and weights; the paper's table (Fig. 2) is not in its text,
+// the standard set is used.  Order: rest, +z, +r, -z, -r, (+z,+r), (-z,+r), (-z,-r), (+z,-r).
+__host__ __device__ constexpr int XZ(int q) {
+  return (q == 1 || q == 5 || q == 8) ? 1 : ((q == 3 || q == 6 || q == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int XR(int q) {
+  return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
+}
+template <typename C> __host__ __device__ constexpr C WQ(int q) {
+  return q == 0 ? C(4) / C(9) : (q < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+// Background (ion) density n_bg(z): uniform, linear ramp or tanh ramp (always FP64).
+__device__ __forceinline__ double nbg(const Physics& p, double z) {
+  if (p.ramp_kind == 0) return p.n0;
+  const double x = (z - p.ramp_start) / p.ramp_len;
+  if (p.ramp_kind == 1) return p.n0 * fmin(fmax(x, 0.0), 1.0);
+  return p.n0 * 0.5 * (1.0 + tanh(2.0 * x - 1.0));
+}
+
+// Rigid bi-Gaussian driver moving at c, evaluated in arithmetic type C.
+template <typename C>
+__device__ __forceinline__ C driver(const Physics& p, double z, double r, double t) {
+  const C dz = (C)(z - (p.zd0 + t));
+  const C rr = (C)r;
+  return (C)p.nb * mexp(-(dz * dz) / (C)(2.0 * p.sigma_z * p.sigma_z)) *
+         mexp(-(rr * rr) / (C)(2.0 * p.sigma_r * p.sigma_r));
+}
+
+// beta = p / gamma from the moments (Eq. (2), third line); zero at or below the density floor.
+__device__ __forceinline__ float mrsqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double mrsqrt(double x) { return 1.0 / sqrt(x); }
+
+template <typename C>
+__device__ __forceinline__ bool velocity(C n, C a1, C a2, C floor_, C& bz, C& br) {
+  if (!(n > floor_)) { bz = C(0); br = C(0); return false; }
+  const C in = C(1) / n;
+  const C pz = a1 * in, pr = a2 * in;
+  const C ig = mrsqrt(C(1) + pz * pz + pr * pr);
+  bz = pz * ig;
+  br = pr * ig;
+  return true;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// XCD-aware block -> tile map: consecutive tiles go to the same XCD (blocks are dispatched
+// round-robin over the 8 XCDs), so halo and pull neighbours share an L2.  A bijection.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = nblocks / 8, rem = nblocks % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+}  // namespace lbm

@@ -42,7 +42,23 @@ struct StepArgs {
   void* E_out;
 };
 
-// Launchers (defined in lbm_kernels.hip).  storage: 0 F64, 1 F32, 2 F16.
+// One reverse step of the adjoint at the state x^k (k, s, shift as for the forward step k).
+// lam_next / lam: 33 pitched FP64 planes (27 populations, 3 moments, E_z, E_r, B_theta);
+// work: 11 pitched FP64 planes; partials: per-block theta partials.
+struct AdjArgs {
+  Physics p;
+  long long k, s;
+  int shift;
+  const void* g;
+  const void* M;
+  const void* E;
+  const double* lam_next;
+  double* lam;
+  double* work;
+  double* partials;
+};
+
+// Launchers (defined in lbm_kernels.hip / lbm_adjoint.hip).  storage: 0 F64, 1 F32, 2 F16.
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st);
 hipError_t launch_init_fluid(int storage, const Physics& p, const double* n_pert,
                              const double* p_init, void* g, void* M, hipStream_t st);
@@ -62,5 +78,10 @@ int diag_blocks(const Physics& p);
 hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
                               const void* M, const void* E, double* partials, double* out,
                               hipStream_t st);
+// Adjoint: per-block partial count, one reverse step (theta partials added to grad_acc[4]),
+// and the theta partials of the initial state (lam_next = lambda^0).
+int adjoint_partial_blocks(const Physics& p);
+hipError_t launch_adjoint_step(int storage, const AdjArgs& a, double* grad_acc, hipStream_t st);
+hipError_t launch_adjoint_init(int storage, const AdjArgs& a, double* grad_acc, hipStream_t st);
 
 }  // namespace lbm

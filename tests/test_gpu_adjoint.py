@@ -1,0 +1,193 @@
+"""The hand-written HIP adjoint against the FP64 CPU adjoint (torch autograd through the oracle)
+and against central finite differences of the GPU forward.
+
+theta = (ramp_len, n0, sigma_r, nb).  Adjoint variables use the 33-plane layout of the state
+(27 populations, 3 moments, E_z, E_r, B_theta).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import lbm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+F64 = torch.float64
+NAMES = ("ramp_len", "n0", "sigma_r", "nb")
+GROUPS = [range(0, 9), range(9, 27), range(27, 28), range(28, 30), range(30, 33)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2201_05473_amd import load_library
+    load_library()
+
+
+def group_errors(x, ref):
+    errs = np.zeros(33)
+    for g in GROUPS:
+        den = max(np.abs(ref[c]).max() for c in g)
+        for c in g:
+            num = np.abs(x[c] - ref[c]).max()
+            errs[c] = num / den if den > 0 else num
+    return errs
+
+
+def theta_of(cfg, grad=True):
+    return {n: torch.tensor(float(cfg[n]), dtype=F64, requires_grad=grad) for n in NAMES}
+
+
+def flat(S, P):
+    return torch.cat([S.g.reshape(27, P.nr, P.nz), S.M, torch.stack([S.Ez, S.Er, S.B])])
+
+
+def oracle_vjp_step(cfg, k, lam_next, n_pert=None, p_init=None):
+    """(lambda^k, theta partials) of step k by autograd through the oracle."""
+    th = theta_of(cfg)
+    P = O.Params(cfg, th)
+    with torch.no_grad():
+        S = O.initial_state(P, n_pert, p_init)
+        for _ in range(k):
+            S = O.step(S, P)
+    leaves = [x.detach().clone().requires_grad_(True) for x in (S.g, S.M, S.Ez, S.Er, S.B)]
+    S1 = O.step(O.State(*leaves, S.k, S.s), P)
+    (flat(S1, P) * torch.as_tensor(lam_next)).sum().backward()
+    lam = torch.cat([leaves[0].grad.reshape(27, P.nr, P.nz), leaves[1].grad,
+                     torch.stack([leaves[2].grad, leaves[3].grad, leaves[4].grad])]).numpy()
+    grad = np.array([0.0 if th[n].grad is None else float(th[n].grad) for n in NAMES])
+    return lam, grad
+
+
+VARIANTS = {
+    "plain": dict(),
+    "window": dict(moving_window=1),
+    "periodic_z": dict(periodic=1),
+    "periodic_zr_cartesian": dict(periodic=3, fields_on=0, cyl_on=0),
+    "tanh_window": dict(ramp_kind=2, ramp_start=3.0, ramp_len=2.0, moving_window=1),
+    "linear_window_floor": dict(ramp_kind=1, ramp_start=4.5, ramp_len=1.5, moving_window=1, n_floor=1e-8),
+    "fields_off": dict(fields_on=0),
+    "cartesian_tanh": dict(cyl_on=0, ramp_kind=2, ramp_start=5.5, ramp_len=1.0),
+}
+
+
+@pytest.mark.parametrize("k", [4, 7])
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_vjp_step_matches_oracle_autograd(name, k):
+    """One reverse step (window-shift step for k = 4 with the window on) at a state reached by k
+    forward steps: lambda^k and the theta partials match the FP64 CPU adjoint to 1e-10."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config(None, nz=150, nr=13, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3,
+                    zd0=5.0, noise_amp=1e-3, seed=11, storage=wl.F64, **VARIANTS[name])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=3)
+    lam_next = np.random.default_rng(100 + k).standard_normal((33, cfg["nr"], cfg["nz"]))
+    print(f"[vjp step] {name} k={k}", flush=True)
+    lat = Lattice(cfg, pert, pinit)
+    lat.step(k)
+    lam, grad = lat.vjp_step(lam_next)
+    lam_ref, grad_ref = oracle_vjp_step(cfg, k, lam_next, pert, pinit)
+    errs = group_errors(lam, lam_ref)
+    assert errs.max() < 1e-10, (errs.argmax(), errs.max())
+    scale = max(np.abs(grad_ref).max(), 1e-300)
+    assert np.abs(grad - grad_ref).max() < 1e-10 * scale, (grad, grad_ref)
+
+
+@pytest.mark.parametrize("name", ["plain", "tanh_window", "linear_window_floor"])
+def test_vjp_init_matches_oracle_autograd(name):
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config(None, nz=150, nr=13, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3,
+                    zd0=5.0, noise_amp=1e-3, seed=11, storage=wl.F64, **VARIANTS[name])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=3)
+    lam0 = np.random.default_rng(7).standard_normal((33, cfg["nr"], cfg["nz"]))
+    lat = Lattice(cfg, pert, pinit)
+    grad = lat.vjp_init(lam0)
+    th = theta_of(cfg)
+    P = O.Params(cfg, th)
+    S = O.initial_state(P, pert, pinit)
+    (flat(S, P) * torch.as_tensor(lam0)).sum().backward()
+    ref = np.array([0.0 if th[n].grad is None else float(th[n].grad) for n in NAMES])
+    assert np.abs(grad - ref).max() < 1e-10 * np.abs(ref).max(), (grad, ref)
+
+
+def wake_cfg(storage=wl.F64):
+    """C4's 128 x 32 copy with the plasma ramp around the driver, so the witness sits in a wake."""
+    cfg = wl.config("C4s", storage=storage)
+    cfg.update(ramp_start=cfg["zd0"] - 7.0, ramp_len=4.0)
+    return cfg
+
+
+def test_adjoint_gradient_matches_oracle_autograd():
+    """lbm_adjoint (forward with checkpoints every 7 steps, ragged last segment, reverse sweep,
+    initial state) on 128 x 32 for 60 steps against autograd through the FP64 oracle."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wake_cfg()
+    n, ck = 60, 7
+    lat = Lattice(cfg)
+    J, grad = lat.adjoint(n, ck, z_behind=cfg["z_behind"], row=0)
+    th = theta_of(cfg)
+    P = O.Params(cfg, th)
+    S = O.initial_state(P)
+    for _ in range(n):
+        S = O.step(S, P)
+    Jref = O.objective(S, P, cfg["z_behind"])
+    Jref.backward()
+    gref = np.array([float(th[nm].grad) for nm in NAMES])
+    print("J", J, float(Jref), "grad", grad, gref, flush=True)
+    assert abs(J - float(Jref)) < 1e-12 * abs(float(Jref))
+    assert np.abs(grad - gref).max() < 1e-9 * np.abs(gref).max(), (grad, gref)
+    assert (lat.counters()[0]) == n
+
+
+def test_autograd_function_backward():
+    """LbmWake: the gradient reaching theta through torch autograd is the adjoint gradient."""
+    from paper_2201_05473_amd import Lattice, wake_objective
+    cfg = wake_cfg()
+    theta = torch.tensor([cfg[nm] for nm in NAMES], dtype=F64, requires_grad=True)
+    J = wake_objective(theta, cfg, 40, 9, z_behind=cfg["z_behind"])
+    (3.0 * J).backward()
+    lat = Lattice(cfg)
+    J2, g2 = lat.adjoint(40, 9, z_behind=cfg["z_behind"])
+    assert abs(float(J) - J2) <= 1e-15 * abs(J2)
+    assert np.allclose(theta.grad.numpy(), 3.0 * g2, rtol=1e-14, atol=0)
+
+
+def gpu_objective(cfg, nsteps, z_behind, row=0):
+    """J from a forward run: E_z on the row, linearly interpolated at z_d(t_{N-1}) - z_behind."""
+    from paper_2201_05473_amd import Lattice
+    lat = Lattice(cfg)
+    lat.step(nsteps)
+    ez = lat.fields()[0, row].cpu().numpy()
+    k, s = lat.counters()
+    h, dt = cfg["dz"], cfg["dz"] * cfg["c_dt_over_dz"]
+    x = (cfg["zd0"] + (k - 1) * dt - z_behind) / h - s - 0.5
+    i0 = int(np.floor(x))
+    w = x - i0
+    return (1 - w) * ez[i0] + w * ez[i0 + 1]
+
+
+def test_adjoint_fd_c4():
+    """C4 (1024 x 256, 2,000 steps, FP32 storage, checkpoints every 45 steps): the adjoint gradient
+    against central finite differences (h = 1e-4) of FP64 forward runs."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C4")
+    n, ck, zb = cfg["nsteps"], 45, cfg["z_behind"]
+    lat = Lattice(cfg)
+    J, grad = lat.adjoint(n, ck, z_behind=zb)
+    lat.close()
+    cfg64 = dict(cfg, storage=wl.F64)
+    J64 = gpu_objective(cfg64, n, zb)
+    fd = np.zeros(4)
+    hstep = 1e-4
+    for a, nm in enumerate(NAMES):
+        cp, cm = dict(cfg64), dict(cfg64)
+        cp[nm] += hstep
+        cm[nm] -= hstep
+        fd[a] = (gpu_objective(cp, n, zb) - gpu_objective(cm, n, zb)) / (2 * hstep)
+    rel = np.abs(grad - fd) / np.abs(fd)
+    print("C4 J32", J, "J64", J64, "adjoint", grad, "fd", fd, "rel", rel, flush=True)
+    assert abs(J - J64) < 1e-4 * abs(J64)
+    assert rel.max() < 1e-4, rel
