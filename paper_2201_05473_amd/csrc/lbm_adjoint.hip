@@ -2,23 +2,31 @@
 //
 // For the state x^k = (g^{k-1}, A*^{k-1}, E^{k-1}, B^{k-1/2}) and the step x^{k+1} = Phi(x^k; theta)
 // of the forward kernel, these kernels compute lambda^k = (dPhi/dx^k)^T lambda^{k+1} and the
-// parameter partials (dPhi/dtheta)^T lambda^{k+1}, theta = (ramp length, n0, sigma_r, n_b), in FP64.
-// All variables are the raw populations, moments and fields (the deviation encoding of the stored
-// density lattice is an identity map for the adjoint).  Gather form throughout: every output has
-// a single writer, no atomics, fixed summation order (bit-reproducible).
+// parameter partials (dPhi/dtheta)^T lambda^{k+1}, theta = (ramp length, n0, sigma_r, n_b).
+// Arithmetic is FP64; the adjoint variables are stored in the precision of the auxiliary planes
+// (FP64 for FP64 storage, FP32 otherwise).  All variables are the raw populations, moments and
+// fields (the deviation encoding of the stored density lattice is an identity map for the adjoint).
 //
-//   adj_site_kernel   per fluid site: recompute the field tile (Ampere, Faraday) and the site's
-//                     forward collision, then the VJP of the collision: A_bar (3, through the
-//                     zeroth moments), F_bar (3, source terms), and the adjoints of the site fields
-//                     E_bar_z, E_bar_r, B_bar; theta partials of the window-front ghost and of the
-//                     new front column.
-//   adj_field_kernel  transposes of the site averages, Faraday and Ampere (with every ghost rule):
-//                     lambda_E, lambda_B and the adjoint of the face currents; theta partials of
-//                     the driver current.
-//   adj_pop_kernel    transpose of the pull (a gather of (1 - 1/tau) g'_bar + A_bar from the site
-//                     each population streams to), and lambda of the moments: current, the lagged
-//                     radial gradient of the axisymmetric source, and the equilibrium ghosts.
-//   adj_init_kernel   theta partials of the initial state.
+// Population adjoints are carried in "pulled" form: f_bar^k(y, q) is the adjoint of the population
+// that site y pulls in step k (the collision input).  The collision's VJP has rank-3 structure,
+// f_bar^k(y, q) = (1 - 1/tau) g_bar^{k+1}(y, q) + A_bar_kk(y) (kk = lattice of q), and the adjoint of
+// the stored population is its transposed pull, g_bar^k(x, q) = f_bar^k(x + xi_q, q).  So each
+// reverse step reads and writes the 27 population planes once, exactly like the forward step.
+// Gather form throughout: every output has a single writer, no atomics, fixed summation order.
+//
+//   adj_site_kernel   per fluid site: gather g_bar^{k+1} (pull of f_bar^{k+1}), recompute the field
+//                     tile (Ampere, Faraday) and the site's forward collision, then the VJP of the
+//                     collision: f_bar^k (27), and the site adjoints F_bar (3, source terms),
+//                     E_bar_z, E_bar_r, B_bar; theta partials of the window-front ghost and of
+//                     the new front column.
+//   adj_cell_kernel   per cell: transposes of the site averages, Faraday and Ampere (every ghost
+//                     rule), staged through LDS: lambda_E, lambda_B; lambda of the moments (face
+//                     currents, the lagged radial gradient of the axisymmetric source, equilibrium
+//                     ghosts); theta partials of the driver current.
+//   adj_state_kernel  lambda^k in the stored-state layout (FP64): the transposed pull of f_bar^k.
+//   adj_cast_kernel   an FP64 stored-state lambda into the adjoint precision (population planes as
+//                     g_bar, read directly by the site kernel in its "state" input mode).
+//   adj_init_*        theta partials of the initial state.
 #include <hip/hip_runtime.h>
 
 #include "lbm_device.h"
@@ -28,8 +36,11 @@ namespace lbm {
 
 namespace {
 
-// work planes written by adj_site_kernel / adj_field_kernel
-constexpr int W_A = 0, W_F = 3, W_EZ = 6, W_ER = 7, W_B = 8, W_JZ = 9, W_JR = 10;
+// work planes written by adj_site_kernel, read by adj_cell_kernel
+constexpr int W_F = 0, W_EZ = 3, W_ER = 4, W_B = 5;
+
+// periodic wrap of an index at most one period outside [0, n)
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // d n_bg / d(ramp_len), d n_bg / d(n0) at z (clamp derivative taken inclusive at the kinks)
 __device__ __forceinline__ void dnbg(const Physics& p, double z, double& dlen, double& dn0) {
@@ -55,19 +66,25 @@ __device__ __forceinline__ void ddriver(const Physics& p, double z, double r, do
   dsr = p.nb * zr * r * r / (p.sigma_r * p.sigma_r * p.sigma_r);
 }
 
-__device__ __forceinline__ void block_sum4(double v[4], double* out) {
+// Block sum of 4 values; thread 0 adds it to acc[0..3] (each block owns its accumulator, and
+// launches on one stream are ordered, so the running sums are deterministic).
+__device__ __forceinline__ void block_sum4(double v[4], double* acc) {
   __shared__ double red[NTHREADS / 64][4];
   const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
   for (int off = 32; off > 0; off >>= 1)
+    #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] += __shfl_down(v[c], off, 64);
   if (lane == 0)
+    #pragma unroll
     for (int c = 0; c < 4; ++c) red[wid][c] = v[c];
   __syncthreads();
   if (threadIdx.x == 0) {
     double r[4] = {0.0, 0.0, 0.0, 0.0};
     for (int w = 0; w < NTHREADS / 64; ++w)
+      #pragma unroll
       for (int c = 0; c < 4; ++c) r[c] += red[w][c];
-    for (int c = 0; c < 4; ++c) out[c] = r[c];
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += r[c];
   }
 }
 
@@ -82,6 +99,7 @@ __device__ __forceinline__ void feq_vjp(const Physics& p, int q, const double M[
   const double cu = XZ(q) * uz + XR(q) * ur;
   const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
   double ubz = 0.0, ubr = 0.0;
+  #pragma unroll
   for (int k = 0; k < 3; ++k) {
     Mbar[k] += a[k] * w * (1.0 + Q);
     const double s = a[k] * w * M[k];
@@ -119,25 +137,16 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const double M[3],
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
-// adj_site_kernel: one thread per logical fluid site (i, j) of x^k.
+// adj_site_kernel: one thread per logical fluid site (i, j) of x^k.  The site fields of step k
+// (E_z, E_r, B_theta averaged to the site as the fluid used them) come from a.site, written by
+// the forward step's recompute at the output index.
 // ------------------------------------------------------------------------------------------
 template <int ST>
 __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   using S = typename Mode<ST, false>::S;
-  using A = typename Mode<ST, false>::A;
+  using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
   const Physics& p = a.p;
-  constexpr int MZ = TZ + 2, MR = TR + 2;
-  constexpr int BZ = TZ + 3, BR = TR + 3;
-  constexpr int EZZ = TZ + 1, EZR = TR + 2;
-  constexpr int ERZ = TZ + 2, ERR = TR + 1;
-  constexpr int BNZ = TZ + 1, BNR = TR + 1;
-  __shared__ double sM[3][MR][MZ];   // raw moments with the ghost ring
-  __shared__ double sJ[2][MR][MZ];
-  __shared__ double sBo[BR][BZ];
-  __shared__ double sEz[EZR][EZZ];
-  __shared__ double sEr[ERR][ERZ];
-  __shared__ double sBn[BNR][BNZ];
-  __shared__ double sN[MZ];
+  __shared__ double sN[TZ + 2];   // n_bg at the columns i0-1 .. i0+TZ
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
@@ -147,138 +156,113 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   const int j0 = (tile / gx) * TR;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
   const double h = p.h, dt = p.dt;
-  const A* Min = (const A*)a.M;
-  const A* Ein = (const A*)a.E;
-  const S* gin = (const S*)a.g;
-  auto zcol = [&](int i) { return p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1)); };
-  auto rrow = [&](int j) { return p.per_r ? wrapi(j, nr) : (j < 0 ? 0 : (j < nr ? j : nr - 1)); };
+  const A* __restrict__ Min = (const A*)a.M;
+  const S* __restrict__ gin = (const S*)a.g;
+  const A* __restrict__ L = (const A*)a.lam_next;
+  const A* __restrict__ Sf = (const A*)a.site;
 
-  for (int t = tid; t < MZ; t += NTHREADS) {
+  const int i = i0 + tx, j = j0 + ty;
+  const bool mine = i < nz && j < nr;
+  const bool dropped = a.shift && i == 0;   // this column leaves the window in step k
+  const int ic = i < nz ? i : nz - 1, jc = j < nr ? j : nr - 1;
+  const int ib = (ic - a.shift) < 0 ? 0 : ic - a.shift;   // output index in x^{k+1}
+
+  // loads: the populations pulled from inside the domain, g_bar^{k+1} at the site's output
+  // position (the transposed pull of f_bar^{k+1}, or read directly), M_bar^{k+1}, site fields
+  S graw[27];
+  A gbar[27];
+  A mbar[3];
+  A sfield[3] = {A(0), A(0), A(0)};
+  bool gok[9];
+  bool ghost[9];   // the pull in direction q reads an equilibrium ghost of a non-periodic edge
+  #pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int ui = ic - XZ(q), uj = jc - XR(q);
+    const int si = p.per_z ? wrap1(ui, nz) : (ui < 0 ? 0 : (ui < nz ? ui : nz - 1));
+    const int sj = p.per_r ? wrap1(uj, nr) : (uj < 0 ? 0 : (uj < nr ? uj : nr - 1));
+    const int off = sj * pitch + si;
+    #pragma unroll
+    for (int kk = 0; kk < 3; ++kk) graw[9 * kk + q] = (gin + (9 * kk + q) * plane)[off];
+    ghost[q] = (!p.per_z && (ui < 0 || ui >= nz)) || (!p.per_r && (uj < 0 || uj >= nr));
+    int yi = ib, yj = jc;
+    bool ok = true;
+    if (a.pull_in) {
+      yi += XZ(q);
+      yj += XR(q);
+      if (p.per_z) yi = wrap1(yi, nz);
+      else if (yi < 0 || yi >= nz) { ok = false; yi = yi < 0 ? 0 : nz - 1; }
+      if (p.per_r) yj = wrap1(yj, nr);
+      else if (yj < 0 || yj >= nr) { ok = false; yj = yj < 0 ? 0 : nr - 1; }
+    }
+    gok[q] = ok;
+    const int yo = yj * pitch + yi;
+    #pragma unroll
+    for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
+  }
+  #pragma unroll
+  for (int kk = 0; kk < 3; ++kk) mbar[kk] = (L + (27 + kk) * plane)[jc * pitch + ib];
+  if (p.fields_on)
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[jc * pitch + ib];
+  // zeroth moments of the populations pulled from inside the domain (deviation form for lattice 0)
+  double Am[3] = {0.0, 0.0, 0.0};
+  #pragma unroll
+  for (int q = 0; q < 9; ++q)
+    if (!ghost[q])
+      #pragma unroll
+      for (int kk = 0; kk < 3; ++kk) Am[kk] += (double)ldv(graw[9 * kk + q]);
+
+  for (int t = tid; t < TZ + 2; t += NTHREADS) {
     const int ii = i0 - 1 + t;
     sN[t] = nbg(p, (double)(a.s + (p.per_z ? wrapi(ii, nz) : ii)) * h);
   }
   __syncthreads();
-  for (int t = tid; t < MR * MZ; t += NTHREADS) {
-    const int bb = t / MZ, aa = t % MZ;
-    const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
-    const int ci = zcol(ii), rj = rrow(jj);
-    const int off = rj * pitch + ci;
-    double m0 = (double)Min[off] + nbg(p, (double)(a.s + ci) * h);
-    double m1 = (double)Min[plane + off], m2 = (double)Min[2 * plane + off];
-    if (!p.per_z && p.window && ii == nz) { m0 = sN[aa]; m1 = 0.0; m2 = 0.0; }
-    if (!p.per_r && jj < 0) m2 = -m2;
-    sM[0][bb][aa] = m0;
-    sM[1][bb][aa] = m1;
-    sM[2][bb][aa] = m2;
-    double bz, br;
-    velocity<double>(m0, m1, m2, p.n_floor, bz, br);
-    sJ[0][bb][aa] = m0 * bz;
-    sJ[1][bb][aa] = m0 * br;
-  }
-  if (p.fields_on) {
-    for (int t = tid; t < BR * BZ; t += NTHREADS) {
-      const int bb = t / BZ, aa = t % BZ;
-      const int jj = j0 - 2 + bb;
-      sBo[bb][aa] = jj < 0 ? 0.0 : (double)Ein[2 * plane + rrow(jj) * pitch + zcol(i0 - 2 + aa)];
-    }
-    for (int t = tid; t < EZR * EZZ; t += NTHREADS) {
-      const int bb = t / EZZ, aa = t % EZZ;
-      sEz[bb][aa] = (double)Ein[rrow(j0 - 1 + bb) * pitch + zcol(i0 - 1 + aa)];
-    }
-    for (int t = tid; t < ERR * ERZ; t += NTHREADS) {
-      const int bb = t / ERZ, aa = t % ERZ;
-      sEr[bb][aa] = (double)Ein[plane + rrow(j0 - 1 + bb) * pitch + zcol(i0 - 1 + aa)];
-    }
-    __syncthreads();
-    const double tb = ((double)a.k - 0.5) * dt;
-    for (int t = tid; t < EZR * EZZ; t += NTHREADS) {
-      const int bb = t / EZZ, aa = t % EZZ;
-      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
-      if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
-        const double rj = (jj + 0.5) * h;
-        const double curl = ((jj + 1.0) * sBo[bb + 1][aa + 1] - jj * sBo[bb][aa + 1]) / rj;
-        const double jf = 0.5 * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
-        const int ci = p.per_z ? wrapi(ii, nz) : ii;
-        const double jb = driver<double>(p, ((double)(a.s + ci) + 0.5) * h, rj, tb);
-        sEz[bb][aa] = sEz[bb][aa] + dt * (curl + jf + jb);
-      }
-    }
-    for (int t = tid; t < ERR * ERZ; t += NTHREADS) {
-      const int bb = t / ERZ, aa = t % ERZ;
-      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
-      if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
-        const double curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) / h;
-        const double jf = 0.5 * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
-        sEr[bb][aa] = sEr[bb][aa] + dt * (curl + jf);
-      }
-    }
-    __syncthreads();
-    if (!p.per_z) {
-      if (i0 == 0)
-        for (int bb = tid; bb < EZR; bb += NTHREADS) sEz[bb][0] = sEz[bb][1];
-      const int af = nz - (i0 - 1);
-      if (af >= 1 && af < ERZ)
-        for (int bb = tid; bb < ERR; bb += NTHREADS) sEr[bb][af] = sEr[bb][af - 1];
-    }
-    __syncthreads();
-    {
-      const int bo = nr - (j0 - 1);
-      if (bo >= 1 && bo < EZR)
-        for (int aa = tid; aa < EZZ; aa += NTHREADS) sEz[bo][aa] = sEz[bo - 1][aa];
-    }
-    if (j0 == 0)
-      for (int aa = tid; aa < ERZ; aa += NTHREADS) sEr[0][aa] = 0.0;
-    __syncthreads();
-    for (int t = tid; t < BNR * BNZ; t += NTHREADS) {
-      const int bb = t / BNZ, aa = t % BNZ;
-      const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
-      double v = 0.0;
-      if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr)
-        v = sBo[bb + 1][aa + 1] + dt * ((sEz[bb + 1][aa] - sEz[bb][aa]) / h - (sEr[bb][aa + 1] - sEr[bb][aa]) / h);
-      sBn[bb][aa] = v;
-    }
-    __syncthreads();
-    if (!p.per_z && i0 == 0)
-      for (int bb = tid; bb < BNR; bb += NTHREADS) sBn[bb][0] = sBn[bb][1];
-  }
-  __syncthreads();
 
-  const int i = i0 + tx, j = j0 + ty;
   double part[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(ramp_len, n0, sigma_r, n_b)
-  if (i < nz && j < nr) {
+  if (mine) {
     const int cell = j * pitch + i;
-    double* W = a.work;
-    if (a.shift && i == 0) {
+    A* __restrict__ Lo = (A*)a.lam;
+    A* __restrict__ W = (A*)a.work;
+    if (dropped) {
       // the first column leaves the window in this step: no site, no adjoint source
-      for (int c = 0; c < 9; ++c) W[c * plane + cell] = 0.0;
+      #pragma unroll
+      for (int c = 0; c < 27; ++c) (Lo + c * plane)[cell] = A(0);
+      #pragma unroll
+      for (int c = 0; c < 6; ++c) (W + c * plane)[cell] = A(0);
     } else {
-      const int oo = j * pitch + (i - a.shift);   // index of the site's output in x^{k+1}
-      const double* L = a.lam_next;
-      // forward recompute of the site (raw values)
-      double f[3][9];
+      // forward recompute of the site's moments (raw values): background of the pulled lattice-0
+      // deviations, and the equilibrium ghosts (moments of the source cell after the z rule then
+      // the r rule; the window front is plasma at rest)
+      #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        const int si = i - XZ(q), sj = j - XR(q);
-        const bool oz = si < 0 || si >= nz, orr = sj < 0 || sj >= nr;
-        if ((oz && !p.per_z) || (orr && !p.per_r)) {
-          const int ga = tx + 1 - XZ(q), gb = ty + 1 - XR(q);
-          const double Mg[3] = {sM[0][gb][ga], sM[1][gb][ga], sM[2][gb][ga]};
+        if (ghost[q]) {
+          int si = i - XZ(q), sj = j - XR(q);
+          double Mg[3];
+          if (!p.per_z && si >= nz && p.window) {
+            Mg[0] = sN[tx + 1 - XZ(q)];
+            Mg[1] = 0.0;
+            Mg[2] = 0.0;
+          } else {
+            si = p.per_z ? wrap1(si, nz) : (si < 0 ? 0 : (si < nz ? si : nz - 1));
+            const int rj = p.per_r ? wrap1(sj, nr) : (sj < 0 ? 0 : (sj < nr ? sj : nr - 1));
+            const int off = rj * pitch + si;
+            const int sa = si - (i0 - 1);
+            Mg[0] = (double)Min[off] + ((sa >= 0 && sa < TZ + 2) ? sN[sa] : nbg(p, (double)(a.s + si) * h));
+            Mg[1] = (double)Min[plane + off];
+            Mg[2] = (double)(Min + 2 * plane)[off];
+          }
+          if (!p.per_r && sj < 0) Mg[2] = -Mg[2];   // axis mirror
           double bz, br;
           velocity<double>(Mg[0], Mg[1], Mg[2], p.n_floor, bz, br);
           const double uz = p.lam * bz, ur = p.lam * br;
           const double cu = XZ(q) * uz + XR(q) * ur;
           const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-          for (int k = 0; k < 3; ++k) f[k][q] = WQ<double>(q) * Mg[k] * (1.0 + Q);
+          #pragma unroll
+          for (int kk = 0; kk < 3; ++kk) Am[kk] += WQ<double>(q) * Mg[kk] * (1.0 + Q);
         } else {
-          const int pi = oz ? wrapi(si, nz) : si, pj = orr ? wrapi(sj, nr) : sj;
-          const int off = pj * pitch + pi;
-          f[0][q] = (double)ldv(gin[q * plane + off]) + WQ<double>(q) * sN[tx + 1 - XZ(q)];
-          f[1][q] = (double)ldv(gin[(9 + q) * plane + off]);
-          f[2][q] = (double)ldv(gin[(18 + q) * plane + off]);
+          Am[0] += WQ<double>(q) * sN[tx + 1 - XZ(q)];
         }
       }
-      double Am[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < 3; ++k)
-        for (int q = 0; q < 9; ++q) Am[k] += f[k][q];
       const double n = Am[0];
       double bz, br;
       const bool live = velocity<double>(Am[0], Am[1], Am[2], p.n_floor, bz, br);
@@ -289,38 +273,31 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
         pr = Am[2] / n;
         ig = 1.0 / sqrt(1.0 + pz * pz + pr * pr);
       }
-      double Ebz = 0.0, Ebr = 0.0, Bb = 0.0;
-      if (p.fields_on) {
-        Ebz = 0.5 * (sEz[ty + 1][tx] + sEz[ty + 1][tx + 1]);
-        Ebr = 0.5 * (sEr[ty][tx + 1] + sEr[ty + 1][tx + 1]);
-        Bb = ((sBo[ty + 2][tx + 2] + sBn[ty + 1][tx + 1]) + (sBo[ty + 2][tx + 1] + sBn[ty + 1][tx]) +
-              (sBo[ty + 1][tx + 2] + sBn[ty][tx + 1]) + (sBo[ty + 1][tx + 1] + sBn[ty][tx])) / 8.0;
-      }
+      const double Ebz = (double)sfield[0], Ebr = (double)sfield[1], Bb = (double)sfield[2];
       const double ir = 1.0 / ((j + 0.5) * h);
 
-      // adjoint inputs
-      double gb[3][9], Mb[3], Fb[3], Ab[3];
-      for (int k = 0; k < 3; ++k) {
-        for (int q = 0; q < 9; ++q) gb[k][q] = L[(9 * k + q) * plane + oo];
-        Mb[k] = L[(27 + k) * plane + oo];
-      }
       // g' = (1 - 1/tau) f + e/tau + w dt F,  M' = A + dt F,  e = w A (1 + Q(u))
+      double Fb[3], Ab[3];
       double ubz = 0.0, ubr = 0.0;
-      for (int k = 0; k < 3; ++k) {
+      #pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
         double sw = 0.0, s0 = 0.0;
+        #pragma unroll
         for (int q = 0; q < 9; ++q) {
+          const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
           const double w = WQ<double>(q);
           const double cu = XZ(q) * uz + XR(q) * ur;
           const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-          const double eb = gb[k][q] / p.tau;
-          sw += w * gb[k][q];
+          const double eb = gbq / p.tau;
+          sw += w * gbq;
           s0 += eb * w * (1.0 + Q);
-          const double s = eb * w * Am[k];
-          ubz += s * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);
-          ubr += s * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
+          const double sq = eb * w * Am[kk];
+          ubz += sq * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);
+          ubr += sq * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
         }
-        Fb[k] = dt * (sw + Mb[k]);
-        Ab[k] = Mb[k] + s0;
+        const double Mb = (double)mbar[kk];
+        Fb[kk] = dt * (sw + Mb);
+        Ab[kk] = Mb + s0;
       }
       double bbz = p.lam * ubz, bbr = p.lam * ubr;
       double Ebz_b = 0.0, Ebr_b = 0.0, Bb_b = 0.0;
@@ -335,9 +312,10 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       }
       if (p.cyl_on) {
         // F_k += (-A_k beta_r + D dA_k/dr) / r
-        for (int k = 0; k < 3; ++k) {
-          bbr += Fb[k] * (-Am[k] * ir);
-          Ab[k] += Fb[k] * (-br * ir);
+        #pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          bbr += Fb[kk] * (-Am[kk] * ir);
+          Ab[kk] += Fb[kk] * (-br * ir);
         }
       }
       if (live) {
@@ -348,28 +326,45 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
         Ab[2] += pbr / n;
         Ab[0] -= (pbz * pz + pbr * pr) / n;
       }
-      for (int k = 0; k < 3; ++k) {
-        W[(W_A + k) * plane + cell] = Ab[k];
-        W[(W_F + k) * plane + cell] = Fb[k];
-      }
-      W[W_EZ * plane + cell] = Ebz_b;
-      W[W_ER * plane + cell] = Ebr_b;
-      W[W_B * plane + cell] = Bb_b;
+      // adjoint of the pulled populations: (1 - 1/tau) g_bar' + A_bar
+      const double c1 = 1.0 - 1.0 / p.tau;
+      #pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+        #pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
+          stv(&(Lo + (9 * kk + q) * plane)[cell], c1 * gbq + Ab[kk]);
+        }
+      #pragma unroll
+      for (int kk = 0; kk < 3; ++kk) stv(&(W + (W_F + kk) * plane)[cell], Fb[kk]);
+      stv(&(W + W_EZ * plane)[cell], Ebz_b);
+      stv(&(W + W_ER * plane)[cell], Ebr_b);
+      stv(&(W + W_B * plane)[cell], Bb_b);
 
       if (p.window && i == nz - 1) {
         // window front ghost: the populations pulled from column nz (xi_z = -1) are w_q n_bg(z_nz)
         double dl, dn;
         dnbg(p, (double)(a.s + nz) * h, dl, dn);
         double sum = 0.0;
+        #pragma unroll
         for (int q = 0; q < 9; ++q)
-          if (XZ(q) == -1) sum += WQ<double>(q) * ((1.0 - 1.0 / p.tau) * gb[0][q] + Ab[0]);
+          if (XZ(q) == -1) sum += WQ<double>(q) * (c1 * (gok[q] ? (double)gbar[q] : 0.0) + Ab[0]);
         part[0] += sum * dl;
         part[1] += sum * dn;
         if (a.shift) {
           // the new front column of x^{k+1} (output index nz - 1): w_q n_bg and n_bg
-          const int of = j * pitch + (nz - 1);
-          double s2 = L[27 * plane + of];
-          for (int q = 0; q < 9; ++q) s2 += WQ<double>(q) * L[q * plane + of];
+          double s2 = (double)(L + 27 * plane)[j * pitch + (nz - 1)];
+          #pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            int yi = nz - 1, yj = j;
+            if (a.pull_in) {
+              yi += XZ(q);
+              yj += XR(q);
+              if (yi >= nz || ((yj < 0 || yj >= nr) && !p.per_r)) continue;
+              if (p.per_r) yj = wrap1(yj, nr);
+            }
+            s2 += WQ<double>(q) * (double)(L + q * plane)[yj * pitch + yi];
+          }
           part[0] += s2 * dl;
           part[1] += s2 * dn;
         }
@@ -380,10 +375,12 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// adj_field_kernel: one thread per cell (i, j) of x^k.
+// adj_cell_kernel: one thread per cell (i, j) of x^k.  Field part staged through LDS:
+// L_B' = adjoint of B^{k+1/2}, L_Ez', L_Er' = adjoints of E^k (as used by step k).
 // ------------------------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
+__global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
+  using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
@@ -392,193 +389,175 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
   const int i0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
   const double h = p.h, dt = p.dt;
-  const double* W = a.work;
-  const double* L = a.lam_next;
-  // site adjoints (zero outside the domain; the dropped column already holds zeros)
+  const A* __restrict__ W = (const A*)a.work;
+  const A* __restrict__ L = (const A*)a.lam_next;
+  A* Lo = (A*)a.lam;   // planes 0..26 (f_bar^k) read, planes 27..32 written
+
+  // LDS regions (origin = lowest logical column / row)
+  constexpr int BBZ = TZ + 3, BBR = TR + 3;   // site B_bar:  cols i0-1..i0+TZ+1, rows j0-1..j0+TR+1
+  constexpr int EBZ = TZ + 2, EBR = TR + 1;   // site Ez_bar: cols i0-1..i0+TZ,   rows j0..j0+TR
+  constexpr int RBZ = TZ + 1, RBR = TR + 2;   // site Er_bar: cols i0..i0+TZ,     rows j0-1..j0+TR
+  constexpr int LBZ = TZ + 2, LBR = TR + 2;   // L_B':        cols i0-1..i0+TZ,   rows j0-1..j0+TR
+  constexpr int LZZ = TZ + 1, LZR = TR + 1;   // L_Ez':       cols i0-1..i0+TZ-1, rows j0..j0+TR
+  constexpr int LRZ = TZ + 1, LRR = TR + 1;   // L_Er':       cols i0..i0+TZ,     rows j0-1..j0+TR-1
+  __shared__ double sBb[BBR][BBZ];
+  __shared__ double sEb[EBR][EBZ];
+  __shared__ double sRb[RBR][RBZ];
+  __shared__ double sLB[LBR][LBZ];
+  __shared__ double sLZ[LZR][LZZ];
+  __shared__ double sLR[LRR][LRZ];
+
+  // cell in the domain after the periodic wrap of z (r is never periodic with fields on)
+  auto cellz = [&](int& i, int j) -> bool {
+    if (j < 0 || j >= nr) return false;
+    if (p.per_z) { i = wrapi(i, nz); return true; }
+    return i >= 0 && i < nz;
+  };
   auto site = [&](int plane_id, int i, int j) -> double {
-    if (j < 0 || j >= nr) return 0.0;
-    if (p.per_z) i = wrapi(i, nz);
-    else if (i < 0 || i >= nz) return 0.0;
-    return W[plane_id * plane + j * pitch + i];
+    return cellz(i, j) ? (double)W[plane_id * plane + j * pitch + i] : 0.0;
   };
   // adjoint of E^k / B^{k+1/2} as state of x^{k+1} (zero for the column dropped by the shift)
   auto next = [&](int c, int i, int j) -> double {
-    if (p.per_z) i = wrapi(i, nz);
+    if (!cellz(i, j)) return 0.0;
     const int o = i - a.shift;
-    if (o < 0 || i >= nz || j < 0 || j >= nr) return 0.0;
-    return L[c * plane + j * pitch + o];
-  };
-  // 1/8 of the B_bar of the sites that average the corner (i, j) (with the rear copy rule)
-  auto bsum = [&](int i, int j) -> double {
-    double s = site(W_B, i, j) + site(W_B, i + 1, j) + site(W_B, i, j + 1) + site(W_B, i + 1, j + 1);
-    if (!p.per_z && i == 0) s += site(W_B, 0, j) + site(W_B, 0, j + 1);
-    return s / 8.0;
-  };
-  auto LBp = [&](int i, int j) -> double {   // adjoint of B^{k+1/2}(i, j)
-    if (j < 0 || j >= nr) return 0.0;
-    if (p.per_z) i = wrapi(i, nz);
-    else if (i < 0 || i >= nz) return 0.0;
-    return next(32, i, j) + bsum(i, j);
-  };
-  auto LEz = [&](int i, int j) -> double {   // adjoint of E_z^k(i, j)
-    if (j < 0 || j >= nr) return 0.0;
-    if (p.per_z) i = wrapi(i, nz);
-    else if (i < 0 || i >= nz) return 0.0;
-    double v = next(30, i, j) + 0.5 * (site(W_EZ, i, j) + site(W_EZ, i + 1, j));
-    if (!p.per_z && i == 0) v += 0.5 * site(W_EZ, 0, j);   // rear copy E_z(-1) = E_z(0)
-    if (p.fields_on) {
-      if (j <= nr - 2) v -= dt / h * LBp(i, j);
-      if (j >= 1) v += dt / h * LBp(i, j - 1);
-    }
-    return v;
-  };
-  auto LEr = [&](int i, int j) -> double {   // adjoint of E_r^k(i, j)
-    if (j < 0 || j >= nr) return 0.0;
-    if (p.per_z) i = wrapi(i, nz);
-    else if (i < 0 || i >= nz) return 0.0;
-    double v = next(31, i, j) + 0.5 * (site(W_ER, i, j) + (j + 1 < nr ? site(W_ER, i, j + 1) : 0.0));
-    if (p.fields_on) {
-      if (p.per_z || i <= nz - 2) v += dt / h * LBp(i, j);
-      if (p.per_z || i >= 1) v -= dt / h * LBp(i - 1, j);
-    }
-    return v;
+    return o < 0 ? 0.0 : (double)L[c * plane + j * pitch + o];
   };
 
   const int i = i0 + tx, j = j0 + ty;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < nz && j < nr) {
-    const int cell = j * pitch + i;
-    double* Lo = a.lam;
-    double* Wo = a.work;
-    if (p.fields_on) {
-      const double lez = LEz(i, j), ler = LEr(i, j);
-      double lb = LBp(i, j) + bsum(i, j);
+  double jz = 0.0, jr = 0.0;
+  const int cell = j * pitch + i;
+  const bool mine = i < nz && j < nr;
+
+  if (p.fields_on) {
+    for (int t = tid; t < BBR * BBZ; t += NTHREADS)
+      sBb[t / BBZ][t % BBZ] = site(W_B, i0 - 1 + t % BBZ, j0 - 1 + t / BBZ);
+    for (int t = tid; t < EBR * EBZ; t += NTHREADS)
+      sEb[t / EBZ][t % EBZ] = site(W_EZ, i0 - 1 + t % EBZ, j0 + t / EBZ);
+    for (int t = tid; t < RBR * RBZ; t += NTHREADS)
+      sRb[t / RBZ][t % RBZ] = site(W_ER, i0 + t % RBZ, j0 - 1 + t / RBZ);
+    __syncthreads();
+    // 1/8 of the B_bar of the sites that average the corner (ci, cj) (rear copy rule included)
+    auto bsum = [&](int ci, int cj) -> double {
+      const int a0 = ci - (i0 - 1), b0 = cj - (j0 - 1);
+      double v = sBb[b0][a0] + sBb[b0][a0 + 1] + sBb[b0 + 1][a0] + sBb[b0 + 1][a0 + 1];
+      if (!p.per_z && ci == 0) v += sBb[b0][a0] + sBb[b0 + 1][a0];
+      return v * 0.125;
+    };
+    // L_B' = lambda'_B + its use in the fluid's B average
+    for (int t = tid; t < LBR * LBZ; t += NTHREADS) {
+      const int ci = i0 - 1 + t % LBZ, cj = j0 - 1 + t / LBZ;
+      int cw = ci;
+      sLB[t / LBZ][t % LBZ] = cellz(cw, cj) ? next(32, ci, cj) + bsum(ci, cj) : 0.0;
+    }
+    __syncthreads();
+    auto LB = [&](int ci, int cj) -> double { return sLB[cj - (j0 - 1)][ci - (i0 - 1)]; };
+    for (int t = tid; t < LZR * LZZ; t += NTHREADS) {
+      const int ci = i0 - 1 + t % LZZ, cj = j0 + t / LZZ;
+      int cw = ci;
+      double v = 0.0;
+      if (cellz(cw, cj)) {
+        const int ea = ci - (i0 - 1), eb = cj - j0;
+        v = next(30, ci, cj) + 0.5 * (sEb[eb][ea] + sEb[eb][ea + 1]);
+        if (!p.per_z && cw == 0) v += 0.5 * sEb[eb][ea];     // rear copy E_z(-1) = E_z(0)
+        if (cj <= nr - 2) v -= dt / h * LB(ci, cj);
+        if (cj >= 1) v += dt / h * LB(ci, cj - 1);
+      }
+      sLZ[t / LZZ][t % LZZ] = v;
+    }
+    for (int t = tid; t < LRR * LRZ; t += NTHREADS) {
+      const int ci = i0 + t % LRZ, cj = j0 - 1 + t / LRZ;
+      int cw = ci;
+      double v = 0.0;
+      if (cellz(cw, cj)) {
+        const int ra = ci - i0, rb = cj - (j0 - 1);
+        v = next(31, ci, cj) + 0.5 * (sRb[rb][ra] + sRb[rb + 1][ra]);
+        if (p.per_z || cw <= nz - 2) v += dt / h * LB(ci, cj);
+        if (p.per_z || cw >= 1) v -= dt / h * LB(ci - 1, cj);
+      }
+      sLR[t / LRZ][t % LRZ] = v;
+    }
+    __syncthreads();
+    if (mine) {
+      auto LZ = [&](int ci, int cj) -> double { return sLZ[cj - j0][ci - (i0 - 1)]; };
+      auto LR = [&](int ci, int cj) -> double { return sLR[cj - (j0 - 1)][ci - i0]; };
+      const double lez = LZ(i, j), ler = LR(i, j);
+      double lb = LB(i, j) + bsum(i, j);
       const double rj = (j + 0.5) * h;
       lb += dt * (j + 1.0) / rj * lez;
-      if (j + 1 < nr) lb -= dt * (j + 1.0) / ((j + 1.5) * h) * LEz(i, j + 1);
+      if (j + 1 < nr) lb -= dt * (j + 1.0) / ((j + 1.5) * h) * LZ(i, j + 1);
       if (p.per_z || i >= 1) lb -= dt / h * ler;
-      if (p.per_z || i + 1 < nz) lb += dt / h * LEr(i + 1, j);
-      Lo[30 * plane + cell] = lez;
-      Lo[31 * plane + cell] = ler;
-      Lo[32 * plane + cell] = lb;
-      double jz = 0.5 * dt * (lez + ((p.per_z || i >= 1) ? LEz(i - 1, j) : 0.0));
+      if (p.per_z || i + 1 < nz) lb += dt / h * LR(i + 1, j);
+      stv(&Lo[30 * plane + cell], lez);
+      stv(&Lo[31 * plane + cell], ler);
+      stv(&Lo[32 * plane + cell], lb);
+      jz = 0.5 * dt * (lez + ((p.per_z || i >= 1) ? LZ(i - 1, j) : 0.0));
       if (!p.per_z && !p.window && i == nz - 1) jz += 0.5 * dt * lez;   // front copy of J_z
-      double jr = 0.5 * dt * (ler + (j >= 1 ? LEr(i, j - 1) : 0.0));
+      jr = 0.5 * dt * (ler + (j >= 1 ? LR(i, j - 1) : 0.0));
       if (j == nr - 1) jr += 0.5 * dt * ler;                             // outer copy of J_r
-      Wo[W_JZ * plane + cell] = jz;
-      Wo[W_JR * plane + cell] = jr;
       // driver current J_b(z_i + dz/2, r_j, t_{k-1/2})
-      const int ci = p.per_z ? wrapi(i, nz) : i;
       double dsr, dnb;
-      ddriver(p, ((double)(a.s + ci) + 0.5) * h, rj, ((double)a.k - 0.5) * dt, dsr, dnb);
+      ddriver(p, ((double)(a.s + i) + 0.5) * h, rj, ((double)a.k - 0.5) * dt, dsr, dnb);
       part[2] += dt * lez * dsr;
       part[3] += dt * lez * dnb;
-    } else {
-      // fields are carried unchanged and unused
-      Lo[30 * plane + cell] = next(30, i, j);
-      Lo[31 * plane + cell] = next(31, i, j);
-      Lo[32 * plane + cell] = next(32, i, j);
-      Wo[W_JZ * plane + cell] = 0.0;
-      Wo[W_JR * plane + cell] = 0.0;
     }
+  } else if (mine) {
+    // fields are carried unchanged and unused
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) stv(&Lo[(30 + c) * plane + cell], next(30 + c, i, j));
   }
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
-}
+  if (!mine) return;   // no barrier below this point
 
-// ------------------------------------------------------------------------------------------
-// adj_pop_kernel: one thread per cell (i, j) of x^k.
-// ------------------------------------------------------------------------------------------
-template <int ST>
-__global__ __launch_bounds__(NTHREADS) void adj_pop_kernel(AdjArgs a) {
-  using A = typename Mode<ST, false>::A;
-  const Physics& p = a.p;
-  const int nz = p.nz, nr = p.nr, pitch = p.pitch;
-  const long long plane = p.plane;
-  const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
-  const int tile = xcd_tile(blockIdx.x, gx * gy);
-  const int i0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
-  const int i = i0 + threadIdx.x % TZ, j = j0 + threadIdx.x / TZ;
-  if (i >= nz || j >= nr) return;
-  const double h = p.h;
-  const double* W = a.work;
-  const double* L = a.lam_next;
-  const A* Min = (const A*)a.M;
-  const int cell = j * pitch + i;
-  const double c1 = 1.0 - 1.0 / p.tau;
-  // a computed site y of step k (inside the domain after periodic wrap, not the dropped column)
-  auto computed = [&](int& yi, int& yj) -> bool {
-    if (p.per_z) yi = wrapi(yi, nz);
-    if (p.per_r) yj = wrapi(yj, nr);
-    if (yi < 0 || yi >= nz || yj < 0 || yj >= nr) return false;
-    return !(a.shift && yi == 0);
-  };
-  // adjoint of the pulled population f_{k,q} at site y: (1 - 1/tau) g'_bar + A_bar
-  auto lamf = [&](int k, int q, int yi, int yj) -> double {
-    const int ys = yj * pitch + yi;
-    return c1 * L[(9 * k + q) * plane + yj * pitch + (yi - a.shift)] + W[(W_A + k) * plane + ys];
-  };
-
-  // transpose of the pull: g_q(x) streams to y = x + xi_q
-  double* Lo = a.lam;
-  for (int k = 0; k < 3; ++k)
-    for (int q = 0; q < 9; ++q) {
-      int yi = i + XZ(q), yj = j + XR(q);
-      Lo[(9 * k + q) * plane + cell] = computed(yi, yj) ? lamf(k, q, yi, yj) : 0.0;
-    }
-
-  // moments: raw values of x^k at this cell
+  // ---- lambda of the moments ----
+  const A* __restrict__ Min = (const A*)a.M;
   const double M[3] = {(double)Min[cell] + nbg(p, (double)(a.s + i) * h), (double)Min[plane + cell],
                        (double)Min[2 * plane + cell]};
   double Mb[3] = {0.0, 0.0, 0.0};
   // (a) face currents of Ampere's law
-  if (p.fields_on) current_vjp(p, M, W[W_JZ * plane + cell], W[W_JR * plane + cell], Mb);
+  if (p.fields_on) current_vjp(p, M, jz, jr, Mb);
   // (b) lagged radial gradient of the axisymmetric source, D (M(j+1) - M(j-1)) / (2 dr r_j)
   if (p.cyl_on) {
     const double c = p.D / (2.0 * h);
     const double par[3] = {1.0, 1.0, -1.0};
+    #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double v = 0.0;
-      if (j >= 1) v += c / ((j - 0.5) * h) * W[(W_F + k) * plane + cell - pitch];
-      if (j + 1 < nr) v -= c / ((j + 1.5) * h) * W[(W_F + k) * plane + cell + pitch];
-      if (j == 0) v -= par[k] * c / (0.5 * h) * W[(W_F + k) * plane + cell];
-      if (j == nr - 1) v += c / ((j + 0.5) * h) * W[(W_F + k) * plane + cell];
+      if (j >= 1) v += c / ((j - 0.5) * h) * (double)W[(W_F + k) * plane + cell - pitch];
+      if (j + 1 < nr) v -= c / ((j + 1.5) * h) * (double)W[(W_F + k) * plane + cell + pitch];
+      if (j == 0) v -= par[k] * c / (0.5 * h) * (double)W[(W_F + k) * plane + cell];
+      if (j == nr - 1) v += c / ((j + 0.5) * h) * (double)W[(W_F + k) * plane + cell];
       Mb[k] += v;
     }
   }
-  // (c) equilibrium ghosts whose moments are copies (or the axis mirror) of this cell: replay the
-  // forward's ghost test for every site within two cells that may pull such a ghost (periodic
-  // dimensions hold at least 5 cells, so the wrapped sites are distinct)
-  const bool edge = (!p.per_z && (i <= 1 || i >= nz - 2)) || (!p.per_r && (j <= 1 || j >= nr - 2));
-  if (edge) {
-    const double Mx[3] = {M[0], M[1], M[2]};
-    for (int dyi = -2; dyi <= 2; ++dyi)
-      for (int dyj = -2; dyj <= 2; ++dyj) {
-        int yi = i + dyi, yj = j + dyj;
-        if (p.per_z) yi = wrapi(yi, nz);
-        else if (yi < 0 || yi >= nz) continue;
-        if (p.per_r) yj = wrapi(yj, nr);
-        else if (yj < 0 || yj >= nr) continue;
-        if (a.shift && yi == 0) continue;   // not a computed site
+  // (c) equilibrium ghosts whose moments are copies (or the axis mirror) of this cell: the ghost
+  // positions (si, sj) outside a non-periodic edge whose source is this cell, each pulled in
+  // direction q by the computed site (si, sj) + xi_q.  The front ghost of the moving window is
+  // plasma at rest and depends on theta only.
+  const bool zlo = !p.per_z && i == 0, zhi = !p.per_z && !p.window && i == nz - 1;
+  const bool rlo = !p.per_r && j == 0, rhi = !p.per_r && j == nr - 1;
+  if (zlo || zhi || rlo || rhi) {
+    const int gzs[2] = {i, zlo ? -1 : nz};
+    const int grs[2] = {j, rlo ? -1 : nr};
+    const int ngz = (zlo || zhi) ? 2 : 1, ngr = (rlo || rhi) ? 2 : 1;
+    for (int a_ = 0; a_ < ngz; ++a_)
+      for (int b_ = 0; b_ < ngr; ++b_) {
+        if (a_ == 0 && b_ == 0) continue;   // the cell itself
+        const int si = gzs[a_], sj = grs[b_];
+        const double sgn = sj < 0 ? -1.0 : 1.0;
+        const double Mg[3] = {M[0], M[1], sgn * M[2]};
+        #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          const int si = yi - XZ(q), sj = yj - XR(q);
-          const bool oz = si < 0 || si >= nz, orr = sj < 0 || sj >= nr;
-          if (!((oz && !p.per_z) || (orr && !p.per_r))) continue;   // a regular pull
-          int ci, rj;
-          double sgn = 1.0;
-          if (p.per_z) ci = wrapi(si, nz);
-          else if (si < 0) ci = 0;
-          else if (si >= nz) {
-            if (p.window) continue;   // plasma at rest: depends on theta only
-            ci = nz - 1;
-          } else ci = si;
-          if (p.per_r) rj = wrapi(sj, nr);
-          else if (sj < 0) { rj = 0; sgn = -1.0; }
-          else if (sj >= nr) rj = nr - 1;
-          else rj = sj;
-          if (ci != i || rj != j) continue;
-          const double Mg[3] = {Mx[0], Mx[1], sgn * Mx[2]};
+          int yi = si + XZ(q), yj = sj + XR(q);
+          if (p.per_z) yi = wrap1(yi, nz);
+          else if (yi < 0 || yi >= nz) continue;
+          if (p.per_r) yj = wrap1(yj, nr);
+          else if (yj < 0 || yj >= nr) continue;
+          if (a.shift && yi == 0) continue;   // not a computed site
+          const int ys = yj * pitch + yi;
+          const double af[3] = {(double)Lo[q * plane + ys], (double)Lo[(9 + q) * plane + ys],
+                                (double)Lo[(18 + q) * plane + ys]};
           double Mgb[3] = {0.0, 0.0, 0.0};
-          const double af[3] = {lamf(0, q, yi, yj), lamf(1, q, yi, yj), lamf(2, q, yi, yj)};
           feq_vjp(p, q, Mg, af, Mgb);
           Mb[0] += Mgb[0];
           Mb[1] += Mgb[1];
@@ -586,67 +565,150 @@ __global__ __launch_bounds__(NTHREADS) void adj_pop_kernel(AdjArgs a) {
         }
       }
   }
-  Lo[27 * plane + cell] = Mb[0];
-  Lo[28 * plane + cell] = Mb[1];
-  Lo[29 * plane + cell] = Mb[2];
+  #pragma unroll
+  for (int k = 0; k < 3; ++k) stv(&Lo[(27 + k) * plane + cell], Mb[k]);
 }
 
 // ------------------------------------------------------------------------------------------
-// adj_init_kernel: theta partials of the initial state, one thread per column.
+// adj_state_kernel: lambda^k in the stored-state layout, FP64, one thread per cell:
+// g_bar^k(x, q) = f_bar^k(x + xi_q, q) over the sites computed in step k, moments and fields copied.
 // ------------------------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(NTHREADS) void adj_init_kernel(AdjArgs a) {
+__global__ __launch_bounds__(NTHREADS) void adj_state_kernel(AdjArgs a, double* out) {
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
-  const int i = blockIdx.x * NTHREADS + threadIdx.x;
+  const int nz = p.nz, nr = p.nr, pitch = p.pitch;
+  const long long plane = p.plane;
+  const int i = blockIdx.x * TZ + threadIdx.x % TZ, j = blockIdx.y * TR + threadIdx.x / TZ;
+  if (i >= nz || j >= nr) return;
+  const A* __restrict__ L = (const A*)a.lam;
+  const int cell = j * pitch + i;
+  #pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    int yi = i + XZ(q), yj = j + XR(q);
+    bool ok = true;
+    if (p.per_z) yi = wrap1(yi, nz);
+    else ok = ok && yi >= 0 && yi < nz;
+    if (p.per_r) yj = wrap1(yj, nr);
+    else ok = ok && yj >= 0 && yj < nr;
+    ok = ok && !(a.shift && yi == 0);
+    #pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+      out[(9 * kk + q) * plane + cell] = ok ? (double)L[(9 * kk + q) * plane + yj * pitch + yi] : 0.0;
+  }
+  for (int c = 27; c < 33; ++c) out[c * plane + cell] = (double)L[c * plane + cell];
+}
+
+// adj_cast_kernel: an FP64 stored-state lambda into the adjoint precision (33 planes)
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void adj_cast_kernel(Physics p, const double* in, void* out) {
+  using A = typename Mode<ST, false>::A;
+  const int i = blockIdx.x * TZ + threadIdx.x % TZ, j = blockIdx.y * TR + threadIdx.x / TZ;
+  if (i >= p.nz || j >= p.nr) return;
+  const int cell = j * p.pitch + i;
+  #pragma unroll
+  for (int c = 0; c < 33; ++c) stv(&((A*)out)[c * p.plane + cell], in[c * p.plane + cell]);
+}
+
+// ------------------------------------------------------------------------------------------
+// adj_init_cell_kernel: theta partials of the initial populations and moments, one thread per cell
+// (n_init = n_bg (1 + delta) at the initial momentum, populations at equilibrium).
+// ------------------------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void adj_init_cell_kernel(AdjArgs a) {
+  using A = typename Mode<ST, false>::A;
+  const Physics& p = a.p;
+  const int nz = p.nz, nr = p.nr, pitch = p.pitch;
+  const long long plane = p.plane;
+  const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
+  const int tile = xcd_tile(blockIdx.x, gx * gy);
+  const int i = (tile % gx) * TZ + threadIdx.x % TZ, j = (tile / gx) * TR + threadIdx.x / TZ;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < p.nz) {
-    const long long plane = p.plane;
-    const double h = p.h, dt = p.dt;
-    const double* L = a.lam_next;   // lambda^0
-    const A* Min = (const A*)a.M;
-    const double z = (double)i * h;
+  if (i < nz && j < nr) {
+    const A* __restrict__ L = (const A*)a.lam_next;   // lambda^0
+    const A* __restrict__ Min = (const A*)a.M;
+    const int cell = j * pitch + i;
+    const double z = (double)i * p.h;
     const double nb0 = nbg(p, z);
     double dl, dn;
     dnbg(p, z, dl, dn);
-    double cer[2] = {0.0, 0.0}, cb[2] = {0.0, 0.0};   // cumulative d/d(sigma_r), d/d(n_b)
-    for (int j = 0; j < p.nr; ++j) {
-      const int cell = j * p.pitch + i;
-      // populations and moments: f_eq of n_init = n_bg (1 + delta) at the initial momentum
-      const double n = (double)Min[cell] + nb0;
-      const double m1 = Min[plane + cell], m2 = Min[2 * plane + cell];
-      double bz, br;
-      const bool live = velocity<double>(n, m1, m2, p.n_floor, bz, br);
-      const double pz = live ? m1 / n : 0.0, pr = live ? m2 / n : 0.0;
-      const double uz = p.lam * bz, ur = p.lam * br;
-      double nbar = L[27 * plane + cell] + pz * L[28 * plane + cell] + pr * L[29 * plane + cell];
-      for (int q = 0; q < 9; ++q) {
-        const double cu = XZ(q) * uz + XR(q) * ur;
-        const double e = WQ<double>(q) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur));
-        nbar += e * (L[q * plane + cell] + pz * L[(9 + q) * plane + cell] + pr * L[(18 + q) * plane + cell]);
+    const double n = (double)Min[cell] + nb0;
+    const double m1 = Min[plane + cell], m2 = Min[2 * plane + cell];
+    double bz, br;
+    const bool live = velocity<double>(n, m1, m2, p.n_floor, bz, br);
+    const double pz = live ? m1 / n : 0.0, pr = live ? m2 / n : 0.0;
+    const double uz = p.lam * bz, ur = p.lam * br;
+    double nbar = (double)L[27 * plane + cell] + pz * (double)L[28 * plane + cell] +
+                  pr * (double)L[29 * plane + cell];
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      // adjoint of the stored population g^0(x, q): direct, or the transposed pull of f_bar^0
+      int yi = i, yj = j;
+      bool ok = true;
+      if (a.pull_in) {
+        yi += XZ(q);
+        yj += XR(q);
+        if (p.per_z) yi = wrap1(yi, nz);
+        else ok = ok && yi >= 0 && yi < nz;
+        if (p.per_r) yj = wrap1(yj, nr);
+        else ok = ok && yj >= 0 && yj < nr;
+        ok = ok && !(a.shift && yi == 0);
       }
-      if (nb0 > 0.0) {
-        const double ratio = n / nb0;   // 1 + delta
-        part[0] += nbar * ratio * dl;
-        part[1] += nbar * ratio * dn;
-      }
-      if (p.fields_on) {
-        // E_r^{-1}(j) = -h / (j+1) sum_{j' <= j} (j' + 1/2) n_b(z_i, r_j', -dt); B^{-1/2} likewise
-        const double r = (j + 0.5) * h;
-        double dsr, dnb;
-        ddriver(p, z, r, -dt, dsr, dnb);
-        cer[0] += (j + 0.5) * dsr;
-        cer[1] += (j + 0.5) * dnb;
-        ddriver(p, z + 0.5 * h, r, -0.5 * dt, dsr, dnb);
-        cb[0] += (j + 0.5) * dsr;
-        cb[1] += (j + 0.5) * dnb;
-        const double f = -h / (j + 1.0);
-        part[2] += f * (L[31 * plane + cell] * cer[0] + L[32 * plane + cell] * cb[0]);
-        part[3] += f * (L[31 * plane + cell] * cer[1] + L[32 * plane + cell] * cb[1]);
-      }
+      if (!ok) continue;
+      const int ys = yj * pitch + yi;
+      const double cu = XZ(q) * uz + XR(q) * ur;
+      const double e = WQ<double>(q) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur));
+      nbar += e * ((double)L[q * plane + ys] + pz * (double)L[(9 + q) * plane + ys] +
+                   pr * (double)L[(18 + q) * plane + ys]);
+    }
+    if (nb0 > 0.0) {
+      const double ratio = n / nb0;   // 1 + delta
+      part[0] += nbar * ratio * dl;
+      part[1] += nbar * ratio * dn;
     }
   }
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
+}
+
+// adj_init_field_kernel: theta partials of the initial driver fields, one thread per column.
+// E_r^{-1}(j) = -h / (j+1) sum_{j' <= j} (j' + 1/2) n_b(z_i, r_j', -dt); B^{-1/2} likewise at
+// z_i + dz/2, -dt/2.  The driver is separable: n_b = nb e_z(z, t) e_r(r).
+template <int ST>
+__global__ __launch_bounds__(64) void adj_init_field_kernel(AdjArgs a) {
+  using A = typename Mode<ST, false>::A;
+  const Physics& p = a.p;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < p.nz && p.fields_on) {
+    const A* __restrict__ L = (const A*)a.lam_next;
+    const long long plane = p.plane;
+    const double h = p.h, dt = p.dt;
+    const double z = (double)i * h;
+    const double d1 = z - (p.zd0 - dt), d2 = z + 0.5 * h - (p.zd0 - 0.5 * dt);
+    const double ez1 = exp(-(d1 * d1) / (2.0 * p.sigma_z * p.sigma_z));
+    const double ez2 = exp(-(d2 * d2) / (2.0 * p.sigma_z * p.sigma_z));
+    const double s3 = p.sigma_r * p.sigma_r * p.sigma_r;
+    double c0 = 0.0, c1 = 0.0;   // sum_{j' <= j} (j' + 1/2) e_r r^2 / sigma_r^3, (j' + 1/2) e_r
+    for (int j = 0; j < p.nr; ++j) {
+      const double r = (j + 0.5) * h;
+      const double er = exp(-(r * r) / (2.0 * p.sigma_r * p.sigma_r));
+      c0 += (j + 0.5) * er * r * r / s3;
+      c1 += (j + 0.5) * er;
+      const int cell = j * p.pitch + i;
+      const double f = -h / (j + 1.0);
+      const double l31 = (double)L[31 * plane + cell], l32 = (double)L[32 * plane + cell];
+      // d/d(sigma_r): nb e_z e_r r^2 / sigma_r^3 ; d/d(n_b): e_z e_r
+      part[2] += f * p.nb * c0 * (l31 * ez1 + l32 * ez2);
+      part[3] += f * c1 * (l31 * ez1 + l32 * ez2);
+    }
+  }
+  // block of 64 threads = one wavefront
+  for (int off = 32; off > 0; off >>= 1)
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) part[c] += __shfl_down(part[c], off, 64);
+  if (threadIdx.x == 0)
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) a.partials[(long long)blockIdx.x * 4 + c] += part[c];
 }
 
 // sum of per-block partials (fixed order) added into acc[4]
@@ -654,12 +716,10 @@ __global__ __launch_bounds__(NTHREADS) void partials_sum_kernel(const double* pa
                                                                 double* acc) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += NTHREADS)
+    #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] += partials[(long long)b * 4 + c];
-  __shared__ double res[4];
-  block_sum4(v, res);
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int c = 0; c < 4; ++c) acc[c] += res[c];
+  // block_sum4 adds into acc from thread 0 only, after its own barrier
+  block_sum4(v, acc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -669,37 +729,52 @@ static int step_blocks(const Physics& p) {
   return ((p.nz + TZ - 1) / TZ) * ((p.nr + TR - 1) / TR);
 }
 
-int adjoint_partial_blocks(const Physics& p) {
-  const int a = step_blocks(p), b = (p.nz + NTHREADS - 1) / NTHREADS;
-  return a > b ? a : b;
-}
+int adjoint_partial_blocks(const Physics& p) { return step_blocks(p); }
 
-#define ADJ_DISPATCH(storage, KERNEL, GRID, STREAM, ARGS)                            \
+#define ADJ_DISPATCH(storage, KERNEL, GRID, BLOCK, STREAM, ...)                      \
   do {                                                                               \
-    if ((storage) == 0) KERNEL<0><<<(GRID), NTHREADS, 0, (STREAM)>>>(ARGS);          \
-    else if ((storage) == 1) KERNEL<1><<<(GRID), NTHREADS, 0, (STREAM)>>>(ARGS);     \
-    else KERNEL<2><<<(GRID), NTHREADS, 0, (STREAM)>>>(ARGS);                         \
+    if ((storage) == 0) KERNEL<0><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);    \
+    else if ((storage) == 1) KERNEL<1><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__); \
+    else KERNEL<2><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);                   \
   } while (0)
 
-hipError_t launch_adjoint_step(int storage, const AdjArgs& a, double* grad_acc, hipStream_t st) {
+// a.partials holds 2 * adjoint_partial_blocks(p) accumulators of 4 doubles (site kernel, then
+// cell kernel); they must be zero before the first step and are summed by adjoint_reduce.
+hipError_t launch_adjoint_step(int storage, const AdjArgs& a, hipStream_t st) {
   const int nb = step_blocks(a.p);
-  ADJ_DISPATCH(storage, adj_site_kernel, dim3(nb), st, a);
+  ADJ_DISPATCH(storage, adj_site_kernel, dim3(nb), NTHREADS, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  partials_sum_kernel<<<1, NTHREADS, 0, st>>>(a.partials, nb, grad_acc);
-  ADJ_DISPATCH(storage, adj_field_kernel, dim3(nb), st, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  partials_sum_kernel<<<1, NTHREADS, 0, st>>>(a.partials, nb, grad_acc);
-  ADJ_DISPATCH(storage, adj_pop_kernel, dim3(nb), st, a);
+  AdjArgs b = a;
+  b.partials = a.partials + (long long)adjoint_partial_blocks(a.p) * 4;
+  ADJ_DISPATCH(storage, adj_cell_kernel, dim3(nb), NTHREADS, st, b);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_init(int storage, const AdjArgs& a, double* grad_acc, hipStream_t st) {
-  const int nb = (a.p.nz + NTHREADS - 1) / NTHREADS;
-  ADJ_DISPATCH(storage, adj_init_kernel, dim3(nb), st, a);
+hipError_t launch_adjoint_init(int storage, const AdjArgs& a, hipStream_t st) {
+  ADJ_DISPATCH(storage, adj_init_cell_kernel, dim3(step_blocks(a.p)), NTHREADS, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  partials_sum_kernel<<<1, NTHREADS, 0, st>>>(a.partials, nb, grad_acc);
+  AdjArgs b = a;
+  b.partials = a.partials + (long long)adjoint_partial_blocks(a.p) * 4;
+  ADJ_DISPATCH(storage, adj_init_field_kernel, dim3((a.p.nz + 63) / 64), 64, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_state(int storage, const AdjArgs& a, double* out, hipStream_t st) {
+  const dim3 grid((a.p.nz + TZ - 1) / TZ, (a.p.nr + TR - 1) / TR);
+  ADJ_DISPATCH(storage, adj_state_kernel, grid, NTHREADS, st, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_cast(int storage, const Physics& p, const double* in, void* out, hipStream_t st) {
+  const dim3 grid((p.nz + TZ - 1) / TZ, (p.nr + TR - 1) / TR);
+  ADJ_DISPATCH(storage, adj_cast_kernel, grid, NTHREADS, st, p, in, out);
+  return hipGetLastError();
+}
+
+hipError_t adjoint_reduce(const Physics& p, const double* partials, double* grad_acc, hipStream_t st) {
+  partials_sum_kernel<<<1, NTHREADS, 0, st>>>(partials, 2 * adjoint_partial_blocks(p), grad_acc);
   return hipGetLastError();
 }
 

@@ -248,6 +248,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     a.M_out = c->M(1 - c->cur);
     a.E_in = c->E(c->cur);
     a.E_out = c->E(1 - c->cur);
+    a.site_out = nullptr;
     HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "step launch");
     c->cur ^= 1;
     c->k += 1;
@@ -432,19 +433,33 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
 // --------------------------------------------------------------------------------------------
 namespace {
 
+size_t state_bytes(const Physics& p, int storage);
+
+// the site fields of one step (E_z, E_r, B_theta averaged to the sites), auxiliary type
+size_t site_bytes(const Physics& p, int storage) {
+  return round_up(3 * (size_t)p.plane * aux_bytes(storage), 256);
+}
+
+// Adjoint workspace: two lambda buffers and the work planes in the adjoint precision (the
+// auxiliary-plane type), the per-block partials, the gradient accumulator; the host-facing VJP
+// calls add an FP64 staging area for lambda in the stored-state layout.
 struct AdjLayout {
-  size_t lamA, lamB, work, partials, grad, vjp_total;
+  size_t lamA, lamB, work, partials, grad, core_total, stage, scratch, site, vjp_total;
 };
 
-AdjLayout adj_layout(const Physics& p) {
+AdjLayout adj_layout(const Physics& p, int storage) {
   AdjLayout L;
-  const size_t plane_d = (size_t)p.plane * sizeof(double);
+  const size_t plane_l = (size_t)p.plane * aux_bytes(storage);
   size_t off = 0;
-  L.lamA = off; off += round_up(33 * plane_d, 256);
-  L.lamB = off; off += round_up(33 * plane_d, 256);
-  L.work = off; off += round_up(11 * plane_d, 256);
-  L.partials = off; off += round_up((size_t)lbm::adjoint_partial_blocks(p) * 4 * sizeof(double), 256);
+  L.lamA = off; off += round_up(33 * plane_l, 256);
+  L.lamB = off; off += round_up(33 * plane_l, 256);
+  L.work = off; off += round_up(6 * plane_l, 256);
+  L.partials = off; off += round_up((size_t)lbm::adjoint_partial_blocks(p) * 8 * sizeof(double), 256);
   L.grad = off; off += 256;
+  L.core_total = off;
+  L.stage = off; off += round_up(33 * (size_t)p.plane * sizeof(double), 256);
+  L.scratch = off; off += state_bytes(p, storage);
+  L.site = off; off += site_bytes(p, storage);
   L.vjp_total = off;
   return L;
 }
@@ -488,21 +503,37 @@ hipError_t download_lam(const Physics& p, double* dst, const double* src, hipStr
                           (size_t)p.nz * sizeof(double), (size_t)33 * p.nr, hipMemcpyDeviceToHost, st);
 }
 
-lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, long long k, const double* lam_next, double* lam,
-                      char* ws, const AdjLayout& L) {
+lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, const void* site, long long k, const void* lam_next,
+                      void* lam, int pull_in, char* ws, const AdjLayout& L) {
   lbm::AdjArgs a;
   a.p = c->p;
   a.k = k;
   a.s = c->p.window ? k / c->p.m : 0;
   a.shift = (c->p.window && (k + 1) % c->p.m == 0) ? 1 : 0;
+  a.pull_in = pull_in;
   a.g = x.g;
   a.M = x.M;
   a.E = x.E;
   a.lam_next = lam_next;
   a.lam = lam;
-  a.work = (double*)(ws + L.work);
+  a.site = site;
+  a.work = ws + L.work;
   a.partials = (double*)(ws + L.partials);
   return a;
+}
+
+// forward step k from x into y, saving the site fields of the step
+hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const StateView& y, void* site) {
+  lbm::StepArgs a;
+  a.p = c->p;
+  a.k = k;
+  a.s = c->p.window ? k / c->p.m : 0;
+  a.shift = (c->p.window && (k + 1) % c->p.m == 0) ? 1 : 0;
+  a.g_in = x.g; a.g_out = y.g;
+  a.M_in = x.M; a.M_out = y.M;
+  a.E_in = x.E; a.E_out = y.E;
+  a.site_out = c->p.fields_on ? site : nullptr;
+  return lbm::launch_step(c->storage, a, c->stream);
 }
 
 }  // namespace
@@ -512,27 +543,30 @@ int lbm_vjp_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
   int rc = validate(cfg, &p);
   if (rc) return rc;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-  *bytes = adj_layout(p).vjp_total;
+  *bytes = adj_layout(p, cfg->storage).vjp_total;
   return LBM_OK;
 }
 
 int lbm_vjp_step(lbm_ctx* c, void* ws, size_t bytes, const double* lam_next, double* lam_out, double grad[4]) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
-  const AdjLayout L = adj_layout(c->p);
+  const AdjLayout L = adj_layout(c->p, c->storage);
   int rc = adj_check(c, ws, bytes, L.vjp_total);
   if (rc) return rc;
   if (!lam_next || !lam_out || !grad) return fail(LBM_EINVAL, "NULL argument");
   char* w = (char*)ws;
-  double* lamA = (double*)(w + L.lamA);
-  double* lamB = (double*)(w + L.lamB);
+  double* stage = (double*)(w + L.stage);
   double* gacc = (double*)(w + L.grad);
   HIP_CHECK(hipMemsetAsync(w, 0, L.vjp_total, c->stream), "clear");
-  HIP_CHECK(upload_lam(c->p, lamA, lam_next, c->stream), "upload");
+  HIP_CHECK(upload_lam(c->p, stage, lam_next, c->stream), "upload");
+  HIP_CHECK(lbm::launch_adjoint_cast(c->storage, c->p, stage, w + L.lamA, c->stream), "cast launch");
   const StateView x{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
-  const lbm::AdjArgs a = adj_args(c, x, c->k, lamA, lamB, w, L);
+  const lbm::AdjArgs a = adj_args(c, x, w + L.site, c->k, w + L.lamA, w + L.lamB, 0, w, L);
   if (a.s != c->s) return fail(LBM_ESTATE, "shift count does not match the step count");
-  HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, gacc, c->stream), "adjoint launch");
-  HIP_CHECK(download_lam(c->p, lam_out, lamB, c->stream), "download");
+  HIP_CHECK(step_with_site(c, c->k, x, state_at(w + L.scratch, c->p, c->storage), w + L.site), "step launch");
+  HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, c->stream), "adjoint launch");
+  HIP_CHECK(lbm::launch_adjoint_state(c->storage, a, stage, c->stream), "adjoint state launch");
+  HIP_CHECK(lbm::adjoint_reduce(c->p, a.partials, gacc, c->stream), "adjoint reduce");
+  HIP_CHECK(download_lam(c->p, lam_out, stage, c->stream), "download");
   HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   return LBM_OK;
@@ -540,19 +574,21 @@ int lbm_vjp_step(lbm_ctx* c, void* ws, size_t bytes, const double* lam_next, dou
 
 int lbm_vjp_init(lbm_ctx* c, void* ws, size_t bytes, const double* lam0, double grad[4]) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
-  const AdjLayout L = adj_layout(c->p);
+  const AdjLayout L = adj_layout(c->p, c->storage);
   int rc = adj_check(c, ws, bytes, L.vjp_total);
   if (rc) return rc;
   if (!lam0 || !grad) return fail(LBM_EINVAL, "NULL argument");
   if (c->k != 0) return fail(LBM_ESTATE, "lbm_vjp_init needs the initial state (step 0)");
   char* w = (char*)ws;
-  double* lamA = (double*)(w + L.lamA);
+  double* stage = (double*)(w + L.stage);
   double* gacc = (double*)(w + L.grad);
   HIP_CHECK(hipMemsetAsync(w, 0, L.vjp_total, c->stream), "clear");
-  HIP_CHECK(upload_lam(c->p, lamA, lam0, c->stream), "upload");
+  HIP_CHECK(upload_lam(c->p, stage, lam0, c->stream), "upload");
+  HIP_CHECK(lbm::launch_adjoint_cast(c->storage, c->p, stage, w + L.lamA, c->stream), "cast launch");
   const StateView x{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
-  const lbm::AdjArgs a = adj_args(c, x, 0, lamA, nullptr, w, L);
-  HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, gacc, c->stream), "adjoint init launch");
+  const lbm::AdjArgs a = adj_args(c, x, nullptr, 0, w + L.lamA, nullptr, 0, w, L);
+  HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, c->stream), "adjoint init launch");
+  HIP_CHECK(lbm::adjoint_reduce(c->p, a.partials, gacc, c->stream), "adjoint reduce");
   HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   return LBM_OK;
@@ -567,7 +603,8 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
   const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
   const size_t sb = state_bytes(p, cfg->storage);
   const int64_t seglen = ckpt_every < nsteps ? ckpt_every : nsteps;
-  *bytes = adj_layout(p).vjp_total + (size_t)nseg * sb + (size_t)seglen * sb;
+  *bytes = adj_layout(p, cfg->storage).core_total + (size_t)nseg * sb + (size_t)(seglen + 1) * sb +
+           (size_t)seglen * site_bytes(p, cfg->storage);
   return LBM_OK;
 }
 
@@ -592,13 +629,16 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   if (iw < 0 || iw >= p.nz - 1) return fail(LBM_EINVAL, "witness position outside the window");
   const double ww = xw - (double)iw;
 
-  const AdjLayout L = adj_layout(p);
+  const AdjLayout L = adj_layout(p, c->storage);
   const size_t sb = state_bytes(p, c->storage);
   const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
   char* w = (char*)ws;
-  char* ckpt = w + L.vjp_total;
+  char* ckpt = w + L.core_total;
   char* seg = ckpt + (size_t)nseg * sb;
-  double* lam[2] = {(double*)(w + L.lamA), (double*)(w + L.lamB)};
+  const int64_t seglen = ckpt_every < nsteps ? ckpt_every : nsteps;
+  char* sites = seg + (size_t)(seglen + 1) * sb;
+  const size_t stb = site_bytes(p, c->storage);
+  char* lam[2] = {w + L.lamA, w + L.lamB};
   double* gacc = (double*)(w + L.grad);
   const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
   const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
@@ -636,12 +676,17 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
     *J = (1.0 - ww) * e0 + ww * e1;
   }
   // seed lambda^N = dJ/dx^N
-  HIP_CHECK(hipMemsetAsync(w, 0, L.vjp_total, c->stream), "clear");
-  const double seedv[2] = {1.0 - ww, ww};
-  HIP_CHECK(hipMemcpyAsync(lam[0] + 30 * (size_t)p.plane + (size_t)obj->row * p.pitch + iw, seedv,
-                           2 * sizeof(double), hipMemcpyHostToDevice, c->stream),
-            "seed");
-  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  HIP_CHECK(hipMemsetAsync(w, 0, L.core_total, c->stream), "clear");
+  {
+    const size_t ab = aux_bytes(c->storage);
+    char* dst = lam[0] + (30 * (size_t)p.plane + (size_t)obj->row * p.pitch + (size_t)iw) * ab;
+    const double seedd[2] = {1.0 - ww, ww};
+    const float seedf[2] = {(float)(1.0 - ww), (float)ww};
+    HIP_CHECK(hipMemcpyAsync(dst, ab == 8 ? (const void*)seedd : (const void*)seedf, 2 * ab,
+                             hipMemcpyHostToDevice, c->stream),
+              "seed");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  }
   int cur = 0;
   // reverse sweep, segment by segment
   for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
@@ -649,31 +694,24 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
     const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
     HIP_CHECK(copy_state(state_at(seg, p, c->storage), state_at(ckpt + (size_t)sgi * sb, p, c->storage)),
               "restore");
-    for (int64_t t = 0; t + 1 < len; ++t) {
-      const StateView xi = state_at(seg + (size_t)t * sb, p, c->storage);
-      const StateView xo = state_at(seg + (size_t)(t + 1) * sb, p, c->storage);
-      lbm::StepArgs a;
-      a.p = p;
-      a.k = k0 + t;
-      a.s = p.window ? a.k / p.m : 0;
-      a.shift = (p.window && (a.k + 1) % p.m == 0) ? 1 : 0;
-      a.g_in = xi.g; a.g_out = xo.g;
-      a.M_in = xi.M; a.M_out = xo.M;
-      a.E_in = xi.E; a.E_out = xo.E;
-      HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "recompute launch");
-    }
+    // recompute the segment's states and the site fields of each of its steps (slot len is scratch)
+    for (int64_t t = 0; t < len; ++t)
+      HIP_CHECK(step_with_site(c, k0 + t, state_at(seg + (size_t)t * sb, p, c->storage),
+                               state_at(seg + (size_t)(t + 1) * sb, p, c->storage), sites + (size_t)t * stb),
+                "recompute launch");
     for (int64_t t = len - 1; t >= 0; --t) {
       const StateView x = state_at(seg + (size_t)t * sb, p, c->storage);
-      const lbm::AdjArgs a = adj_args(c, x, k0 + t, lam[cur], lam[1 - cur], w, L);
-      HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, gacc, c->stream), "adjoint launch");
+      const lbm::AdjArgs a = adj_args(c, x, sites + (size_t)t * stb, k0 + t, lam[cur], lam[1 - cur], 1, w, L);
+      HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, c->stream), "adjoint launch");
       cur ^= 1;
     }
   }
   // initial state
   {
     const StateView x0 = state_at(ckpt, p, c->storage);
-    const lbm::AdjArgs a = adj_args(c, x0, 0, lam[cur], nullptr, w, L);
-    HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, gacc, c->stream), "adjoint init launch");
+    const lbm::AdjArgs a = adj_args(c, x0, nullptr, 0, lam[cur], nullptr, 1, w, L);
+    HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, c->stream), "adjoint init launch");
+    HIP_CHECK(lbm::adjoint_reduce(c->p, a.partials, gacc, c->stream), "adjoint reduce");
   }
   HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");

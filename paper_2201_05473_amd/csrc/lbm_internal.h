@@ -40,21 +40,28 @@ struct StepArgs {
   void* M_out;
   const void* E_in;  // [3 planes] E_z, E_r, B_theta
   void* E_out;
+  void* site_out;    // optional (fields on): [3 planes] E_z, E_r, B_theta averaged to the sites as
+                     // used by the fluid, at the output index; nullptr to skip
 };
 
 // One reverse step of the adjoint at the state x^k (k, s, shift as for the forward step k).
-// lam_next / lam: 33 pitched FP64 planes (27 populations, 3 moments, E_z, E_r, B_theta);
-// work: 11 pitched FP64 planes; partials: per-block theta partials.
+// lam_next / lam: 33 pitched planes in the adjoint precision (FP64 for FP64 storage, FP32
+// otherwise): 27 population planes, 3 moments, E_z, E_r, B_theta.  The population planes of lam
+// (output) hold f_bar^k, the adjoint of the populations each site pulls in step k; those of
+// lam_next hold f_bar^{k+1} (pull_in = 1) or the adjoint of the stored populations g^{k+1}
+// (pull_in = 0).  work: 6 pitched planes (adjoint precision); partials: per-block theta partials.
 struct AdjArgs {
   Physics p;
   long long k, s;
   int shift;
+  int pull_in;
   const void* g;
   const void* M;
   const void* E;
-  const double* lam_next;
-  double* lam;
-  double* work;
+  const void* lam_next;
+  void* lam;
+  void* work;
+  const void* site;   // site fields of step k (3 planes, auxiliary type, output index), fields on
   double* partials;
 };
 
@@ -78,10 +85,16 @@ int diag_blocks(const Physics& p);
 hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
                               const void* M, const void* E, double* partials, double* out,
                               hipStream_t st);
-// Adjoint: per-block partial count, one reverse step (theta partials added to grad_acc[4]),
-// and the theta partials of the initial state (lam_next = lambda^0).
+// Adjoint: per-block accumulators (2 * adjoint_partial_blocks of 4 doubles, zeroed by the caller),
+// one reverse step, the theta partials of the initial state (lam_next = lambda^0), and the final
+// sum of the accumulators added into grad_acc[4].
 int adjoint_partial_blocks(const Physics& p);
-hipError_t launch_adjoint_step(int storage, const AdjArgs& a, double* grad_acc, hipStream_t st);
-hipError_t launch_adjoint_init(int storage, const AdjArgs& a, double* grad_acc, hipStream_t st);
+hipError_t launch_adjoint_step(int storage, const AdjArgs& a, hipStream_t st);
+hipError_t launch_adjoint_init(int storage, const AdjArgs& a, hipStream_t st);
+hipError_t adjoint_reduce(const Physics& p, const double* partials, double* grad_acc, hipStream_t st);
+// lambda^k (a.lam) in the stored-state layout: 33 pitched FP64 planes written to out.
+hipError_t launch_adjoint_state(int storage, const AdjArgs& a, double* out, hipStream_t st);
+// 33 pitched FP64 planes (stored-state layout) into the adjoint precision.
+hipError_t launch_adjoint_cast(int storage, const Physics& p, const double* in, void* out, hipStream_t st);
 
 }  // namespace lbm

@@ -22,7 +22,7 @@ namespace lbm {
 // phase can wait for the halo loads alone while the population loads stay in flight across the
 // LDS barriers (which only wait for LDS traffic).
 // ------------------------------------------------------------------------------------------
-template <int ST, bool FIELDS, bool M64>
+template <int ST, bool FIELDS, bool M64, bool SITE>
 __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using S = typename Mode<ST, M64>::S;
   using C = typename Mode<ST, M64>::C;
@@ -337,6 +337,12 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     Ebr = (C)(CF(0.5) * (sEr[ty][tx + 1] + sEr[ty + 1][tx + 1]));
     Bb = (C)((sBo[ty + 2][tx + 2] + sBo[ty + 2][tx + 1] + sBo[ty + 1][tx + 2] + sBo[ty + 1][tx + 1] +
               sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * CF(0.125));
+    if (SITE) {
+      A* So = (A*)a.site_out;
+      stv(So + oo, Ebz);
+      stv(So + plane + oo, Ebr);
+      stv(So + 2 * plane + oo, Bb);
+    }
   }
 
   // Eq. (4): F = -n (E + beta x B), (beta x B)_z = beta_r B, (beta x B)_r = -beta_z B
@@ -622,8 +628,9 @@ static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr);
 
 template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
-  if (a.p.fields_on) step_kernel<ST, true, M64><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else step_kernel<ST, false, M64><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on) step_kernel<ST, true, M64, false><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else step_kernel<ST, false, M64, false><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
