@@ -72,49 +72,19 @@ __device__ __forceinline__ void block_sum4(double v[4], double* acc) {
   __shared__ double red[NTHREADS / 64][4];
   const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
   for (int off = 32; off > 0; off >>= 1)
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 4; ++c) v[c] += __shfl_down(v[c], off, 64);
   if (lane == 0)
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 4; ++c) red[wid][c] = v[c];
   __syncthreads();
   if (threadIdx.x == 0) {
     double r[4] = {0.0, 0.0, 0.0, 0.0};
     for (int w = 0; w < NTHREADS / 64; ++w)
-      #pragma unroll
+#pragma unroll
       for (int c = 0; c < 4; ++c) r[c] += red[w][c];
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] += r[c];
-  }
-}
-
-// VJP of f_eq_q(M) (all three lattices at once) with respect to the moments M:
-// f_eq_{k,q} = w_q M_k (1 + Q_q(u)), u = lam beta(M).  a[k] is the adjoint of f_eq_{k,q}.
-__device__ __forceinline__ void feq_vjp(const Physics& p, int q, const double M[3], const double a[3],
-                                        double Mbar[3]) {
-  const double w = WQ<double>(q);
-  double bz, br;
-  const bool live = velocity<double>(M[0], M[1], M[2], p.n_floor, bz, br);
-  const double uz = p.lam * bz, ur = p.lam * br;
-  const double cu = XZ(q) * uz + XR(q) * ur;
-  const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-  double ubz = 0.0, ubr = 0.0;
-  #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    Mbar[k] += a[k] * w * (1.0 + Q);
-    const double s = a[k] * w * M[k];
-    ubz += s * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);
-    ubr += s * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
-  }
-  if (live) {
-    const double n = M[0], pz = M[1] / n, pr = M[2] / n;
-    const double g2 = 1.0 + pz * pz + pr * pr, ig = 1.0 / sqrt(g2), ig3 = ig / g2;
-    const double bbz = p.lam * ubz, bbr = p.lam * ubr;
-    const double pdot = pz * bbz + pr * bbr;
-    const double pbz = bbz * ig - pz * pdot * ig3, pbr = bbr * ig - pr * pdot * ig3;
-    Mbar[1] += pbz / n;
-    Mbar[2] += pbr / n;
-    Mbar[0] -= (pbz * pz + pbr * pr) / n;
   }
 }
 
@@ -175,13 +145,13 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   A sfield[3] = {A(0), A(0), A(0)};
   bool gok[9];
   bool ghost[9];   // the pull in direction q reads an equilibrium ghost of a non-periodic edge
-  #pragma unroll
+#pragma unroll
   for (int q = 0; q < 9; ++q) {
     const int ui = ic - XZ(q), uj = jc - XR(q);
     const int si = p.per_z ? wrap1(ui, nz) : (ui < 0 ? 0 : (ui < nz ? ui : nz - 1));
     const int sj = p.per_r ? wrap1(uj, nr) : (uj < 0 ? 0 : (uj < nr ? uj : nr - 1));
     const int off = sj * pitch + si;
-    #pragma unroll
+#pragma unroll
     for (int kk = 0; kk < 3; ++kk) graw[9 * kk + q] = (gin + (9 * kk + q) * plane)[off];
     ghost[q] = (!p.per_z && (ui < 0 || ui >= nz)) || (!p.per_r && (uj < 0 || uj >= nr));
     int yi = ib, yj = jc;
@@ -196,20 +166,20 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
     }
     gok[q] = ok;
     const int yo = yj * pitch + yi;
-    #pragma unroll
+#pragma unroll
     for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
   }
-  #pragma unroll
+#pragma unroll
   for (int kk = 0; kk < 3; ++kk) mbar[kk] = (L + (27 + kk) * plane)[jc * pitch + ib];
   if (p.fields_on)
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[jc * pitch + ib];
   // zeroth moments of the populations pulled from inside the domain (deviation form for lattice 0)
   double Am[3] = {0.0, 0.0, 0.0};
-  #pragma unroll
+#pragma unroll
   for (int q = 0; q < 9; ++q)
     if (!ghost[q])
-      #pragma unroll
+#pragma unroll
       for (int kk = 0; kk < 3; ++kk) Am[kk] += (double)ldv(graw[9 * kk + q]);
 
   for (int t = tid; t < TZ + 2; t += NTHREADS) {
@@ -225,15 +195,15 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
     A* __restrict__ W = (A*)a.work;
     if (dropped) {
       // the first column leaves the window in this step: no site, no adjoint source
-      #pragma unroll
+#pragma unroll
       for (int c = 0; c < 27; ++c) (Lo + c * plane)[cell] = A(0);
-      #pragma unroll
+#pragma unroll
       for (int c = 0; c < 6; ++c) (W + c * plane)[cell] = A(0);
     } else {
       // forward recompute of the site's moments (raw values): background of the pulled lattice-0
       // deviations, and the equilibrium ghosts (moments of the source cell after the z rule then
       // the r rule; the window front is plasma at rest)
-      #pragma unroll
+#pragma unroll
       for (int q = 0; q < 9; ++q) {
         if (ghost[q]) {
           int si = i - XZ(q), sj = j - XR(q);
@@ -257,7 +227,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
           const double uz = p.lam * bz, ur = p.lam * br;
           const double cu = XZ(q) * uz + XR(q) * ur;
           const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-          #pragma unroll
+#pragma unroll
           for (int kk = 0; kk < 3; ++kk) Am[kk] += WQ<double>(q) * Mg[kk] * (1.0 + Q);
         } else {
           Am[0] += WQ<double>(q) * sN[tx + 1 - XZ(q)];
@@ -279,25 +249,33 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       // g' = (1 - 1/tau) f + e/tau + w dt F,  M' = A + dt F,  e = w A (1 + Q(u))
       double Fb[3], Ab[3];
       double ubz = 0.0, ubr = 0.0;
-      #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) {
-        double sw = 0.0, s0 = 0.0;
-        #pragma unroll
-        for (int q = 0; q < 9; ++q) {
+      double sw[3] = {0.0, 0.0, 0.0}, s0[3] = {0.0, 0.0, 0.0};
+      const double itau = 1.0 / p.tau, usq = uz * uz + ur * ur;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const double w = WQ<double>(q);
+        const double cu = XZ(q) * uz + XR(q) * ur;
+        const double e1 = w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);   // e_q / A
+        const double fz = w * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);    // w dQ/du_z
+        const double fr = w * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
+        double az = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
           const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
-          const double w = WQ<double>(q);
-          const double cu = XZ(q) * uz + XR(q) * ur;
-          const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-          const double eb = gbq / p.tau;
-          sw += w * gbq;
-          s0 += eb * w * (1.0 + Q);
-          const double sq = eb * w * Am[kk];
-          ubz += sq * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);
-          ubr += sq * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
+          sw[kk] += w * gbq;
+          s0[kk] += gbq * e1;
+          az += gbq * Am[kk];
         }
+        ubz += az * fz;
+        ubr += az * fr;
+      }
+      ubz *= itau;
+      ubr *= itau;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
         const double Mb = (double)mbar[kk];
-        Fb[kk] = dt * (sw + Mb);
-        Ab[kk] = Mb + s0;
+        Fb[kk] = dt * (sw[kk] + Mb);
+        Ab[kk] = Mb + s0[kk] * itau;
       }
       double bbz = p.lam * ubz, bbr = p.lam * ubr;
       double Ebz_b = 0.0, Ebr_b = 0.0, Bb_b = 0.0;
@@ -312,7 +290,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       }
       if (p.cyl_on) {
         // F_k += (-A_k beta_r + D dA_k/dr) / r
-        #pragma unroll
+#pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
           bbr += Fb[kk] * (-Am[kk] * ir);
           Ab[kk] += Fb[kk] * (-br * ir);
@@ -328,14 +306,14 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       }
       // adjoint of the pulled populations: (1 - 1/tau) g_bar' + A_bar
       const double c1 = 1.0 - 1.0 / p.tau;
-      #pragma unroll
+#pragma unroll
       for (int kk = 0; kk < 3; ++kk)
-        #pragma unroll
+#pragma unroll
         for (int q = 0; q < 9; ++q) {
           const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
           stv(&(Lo + (9 * kk + q) * plane)[cell], c1 * gbq + Ab[kk]);
         }
-      #pragma unroll
+#pragma unroll
       for (int kk = 0; kk < 3; ++kk) stv(&(W + (W_F + kk) * plane)[cell], Fb[kk]);
       stv(&(W + W_EZ * plane)[cell], Ebz_b);
       stv(&(W + W_ER * plane)[cell], Ebr_b);
@@ -346,7 +324,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
         double dl, dn;
         dnbg(p, (double)(a.s + nz) * h, dl, dn);
         double sum = 0.0;
-        #pragma unroll
+#pragma unroll
         for (int q = 0; q < 9; ++q)
           if (XZ(q) == -1) sum += WQ<double>(q) * (c1 * (gok[q] ? (double)gbar[q] : 0.0) + Ab[0]);
         part[0] += sum * dl;
@@ -354,7 +332,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
         if (a.shift) {
           // the new front column of x^{k+1} (output index nz - 1): w_q n_bg and n_bg
           double s2 = (double)(L + 27 * plane)[j * pitch + (nz - 1)];
-          #pragma unroll
+#pragma unroll
           for (int q = 0; q < 9; ++q) {
             int yi = nz - 1, yj = j;
             if (a.pull_in) {
@@ -407,35 +385,84 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
   __shared__ double sLZ[LZR][LZZ];
   __shared__ double sLR[LRR][LRZ];
 
-  // cell in the domain after the periodic wrap of z (r is never periodic with fields on)
-  auto cellz = [&](int& i, int j) -> bool {
-    if (j < 0 || j >= nr) return false;
-    if (p.per_z) { i = wrapi(i, nz); return true; }
-    return i >= 0 && i < nz;
+  // cell (ci, cj) in the domain after the periodic wrap of z (r is never periodic with fields
+  // on); ci becomes the wrapped column
+  auto cellz = [&](int& ci, int cj) -> bool {
+    if (cj < 0 || cj >= nr) return false;
+    if (p.per_z) { ci = wrapi(ci, nz); return true; }
+    return ci >= 0 && ci < nz;
   };
-  auto site = [&](int plane_id, int i, int j) -> double {
-    return cellz(i, j) ? (double)W[plane_id * plane + j * pitch + i] : 0.0;
+  // clamped in-plane offset of a site value (ok: in the domain)
+  auto woff = [&](int ci, int cj, bool& ok) -> int {
+    ok = cellz(ci, cj);
+    ci = ci < 0 ? 0 : (ci >= nz ? nz - 1 : ci);
+    cj = cj < 0 ? 0 : (cj >= nr ? nr - 1 : cj);
+    return cj * pitch + ci;
   };
-  // adjoint of E^k / B^{k+1/2} as state of x^{k+1} (zero for the column dropped by the shift)
-  auto next = [&](int c, int i, int j) -> double {
-    if (!cellz(i, j)) return 0.0;
-    const int o = i - a.shift;
-    return o < 0 ? 0.0 : (double)L[c * plane + j * pitch + o];
+  // clamped offset in x^{k+1} of the state value at logical cell (ci, cj) of x^k (ok: it exists,
+  // i.e. in the domain and not the column dropped by the shift)
+  auto noff = [&](int ci, int cj, bool& ok) -> int {
+    ok = cellz(ci, cj);
+    int o = ci - a.shift;
+    ok = ok && o >= 0;
+    o = o < 0 ? 0 : (o >= nz ? nz - 1 : o);
+    cj = cj < 0 ? 0 : (cj >= nr ? nr - 1 : cj);
+    return cj * pitch + o;
   };
 
   const int i = i0 + tx, j = j0 + ty;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   double jz = 0.0, jr = 0.0;
-  const int cell = j * pitch + i;
+  const int ic = i < nz ? i : nz - 1, jc = j < nr ? j : nr - 1;
+  const int cell = j * pitch + i, cellc = jc * pitch + ic;
   const bool mine = i < nz && j < nr;
 
+  // per-cell loads first: moments of x^k, and F_bar at rows j-1, j, j+1 (axisymmetric source)
+  const A* __restrict__ Min = (const A*)a.M;
+  A mraw[3], fb[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) mraw[k] = (Min + k * plane)[cellc];
+  if (p.cyl_on) {
+    const int cm = jc >= 1 ? cellc - pitch : cellc, cp = jc + 1 < nr ? cellc + pitch : cellc;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      fb[k][0] = (W + (W_F + k) * plane)[cm];
+      fb[k][1] = (W + (W_F + k) * plane)[cellc];
+      fb[k][2] = (W + (W_F + k) * plane)[cp];
+    }
+  }
+
   if (p.fields_on) {
-    for (int t = tid; t < BBR * BBZ; t += NTHREADS)
-      sBb[t / BBZ][t % BBZ] = site(W_B, i0 - 1 + t % BBZ, j0 - 1 + t / BBZ);
-    for (int t = tid; t < EBR * EBZ; t += NTHREADS)
-      sEb[t / EBZ][t % EBZ] = site(W_EZ, i0 - 1 + t % EBZ, j0 + t / EBZ);
-    for (int t = tid; t < RBR * RBZ; t += NTHREADS)
-      sRb[t / RBZ][t % RBZ] = site(W_ER, i0 + t % RBZ, j0 - 1 + t / RBZ);
+    constexpr int NBB = BBR * BBZ, NEB = EBR * EBZ, NRB = RBR * RBZ;
+    constexpr int NLB = LBR * LBZ, NLZ = LZR * LZZ, NLR = LRR * LRZ;
+    static_assert(NBB <= 2 * NTHREADS && NEB <= 2 * NTHREADS && NRB <= 2 * NTHREADS &&
+                      NLB <= 2 * NTHREADS && NLZ <= 2 * NTHREADS && NLR <= 2 * NTHREADS,
+                  "two slots per thread cover every LDS region");
+    // all halo loads in flight at once (clamped addresses, selected by the flags)
+    A rBb[2], rEb[2], rRb[2], rLB[2], rLZ[2], rLR[2];
+    bool oBb[2], oEb[2], oRb[2], oLB[2], oLZ[2], oLR[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      int t = min(tid + sl * NTHREADS, NBB - 1);
+      rBb[sl] = (W + W_B * plane)[woff(i0 - 1 + t % BBZ, j0 - 1 + t / BBZ, oBb[sl])];
+      t = min(tid + sl * NTHREADS, NEB - 1);
+      rEb[sl] = (W + W_EZ * plane)[woff(i0 - 1 + t % EBZ, j0 + t / EBZ, oEb[sl])];
+      t = min(tid + sl * NTHREADS, NRB - 1);
+      rRb[sl] = (W + W_ER * plane)[woff(i0 + t % RBZ, j0 - 1 + t / RBZ, oRb[sl])];
+      t = min(tid + sl * NTHREADS, NLB - 1);
+      rLB[sl] = (L + 32 * plane)[noff(i0 - 1 + t % LBZ, j0 - 1 + t / LBZ, oLB[sl])];
+      t = min(tid + sl * NTHREADS, NLZ - 1);
+      rLZ[sl] = (L + 30 * plane)[noff(i0 - 1 + t % LZZ, j0 + t / LZZ, oLZ[sl])];
+      t = min(tid + sl * NTHREADS, NLR - 1);
+      rLR[sl] = (L + 31 * plane)[noff(i0 + t % LRZ, j0 - 1 + t / LRZ, oLR[sl])];
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      int t = tid + sl * NTHREADS;
+      if (t < NBB) sBb[t / BBZ][t % BBZ] = oBb[sl] ? (double)rBb[sl] : 0.0;
+      if (t < NEB) sEb[t / EBZ][t % EBZ] = oEb[sl] ? (double)rEb[sl] : 0.0;
+      if (t < NRB) sRb[t / RBZ][t % RBZ] = oRb[sl] ? (double)rRb[sl] : 0.0;
+    }
     __syncthreads();
     // 1/8 of the B_bar of the sites that average the corner (ci, cj) (rear copy rule included)
     auto bsum = [&](int ci, int cj) -> double {
@@ -445,37 +472,46 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
       return v * 0.125;
     };
     // L_B' = lambda'_B + its use in the fluid's B average
-    for (int t = tid; t < LBR * LBZ; t += NTHREADS) {
-      const int ci = i0 - 1 + t % LBZ, cj = j0 - 1 + t / LBZ;
-      int cw = ci;
-      sLB[t / LBZ][t % LBZ] = cellz(cw, cj) ? next(32, ci, cj) + bsum(ci, cj) : 0.0;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int t = tid + sl * NTHREADS;
+      if (t < NLB) {
+        const int ci = i0 - 1 + t % LBZ, cj = j0 - 1 + t / LBZ;
+        int cw = ci;
+        sLB[t / LBZ][t % LBZ] =
+            cellz(cw, cj) ? (oLB[sl] ? (double)rLB[sl] : 0.0) + bsum(ci, cj) : 0.0;
+      }
     }
     __syncthreads();
     auto LB = [&](int ci, int cj) -> double { return sLB[cj - (j0 - 1)][ci - (i0 - 1)]; };
-    for (int t = tid; t < LZR * LZZ; t += NTHREADS) {
-      const int ci = i0 - 1 + t % LZZ, cj = j0 + t / LZZ;
-      int cw = ci;
-      double v = 0.0;
-      if (cellz(cw, cj)) {
-        const int ea = ci - (i0 - 1), eb = cj - j0;
-        v = next(30, ci, cj) + 0.5 * (sEb[eb][ea] + sEb[eb][ea + 1]);
-        if (!p.per_z && cw == 0) v += 0.5 * sEb[eb][ea];     // rear copy E_z(-1) = E_z(0)
-        if (cj <= nr - 2) v -= dt / h * LB(ci, cj);
-        if (cj >= 1) v += dt / h * LB(ci, cj - 1);
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int t = tid + sl * NTHREADS;
+      if (t < NLZ) {
+        const int ci = i0 - 1 + t % LZZ, cj = j0 + t / LZZ;
+        int cw = ci;
+        double v = 0.0;
+        if (cellz(cw, cj)) {
+          const int ea = ci - (i0 - 1), eb = cj - j0;
+          v = (oLZ[sl] ? (double)rLZ[sl] : 0.0) + 0.5 * (sEb[eb][ea] + sEb[eb][ea + 1]);
+          if (!p.per_z && cw == 0) v += 0.5 * sEb[eb][ea];     // rear copy E_z(-1) = E_z(0)
+          if (cj <= nr - 2) v -= dt / h * LB(ci, cj);
+          if (cj >= 1) v += dt / h * LB(ci, cj - 1);
+        }
+        sLZ[t / LZZ][t % LZZ] = v;
       }
-      sLZ[t / LZZ][t % LZZ] = v;
-    }
-    for (int t = tid; t < LRR * LRZ; t += NTHREADS) {
-      const int ci = i0 + t % LRZ, cj = j0 - 1 + t / LRZ;
-      int cw = ci;
-      double v = 0.0;
-      if (cellz(cw, cj)) {
-        const int ra = ci - i0, rb = cj - (j0 - 1);
-        v = next(31, ci, cj) + 0.5 * (sRb[rb][ra] + sRb[rb + 1][ra]);
-        if (p.per_z || cw <= nz - 2) v += dt / h * LB(ci, cj);
-        if (p.per_z || cw >= 1) v -= dt / h * LB(ci - 1, cj);
+      if (t < NLR) {
+        const int ci = i0 + t % LRZ, cj = j0 - 1 + t / LRZ;
+        int cw = ci;
+        double v = 0.0;
+        if (cellz(cw, cj)) {
+          const int ra = ci - i0, rb = cj - (j0 - 1);
+          v = (oLR[sl] ? (double)rLR[sl] : 0.0) + 0.5 * (sRb[rb][ra] + sRb[rb + 1][ra]);
+          if (p.per_z || cw <= nz - 2) v += dt / h * LB(ci, cj);
+          if (p.per_z || cw >= 1) v -= dt / h * LB(ci - 1, cj);
+        }
+        sLR[t / LRZ][t % LRZ] = v;
       }
-      sLR[t / LRZ][t % LRZ] = v;
     }
     __syncthreads();
     if (mine) {
@@ -488,9 +524,9 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
       if (j + 1 < nr) lb -= dt * (j + 1.0) / ((j + 1.5) * h) * LZ(i, j + 1);
       if (p.per_z || i >= 1) lb -= dt / h * ler;
       if (p.per_z || i + 1 < nz) lb += dt / h * LR(i + 1, j);
-      stv(&Lo[30 * plane + cell], lez);
-      stv(&Lo[31 * plane + cell], ler);
-      stv(&Lo[32 * plane + cell], lb);
+      stv(&(Lo + 30 * plane)[cell], lez);
+      stv(&(Lo + 31 * plane)[cell], ler);
+      stv(&(Lo + 32 * plane)[cell], lb);
       jz = 0.5 * dt * (lez + ((p.per_z || i >= 1) ? LZ(i - 1, j) : 0.0));
       if (!p.per_z && !p.window && i == nz - 1) jz += 0.5 * dt * lez;   // front copy of J_z
       jr = 0.5 * dt * (ler + (j >= 1 ? LR(i, j - 1) : 0.0));
@@ -503,16 +539,18 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
     }
   } else if (mine) {
     // fields are carried unchanged and unused
-    #pragma unroll
-    for (int c = 0; c < 3; ++c) stv(&Lo[(30 + c) * plane + cell], next(30 + c, i, j));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bool ok;
+      const int o = noff(i, j, ok);
+      stv(&(Lo + (30 + c) * plane)[cell], ok ? (double)(L + (30 + c) * plane)[o] : 0.0);
+    }
   }
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
   if (!mine) return;   // no barrier below this point
 
   // ---- lambda of the moments ----
-  const A* __restrict__ Min = (const A*)a.M;
-  const double M[3] = {(double)Min[cell] + nbg(p, (double)(a.s + i) * h), (double)Min[plane + cell],
-                       (double)Min[2 * plane + cell]};
+  const double M[3] = {(double)mraw[0] + nbg(p, (double)(a.s + i) * h), (double)mraw[1], (double)mraw[2]};
   double Mb[3] = {0.0, 0.0, 0.0};
   // (a) face currents of Ampere's law
   if (p.fields_on) current_vjp(p, M, jz, jr, Mb);
@@ -520,53 +558,99 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
   if (p.cyl_on) {
     const double c = p.D / (2.0 * h);
     const double par[3] = {1.0, 1.0, -1.0};
-    #pragma unroll
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
       double v = 0.0;
-      if (j >= 1) v += c / ((j - 0.5) * h) * (double)W[(W_F + k) * plane + cell - pitch];
-      if (j + 1 < nr) v -= c / ((j + 1.5) * h) * (double)W[(W_F + k) * plane + cell + pitch];
-      if (j == 0) v -= par[k] * c / (0.5 * h) * (double)W[(W_F + k) * plane + cell];
-      if (j == nr - 1) v += c / ((j + 0.5) * h) * (double)W[(W_F + k) * plane + cell];
+      if (j >= 1) v += c / ((j - 0.5) * h) * (double)fb[k][0];
+      if (j + 1 < nr) v -= c / ((j + 1.5) * h) * (double)fb[k][2];
+      if (j == 0) v -= par[k] * c / (0.5 * h) * (double)fb[k][1];
+      if (j == nr - 1) v += c / ((j + 0.5) * h) * (double)fb[k][1];
       Mb[k] += v;
     }
   }
   // (c) equilibrium ghosts whose moments are copies (or the axis mirror) of this cell: the ghost
-  // positions (si, sj) outside a non-periodic edge whose source is this cell, each pulled in
-  // direction q by the computed site (si, sj) + xi_q.  The front ghost of the moving window is
-  // plasma at rest and depends on theta only.
+  // positions outside a non-periodic edge whose source is this cell, each pulled by the computed
+  // site ghost + xi_q.  A side ghost is pulled in the three directions that point back into the
+  // domain, a corner ghost in one.  The front ghost of the moving window is plasma at rest and
+  // depends on theta only.
   const bool zlo = !p.per_z && i == 0, zhi = !p.per_z && !p.window && i == nz - 1;
   const bool rlo = !p.per_r && j == 0, rhi = !p.per_r && j == nr - 1;
   if (zlo || zhi || rlo || rhi) {
-    const int gzs[2] = {i, zlo ? -1 : nz};
-    const int grs[2] = {j, rlo ? -1 : nr};
-    const int ngz = (zlo || zhi) ? 2 : 1, ngr = (rlo || rhi) ? 2 : 1;
-    for (int a_ = 0; a_ < ngz; ++a_)
-      for (int b_ = 0; b_ < ngr; ++b_) {
-        if (a_ == 0 && b_ == 0) continue;   // the cell itself
-        const int si = gzs[a_], sj = grs[b_];
-        const double sgn = sj < 0 ? -1.0 : 1.0;
-        const double Mg[3] = {M[0], M[1], sgn * M[2]};
-        #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          int yi = si + XZ(q), yj = sj + XR(q);
-          if (p.per_z) yi = wrap1(yi, nz);
-          else if (yi < 0 || yi >= nz) continue;
-          if (p.per_r) yj = wrap1(yj, nr);
-          else if (yj < 0 || yj >= nr) continue;
-          if (a.shift && yi == 0) continue;   // not a computed site
-          const int ys = yj * pitch + yi;
-          const double af[3] = {(double)Lo[q * plane + ys], (double)Lo[(9 + q) * plane + ys],
-                                (double)Lo[(18 + q) * plane + ys]};
-          double Mgb[3] = {0.0, 0.0, 0.0};
-          feq_vjp(p, q, Mg, af, Mgb);
-          Mb[0] += Mgb[0];
-          Mb[1] += Mgb[1];
-          Mb[2] += sgn * Mgb[2];
-        }
+    const int gz = zlo ? -1 : nz, gr = rlo ? -1 : nr;
+    // slots 0..2: the r-side ghost (i, gr); 3..5: the z-side ghost (gz, j); 6: the corner (gz, gr)
+    int gsi[7], gsj[7], gq[7], yo[7];
+    bool gv[7];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      gsi[c] = i;
+      gsj[c] = gr;
+      gq[c] = rlo ? (c == 0 ? 2 : (c == 1 ? 5 : 6)) : (c == 0 ? 4 : (c == 1 ? 7 : 8));
+      gv[c] = rlo || rhi;
+      gsi[3 + c] = gz;
+      gsj[3 + c] = j;
+      gq[3 + c] = zlo ? (c == 0 ? 1 : (c == 1 ? 5 : 8)) : (c == 0 ? 3 : (c == 1 ? 6 : 7));
+      gv[3 + c] = zlo || zhi;
+    }
+    gsi[6] = gz;
+    gsj[6] = gr;
+    gq[6] = zlo ? (rlo ? 5 : 8) : (rlo ? 6 : 7);
+    gv[6] = (zlo || zhi) && (rlo || rhi);
+    A af[7][3];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      int yi = gsi[c] + XZ(gq[c]), yj = gsj[c] + XR(gq[c]);
+      if (p.per_z) yi = wrap1(yi, nz);
+      else gv[c] = gv[c] && yi >= 0 && yi < nz;
+      if (p.per_r) yj = wrap1(yj, nr);
+      else gv[c] = gv[c] && yj >= 0 && yj < nr;
+      gv[c] = gv[c] && !(a.shift && yi == 0);   // a computed site
+      yi = yi < 0 ? 0 : (yi >= nz ? nz - 1 : yi);
+      yj = yj < 0 ? 0 : (yj >= nr ? nr - 1 : yj);
+      yo[c] = yj * pitch + yi;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) af[c][k] = (Lo + (9 * k + gq[c]) * plane)[yo[c]];
+    }
+    // VJP of f_eq_{k,q}(Mg) = w_q Mg_k (1 + Q_q(u)), u = lam beta(Mg), Mg = (M0, M1, +-M2); the
+    // velocity of the mirrored moments is (beta_z, -beta_r)
+    double bz, br;
+    const bool live = velocity<double>(M[0], M[1], M[2], p.n_floor, bz, br);
+    const double n = M[0];
+    const double pz = live ? M[1] / n : 0.0, pr0 = live ? M[2] / n : 0.0;
+    const double g2 = 1.0 + pz * pz + pr0 * pr0, ig = live ? 1.0 / sqrt(g2) : 0.0, ig3 = ig / g2;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      if (!gv[c]) continue;
+      const int q = gq[c];
+      const double sgn = gsj[c] < 0 ? -1.0 : 1.0;
+      const double w = WQ<double>(q);
+      const double uz = p.lam * bz, ur = p.lam * sgn * br, pr = sgn * pr0;
+      const double Mg[3] = {M[0], M[1], sgn * M[2]};
+      const double cu = XZ(q) * uz + XR(q) * ur;
+      const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
+      double Mgb[3], ubz = 0.0, ubr = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double ak = (double)af[c][k];
+        Mgb[k] = ak * w * (1.0 + Q);
+        const double sk = ak * w * Mg[k];
+        ubz += sk * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);
+        ubr += sk * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
       }
+      if (live) {
+        const double bbz = p.lam * ubz, bbr = p.lam * ubr;
+        const double pdot = pz * bbz + pr * bbr;
+        const double pbz = bbz * ig - pz * pdot * ig3, pbr = bbr * ig - pr * pdot * ig3;
+        Mgb[1] += pbz / n;
+        Mgb[2] += pbr / n;
+        Mgb[0] -= (pbz * pz + pbr * pr) / n;
+      }
+      Mb[0] += Mgb[0];
+      Mb[1] += Mgb[1];
+      Mb[2] += sgn * Mgb[2];
+    }
   }
-  #pragma unroll
-  for (int k = 0; k < 3; ++k) stv(&Lo[(27 + k) * plane + cell], Mb[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) stv(&(Lo + (27 + k) * plane)[cell], Mb[k]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -583,7 +667,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_state_kernel(AdjArgs a, double* 
   if (i >= nz || j >= nr) return;
   const A* __restrict__ L = (const A*)a.lam;
   const int cell = j * pitch + i;
-  #pragma unroll
+#pragma unroll
   for (int q = 0; q < 9; ++q) {
     int yi = i + XZ(q), yj = j + XR(q);
     bool ok = true;
@@ -592,7 +676,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_state_kernel(AdjArgs a, double* 
     if (p.per_r) yj = wrap1(yj, nr);
     else ok = ok && yj >= 0 && yj < nr;
     ok = ok && !(a.shift && yi == 0);
-    #pragma unroll
+#pragma unroll
     for (int kk = 0; kk < 3; ++kk)
       out[(9 * kk + q) * plane + cell] = ok ? (double)L[(9 * kk + q) * plane + yj * pitch + yi] : 0.0;
   }
@@ -606,7 +690,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cast_kernel(Physics p, const dou
   const int i = blockIdx.x * TZ + threadIdx.x % TZ, j = blockIdx.y * TR + threadIdx.x / TZ;
   if (i >= p.nz || j >= p.nr) return;
   const int cell = j * p.pitch + i;
-  #pragma unroll
+#pragma unroll
   for (int c = 0; c < 33; ++c) stv(&((A*)out)[c * p.plane + cell], in[c * p.plane + cell]);
 }
 
@@ -640,7 +724,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_init_cell_kernel(AdjArgs a) {
     const double uz = p.lam * bz, ur = p.lam * br;
     double nbar = (double)L[27 * plane + cell] + pz * (double)L[28 * plane + cell] +
                   pr * (double)L[29 * plane + cell];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 9; ++q) {
       // adjoint of the stored population g^0(x, q): direct, or the transposed pull of f_bar^0
       int yi = i, yj = j;
@@ -704,10 +788,10 @@ __global__ __launch_bounds__(64) void adj_init_field_kernel(AdjArgs a) {
   }
   // block of 64 threads = one wavefront
   for (int off = 32; off > 0; off >>= 1)
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 4; ++c) part[c] += __shfl_down(part[c], off, 64);
   if (threadIdx.x == 0)
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 4; ++c) a.partials[(long long)blockIdx.x * 4 + c] += part[c];
 }
 
@@ -716,7 +800,7 @@ __global__ __launch_bounds__(NTHREADS) void partials_sum_kernel(const double* pa
                                                                 double* acc) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += NTHREADS)
-    #pragma unroll
+#pragma unroll
     for (int c = 0; c < 4; ++c) v[c] += partials[(long long)b * 4 + c];
   // block_sum4 adds into acc from thread 0 only, after its own barrier
   block_sum4(v, acc);

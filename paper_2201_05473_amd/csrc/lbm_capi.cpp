@@ -143,6 +143,10 @@ struct lbm_ctx {
   int cur;
   long long k, s;
   hipStream_t stream;
+  // the adjoint's second stream (segment recompute, overlapped with the reverse sweep) and its
+  // events; created on first use, default priority
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   void* g(int b) { return ws + L.g[b]; }
   void* M(int b) { return ws + L.M[b]; }
   void* E(int b) { return ws + L.E[b]; }
@@ -523,7 +527,8 @@ lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, const void* site, long lon
 }
 
 // forward step k from x into y, saving the site fields of the step
-hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const StateView& y, void* site) {
+hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const StateView& y, void* site,
+                          hipStream_t st) {
   lbm::StepArgs a;
   a.p = c->p;
   a.k = k;
@@ -533,7 +538,7 @@ hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const Sta
   a.M_in = x.M; a.M_out = y.M;
   a.E_in = x.E; a.E_out = y.E;
   a.site_out = c->p.fields_on ? site : nullptr;
-  return lbm::launch_step(c->storage, a, c->stream);
+  return lbm::launch_step(c->storage, a, st);
 }
 
 }  // namespace
@@ -562,7 +567,8 @@ int lbm_vjp_step(lbm_ctx* c, void* ws, size_t bytes, const double* lam_next, dou
   const StateView x{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
   const lbm::AdjArgs a = adj_args(c, x, w + L.site, c->k, w + L.lamA, w + L.lamB, 0, w, L);
   if (a.s != c->s) return fail(LBM_ESTATE, "shift count does not match the step count");
-  HIP_CHECK(step_with_site(c, c->k, x, state_at(w + L.scratch, c->p, c->storage), w + L.site), "step launch");
+  HIP_CHECK(step_with_site(c, c->k, x, state_at(w + L.scratch, c->p, c->storage), w + L.site, c->stream),
+            "step launch");
   HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, c->stream), "adjoint launch");
   HIP_CHECK(lbm::launch_adjoint_state(c->storage, a, stage, c->stream), "adjoint state launch");
   HIP_CHECK(lbm::adjoint_reduce(c->p, a.partials, gacc, c->stream), "adjoint reduce");
@@ -603,8 +609,9 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
   const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
   const size_t sb = state_bytes(p, cfg->storage);
   const int64_t seglen = ckpt_every < nsteps ? ckpt_every : nsteps;
-  *bytes = adj_layout(p, cfg->storage).core_total + (size_t)nseg * sb + (size_t)(seglen + 1) * sb +
-           (size_t)seglen * site_bytes(p, cfg->storage);
+  const int64_t nbuf = nseg > 1 ? 2 : 1;   // segment buffers (recompute overlaps the reverse sweep)
+  *bytes = adj_layout(p, cfg->storage).core_total + (size_t)nseg * sb +
+           (size_t)nbuf * ((size_t)(seglen + 1) * sb + (size_t)seglen * site_bytes(p, cfg->storage));
   return LBM_OK;
 }
 
@@ -634,25 +641,30 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
   char* w = (char*)ws;
   char* ckpt = w + L.core_total;
-  char* seg = ckpt + (size_t)nseg * sb;
   const int64_t seglen = ckpt_every < nsteps ? ckpt_every : nsteps;
-  char* sites = seg + (size_t)(seglen + 1) * sb;
   const size_t stb = site_bytes(p, c->storage);
+  const size_t segbuf = (size_t)(seglen + 1) * sb + (size_t)seglen * stb;
+  char* seg[2] = {ckpt + (size_t)nseg * sb, ckpt + (size_t)nseg * sb + segbuf};   // [1] unused if nseg == 1
   char* lam[2] = {w + L.lamA, w + L.lamB};
   double* gacc = (double*)(w + L.grad);
   const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
   const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
-  auto copy_state = [&](const StateView& dst, const StateView& src) -> hipError_t {
-    hipError_t e = hipMemcpyAsync(dst.g, src.g, gbytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst.M, src.M, mbytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst.E, src.E, mbytes, hipMemcpyDeviceToDevice, c->stream);
+  auto copy_state = [&](const StateView& dst, const StateView& src, hipStream_t st) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst.g, src.g, gbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.M, src.M, mbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.E, src.E, mbytes, hipMemcpyDeviceToDevice, st);
     return e;
   };
+  if (!c->aux) {
+    HIP_CHECK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "stream create");
+    for (hipEvent_t* e : {&c->ev_fwd, &c->ev_rec[0], &c->ev_rec[1], &c->ev_rev[0], &c->ev_rev[1]})
+      HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
+  }
 
   // forward pass with checkpoints
   for (int64_t sgi = 0; sgi < nseg; ++sgi) {
     const StateView cur{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
-    HIP_CHECK(copy_state(state_at(ckpt + (size_t)sgi * sb, p, c->storage), cur), "checkpoint");
+    HIP_CHECK(copy_state(state_at(ckpt + (size_t)sgi * sb, p, c->storage), cur, c->stream), "checkpoint");
     const int64_t len = std::min<int64_t>(ckpt_every, nsteps - sgi * ckpt_every);
     rc = lbm_step(c, len);
     if (rc) return rc;
@@ -688,23 +700,43 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
     HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   }
   int cur = 0;
-  // reverse sweep, segment by segment
-  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+  // Reverse sweep, segment by segment.  The recompute of segment sgi - 1 (states from its
+  // checkpoint, and the site fields of each step) runs on the second stream while the reverse
+  // sweep of segment sgi runs on the caller's stream; segments alternate between two buffers.
+  auto recompute = [&](int64_t sgi, char* buf) -> hipError_t {
     const int64_t k0 = sgi * ckpt_every;
     const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
-    HIP_CHECK(copy_state(state_at(seg, p, c->storage), state_at(ckpt + (size_t)sgi * sb, p, c->storage)),
-              "restore");
-    // recompute the segment's states and the site fields of each of its steps (slot len is scratch)
-    for (int64_t t = 0; t < len; ++t)
-      HIP_CHECK(step_with_site(c, k0 + t, state_at(seg + (size_t)t * sb, p, c->storage),
-                               state_at(seg + (size_t)(t + 1) * sb, p, c->storage), sites + (size_t)t * stb),
-                "recompute launch");
+    char* sites = buf + (size_t)(seglen + 1) * sb;
+    hipError_t e = copy_state(state_at(buf, p, c->storage), state_at(ckpt + (size_t)sgi * sb, p, c->storage), c->aux);
+    for (int64_t t = 0; e == hipSuccess && t < len; ++t)   // slot len is scratch
+      e = step_with_site(c, k0 + t, state_at(buf + (size_t)t * sb, p, c->storage),
+                         state_at(buf + (size_t)(t + 1) * sb, p, c->storage), sites + (size_t)t * stb, c->aux);
+    return e;
+  };
+  HIP_CHECK(hipEventRecord(c->ev_fwd, c->stream), "event record");
+  HIP_CHECK(hipStreamWaitEvent(c->aux, c->ev_fwd, 0), "stream wait");
+  HIP_CHECK(recompute(nseg - 1, seg[(nseg - 1) % 2]), "recompute launch");
+  HIP_CHECK(hipEventRecord(c->ev_rec[(nseg - 1) % 2], c->aux), "event record");
+  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int b = (int)(sgi % 2);
+    if (sgi >= 1) {
+      const int b2 = (int)((sgi - 1) % 2);
+      if (sgi + 1 <= nseg - 1)   // buffer b2 last held segment sgi + 1: its reverse sweep must be done
+        HIP_CHECK(hipStreamWaitEvent(c->aux, c->ev_rev[b2], 0), "stream wait");
+      HIP_CHECK(recompute(sgi - 1, seg[b2]), "recompute launch");
+      HIP_CHECK(hipEventRecord(c->ev_rec[b2], c->aux), "event record");
+    }
+    HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_rec[b], 0), "stream wait");
+    const int64_t k0 = sgi * ckpt_every;
+    const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
+    char* sites = seg[b] + (size_t)(seglen + 1) * sb;
     for (int64_t t = len - 1; t >= 0; --t) {
-      const StateView x = state_at(seg + (size_t)t * sb, p, c->storage);
+      const StateView x = state_at(seg[b] + (size_t)t * sb, p, c->storage);
       const lbm::AdjArgs a = adj_args(c, x, sites + (size_t)t * stb, k0 + t, lam[cur], lam[1 - cur], 1, w, L);
       HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, c->stream), "adjoint launch");
       cur ^= 1;
     }
+    HIP_CHECK(hipEventRecord(c->ev_rev[b], c->stream), "event record");
   }
   // initial state
   {
@@ -727,6 +759,12 @@ int lbm_counters(lbm_ctx* c, int64_t* step, int64_t* shifts) {
 
 int lbm_destroy(lbm_ctx* c) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  for (hipEvent_t e : {c->ev_fwd, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return LBM_OK;
 }
