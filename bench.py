@@ -82,8 +82,9 @@ def rel_err(a, b) -> float:
     return float((a - b).abs().max()) / den if den > 0 else float((a - b).abs().max())
 
 
-def cpu_baseline(sample_steps: int = 1) -> dict:
-    """The FP64 oracle, as it stands, on the host cores: C2 at full size for sample_steps steps."""
+def cpu_baseline(sample_steps: int = 60) -> dict:
+    """The FP64 oracle, as it stands, on the host cores: C2 at full size for sample_steps steps
+    (about 10 s on 16 cores)."""
     import torch
 
     import workloads as wl
@@ -101,6 +102,66 @@ def cpu_baseline(sample_steps: int = 1) -> dict:
             "sample": f"C2 2048x512 FP64 oracle (torch CPU), {sample_steps} step(s) after one untimed step"}
 
 
+def objective_f64(cfg: dict, nsteps: int, z_behind: float, row: int = 0) -> float:
+    """J from a plain forward run: E_z on the row, linearly interpolated at z_d(t_{N-1}) - z_behind."""
+    from paper_2201_05473_amd import Lattice
+    lat = Lattice(cfg)
+    lat.step(nsteps)
+    ez = lat.fields()[0, row].double().cpu().numpy()
+    k, s = lat.counters()
+    lat.close()
+    h, dt = cfg["dz"], cfg["dz"] * cfg["c_dt_over_dz"]
+    x = (cfg["zd0"] + (k - 1) * dt - z_behind) / h - s - 0.5
+    i0 = int(x // 1)
+    w = x - i0
+    return (1 - w) * ez[i0] + w * ez[i0 + 1]
+
+
+def adjoint_c4(ckpt_every: int = 45) -> dict:
+    """C4 (1024 x 256, 2,000 steps, FP32): wall time of lbm_adjoint (its own checkpointed forward
+    included) over that of lbm_step(2000), and the gradient against central finite differences
+    (h = 1e-4) of FP64 forward runs."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C4")
+    n, zb = cfg["nsteps"], cfg["z_behind"]
+    names = ("ramp_len", "n0", "sigma_r", "nb")
+    t_fwd, t_adj = [], []
+    for _ in range(3):
+        lat = Lattice(cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(n)
+        torch.cuda.synchronize()
+        t_fwd.append(time.perf_counter() - t0)
+        lat.close()
+        lat = Lattice(cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, grad = lat.adjoint(n, ckpt_every, z_behind=zb)
+        torch.cuda.synchronize()
+        t_adj.append(time.perf_counter() - t0)
+        lat.close()
+    cfg64 = dict(cfg, storage=wl.F64)
+    fd = np.zeros(4)
+    for a, nm in enumerate(names):
+        cp, cm = dict(cfg64), dict(cfg64)
+        cp[nm] += 1e-4
+        cm[nm] -= 1e-4
+        fd[a] = (objective_f64(cp, n, zb) - objective_f64(cm, n, zb)) / 2e-4
+    rel = np.abs(grad - fd) / np.abs(fd)
+    tf, ta = min(t_fwd), min(t_adj)
+    return {"workload": "C4: 1024x256, dz=0.05, FP32, tanh ramp, 2000 steps, witness 4/k_p behind the driver",
+            "ckpt_every": ckpt_every, "t_forward_ms": tf * 1e3, "t_adjoint_ms": ta * 1e3,
+            "ratio": ta / tf, "J": J, "J_f64": objective_f64(cfg64, n, zb),
+            "grad": {nm: float(g) for nm, g in zip(names, grad)},
+            "fd_f64": {nm: float(g) for nm, g in zip(names, fd)},
+            "rel_err_vs_fd": {nm: float(r) for nm, r in zip(names, rel)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +174,9 @@ def main():
                          "(the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--storage", choices=("f64", "f32", "f16"), default="f32",
                     help="population storage of the --profile run")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="for rocprofv3: one C4 lbm_adjoint (2,000 steps, checkpoints every 45) after a "
+                         "warm-up run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
@@ -129,6 +193,20 @@ def main():
     cfg = wl.config("C2")
     sites = cfg["nz"] * cfg["nr"]
     steps, warmup = args.steps, args.warmup
+
+    if args.profile_adjoint:
+        from paper_2201_05473_amd import Lattice
+        c4 = wl.config("C4")
+        for rep in range(2):
+            lat = Lattice(c4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            J, grad = lat.adjoint(c4["nsteps"], 45, z_behind=c4["z_behind"])
+            torch.cuda.synchronize()
+            lat.close()
+        print(json.dumps({"profile_adjoint": True, "J": J, "grad": list(map(float, grad)),
+                          "t_adjoint_ms": (time.perf_counter() - t0) * 1e3}))
+        return
 
     if args.profile:
         storage = {"f64": wl.F64, "f32": wl.F32, "f16": wl.F16}[args.storage]
@@ -205,7 +283,9 @@ def main():
             c3[name] = {"MLUPS": n3 * 1000 / w / 1e6, "alg_GBps": b * n3 / (e / 1000) / 1e9,
                         "frac_of_peak": b * n3 / (e / 1000) / 1e9 / PEAK_HBM_GBS}
         out["modes_C3"] = c3
-        out["adjoint_forward_ratio"] = None
+        adj = adjoint_c4()
+        out["adjoint_forward_ratio"] = adj["ratio"]
+        out["adjoint_C4"] = adj
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
