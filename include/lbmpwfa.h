@@ -102,7 +102,8 @@ typedef struct lbm_ctx lbm_ctx;
 /* Device workspace needed by a configuration (bytes).  LBM_EINVAL for an invalid config. */
 int lbm_workspace_bytes(const lbm_config* cfg, size_t* bytes);
 
-/* Create a context and set the initial state (Sec. II/III set-up, R16 and R18 readings):
+/* Create a context and set the initial state (Sec. II/III set-up; the seeded density
+ * perturbation is an input, and the initial field is the driver's discrete Gauss field):
  * populations at the local equilibrium of density n_bg(z_i) (1 + n_pert[j][i]) and momentum
  * p_init[c][j][i] (c = 0: p_z, 1: p_r); E_z = 0; E_r and B_theta = the driver's discrete Gauss
  * field at t = -dt and t = -dt/2.  n_pert (host, [nr][nz]) and p_init (host, [2][nr][nz]) may
@@ -150,9 +151,11 @@ int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);
  *
  * theta = (ramp_len, n0, sigma_r, nb).  The objective J is the witness field: E_z of the state
  * on row obj->row, linearly interpolated in z at z_d(t_{N-1}) - obj->z_behind after N steps
- * (the time level of E in the state).  All adjoint arithmetic and adjoint variables are FP64;
- * the forward states are used in their storage precision.  Adjoint variables use the layout of
- * lbm_get_state: [27][nr][nz] populations, [3][nr][nz] moments, [3][nr][nz] E_z, E_r, B_theta.
+ * (the time level of E in the state).  Adjoint arithmetic is FP64; on the device the adjoint
+ * variables are stored in the precision of the auxiliary planes (FP64 for LBM_F64, FP32 for
+ * LBM_F32 and LBM_F16), and the forward states are used in their storage precision.  Host-side
+ * adjoint arrays are FP64 in the layout of lbm_get_state: [27][nr][nz] populations,
+ * [3][nr][nz] moments, [3][nr][nz] E_z, E_r, B_theta.
  * ------------------------------------------------------------------------------------------- */
 typedef struct { double z_behind; int32_t row; } lbm_objective;
 
@@ -176,9 +179,13 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
 
 /* Objective and its gradient dJ/d(ramp_len, n0, sigma_r, nb) over nsteps steps from the
  * initial state.  The context must be at step 0.  Forward pass with a stored checkpoint every
- * ckpt_every steps, then segment by segment in reverse: recompute the segment's states from its
- * checkpoint and run the reverse steps.  On return the context holds the state after nsteps.
- * Synchronising. */
+ * ckpt_every steps, then segment by segment in reverse: recompute the segment's states (and the
+ * site-averaged fields of each of its steps) from its checkpoint, and run the reverse steps.
+ * The recompute of the next segment runs on a second stream, created by the library on first
+ * use (default priority, released by lbm_destroy), while the reverse steps run on the caller's
+ * stream; with more than one segment the workspace holds two segment buffers.  On return the
+ * context holds the state after nsteps.  Synchronising.  Periodic dimensions need at least 5
+ * cells. */
 int lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every,
                 void* adj_ws, size_t adj_bytes, double* J, double grad[4]);
 
