@@ -119,8 +119,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   __shared__ double sN[TZ + 2];   // n_bg at the columns i0-1 .. i0+TZ
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
-  const int ps = pitch;   // plane stride (row-interleaved buffers)
-  const int RG = NPOP * pitch, RA = NAUX * pitch, RL = NLAM * pitch, RW = NWORK * pitch, RS = NSITE * pitch;
+  const long long plane = p.plane;
   const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   const int i0 = (tile % gx) * TZ;   // logical columns of x^k
@@ -151,9 +150,9 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
     const int ui = ic - XZ(q), uj = jc - XR(q);
     const int si = p.per_z ? wrap1(ui, nz) : (ui < 0 ? 0 : (ui < nz ? ui : nz - 1));
     const int sj = p.per_r ? wrap1(uj, nr) : (uj < 0 ? 0 : (uj < nr ? uj : nr - 1));
-    const int off = sj * RG + si;
+    const int off = sj * pitch + si;
 #pragma unroll
-    for (int kk = 0; kk < 3; ++kk) graw[9 * kk + q] = (gin + (9 * kk + q) * ps)[off];
+    for (int kk = 0; kk < 3; ++kk) graw[9 * kk + q] = (gin + (9 * kk + q) * plane)[off];
     ghost[q] = (!p.per_z && (ui < 0 || ui >= nz)) || (!p.per_r && (uj < 0 || uj >= nr));
     int yi = ib, yj = jc;
     bool ok = true;
@@ -166,15 +165,15 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       else if (yj < 0 || yj >= nr) { ok = false; yj = yj < 0 ? 0 : nr - 1; }
     }
     gok[q] = ok;
-    const int yo = yj * RL + yi;
+    const int yo = yj * pitch + yi;
 #pragma unroll
-    for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * ps)[yo];
+    for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
   }
 #pragma unroll
-  for (int kk = 0; kk < 3; ++kk) mbar[kk] = (L + (27 + kk) * ps)[jc * RL + ib];
+  for (int kk = 0; kk < 3; ++kk) mbar[kk] = (L + (27 + kk) * plane)[jc * pitch + ib];
   if (p.fields_on)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * ps)[jc * RS + ib];
+    for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[jc * pitch + ib];
   // zeroth moments of the populations pulled from inside the domain (deviation form for lattice 0)
   double Am[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -191,15 +190,15 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 
   double part[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(ramp_len, n0, sigma_r, n_b)
   if (mine) {
-    const int cell = j * RL + i, cellw = j * RW + i;   // offsets in the adjoint / work buffers
+    const int cell = j * pitch + i;
     A* __restrict__ Lo = (A*)a.lam;
     A* __restrict__ W = (A*)a.work;
     if (dropped) {
       // the first column leaves the window in this step: no site, no adjoint source
 #pragma unroll
-      for (int c = 0; c < 27; ++c) (Lo + c * ps)[cell] = A(0);
+      for (int c = 0; c < 27; ++c) (Lo + c * plane)[cell] = A(0);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) (W + c * ps)[cellw] = A(0);
+      for (int c = 0; c < 6; ++c) (W + c * plane)[cell] = A(0);
     } else {
       // forward recompute of the site's moments (raw values): background of the pulled lattice-0
       // deviations, and the equilibrium ghosts (moments of the source cell after the z rule then
@@ -216,11 +215,11 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
           } else {
             si = p.per_z ? wrap1(si, nz) : (si < 0 ? 0 : (si < nz ? si : nz - 1));
             const int rj = p.per_r ? wrap1(sj, nr) : (sj < 0 ? 0 : (sj < nr ? sj : nr - 1));
-            const int off = rj * RA + si;
+            const int off = rj * pitch + si;
             const int sa = si - (i0 - 1);
             Mg[0] = (double)Min[off] + ((sa >= 0 && sa < TZ + 2) ? sN[sa] : nbg(p, (double)(a.s + si) * h));
-            Mg[1] = (double)Min[ps + off];
-            Mg[2] = (double)(Min + 2 * ps)[off];
+            Mg[1] = (double)Min[plane + off];
+            Mg[2] = (double)(Min + 2 * plane)[off];
           }
           if (!p.per_r && sj < 0) Mg[2] = -Mg[2];   // axis mirror
           double bz, br;
@@ -312,13 +311,13 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
           const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
-          stv(&(Lo + (9 * kk + q) * ps)[cell], c1 * gbq + Ab[kk]);
+          stv(&(Lo + (9 * kk + q) * plane)[cell], c1 * gbq + Ab[kk]);
         }
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) stv(&(W + (W_F + kk) * ps)[cellw], Fb[kk]);
-      stv(&(W + W_EZ * ps)[cellw], Ebz_b);
-      stv(&(W + W_ER * ps)[cellw], Ebr_b);
-      stv(&(W + W_B * ps)[cellw], Bb_b);
+      for (int kk = 0; kk < 3; ++kk) stv(&(W + (W_F + kk) * plane)[cell], Fb[kk]);
+      stv(&(W + W_EZ * plane)[cell], Ebz_b);
+      stv(&(W + W_ER * plane)[cell], Ebr_b);
+      stv(&(W + W_B * plane)[cell], Bb_b);
 
       if (p.window && i == nz - 1) {
         // window front ghost: the populations pulled from column nz (xi_z = -1) are w_q n_bg(z_nz)
@@ -332,7 +331,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
         part[1] += sum * dn;
         if (a.shift) {
           // the new front column of x^{k+1} (output index nz - 1): w_q n_bg and n_bg
-          double s2 = (double)(L + 27 * ps)[j * RL + (nz - 1)];
+          double s2 = (double)(L + 27 * plane)[j * pitch + (nz - 1)];
 #pragma unroll
           for (int q = 0; q < 9; ++q) {
             int yi = nz - 1, yj = j;
@@ -342,7 +341,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
               if (yi >= nz || ((yj < 0 || yj >= nr) && !p.per_r)) continue;
               if (p.per_r) yj = wrap1(yj, nr);
             }
-            s2 += WQ<double>(q) * (double)(L + q * ps)[yj * RL + yi];
+            s2 += WQ<double>(q) * (double)(L + q * plane)[yj * pitch + yi];
           }
           part[0] += s2 * dl;
           part[1] += s2 * dn;
@@ -362,8 +361,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
-  const int ps = pitch;   // plane stride (row-interleaved buffers)
-  const int RG = NPOP * pitch, RA = NAUX * pitch, RL = NLAM * pitch, RW = NWORK * pitch, RS = NSITE * pitch;
+  const long long plane = p.plane;
   const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   const int i0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
@@ -394,12 +392,12 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
     if (p.per_z) { ci = wrapi(ci, nz); return true; }
     return ci >= 0 && ci < nz;
   };
-  // clamped offset of a site value in the work buffer (ok: in the domain)
+  // clamped in-plane offset of a site value (ok: in the domain)
   auto woff = [&](int ci, int cj, bool& ok) -> int {
     ok = cellz(ci, cj);
     ci = ci < 0 ? 0 : (ci >= nz ? nz - 1 : ci);
     cj = cj < 0 ? 0 : (cj >= nr ? nr - 1 : cj);
-    return cj * RW + ci;
+    return cj * pitch + ci;
   };
   // clamped offset in x^{k+1} of the state value at logical cell (ci, cj) of x^k (ok: it exists,
   // i.e. in the domain and not the column dropped by the shift)
@@ -409,29 +407,28 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
     ok = ok && o >= 0;
     o = o < 0 ? 0 : (o >= nz ? nz - 1 : o);
     cj = cj < 0 ? 0 : (cj >= nr ? nr - 1 : cj);
-    return cj * RL + o;
+    return cj * pitch + o;
   };
 
   const int i = i0 + tx, j = j0 + ty;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   double jz = 0.0, jr = 0.0;
   const int ic = i < nz ? i : nz - 1, jc = j < nr ? j : nr - 1;
-  const int cell = j * RL + i;                        // this cell in the adjoint buffers
-  const int cella = jc * RA + ic, cellw = jc * RW + ic;   // ... in the auxiliary / work buffers (clamped)
+  const int cell = j * pitch + i, cellc = jc * pitch + ic;
   const bool mine = i < nz && j < nr;
 
   // per-cell loads first: moments of x^k, and F_bar at rows j-1, j, j+1 (axisymmetric source)
   const A* __restrict__ Min = (const A*)a.M;
   A mraw[3], fb[3][3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) mraw[k] = (Min + k * ps)[cella];
+  for (int k = 0; k < 3; ++k) mraw[k] = (Min + k * plane)[cellc];
   if (p.cyl_on) {
-    const int cm = jc >= 1 ? cellw - RW : cellw, cp = jc + 1 < nr ? cellw + RW : cellw;
+    const int cm = jc >= 1 ? cellc - pitch : cellc, cp = jc + 1 < nr ? cellc + pitch : cellc;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      fb[k][0] = (W + (W_F + k) * ps)[cm];
-      fb[k][1] = (W + (W_F + k) * ps)[cellw];
-      fb[k][2] = (W + (W_F + k) * ps)[cp];
+      fb[k][0] = (W + (W_F + k) * plane)[cm];
+      fb[k][1] = (W + (W_F + k) * plane)[cellc];
+      fb[k][2] = (W + (W_F + k) * plane)[cp];
     }
   }
 
@@ -447,17 +444,17 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       int t = min(tid + sl * NTHREADS, NBB - 1);
-      rBb[sl] = (W + W_B * ps)[woff(i0 - 1 + t % BBZ, j0 - 1 + t / BBZ, oBb[sl])];
+      rBb[sl] = (W + W_B * plane)[woff(i0 - 1 + t % BBZ, j0 - 1 + t / BBZ, oBb[sl])];
       t = min(tid + sl * NTHREADS, NEB - 1);
-      rEb[sl] = (W + W_EZ * ps)[woff(i0 - 1 + t % EBZ, j0 + t / EBZ, oEb[sl])];
+      rEb[sl] = (W + W_EZ * plane)[woff(i0 - 1 + t % EBZ, j0 + t / EBZ, oEb[sl])];
       t = min(tid + sl * NTHREADS, NRB - 1);
-      rRb[sl] = (W + W_ER * ps)[woff(i0 + t % RBZ, j0 - 1 + t / RBZ, oRb[sl])];
+      rRb[sl] = (W + W_ER * plane)[woff(i0 + t % RBZ, j0 - 1 + t / RBZ, oRb[sl])];
       t = min(tid + sl * NTHREADS, NLB - 1);
-      rLB[sl] = (L + 32 * ps)[noff(i0 - 1 + t % LBZ, j0 - 1 + t / LBZ, oLB[sl])];
+      rLB[sl] = (L + 32 * plane)[noff(i0 - 1 + t % LBZ, j0 - 1 + t / LBZ, oLB[sl])];
       t = min(tid + sl * NTHREADS, NLZ - 1);
-      rLZ[sl] = (L + 30 * ps)[noff(i0 - 1 + t % LZZ, j0 + t / LZZ, oLZ[sl])];
+      rLZ[sl] = (L + 30 * plane)[noff(i0 - 1 + t % LZZ, j0 + t / LZZ, oLZ[sl])];
       t = min(tid + sl * NTHREADS, NLR - 1);
-      rLR[sl] = (L + 31 * ps)[noff(i0 + t % LRZ, j0 - 1 + t / LRZ, oLR[sl])];
+      rLR[sl] = (L + 31 * plane)[noff(i0 + t % LRZ, j0 - 1 + t / LRZ, oLR[sl])];
     }
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
@@ -527,9 +524,9 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
       if (j + 1 < nr) lb -= dt * (j + 1.0) / ((j + 1.5) * h) * LZ(i, j + 1);
       if (p.per_z || i >= 1) lb -= dt / h * ler;
       if (p.per_z || i + 1 < nz) lb += dt / h * LR(i + 1, j);
-      stv(&(Lo + 30 * ps)[cell], lez);
-      stv(&(Lo + 31 * ps)[cell], ler);
-      stv(&(Lo + 32 * ps)[cell], lb);
+      stv(&(Lo + 30 * plane)[cell], lez);
+      stv(&(Lo + 31 * plane)[cell], ler);
+      stv(&(Lo + 32 * plane)[cell], lb);
       jz = 0.5 * dt * (lez + ((p.per_z || i >= 1) ? LZ(i - 1, j) : 0.0));
       if (!p.per_z && !p.window && i == nz - 1) jz += 0.5 * dt * lez;   // front copy of J_z
       jr = 0.5 * dt * (ler + (j >= 1 ? LR(i, j - 1) : 0.0));
@@ -546,7 +543,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
     for (int c = 0; c < 3; ++c) {
       bool ok;
       const int o = noff(i, j, ok);
-      stv(&(Lo + (30 + c) * ps)[cell], ok ? (double)(L + (30 + c) * ps)[o] : 0.0);
+      stv(&(Lo + (30 + c) * plane)[cell], ok ? (double)(L + (30 + c) * plane)[o] : 0.0);
     }
   }
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
@@ -609,9 +606,9 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
       gv[c] = gv[c] && !(a.shift && yi == 0);   // a computed site
       yi = yi < 0 ? 0 : (yi >= nz ? nz - 1 : yi);
       yj = yj < 0 ? 0 : (yj >= nr ? nr - 1 : yj);
-      yo[c] = yj * RL + yi;
+      yo[c] = yj * pitch + yi;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) af[c][k] = (Lo + (9 * k + gq[c]) * ps)[yo[c]];
+      for (int k = 0; k < 3; ++k) af[c][k] = (Lo + (9 * k + gq[c]) * plane)[yo[c]];
     }
     // VJP of f_eq_{k,q}(Mg) = w_q Mg_k (1 + Q_q(u)), u = lam beta(Mg), Mg = (M0, M1, +-M2); the
     // velocity of the mirrored moments is (beta_z, -beta_r)
@@ -653,7 +650,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
     }
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) stv(&(Lo + (27 + k) * ps)[cell], Mb[k]);
+  for (int k = 0; k < 3; ++k) stv(&(Lo + (27 + k) * plane)[cell], Mb[k]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -665,12 +662,11 @@ __global__ __launch_bounds__(NTHREADS) void adj_state_kernel(AdjArgs a, double* 
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
-  const int ps = pitch;   // plane stride (row-interleaved buffers)
-  const int RG = NPOP * pitch, RA = NAUX * pitch, RL = NLAM * pitch, RW = NWORK * pitch, RS = NSITE * pitch;
+  const long long plane = p.plane;
   const int i = blockIdx.x * TZ + threadIdx.x % TZ, j = blockIdx.y * TR + threadIdx.x / TZ;
   if (i >= nz || j >= nr) return;
   const A* __restrict__ L = (const A*)a.lam;
-  const int cell = j * RL + i;   // the output uses the same 33-plane layout, in FP64
+  const int cell = j * pitch + i;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     int yi = i + XZ(q), yj = j + XR(q);
@@ -682,9 +678,9 @@ __global__ __launch_bounds__(NTHREADS) void adj_state_kernel(AdjArgs a, double* 
     ok = ok && !(a.shift && yi == 0);
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
-      out[(9 * kk + q) * ps + cell] = ok ? (double)L[(9 * kk + q) * ps + yj * RL + yi] : 0.0;
+      out[(9 * kk + q) * plane + cell] = ok ? (double)L[(9 * kk + q) * plane + yj * pitch + yi] : 0.0;
   }
-  for (int c = 27; c < 33; ++c) out[c * ps + cell] = (double)L[c * ps + cell];
+  for (int c = 27; c < 33; ++c) out[c * plane + cell] = (double)L[c * plane + cell];
 }
 
 // adj_cast_kernel: an FP64 stored-state lambda into the adjoint precision (33 planes)
@@ -693,9 +689,9 @@ __global__ __launch_bounds__(NTHREADS) void adj_cast_kernel(Physics p, const dou
   using A = typename Mode<ST, false>::A;
   const int i = blockIdx.x * TZ + threadIdx.x % TZ, j = blockIdx.y * TR + threadIdx.x / TZ;
   if (i >= p.nz || j >= p.nr) return;
-  const int cell = j * NLAM * p.pitch + i;   // 33-plane row-interleaved, both sides
+  const int cell = j * p.pitch + i;
 #pragma unroll
-  for (int c = 0; c < 33; ++c) stv(&((A*)out)[c * p.pitch + cell], in[c * p.pitch + cell]);
+  for (int c = 0; c < 33; ++c) stv(&((A*)out)[c * p.plane + cell], in[c * p.plane + cell]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -707,8 +703,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_init_cell_kernel(AdjArgs a) {
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
-  const int ps = pitch;   // plane stride (row-interleaved buffers)
-  const int RG = NPOP * pitch, RA = NAUX * pitch, RL = NLAM * pitch, RW = NWORK * pitch, RS = NSITE * pitch;
+  const long long plane = p.plane;
   const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   const int i = (tile % gx) * TZ + threadIdx.x % TZ, j = (tile / gx) * TR + threadIdx.x / TZ;
@@ -716,19 +711,19 @@ __global__ __launch_bounds__(NTHREADS) void adj_init_cell_kernel(AdjArgs a) {
   if (i < nz && j < nr) {
     const A* __restrict__ L = (const A*)a.lam_next;   // lambda^0
     const A* __restrict__ Min = (const A*)a.M;
-    const int cell = j * RL + i, cella = j * RA + i;
+    const int cell = j * pitch + i;
     const double z = (double)i * p.h;
     const double nb0 = nbg(p, z);
     double dl, dn;
     dnbg(p, z, dl, dn);
-    const double n = (double)Min[cella] + nb0;
-    const double m1 = Min[ps + cella], m2 = Min[2 * ps + cella];
+    const double n = (double)Min[cell] + nb0;
+    const double m1 = Min[plane + cell], m2 = Min[2 * plane + cell];
     double bz, br;
     const bool live = velocity<double>(n, m1, m2, p.n_floor, bz, br);
     const double pz = live ? m1 / n : 0.0, pr = live ? m2 / n : 0.0;
     const double uz = p.lam * bz, ur = p.lam * br;
-    double nbar = (double)L[27 * ps + cell] + pz * (double)L[28 * ps + cell] +
-                  pr * (double)L[29 * ps + cell];
+    double nbar = (double)L[27 * plane + cell] + pz * (double)L[28 * plane + cell] +
+                  pr * (double)L[29 * plane + cell];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       // adjoint of the stored population g^0(x, q): direct, or the transposed pull of f_bar^0
@@ -744,11 +739,11 @@ __global__ __launch_bounds__(NTHREADS) void adj_init_cell_kernel(AdjArgs a) {
         ok = ok && !(a.shift && yi == 0);
       }
       if (!ok) continue;
-      const int ys = yj * RL + yi;
+      const int ys = yj * pitch + yi;
       const double cu = XZ(q) * uz + XR(q) * ur;
       const double e = WQ<double>(q) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur));
-      nbar += e * ((double)L[q * ps + ys] + pz * (double)L[(9 + q) * ps + ys] +
-                   pr * (double)L[(18 + q) * ps + ys]);
+      nbar += e * ((double)L[q * plane + ys] + pz * (double)L[(9 + q) * plane + ys] +
+                   pr * (double)L[(18 + q) * plane + ys]);
     }
     if (nb0 > 0.0) {
       const double ratio = n / nb0;   // 1 + delta
@@ -770,7 +765,7 @@ __global__ __launch_bounds__(64) void adj_init_field_kernel(AdjArgs a) {
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < p.nz && p.fields_on) {
     const A* __restrict__ L = (const A*)a.lam_next;
-    const int ps = p.pitch, RL = NLAM * p.pitch;
+    const long long plane = p.plane;
     const double h = p.h, dt = p.dt;
     const double z = (double)i * h;
     const double d1 = z - (p.zd0 - dt), d2 = z + 0.5 * h - (p.zd0 - 0.5 * dt);
@@ -783,9 +778,9 @@ __global__ __launch_bounds__(64) void adj_init_field_kernel(AdjArgs a) {
       const double er = exp(-(r * r) / (2.0 * p.sigma_r * p.sigma_r));
       c0 += (j + 0.5) * er * r * r / s3;
       c1 += (j + 0.5) * er;
-      const int cell = j * RL + i;
+      const int cell = j * p.pitch + i;
       const double f = -h / (j + 1.0);
-      const double l31 = (double)L[31 * ps + cell], l32 = (double)L[32 * ps + cell];
+      const double l31 = (double)L[31 * plane + cell], l32 = (double)L[32 * plane + cell];
       // d/d(sigma_r): nb e_z e_r r^2 / sigma_r^3 ; d/d(n_b): e_z e_r
       part[2] += f * p.nb * c0 * (l31 * ez1 + l32 * ez2);
       part[3] += f * c1 * (l31 * ez1 + l32 * ez2);

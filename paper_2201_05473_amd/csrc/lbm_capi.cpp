@@ -84,9 +84,6 @@ int validate(const lbm_config* c, Physics* p) {
     q.nr = c->nr;
     q.pitch = (int)round_up((size_t)c->nz, lbm::PITCH_ALIGN);
     q.plane = (long long)q.nr * q.pitch;
-    // element offsets inside a 33-plane buffer are 32-bit
-    if ((long long)lbm::NLAM * q.plane >= (1LL << 31))
-      return fail(LBM_EINVAL, "grid too large (%d x %d)", c->nz, c->nr);
     q.h = c->dz;
     q.lam = lam;
     q.dt = lam * c->dz;
@@ -112,26 +109,21 @@ int validate(const lbm_config* c, Physics* p) {
   return LBM_OK;
 }
 
-// Workspace layout: two population buffers (27 planes), two auxiliary buffers (6 planes: the
-// moments at planes 0..2, E_z, E_r, B_theta at planes 3..5), both row-interleaved, and the
+// Workspace layout: two population buffers, two moment buffers, two field buffers, and the
 // reduction scratch, each 256-byte aligned.
 struct Layout {
-  size_t g[2], X[2], partials, out, total;
+  size_t g[2], M[2], E[2], partials, out, total;
 };
-
-size_t pop_region(const Physics& p, int storage) {
-  return round_up((size_t)lbm::NPOP * (size_t)p.plane * pop_bytes(storage), 256);
-}
-size_t aux_region(const Physics& p, int storage) {
-  return round_up((size_t)lbm::NAUX * (size_t)p.plane * aux_bytes(storage), 256);
-}
 
 Layout layout(const Physics& p, int storage) {
   Layout L;
-  const size_t gb = pop_region(p, storage), xb = aux_region(p, storage);
+  const size_t plane = (size_t)p.plane;
+  const size_t gb = round_up(27 * plane * pop_bytes(storage), 256);
+  const size_t mb = round_up(3 * plane * aux_bytes(storage), 256);
   size_t off = 0;
   for (int b = 0; b < 2; ++b) { L.g[b] = off; off += gb; }
-  for (int b = 0; b < 2; ++b) { L.X[b] = off; off += xb; }
+  for (int b = 0; b < 2; ++b) { L.M[b] = off; off += mb; }
+  for (int b = 0; b < 2; ++b) { L.E[b] = off; off += mb; }
   L.partials = off;
   off += round_up((size_t)lbm::diag_blocks(p) * 8 * sizeof(double), 256);
   L.out = off;
@@ -156,8 +148,8 @@ struct lbm_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   void* g(int b) { return ws + L.g[b]; }
-  void* M(int b) { return ws + L.X[b]; }
-  void* E(int b) { return ws + L.X[b] + 3 * (size_t)p.pitch * aux_bytes(storage); }
+  void* M(int b) { return ws + L.M[b]; }
+  void* E(int b) { return ws + L.E[b]; }
   double* partials() { return (double*)(ws + L.partials); }
   double* red_out() { return (double*)(ws + L.out); }
   // Scratch for host transfers: the inactive population buffer (free between steps).
@@ -346,18 +338,18 @@ struct CkptHeader {
   char pad[24];
 };
 static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
-const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '2'};
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '1'};
 
 size_t region_bytes(const lbm_ctx* c, int which) {
   const size_t plane = (size_t)c->p.plane;
-  return which == 0 ? lbm::NPOP * plane * pop_bytes(c->storage) : lbm::NAUX * plane * aux_bytes(c->storage);
+  return which == 0 ? 27 * plane * pop_bytes(c->storage) : 3 * plane * aux_bytes(c->storage);
 }
 }  // namespace
 
 int lbm_checkpoint_bytes(lbm_ctx* c, size_t* bytes) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + region_bytes(c, 1);
+  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + 2 * region_bytes(c, 1);
   return LBM_OK;
 }
 
@@ -381,9 +373,9 @@ int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
     std::memcpy(d, &h, sizeof h);
   }
   size_t off = sizeof h;
-  const void* src[2] = {c->g(c->cur), c->M(c->cur)};   // populations, auxiliary planes
-  for (int r = 0; r < 2; ++r) {
-    const size_t nb = region_bytes(c, r);
+  const void* src[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  for (int r = 0; r < 3; ++r) {
+    const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
     HIP_CHECK(hipMemcpyAsync(d + off, src[r], nb, kind, c->stream), "save copy");
     off += nb;
   }
@@ -408,9 +400,9 @@ int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
   if (h.step < 0 || h.shifts < 0) return fail(LBM_EINVAL, "corrupt checkpoint counters");
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   size_t off = sizeof h;
-  void* dstp[2] = {c->g(c->cur), c->M(c->cur)};
-  for (int r = 0; r < 2; ++r) {
-    const size_t nb = region_bytes(c, r);
+  void* dstp[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  for (int r = 0; r < 3; ++r) {
+    const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
     HIP_CHECK(hipMemcpyAsync(dstp[r], s + off, nb, kind, c->stream), "load copy");
     off += nb;
   }
@@ -449,7 +441,7 @@ size_t state_bytes(const Physics& p, int storage);
 
 // the site fields of one step (E_z, E_r, B_theta averaged to the sites), auxiliary type
 size_t site_bytes(const Physics& p, int storage) {
-  return round_up((size_t)lbm::NSITE * (size_t)p.plane * aux_bytes(storage), 256);
+  return round_up(3 * (size_t)p.plane * aux_bytes(storage), 256);
 }
 
 // Adjoint workspace: two lambda buffers and the work planes in the adjoint precision (the
@@ -463,31 +455,36 @@ AdjLayout adj_layout(const Physics& p, int storage) {
   AdjLayout L;
   const size_t plane_l = (size_t)p.plane * aux_bytes(storage);
   size_t off = 0;
-  L.lamA = off; off += round_up(lbm::NLAM * plane_l, 256);
-  L.lamB = off; off += round_up(lbm::NLAM * plane_l, 256);
-  L.work = off; off += round_up(lbm::NWORK * plane_l, 256);
+  L.lamA = off; off += round_up(33 * plane_l, 256);
+  L.lamB = off; off += round_up(33 * plane_l, 256);
+  L.work = off; off += round_up(6 * plane_l, 256);
   L.partials = off; off += round_up((size_t)lbm::adjoint_partial_blocks(p) * 8 * sizeof(double), 256);
   L.grad = off; off += 256;
   L.core_total = off;
-  L.stage = off; off += round_up(lbm::NLAM * (size_t)p.plane * sizeof(double), 256);
+  L.stage = off; off += round_up(33 * (size_t)p.plane * sizeof(double), 256);
   L.scratch = off; off += state_bytes(p, storage);
   L.site = off; off += site_bytes(p, storage);
   L.vjp_total = off;
   return L;
 }
 
-// bytes of one stored state in the native layout (populations, auxiliary planes)
-size_t state_bytes(const Physics& p, int storage) { return pop_region(p, storage) + aux_region(p, storage); }
+// bytes of one stored state in the native layout (populations, moments, fields)
+size_t state_bytes(const Physics& p, int storage) {
+  const size_t plane = (size_t)p.plane;
+  return round_up(27 * plane * pop_bytes(storage), 256) + 2 * round_up(3 * plane * aux_bytes(storage), 256);
+}
 
 struct StateView {
   void* g;
-  void* M;   // auxiliary buffer: moments at planes 0..2
-  void* E;   // E_z, E_r, B_theta at planes 3..5 of the same buffer
+  void* M;
+  void* E;
 };
 
 StateView state_at(char* base, const Physics& p, int storage) {
-  char* x = base + pop_region(p, storage);
-  return StateView{base, x, x + 3 * (size_t)p.pitch * aux_bytes(storage)};
+  const size_t plane = (size_t)p.plane;
+  const size_t gb = round_up(27 * plane * pop_bytes(storage), 256);
+  const size_t mb = round_up(3 * plane * aux_bytes(storage), 256);
+  return StateView{base, base + gb, base + gb + mb};
 }
 
 int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
@@ -500,22 +497,14 @@ int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
   return LBM_OK;
 }
 
-// host [33][nr][nz] <-> device row-interleaved [nr][33][pitch] (FP64), one 2D copy per plane
+// host [33][nr][nz] <-> device [33][nr][pitch] (FP64)
 hipError_t upload_lam(const Physics& p, double* dst, const double* src, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  for (int c = 0; c < lbm::NLAM && e == hipSuccess; ++c)
-    e = hipMemcpy2DAsync(dst + (size_t)c * p.pitch, (size_t)lbm::NLAM * p.pitch * sizeof(double),
-                         src + (size_t)c * p.nr * p.nz, (size_t)p.nz * sizeof(double),
-                         (size_t)p.nz * sizeof(double), (size_t)p.nr, hipMemcpyHostToDevice, st);
-  return e;
+  return hipMemcpy2DAsync(dst, (size_t)p.pitch * sizeof(double), src, (size_t)p.nz * sizeof(double),
+                          (size_t)p.nz * sizeof(double), (size_t)33 * p.nr, hipMemcpyHostToDevice, st);
 }
 hipError_t download_lam(const Physics& p, double* dst, const double* src, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  for (int c = 0; c < lbm::NLAM && e == hipSuccess; ++c)
-    e = hipMemcpy2DAsync(dst + (size_t)c * p.nr * p.nz, (size_t)p.nz * sizeof(double),
-                         src + (size_t)c * p.pitch, (size_t)lbm::NLAM * p.pitch * sizeof(double),
-                         (size_t)p.nz * sizeof(double), (size_t)p.nr, hipMemcpyDeviceToHost, st);
-  return e;
+  return hipMemcpy2DAsync(dst, (size_t)p.nz * sizeof(double), src, (size_t)p.pitch * sizeof(double),
+                          (size_t)p.nz * sizeof(double), (size_t)33 * p.nr, hipMemcpyDeviceToHost, st);
 }
 
 lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, const void* site, long long k, const void* lam_next,
@@ -658,10 +647,12 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   char* seg[2] = {ckpt + (size_t)nseg * sb, ckpt + (size_t)nseg * sb + segbuf};   // [1] unused if nseg == 1
   char* lam[2] = {w + L.lamA, w + L.lamB};
   double* gacc = (double*)(w + L.grad);
-  const size_t gbytes = pop_region(p, c->storage), xbytes = aux_region(p, c->storage);
+  const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
+  const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
   auto copy_state = [&](const StateView& dst, const StateView& src, hipStream_t st) -> hipError_t {
     hipError_t e = hipMemcpyAsync(dst.g, src.g, gbytes, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst.M, src.M, xbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.M, src.M, mbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.E, src.E, mbytes, hipMemcpyDeviceToDevice, st);
     return e;
   };
   if (!c->aux) {
@@ -681,7 +672,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   // objective
   {
     const size_t ab = aux_bytes(c->storage);
-    const char* ez = (const char*)c->E(c->cur) + ((size_t)obj->row * lbm::NAUX * p.pitch + (size_t)iw) * ab;
+    const char* ez = (const char*)c->E(c->cur) + ((size_t)obj->row * p.pitch + (size_t)iw) * ab;
     double e0, e1;
     if (ab == 8) {
       double v[2];
@@ -700,7 +691,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   HIP_CHECK(hipMemsetAsync(w, 0, L.core_total, c->stream), "clear");
   {
     const size_t ab = aux_bytes(c->storage);
-    char* dst = lam[0] + (30 * (size_t)p.pitch + (size_t)obj->row * lbm::NLAM * p.pitch + (size_t)iw) * ab;
+    char* dst = lam[0] + (30 * (size_t)p.plane + (size_t)obj->row * p.pitch + (size_t)iw) * ab;
     const double seedd[2] = {1.0 - ww, ww};
     const float seedf[2] = {(float)(1.0 - ww), (float)ww};
     HIP_CHECK(hipMemcpyAsync(dst, ab == 8 ? (const void*)seedd : (const void*)seedf, 2 * ab,

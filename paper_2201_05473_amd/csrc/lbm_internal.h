@@ -17,16 +17,9 @@ constexpr int PITCH_ALIGN = 64;
 constexpr int RED_THREADS = 256;
 
 // Physical and grid parameters of a run (fixed for a context).
-// Row-interleaved layout: a buffer of C planes (populations 27, auxiliary 6 = moments 3 + fields
-// 3, adjoint 33, adjoint work 6, site fields 3) keeps row j of plane c at elements
-// (j C + c) pitch .. (j C + c) pitch + nz - 1, i.e. element (c, j, i) at c pitch + j (C pitch) + i.
-// The planes of one row are contiguous, so the streams of a tile stay within a small address
-// range instead of one stream per plane several MB apart.
-constexpr int NPOP = 27, NAUX = 6, NLAM = 33, NWORK = 6, NSITE = 3;
-
 struct Physics {
-  int nz, nr, pitch;        // pitch: row length in elements (multiple of PITCH_ALIGN)
-  long long plane;          // nr * pitch: elements of one plane over the whole grid (sizes only)
+  int nz, nr, pitch;
+  long long plane;          // nr * pitch elements
   double h, dt, lam, tau, D, n_floor;
   double n0, ramp_start, ramp_len;
   int ramp_kind;
@@ -43,12 +36,12 @@ struct StepArgs {
   int shift;        // 1 if the window moves at the end of this step
   const void* g_in;
   void* g_out;
-  const void* M_in;  // auxiliary buffer (6 planes): moments at planes 0..2 ...
+  const void* M_in;
   void* M_out;
-  const void* E_in;  // ... and E_z, E_r, B_theta at planes 3..5 (E_in = M_in + 3 pitch)
+  const void* E_in;  // [3 planes] E_z, E_r, B_theta
   void* E_out;
-  void* site_out;    // optional (fields on): 3-plane buffer of E_z, E_r, B_theta averaged to the
-                     // sites as used by the fluid, at the output index; nullptr to skip
+  void* site_out;    // optional (fields on): [3 planes] E_z, E_r, B_theta averaged to the sites as
+                     // used by the fluid, at the output index; nullptr to skip
 };
 
 // One reverse step of the adjoint at the state x^k (k, s, shift as for the forward step k).

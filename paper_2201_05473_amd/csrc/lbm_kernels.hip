@@ -49,7 +49,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   __shared__ CF sIr[EZR];   // 1 / r_j at the fluid / E_z rows
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
-  const int RG = NPOP * pitch, RA = NAUX * pitch;   // row strides: population / auxiliary buffers
+  const long long plane = p.plane;
   const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   const int o0 = (tile % gx) * TZ;
@@ -68,13 +68,13 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   // row after the r rule (axis mirror row 0, outer copy, wrap); always in range.
   auto zcol = [&](int i) { return p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1)); };
   auto rrow = [&](int j) { return p.per_r ? wrapi(j, nr) : (j < 0 ? 0 : (j < nr ? j : nr - 1)); };
-  // plane bases (uniform) + 32-bit offsets (a buffer holds fewer than 2^31 elements)
+  // plane bases (uniform) + 32-bit in-plane offsets (a plane holds fewer than 2^31 elements)
   const A* M0p = Min;
-  const A* M1p = Min + pitch;
-  const A* M2p = Min + 2 * pitch;
+  const A* M1p = Min + plane;
+  const A* M2p = Min + 2 * plane;
   const A* Ezp = Ein;
-  const A* Erp = Ein + pitch;
-  const A* Bp = Ein + 2 * pitch;
+  const A* Erp = Ein + plane;
+  const A* Bp = Ein + 2 * plane;
 
   // --- 1. halo loads into registers --------------------------------------------------------
   A hm[SM][3];
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 #pragma unroll
   for (int s = 0; s < SM; ++s) {
     const int t = min(tid + s * NTHREADS, NM - 1);
-    const int off = rrow(j0 - 1 + t / MZ) * RA + zcol(i0 - 1 + t % MZ);
+    const int off = rrow(j0 - 1 + t / MZ) * pitch + zcol(i0 - 1 + t % MZ);
     hm[s][0] = M0p[off];
     hm[s][1] = M1p[off];
     hm[s][2] = M2p[off];
@@ -91,17 +91,17 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       const int t = min(tid + s * NTHREADS, NB - 1);
-      hb[s] = Bp[rrow(j0 - 2 + t / BZ) * RA + zcol(i0 - 2 + t % BZ)];
+      hb[s] = Bp[rrow(j0 - 2 + t / BZ) * pitch + zcol(i0 - 2 + t % BZ)];
     }
 #pragma unroll
     for (int s = 0; s < SEZ; ++s) {
       const int t = min(tid + s * NTHREADS, NEZ - 1);
-      hez[s] = Ezp[rrow(j0 - 1 + t / EZZ) * RA + zcol(i0 - 1 + t % EZZ)];
+      hez[s] = Ezp[rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ)];
     }
 #pragma unroll
     for (int s = 0; s < SER; ++s) {
       const int t = min(tid + s * NTHREADS, NER - 1);
-      her[s] = Erp[rrow(j0 - 1 + t / ERZ) * RA + zcol(i0 - 1 + t % ERZ)];
+      her[s] = Erp[rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ)];
     }
   }
 
@@ -116,10 +116,10 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     // ghost sources are replaced below; their (in-range) load is discarded
-    const int off = rrow(j - XR(q)) * RG + zcol(i - XZ(q));
-    r0[q] = (gin + q * pitch)[off];
-    r1[q] = (gin + (9 + q) * pitch)[off];
-    r2[q] = (gin + (18 + q) * pitch)[off];
+    const int off = rrow(j - XR(q)) * pitch + zcol(i - XZ(q));
+    r0[q] = (gin + q * plane)[off];
+    r1[q] = (gin + (9 + q) * plane)[off];
+    r2[q] = (gin + (18 + q) * plane)[off];
   }
 
   // --- 3. per-column and per-row factors of the tile --------------------------------------
@@ -266,21 +266,21 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 
   // --- 8. fluid phase: one site per thread ------------------------------------------------
   if (!site_ok) return;   // no barrier below this point
-  const int og = j * RG + o;   // output offsets in the population / auxiliary buffers
-  const int oa = j * RA + o;
+  const int oo32 = j * pitch + o;
+  const long long oo = oo32;
   S* gout = (S*)a.g_out;
   A* Mout = (A*)a.M_out;
   A* Eout = (A*)a.E_out;
 
   if (fresh_site) {
     // new front column of the moved window: plasma at rest at n_bg, no fields
-    for (int c = 0; c < 27; ++c) stv(gout + c * pitch + og, C(0));
-    stv(Mout + oa, C(0));
-    stv(Mout + pitch + oa, C(0));
-    stv(Mout + 2 * pitch + oa, C(0));
-    stv(Eout + oa, C(0));
-    stv(Eout + pitch + oa, C(0));
-    stv(Eout + 2 * pitch + oa, C(0));
+    for (int c = 0; c < 27; ++c) stv(gout + c * plane + oo, C(0));
+    stv(Mout + oo, C(0));
+    stv(Mout + plane + oo, C(0));
+    stv(Mout + 2 * plane + oo, C(0));
+    stv(Eout + oo, C(0));
+    stv(Eout + plane + oo, C(0));
+    stv(Eout + 2 * plane + oo, C(0));
     return;
   }
 
@@ -339,10 +339,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
               sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * CF(0.125));
     if (SITE) {
       A* So = (A*)a.site_out;
-      const int os = j * (NSITE * pitch) + o;
-      stv(So + os, Ebz);
-      stv(So + pitch + os, Ebr);
-      stv(So + 2 * pitch + os, Bb);
+      stv(So + oo, Ebz);
+      stv(So + plane + oo, Ebr);
+      stv(So + 2 * plane + oo, Bb);
     }
   }
 
@@ -372,23 +371,23 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     const C e1 = w * A1 * (C(1) + Q);
     const C e2 = w * A2 * (C(1) + Q);
     const C wdt = w * dtc;
-    stv(gout + q * pitch + og, f0[q] - (f0[q] - e0) * itau + wdt * F0);
-    stv(gout + (9 + q) * pitch + og, f1[q] - (f1[q] - e1) * itau + wdt * F1);
-    stv(gout + (18 + q) * pitch + og, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+    stv(gout + q * plane + oo32, f0[q] - (f0[q] - e0) * itau + wdt * F0);
+    stv(gout + (9 + q) * plane + oo32, f1[q] - (f1[q] - e1) * itau + wdt * F1);
+    stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
   }
-  stv(Mout + oa, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
-  stv(Mout + pitch + oa, A1 + dtc * F1);
-  stv(Mout + 2 * pitch + oa, A2 + dtc * F2);
+  stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
+  stv(Mout + plane + oo, A1 + dtc * F1);
+  stv(Mout + 2 * plane + oo, A2 + dtc * F2);
 
   if (FIELDS) {
-    stv(Eout + oa, (A)sEz[ty + 1][tx + 1]);
-    stv(Eout + pitch + oa, (A)sEr[ty + 1][tx + 1]);
-    stv(Eout + 2 * pitch + oa, (A)sBn[ty + 1][tx + 1]);
+    stv(Eout + oo, (A)sEz[ty + 1][tx + 1]);
+    stv(Eout + plane + oo, (A)sEr[ty + 1][tx + 1]);
+    stv(Eout + 2 * plane + oo, (A)sBn[ty + 1][tx + 1]);
   } else {
-    const int io = j * RA + i;
-    stv(Eout + oa, (C)Ein[io]);
-    stv(Eout + pitch + oa, (C)Ein[pitch + io]);
-    stv(Eout + 2 * pitch + oa, (C)Ein[2 * pitch + io]);
+    const long long io = (long long)j * pitch + i;
+    stv(Eout + oo, (C)Ein[io]);
+    stv(Eout + plane + oo, (C)Ein[plane + io]);
+    stv(Eout + 2 * plane + oo, (C)Ein[2 * plane + io]);
   }
 }
 
@@ -404,7 +403,7 @@ __global__ void init_fluid_kernel(Physics p, const double* n_pert, const double*
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
   const long long u = (long long)j * p.nz + i;
-  const int og = j * NPOP * p.pitch + i, oa = j * NAUX * p.pitch + i;
+  const long long oo = (long long)j * p.pitch + i;
   const double nb = nbg(p, (double)i * p.h);
   const double n = n_pert ? nb * (1.0 + n_pert[u]) : nb;
   const double a1 = p_init ? n * p_init[u] : 0.0;
@@ -418,13 +417,13 @@ __global__ void init_fluid_kernel(Physics p, const double* n_pert, const double*
     const double w = WQ<double>(q);
     const double cu = XZ(q) * uz + XR(q) * ur;
     const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-    stv(g + q * p.pitch + og, w * ((n - nb) + n * Q));
-    stv(g + (9 + q) * p.pitch + og, w * a1 * (1.0 + Q));
-    stv(g + (18 + q) * p.pitch + og, w * a2 * (1.0 + Q));
+    stv(g + q * p.plane + oo, w * ((n - nb) + n * Q));
+    stv(g + (9 + q) * p.plane + oo, w * a1 * (1.0 + Q));
+    stv(g + (18 + q) * p.plane + oo, w * a2 * (1.0 + Q));
   }
-  stv(M + oa, n - nb);
-  stv(M + p.pitch + oa, a1);
-  stv(M + 2 * p.pitch + oa, a2);
+  stv(M + oo, n - nb);
+  stv(M + p.plane + oo, a1);
+  stv(M + 2 * p.plane + oo, a2);
 }
 
 // Driver field from the discrete Gauss law: E_r^{-1} at (z_i, t = -dt), B^{-1/2} at
@@ -438,7 +437,7 @@ __global__ void init_fields_kernel(Physics p, void* Ev) {
   double ce = 0.0, cb = 0.0;
   const double z = (double)i * p.h;
   for (int j = 0; j < p.nr; ++j) {
-    const int oa = j * NAUX * p.pitch + i;
+    const long long oo = (long long)j * p.pitch + i;
     double er = 0.0, b = 0.0;
     if (p.fields_on) {
       const double r = (j + 0.5) * p.h;
@@ -447,9 +446,9 @@ __global__ void init_fields_kernel(Physics p, void* Ev) {
       er = -p.h * ce / (j + 1.0);
       b = -p.h * cb / (j + 1.0);
     }
-    stv(E + oa, 0.0);
-    stv(E + p.pitch + oa, er);
-    stv(E + 2 * p.pitch + oa, b);
+    stv(E + oo, 0.0);
+    stv(E + p.plane + oo, er);
+    stv(E + 2 * p.plane + oo, b);
   }
 }
 
@@ -463,9 +462,9 @@ __global__ void moments_out_kernel(Physics p, long long s, const void* Mv, void*
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
   const A* M = (const A*)Mv;
-  const int oa = j * NAUX * p.pitch + i;
-  const double n = (double)M[oa] + nbg(p, (double)(s + i) * p.h);
-  const double a1 = (double)M[p.pitch + oa], a2 = (double)M[2 * p.pitch + oa];
+  const long long oo = (long long)j * p.pitch + i;
+  const double n = (double)M[oo] + nbg(p, (double)(s + i) * p.h);
+  const double a1 = (double)M[p.plane + oo], a2 = (double)M[2 * p.plane + oo];
   double bz, br;
   velocity<double>(n, a1, a2, p.n_floor, bz, br);
   const long long u = (long long)j * p.nz + i, pl = (long long)p.nr * p.nz;
@@ -483,10 +482,10 @@ __global__ void fields_out_kernel(Physics p, const void* Ev, void* dst, int dst_
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
   const A* E = (const A*)Ev;
-  const int oa = j * NAUX * p.pitch + i;
+  const long long oo = (long long)j * p.pitch + i;
   const long long u = (long long)j * p.nz + i, pl = (long long)p.nr * p.nz;
   for (int c = 0; c < 3; ++c) {
-    const double v = (double)E[c * p.pitch + oa];
+    const double v = (double)E[c * p.plane + oo];
     if (dst_f64) ((double*)dst)[c * pl + u] = v;
     else ((float*)dst)[c * pl + u] = (float)v;
   }
@@ -500,16 +499,16 @@ __global__ void state_get_kernel(Physics p, long long s, const void* gv, const v
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
-  const int og = j * NPOP * p.pitch + i, oa = j * NAUX * p.pitch + i;
+  const long long oo = (long long)j * p.pitch + i;
   double v;
   if (c < 27) {
-    v = (double)ldv(((const S*)gv)[c * p.pitch + og]);
+    v = (double)ldv(((const S*)gv)[c * p.plane + oo]);
     if (c < 9) v += WQ<double>(c) * nbg(p, (double)(s + i) * p.h);
   } else if (c < 30) {
-    v = (double)((const A*)Mv)[(c - 27) * p.pitch + oa];
+    v = (double)((const A*)Mv)[(c - 27) * p.plane + oo];
     if (c == 27) v += nbg(p, (double)(s + i) * p.h);
   } else {
-    v = (double)((const A*)Ev)[(c - 30) * p.pitch + oa];
+    v = (double)((const A*)Ev)[(c - 30) * p.plane + oo];
   }
   dst[(long long)j * p.nz + i] = v;
 }
@@ -522,16 +521,16 @@ __global__ void state_set_kernel(Physics p, long long s, void* gv, void* Mv, voi
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= p.nz || j >= p.nr) return;
-  const int og = j * NPOP * p.pitch + i, oa = j * NAUX * p.pitch + i;
+  const long long oo = (long long)j * p.pitch + i;
   double v = src[(long long)j * p.nz + i];
   if (c < 27) {
     if (c < 9) v -= WQ<double>(c) * nbg(p, (double)(s + i) * p.h);
-    stv(((S*)gv) + c * p.pitch + og, v);
+    stv(((S*)gv) + c * p.plane + oo, v);
   } else if (c < 30) {
     if (c == 27) v -= nbg(p, (double)(s + i) * p.h);
-    stv(((A*)Mv) + (c - 27) * p.pitch + oa, v);
+    stv(((A*)Mv) + (c - 27) * p.plane + oo, v);
   } else {
-    stv(((A*)Ev) + (c - 30) * p.pitch + oa, v);
+    stv(((A*)Ev) + (c - 30) * p.plane + oo, v);
   }
 }
 
@@ -576,19 +575,18 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
     const int i = (int)(u % p.nz), j = (int)(u / p.nz);
     const A* M = (const A*)Mv;
     const A* E = (const A*)Ev;
-    const int RA = NAUX * p.pitch;
-    const int oo = j * RA + i;
+    const long long oo = (long long)j * p.pitch + i;
     const double h = p.h, r = (j + 0.5) * h, re = (j + 1.0) * h;
     const double z = (double)(s + i) * h;
     const double nb0 = nbg(p, z);
-    const double m0 = (double)M[oo] + nb0, m1 = M[p.pitch + oo], m2 = M[2 * p.pitch + oo];
-    const double ez = E[oo], er = E[p.pitch + oo], b = E[2 * p.pitch + oo];
+    const double m0 = (double)M[oo] + nb0, m1 = M[p.plane + oo], m2 = M[2 * p.plane + oo];
+    const double ez = E[oo], er = E[p.plane + oo], b = E[2 * p.plane + oo];
     const double twopi = 6.283185307179586;
     v[0] = twopi * r * h * h * m0;
     v[1] = 0.5 * twopi * h * h * (r * ez * ez + re * er * er + re * b * b);
     if (i >= 1) {
       const double ezl = E[oo - 1];
-      const double erb = j > 0 ? (double)E[p.pitch + oo - RA] : 0.0;
+      const double erb = j > 0 ? (double)E[p.plane + oo - p.pitch] : 0.0;
       const double div = (ez - ezl) / h + ((j + 1.0) * er - j * erb) / ((j + 0.5) * h);
       const double rho = nb0 - m0 - driver<double>(p, z, r, ((double)k - 1.0) * p.dt);
       v[2] = fabs(div - rho);
