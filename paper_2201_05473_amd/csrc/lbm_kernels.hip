@@ -117,9 +117,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   for (int q = 0; q < 9; ++q) {
     // ghost sources are replaced below; their (in-range) load is discarded
     const int off = rrow(j - XR(q)) * pitch + zcol(i - XZ(q));
-    r0[q] = (gin + q * plane)[off];
-    r1[q] = (gin + (9 + q) * plane)[off];
-    r2[q] = (gin + (18 + q) * plane)[off];
+    r0[q] = ldpop(&(gin + q * plane)[off]);
+    r1[q] = ldpop(&(gin + (9 + q) * plane)[off]);
+    r2[q] = ldpop(&(gin + (18 + q) * plane)[off]);
   }
 
   // --- 3. per-column and per-row factors of the tile --------------------------------------
