@@ -111,8 +111,11 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const double M[3],
 // (E_z, E_r, B_theta averaged to the site as the fluid used them) come from a.site, written by
 // the forward step's recompute at the output index.
 // ------------------------------------------------------------------------------------------
+// Site part of a reverse step for the tile whose first site is (i0, j0) (logical columns of x^k).
+// mreg: M_bar^{k+1} of the thread's site output, when the caller has it in registers (else read
+// from lam_next).  theta partials are added to part.  Every thread of the block must call it.
 template <int ST>
-__global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
+__device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const double* mreg, double part[4]) {
   using S = typename Mode<ST, false>::S;
   using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
   const Physics& p = a.p;
@@ -120,10 +123,6 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
-  const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
-  const int tile = xcd_tile(blockIdx.x, gx * gy);
-  const int i0 = (tile % gx) * TZ;   // logical columns of x^k
-  const int j0 = (tile / gx) * TR;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
   const double h = p.h, dt = p.dt;
   const A* __restrict__ Min = (const A*)a.M;
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
     for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
   }
 #pragma unroll
-  for (int kk = 0; kk < 3; ++kk) mbar[kk] = (L + (27 + kk) * plane)[jc * pitch + ib];
+  for (int kk = 0; kk < 3; ++kk) mbar[kk] = mreg ? A(0) : (L + (27 + kk) * plane)[jc * pitch + ib];
   if (p.fields_on)
 #pragma unroll
     for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[jc * pitch + ib];
@@ -188,7 +187,16 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   }
   __syncthreads();
 
-  double part[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(ramp_len, n0, sigma_r, n_b)
+  if (a.shift && i == nz && j < nr) {
+    // the column dropped in this step (column 0) has no site: zero adjoint sources.  Written
+    // here too because a caller may start its tile at column 1 (tiles of the output frame)
+    A* __restrict__ Lo = (A*)a.lam;
+    A* __restrict__ W = (A*)a.work;
+#pragma unroll
+    for (int c = 0; c < 27; ++c) (Lo + c * plane)[j * pitch] = A(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) (W + c * plane)[j * pitch] = A(0);
+  }
   if (mine) {
     const int cell = j * pitch + i;
     A* __restrict__ Lo = (A*)a.lam;
@@ -273,7 +281,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       ubr *= itau;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
-        const double Mb = (double)mbar[kk];
+        const double Mb = mreg ? mreg[kk] : (double)mbar[kk];
         Fb[kk] = dt * (sw[kk] + Mb);
         Ab[kk] = Mb + s0[kk] * itau;
       }
@@ -349,6 +357,14 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
       }
     }
   }
+}
+
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
+  const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
+  const int tile = xcd_tile(blockIdx.x, gx * gy);
+  double part[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(ramp_len, n0, sigma_r, n_b)
+  site_body<ST>(a, (tile % gx) * TZ, (tile / gx) * TR, nullptr, part);
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
 }
 
@@ -356,15 +372,15 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 // adj_cell_kernel: one thread per cell (i, j) of x^k.  Field part staged through LDS:
 // L_B' = adjoint of B^{k+1/2}, L_Ez', L_Er' = adjoints of E^k (as used by step k).
 // ------------------------------------------------------------------------------------------
+// Cell part of a reverse step for the tile whose first cell is (i0, j0) of x^k.  The moment
+// adjoint of the thread's cell (zero for a thread outside the grid) is returned in mb_out as well
+// as stored.  theta partials are added to part.  Every thread of the block must call it.
 template <int ST>
-__global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
+__device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, double part[4], double mb_out[3]) {
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
-  const int gx = (nz + TZ - 1) / TZ, gy = (nr + TR - 1) / TR;
-  const int tile = xcd_tile(blockIdx.x, gx * gy);
-  const int i0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
   const double h = p.h, dt = p.dt;
   const A* __restrict__ W = (const A*)a.work;
@@ -411,7 +427,6 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
   };
 
   const int i = i0 + tx, j = j0 + ty;
-  double part[4] = {0.0, 0.0, 0.0, 0.0};
   double jz = 0.0, jr = 0.0;
   const int ic = i < nz ? i : nz - 1, jc = j < nr ? j : nr - 1;
   const int cell = j * pitch + i, cellc = jc * pitch + ic;
@@ -546,7 +561,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
       stv(&(Lo + (30 + c) * plane)[cell], ok ? (double)(L + (30 + c) * plane)[o] : 0.0);
     }
   }
-  block_sum4(part, a.partials + (long long)blockIdx.x * 4);
+  mb_out[0] = mb_out[1] = mb_out[2] = 0.0;
   if (!mine) return;   // no barrier below this point
 
   // ---- lambda of the moments ----
@@ -650,7 +665,37 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
     }
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) stv(&(Lo + (27 + k) * plane)[cell], Mb[k]);
+  for (int k = 0; k < 3; ++k) {
+    stv(&(Lo + (27 + k) * plane)[cell], Mb[k]);
+    mb_out[k] = (double)(A)Mb[k];   // as stored, so the fused step reads what a split one would
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
+  const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
+  const int tile = xcd_tile(blockIdx.x, gx * gy);
+  double part[4] = {0.0, 0.0, 0.0, 0.0}, mb[3];
+  cell_body<ST>(a, (tile % gx) * TZ, (tile / gx) * TR, part, mb);
+  block_sum4(part, a.partials + (long long)blockIdx.x * 4);
+}
+
+// Fused reverse work of two consecutive steps: the cell part of step k (ac, cells of x^k) and the
+// site part of step k - 1 (as, sites of x^{k-1}).  Thread (tx, ty) takes cell o = o0 + tx of x^k
+// and the site o + shift_{k-1} of x^{k-1}, whose output is that cell, so the site part takes
+// M_bar^k from the cell part's registers.  ac.lam and as.lam_next are the same buffer (lambda^k):
+// the cell part writes its planes 27..32, the site part reads planes 0..26 (written by the
+// previous launch) and writes f_bar^{k-1} into as.lam, whose planes 30..32 (lambda^{k+1}) the cell
+// part reads; the two steps use different work buffers.
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void adj_fused_kernel(AdjArgs ac, AdjArgs as) {
+  const int gx = (ac.p.nz + TZ - 1) / TZ, gy = (ac.p.nr + TR - 1) / TR;
+  const int tile = xcd_tile(blockIdx.x, gx * gy);
+  const int o0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
+  double part[4] = {0.0, 0.0, 0.0, 0.0}, mb[3];
+  cell_body<ST>(ac, o0, j0, part, mb);
+  site_body<ST>(as, o0 + as.shift, j0, mb, part);
+  block_sum4(part, as.partials + (long long)blockIdx.x * 4);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -832,6 +877,23 @@ hipError_t launch_adjoint_step(int storage, const AdjArgs& a, hipStream_t st) {
   AdjArgs b = a;
   b.partials = a.partials + (long long)adjoint_partial_blocks(a.p) * 4;
   ADJ_DISPATCH(storage, adj_cell_kernel, dim3(nb), NTHREADS, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_site(int storage, const AdjArgs& a, hipStream_t st) {
+  ADJ_DISPATCH(storage, adj_site_kernel, dim3(step_blocks(a.p)), NTHREADS, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_cell(int storage, const AdjArgs& a, hipStream_t st) {
+  AdjArgs b = a;
+  b.partials = a.partials + (long long)adjoint_partial_blocks(a.p) * 4;
+  ADJ_DISPATCH(storage, adj_cell_kernel, dim3(step_blocks(a.p)), NTHREADS, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_fused(int storage, const AdjArgs& cell, const AdjArgs& site, hipStream_t st) {
+  ADJ_DISPATCH(storage, adj_fused_kernel, dim3(step_blocks(cell.p)), NTHREADS, st, cell, site);
   return hipGetLastError();
 }
 

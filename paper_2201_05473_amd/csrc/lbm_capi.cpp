@@ -448,7 +448,7 @@ size_t site_bytes(const Physics& p, int storage) {
 // auxiliary-plane type), the per-block partials, the gradient accumulator; the host-facing VJP
 // calls add an FP64 staging area for lambda in the stored-state layout.
 struct AdjLayout {
-  size_t lamA, lamB, work, partials, grad, core_total, stage, scratch, site, vjp_total;
+  size_t lamA, lamB, work, work2, partials, grad, core_total, stage, scratch, site, vjp_total;
 };
 
 AdjLayout adj_layout(const Physics& p, int storage) {
@@ -458,6 +458,7 @@ AdjLayout adj_layout(const Physics& p, int storage) {
   L.lamA = off; off += round_up(33 * plane_l, 256);
   L.lamB = off; off += round_up(33 * plane_l, 256);
   L.work = off; off += round_up(6 * plane_l, 256);
+  L.work2 = off; off += round_up(6 * plane_l, 256);   // consecutive steps of the fused sweep
   L.partials = off; off += round_up((size_t)lbm::adjoint_partial_blocks(p) * 8 * sizeof(double), 256);
   L.grad = off; off += 256;
   L.core_total = off;
@@ -508,7 +509,7 @@ hipError_t download_lam(const Physics& p, double* dst, const double* src, hipStr
 }
 
 lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, const void* site, long long k, const void* lam_next,
-                      void* lam, int pull_in, char* ws, const AdjLayout& L) {
+                      void* lam, int pull_in, char* ws, const AdjLayout& L, int work_buf = 0) {
   lbm::AdjArgs a;
   a.p = c->p;
   a.k = k;
@@ -521,7 +522,7 @@ lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, const void* site, long lon
   a.lam_next = lam_next;
   a.lam = lam;
   a.site = site;
-  a.work = ws + L.work;
+  a.work = ws + (work_buf ? L.work2 : L.work);
   a.partials = (double*)(ws + L.partials);
   return a;
 }
@@ -717,6 +718,19 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   HIP_CHECK(hipStreamWaitEvent(c->aux, c->ev_fwd, 0), "stream wait");
   HIP_CHECK(recompute(nseg - 1, seg[(nseg - 1) % 2]), "recompute launch");
   HIP_CHECK(hipEventRecord(c->ev_rec[(nseg - 1) % 2], c->aux), "event record");
+  // Within the sweep, the cell part of step k and the site part of step k - 1 run as one fused
+  // launch; the site part of the last step and the cell part of step 0 run alone.  At a segment
+  // boundary the fused launch reads the last state (and site fields) of the previous segment,
+  // so the caller's stream waits for that segment's recompute first; a segment buffer is
+  // released once the cell part of its first step has run.
+  auto xs = [&](int64_t k) -> StateView {
+    const int64_t sgi = k / ckpt_every;
+    return state_at(seg[sgi % 2] + (size_t)(k - sgi * ckpt_every) * sb, p, c->storage);
+  };
+  auto site_of = [&](int64_t k) -> const void* {
+    const int64_t sgi = k / ckpt_every;
+    return seg[sgi % 2] + (size_t)(seglen + 1) * sb + (size_t)(k - sgi * ckpt_every) * stb;
+  };
   for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
     const int b = (int)(sgi % 2);
     if (sgi >= 1) {
@@ -726,14 +740,24 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
       HIP_CHECK(recompute(sgi - 1, seg[b2]), "recompute launch");
       HIP_CHECK(hipEventRecord(c->ev_rec[b2], c->aux), "event record");
     }
-    HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_rec[b], 0), "stream wait");
     const int64_t k0 = sgi * ckpt_every;
     const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
-    char* sites = seg[b] + (size_t)(seglen + 1) * sb;
-    for (int64_t t = len - 1; t >= 0; --t) {
-      const StateView x = state_at(seg[b] + (size_t)t * sb, p, c->storage);
-      const lbm::AdjArgs a = adj_args(c, x, sites + (size_t)t * stb, k0 + t, lam[cur], lam[1 - cur], 1, w, L);
-      HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, c->stream), "adjoint launch");
+    for (int64_t k = k0 + len - 1; k >= k0; --k) {
+      if (k == nsteps - 1) {
+        HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_rec[b], 0), "stream wait");
+        const lbm::AdjArgs as = adj_args(c, xs(k), site_of(k), k, lam[cur], lam[1 - cur], 1, w, L, (int)(k % 2));
+        HIP_CHECK(lbm::launch_adjoint_site(c->storage, as, c->stream), "adjoint launch");
+      }
+      // cell part of step k: lambda^{k+1} in lam[cur], lambda^k (populations done) in lam[1 - cur]
+      const lbm::AdjArgs ac = adj_args(c, xs(k), nullptr, k, lam[cur], lam[1 - cur], 1, w, L, (int)(k % 2));
+      if (k >= 1) {
+        if (k == k0) HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_rec[(sgi - 1) % 2], 0), "stream wait");
+        const lbm::AdjArgs as = adj_args(c, xs(k - 1), site_of(k - 1), k - 1, lam[1 - cur], lam[cur], 1, w, L,
+                                         (int)((k - 1) % 2));
+        HIP_CHECK(lbm::launch_adjoint_fused(c->storage, ac, as, c->stream), "adjoint launch");
+      } else {
+        HIP_CHECK(lbm::launch_adjoint_cell(c->storage, ac, c->stream), "adjoint launch");
+      }
       cur ^= 1;
     }
     HIP_CHECK(hipEventRecord(c->ev_rev[b], c->stream), "event record");

@@ -90,6 +90,11 @@ hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long l
 // sum of the accumulators added into grad_acc[4].
 int adjoint_partial_blocks(const Physics& p);
 hipError_t launch_adjoint_step(int storage, const AdjArgs& a, hipStream_t st);
+// The two halves of a reverse step (site part, then cell part), and the fused launch of the cell
+// part of step k with the site part of step k - 1 (same partial accumulators as the site part).
+hipError_t launch_adjoint_site(int storage, const AdjArgs& a, hipStream_t st);
+hipError_t launch_adjoint_cell(int storage, const AdjArgs& a, hipStream_t st);
+hipError_t launch_adjoint_fused(int storage, const AdjArgs& cell, const AdjArgs& site, hipStream_t st);
 hipError_t launch_adjoint_init(int storage, const AdjArgs& a, hipStream_t st);
 hipError_t adjoint_reduce(const Physics& p, const double* partials, double* grad_acc, hipStream_t st);
 // lambda^k (a.lam) in the stored-state layout: 33 pitched FP64 planes written to out.
