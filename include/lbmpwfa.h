@@ -189,6 +189,19 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
 int lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every,
                 void* adj_ws, size_t adj_bytes, double* J, double grad[4]);
 
+/* Objective and gradient as lbm_adjoint, under a budget of `snapshots` stored states instead of
+ * a checkpoint interval: binomial (revolve-type) checkpointing.  With s snapshots and every step
+ * advanced at most t times, C(s + t, s) steps can be reversed; the recursion places each next
+ * snapshot so that the later part of a range fits one snapshot fewer.  The workspace holds the
+ * snapshots and the site fields of one step.  The context's two state buffers serve as scratch;
+ * on return the context holds its initial state (step 0) again.  steps_advanced (may be NULL)
+ * receives the number of forward steps taken, including the one each reverse step recomputes.
+ * Synchronising.  Periodic dimensions need at least 5 cells. */
+int lbm_adjoint_revolve_workspace_bytes(const lbm_config* cfg, int32_t snapshots, size_t* bytes);
+int lbm_adjoint_revolve(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, int32_t snapshots,
+                        void* adj_ws, size_t adj_bytes, double* J, double grad[4],
+                        int64_t* steps_advanced);
+
 /* FP64 diagnostics of the current state (deterministic two-pass reduction).  Synchronising. */
 int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 

@@ -91,6 +91,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "lbm_adjoint_workspace_bytes": (c_int32, [P(LbmConfig), c_int64, c_int32, P(c_size_t)]),
         "lbm_adjoint": (c_int32, [c_void_p, P(LbmObjective), c_int64, c_int32, c_void_p, c_size_t,
                                   P(c_double), c_void_p]),
+        "lbm_adjoint_revolve_workspace_bytes": (c_int32, [P(LbmConfig), c_int32, P(c_size_t)]),
+        "lbm_adjoint_revolve": (c_int32, [c_void_p, P(LbmObjective), c_int64, c_int32, c_void_p, c_size_t,
+                                          P(c_double), c_void_p, P(c_int64)]),
         "lbm_destroy": (c_int32, [c_void_p]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -243,6 +246,26 @@ def lbm_adjoint(ctx: int, z_behind: float, row: int, nsteps: int, ckpt_every: in
     return J.value, grad
 
 
+def lbm_adjoint_revolve_workspace_bytes(cfg: dict | LbmConfig, snapshots: int) -> int:
+    c = cfg if isinstance(cfg, LbmConfig) else make_config(cfg)
+    n = c_size_t(0)
+    _check(load_library().lbm_adjoint_revolve_workspace_bytes(ctypes.byref(c), c_int32(snapshots), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_adjoint_revolve(ctx: int, z_behind: float, row: int, nsteps: int, snapshots: int, ws_ptr: int,
+                        ws_bytes: int):
+    """(J, grad, forward steps taken) with binomial checkpointing under a snapshot budget."""
+    obj = LbmObjective(float(z_behind), int(row))
+    J = c_double(0.0)
+    adv = c_int64(0)
+    grad = np.zeros(4, dtype=np.float64)
+    _check(load_library().lbm_adjoint_revolve(c_void_p(ctx), ctypes.byref(obj), c_int64(nsteps),
+                                              c_int32(snapshots), c_void_p(ws_ptr), c_size_t(ws_bytes),
+                                              ctypes.byref(J), grad.ctypes.data_as(c_void_p), ctypes.byref(adv)))
+    return J.value, grad, adv.value
+
+
 def lbm_counters(ctx: int):
     k, s = c_int64(0), c_int64(0)
     _check(load_library().lbm_counters(c_void_p(ctx), ctypes.byref(k), ctypes.byref(s)))
@@ -344,6 +367,13 @@ class Lattice:
         nbytes = lbm_adjoint_workspace_bytes(self.cfg, nsteps, ckpt_every)
         buf, ptr = self._scratch(nbytes)
         return lbm_adjoint(self.ctx, z_behind, row, nsteps, ckpt_every, ptr, nbytes)
+
+    def adjoint_revolve(self, nsteps: int, snapshots: int, z_behind: float = 4.0, row: int = 0):
+        """(J, dJ/d(ramp_len, n0, sigma_r, nb), forward steps taken) with binomial checkpointing
+        under a budget of `snapshots` stored states; the lattice is back at its initial state after."""
+        nbytes = lbm_adjoint_revolve_workspace_bytes(self.cfg, snapshots)
+        buf, ptr = self._scratch(nbytes)
+        return lbm_adjoint_revolve(self.ctx, z_behind, row, nsteps, snapshots, ptr, nbytes)
 
     def counters(self):
         return lbm_counters(self.ctx)

@@ -774,6 +774,211 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   return LBM_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// Adjoint with a snapshot budget: binomial (revolve-type) checkpointing.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// beta(s, t) = C(s + t, s): the longest step range that s snapshots reverse with every step
+// advanced at most t times (Griewank's binomial bound); saturates at 2^62.
+int64_t beta(int64_t s, int64_t t) {
+  double v = 1.0;
+  for (int64_t i = 1; i <= t; ++i) {
+    v = v * (double)(s + i) / (double)i;
+    if (v > 4.6e18) return (int64_t)1 << 62;
+  }
+  return (int64_t)(v + 0.5);
+}
+
+struct Revolve {
+  lbm_ctx* c;
+  const AdjLayout* L;
+  char* w;
+  char* snaps;     // snapshot slots, one state each
+  char* sites;     // site fields of the step being reversed
+  size_t sb;
+  char* lam[2];
+  int cur;
+  int64_t nsteps;
+  int32_t row;
+  long long iw;
+  double ww, J;
+  int64_t advanced;   // forward steps taken (statistics)
+
+  StateView slot(int i) const { return state_at(snaps + (size_t)i * sb, c->p, c->storage); }
+  StateView ctxbuf(int b) const { return StateView{c->g(b), c->M(b), c->E(b)}; }
+
+  lbm::StepArgs step_args(int64_t k, const StateView& x, const StateView& y, void* site) const {
+    lbm::StepArgs a;
+    a.p = c->p;
+    a.k = k;
+    a.s = c->p.window ? k / c->p.m : 0;
+    a.shift = (c->p.window && (k + 1) % c->p.m == 0) ? 1 : 0;
+    a.g_in = x.g; a.g_out = y.g;
+    a.M_in = x.M; a.M_out = y.M;
+    a.E_in = x.E; a.E_out = y.E;
+    a.site_out = site;
+    return a;
+  }
+
+  // x^{from} (in snapshot slot src) advanced to x^{to}, to > from: into snapshot slot dst if
+  // dst >= 0, else into one of the context's two buffers, whose index goes to *where.
+  // Intermediate states alternate between the context's buffers (never in place).
+  int advance(int64_t from, int64_t to, int src, int dst, int* where = nullptr) {
+    StateView x = slot(src);
+    int b = 0;
+    for (int64_t k = from; k < to; ++k) {
+      const bool last = k + 1 == to;
+      const StateView y = (last && dst >= 0) ? slot(dst) : ctxbuf(b);
+      HIP_CHECK(lbm::launch_step(c->storage, step_args(k, x, y, nullptr), c->stream), "step launch");
+      if (last && dst < 0 && where) *where = b;
+      x = y;
+      b ^= 1;
+      ++advanced;
+    }
+    return LBM_OK;
+  }
+
+  // reverse step k from x^k (in x): the step again with its site fields saved (its output, x^{k+1},
+  // gives J when k = N - 1), then the reverse kernels
+  int reverse_step(int64_t k, const StateView& x) {
+    const StateView y = (x.g == c->g(0)) ? ctxbuf(1) : ctxbuf(0);   // not x itself
+    HIP_CHECK(lbm::launch_step(c->storage, step_args(k, x, y, c->p.fields_on ? sites : nullptr), c->stream),
+              "step launch");
+    ++advanced;
+    if (k == nsteps - 1) {
+      const size_t ab = aux_bytes(c->storage);
+      const char* ez = (const char*)y.E + ((size_t)row * c->p.pitch + (size_t)iw) * ab;
+      double e[2];
+      if (ab == 8) {
+        HIP_CHECK(hipMemcpyAsync(e, ez, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "objective");
+      } else {
+        float f[2];
+        HIP_CHECK(hipMemcpyAsync(f, ez, 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream), "objective");
+        HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+        e[0] = f[0];
+        e[1] = f[1];
+      }
+      HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+      J = (1.0 - ww) * e[0] + ww * e[1];
+    }
+    const lbm::AdjArgs a = adj_args(c, x, sites, k, lam[cur], lam[1 - cur], 1, w, *L);
+    HIP_CHECK(lbm::launch_adjoint_step(c->storage, a, c->stream), "adjoint launch");
+    cur ^= 1;
+    return LBM_OK;
+  }
+
+  // lambda^a from lambda^b, with x^a in snapshot slot `sa` and the slots above it free (nfree)
+  int reverse(int64_t a, int64_t b, int sa, int nfree) {
+    const int64_t l = b - a;
+    if (l == 1) return reverse_step(a, slot(sa));
+    if (nfree == 0) {
+      // no snapshot left: advance from x^a for every step of the range
+      for (int64_t k = b - 1; k > a; --k) {
+        int where = 0;
+        int rc = advance(a, k, sa, -1, &where);
+        if (rc) return rc;
+        rc = reverse_step(k, ctxbuf(where));
+        if (rc) return rc;
+      }
+      return reverse_step(a, slot(sa));
+    }
+    int64_t t = 1;
+    while (beta(nfree, t) < l) ++t;
+    const int64_t m = b - std::min<int64_t>(beta(nfree - 1, t), l - 1);
+    int rc = advance(a, m, sa, sa + 1);
+    if (rc) return rc;
+    rc = reverse(m, b, sa + 1, nfree - 1);
+    if (rc) return rc;
+    return reverse(a, m, sa, nfree);
+  }
+};
+
+}  // namespace
+
+int lbm_adjoint_revolve_workspace_bytes(const lbm_config* cfg, int32_t snapshots, size_t* bytes) {
+  Physics p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  if (snapshots < 1) return fail(LBM_EINVAL, "snapshots must be >= 1");
+  *bytes = adj_layout(p, cfg->storage).core_total + (size_t)snapshots * state_bytes(p, cfg->storage) +
+           site_bytes(p, cfg->storage);
+  return LBM_OK;
+}
+
+int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t snapshots, void* ws,
+                        size_t bytes, double* J, double grad[4], int64_t* steps_advanced) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!obj || !J || !grad) return fail(LBM_EINVAL, "NULL argument");
+  if (nsteps < 1 || snapshots < 1) return fail(LBM_EINVAL, "nsteps and snapshots must be >= 1");
+  if (c->k != 0) return fail(LBM_ESTATE, "lbm_adjoint_revolve needs the context at its initial state (step 0)");
+  size_t need;
+  int rc = lbm_adjoint_revolve_workspace_bytes(&c->cfg, snapshots, &need);
+  if (rc) return rc;
+  rc = adj_check(c, ws, bytes, need);
+  if (rc) return rc;
+  const Physics& p = c->p;
+  if (obj->row < 0 || obj->row >= p.nr) return fail(LBM_EINVAL, "objective row out of range");
+  const long long sN = p.window ? nsteps / p.m : 0;
+  const double zstar = p.zd0 + (double)(nsteps - 1) * p.dt - obj->z_behind;
+  const double xw = zstar / p.h - (double)sN - 0.5;
+  const long long iw = (long long)std::floor(xw);
+  if (iw < 0 || iw >= p.nz - 1) return fail(LBM_EINVAL, "witness position outside the window");
+
+  const AdjLayout L = adj_layout(p, c->storage);
+  Revolve r;
+  r.c = c;
+  r.L = &L;
+  r.w = (char*)ws;
+  r.sb = state_bytes(p, c->storage);
+  r.snaps = r.w + L.core_total;
+  r.sites = r.snaps + (size_t)snapshots * r.sb;
+  r.lam[0] = r.w + L.lamA;
+  r.lam[1] = r.w + L.lamB;
+  r.cur = 0;
+  r.nsteps = nsteps;
+  r.row = obj->row;
+  r.iw = iw;
+  r.ww = xw - (double)iw;
+  r.J = 0.0;
+  r.advanced = 0;
+  // snapshot 0 = x^0 (the context's state); lambda^N = dJ/dx^N
+  const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
+  const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
+  const StateView x0 = r.slot(0), ctx0{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  HIP_CHECK(hipMemcpyAsync(x0.g, ctx0.g, gbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
+  HIP_CHECK(hipMemcpyAsync(x0.M, ctx0.M, mbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
+  HIP_CHECK(hipMemcpyAsync(x0.E, ctx0.E, mbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
+  HIP_CHECK(hipMemsetAsync(r.w, 0, L.core_total, c->stream), "clear");
+  {
+    const size_t ab = aux_bytes(c->storage);
+    char* dst = r.lam[0] + (30 * (size_t)p.plane + (size_t)obj->row * p.pitch + (size_t)iw) * ab;
+    const double seedd[2] = {1.0 - r.ww, r.ww};
+    const float seedf[2] = {(float)(1.0 - r.ww), (float)r.ww};
+    HIP_CHECK(hipMemcpyAsync(dst, ab == 8 ? (const void*)seedd : (const void*)seedf, 2 * ab,
+                             hipMemcpyHostToDevice, c->stream),
+              "seed");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  }
+  rc = r.reverse(0, nsteps, 0, snapshots - 1);
+  if (rc) return rc;
+  {
+    const lbm::AdjArgs a = adj_args(c, x0, nullptr, 0, r.lam[r.cur], nullptr, 1, r.w, L);
+    HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, c->stream), "adjoint init launch");
+    HIP_CHECK(lbm::adjoint_reduce(p, a.partials, (double*)(r.w + L.grad), c->stream), "adjoint reduce");
+  }
+  // the context's buffers served as scratch: restore the initial state
+  HIP_CHECK(hipMemcpyAsync(ctx0.g, x0.g, gbytes, hipMemcpyDeviceToDevice, c->stream), "restore");
+  HIP_CHECK(hipMemcpyAsync(ctx0.M, x0.M, mbytes, hipMemcpyDeviceToDevice, c->stream), "restore");
+  HIP_CHECK(hipMemcpyAsync(ctx0.E, x0.E, mbytes, hipMemcpyDeviceToDevice, c->stream), "restore");
+  HIP_CHECK(hipMemcpyAsync(grad, r.w + L.grad, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  *J = r.J;
+  if (steps_advanced) *steps_advanced = r.advanced;
+  return LBM_OK;
+}
+
 int lbm_counters(lbm_ctx* c, int64_t* step, int64_t* shifts) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (step) *step = c->k;
