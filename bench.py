@@ -162,6 +162,56 @@ def adjoint_c4(ckpt_every: int = 45) -> dict:
             "rel_err_vs_fd": {nm: float(r) for nm, r in zip(names, rel)}}
 
 
+def long_plasma_c5(budget_gb: float = 64.0, fd_params=("sigma_r", "nb")) -> dict:
+    """C5 (8192 x 2048, 20,000 steps, FP32, tanh ramp of seed-drawn length): forward MLUPS, the
+    binomial-checkpointed adjoint under a snapshot budget of budget_gb, its time over the
+    forward's, and the gradient against central differences (h = 1e-4) of FP64 forward runs for
+    the parameters in fd_params.  Prints a progress line per phase."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C5")
+    n, zb = cfg["nsteps"], cfg["z_behind"]
+    sites = cfg["nz"] * cfg["nr"]
+    names = ("ramp_len", "n0", "sigma_r", "nb")
+    state_bytes = sites * (27 * 4 + 6 * 4)
+    snapshots = int(budget_gb * 1e9 // state_bytes)
+    lat = Lattice(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(n)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    lat.close()
+    print(f"[C5] forward {tf:.2f} s", file=sys.stderr, flush=True)
+    lat = Lattice(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, grad, adv = lat.adjoint_revolve(n, snapshots, z_behind=zb)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    lat.close()
+    print(f"[C5] adjoint {ta:.2f} s, {adv} forward steps", file=sys.stderr, flush=True)
+    cfg64 = dict(cfg, storage=wl.F64)
+    J64 = objective_f64(cfg64, n, zb)
+    fd = {}
+    for nm in fd_params:
+        cp, cm = dict(cfg64), dict(cfg64)
+        cp[nm] += 1e-4
+        cm[nm] -= 1e-4
+        fd[nm] = (objective_f64(cp, n, zb) - objective_f64(cm, n, zb)) / 2e-4
+        print(f"[C5] fd {nm} done", file=sys.stderr, flush=True)
+    g = dict(zip(names, map(float, grad)))
+    return {"workload": "C5: 8192x2048, dz=0.02, FP32, tanh ramp of length %.2f, driver n_b=0.5 "
+                        "sigma_z=0.5 sigma_r=0.25, 20000 steps" % cfg["ramp_len"],
+            "forward_MLUPS": sites * n / tf / 1e6, "t_forward_s": tf, "t_adjoint_s": ta, "ratio": ta / tf,
+            "snapshots": snapshots, "snapshot_GB": snapshots * state_bytes / 1e9, "forward_steps_taken": adv,
+            "J": J, "J_f64": J64, "grad": g, "fd_f64": fd,
+            "rel_err_vs_fd": {nm: abs(g[nm] - fd[nm]) / abs(fd[nm]) for nm in fd}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +224,9 @@ def main():
                          "(the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--storage", choices=("f64", "f32", "f16"), default="f32",
                     help="population storage of the --profile run")
+    ap.add_argument("--c5", action="store_true",
+                    help="the long-plasma case C5 instead of the headline: forward MLUPS, adjoint under "
+                         "a 64 GB snapshot budget, gradient against FP64 finite differences (minutes)")
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="for rocprofv3: one C4 lbm_adjoint (2,000 steps, checkpoints every 45) after a "
                          "warm-up run")
@@ -193,6 +246,10 @@ def main():
     cfg = wl.config("C2")
     sites = cfg["nz"] * cfg["nr"]
     steps, warmup = args.steps, args.warmup
+
+    if args.c5:
+        print(json.dumps({"c5": long_plasma_c5()}))
+        return
 
     if args.profile_adjoint:
         from paper_2201_05473_amd import Lattice

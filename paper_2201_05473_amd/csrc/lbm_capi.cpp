@@ -868,29 +868,33 @@ struct Revolve {
     return LBM_OK;
   }
 
-  // lambda^a from lambda^b, with x^a in snapshot slot `sa` and the slots above it free (nfree)
+  // lambda^a from lambda^b, with x^a in snapshot slot `sa` and the slots above it free (nfree).
+  // The later part of a range recurses with one snapshot fewer (depth <= nfree); the earlier
+  // part continues in the loop.
   int reverse(int64_t a, int64_t b, int sa, int nfree) {
-    const int64_t l = b - a;
-    if (l == 1) return reverse_step(a, slot(sa));
-    if (nfree == 0) {
-      // no snapshot left: advance from x^a for every step of the range
-      for (int64_t k = b - 1; k > a; --k) {
-        int where = 0;
-        int rc = advance(a, k, sa, -1, &where);
-        if (rc) return rc;
-        rc = reverse_step(k, ctxbuf(where));
-        if (rc) return rc;
+    for (;;) {
+      const int64_t l = b - a;
+      if (l == 1) return reverse_step(a, slot(sa));
+      if (nfree == 0) {
+        // no snapshot left: advance from x^a for every step of the range
+        for (int64_t k = b - 1; k > a; --k) {
+          int where = 0;
+          int rc = advance(a, k, sa, -1, &where);
+          if (rc) return rc;
+          rc = reverse_step(k, ctxbuf(where));
+          if (rc) return rc;
+        }
+        return reverse_step(a, slot(sa));
       }
-      return reverse_step(a, slot(sa));
+      int64_t t = 1;
+      while (beta(nfree, t) < l) ++t;
+      const int64_t m = b - std::min<int64_t>(beta(nfree - 1, t), l - 1);
+      int rc = advance(a, m, sa, sa + 1);
+      if (rc) return rc;
+      rc = reverse(m, b, sa + 1, nfree - 1);
+      if (rc) return rc;
+      b = m;
     }
-    int64_t t = 1;
-    while (beta(nfree, t) < l) ++t;
-    const int64_t m = b - std::min<int64_t>(beta(nfree - 1, t), l - 1);
-    int rc = advance(a, m, sa, sa + 1);
-    if (rc) return rc;
-    rc = reverse(m, b, sa + 1, nfree - 1);
-    if (rc) return rc;
-    return reverse(a, m, sa, nfree);
   }
 };
 
