@@ -205,6 +205,14 @@ int lbm_adjoint_revolve(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, 
 /* FP64 diagnostics of the current state (deterministic two-pass reduction).  Synchronising. */
 int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 
+/* Bubble length (Sec. IV, Fig. 4): the number of sites of row `row` at lab positions z in
+ * [z_from, z_to] whose electron density is below n_star times the local background density
+ * n_bg(z) (sites in vacuum, n_bg = 0, excluded; the paper uses n_star = 0.95), and that number
+ * times dz (length may be NULL).  The comparison is made in FP64.  Synchronising.  LBM_EINVAL for
+ * a row outside [0, nr), n_star <= 0 or a NaN bound. */
+int lbm_bubble_length(lbm_ctx* ctx, int32_t row, double n_star, double z_from, double z_to,
+                      int64_t* count, double* length);
+
 /* Step and window-shift counters of the state. */
 int lbm_counters(lbm_ctx* ctx, int64_t* step, int64_t* shifts);
 

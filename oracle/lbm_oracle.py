@@ -51,6 +51,8 @@ Readings of the paper (where it is silent, garbled or inconsistent; each is list
       on the axis.
   R19 Where A_0 <= n_floor the momentum, velocity, current and Lorentz force are zero.
   R23 Ramp shapes: linear n0 clamp((z - z_p)/L, 0, 1) and tanh n0 (1 + tanh(2 (z - z_p)/L - 1)) / 2.
+  R28 Bubble length (Sec. IV, Fig. 4): sites of one row, in a given lab z-range, whose density is
+      below n* = 0.95 times the local background (vacuum sites excluded), times dz.
 
 State after k completed steps (k = 0 is the initial state):
     g  [3][9][nr][nz]   post-collision populations of step k-1 (raw values, not deviations)
@@ -468,6 +470,21 @@ def diagnostics(S: State, P: Params) -> dict:
     return dict(charge=float(charge), field_energy=float(energy),
                 gauss_max=float(G.abs().max()) if G.numel() else 0.0,
                 umax=float(umax), nonfinite=int(not finite), step=S.k, shifts=S.s)
+
+
+def bubble_length(n, s: int, P: Params, row: int, n_star: float = 0.95, z_from: float = -math.inf,
+                  z_to: float = math.inf):
+    """Bubble length of Sec. IV (Fig. 4): the number of sites whose electron density lies below
+    the threshold n* times the unperturbed density, times dz.  Reading R28: the sites are those of
+    one row (the paper takes longitudinal profiles at a fixed radius) at lab positions
+    z_i = (s + i) dz in [z_from, z_to], the threshold is relative to the local background n_bg(z_i)
+    (so a density ramp is not counted), sites in vacuum (n_bg = 0) are excluded and the comparison
+    is strict.  n: the electron density [nr][nz] (raw, FP64).  Returns (count, count * dz)."""
+    z = (s + torch.arange(P.nz, dtype=DT)) * P.h
+    nbg = n_background(z, P)
+    sel = (z >= z_from) & (z <= z_to) & (nbg > 0.0) & (n[row] < n_star * nbg)
+    count = int(sel.sum())
+    return count, count * P.h
 
 
 def objective(S: State, P: Params, z_behind: float):

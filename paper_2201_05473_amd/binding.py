@@ -8,6 +8,7 @@ context and its workspace.  If the library is missing this module raises: there 
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -94,6 +95,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "lbm_adjoint_revolve_workspace_bytes": (c_int32, [P(LbmConfig), c_int32, P(c_size_t)]),
         "lbm_adjoint_revolve": (c_int32, [c_void_p, P(LbmObjective), c_int64, c_int32, c_void_p, c_size_t,
                                           P(c_double), c_void_p, P(c_int64)]),
+        "lbm_bubble_length": (c_int32, [c_void_p, c_int32, c_double, c_double, c_double, P(c_int64),
+                                        P(c_double)]),
         "lbm_destroy": (c_int32, [c_void_p]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -266,6 +269,16 @@ def lbm_adjoint_revolve(ctx: int, z_behind: float, row: int, nsteps: int, snapsh
     return J.value, grad, adv.value
 
 
+def lbm_bubble_length(ctx: int, row: int = 0, n_star: float = 0.95, z_from: float = -math.inf,
+                      z_to: float = math.inf):
+    """(count, length) of the sites of a row below n_star times the background density."""
+    n = c_int64(0)
+    length = c_double(0.0)
+    _check(load_library().lbm_bubble_length(c_void_p(ctx), c_int32(row), c_double(n_star), c_double(z_from),
+                                            c_double(z_to), ctypes.byref(n), ctypes.byref(length)))
+    return n.value, length.value
+
+
 def lbm_counters(ctx: int):
     k, s = c_int64(0), c_int64(0)
     _check(load_library().lbm_counters(c_void_p(ctx), ctypes.byref(k), ctypes.byref(s)))
@@ -374,6 +387,10 @@ class Lattice:
         nbytes = lbm_adjoint_revolve_workspace_bytes(self.cfg, snapshots)
         buf, ptr = self._scratch(nbytes)
         return lbm_adjoint_revolve(self.ctx, z_behind, row, nsteps, snapshots, ptr, nbytes)
+
+    def bubble_length(self, row: int = 0, n_star: float = 0.95, z_from: float = -math.inf,
+                      z_to: float = math.inf):
+        return lbm_bubble_length(self.ctx, row, n_star, z_from, z_to)
 
     def counters(self):
         return lbm_counters(self.ctx)

@@ -983,6 +983,24 @@ int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, in
   return LBM_OK;
 }
 
+int lbm_bubble_length(lbm_ctx* c, int32_t row, double n_star, double z_from, double z_to, int64_t* count,
+                      double* length) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (!count) return fail(LBM_EINVAL, "count is NULL");
+  if (row < 0 || row >= c->p.nr) return fail(LBM_EINVAL, "row out of range");
+  if (!(n_star > 0.0) || !std::isfinite(n_star)) return fail(LBM_EINVAL, "n_star must be positive");
+  if (std::isnan(z_from) || std::isnan(z_to)) return fail(LBM_EINVAL, "z range is NaN");
+  long long* d = (long long*)c->red_out();
+  HIP_CHECK(lbm::launch_bubble(c->storage, c->p, c->s, c->M(c->cur), row, n_star, z_from, z_to, d, c->stream),
+            "bubble launch");
+  long long h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  *count = h;
+  if (length) *length = (double)h * c->p.h;
+  return LBM_OK;
+}
+
 int lbm_counters(lbm_ctx* c, int64_t* step, int64_t* shifts) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (step) *step = c->k;

@@ -67,6 +67,9 @@ struct AdjArgs {
 
 // Launchers (defined in lbm_kernels.hip / lbm_adjoint.hip).  storage: 0 F64, 1 F32, 2 F16.
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st);
+// Bubble length count of one row (single block) into *out (device).
+hipError_t launch_bubble(int storage, const Physics& p, long long s, const void* M, int row, double n_star,
+                         double z0, double z1, long long* out, hipStream_t st);
 hipError_t launch_init_fluid(int storage, const Physics& p, const double* n_pert,
                              const double* p_init, void* g, void* M, hipStream_t st);
 hipError_t launch_init_fields(int storage, const Physics& p, void* E, hipStream_t st);

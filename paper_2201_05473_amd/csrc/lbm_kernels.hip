@@ -614,6 +614,33 @@ __global__ __launch_bounds__(RED_THREADS) void diag_final_kernel(const double* p
   block_reduce5(v, out);
 }
 
+// Bubble length (Sec. IV, Fig. 4): the sites of row `row` at lab positions z in [z0, z1] whose
+// electron density is below n_star times the local background (vacuum sites excluded).  One
+// block counts the whole row (an integer count: no atomics, exact).
+template <int ST>
+__global__ __launch_bounds__(RED_THREADS) void bubble_kernel(Physics p, long long s, const void* Mv, int row,
+                                                            double n_star, double z0, double z1,
+                                                            long long* out) {
+  using A = typename Mode<ST, false>::A;
+  const A* M = (const A*)Mv;
+  long long cnt = 0;
+  for (int i = threadIdx.x; i < p.nz; i += RED_THREADS) {
+    const double z = (double)(s + i) * p.h;
+    const double nb = nbg(p, z);
+    const double n = (double)M[(long long)row * p.pitch + i] + nb;
+    cnt += (z >= z0 && z <= z1 && nb > 0.0 && n < n_star * nb) ? 1 : 0;
+  }
+  __shared__ long long red[RED_THREADS / 64];
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+    *out = t;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------------
@@ -641,6 +668,12 @@ hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
   else if (storage == 1) launch_step_t<1, false>(a, grid, st);
   else if (a.p.fp64_math) launch_step_t<2, true>(a, grid, st);
   else launch_step_t<2, false>(a, grid, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_bubble(int storage, const Physics& p, long long s, const void* M, int row, double n_star,
+                         double z0, double z1, long long* out, hipStream_t st) {
+  LBM_DISPATCH(storage, bubble_kernel, dim3(1), dim3(RED_THREADS), st, p, s, M, row, n_star, z0, z1, out);
   return hipGetLastError();
 }
 

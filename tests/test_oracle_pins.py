@@ -439,3 +439,33 @@ def test_table1_gain_column():
         t = json.load(fh)
     for f, l, gain in zip(t["fct_ks"], t["lbm_ks"], t["gain_percent"]):
         assert abs(U.gain_percent(f, l) - gain) < 0.01
+
+
+# --- bubble length (Sec. IV, Fig. 4; reading R28) -----------------------------------------------
+
+def test_bubble_length_counts_depleted_sites_by_hand():
+    """A hand-made density row: 7 sites clearly below n* n_bg, one exactly at it (not counted),
+    ramp sites in vacuum (n_bg = 0, not counted), and a z-range that cuts the depleted region."""
+    cfg = wl.config(None, nz=40, nr=4, dz=0.1, dr=0.1, ramp_kind=1, ramp_start=0.5, ramp_len=0.5, n0=2.0)
+    P = O.Params(cfg)
+    z = torch.arange(40, dtype=torch.float64) * 0.1
+    nbg = O.n_background(z, P)
+    n = nbg.repeat(4, 1).clone()
+    assert float(nbg[4]) == 0.0 and float(nbg[12]) == 2.0
+    n[1, 20:27] = 0.5 * nbg[20:27]               # depleted: 7 sites
+    n[1, 27] = 0.95 * nbg[27]                    # exactly at the threshold: not counted
+    n[1, 0:5] = -1.0                             # below threshold but in vacuum: not counted
+    n[2, 10:30] = 0.0                            # another row: not counted on row 1
+    assert O.bubble_length(n, 0, P, row=1) == (7, 7 * 0.1)
+    assert O.bubble_length(n, 0, P, row=1, z_from=2.25, z_to=2.55)[0] == 3   # sites 23, 24, 25
+    assert O.bubble_length(n, 0, P, row=2)[0] == 20
+    # the window shift moves the lab positions: with s = 10 the depleted sites sit in n0 plasma
+    assert O.bubble_length(n, 10, P, row=1, z_from=3.0)[0] == 7
+
+
+def test_bubble_length_of_a_uniform_rest_plasma_is_zero():
+    cfg = wl.config(None, nz=30, nr=5, dz=0.05)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    n = O.moments_out(S, P)[0]
+    assert O.bubble_length(n, 0, P, row=0)[0] == 0
