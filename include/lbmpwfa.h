@@ -49,6 +49,19 @@ enum {
  * w_i n_bg(z); diagnostics are always accumulated in FP64. */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
 
+/* Collision operator of the three lattices.  The paper uses BGK (Eq. (7)) and notes (Sec. IV)
+ * that BGK is the simplest choice and that other collision operators may stabilise the
+ * non-linear regime.  Two are offered, each relaxing toward the equilibrium of Eq. (9), with the
+ * source of Eq. (10) added unchanged:
+ *   LBM_BGK  Eq. (7): one relaxation time tau for every population.
+ *   LBM_TRT  two relaxation times: the part of f - f_eq that is even under xi -> -xi (pairs of
+ *            opposite directions) relaxes with tau_plus, the odd part with tau.
+ *   LBM_REG  regularised BGK: before relaxing with tau, f - f_eq is replaced by its projection
+ *            on the first-order Hermite polynomials, w_i xi_i . j_neq / c_s^2 with
+ *            j_neq = sum_i xi_i (f_i - f_eq_i); every non-equilibrium moment above the first is
+ *            dropped. */
+enum { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2 };
+
 /* Run configuration.  Physical meaning (normalised units):
  *   nz, nr        grid size (both >= 3)
  *   dz, dr        cell size; must be equal (the D2Q9 lattice is square)
@@ -70,7 +83,12 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
  *   check_every   > 0: every that many steps lbm_step synchronises and checks for non-finite
  *                 values (LBM_EUNSTABLE); 0: no checks
  *   fp64_math     1: FP64 arithmetic in the step for FP32 / FP16 storage (storage unchanged);
- *                 0: arithmetic in FP32.  Ignored for LBM_F64 (always FP64). */
+ *                 0: arithmetic in FP32.  Ignored for LBM_F64 (always FP64).
+ *   collision     LBM_BGK, LBM_TRT or LBM_REG (below).  All three conserve A + dt F and relax
+ *                 the first moment with 1/tau, so D of Eq. (12) is the same for all three
+ *   trt_magic     LBM_TRT only: Lambda = (tau_plus - 1/2)(tau - 1/2) > 0, which fixes the
+ *                 relaxation time tau_plus of the symmetric part; Lambda = (tau - 1/2)^2 is BGK.
+ *                 Ignored otherwise. */
 typedef struct {
   int32_t nz, nr;
   double dz, dr, c_dt_over_dz, tau;
@@ -83,6 +101,8 @@ typedef struct {
   double n_floor;
   int32_t check_every;
   int32_t fp64_math;
+  int32_t collision;
+  double trt_magic;
 } lbm_config;
 
 /* FP64 diagnostics of the current state (all sums over the window):

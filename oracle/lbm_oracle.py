@@ -53,6 +53,17 @@ Readings of the paper (where it is silent, garbled or inconsistent; each is list
   R23 Ramp shapes: linear n0 clamp((z - z_p)/L, 0, 1) and tanh n0 (1 + tanh(2 (z - z_p)/L - 1)) / 2.
   R28 Bubble length (Sec. IV, Fig. 4): sites of one row, in a given lab z-range, whose density is
       below n* = 0.95 times the local background (vacuum sites excluded), times dz.
+  R29 Collision operators other than BGK (Sec. IV names BGK as the simplest choice and leaves
+      others to future work without naming one).  Two are offered; both keep the equilibrium of
+      Eq. (9) and add the source of Eq. (10) unchanged after relaxing:
+        TRT  two relaxation times: the non-equilibrium part f - f_eq is split into its even and
+             odd parts under xi -> -xi; the odd part (which carries the flux, hence D) relaxes
+             with tau, the even part with tau_plus = 1/2 + Lambda / (tau - 1/2) for a given
+             Lambda (Lambda = (tau - 1/2)^2 gives BGK back);
+        REG  regularised BGK for an advected scalar: f - f_eq is replaced by its first-order
+             Hermite projection w_i xi_i . j_neq / c_s^2, j_neq = sum_i xi_i (f_i - f_eq_i),
+             before relaxing with tau (every non-equilibrium moment above the first is dropped).
+      Both relax the first moment exactly as BGK does, so D of Eq. (12) is unchanged.
 
 State after k completed steps (k = 0 is the initial state):
     g  [3][9][nr][nz]   post-collision populations of step k-1 (raw values, not deviations)
@@ -80,6 +91,10 @@ DT = torch.float64
 XI = ((0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1))
 W = (4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
      1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0)
+# Index of the opposite direction, xi_{OPP[q]} = -xi_q.
+OPP = tuple(XI.index((-xz, -xr)) for (xz, xr) in XI)
+# Collision operators (R29).
+BGK, TRT, REG = 0, 1, 2
 # Mirror parity of (n, n p_z, n p_r) across the axis r = 0 (R11).
 PARITY = (1.0, 1.0, -1.0)
 
@@ -106,6 +121,15 @@ class Params:
             raise ValueError("tau must exceed 1/2")
         # Eq. (12) in lattice units, converted to normalised units: D = (tau - 1/2)/3 dz^2/dt.
         self.D = (self.tau - 0.5) / 3.0 * self.h * self.h / self.dt
+        self.collision = int(cfg.get("collision", BGK))
+        if self.collision not in (BGK, TRT, REG):
+            raise ValueError("unknown collision operator")
+        self.tau_plus = self.tau
+        if self.collision == TRT:
+            magic = float(cfg.get("trt_magic", 0.25))
+            if not magic > 0.0:
+                raise ValueError("the TRT parameter Lambda must be positive")
+            self.tau_plus = 0.5 + magic / (self.tau - 0.5)
         self.window = bool(cfg.get("moving_window", 0))
         per = int(cfg.get("periodic", 0))
         self.per_z, self.per_r = bool(per & 1), bool(per & 2)
@@ -183,6 +207,27 @@ def equilibrium(A, uz, ur):
         cu = xz * uz + xr * ur
         out.append(w * A * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq))
     return torch.stack(out)
+
+
+def collide(f, feq, P: Params):
+    """Relaxation of [9][...] populations f toward feq, without the source: Eq. (7) (BGK) or one
+    of the operators of reading R29."""
+    neq = f - feq
+    if P.collision == BGK:
+        return f - neq / P.tau
+    if P.collision == TRT:
+        mirrored = neq[list(OPP)]
+        even = 0.5 * (neq + mirrored)
+        odd = 0.5 * (neq - mirrored)
+        return f - even / P.tau_plus - odd / P.tau
+    # REG: keep only the first-order Hermite part of neq, w_i xi_i . j_neq / c_s^2 (c_s^2 = 1/3)
+    shape = (9,) + (1,) * (f.dim() - 1)
+    xz = torch.tensor([x[0] for x in XI], dtype=DT).reshape(shape)
+    xr = torch.tensor([x[1] for x in XI], dtype=DT).reshape(shape)
+    w = torch.tensor(W, dtype=DT).reshape(shape)
+    jz = (xz * neq).sum(dim=0)
+    jr = (xr * neq).sum(dim=0)
+    return feq + (1.0 - 1.0 / P.tau) * 3.0 * w * (xz * jz + xr * jr)
 
 
 def velocity(M, P: Params):
@@ -338,8 +383,8 @@ def fluid_update(g, Mp, Ebar_z, Ebar_r, Bbar, P: Params):
     gnew, Mnew = [], []
     for kk in range(3):
         feq = equilibrium(A[kk], uz, ur)
-        # Eq. (7) BGK relaxation plus the source of Eq. (10) per step (R5)
-        gnew.append(f[kk] - (f[kk] - feq) / P.tau + w * P.dt * F[kk])
+        # Eq. (7) BGK relaxation (or R29) plus the source of Eq. (10) per step (R5)
+        gnew.append(collide(f[kk], feq, P) + w * P.dt * F[kk])
         Mnew.append(A[kk] + P.dt * F[kk])
     return torch.stack(gnew), torch.stack(Mnew)
 

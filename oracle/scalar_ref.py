@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (pin "brute force": the vectorised oracle in lbm_oracle
 with this loop-by-loop version to round-off).  Everything here is plain Python floats, one site
 and one population at a time, with the boundary rules written as explicit per-position
 functions instead of padded arrays.  The definitions are the same ones listed in the header of
-lbm_oracle.py (Eqs. (4)-(14) of the paper plus readings R1-R23).
+lbm_oracle.py (Eqs. (4)-(14) of the paper plus readings R1-R23 and R29).
 """
 from __future__ import annotations
 
@@ -22,6 +22,10 @@ class Grid:
         self.dt = self.lam * self.h
         self.tau = float(cfg["tau"])
         self.D = (self.tau - 0.5) / 3 * self.h ** 2 / self.dt
+        self.coll = int(cfg.get("collision", 0))          # 0 BGK, 1 TRT, 2 regularised (R29)
+        self.tau_p = self.tau
+        if self.coll == 1:
+            self.tau_p = 0.5 + float(cfg.get("trt_magic", 0.25)) / (self.tau - 0.5)
         self.window = bool(cfg.get("moving_window", 0))
         per = int(cfg.get("periodic", 0))
         self.pz, self.pr = bool(per & 1), bool(per & 2)
@@ -174,9 +178,21 @@ def step(G, st):
                 for kk in range(3):
                     F[kk] += -A[kk] * br / rj + G.D * (up[kk] - dn[kk]) / (2 * h) / rj
             for kk in range(3):
+                fe = [feq(q, A[kk], uz, ur) for q in range(9)]
+                neq = [f[kk][q] - fe[q] for q in range(9)]
+                jz = sum(XI[q][0] * neq[q] for q in range(9))
+                jr = sum(XI[q][1] * neq[q] for q in range(9))
                 for q in range(9):
-                    fe = feq(q, A[kk], uz, ur)
-                    gn[kk][q][j][i] = f[kk][q] - (f[kk][q] - fe) / G.tau + W[q] * dt * F[kk]
+                    if G.coll == 0:
+                        post = f[kk][q] - neq[q] / G.tau
+                    elif G.coll == 1:
+                        back = [p for p in range(9) if XI[p][0] == -XI[q][0] and XI[p][1] == -XI[q][1]][0]
+                        even = 0.5 * (neq[q] + neq[back])
+                        odd = 0.5 * (neq[q] - neq[back])
+                        post = f[kk][q] - even / G.tau_p - odd / G.tau
+                    else:
+                        post = fe[q] + (1 - 1 / G.tau) * 3 * W[q] * (XI[q][0] * jz + XI[q][1] * jr)
+                    gn[kk][q][j][i] = post + W[q] * dt * F[kk]
                 Mn[kk][j][i] = A[kk] + dt * F[kk]
     if G.window and (k + 1) % G.m == 0:
         nf = G.nbg((s + nz) * h)

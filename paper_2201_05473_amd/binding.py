@@ -37,6 +37,8 @@ class LbmConfig(ctypes.Structure):
         ("n_floor", c_double),
         ("check_every", c_int32),
         ("fp64_math", c_int32),
+        ("collision", c_int32),
+        ("trt_magic", c_double),
     ]
 
 

@@ -70,6 +70,8 @@ def test_printed_equilibrium_coefficients_violate_moments():
     dict(periodic=3, fields_on=0, cyl_on=0),
     dict(ramp_kind=2, ramp_start=0.1, ramp_len=0.2, moving_window=1),
     dict(ramp_kind=1, ramp_start=0.3, ramp_len=0.3, n_floor=1e-3),
+    dict(collision=1, trt_magic=0.1, moving_window=1),
+    dict(collision=2, ramp_kind=2, ramp_start=0.1, ramp_len=0.2),
 ])
 def test_brute_force_agreement(variant):
     cfg = wl.config(None, nz=8, nr=4, dz=0.1, dr=0.1, nb=0.3, sigma_z=0.2, sigma_r=0.15, zd0=0.4,
@@ -90,8 +92,9 @@ def test_brute_force_agreement(variant):
 # P_rest: a uniform plasma at rest with no driver is a fixed point (ghosts, axis, window)
 # ---------------------------------------------------------------------------------------------
 
-def test_rest_is_fixed_point():
-    cfg = wl.config(None, nz=32, nr=12, moving_window=1, n0=1.0, nb=0.0)
+@pytest.mark.parametrize("collision", [0, 1, 2])
+def test_rest_is_fixed_point(collision):
+    cfg = wl.config(None, nz=32, nr=12, moving_window=1, n0=1.0, nb=0.0, collision=collision)
     P = O.Params(cfg)
     S0 = O.initial_state(P)
     S = S0
@@ -174,11 +177,15 @@ def test_momentum_diffusion_wave(tau):
 # P_D: diffusivity of Eq. (12) from the variance growth of a bump (Cartesian, fields off)
 # ---------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("tau", [0.6, 0.8])
-def test_diffusivity(tau):
+@pytest.mark.parametrize("tau,collision,magic", [(0.6, 0, 0.25), (0.8, 0, 0.25), (0.6, 1, 0.25),
+                                                 (0.8, 1, 1.0 / 12.0), (0.6, 2, 0.25)])
+def test_diffusivity(tau, collision, magic):
+    """For TRT and the regularised operator (R29) D depends on tau alone: with tau = 0.6 and
+    Lambda = 1/4 the even rate is tau_plus = 3, which would give a five times larger D if the two
+    rates were swapped."""
     n = 96
     cfg = wl.config(None, nz=n, nr=n, dz=0.05, dr=0.05, periodic=3, fields_on=0, cyl_on=0,
-                    nb=0.0, tau=tau)
+                    nb=0.0, tau=tau, collision=collision, trt_magic=magic)
     P = O.Params(cfg)
     zc, rc = 48 * 0.05, 48.5 * 0.05
     S = O.initial_state(P, wl.gaussian_bump(cfg, 0.1, 0.2, 0.2, zc=zc, rc=rc))
@@ -469,3 +476,79 @@ def test_bubble_length_of_a_uniform_rest_plasma_is_zero():
     S = O.initial_state(P)
     n = O.moments_out(S, P)[0]
     assert O.bubble_length(n, 0, P, row=0)[0] == 0
+
+
+# --- collision operators other than BGK (Sec. IV remark; reading R29) ---------------------------
+
+def _moments9(f):
+    """The nine D2Q9 moments of [9][...] populations: A, j_z, j_r, Pi_zz, Pi_rr, Pi_zr, q_z, q_r, m4
+    (q_z = sum xi_z xi_r^2 f, q_r = sum xi_r xi_z^2 f, m4 = sum xi_z^2 xi_r^2 f); they determine f."""
+    out = []
+    for a, b in ((0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (1, 2), (2, 1), (2, 2)):
+        out.append(sum((xz ** a) * (xr ** b) * f[q] for q, (xz, xr) in enumerate(O.XI)))
+    return torch.stack(out)
+
+
+@pytest.mark.parametrize("collision", [0, 1, 2])
+def test_collision_relaxes_each_moment_at_its_rate(collision):
+    """Spatially uniform random populations on a doubly periodic lattice with fields and sources
+    off: streaming is the identity, so one step is one collision.  The moment-space statement of
+    each operator: BGK relaxes all eight non-conserved moments with 1/tau; TRT relaxes the odd
+    ones (j, q) with 1/tau and the even ones (Pi, m4) with 1/tau_plus; the regularised operator
+    relaxes j with 1/tau, sets Pi and m4 to equilibrium and sets q to q_eq + (1 - 1/tau) j_neq / 3
+    (the q-moment of the first-order Hermite term, since sum w xi_z^2 xi_r^2 = 1/9)."""
+    tau, magic = 0.7, 0.09
+    cfg = wl.config(None, nz=3, nr=3, periodic=3, fields_on=0, cyl_on=0, tau=tau,
+                    collision=collision, trt_magic=magic)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    gen = torch.Generator().manual_seed(11)
+    g0 = (0.05 + torch.rand(3, 9, dtype=F64, generator=gen))[:, :, None, None].expand(3, 9, 3, 3)
+    S.g = g0.reshape(27, 3, 3).clone().reshape(S.g.shape)
+    S.M = g0.sum(1).clone()
+    S1 = O.step(S, P)
+    g1 = S1.g.reshape(3, 9, 3, 3)
+    tau_p = 0.5 + magic / (tau - 0.5) if collision == 1 else tau
+    for kk in range(3):
+        m0 = _moments9(g0[kk])
+        A = [g0[c].sum(0) for c in range(3)]
+        bz, br, _ = O.velocity(torch.stack(A), P)
+        meq = _moments9(O.equilibrium(m0[0], P.lam * bz, P.lam * br))
+        m1 = _moments9(g1[kk])
+        expect = m0.clone()
+        odd, even = [1, 2, 6, 7], [3, 4, 5, 8]
+        if collision == 2:
+            expect[1:3] = m0[1:3] - (m0[1:3] - meq[1:3]) / tau
+            expect[even] = meq[even]
+            expect[6:8] = meq[6:8] + (1 - 1 / tau) * (m0[1:3] - meq[1:3]) / 3
+        else:
+            expect[odd] = m0[odd] - (m0[odd] - meq[odd]) / tau
+            expect[even] = m0[even] - (m0[even] - meq[even]) / tau_p
+        assert float((m1 - expect).abs().max()) < 1e-14, (kk, m1 - expect)
+        # the test is not vacuous: the populations were far from equilibrium
+        assert float((m0[3:] - meq[3:]).abs().max()) > 0.05
+
+
+def test_trt_with_lambda_of_bgk_is_bgk():
+    """Lambda = (tau - 1/2)^2 makes tau_plus = tau: TRT must then reproduce BGK over a coupled,
+    driven, windowed run."""
+    tau = 0.7
+    base = dict(nz=40, nr=10, dz=0.05, dr=0.05, nb=0.8, sigma_z=0.3, sigma_r=0.3, zd0=1.5, tau=tau,
+                moving_window=1, noise_amp=0.02, seed=5)
+    cfg_b = wl.config(None, **base)
+    cfg_t = wl.config(None, collision=1, trt_magic=(tau - 0.5) ** 2, **base)
+    Sb, _ = _run(cfg_b, 30, wl.density_perturbation(cfg_b))
+    St, _ = _run(cfg_t, 30, wl.density_perturbation(cfg_t))
+    for a, b in ((Sb.g, St.g), (Sb.M, St.M), (Sb.Ez, St.Ez), (Sb.B, St.B)):
+        assert float((a - b).abs().max()) < 1e-13 * max(1.0, float(a.abs().max()))
+    cfg_o = wl.config(None, collision=1, trt_magic=0.25, **base)
+    So, _ = _run(cfg_o, 30, wl.density_perturbation(cfg_o))
+    assert float((Sb.g - So.g).abs().max()) > 1e-6
+
+
+def test_collision_operators_conserve_per_site():
+    for collision in (1, 2):
+        cfg = wl.config(None, nz=24, nr=10, nb=0.4, sigma_z=0.3, sigma_r=0.3, zd0=0.6, noise_amp=0.01,
+                        seed=4, moving_window=1, collision=collision)
+        S, _ = _run(cfg, 9, wl.density_perturbation(cfg), wl.random_momentum(cfg, 0.1))
+        assert float((S.g.sum(1) - S.M).abs().max()) < 1e-14

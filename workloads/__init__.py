@@ -28,6 +28,7 @@ import copy
 import numpy as np
 
 F64, F32, F16 = 0, 1, 2
+BGK, TRT, REG = 0, 1, 2
 
 # Field names and order of the C configuration struct (see include/lbmpwfa.h).
 CONFIG_FIELDS = (
@@ -35,6 +36,7 @@ CONFIG_FIELDS = (
     "moving_window", "periodic", "fields_on", "cyl_on",
     "n0", "ramp_kind", "ramp_start", "ramp_len",
     "nb", "sigma_z", "sigma_r", "zd0", "n_floor", "check_every", "fp64_math",
+    "collision", "trt_magic",
 )
 
 _BASE = dict(
@@ -42,6 +44,7 @@ _BASE = dict(
     moving_window=0, periodic=0, fields_on=1, cyl_on=1,
     n0=1.0, ramp_kind=0, ramp_start=0.0, ramp_len=1.0,
     nb=0.0, sigma_z=0.5, sigma_r=0.5, zd0=0.0, n_floor=1e-10, check_every=0, fp64_math=0,
+    collision=0, trt_magic=0.25,
     # workload-level fields (not part of the C struct)
     noise_amp=0.0, seed=0, nsteps=1, z_behind=4.0,
 )
