@@ -338,8 +338,11 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
         part[0] += sum * dl;
         part[1] += sum * dn;
         if (a.shift) {
-          // the new front column of x^{k+1} (output index nz - 1): w_q n_bg and n_bg
-          double s2 = (double)(L + 27 * plane)[j * pitch + (nz - 1)];
+          // the new front column of x^{k+1} (output index nz - 1): w_q n_bg and n_bg.  Its moment
+          // adjoint M_bar^{k+1} is read here only in the split form; in the fused form it is made
+          // in the same launch, possibly by another block, so the thread that makes it adds its
+          // term (adj_fused_kernel)
+          double s2 = mreg ? 0.0 : (double)(L + 27 * plane)[j * pitch + (nz - 1)];
 #pragma unroll
           for (int q = 0; q < 9; ++q) {
             int yi = nz - 1, yj = j;
@@ -694,6 +697,15 @@ __global__ __launch_bounds__(NTHREADS) void adj_fused_kernel(AdjArgs ac, AdjArgs
   const int o0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
   double part[4] = {0.0, 0.0, 0.0, 0.0}, mb[3];
   cell_body<ST>(ac, o0, j0, part, mb);
+  const Physics& p = ac.p;
+  if (p.window && as.shift && o0 + (int)threadIdx.x % TZ == p.nz - 1 && j0 + (int)threadIdx.x / TZ < p.nr) {
+    // this cell is the front column that step k - 1's window shift created (density n_bg):
+    // the moment-adjoint part of its theta partial (the population part is in site_body)
+    double dl, dn;
+    dnbg(p, (double)(as.s + p.nz) * p.h, dl, dn);
+    part[0] += mb[0] * dl;
+    part[1] += mb[0] * dn;
+  }
   site_body<ST>(as, o0 + as.shift, j0, mb, part);
   block_sum4(part, as.partials + (long long)blockIdx.x * 4);
 }
