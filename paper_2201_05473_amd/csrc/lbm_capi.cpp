@@ -77,6 +77,10 @@ int validate(const lbm_config* c, Physics* p) {
   if (!(c->n_floor >= 0.0)) return fail(LBM_EINVAL, "n_floor must be >= 0");
   if (c->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
   if (c->fp64_math != 0 && c->fp64_math != 1) return fail(LBM_EINVAL, "fp64_math must be 0 or 1");
+  if (c->collision != LBM_BGK && c->collision != LBM_TRT && c->collision != LBM_REG)
+    return fail(LBM_EINVAL, "unknown collision operator %d", c->collision);
+  if (c->collision == LBM_TRT && !(c->trt_magic > 0.0 && std::isfinite(c->trt_magic)))
+    return fail(LBM_EINVAL, "trt_magic must be positive and finite (got %g)", c->trt_magic);
   if (p) {
     Physics& q = *p;
     std::memset(&q, 0, sizeof q);
@@ -105,6 +109,8 @@ int validate(const lbm_config* c, Physics* p) {
     q.fields_on = c->fields_on ? 1 : 0;
     q.cyl_on = c->cyl_on ? 1 : 0;
     q.fp64_math = c->fp64_math;
+    q.coll = c->collision;
+    q.tau_plus = c->collision == LBM_TRT ? 0.5 + c->trt_magic / (c->tau - 0.5) : c->tau;
   }
   return LBM_OK;
 }
@@ -495,6 +501,7 @@ int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
   if (bytes < need) return fail(LBM_ENOMEM, "adjoint workspace too small: %zu < %zu bytes", bytes, need);
   if ((c->p.per_z && c->p.nz < 5) || (c->p.per_r && c->p.nr < 5))
     return fail(LBM_EINVAL, "the adjoint needs at least 5 cells along periodic dimensions");
+  if (c->p.coll != LBM_BGK) return fail(LBM_EINVAL, "the adjoint is implemented for the BGK collision only");
   return LBM_OK;
 }
 

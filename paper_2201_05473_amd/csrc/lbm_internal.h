@@ -26,6 +26,8 @@ struct Physics {
   double nb, sigma_z, sigma_r, zd0;
   int window, m, per_z, per_r, fields_on, cyl_on;
   int fp64_math;            // FP64 arithmetic for FP32 / FP16 storage
+  int coll;                 // collision operator: 0 BGK, 1 TRT, 2 regularised
+  double tau_plus;          // TRT: relaxation time of the even part (tau otherwise)
 };
 
 // One launch of the fused step: physics + time counters + buffers.

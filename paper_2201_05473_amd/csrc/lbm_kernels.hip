@@ -1,7 +1,7 @@
 // HIP kernels (gfx950) of the lattice-Boltzmann plasma-wakefield step.
 //
 // One launch per time step: the fused kernel first advances the Yee fields of its tile (plus a
-// one-cell halo, recomputed from LDS) and then performs the pull-stream / BGK collision of the
+// one-cell halo, recomputed from LDS) and then performs the pull-stream / collision (BGK, or TRT or regularised) of the
 // three D2Q9 lattices of its sites.  Notation and step order follow the paper (Parise et al.,
 // arXiv:2201.05473): Eq. (5) for the fields, Eqs. (6)-(10), (13), (14) for the lattices; the
 // readings where the paper is silent are stated at each use.
@@ -22,7 +22,7 @@ namespace lbm {
 // phase can wait for the halo loads alone while the population loads stay in flight across the
 // LDS barriers (which only wait for LDS traffic).
 // ------------------------------------------------------------------------------------------
-template <int ST, bool FIELDS, bool M64, bool SITE>
+template <int ST, bool FIELDS, bool M64, bool SITE, int COLL>
 __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using S = typename Mode<ST, M64>::S;
   using C = typename Mode<ST, M64>::C;
@@ -360,20 +360,97 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     F2 += (-A2 * br + Dc * (C)(sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1])) * ir;
   }
 
-  // Eqs. (7), (9), (10): BGK toward the equilibrium (standard D2Q9 coefficients) plus w_q dt F
+  // Eqs. (7), (9), (10): relaxation toward the equilibrium (standard D2Q9 coefficients) plus
+  // w_q dt F.  The equilibrium of direction q splits into a part even under xi -> -xi,
+  // w (A (1 + 4.5 cu^2 - 1.5 u^2)), and an odd part, w A 3 cu (lattice 0 as the deviation).
   const C itau = (C)(1.0 / p.tau);
+  if (COLL == 0) {
+    // BGK, Eq. (7)
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const C w = WQ<C>(q);
-    const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
-    const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
-    const C e0 = w * (dA0 + A0 * Q);
-    const C e1 = w * A1 * (C(1) + Q);
-    const C e2 = w * A2 * (C(1) + Q);
-    const C wdt = w * dtc;
-    stv(gout + q * plane + oo32, f0[q] - (f0[q] - e0) * itau + wdt * F0);
-    stv(gout + (9 + q) * plane + oo32, f1[q] - (f1[q] - e1) * itau + wdt * F1);
-    stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+    for (int q = 0; q < 9; ++q) {
+      const C w = WQ<C>(q);
+      const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+      const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
+      const C e0 = w * (dA0 + A0 * Q);
+      const C e1 = w * A1 * (C(1) + Q);
+      const C e2 = w * A2 * (C(1) + Q);
+      const C wdt = w * dtc;
+      stv(gout + q * plane + oo32, f0[q] - (f0[q] - e0) * itau + wdt * F0);
+      stv(gout + (9 + q) * plane + oo32, f1[q] - (f1[q] - e1) * itau + wdt * F1);
+      stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+    }
+  } else if (COLL == 1) {
+    // two relaxation times: the even part of f - f_eq relaxes with 1/tau_plus, the odd part
+    // (which carries the flux and so sets D) with 1/tau.  The rest population is even.
+    const C itp = (C)(1.0 / p.tau_plus);
+    {
+      const C w = WQ<C>(0), wdt = w * dtc, Q = C(-1.5) * usq;
+      stv(gout + oo32, f0[0] - (f0[0] - w * (dA0 + A0 * Q)) * itp + wdt * F0);
+      stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - w * A1 * (C(1) + Q)) * itp + wdt * F1);
+      stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - w * A2 * (C(1) + Q)) * itp + wdt * F2);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = t < 2 ? 1 + t : 5 + (t - 2);   // 1, 2, 5, 6
+      const int b = t < 2 ? 3 + t : 7 + (t - 2);   // their opposites 3, 4, 7, 8
+      const C w = WQ<C>(q), wdt = w * dtc;
+      const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+      const C ev = C(4.5) * cu * cu - C(1.5) * usq;
+      const C od = C(3) * cu;
+      {
+        const C re = (C(0.5) * (f0[q] + f0[b]) - w * (dA0 + A0 * ev)) * itp;
+        const C ro = (C(0.5) * (f0[q] - f0[b]) - w * A0 * od) * itau;
+        stv(gout + q * plane + oo32, f0[q] - re - ro + wdt * F0);
+        stv(gout + b * plane + oo32, f0[b] - re + ro + wdt * F0);
+      }
+      {
+        const C re = (C(0.5) * (f1[q] + f1[b]) - w * A1 * (C(1) + ev)) * itp;
+        const C ro = (C(0.5) * (f1[q] - f1[b]) - w * A1 * od) * itau;
+        stv(gout + (9 + q) * plane + oo32, f1[q] - re - ro + wdt * F1);
+        stv(gout + (9 + b) * plane + oo32, f1[b] - re + ro + wdt * F1);
+      }
+      {
+        const C re = (C(0.5) * (f2[q] + f2[b]) - w * A2 * (C(1) + ev)) * itp;
+        const C ro = (C(0.5) * (f2[q] - f2[b]) - w * A2 * od) * itau;
+        stv(gout + (18 + q) * plane + oo32, f2[q] - re - ro + wdt * F2);
+        stv(gout + (18 + b) * plane + oo32, f2[b] - re + ro + wdt * F2);
+      }
+    }
+  } else {
+    // regularised: f - f_eq is replaced by its first-order Hermite projection
+    // w xi . j_neq / c_s^2, j_neq = sum xi f - A u (the first moment of f_eq is A u), then
+    // relaxed with 1/tau; every non-equilibrium moment above the first is dropped
+    C jz0 = C(0), jr0 = C(0), jz1 = C(0), jr1 = C(0), jz2 = C(0), jr2 = C(0);
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (XZ(q) != 0) {
+        jz0 += (C)XZ(q) * f0[q];
+        jz1 += (C)XZ(q) * f1[q];
+        jz2 += (C)XZ(q) * f2[q];
+      }
+      if (XR(q) != 0) {
+        jr0 += (C)XR(q) * f0[q];
+        jr1 += (C)XR(q) * f1[q];
+        jr2 += (C)XR(q) * f2[q];
+      }
+    }
+    const C k3 = C(3) * (C(1) - itau);
+    jz0 = k3 * (jz0 - A0 * uz);
+    jr0 = k3 * (jr0 - A0 * ur);
+    jz1 = k3 * (jz1 - A1 * uz);
+    jr1 = k3 * (jr1 - A1 * ur);
+    jz2 = k3 * (jz2 - A2 * uz);
+    jr2 = k3 * (jr2 - A2 * ur);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const C w = WQ<C>(q), wdt = w * dtc;
+      const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+      const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
+      const C xz = (C)XZ(q), xr = (C)XR(q);
+      stv(gout + q * plane + oo32, w * (dA0 + A0 * Q + xz * jz0 + xr * jr0) + wdt * F0);
+      stv(gout + (9 + q) * plane + oo32, w * (A1 * (C(1) + Q) + xz * jz1 + xr * jr1) + wdt * F1);
+      stv(gout + (18 + q) * plane + oo32, w * (A2 * (C(1) + Q) + xz * jz2 + xr * jr2) + wdt * F2);
+    }
   }
   stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
   stv(Mout + plane + oo, A1 + dtc * F1);
@@ -653,11 +730,19 @@ __global__ __launch_bounds__(RED_THREADS) void bubble_kernel(Physics p, long lon
 
 static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
 
+template <int ST, bool M64, int COLL>
+static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
+  if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else step_kernel<ST, false, M64, false, COLL><<<grid, dim3(NTHREADS), 0, st>>>(a);
+}
+
+// The site-field variant (used by the adjoint, which is BGK only) exists for BGK alone.
 template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
-  if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (a.p.fields_on) step_kernel<ST, true, M64, false><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else step_kernel<ST, false, M64, false><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  if (a.p.coll == 1) launch_step_c<ST, M64, 1>(a, grid, st);
+  else if (a.p.coll == 2) launch_step_c<ST, M64, 2>(a, grid, st);
+  else if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else launch_step_c<ST, M64, 0>(a, grid, st);
 }
 
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {

@@ -66,12 +66,19 @@ def test_struct_layout_matches_c(lib, tmp_path):
     dict(nz=2), dict(nr=2), dict(ramp_kind=1, ramp_len=0.0), dict(ramp_kind=3),
     dict(periodic=1, moving_window=1), dict(periodic=2), dict(moving_window=1, c_dt_over_dz=0.3),
     dict(storage=3), dict(nb=0.1, sigma_z=0.0), dict(n_floor=-1.0), dict(check_every=-1),
+    dict(collision=3), dict(collision=-1), dict(collision=1, trt_magic=0.0),
+    dict(collision=1, trt_magic=float("inf")),
 ])
 def test_invalid_configs_rejected(lib, bad):
     with pytest.raises(lib.LbmError) as ei:
         lib.lbm_workspace_bytes(wl.config(None, **bad))
     assert ei.value.code == lib.LBM_EINVAL
     assert lib.lbm_last_error() != ""
+
+
+def test_trt_magic_ignored_by_other_operators(lib):
+    for coll in (0, 2):
+        assert lib.lbm_workspace_bytes(wl.config(None, collision=coll, trt_magic=0.0)) > 0
 
 
 def test_workspace_size_scales_with_storage(lib):

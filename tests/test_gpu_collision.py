@@ -1,0 +1,156 @@
+"""GPU parity of the collision operators other than BGK (reading R29: two relaxation times, and
+the regularised operator) against the FP64 oracle, through the C ABI, and their rejection by the
+adjoint, which is implemented for BGK only.
+
+FP64 storage matches to 1e-10 (max-norm per state group, as for BGK); FP32 and FP16 storage use
+the bounds stated at the test.  tau = 0.7 so that the TRT even rate differs from the odd one
+(Lambda = 1/4: tau_plus = 1.75; Lambda = 1/12: tau_plus = 0.917).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import lbm_oracle as O
+from test_gpu_parity import TOL64, comp_errors, oracle_state, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2201_05473_amd import load_library
+    load_library()
+
+
+COLLISIONS = {
+    "trt_quarter": dict(collision=wl.TRT, trt_magic=0.25),
+    "trt_twelfth": dict(collision=wl.TRT, trt_magic=1.0 / 12.0),
+    "regularised": dict(collision=wl.REG),
+}
+VARIANTS = {
+    "window": dict(moving_window=1),
+    "periodic_z": dict(periodic=1),
+    "periodic_zr_cartesian": dict(periodic=3, fields_on=0, cyl_on=0),
+    "tanh_window": dict(ramp_kind=2, ramp_start=3.0, ramp_len=2.0, moving_window=1),
+    "linear_vacuum_floor": dict(ramp_kind=1, ramp_start=4.5, ramp_len=1.5, moving_window=1, n_floor=1e-8),
+}
+
+
+@pytest.mark.parametrize("var", list(VARIANTS))
+@pytest.mark.parametrize("coll", list(COLLISIONS))
+def test_fp64_parity(coll, var):
+    """150 x 13 (three 64-wide tiles with a ragged tail, four 4-row tiles with a ragged tail),
+    27 steps, driver, noise and random initial momentum: every state value."""
+    cfg = wl.config(None, nz=150, nr=13, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3,
+                    zd0=5.0, noise_amp=1e-3, seed=11, storage=wl.F64, tau=0.7,
+                    **COLLISIONS[coll], **VARIANTS[var])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=3)
+    print(f"[collision fp64 parity] {coll} {var} 150x13, 27 steps", flush=True)
+    lat = run_gpu(cfg, 27, pert, pinit)
+    st, k, s = lat.state()
+    S, P = O.run(cfg, 27, pert, pinit)
+    assert (k, s) == (S.k, S.s)
+    errs = comp_errors(st, oracle_state(S, P))
+    assert errs.max() < TOL64, (errs.argmax(), errs.max())
+    lat.close()
+
+
+@pytest.mark.parametrize("coll", ["trt_quarter", "regularised"])
+def test_reduced_precision_parity_c2_copy(coll):
+    """C2's 512 x 128 copy with the plasma already around the driver, 400 steps: FP32 and FP16
+    storage against the FP64 oracle (max-norm relative error of n, E_z, E_r).
+
+    Bounds.  Density: those of the BGK test (1e-5 with FP32 arithmetic, 1e-7 with FP64
+    arithmetic).  Fields: on this case the FP32 storage of populations and fields alone puts the
+    E_z error near 1e-5, and where it lies depends on the operator (with FP64 arithmetic on FP32
+    storage, where the arithmetic adds nothing: BGK 9.9e-6, TRT 1.1e-5, regularised 1.7e-5).  So
+    the test takes that storage floor from the FP64-arithmetic run, bounds it by 3e-5, and bounds
+    the FP32-arithmetic field error by twice it (FP32 arithmetic may add at most the floor again;
+    measured: 1.0-1.45 times).  FP16: 5e-3 as for BGK."""
+    cfg64 = wl.config("C2s", **COLLISIONS[coll])
+    cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
+    S, P = O.run(cfg64, 400)
+    ref = {"n": S.M[0].numpy(), "Ez": S.Ez.numpy(), "Er": S.Er.numpy()}
+    errs = {}
+    for (storage, m64) in ((wl.F32, 0), (wl.F32, 1), (wl.F16, 0)):
+        print(f"[collision reduced precision] {coll} C2s storage={storage} fp64_math={m64}", flush=True)
+        lat = run_gpu(dict(cfg64, storage=storage, fp64_math=m64), 400)
+        st, _, _ = lat.state()
+        errs[(storage, m64)] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
+                                "Er": O.rel_err(st[31], ref["Er"])}
+        print(coll, storage, m64, errs[(storage, m64)], flush=True)
+        lat.close()
+    f32, floor, f16 = errs[(wl.F32, 0)], errs[(wl.F32, 1)], errs[(wl.F16, 0)]
+    assert f32["n"] < 1e-5 and floor["n"] < 1e-7, errs
+    for q in ("Ez", "Er"):
+        assert floor[q] < 3e-5, errs
+        assert f32[q] < 2.0 * floor[q], (q, errs)
+    assert max(f16.values()) < 5e-3, errs
+
+
+@pytest.mark.parametrize("coll", ["trt_quarter", "regularised"])
+def test_full_size_c2_single_step(coll):
+    """C2 at full size (2048 x 512, the benchmark's launch configuration), one step from the
+    initial state with a seeded density perturbation and momentum, so that the populations leave
+    equilibrium: FP64 to 1e-10, FP32 moments to 1e-6."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C2", storage=wl.F64, noise_amp=1e-2, seed=7, **COLLISIONS[coll])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=9)
+    S, P = O.run(cfg, 1, pert, pinit)
+    ref = oracle_state(S, P)
+    for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6)):
+        print(f"[collision full size] {coll} C2 storage={storage}", flush=True)
+        lat = Lattice(dict(cfg, storage=storage), pert, pinit)
+        lat.step(1)
+        st, k, s = lat.state()
+        assert (k, s) == (S.k, S.s)
+        errs = comp_errors(st, ref)
+        if storage == wl.F64:
+            assert errs.max() < tol, (errs.argmax(), errs.max())
+        else:
+            assert errs[27:].max() < tol, errs[27:]
+        lat.close()
+
+
+def test_adjoint_rejects_other_collisions():
+    from paper_2201_05473_amd import LBM_EINVAL, LbmError, Lattice
+    cfg = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.3, collision=wl.TRT)
+    lat = Lattice(cfg)
+    with pytest.raises(LbmError) as ei:
+        lat.adjoint(4, 2)
+    assert ei.value.code == LBM_EINVAL
+    with pytest.raises(LbmError) as ei:
+        lat.vjp_step(np.zeros((33, 8, 64)))
+    assert ei.value.code == LBM_EINVAL
+    lat.close()
+
+
+def test_regularised_operator_tames_the_nonlinear_wake():
+    """The paper attributes the rise of the smallest usable D in the nonlinear regime to BGK.
+    Nonlinear wake (n_b = 2, Q~ = 3.9; 2048 x 256, dz = 0.02, FP32, 6,000 steps) at tau = 0.55
+    (D = 0.0017, below BGK's usable range): BGK's most negative density is about -0.04, the
+    regularised operator's about -5e-5.  The test asks for a hundredfold smaller excursion."""
+    import math
+
+    from paper_2201_05473_amd import Lattice
+    nmin = {}
+    for coll in (wl.BGK, wl.REG):
+        cfg = wl.config(None, nz=2048, nr=256, dz=0.02, dr=0.02, c_dt_over_dz=0.2, tau=0.55, storage=wl.F32,
+                        moving_window=1, n0=1.0, ramp_kind=2, nb=2.0, sigma_z=0.5, sigma_r=0.5, n_floor=1e-6,
+                        collision=coll)
+        zd0 = cfg["nz"] * cfg["dz"] - 4.0
+        cfg.update(zd0=zd0, ramp_start=zd0 + 2.0, ramp_len=2.0)
+        lat = Lattice(cfg)
+        lat.step(6000)
+        n = lat.moments()[0]
+        assert lat.diagnostics()["nonfinite"] == 0
+        nmin[coll] = float(n.min())
+        print(f"[nonlinear wake] collision={coll} tau=0.55 n_min={nmin[coll]:.3e}", flush=True)
+        lat.close()
+    assert nmin[wl.BGK] < -1e-2, nmin
+    assert math.isfinite(nmin[wl.REG]) and abs(min(nmin[wl.REG], 0.0)) < 1e-2 * abs(nmin[wl.BGK]), nmin
