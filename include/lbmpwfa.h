@@ -201,11 +201,13 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
  * initial state.  The context must be at step 0.  Forward pass with a stored checkpoint every
  * ckpt_every steps, then segment by segment in reverse: recompute the segment's states (and the
  * site-averaged fields of each of its steps) from its checkpoint, and run the reverse steps.
- * The recompute of the next segment runs on a second stream, created by the library on first
- * use (default priority, released by lbm_destroy), while the reverse steps run on the caller's
- * stream; with more than one segment the workspace holds two segment buffers.  On return the
- * context holds the state after nsteps.  Synchronising.  Periodic dimensions need at least 5
- * cells. */
+ * The last segment is kept from the forward pass (its states and site fields go straight to a
+ * segment buffer), so it is not recomputed.  The recompute of the next segment runs on a second
+ * stream, created by the library on first use (default priority, released by lbm_destroy),
+ * while the reverse steps run on the caller's stream; with more than one segment the workspace
+ * holds two segment buffers.  On return the context holds the state after nsteps (on an error
+ * it still holds the initial state).  cfg.check_every is not applied inside this call.
+ * Synchronising.  Periodic dimensions need at least 5 cells. */
 int lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every,
                 void* adj_ws, size_t adj_bytes, double* J, double grad[4]);
 

@@ -60,8 +60,7 @@ __device__ __forceinline__ void dnbg(const Physics& p, double z, double& dlen, d
 __device__ __forceinline__ void ddriver(const Physics& p, double z, double r, double t, double& dsr,
                                         double& dnb) {
   const double dz = z - (p.zd0 + t);
-  const double zr = exp(-(dz * dz) / (2.0 * p.sigma_z * p.sigma_z)) *
-                    exp(-(r * r) / (2.0 * p.sigma_r * p.sigma_r));
+  const double zr = exp(-(dz * dz) / (2.0 * p.sigma_z * p.sigma_z) - (r * r) / (2.0 * p.sigma_r * p.sigma_r));
   dnb = zr;
   dsr = p.nb * zr * r * r / (p.sigma_r * p.sigma_r * p.sigma_r);
 }
@@ -93,15 +92,15 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const double M[3],
                                             double Mbar[3]) {
   double bz, br;
   if (!velocity<double>(M[0], M[1], M[2], p.n_floor, bz, br)) return;
-  const double n = M[0], pz = M[1] / n, pr = M[2] / n;
-  const double g2 = 1.0 + pz * pz + pr * pr, ig = 1.0 / sqrt(g2), ig3 = ig / g2;
+  const double n = M[0], in = 1.0 / n, pz = M[1] * in, pr = M[2] * in;
+  const double g2 = 1.0 + pz * pz + pr * pr, ig = 1.0 / sqrt(g2), ig3 = ig * ig * ig;
   // J_a = n p_a / gamma: dJ_a/dp_b = n (delta_ab / gamma - p_a p_b / gamma^3), dJ_a/dn|_p = beta_a
   const double jdot = jzb * pz + jrb * pr;
   const double pbz = n * (jzb * ig - pz * jdot * ig3), pbr = n * (jrb * ig - pr * jdot * ig3);
   const double nbar = jzb * bz + jrb * br;
-  Mbar[1] += pbz / n;
-  Mbar[2] += pbr / n;
-  Mbar[0] += nbar - (pbz * pz + pbr * pr) / n;
+  Mbar[1] += pbz * in;
+  Mbar[2] += pbr * in;
+  Mbar[0] += nbar - (pbz * pz + pbr * pr) * in;
 }
 
 }  // namespace
@@ -245,10 +244,11 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
       double bz, br;
       const bool live = velocity<double>(Am[0], Am[1], Am[2], p.n_floor, bz, br);
       const double uz = p.lam * bz, ur = p.lam * br;
-      double pz = 0.0, pr = 0.0, ig = 1.0;
+      double pz = 0.0, pr = 0.0, ig = 1.0, in = 0.0;
       if (live) {
-        pz = Am[1] / n;
-        pr = Am[2] / n;
+        in = 1.0 / n;
+        pz = Am[1] * in;
+        pr = Am[2] * in;
         ig = 1.0 / sqrt(1.0 + pz * pz + pr * pr);
       }
       const double Ebz = (double)sfield[0], Ebr = (double)sfield[1], Bb = (double)sfield[2];
@@ -305,15 +305,15 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
         }
       }
       if (live) {
-        const double g2 = 1.0 + pz * pz + pr * pr, ig3 = ig / g2;
+        const double ig3 = ig * ig * ig;
         const double pdot = pz * bbz + pr * bbr;
         const double pbz = bbz * ig - pz * pdot * ig3, pbr = bbr * ig - pr * pdot * ig3;
-        Ab[1] += pbz / n;
-        Ab[2] += pbr / n;
-        Ab[0] -= (pbz * pz + pbr * pr) / n;
+        Ab[1] += pbz * in;
+        Ab[2] += pbr * in;
+        Ab[0] -= (pbz * pz + pbr * pr) * in;
       }
       // adjoint of the pulled populations: (1 - 1/tau) g_bar' + A_bar
-      const double c1 = 1.0 - 1.0 / p.tau;
+      const double c1 = 1.0 - itau;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
@@ -385,7 +385,7 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
-  const double h = p.h, dt = p.dt;
+  const double h = p.h, dt = p.dt, dth = dt / h;
   const A* __restrict__ W = (const A*)a.work;
   const A* __restrict__ L = (const A*)a.lam_next;
   A* Lo = (A*)a.lam;   // planes 0..26 (f_bar^k) read, planes 27..32 written
@@ -513,8 +513,8 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
           const int ea = ci - (i0 - 1), eb = cj - j0;
           v = (oLZ[sl] ? (double)rLZ[sl] : 0.0) + 0.5 * (sEb[eb][ea] + sEb[eb][ea + 1]);
           if (!p.per_z && cw == 0) v += 0.5 * sEb[eb][ea];     // rear copy E_z(-1) = E_z(0)
-          if (cj <= nr - 2) v -= dt / h * LB(ci, cj);
-          if (cj >= 1) v += dt / h * LB(ci, cj - 1);
+          if (cj <= nr - 2) v -= dth * LB(ci, cj);
+          if (cj >= 1) v += dth * LB(ci, cj - 1);
         }
         sLZ[t / LZZ][t % LZZ] = v;
       }
@@ -525,8 +525,8 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
         if (cellz(cw, cj)) {
           const int ra = ci - i0, rb = cj - (j0 - 1);
           v = (oLR[sl] ? (double)rLR[sl] : 0.0) + 0.5 * (sRb[rb][ra] + sRb[rb + 1][ra]);
-          if (p.per_z || cw <= nz - 2) v += dt / h * LB(ci, cj);
-          if (p.per_z || cw >= 1) v -= dt / h * LB(ci - 1, cj);
+          if (p.per_z || cw <= nz - 2) v += dth * LB(ci, cj);
+          if (p.per_z || cw >= 1) v -= dth * LB(ci - 1, cj);
         }
         sLR[t / LRZ][t % LRZ] = v;
       }
@@ -540,8 +540,8 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
       const double rj = (j + 0.5) * h;
       lb += dt * (j + 1.0) / rj * lez;
       if (j + 1 < nr) lb -= dt * (j + 1.0) / ((j + 1.5) * h) * LZ(i, j + 1);
-      if (p.per_z || i >= 1) lb -= dt / h * ler;
-      if (p.per_z || i + 1 < nz) lb += dt / h * LR(i + 1, j);
+      if (p.per_z || i >= 1) lb -= dth * ler;
+      if (p.per_z || i + 1 < nz) lb += dth * LR(i + 1, j);
       stv(&(Lo + 30 * plane)[cell], lez);
       stv(&(Lo + 31 * plane)[cell], ler);
       stv(&(Lo + 32 * plane)[cell], lb);
@@ -633,8 +633,9 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
     double bz, br;
     const bool live = velocity<double>(M[0], M[1], M[2], p.n_floor, bz, br);
     const double n = M[0];
-    const double pz = live ? M[1] / n : 0.0, pr0 = live ? M[2] / n : 0.0;
-    const double g2 = 1.0 + pz * pz + pr0 * pr0, ig = live ? 1.0 / sqrt(g2) : 0.0, ig3 = ig / g2;
+    const double in = live ? 1.0 / n : 0.0;
+    const double pz = M[1] * in, pr0 = M[2] * in;
+    const double g2 = 1.0 + pz * pz + pr0 * pr0, ig = live ? 1.0 / sqrt(g2) : 0.0, ig3 = ig * ig * ig;
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
       if (!gv[c]) continue;
@@ -658,9 +659,9 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
         const double bbz = p.lam * ubz, bbr = p.lam * ubr;
         const double pdot = pz * bbz + pr * bbr;
         const double pbz = bbz * ig - pz * pdot * ig3, pbr = bbr * ig - pr * pdot * ig3;
-        Mgb[1] += pbz / n;
-        Mgb[2] += pbr / n;
-        Mgb[0] -= (pbz * pz + pbr * pr) / n;
+        Mgb[1] += pbz * in;
+        Mgb[2] += pbr * in;
+        Mgb[0] -= (pbz * pz + pbr * pr) * in;
       }
       Mb[0] += Mgb[0];
       Mb[1] += Mgb[1];
@@ -690,8 +691,24 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
 // the cell part writes its planes 27..32, the site part reads planes 0..26 (written by the
 // previous launch) and writes f_bar^{k-1} into as.lam, whose planes 30..32 (lambda^{k+1}) the cell
 // part reads; the two steps use different work buffers.
+// The site step's arguments arrive without their physics (the same as ac.p), which keeps the
+// kernel's uniform values to one copy of the physics.
 template <int ST>
-__global__ __launch_bounds__(NTHREADS) void adj_fused_kernel(AdjArgs ac, AdjArgs as) {
+__device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss) {
+  AdjArgs as;
+  as.p = ac.p;
+  as.k = ss.k;
+  as.s = ss.s;
+  as.shift = ss.shift;
+  as.pull_in = ss.pull_in;
+  as.g = ss.g;
+  as.M = ss.M;
+  as.E = ss.E;
+  as.lam_next = ss.lam_next;
+  as.lam = ss.lam;
+  as.work = ss.work;
+  as.site = ss.site;
+  as.partials = ss.partials;
   const int gx = (ac.p.nz + TZ - 1) / TZ, gy = (ac.p.nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   const int o0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
@@ -708,6 +725,19 @@ __global__ __launch_bounds__(NTHREADS) void adj_fused_kernel(AdjArgs ac, AdjArgs
   }
   site_body<ST>(as, o0 + as.shift, j0, mb, part);
   block_sum4(part, as.partials + (long long)blockIdx.x * 4);
+}
+
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) void adj_fused_kernel(AdjArgs ac, AdjStep ss) {
+  fused_body<ST>(ac, ss);
+}
+
+// FP32 and FP16 storage: held to 128 VGPRs (4 waves per SIMD), where the kernel fits without
+// spills; one register more would drop it to 3 waves per SIMD.
+template <int ST>
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(4))) void adj_fused4_kernel(AdjArgs ac,
+                                                                                                     AdjStep ss) {
+  fused_body<ST>(ac, ss);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -905,7 +935,12 @@ hipError_t launch_adjoint_cell(int storage, const AdjArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_adjoint_fused(int storage, const AdjArgs& cell, const AdjArgs& site, hipStream_t st) {
-  ADJ_DISPATCH(storage, adj_fused_kernel, dim3(step_blocks(cell.p)), NTHREADS, st, cell, site);
+  const AdjStep ss{site.k, site.s, site.shift, site.pull_in, site.g, site.M, site.E,
+                   site.lam_next, site.lam, site.work, site.site, site.partials};
+  const dim3 grid(step_blocks(cell.p));
+  if (storage == 0) adj_fused_kernel<0><<<grid, NTHREADS, 0, st>>>(cell, ss);
+  else if (storage == 1) adj_fused4_kernel<1><<<grid, NTHREADS, 0, st>>>(cell, ss);
+  else adj_fused4_kernel<2><<<grid, NTHREADS, 0, st>>>(cell, ss);
   return hipGetLastError();
 }
 

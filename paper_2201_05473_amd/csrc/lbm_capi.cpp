@@ -655,32 +655,46 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   char* seg[2] = {ckpt + (size_t)nseg * sb, ckpt + (size_t)nseg * sb + segbuf};   // [1] unused if nseg == 1
   char* lam[2] = {w + L.lamA, w + L.lamB};
   double* gacc = (double*)(w + L.grad);
-  const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
-  const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
-  auto copy_state = [&](const StateView& dst, const StateView& src, hipStream_t st) -> hipError_t {
-    hipError_t e = hipMemcpyAsync(dst.g, src.g, gbytes, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst.M, src.M, mbytes, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst.E, src.E, mbytes, hipMemcpyDeviceToDevice, st);
-    return e;
-  };
   if (!c->aux) {
     HIP_CHECK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "stream create");
     for (hipEvent_t* e : {&c->ev_fwd, &c->ev_rec[0], &c->ev_rec[1], &c->ev_rev[0], &c->ev_rev[1]})
       HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
   }
 
-  // forward pass with checkpoints
-  for (int64_t sgi = 0; sgi < nseg; ++sgi) {
-    const StateView cur{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
-    HIP_CHECK(copy_state(state_at(ckpt + (size_t)sgi * sb, p, c->storage), cur, c->stream), "checkpoint");
-    const int64_t len = std::min<int64_t>(ckpt_every, nsteps - sgi * ckpt_every);
-    rc = lbm_step(c, len);
-    if (rc) return rc;
+  // Forward pass.  x^0 stays in the context's current buffer and is checkpoint 0; each later
+  // checkpoint is written by the step that makes it (no copies).  The last segment runs with its
+  // site fields straight into its segment buffer, so the reverse sweep needs no recompute of it;
+  // x^N goes to the context's other buffer, which becomes current when the call ends.
+  const int c0 = c->cur;
+  const StateView x0{c->g(c0), c->M(c0), c->E(c0)};
+  const StateView xN{c->g(1 - c0), c->M(1 - c0), c->E(1 - c0)};
+  auto ck_at = [&](int64_t sgi) -> StateView {
+    return sgi == 0 ? x0 : state_at(ckpt + (size_t)sgi * sb, p, c->storage);
+  };
+  {
+    // ping-pong states between checkpoints: the context's other buffer and the first slot of the
+    // segment buffer that the last segment does not use
+    const StateView pp[2] = {xN, state_at(seg[nseg % 2], p, c->storage)};
+    StateView src = x0;
+    for (int64_t sgi = 0; sgi + 1 < nseg; ++sgi)
+      for (int64_t t = 0; t < ckpt_every; ++t) {
+        const StateView dst = t == ckpt_every - 1 ? ck_at(sgi + 1) : pp[t % 2];
+        HIP_CHECK(step_with_site(c, sgi * ckpt_every + t, src, dst, nullptr, c->stream), "step launch");
+        src = dst;
+      }
+    const int64_t k0 = (nseg - 1) * ckpt_every, len = nsteps - k0;
+    char* buf = seg[(nseg - 1) % 2];
+    char* sites = buf + (size_t)(seglen + 1) * sb;
+    for (int64_t t = 0; t < len; ++t) {
+      const StateView dst = t == len - 1 ? xN : state_at(buf + (size_t)(t + 1) * sb, p, c->storage);
+      HIP_CHECK(step_with_site(c, k0 + t, src, dst, sites + (size_t)t * stb, c->stream), "step launch");
+      src = dst;
+    }
   }
   // objective
   {
     const size_t ab = aux_bytes(c->storage);
-    const char* ez = (const char*)c->E(c->cur) + ((size_t)obj->row * p.pitch + (size_t)iw) * ab;
+    const char* ez = (const char*)xN.E + ((size_t)obj->row * p.pitch + (size_t)iw) * ab;
     double e0, e1;
     if (ab == 8) {
       double v[2];
@@ -711,20 +725,22 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   // Reverse sweep, segment by segment.  The recompute of segment sgi - 1 (states from its
   // checkpoint, and the site fields of each step) runs on the second stream while the reverse
   // sweep of segment sgi runs on the caller's stream; segments alternate between two buffers.
+  // Segments other than the last are full length; their first state is read from the checkpoint,
+  // slots 1 .. len - 1 of the buffer hold the later states (slot len is scratch).
   auto recompute = [&](int64_t sgi, char* buf) -> hipError_t {
     const int64_t k0 = sgi * ckpt_every;
-    const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
     char* sites = buf + (size_t)(seglen + 1) * sb;
-    hipError_t e = copy_state(state_at(buf, p, c->storage), state_at(ckpt + (size_t)sgi * sb, p, c->storage), c->aux);
-    for (int64_t t = 0; e == hipSuccess && t < len; ++t)   // slot len is scratch
-      e = step_with_site(c, k0 + t, state_at(buf + (size_t)t * sb, p, c->storage),
-                         state_at(buf + (size_t)(t + 1) * sb, p, c->storage), sites + (size_t)t * stb, c->aux);
+    hipError_t e = hipSuccess;
+    StateView src = ck_at(sgi);
+    for (int64_t t = 0; e == hipSuccess && t < ckpt_every; ++t) {
+      const StateView dst = state_at(buf + (size_t)(t + 1) * sb, p, c->storage);
+      e = step_with_site(c, k0 + t, src, dst, sites + (size_t)t * stb, c->aux);
+      src = dst;
+    }
     return e;
   };
   HIP_CHECK(hipEventRecord(c->ev_fwd, c->stream), "event record");
   HIP_CHECK(hipStreamWaitEvent(c->aux, c->ev_fwd, 0), "stream wait");
-  HIP_CHECK(recompute(nseg - 1, seg[(nseg - 1) % 2]), "recompute launch");
-  HIP_CHECK(hipEventRecord(c->ev_rec[(nseg - 1) % 2], c->aux), "event record");
   // Within the sweep, the cell part of step k and the site part of step k - 1 run as one fused
   // launch; the site part of the last step and the cell part of step 0 run alone.  At a segment
   // boundary the fused launch reads the last state (and site fields) of the previous segment,
@@ -732,6 +748,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   // released once the cell part of its first step has run.
   auto xs = [&](int64_t k) -> StateView {
     const int64_t sgi = k / ckpt_every;
+    if (k == sgi * ckpt_every) return ck_at(sgi);
     return state_at(seg[sgi % 2] + (size_t)(k - sgi * ckpt_every) * sb, p, c->storage);
   };
   auto site_of = [&](int64_t k) -> const void* {
@@ -751,7 +768,6 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
     const int64_t len = std::min<int64_t>(ckpt_every, nsteps - k0);
     for (int64_t k = k0 + len - 1; k >= k0; --k) {
       if (k == nsteps - 1) {
-        HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_rec[b], 0), "stream wait");
         const lbm::AdjArgs as = adj_args(c, xs(k), site_of(k), k, lam[cur], lam[1 - cur], 1, w, L, (int)(k % 2));
         HIP_CHECK(lbm::launch_adjoint_site(c->storage, as, c->stream), "adjoint launch");
       }
@@ -771,13 +787,16 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   }
   // initial state
   {
-    const StateView x0 = state_at(ckpt, p, c->storage);
     const lbm::AdjArgs a = adj_args(c, x0, nullptr, 0, lam[cur], nullptr, 1, w, L);
     HIP_CHECK(lbm::launch_adjoint_init(c->storage, a, c->stream), "adjoint init launch");
     HIP_CHECK(lbm::adjoint_reduce(c->p, a.partials, gacc, c->stream), "adjoint reduce");
   }
   HIP_CHECK(hipMemcpyAsync(grad, gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  // the context now holds x^N
+  c->cur = 1 - c0;
+  c->k = nsteps;
+  c->s = sN;
   return LBM_OK;
 }
 

@@ -67,6 +67,22 @@ struct AdjArgs {
   double* partials;
 };
 
+// The fields of AdjArgs that change from one reverse step to the next (everything but the
+// physics), so that a launch covering two steps carries the physics once.
+struct AdjStep {
+  long long k, s;
+  int shift;
+  int pull_in;
+  const void* g;
+  const void* M;
+  const void* E;
+  const void* lam_next;
+  void* lam;
+  void* work;
+  const void* site;
+  double* partials;
+};
+
 // Launchers (defined in lbm_kernels.hip / lbm_adjoint.hip).  storage: 0 F64, 1 F32, 2 F16.
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st);
 // Bubble length count of one row (single block) into *out (device).
