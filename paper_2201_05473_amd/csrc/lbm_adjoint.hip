@@ -3,9 +3,13 @@
 // For the state x^k = (g^{k-1}, A*^{k-1}, E^{k-1}, B^{k-1/2}) and the step x^{k+1} = Phi(x^k; theta)
 // of the forward kernel, these kernels compute lambda^k = (dPhi/dx^k)^T lambda^{k+1} and the
 // parameter partials (dPhi/dtheta)^T lambda^{k+1}, theta = (ramp length, n0, sigma_r, n_b).
-// Arithmetic is FP64; the adjoint variables are stored in the precision of the auxiliary planes
-// (FP64 for FP64 storage, FP32 otherwise).  All variables are the raw populations, moments and
-// fields (the deviation encoding of the stored density lattice is an identity map for the adjoint).
+// The adjoint variables are stored in the precision of the auxiliary planes (FP64 for FP64
+// storage, FP32 otherwise).  Arithmetic: the site part (the collision's VJP) computes in the
+// forward step's precision (FP64 for FP64 storage, FP32 otherwise); the cell part (transposes of
+// the Yee curls and site averages, which difference neighbouring adjoints) and every theta
+// partial stay in FP64, where FP32 would lose the cancelling digits.  All variables are the raw
+// populations, moments and fields (the deviation encoding of the stored density lattice is an
+// identity map for the adjoint).
 //
 // Population adjoints are carried in "pulled" form: f_bar^k(y, q) is the adjoint of the population
 // that site y pulls in step k (the collision input).  The collision's VJP has rank-3 structure,
@@ -88,16 +92,16 @@ __device__ __forceinline__ void block_sum4(double v[4], double* acc) {
 }
 
 // VJP of J = n beta(M) (the face current of Ampere's law) with respect to M.
-__device__ __forceinline__ void current_vjp(const Physics& p, const double M[3], double jzb, double jrb,
-                                            double Mbar[3]) {
-  double bz, br;
-  if (!velocity<double>(M[0], M[1], M[2], p.n_floor, bz, br)) return;
-  const double n = M[0], in = 1.0 / n, pz = M[1] * in, pr = M[2] * in;
-  const double g2 = 1.0 + pz * pz + pr * pr, ig = 1.0 / sqrt(g2), ig3 = ig * ig * ig;
+template <typename T>
+__device__ __forceinline__ void current_vjp(const Physics& p, const T M[3], T jzb, T jrb, T Mbar[3]) {
+  T bz, br;
+  if (!velocity<T>(M[0], M[1], M[2], (T)p.n_floor, bz, br)) return;
+  const T n = M[0], in = T(1) / n, pz = M[1] * in, pr = M[2] * in;
+  const T g2 = T(1) + pz * pz + pr * pr, ig = T(1) / sqrt(g2), ig3 = ig * ig * ig;
   // J_a = n p_a / gamma: dJ_a/dp_b = n (delta_ab / gamma - p_a p_b / gamma^3), dJ_a/dn|_p = beta_a
-  const double jdot = jzb * pz + jrb * pr;
-  const double pbz = n * (jzb * ig - pz * jdot * ig3), pbr = n * (jrb * ig - pr * jdot * ig3);
-  const double nbar = jzb * bz + jrb * br;
+  const T jdot = jzb * pz + jrb * pr;
+  const T pbz = n * (jzb * ig - pz * jdot * ig3), pbr = n * (jrb * ig - pr * jdot * ig3);
+  const T nbar = jzb * bz + jrb * br;
   Mbar[1] += pbz * in;
   Mbar[2] += pbr * in;
   Mbar[0] += nbar - (pbz * pz + pbr * pr) * in;
@@ -114,16 +118,18 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const double M[3],
 // mreg: M_bar^{k+1} of the thread's site output, when the caller has it in registers (else read
 // from lam_next).  theta partials are added to part.  Every thread of the block must call it.
 template <int ST>
-__device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const double* mreg, double part[4]) {
+__device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const typename Mode<ST, false>::C* mreg, double part[4]) {
   using S = typename Mode<ST, false>::S;
   using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
+  using T = typename Mode<ST, false>::C;   // arithmetic (FP64 for FP64 storage, else FP32)
   const Physics& p = a.p;
   __shared__ double sN[TZ + 2];   // n_bg at the columns i0-1 .. i0+TZ
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
-  const double h = p.h, dt = p.dt;
+  const double h = p.h;
+  const T dt = (T)p.dt, lam = (T)p.lam, floor_ = (T)p.n_floor;
   const A* __restrict__ Min = (const A*)a.M;
   const S* __restrict__ gin = (const S*)a.g;
   const A* __restrict__ L = (const A*)a.lam_next;
@@ -173,12 +179,12 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
 #pragma unroll
     for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[jc * pitch + ib];
   // zeroth moments of the populations pulled from inside the domain (deviation form for lattice 0)
-  double Am[3] = {0.0, 0.0, 0.0};
+  T Am[3] = {T(0.0), T(0.0), T(0.0)};
 #pragma unroll
   for (int q = 0; q < 9; ++q)
     if (!ghost[q])
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) Am[kk] += (double)ldv(graw[9 * kk + q]);
+      for (int kk = 0; kk < 3; ++kk) Am[kk] += (T)ldv(graw[9 * kk + q]);
 
   for (int t = tid; t < TZ + 2; t += NTHREADS) {
     const int ii = i0 - 1 + t;
@@ -214,62 +220,62 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
       for (int q = 0; q < 9; ++q) {
         if (ghost[q]) {
           int si = i - XZ(q), sj = j - XR(q);
-          double Mg[3];
+          T Mg[3];
           if (!p.per_z && si >= nz && p.window) {
-            Mg[0] = sN[tx + 1 - XZ(q)];
-            Mg[1] = 0.0;
-            Mg[2] = 0.0;
+            Mg[0] = (T)sN[tx + 1 - XZ(q)];
+            Mg[1] = T(0.0);
+            Mg[2] = T(0.0);
           } else {
             si = p.per_z ? wrap1(si, nz) : (si < 0 ? 0 : (si < nz ? si : nz - 1));
             const int rj = p.per_r ? wrap1(sj, nr) : (sj < 0 ? 0 : (sj < nr ? sj : nr - 1));
             const int off = rj * pitch + si;
             const int sa = si - (i0 - 1);
-            Mg[0] = (double)Min[off] + ((sa >= 0 && sa < TZ + 2) ? sN[sa] : nbg(p, (double)(a.s + si) * h));
-            Mg[1] = (double)Min[plane + off];
-            Mg[2] = (double)(Min + 2 * plane)[off];
+            Mg[0] = (T)((double)Min[off] + ((sa >= 0 && sa < TZ + 2) ? sN[sa] : nbg(p, (double)(a.s + si) * h)));
+            Mg[1] = (T)Min[plane + off];
+            Mg[2] = (T)(Min + 2 * plane)[off];
           }
           if (!p.per_r && sj < 0) Mg[2] = -Mg[2];   // axis mirror
-          double bz, br;
-          velocity<double>(Mg[0], Mg[1], Mg[2], p.n_floor, bz, br);
-          const double uz = p.lam * bz, ur = p.lam * br;
-          const double cu = XZ(q) * uz + XR(q) * ur;
-          const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
+          T bz, br;
+          velocity<T>(Mg[0], Mg[1], Mg[2], floor_, bz, br);
+          const T uz = lam * bz, ur = lam * br;
+          const T cu = XZ(q) * uz + XR(q) * ur;
+          const T Q = T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * (uz * uz + ur * ur);
 #pragma unroll
-          for (int kk = 0; kk < 3; ++kk) Am[kk] += WQ<double>(q) * Mg[kk] * (1.0 + Q);
+          for (int kk = 0; kk < 3; ++kk) Am[kk] += WQ<T>(q) * Mg[kk] * (T(1.0) + Q);
         } else {
-          Am[0] += WQ<double>(q) * sN[tx + 1 - XZ(q)];
+          Am[0] += WQ<T>(q) * (T)sN[tx + 1 - XZ(q)];
         }
       }
-      const double n = Am[0];
-      double bz, br;
-      const bool live = velocity<double>(Am[0], Am[1], Am[2], p.n_floor, bz, br);
-      const double uz = p.lam * bz, ur = p.lam * br;
-      double pz = 0.0, pr = 0.0, ig = 1.0, in = 0.0;
+      const T n = Am[0];
+      T bz, br;
+      const bool live = velocity<T>(Am[0], Am[1], Am[2], floor_, bz, br);
+      const T uz = lam * bz, ur = lam * br;
+      T pz = T(0.0), pr = T(0.0), ig = T(1.0), in = T(0.0);
       if (live) {
-        in = 1.0 / n;
+        in = T(1.0) / n;
         pz = Am[1] * in;
         pr = Am[2] * in;
-        ig = 1.0 / sqrt(1.0 + pz * pz + pr * pr);
+        ig = T(1.0) / sqrt(T(1.0) + pz * pz + pr * pr);
       }
-      const double Ebz = (double)sfield[0], Ebr = (double)sfield[1], Bb = (double)sfield[2];
-      const double ir = 1.0 / ((j + 0.5) * h);
+      const T Ebz = (T)sfield[0], Ebr = (T)sfield[1], Bb = (T)sfield[2];
+      const T ir = (T)(1.0 / ((j + 0.5) * h));
 
       // g' = (1 - 1/tau) f + e/tau + w dt F,  M' = A + dt F,  e = w A (1 + Q(u))
-      double Fb[3], Ab[3];
-      double ubz = 0.0, ubr = 0.0;
-      double sw[3] = {0.0, 0.0, 0.0}, s0[3] = {0.0, 0.0, 0.0};
-      const double itau = 1.0 / p.tau, usq = uz * uz + ur * ur;
+      T Fb[3], Ab[3];
+      T ubz = T(0.0), ubr = T(0.0);
+      T sw[3] = {T(0.0), T(0.0), T(0.0)}, s0[3] = {T(0.0), T(0.0), T(0.0)};
+      const T itau = T(1.0) / (T)p.tau, usq = uz * uz + ur * ur;
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        const double w = WQ<double>(q);
-        const double cu = XZ(q) * uz + XR(q) * ur;
-        const double e1 = w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);   // e_q / A
-        const double fz = w * (3.0 * XZ(q) + 9.0 * cu * XZ(q) - 3.0 * uz);    // w dQ/du_z
-        const double fr = w * (3.0 * XR(q) + 9.0 * cu * XR(q) - 3.0 * ur);
-        double az = 0.0;
+        const T w = WQ<T>(q);
+        const T cu = XZ(q) * uz + XR(q) * ur;
+        const T e1 = w * (T(1.0) + T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * usq);   // e_q / A
+        const T fz = w * (T(3.0) * XZ(q) + T(9.0) * cu * XZ(q) - T(3.0) * uz);    // w dQ/du_z
+        const T fr = w * (T(3.0) * XR(q) + T(9.0) * cu * XR(q) - T(3.0) * ur);
+        T az = T(0.0);
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
-          const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
+          const T gbq = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
           sw[kk] += w * gbq;
           s0[kk] += gbq * e1;
           az += gbq * Am[kk];
@@ -281,12 +287,12 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
       ubr *= itau;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
-        const double Mb = mreg ? mreg[kk] : (double)mbar[kk];
+        const T Mb = mreg ? mreg[kk] : (T)mbar[kk];
         Fb[kk] = dt * (sw[kk] + Mb);
         Ab[kk] = Mb + s0[kk] * itau;
       }
-      double bbz = p.lam * ubz, bbr = p.lam * ubr;
-      double Ebz_b = 0.0, Ebr_b = 0.0, Bb_b = 0.0;
+      T bbz = lam * ubz, bbr = lam * ubr;
+      T Ebz_b = T(0.0), Ebr_b = T(0.0), Bb_b = T(0.0);
       if (live) {
         // F1 = -n (E_z + beta_r B), F2 = -n (E_r - beta_z B)
         bbr += Fb[1] * (-n * Bb);
@@ -305,20 +311,20 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
         }
       }
       if (live) {
-        const double ig3 = ig * ig * ig;
-        const double pdot = pz * bbz + pr * bbr;
-        const double pbz = bbz * ig - pz * pdot * ig3, pbr = bbr * ig - pr * pdot * ig3;
+        const T ig3 = ig * ig * ig;
+        const T pdot = pz * bbz + pr * bbr;
+        const T pbz = bbz * ig - pz * pdot * ig3, pbr = bbr * ig - pr * pdot * ig3;
         Ab[1] += pbz * in;
         Ab[2] += pbr * in;
         Ab[0] -= (pbz * pz + pbr * pr) * in;
       }
       // adjoint of the pulled populations: (1 - 1/tau) g_bar' + A_bar
-      const double c1 = 1.0 - itau;
+      const T c1 = T(1.0) - itau;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          const double gbq = gok[q] ? (double)gbar[9 * kk + q] : 0.0;
+          const T gbq = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
           stv(&(Lo + (9 * kk + q) * plane)[cell], c1 * gbq + Ab[kk]);
         }
 #pragma unroll
@@ -334,7 +340,7 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
         double sum = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-          if (XZ(q) == -1) sum += WQ<double>(q) * (c1 * (gok[q] ? (double)gbar[q] : 0.0) + Ab[0]);
+          if (XZ(q) == -1) sum += WQ<double>(q) * (double)(c1 * (gok[q] ? (T)gbar[q] : T(0)) + Ab[0]);
         part[0] += sum * dl;
         part[1] += sum * dn;
         if (a.shift) {
@@ -379,7 +385,8 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 // adjoint of the thread's cell (zero for a thread outside the grid) is returned in mb_out as well
 // as stored.  theta partials are added to part.  Every thread of the block must call it.
 template <int ST>
-__device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, double part[4], double mb_out[3]) {
+__device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, double part[4],
+                                          typename Mode<ST, false>::C mb_out[3]) {
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
@@ -564,7 +571,7 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
       stv(&(Lo + (30 + c) * plane)[cell], ok ? (double)(L + (30 + c) * plane)[o] : 0.0);
     }
   }
-  mb_out[0] = mb_out[1] = mb_out[2] = 0.0;
+  mb_out[0] = mb_out[1] = mb_out[2] = 0;
   if (!mine) return;   // no barrier below this point
 
   // ---- lambda of the moments ----
@@ -671,7 +678,7 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     stv(&(Lo + (27 + k) * plane)[cell], Mb[k]);
-    mb_out[k] = (double)(A)Mb[k];   // as stored, so the fused step reads what a split one would
+    mb_out[k] = (A)Mb[k];   // as stored, so the fused step reads what a split one would
   }
 }
 
@@ -679,7 +686,8 @@ template <int ST>
 __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
   const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
-  double part[4] = {0.0, 0.0, 0.0, 0.0}, mb[3];
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  typename Mode<ST, false>::C mb[3];
   cell_body<ST>(a, (tile % gx) * TZ, (tile / gx) * TR, part, mb);
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
 }
@@ -712,7 +720,8 @@ __device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss)
   const int gx = (ac.p.nz + TZ - 1) / TZ, gy = (ac.p.nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   const int o0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
-  double part[4] = {0.0, 0.0, 0.0, 0.0}, mb[3];
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  typename Mode<ST, false>::C mb[3];
   cell_body<ST>(ac, o0, j0, part, mb);
   const Physics& p = ac.p;
   if (p.window && as.shift && o0 + (int)threadIdx.x % TZ == p.nz - 1 && j0 + (int)threadIdx.x / TZ < p.nr) {
