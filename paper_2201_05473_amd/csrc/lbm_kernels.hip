@@ -22,7 +22,8 @@ namespace lbm {
 // phase can wait for the halo loads alone while the population loads stay in flight across the
 // LDS barriers (which only wait for LDS traffic).
 // ------------------------------------------------------------------------------------------
-template <int ST, bool FIELDS, bool M64, bool SITE, int COLL>
+// PER = false: the grid is known not to be periodic, and the wrap code is compiled out.
+template <int ST, bool FIELDS, bool M64, bool SITE, int COLL, bool PER>
 __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using S = typename Mode<ST, M64>::S;
   using C = typename Mode<ST, M64>::C;
@@ -66,8 +67,8 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
 
   // Column of a logical position after the z rule for copies (rear copy, front copy, wrap) and
   // row after the r rule (axis mirror row 0, outer copy, wrap); always in range.
-  auto zcol = [&](int i) { return p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1)); };
-  auto rrow = [&](int j) { return p.per_r ? wrapi(j, nr) : (j < 0 ? 0 : (j < nr ? j : nr - 1)); };
+  auto zcol = [&](int i) { return PER && p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1)); };
+  auto rrow = [&](int j) { return PER && p.per_r ? wrapi(j, nr) : (j < 0 ? 0 : (j < nr ? j : nr - 1)); };
   // plane bases (uniform) + 32-bit in-plane offsets (a plane holds fewer than 2^31 elements)
   const A* M0p = Min;
   const A* M1p = Min + plane;
@@ -126,14 +127,14 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   // background density at the lab position of the physical column
   for (int t = tid; t < MZ; t += NTHREADS) {
     const int ii = i0 - 1 + t;
-    sN[t] = nbg(p, (double)(a.s + (p.per_z ? wrapi(ii, nz) : ii)) * h);
+    sN[t] = nbg(p, (double)(a.s + (PER && p.per_z ? wrapi(ii, nz) : ii)) * h);
   }
   // the driver density factorises into a column and a row factor
   const double tb = ((double)a.k - 0.5) * dt;
   if (FIELDS) {
     for (int t = tid; t < EZZ; t += NTHREADS) {
       const int ii = i0 - 1 + t;
-      const int ci = p.per_z ? wrapi(ii, nz) : ii;
+      const int ci = PER && p.per_z ? wrapi(ii, nz) : ii;
       const CF dz = (CF)(((double)(a.s + ci) + 0.5) * h - (p.zd0 + tb));
       sDz[t] = mexp(-(dz * dz) / (CF)(2.0 * p.sigma_z * p.sigma_z));
     }
@@ -730,10 +731,16 @@ __global__ __launch_bounds__(RED_THREADS) void bubble_kernel(Physics p, long lon
 
 static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
 
+// FP16 storage moves half the bytes of FP32 and is instruction-bound: it takes the variant with
+// the wrap code compiled out when the grid is not periodic (8 % faster on 2048 x 512).  FP32 and
+// FP64 are bandwidth-bound and measure the same either way, so they keep one variant.
 template <int ST, bool M64, int COLL>
 static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
-  if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else step_kernel<ST, false, M64, false, COLL><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  const bool np = ST == 2 && !a.p.per_z && !a.p.per_r;
+  if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, ST != 2><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (np) step_kernel<ST, false, M64, false, COLL, ST != 2><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else step_kernel<ST, false, M64, false, COLL, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
 // The site-field variant (used by the adjoint, which is BGK only) exists for BGK alone.
@@ -741,7 +748,7 @@ template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
   if (a.p.coll == 1) launch_step_c<ST, M64, 1>(a, grid, st);
   else if (a.p.coll == 2) launch_step_c<ST, M64, 2>(a, grid, st);
-  else if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else launch_step_c<ST, M64, 0>(a, grid, st);
 }
 
