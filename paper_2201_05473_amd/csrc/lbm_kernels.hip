@@ -366,30 +366,37 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   // w (A (1 + 4.5 cu^2 - 1.5 u^2)), and an odd part, w A 3 cu (lattice 0 as the deviation).
   const C itau = (C)(1.0 / p.tau);
   if (COLL == 0) {
-    // BGK, Eq. (7)
+    // BGK, Eq. (7).  The rest population's equilibrium is taken as the moment minus the other
+    // eight (equal to Eq. (9) in exact arithmetic), their sum accumulated in FP64 and the
+    // difference rounded once, so that the equilibrium's zeroth moments are the moments
+    // themselves to half an ulp in any precision.  In FP32 the rounding of the equilibria would
+    // otherwise drift the density and momentum moments over many steps.
+    double se0 = 0.0, se1 = 0.0, se2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q);
       const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
       const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
       const C e0 = w * (dA0 + A0 * Q);
       const C e1 = w * A1 * (C(1) + Q);
       const C e2 = w * A2 * (C(1) + Q);
+      se0 += e0;
+      se1 += e1;
+      se2 += e2;
       const C wdt = w * dtc;
       stv(gout + q * plane + oo32, f0[q] - (f0[q] - e0) * itau + wdt * F0);
       stv(gout + (9 + q) * plane + oo32, f1[q] - (f1[q] - e1) * itau + wdt * F1);
       stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
     }
+    const C wdt = WQ<C>(0) * dtc;
+    stv(gout + oo32, f0[0] - (f0[0] - (C)((double)dA0 - se0)) * itau + wdt * F0);
+    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((double)A1 - se1)) * itau + wdt * F1);
+    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((double)A2 - se2)) * itau + wdt * F2);
   } else if (COLL == 1) {
     // two relaxation times: the even part of f - f_eq relaxes with 1/tau_plus, the odd part
     // (which carries the flux and so sets D) with 1/tau.  The rest population is even.
     const C itp = (C)(1.0 / p.tau_plus);
-    {
-      const C w = WQ<C>(0), wdt = w * dtc, Q = C(-1.5) * usq;
-      stv(gout + oo32, f0[0] - (f0[0] - w * (dA0 + A0 * Q)) * itp + wdt * F0);
-      stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - w * A1 * (C(1) + Q)) * itp + wdt * F1);
-      stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - w * A2 * (C(1) + Q)) * itp + wdt * F2);
-    }
+    double se0 = 0.0, se1 = 0.0, se2 = 0.0;   // equilibria of the eight moving directions
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int q = t < 2 ? 1 + t : 5 + (t - 2);   // 1, 2, 5, 6
@@ -398,6 +405,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
       const C ev = C(4.5) * cu * cu - C(1.5) * usq;
       const C od = C(3) * cu;
+      se0 += C(2) * w * (dA0 + A0 * ev);
+      se1 += C(2) * w * A1 * (C(1) + ev);
+      se2 += C(2) * w * A2 * (C(1) + ev);
       {
         const C re = (C(0.5) * (f0[q] + f0[b]) - w * (dA0 + A0 * ev)) * itp;
         const C ro = (C(0.5) * (f0[q] - f0[b]) - w * A0 * od) * itau;
@@ -417,6 +427,11 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
         stv(gout + (18 + b) * plane + oo32, f2[b] - re + ro + wdt * F2);
       }
     }
+    // the rest population (even): its equilibrium is the moment minus the other eight, as for BGK
+    const C wdt = WQ<C>(0) * dtc;
+    stv(gout + oo32, f0[0] - (f0[0] - (C)((double)dA0 - se0)) * itp + wdt * F0);
+    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((double)A1 - se1)) * itp + wdt * F1);
+    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((double)A2 - se2)) * itp + wdt * F2);
   } else {
     // regularised: f - f_eq is replaced by its first-order Hermite projection
     // w xi . j_neq / c_s^2, j_neq = sum xi f - A u (the first moment of f_eq is A u), then
@@ -442,16 +457,26 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     jr1 = k3 * (jr1 - A1 * ur);
     jz2 = k3 * (jz2 - A2 * uz);
     jr2 = k3 * (jr2 - A2 * ur);
+    double se0 = 0.0, se1 = 0.0, se2 = 0.0;   // equilibria of the eight moving directions
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q), wdt = w * dtc;
       const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
       const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
       const C xz = (C)XZ(q), xr = (C)XR(q);
-      stv(gout + q * plane + oo32, w * (dA0 + A0 * Q + xz * jz0 + xr * jr0) + wdt * F0);
-      stv(gout + (9 + q) * plane + oo32, w * (A1 * (C(1) + Q) + xz * jz1 + xr * jr1) + wdt * F1);
-      stv(gout + (18 + q) * plane + oo32, w * (A2 * (C(1) + Q) + xz * jz2 + xr * jr2) + wdt * F2);
+      const C e0 = w * (dA0 + A0 * Q), e1 = w * A1 * (C(1) + Q), e2 = w * A2 * (C(1) + Q);
+      se0 += e0;
+      se1 += e1;
+      se2 += e2;
+      stv(gout + q * plane + oo32, e0 + w * (xz * jz0 + xr * jr0) + wdt * F0);
+      stv(gout + (9 + q) * plane + oo32, e1 + w * (xz * jz1 + xr * jr1) + wdt * F1);
+      stv(gout + (18 + q) * plane + oo32, e2 + w * (xz * jz2 + xr * jr2) + wdt * F2);
     }
+    // the rest population (no first-order part): the moment minus the other eight, as for BGK
+    const C wdt = WQ<C>(0) * dtc;
+    stv(gout + oo32, (C)((double)dA0 - se0) + wdt * F0);
+    stv(gout + 9 * plane + oo32, (C)((double)A1 - se1) + wdt * F1);
+    stv(gout + 18 * plane + oo32, (C)((double)A2 - se2) + wdt * F2);
   }
   stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
   stv(Mout + plane + oo, A1 + dtc * F1);

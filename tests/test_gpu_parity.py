@@ -189,32 +189,37 @@ def test_nonfinite_state_is_reported():
 def test_fp32_fp16_parity_c2_copy():
     """C2's 512 x 128 copy with the plasma already around the driver (so that a wake exists and
     E_z is not a near-cancellation residual), FP32 and FP16 storage against the FP64 oracle
-    after 400 steps: max-norm relative error of n, E_z, E_r."""
+    after 400 steps: max-norm relative error of n, E_z, E_r.
+
+    Bounds.  Density: 1e-5 with FP32 arithmetic (measured 5e-8), 1e-7 with FP64 arithmetic (the
+    collision then conserves mass to FP64 round-off).  Fields: the FP32 storage of populations and
+    fields alone puts E_z near 1e-5 on this short case (FP64 arithmetic on FP32 storage, where the
+    arithmetic adds nothing: 9.9e-6); that storage floor is bounded by 2e-5, and the FP32-arithmetic
+    field error by twice the floor (measured 7.9e-6 for E_z, 3.8e-6 for E_r).  The equilibrium's
+    zeroth moments are exact, so the FP32-arithmetic error stays at the floor over long runs too
+    (C2, 10,000 steps: E_z 5.9e-6).  FP16 storage: 5e-3 (11-bit significand of the stored
+    deviations)."""
     cfg64 = wl.config("C2s")
     cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
     S, P = O.run(cfg64, 400)
     ref = {"n": S.M[0].numpy(), "Ez": S.Ez.numpy(), "Er": S.Er.numpy()}
-    # (storage, FP64 arithmetic) -> tolerance per quantity.  FP32 storage: the 1e-5 bound on
-    # density and E_z; with FP64 arithmetic the collision conserves mass to FP64 round-off and
-    # the density error drops below 1e-7 (E_z stays limited by the FP32 storage of the fields).
-    # FP16 storage: 5e-3 (11-bit significand of the stored deviations).
-    tol = {(wl.F32, 0): {"n": 1e-5, "Ez": 1e-5, "Er": 1e-5},
-           (wl.F32, 1): {"n": 1e-7, "Ez": 1e-5, "Er": 1e-5},
-           (wl.F16, 0): {"n": 5e-3, "Ez": 5e-3, "Er": 5e-3},
-           (wl.F16, 1): {"n": 5e-3, "Ez": 5e-3, "Er": 5e-3}}
-    errs_all = {}
-    for (storage, m64) in tol:
+    errs = {}
+    for (storage, m64) in ((wl.F32, 0), (wl.F32, 1), (wl.F16, 0), (wl.F16, 1)):
         cfg = dict(cfg64, storage=storage, fp64_math=m64)
         print(f"[reduced precision] C2s storage={storage} fp64_math={m64} 400 steps", flush=True)
         lat = run_gpu(cfg, 400)
         st, _, _ = lat.state()
-        errs_all[(storage, m64)] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
-                                    "Er": O.rel_err(st[31], ref["Er"])}
-        print(storage, m64, errs_all[(storage, m64)], flush=True)
+        errs[(storage, m64)] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
+                                "Er": O.rel_err(st[31], ref["Er"])}
+        print(storage, m64, errs[(storage, m64)], flush=True)
         lat.close()
-    for key, errs in errs_all.items():
-        for q, e in errs.items():
-            assert e < tol[key][q], (key, q, errs)
+    f32, floor = errs[(wl.F32, 0)], errs[(wl.F32, 1)]
+    assert f32["n"] < 1e-5 and floor["n"] < 1e-7, errs
+    for q in ("Ez", "Er"):
+        assert floor[q] < 2e-5, errs
+        assert f32[q] < 2.0 * floor[q], (q, errs)
+    for key in ((wl.F16, 0), (wl.F16, 1)):
+        assert max(errs[key].values()) < 5e-3, errs
 
 
 def test_full_size_c2_single_steps():
