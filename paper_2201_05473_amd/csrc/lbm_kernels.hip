@@ -8,6 +8,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -29,6 +31,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using C = typename Mode<ST, M64>::C;
   using A = typename Mode<ST, M64>::A;
   using CF = typename Mode<ST, M64>::CF;
+  // sums of the eight moving equilibria: FP64, except for FP16 storage, whose error is set by its
+  // storage and whose step is instruction-bound (FP64 sums cost it 6 %)
+  using SE = typename std::conditional<ST == 2, C, double>::type;
   const Physics& p = a.p;
   constexpr int MZ = TZ + 2, MR = TR + 2;    // moments:  cols i0-1..i0+TZ,   rows j0-1..j0+TR
   constexpr int BZ = TZ + 3, BR = TR + 3;    // B^{k-1/2}: cols i0-2..i0+TZ,  rows j0-2..j0+TR
@@ -367,11 +372,11 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   const C itau = (C)(1.0 / p.tau);
   if (COLL == 0) {
     // BGK, Eq. (7).  The rest population's equilibrium is taken as the moment minus the other
-    // eight (equal to Eq. (9) in exact arithmetic), their sum accumulated in FP64 and the
-    // difference rounded once, so that the equilibrium's zeroth moments are the moments
-    // themselves to half an ulp in any precision.  In FP32 the rounding of the equilibria would
+    // eight (equal to Eq. (9) in exact arithmetic), their sum accumulated in FP64 (type SE) and
+    // the difference rounded once, so that the equilibrium's zeroth moments are the moments
+    // themselves to half an ulp.  In FP32 the rounding of the equilibria would
     // otherwise drift the density and momentum moments over many steps.
-    double se0 = 0.0, se1 = 0.0, se2 = 0.0;
+    SE se0 = 0, se1 = 0, se2 = 0;
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q);
@@ -389,14 +394,14 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
     }
     const C wdt = WQ<C>(0) * dtc;
-    stv(gout + oo32, f0[0] - (f0[0] - (C)((double)dA0 - se0)) * itau + wdt * F0);
-    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((double)A1 - se1)) * itau + wdt * F1);
-    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((double)A2 - se2)) * itau + wdt * F2);
+    stv(gout + oo32, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itau + wdt * F0);
+    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itau + wdt * F1);
+    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itau + wdt * F2);
   } else if (COLL == 1) {
     // two relaxation times: the even part of f - f_eq relaxes with 1/tau_plus, the odd part
     // (which carries the flux and so sets D) with 1/tau.  The rest population is even.
     const C itp = (C)(1.0 / p.tau_plus);
-    double se0 = 0.0, se1 = 0.0, se2 = 0.0;   // equilibria of the eight moving directions
+    SE se0 = 0, se1 = 0, se2 = 0;   // equilibria of the eight moving directions
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int q = t < 2 ? 1 + t : 5 + (t - 2);   // 1, 2, 5, 6
@@ -429,9 +434,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     }
     // the rest population (even): its equilibrium is the moment minus the other eight, as for BGK
     const C wdt = WQ<C>(0) * dtc;
-    stv(gout + oo32, f0[0] - (f0[0] - (C)((double)dA0 - se0)) * itp + wdt * F0);
-    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((double)A1 - se1)) * itp + wdt * F1);
-    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((double)A2 - se2)) * itp + wdt * F2);
+    stv(gout + oo32, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itp + wdt * F0);
+    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itp + wdt * F1);
+    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itp + wdt * F2);
   } else {
     // regularised: f - f_eq is replaced by its first-order Hermite projection
     // w xi . j_neq / c_s^2, j_neq = sum xi f - A u (the first moment of f_eq is A u), then
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     jr1 = k3 * (jr1 - A1 * ur);
     jz2 = k3 * (jz2 - A2 * uz);
     jr2 = k3 * (jr2 - A2 * ur);
-    double se0 = 0.0, se1 = 0.0, se2 = 0.0;   // equilibria of the eight moving directions
+    SE se0 = 0, se1 = 0, se2 = 0;   // equilibria of the eight moving directions
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q), wdt = w * dtc;
@@ -474,9 +479,9 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     }
     // the rest population (no first-order part): the moment minus the other eight, as for BGK
     const C wdt = WQ<C>(0) * dtc;
-    stv(gout + oo32, (C)((double)dA0 - se0) + wdt * F0);
-    stv(gout + 9 * plane + oo32, (C)((double)A1 - se1) + wdt * F1);
-    stv(gout + 18 * plane + oo32, (C)((double)A2 - se2) + wdt * F2);
+    stv(gout + oo32, (C)((SE)dA0 - se0) + wdt * F0);
+    stv(gout + 9 * plane + oo32, (C)((SE)A1 - se1) + wdt * F1);
+    stv(gout + 18 * plane + oo32, (C)((SE)A2 - se2) + wdt * F2);
   }
   stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
   stv(Mout + plane + oo, A1 + dtc * F1);
