@@ -64,6 +64,24 @@ Readings of the paper (where it is silent, garbled or inconsistent; each is list
              Hermite projection w_i xi_i . j_neq / c_s^2, j_neq = sum_i xi_i (f_i - f_eq_i),
              before relaxing with tau (every non-equilibrium moment above the first is dropped).
       Both relax the first moment exactly as BGK does, so D of Eq. (12) is unchanged.
+  R30 Particle driver (Sec. II: the bunch as macroparticles obeying Eq. (1), coupled through the
+      currents projected on the grid).  Macroparticles in 3D Cartesian (x, y, z, p_x, p_y, p_z)
+      with weights w (electrons, in units of n_0 / k_p^3).  State after k steps: positions at
+      t_{k-1}, momenta at t_{k-1/2}.  Step k: positions move by dt p/gamma to t_k; the current
+      w beta at the midpoint is J_b(t_{k-1/2}) of Ampere's law (z and r components); after the
+      fields and the fluid, a Boris push with E^k and B^k = (B^{k-1/2} + B^{k+1/2})/2 at the
+      new position gives the momenta at t_{k+1/2}.  Projection and interpolation are linear in
+      z onto the field's own points and linear in r between its rows: rows r_j = (j + 1/2) dr
+      for E_z and densities (the row below the axis folds onto row 0), rows (j + 1) dr for E_r
+      and B_theta (their axis value is zero; a share below the first row is dropped).  A node's
+      density is its share of w over the annular volume 2 pi r dz dr of the node (charge is
+      conserved exactly; rows j >= 1 are exact for a uniform density, row 0 collects 13/12 of
+      it because of the fold, as linear weighting in cylindrical geometry does).  A particle
+      whose stencil at the midpoint or at the new position (in the window frames before and
+      after the step's shift) leaves columns [1, nz - 2] or the rows is lost: its weight is set
+      to zero and it no longer moves.  The initial field is the discrete Gauss field of the
+      deposited bunch density (positions at t = -dt for E_r, at t = -dt/2 for B_theta, with
+      B_theta = E_r as for the rigid driver).
 
 State after k completed steps (k = 0 is the initial state):
     g  [3][9][nr][nz]   post-collision populations of step k-1 (raw values, not deviations)
@@ -111,6 +129,7 @@ class Params:
 
     def __init__(self, cfg: dict, theta: dict | None = None):
         self.nz, self.nr = int(cfg["nz"]), int(cfg["nr"])
+        self.driver = int(cfg.get("driver", 0))    # 0 rigid bi-Gaussian, 1 macroparticles (R30)
         self.h = float(cfg["dz"])
         if abs(float(cfg["dr"]) - self.h) > 1e-12 * self.h:
             raise ValueError("the lattice needs dz == dr")
@@ -191,6 +210,140 @@ def gauss_field(z, t: float, P: Params):
     Finite-volume form of (1/r) d(r E_r)/dr = -n_b on the rows j: E_r at r = (j+1) dr is
     -(dr / (j+1)) * sum_{j' <= j} (j' + 1/2) n_b(r_j').  For beta_b = 1, B_theta = E_r."""
     nb = driver_density(z, P.r, t, P)
+    cum = torch.cumsum((P.jj + 0.5) * nb, dim=0)
+    return -P.h * cum / (P.jj + 1.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Particle driver: macroparticles of Eq. (1) and their projection on the grid (reading R30)
+# ---------------------------------------------------------------------------------------------
+
+def _stencil(z, r, s: int, P: Params, zoff: float, edge: bool):
+    """Linear weights of lab positions (z, r) onto the nodes z = (s + i + zoff) dz and the rows
+    r_j = (j + 1/2) dr (edge False) or (j + 1) dr (edge True).  Returns (i0, fz, j0, fr): node
+    pairs (i0, i0 + 1) with weights (1 - fz, fz) and (j0, j0 + 1) with (1 - fr, fr)."""
+    u = z / P.h - s - zoff
+    v = r / P.h - (1.0 if edge else 0.5)
+    i0 = torch.floor(u)
+    j0 = torch.floor(v)
+    return i0.long(), u - i0, j0.long(), v - j0
+
+
+def _inside(z, r, s: int, P: Params, zoff: float, edge: bool):
+    """The stencil lies in columns [1, nz - 2] and in the rows (row -1 is the fold or the axis)."""
+    i0, _, j0, _ = _stencil(z, r, s, P, zoff, edge)
+    return (i0 >= 1) & (i0 + 1 <= P.nz - 2) & (j0 >= -1) & (j0 + 1 <= P.nr - 1)
+
+
+def deposit(val, z, r, s: int, P: Params, zoff: float, edge: bool):
+    """Node densities [nr][nz] of the particle quantities val (weights included): each share over
+    the node's annular volume 2 pi r_node dz dr (R30).  Particles whose stencil is not inside
+    contribute nothing."""
+    ok = _inside(z, r, s, P, zoff, edge)
+    i0, fz, j0, fr = _stencil(z[ok], r[ok], s, P, zoff, edge)
+    v = val[ok]
+    out = torch.zeros(P.nr, P.nz, dtype=DT)
+    for di, wz in ((0, 1.0 - fz), (1, fz)):
+        for dj, wr in ((0, 1.0 - fr), (1, fr)):
+            j = j0 + dj
+            if edge:
+                keep = j >= 0                    # the axis node of E_r / J_r carries nothing
+            else:
+                keep = torch.ones_like(j, dtype=torch.bool)
+                j = torch.clamp(j, min=0)        # the row below the axis folds onto row 0
+            out.index_put_((j[keep], (i0 + di)[keep]), (v * wz * wr)[keep], accumulate=True)
+    rnode = (P.jj + (1.0 if edge else 0.5)) * P.h
+    return out / (2.0 * math.pi * rnode * P.h * P.h)
+
+
+def gather(F, z, r, s: int, P: Params, zoff: float, edge: bool):
+    """F [nr][nz] interpolated at the particles with the same weights as deposit; E_r and
+    B_theta (edge rows) are zero on the axis, E_z (centre rows) is even across it.  Only
+    meaningful for particles whose stencil is inside."""
+    i0, fz, j0, fr = _stencil(z, r, s, P, zoff, edge)
+    i0 = torch.clamp(i0, 0, P.nz - 2)
+    out = torch.zeros_like(z)
+    for di, wz in ((0, 1.0 - fz), (1, fz)):
+        for dj, wr in ((0, 1.0 - fr), (1, fr)):
+            j = torch.clamp(j0 + dj, -1, P.nr - 1)
+            val = F[torch.clamp(j, min=0), i0 + di]
+            if edge:
+                val = torch.where(j >= 0, val, torch.zeros_like(val))
+            out = out + wz * wr * val
+    return out
+
+
+def boris(p, E, B, dt: float):
+    """Boris push for dp/dt = -(E + beta x B) (Eq. (1) with the electron charge, normalised):
+    half electric kick, rotation about B through 2 atan(|B| dt / (2 gamma)), half kick.
+    p, E, B: [3][N] Cartesian."""
+    pm = p - 0.5 * dt * E
+    gam = torch.sqrt(1.0 + (pm * pm).sum(0))
+    t = -0.5 * dt * B / gam
+    pp = pm + torch.cross(pm, t, dim=0)
+    sv = 2.0 * t / (1.0 + (t * t).sum(0))
+    return pm + torch.cross(pp, sv, dim=0) - 0.5 * dt * E
+
+
+def _beta(p):
+    return p / torch.sqrt(1.0 + (p * p).sum(0))
+
+
+def bunch_move(bunch, k: int, s: int, P: Params):
+    """Particle part of step k before the fields: positions from t_{k-1} to t_k, and the
+    driver current J_b(t_{k-1/2}) = sum w beta at the midpoints on the E_z and E_r points.
+    Returns (bunch', J_bz, J_br)."""
+    x, p, w = bunch[0:3], bunch[3:6], bunch[6]
+    beta = _beta(p)
+    xn = x + P.dt * beta
+    xm = 0.5 * (x + xn)
+    rm = torch.sqrt(xm[0] ** 2 + xm[1] ** 2)
+    rn = torch.sqrt(xn[0] ** 2 + xn[1] ** 2)
+    ok = w != 0.0
+    for zz, rr, zoff, edge in ((xm[2], rm, 0.5, False), (xm[2], rm, 0.0, True),
+                               (xn[2], rn, 0.5, False), (xn[2], rn, 0.0, True), (xn[2], rn, 0.5, True)):
+        ok = ok & _inside(zz, rr, s, P, zoff, edge)
+    out = bunch.clone()
+    out[0:3] = torch.where(ok, xn, x)
+    out[6] = torch.where(ok, w, torch.zeros_like(w))
+    wl = out[6]
+    br = torch.where(rm > 0.0, (xm[0] * beta[0] + xm[1] * beta[1]) / torch.where(rm > 0.0, rm, 1.0),
+                     torch.zeros_like(rm))
+    Jbz = deposit(wl * beta[2], xm[2], rm, s, P, 0.5, False)
+    Jbr = deposit(wl * br, xm[2], rm, s, P, 0.0, True)
+    return out, Jbz, Jbr
+
+
+def bunch_push(bunch, Ez1, Er1, B0, B1, s: int, P: Params):
+    """Particle part of step k after the fields: momenta from t_{k-1/2} to t_{k+1/2} with E^k and
+    B^k = (B^{k-1/2} + B^{k+1/2})/2 at the positions at t_k (arrays in the frame before the
+    step's window shift).  Lost particles (w = 0) keep their momenta."""
+    x, p, w = bunch[0:3], bunch[3:6], bunch[6]
+    r = torch.sqrt(x[0] ** 2 + x[1] ** 2)
+    ez = gather(Ez1, x[2], r, s, P, 0.5, False)
+    er = gather(Er1, x[2], r, s, P, 0.0, True)
+    bt = 0.5 * (gather(B0, x[2], r, s, P, 0.5, True) + gather(B1, x[2], r, s, P, 0.5, True))
+    safe = torch.where(r > 0.0, r, torch.ones_like(r))
+    cx = torch.where(r > 0.0, x[0] / safe, torch.zeros_like(r))
+    cy = torch.where(r > 0.0, x[1] / safe, torch.zeros_like(r))
+    E = torch.stack([er * cx, er * cy, ez])
+    B = torch.stack([-bt * cy, bt * cx, torch.zeros_like(bt)])
+    pn = boris(p, E, B, P.dt)
+    out = bunch.clone()
+    out[3:6] = torch.where(w != 0.0, pn, p)
+    return out
+
+
+def bunch_density(bunch, s: int, P: Params, zoff: float, t_ahead: float = 0.0):
+    """Bunch density on the nodes z = (s + i + zoff) dz, rows r_j, with the positions moved by
+    t_ahead along their velocities."""
+    x = bunch[0:3] + t_ahead * _beta(bunch[3:6])
+    r = torch.sqrt(x[0] ** 2 + x[1] ** 2)
+    return deposit(bunch[6], x[2], r, s, P, zoff, False)
+
+
+def bunch_gauss_field(nb, P: Params):
+    """E_r of the discrete Gauss law for the density nb [nr][nz] (as gauss_field)."""
     cum = torch.cumsum((P.jj + 0.5) * nb, dim=0)
     return -P.h * cum / (P.jj + 1.0)
 
@@ -325,8 +478,9 @@ def _above_copy(X):
 # Field update: Eq. (5), Yee scheme (R2, R12, R13, R17)
 # ---------------------------------------------------------------------------------------------
 
-def field_update(Ez, Er, B, Mp, k: int, s: int, P: Params):
-    """Ampere then Faraday: returns (E_z^k, E_r^k, B^{k+1/2}) from (E^{k-1}, B^{k-1/2}, A*^{k-1})."""
+def field_update(Ez, Er, B, Mp, k: int, s: int, P: Params, Jb=None):
+    """Ampere then Faraday: returns (E_z^k, E_r^k, B^{k+1/2}) from (E^{k-1}, B^{k-1/2}, A*^{k-1}).
+    Jb: the particle driver's (J_bz, J_br) at t_{k-1/2} (R30); None for the rigid driver."""
     h, dt = P.h, P.dt
     jj = P.jj
     # (curl B)_z = (1/r) d(r B)/dr at E_z points; the r = 0 edge flux vanishes.
@@ -336,10 +490,13 @@ def field_update(Ez, Er, B, Mp, k: int, s: int, P: Params):
     Jz, Jr = current(Mp, P)
     Jz_face = 0.5 * (Jz[1:-1, 1:-1] + Jz[1:-1, 2:])
     Jr_face = 0.5 * (Jr[1:-1, 1:-1] + Jr[2:, 1:-1])
-    zE = (s + P.ii + 0.5) * h
-    Jb = driver_density(zE, P.r, (k - 0.5) * dt, P)
-    Ez1 = Ez + dt * (curl_z + Jz_face + Jb)
-    Er1 = Er + dt * (curl_r + Jr_face)
+    if Jb is None:
+        zE = (s + P.ii + 0.5) * h
+        Jbz, Jbr = driver_density(zE, P.r, (k - 0.5) * dt, P), 0.0
+    else:
+        Jbz, Jbr = Jb
+    Ez1 = Ez + dt * (curl_z + Jz_face + Jbz)
+    Er1 = Er + dt * (curl_r + Jr_face + Jbr)
     # dB_theta/dt = dE_z/dr - dE_r/dz
     B1 = B + dt * ((_above_copy(Ez1) - Ez1) / h - (_right(Er1, P) - Er1) / h)
     return Ez1, Er1, B1
@@ -394,19 +551,22 @@ def fluid_update(g, Mp, Ebar_z, Ebar_r, Bbar, P: Params):
 # ---------------------------------------------------------------------------------------------
 
 class State:
-    __slots__ = ("g", "M", "Ez", "Er", "B", "k", "s")
+    __slots__ = ("g", "M", "Ez", "Er", "B", "k", "s", "bunch")
 
-    def __init__(self, g, M, Ez, Er, B, k=0, s=0):
+    def __init__(self, g, M, Ez, Er, B, k=0, s=0, bunch=None):
         self.g, self.M, self.Ez, self.Er, self.B, self.k, self.s = g, M, Ez, Er, B, k, s
+        self.bunch = bunch   # [7][N]: x, y, z, p_x, p_y, p_z, w (R30), or None
 
     def clone(self):
         return State(self.g.clone(), self.M.clone(), self.Ez.clone(), self.Er.clone(),
-                     self.B.clone(), self.k, self.s)
+                     self.B.clone(), self.k, self.s, None if self.bunch is None else self.bunch.clone())
 
 
-def initial_state(P: Params, n_pert=None, p_init=None) -> State:
+def initial_state(P: Params, n_pert=None, p_init=None, bunch=None) -> State:
     """Plasma at its local equilibrium with density n_bg(z)(1 + n_pert) and momentum p_init,
-    the driver's discrete Gauss field E_r^{-1} at t = -dt and B^{-1/2} at t = -dt/2, E_z = 0."""
+    the driver's discrete Gauss field E_r^{-1} at t = -dt and B^{-1/2} at t = -dt/2, E_z = 0.
+    bunch: [7][N] macroparticles (positions at t = -dt, momenta at t = -dt/2) for the particle
+    driver (R30)."""
     z = P.ii * P.h
     nbg = n_background(z, P) * torch.ones(P.nr, 1, dtype=DT)
     n = nbg if n_pert is None else nbg * (1.0 + torch.as_tensor(n_pert, dtype=DT))
@@ -420,12 +580,19 @@ def initial_state(P: Params, n_pert=None, p_init=None) -> State:
     bz, br, _ = velocity(M, P)
     g = torch.stack([equilibrium(M[kk], P.lam * bz, P.lam * br) for kk in range(3)])
     zeros = torch.zeros(P.nr, P.nz, dtype=DT)
-    if P.fields_on:
+    bt = None if bunch is None else torch.as_tensor(bunch, dtype=DT).clone()
+    if P.fields_on and P.driver == 1:
+        if bt is None:
+            Er, B = zeros.clone(), zeros.clone()
+        else:
+            Er = bunch_gauss_field(bunch_density(bt, 0, P, 0.0), P)
+            B = bunch_gauss_field(bunch_density(bt, 0, P, 0.5, 0.5 * P.dt), P)
+    elif P.fields_on:
         Er = gauss_field(z, -P.dt, P)
         B = gauss_field(z + 0.5 * P.h, -0.5 * P.dt, P)
     else:
         Er, B = zeros.clone(), zeros.clone()
-    return State(g, M, zeros.clone(), Er, B, 0, 0)
+    return State(g, M, zeros.clone(), Er, B, 0, 0, bt if P.driver == 1 else None)
 
 
 def shift_due(k: int, P: Params) -> bool:
@@ -436,13 +603,19 @@ def shift_due(k: int, P: Params) -> bool:
 def step(S: State, P: Params) -> State:
     """Advance the state by one step (module docstring, steps 1-4)."""
     Mp = padded_moments(S.M, P, S.s)
+    bunch, Jb = S.bunch, None
+    if bunch is not None:
+        bunch, Jbz, Jbr = bunch_move(bunch, S.k, S.s, P)
+        Jb = (Jbz, Jbr)
     if P.fields_on:
-        Ez1, Er1, B1 = field_update(S.Ez, S.Er, S.B, Mp, S.k, S.s, P)
+        Ez1, Er1, B1 = field_update(S.Ez, S.Er, S.B, Mp, S.k, S.s, P, Jb)
         Ebz, Ebr, Bb = fields_at_sites(Ez1, Er1, S.B, B1, P)
     else:
         Ez1, Er1, B1 = S.Ez, S.Er, S.B
         Ebz = Ebr = Bb = torch.zeros(P.nr, P.nz, dtype=DT)
     g1, M1 = fluid_update(S.g, Mp, Ebz, Ebr, Bb, P)
+    if bunch is not None:
+        bunch = bunch_push(bunch, Ez1, Er1, S.B, B1, S.s, P)
     s = S.s
     if shift_due(S.k, P):
         nf = n_background(_t((s + P.nz) * P.h), P)
@@ -459,13 +632,13 @@ def step(S: State, P: Params) -> State:
         Er1 = torch.cat([Er1[:, 1:], zc], dim=-1)
         B1 = torch.cat([B1[:, 1:], zc], dim=-1)
         s += 1
-    return State(g1, M1, Ez1, Er1, B1, S.k + 1, s)
+    return State(g1, M1, Ez1, Er1, B1, S.k + 1, s, bunch)
 
 
-def run(cfg: dict, nsteps: int, n_pert=None, p_init=None, theta=None, callback=None):
+def run(cfg: dict, nsteps: int, n_pert=None, p_init=None, theta=None, callback=None, bunch=None):
     """Initial state plus nsteps steps; returns (final state, Params)."""
     P = Params(cfg, theta)
-    S = initial_state(P, n_pert, p_init)
+    S = initial_state(P, n_pert, p_init, bunch)
     for _ in range(nsteps):
         S = step(S, P)
         if callback is not None:
@@ -496,7 +669,11 @@ def gauss_residual(S: State, P: Params):
     div = (S.Ez - _left(S.Ez, P)) / h \
         + ((jj + 1.0) * S.Er - jj * _below_axis_zero(S.Er)) / ((jj + 0.5) * h)
     z = (S.s + P.ii) * h
-    rho = n_background(z, P) - S.M[0] - driver_density(z, P.r, (S.k - 1) * P.dt, P)
+    if P.driver == 1:
+        nb = torch.zeros_like(S.M[0]) if S.bunch is None else bunch_density(S.bunch, S.s, P, 0.0)
+    else:
+        nb = driver_density(z, P.r, (S.k - 1) * P.dt, P)
+    rho = n_background(z, P) - S.M[0] - nb
     return (div - rho)[:, 1:]
 
 

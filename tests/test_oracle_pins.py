@@ -552,3 +552,191 @@ def test_collision_operators_conserve_per_site():
                         seed=4, moving_window=1, collision=collision)
         S, _ = _run(cfg, 9, wl.density_perturbation(cfg), wl.random_momentum(cfg, 0.1))
         assert float((S.g.sum(1) - S.M).abs().max()) < 1e-14
+
+
+# --- particle driver (Sec. II, Eq. (1); reading R30) ---------------------------------------------
+
+def _quadrature_bunch(cfg, nzq=64, nrq=48, nphi=4, beta_z_gamma=1e4):
+    """A smooth bi-Gaussian bunch as a dense deterministic quadrature: particles on a polar grid
+    (rings of nphi particles at radii (m + 1/2) dq_r, slices at z spacing dq_z), each carrying the
+    rigid driver's density times its quadrature volume, all at p_z = beta_z_gamma, positions at
+    t = -dt (the rigid driver's centre then)."""
+    sr, sz, nb = cfg["sigma_r"], cfg["sigma_z"], cfg["nb"]
+    dt = cfg["c_dt_over_dz"] * cfg["dz"]
+    zc = cfg["zd0"] - dt
+    dqz = 8.0 * sz / nzq / 4.0
+    dqr = 4.0 * sr / nrq / 2.0
+    zs = zc + (np.arange(4 * nzq) - 2 * nzq + 0.5) * dqz
+    rs = (np.arange(2 * nrq) + 0.5) * dqr
+    phis = (np.arange(nphi) + 0.25) * 2.0 * np.pi / nphi
+    Z, R, PH = np.meshgrid(zs, rs, phis, indexing="ij")
+    Z, R, PH = Z.ravel(), R.ravel(), PH.ravel()
+    dens = nb * np.exp(-(Z - zc) ** 2 / (2 * sz * sz)) * np.exp(-R ** 2 / (2 * sr * sr))
+    vol = R * dqr * dqz * (2.0 * np.pi / nphi)
+    out = np.zeros((7, Z.size))
+    out[0], out[1], out[2] = R * np.cos(PH), R * np.sin(PH), Z
+    out[5] = beta_z_gamma
+    out[6] = dens * vol
+    return out
+
+
+def test_boris_uniform_magnetic_field_rotates_exactly():
+    """Pure B along z: |p| is conserved to round-off and each step rotates p_perp by exactly
+    2 atan(|B| dt / (2 gamma)) (the Boris rotation angle), clockwise for the electron charge."""
+    p = torch.tensor([[0.3], [0.0], [0.7]], dtype=F64)
+    E = torch.zeros(3, 1, dtype=F64)
+    B = torch.tensor([[0.0], [0.0], [0.9]], dtype=F64)
+    dt = 0.05
+    gam = math.sqrt(1.0 + float((p * p).sum()))
+    ang = 2.0 * math.atan(0.9 * dt / (2.0 * gam))
+    q = p.clone()
+    for k in range(1, 101):
+        q = O.boris(q, E, B, dt)
+        phi = math.atan2(float(q[1, 0]), float(q[0, 0]))
+        expect = math.remainder(+k * ang, 2 * math.pi)   # dp/dt = -beta x B: positive rotation
+        assert abs(math.remainder(phi - expect, 2 * math.pi)) < 1e-12
+    assert abs(float((q * q).sum()) - float((p * p).sum())) < 1e-14
+    assert abs(float(q[2, 0]) - 0.7) < 1e-15
+
+
+def test_boris_uniform_electric_field_kicks_exactly():
+    p = torch.tensor([[0.1], [-0.2], [3.0]], dtype=F64)
+    E = torch.tensor([[0.02], [0.01], [-0.5]], dtype=F64)
+    q = p.clone()
+    for _ in range(40):
+        q = O.boris(q, E, torch.zeros(3, 1, dtype=F64), 0.01)
+    assert float((q - (p - 40 * 0.01 * E)).abs().max()) < 1e-14
+
+
+def _rand_particles(P, n, seed, r_max):
+    g = torch.Generator().manual_seed(seed)
+    z = (2.0 + (P.nz - 5) * torch.rand(n, generator=g, dtype=F64)) * P.h
+    r = r_max * torch.rand(n, generator=g, dtype=F64)
+    return z, r, torch.rand(n, generator=g, dtype=F64)
+
+
+def test_deposit_conserves_charge_and_is_the_transpose_of_gather():
+    cfg = wl.config(None, nz=40, nr=12, dz=0.1, dr=0.1)
+    P = O.Params(cfg)
+    z, r, w = _rand_particles(P, 500, 3, 0.9)
+    vol_c = 2 * math.pi * P.r * P.h * P.h
+    vol_e = 2 * math.pi * P.r_edge * P.h * P.h
+    for zoff, edge, vol in ((0.0, False, vol_c), (0.5, False, vol_c), (0.0, True, vol_e), (0.5, True, vol_e)):
+        n = O.deposit(w, z, r, 0, P, zoff, edge)
+        if not edge:   # the centre rows keep every share (the fold); the edge rows drop the axis share
+            assert abs(float((n * vol).sum()) - float(w.sum())) < 1e-12 * float(w.sum())
+        F = torch.rand(P.nr, P.nz, generator=torch.Generator().manual_seed(7), dtype=F64)
+        lhs = float((F * n * vol).sum())
+        rhs = float((w * O.gather(F, z, r, 0, P, zoff, edge)).sum())
+        assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+
+
+def test_gather_reproduces_linear_fields():
+    cfg = wl.config(None, nz=40, nr=12, dz=0.1, dr=0.1)
+    P = O.Params(cfg)
+    z, r, _ = _rand_particles(P, 300, 5, 1.0)
+    zc = (P.ii + 0.5) * P.h
+    # E_z-type (centre rows) field a + b z + c r, away from the fold (r >= dr / 2)
+    F = 0.3 + 0.7 * zc - 1.1 * P.r
+    keep = r >= 0.5 * P.h
+    got = O.gather(F, z, r, 0, P, 0.5, False)[keep]
+    assert float((got - (0.3 + 0.7 * z - 1.1 * r)[keep]).abs().max()) < 1e-13
+    # E_r-type (edge rows, zero on the axis) field r (a + b z): exact down to the axis
+    F = P.r_edge * (0.4 - 0.2 * P.ii * P.h)
+    got = O.gather(F, z, r, 0, P, 0.0, True)
+    assert float((got - r * (0.4 - 0.2 * z)).abs().max()) < 1e-13
+
+
+def test_deposit_brute_force():
+    cfg = wl.config(None, nz=12, nr=5, dz=0.1, dr=0.1)
+    P = O.Params(cfg)
+    z, r, w = _rand_particles(P, 40, 9, 0.45)
+    for zoff, edge in ((0.5, False), (0.0, True)):
+        ref = np.zeros((P.nr, P.nz))
+        for zz, rr, ww in zip(z.tolist(), r.tolist(), w.tolist()):
+            u = zz / P.h - zoff
+            v = rr / P.h - (1.0 if edge else 0.5)
+            i0, j0 = math.floor(u), math.floor(v)
+            if not (1 <= i0 <= P.nz - 3 and -1 <= j0 <= P.nr - 2):
+                continue
+            for di, wz in ((0, 1 - (u - i0)), (1, u - i0)):
+                for dj, wr in ((0, 1 - (v - j0)), (1, v - j0)):
+                    j = j0 + dj
+                    if j < 0:
+                        if edge:
+                            continue
+                        j = 0
+                    rn = (j + (1.0 if edge else 0.5)) * P.h
+                    ref[j, i0 + di] += ww * wz * wr / (2 * math.pi * rn * P.h * P.h)
+        got = O.deposit(w, z, r, 0, P, zoff, edge).numpy()
+        assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_particle_bunch_reproduces_the_rigid_driver_current():
+    """A dense smooth bunch at gamma = 1e4 (quadrature spacing dz/4): the deposited J_bz at
+    t_{-1/2} equals the rigid driver's n_b(z - t) at the E_z points of rows j >= 1 to the linear
+    shape's O(dz^2) smoothing (2 % of the peak).  Row 0 collects the share folded from below the
+    axis: a smooth density comes out 13/12 times its axis value (R30), here to 3 %."""
+    cfg = wl.config(None, nz=80, nr=24, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3, zd0=2.0,
+                    driver=1)
+    P = O.Params(cfg)
+    b = torch.as_tensor(_quadrature_bunch(cfg), dtype=F64)
+    _, Jbz, Jbr = O.bunch_move(b, 0, 0, P)
+    ref = O.driver_density((P.ii + 0.5) * P.h, P.r, -0.5 * P.dt, P)
+    assert float((Jbz[1:] - ref[1:]).abs().max()) < 0.02 * float(ref.max())
+    peak = int(torch.argmax(ref[0]))
+    assert abs(float(Jbz[0, peak] / ref[0, peak]) - 13.0 / 12.0) < 0.03
+    assert float(Jbr.abs().max()) < 1e-12
+
+
+def test_particle_driver_wake_matches_the_rigid_driver():
+    """The rigid driver is the gamma -> infinity limit of the particle driver: over 60 coupled steps
+    with the window moving, the fields and density of the two runs agree to the projection's
+    smoothing (3 % of the wake amplitudes), and the bunch stays unchanged in shape (gamma = 1e4)."""
+    base = dict(nz=100, nr=28, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3, zd0=2.6,
+                moving_window=1)   # the whole bunch (4 sigma) inside the window
+    cfg_r = wl.config(None, **base)
+    cfg_p = wl.config(None, driver=1, **base)
+    Sr, P = _run(cfg_r, 60)
+    b = _quadrature_bunch(cfg_p)
+    Sp, _ = O.run(cfg_p, 60, bunch=b)
+    for a, c in ((Sp.Ez, Sr.Ez), (Sp.Er, Sr.Er), (Sp.B, Sr.B), (Sp.M[0] - Sr.M[0], None)):
+        if c is None:
+            continue
+        assert float((a - c).abs().max()) < 0.03 * float(c.abs().max())
+    dn_p = Sp.M[0] - 1.0
+    dn_r = Sr.M[0] - 1.0
+    assert float((dn_p - dn_r).abs().max()) < 0.03 * float(dn_r.abs().max())
+    assert float(Sp.bunch[6].min()) > 0.0                      # no particle lost
+    assert (Sp.k, Sp.s) == (60, 12)
+
+
+def test_particle_driver_initial_gauss_law_is_exact():
+    cfg = wl.config(None, nz=60, nr=16, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3, zd0=1.5, driver=1)
+    P = O.Params(cfg)
+    b = wl.bunch(cfg, 3000, seed=2)
+    S = O.initial_state(P, None, None, b)
+    assert float(S.Er.abs().max()) > 1e-3
+    assert float(O.gauss_residual(S, P).abs().max()) < 1e-14
+
+
+def test_free_particle_moves_exactly_and_is_lost_at_the_window_edge():
+    """Fields off: positions advance by dt p / gamma per step; a particle heading out of the
+    columns [1, nz - 2] is frozen with zero weight once its stencil would leave them."""
+    cfg = wl.config(None, nz=30, nr=8, dz=0.1, dr=0.1, driver=1, fields_on=0)
+    P = O.Params(cfg)
+    b = torch.zeros(7, 2, dtype=F64)
+    b[0:3, 0] = torch.tensor([0.05, 0.02, 1.0])
+    b[3:6, 0] = torch.tensor([0.0, 0.0, 2.0])
+    b[0:3, 1] = torch.tensor([0.03, 0.0, 0.5])
+    b[3:6, 1] = torch.tensor([0.0, 0.0, -3.0])
+    b[6] = 1.0
+    S = O.initial_state(P, None, None, b)
+    v0 = 2.0 / math.sqrt(5.0)
+    for k in range(30):
+        S = O.step(S, P)
+        assert abs(float(S.bunch[2, 0]) - (1.0 + (k + 1) * P.dt * v0)) < 1e-13
+    assert float(S.bunch[6, 0]) == 1.0
+    assert float(S.bunch[6, 1]) == 0.0        # the backward particle left through the rear edge
+    z1 = float(S.bunch[2, 1])
+    assert 0.15 <= z1 < 0.15 + 0.02           # frozen where its midpoint stencil still fit column 1

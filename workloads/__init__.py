@@ -29,6 +29,7 @@ import numpy as np
 
 F64, F32, F16 = 0, 1, 2
 BGK, TRT, REG = 0, 1, 2
+RIGID, PARTICLES = 0, 1
 
 # Field names and order of the C configuration struct (see include/lbmpwfa.h).
 CONFIG_FIELDS = (
@@ -36,7 +37,7 @@ CONFIG_FIELDS = (
     "moving_window", "periodic", "fields_on", "cyl_on",
     "n0", "ramp_kind", "ramp_start", "ramp_len",
     "nb", "sigma_z", "sigma_r", "zd0", "n_floor", "check_every", "fp64_math",
-    "collision", "trt_magic",
+    "collision", "trt_magic", "driver", "max_particles",
 )
 
 _BASE = dict(
@@ -44,7 +45,7 @@ _BASE = dict(
     moving_window=0, periodic=0, fields_on=1, cyl_on=1,
     n0=1.0, ramp_kind=0, ramp_start=0.0, ramp_len=1.0,
     nb=0.0, sigma_z=0.5, sigma_r=0.5, zd0=0.0, n_floor=1e-10, check_every=0, fp64_math=0,
-    collision=0, trt_magic=0.25,
+    collision=0, trt_magic=0.25, driver=0, max_particles=0,
     # workload-level fields (not part of the C struct)
     noise_amp=0.0, seed=0, nsteps=1, z_behind=4.0,
 )
@@ -166,3 +167,31 @@ def gaussian_bump(cfg: dict, amp: float, sz: float | None, sr: float | None,
     fz = np.ones(nz) if sz is None else np.exp(-(z - zc) ** 2 / (2 * sz * sz))
     fr = np.ones(nr) if sr is None else np.exp(-(r - rc) ** 2 / (2 * sr * sr))
     return amp * fr[:, None] * fz[None, :]
+
+
+def bunch(cfg: dict, n: int, gamma: float = 5000.0, emittance: float = 0.0, energy_spread: float = 0.0,
+          seed: int = 5) -> np.ndarray:
+    """Seeded bi-Gaussian macroparticle bunch, [7][n]: x, y, z, p_x, p_y, p_z, w.
+
+    Positions: Gaussian with rms sigma_r in x and y and sigma_z in z around (0, 0, zd0 - dt), the
+    rigid driver's centre at t = -dt (dt = c_dt_over_dz * dz; for gamma >> 1 the bunch moves at
+    c).  Momenta at t = -dt/2: p_z = gamma (1 + energy_spread N(0, 1)) (p_z ~ gamma for the
+    electrons of the bunch), p_x and p_y Gaussian with rms emittance / sigma_r (the normalised
+    rms emittance in units of 1/k_p).  Weights: equal, so that the bunch holds the electrons of the
+    rigid driver's peak density n_b over its volume, n_b (2 pi)^(3/2) sigma_r^2 sigma_z, in units
+    of n_0 / k_p^3 (the paper's bunch of Sec. IV is of this shape: gamma = 5000, a 74 mm mrad
+    emittance and a 0.01 % energy spread).
+    """
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    sr, sz = float(cfg["sigma_r"]), float(cfg["sigma_z"])
+    dt = float(cfg["c_dt_over_dz"]) * float(cfg["dz"])
+    out = np.zeros((7, n))
+    out[0] = sr * rng.standard_normal(n)
+    out[1] = sr * rng.standard_normal(n)
+    out[2] = float(cfg["zd0"]) - dt + sz * rng.standard_normal(n)
+    pt = emittance / sr if sr > 0 else 0.0
+    out[3] = pt * rng.standard_normal(n)
+    out[4] = pt * rng.standard_normal(n)
+    out[5] = gamma * (1.0 + energy_spread * rng.standard_normal(n))
+    out[6] = float(cfg["nb"]) * (2.0 * np.pi) ** 1.5 * sr * sr * sz / n
+    return out
