@@ -62,6 +62,24 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
  *            dropped. */
 enum { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2 };
 
+/* Driver of the wake.  The paper drives the plasma with the electron bunch of its hybrid code:
+ * macroparticles moved by the Lorentz force (Sec. II, Eq. (1)) whose current, projected on the
+ * grid, enters Ampere's law.
+ *   LBM_DRIVER_RIGID      a rigid bi-Gaussian bunch at c (its current and initial field are
+ *                         closed forms);
+ *   LBM_DRIVER_PARTICLES  macroparticles.  Each step moves them by dt p / gamma, projects their
+ *                         current w beta at the midpoints (linear in z onto the field points,
+ *                         linear in r between rows; the share below the axis folds onto row 0
+ *                         for densities and J_z, and is dropped for J_r, which vanishes there) as
+ *                         J_b(t_{k-1/2}) of Ampere's law (z and r components), and after the fields
+ *                         and the fluid pushes the momenta with the Boris scheme in E^k and
+ *                         B^k = (B^{k-1/2} + B^{k+1/2}) / 2 interpolated with the same weights.
+ *                         A particle whose stencil leaves columns [1, nz - 2] or the rows is lost
+ *                         (its weight set to zero, no longer moved).  Deposition uses atomic
+ *                         additions, so sums over particles are not ordered: results agree with an
+ *                         ordered sum to round-off, not bit for bit. */
+enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
+
 /* Run configuration.  Physical meaning (normalised units):
  *   nz, nr        grid size (both >= 3)
  *   dz, dr        cell size; must be equal (the D2Q9 lattice is square)
@@ -88,7 +106,11 @@ enum { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2 };
  *                 the first moment with 1/tau, so D of Eq. (12) is the same for all three
  *   trt_magic     LBM_TRT only: Lambda = (tau_plus - 1/2)(tau - 1/2) > 0, which fixes the
  *                 relaxation time tau_plus of the symmetric part; Lambda = (tau - 1/2)^2 is BGK.
- *                 Ignored otherwise. */
+ *                 Ignored otherwise.
+ *   driver        LBM_DRIVER_RIGID (nb, sigma_z, sigma_r, zd0 above) or LBM_DRIVER_PARTICLES
+ *                 (a macroparticle bunch set with lbm_set_bunch; nb .. zd0 are then unused)
+ *   max_particles LBM_DRIVER_PARTICLES: capacity of the bunch, in [0, 2^31); the workspace holds
+ *                 7 doubles per particle.  Ignored otherwise. */
 typedef struct {
   int32_t nz, nr;
   double dz, dr, c_dt_over_dz, tau;
@@ -103,6 +125,8 @@ typedef struct {
   int32_t fp64_math;
   int32_t collision;
   double trt_magic;
+  int32_t driver;
+  int64_t max_particles;
 } lbm_config;
 
 /* FP64 diagnostics of the current state (all sums over the window):
@@ -161,7 +185,9 @@ int lbm_set_state(lbm_ctx* ctx, const double* src, int64_t step, int64_t shifts)
  * a 64-byte header (magic, storage, nz, nr, step, shift count) followed by the active
  * population, moment and field buffers as stored.  lbm_checkpoint_bytes gives its size.
  * dst/src may be host or device memory (flag); both calls synchronise the stream.  lbm_load
- * returns LBM_EINVAL if the checkpoint was written for another grid or storage precision. */
+ * returns LBM_EINVAL if the checkpoint was written for another grid or storage precision.  The
+ * bunch of LBM_DRIVER_PARTICLES is not part of it: keep it with lbm_get_bunch and restore it with
+ * lbm_set_bunch(init_fields = 0). */
 int lbm_checkpoint_bytes(lbm_ctx* ctx, size_t* bytes);
 int lbm_save(lbm_ctx* ctx, void* dst, int32_t dst_on_device);
 int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);
@@ -234,6 +260,22 @@ int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
  * a row outside [0, nr), n_star <= 0 or a NaN bound. */
 int lbm_bubble_length(lbm_ctx* ctx, int32_t row, double n_star, double z_from, double z_to,
                       int64_t* count, double* length);
+
+/* Macroparticle bunch of LBM_DRIVER_PARTICLES (Sec. II, Eq. (1)), host memory, [7][n] row-major:
+ * x, y, z (lab frame, z along the axis), p_x, p_y, p_z (units of m_e c), w (electrons, in units of
+ * n_0 / k_p^3).  Positions are at t_{k-1} and momenta at t_{k-1/2} for a context after k steps
+ * (after lbm_init: positions at t = -dt, momenta at t = -dt/2).  n <= cfg.max_particles.
+ * init_fields = 1 (only at step 0) also sets the initial field from the bunch: E_z = 0, E_r and
+ * B_theta from the discrete Gauss law of the bunch density deposited at t = -dt (E_r) and at
+ * t = -dt/2 (B_theta, with B_theta = E_r as for a bunch at c); the fluid is not touched.
+ * init_fields = 0 keeps the fields (to resume a run).  Synchronising.  LBM_EINVAL for another
+ * driver, n out of range, or init_fields at a step other than 0. */
+int lbm_set_bunch(lbm_ctx* ctx, int64_t n, const double* bunch, int32_t init_fields);
+
+/* Current bunch, [7][n] in the layout of lbm_set_bunch, into host memory of at least 7 * n_max
+ * doubles; the number of particles goes to *n (lost particles included, with w = 0).  LBM_EINVAL
+ * if n_max is smaller.  Synchronising. */
+int lbm_get_bunch(lbm_ctx* ctx, double* bunch, int64_t n_max, int64_t* n);
 
 /* Step and window-shift counters of the state. */
 int lbm_counters(lbm_ctx* ctx, int64_t* step, int64_t* shifts);

@@ -39,6 +39,8 @@ class LbmConfig(ctypes.Structure):
         ("fp64_math", c_int32),
         ("collision", c_int32),
         ("trt_magic", c_double),
+        ("driver", c_int32),
+        ("max_particles", c_int64),
     ]
 
 
@@ -99,6 +101,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
                                           P(c_double), c_void_p, P(c_int64)]),
         "lbm_bubble_length": (c_int32, [c_void_p, c_int32, c_double, c_double, c_double, P(c_int64),
                                         P(c_double)]),
+        "lbm_set_bunch": (c_int32, [c_void_p, c_int64, c_void_p, c_int32]),
+        "lbm_get_bunch": (c_int32, [c_void_p, c_void_p, c_int64, P(c_int64)]),
         "lbm_destroy": (c_int32, [c_void_p]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -122,7 +126,7 @@ def make_config(cfg: dict) -> LbmConfig:
         v = cfg[name]
         if name == "storage" and isinstance(v, str):
             v = _STORAGE[v]
-        setattr(c, name, int(v) if ctype is c_int32 else float(v))
+        setattr(c, name, int(v) if ctype in (c_int32, c_int64) else float(v))
     return c
 
 
@@ -281,6 +285,24 @@ def lbm_bubble_length(ctx: int, row: int = 0, n_star: float = 0.95, z_from: floa
     return n.value, length.value
 
 
+def lbm_set_bunch(ctx: int, bunch, init_fields: bool = True):
+    """Upload a [7][n] macroparticle bunch (x, y, z, p_x, p_y, p_z, w); init_fields also sets the
+    initial field from it (step 0 only)."""
+    b = np.ascontiguousarray(np.asarray(bunch, dtype=np.float64))
+    if b.ndim != 2 or b.shape[0] != 7:
+        raise ValueError("bunch must have shape [7][n]")
+    _check(load_library().lbm_set_bunch(c_void_p(ctx), c_int64(b.shape[1]), b.ctypes.data_as(c_void_p),
+                                        c_int32(1 if init_fields else 0)))
+
+
+def lbm_get_bunch(ctx: int, n_max: int):
+    """The current bunch as a [7][n] float64 array (lost particles have w = 0)."""
+    out = np.zeros(7 * max(n_max, 1))
+    n = c_int64(0)
+    _check(load_library().lbm_get_bunch(c_void_p(ctx), out.ctypes.data_as(c_void_p), c_int64(n_max), ctypes.byref(n)))
+    return out[:7 * n.value].reshape(7, n.value)
+
+
 def lbm_counters(ctx: int):
     k, s = c_int64(0), c_int64(0)
     _check(load_library().lbm_counters(c_void_p(ctx), ctypes.byref(k), ctypes.byref(s)))
@@ -393,6 +415,12 @@ class Lattice:
     def bubble_length(self, row: int = 0, n_star: float = 0.95, z_from: float = -math.inf,
                       z_to: float = math.inf):
         return lbm_bubble_length(self.ctx, row, n_star, z_from, z_to)
+
+    def set_bunch(self, bunch, init_fields: bool = True):
+        lbm_set_bunch(self.ctx, bunch, init_fields)
+
+    def bunch(self):
+        return lbm_get_bunch(self.ctx, int(self.cfg.get("max_particles", 0)))
 
     def counters(self):
         return lbm_counters(self.ctx)

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "liblbmpwfa.so")
-SOURCES = ("csrc/lbm_kernels.hip", "csrc/lbm_adjoint.hip", "csrc/lbm_capi.cpp")
+SOURCES = ("csrc/lbm_kernels.hip", "csrc/lbm_adjoint.hip", "csrc/lbm_bunch.hip", "csrc/lbm_capi.cpp")
 HIPCC_FLAGS = (
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off (compiler-generated v_pk_* FP32 ops are avoided)

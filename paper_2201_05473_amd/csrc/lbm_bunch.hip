@@ -1,0 +1,230 @@
+// Particle driver (gfx950): the electron bunch as macroparticles of Sec. II, Eq. (1), coupled to
+// the grid through its projected current.
+//
+// The bunch is stored as SoA doubles [7][cap]: x, y, z (lab frame), p_x, p_y, p_z (m_e c units),
+// w (electrons, n_0 / k_p^3).  After k steps the positions are at t_{k-1} and the momenta at
+// t_{k-1/2}.  Step k runs:
+//   bunch_move_kernel  positions to t_k, current w beta at the midpoints -> J_b(t_{k-1/2}) (z at the
+//                      E_z points, r at the E_r points), hardware float atomics;
+//   (the step kernel reads J_b in Ampere's law)
+//   bunch_push_kernel  Boris push of the momenta to t_{k+1/2} with E^k and
+//                      B^k = (B^{k-1/2} + B^{k+1/2}) / 2 at the positions at t_k.
+// Projection and interpolation share one stencil: linear in z onto the field's own points, linear
+// in r between its rows, rows r_j = (j + 1/2) dr for E_z and densities (the row below the axis folds
+// onto row 0) or (j + 1) dr for E_r and B_theta (zero on the axis; the share below the first row is
+// dropped).  A particle whose stencil leaves columns [1, nz - 2] or the rows is lost: weight zero,
+// no longer moved.  One thread per particle; the bunch is small next to the grid.
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr int BT = 256;   // threads per block of the particle kernels
+constexpr double TWO_PI = 6.283185307179586;
+
+struct Stencil {
+  int i0, j0;     // lower node column and row
+  double fz, fr;  // weight of the upper node in z and in r
+};
+
+// Nodes z = (s + i + zoff) dz and rows (j + 1/2) dr (edge = false) or (j + 1) dr (edge = true).
+__device__ __forceinline__ Stencil stencil(const Physics& p, double z, double r, long long s, double zoff,
+                                           bool edge) {
+  const double u = z / p.h - (double)s - zoff;
+  const double v = r / p.h - (edge ? 1.0 : 0.5);
+  const double fi = floor(u), fj = floor(v);
+  Stencil st;
+  st.i0 = (int)fi;
+  st.j0 = (int)fj;
+  st.fz = u - fi;
+  st.fr = v - fj;
+  return st;
+}
+
+__device__ __forceinline__ bool inside(const Physics& p, const Stencil& st) {
+  return st.i0 >= 1 && st.i0 + 1 <= p.nz - 2 && st.j0 >= -1 && st.j0 + 1 <= p.nr - 1;
+}
+
+__device__ __forceinline__ void atomic_add(float* a, double v) { unsafeAtomicAdd(a, (float)v); }
+__device__ __forceinline__ void atomic_add(double* a, double v) { unsafeAtomicAdd(a, v); }
+
+// Adds val, spread over the stencil's nodes and divided by each node's annular volume
+// 2 pi r_node dz dr, to the pitched plane F.
+template <typename T>
+__device__ __forceinline__ void deposit(const Physics& p, const Stencil& st, bool edge, double val, T* F) {
+#pragma unroll
+  for (int di = 0; di < 2; ++di) {
+    const double wz = di ? st.fz : 1.0 - st.fz;
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      const double wr = dj ? st.fr : 1.0 - st.fr;
+      int j = st.j0 + dj;
+      if (j < 0) {
+        if (edge) continue;   // the axis node of E_r / J_r carries nothing
+        j = 0;                // the row below the axis folds onto row 0
+      }
+      const double rn = ((double)j + (edge ? 1.0 : 0.5)) * p.h;
+      atomic_add(F + (long long)j * p.pitch + (st.i0 + di), val * wz * wr / (TWO_PI * rn * p.h * p.h));
+    }
+  }
+}
+
+// F at the particle with the stencil's weights; col_shift maps the stencil's columns to the array's
+// (1 for an array written after a window shift).
+template <typename A>
+__device__ __forceinline__ double gather(const Physics& p, const Stencil& st, bool edge, const A* F, int col_shift) {
+  double out = 0.0;
+#pragma unroll
+  for (int di = 0; di < 2; ++di) {
+    const double wz = di ? st.fz : 1.0 - st.fz;
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      const double wr = dj ? st.fr : 1.0 - st.fr;
+      const int j = st.j0 + dj;
+      double val;
+      if (j < 0) val = edge ? 0.0 : (double)F[st.i0 + di - col_shift];
+      else val = (double)F[(long long)j * p.pitch + st.i0 + di - col_shift];
+      out = out + wz * wr * val;
+    }
+  }
+  return out;
+}
+
+template <int ST>
+__global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, double* b, int n, long long cap,
+                                                        void* jbv) {
+  using A = typename Mode<ST, false>::A;
+  const int q = blockIdx.x * BT + threadIdx.x;
+  if (q >= n) return;
+  const double w = b[6 * cap + q];
+  if (w == 0.0) return;
+  const double x = b[q], y = b[cap + q], z = b[2 * cap + q];
+  const double px = b[3 * cap + q], py = b[4 * cap + q], pz = b[5 * cap + q];
+  const double g = sqrt(1.0 + (px * px + py * py + pz * pz));
+  const double bx = px / g, by = py / g, bz = pz / g;
+  const double xn = x + p.dt * bx, yn = y + p.dt * by, zn = z + p.dt * bz;
+  const double xm = 0.5 * (x + xn), ym = 0.5 * (y + yn), zm = 0.5 * (z + zn);
+  const double rm = sqrt(xm * xm + ym * ym), rn = sqrt(xn * xn + yn * yn);
+  const Stencil jz = stencil(p, zm, rm, s, 0.5, false), jr = stencil(p, zm, rm, s, 0.0, true);
+  const bool ok = inside(p, jz) && inside(p, jr) && inside(p, stencil(p, zn, rn, s, 0.5, false)) &&
+                  inside(p, stencil(p, zn, rn, s, 0.0, true)) && inside(p, stencil(p, zn, rn, s, 0.5, true));
+  if (!ok) {
+    b[6 * cap + q] = 0.0;   // lost
+    return;
+  }
+  b[q] = xn;
+  b[cap + q] = yn;
+  b[2 * cap + q] = zn;
+  const double br = rm > 0.0 ? (xm * bx + ym * by) / rm : 0.0;
+  A* J = (A*)jbv;
+  deposit(p, jz, false, w * bz, J);
+  deposit(p, jr, true, w * br, J + p.plane);
+}
+
+template <int ST>
+__global__ __launch_bounds__(BT) void bunch_push_kernel(Physics p, long long s, int shift, const void* Einv,
+                                                        const void* Eoutv, double* b, int n, long long cap) {
+  using A = typename Mode<ST, false>::A;
+  const int q = blockIdx.x * BT + threadIdx.x;
+  if (q >= n) return;
+  if (b[6 * cap + q] == 0.0) return;
+  const A* Ein = (const A*)Einv;
+  const A* Eout = (const A*)Eoutv;
+  const double x = b[q], y = b[cap + q], z = b[2 * cap + q];
+  const double r = sqrt(x * x + y * y);
+  const Stencil sc = stencil(p, z, r, s, 0.5, false);   // E_z points
+  const Stencil se = stencil(p, z, r, s, 0.0, true);    // E_r points
+  const Stencil sb = stencil(p, z, r, s, 0.5, true);    // B_theta points
+  const double ez = gather(p, sc, false, Eout, shift);
+  const double er = gather(p, se, true, Eout + p.plane, shift);
+  const double bt = 0.5 * (gather(p, sb, true, Ein + 2 * p.plane, 0) + gather(p, sb, true, Eout + 2 * p.plane, shift));
+  const double cx = r > 0.0 ? x / r : 0.0, cy = r > 0.0 ? y / r : 0.0;
+  const double Ex = er * cx, Ey = er * cy, Ez = ez;
+  const double Bx = -bt * cy, By = bt * cx, Bz = 0.0;
+  // Boris push for dp/dt = -(E + beta x B): half kick, rotation, half kick
+  const double dt = p.dt;
+  const double mx = b[3 * cap + q] - 0.5 * dt * Ex, my = b[4 * cap + q] - 0.5 * dt * Ey,
+               mz = b[5 * cap + q] - 0.5 * dt * Ez;
+  const double g = sqrt(1.0 + (mx * mx + my * my + mz * mz));
+  const double tx = -0.5 * dt * Bx / g, ty = -0.5 * dt * By / g, tz = -0.5 * dt * Bz / g;
+  const double ux = mx + (my * tz - mz * ty), uy = my + (mz * tx - mx * tz), uz = mz + (mx * ty - my * tx);
+  const double t2 = 1.0 + (tx * tx + ty * ty + tz * tz);
+  const double sx = 2.0 * tx / t2, sy = 2.0 * ty / t2, sz = 2.0 * tz / t2;
+  b[3 * cap + q] = mx + (uy * sz - uz * sy) - 0.5 * dt * Ex;
+  b[4 * cap + q] = my + (uz * sx - ux * sz) - 0.5 * dt * Ey;
+  b[5 * cap + q] = mz + (ux * sy - uy * sx) - 0.5 * dt * Ez;
+}
+
+__global__ __launch_bounds__(BT) void bunch_density_kernel(Physics p, long long s, double zoff, double t_ahead,
+                                                           const double* b, int n, long long cap, double* dens) {
+  const int q = blockIdx.x * BT + threadIdx.x;
+  if (q >= n) return;
+  const double px = b[3 * cap + q], py = b[4 * cap + q], pz = b[5 * cap + q];
+  const double g = sqrt(1.0 + (px * px + py * py + pz * pz));
+  const double x = b[q] + t_ahead * (px / g), y = b[cap + q] + t_ahead * (py / g);
+  const double z = b[2 * cap + q] + t_ahead * (pz / g);
+  const double r = sqrt(x * x + y * y);
+  const Stencil st = stencil(p, z, r, s, zoff, false);
+  if (!inside(p, st)) return;
+  deposit(p, st, false, b[6 * cap + q], dens);
+}
+
+// Discrete Gauss law of the density (one thread per column): E_r at r = (j + 1) dr is
+// -(dr / (j + 1)) sum_{j' <= j} (j' + 1/2) n(r_j').
+template <int ST>
+__global__ void bunch_gauss_kernel(Physics p, const double* dens, void* Ev, int comp) {
+  using A = typename Mode<ST, false>::A;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.nz) return;
+  A* E = (A*)Ev + comp * p.plane;
+  double cum = 0.0;
+  for (int j = 0; j < p.nr; ++j) {
+    const long long oo = (long long)j * p.pitch + i;
+    cum += (j + 0.5) * dens[oo];
+    stv(E + oo, -p.h * cum / (j + 1.0));
+  }
+}
+
+}  // namespace
+
+#define BUNCH_DISPATCH(storage, KERNEL, GRID, STREAM, ...)                         \
+  do {                                                                             \
+    if ((storage) == 0) KERNEL<0><<<(GRID), BT, 0, (STREAM)>>>(__VA_ARGS__);       \
+    else if ((storage) == 1) KERNEL<1><<<(GRID), BT, 0, (STREAM)>>>(__VA_ARGS__);  \
+    else KERNEL<2><<<(GRID), BT, 0, (STREAM)>>>(__VA_ARGS__);                      \
+  } while (0)
+
+hipError_t launch_bunch_move(int storage, const Physics& p, long long s, double* bunch, int n, long long cap,
+                             void* jb, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  BUNCH_DISPATCH(storage, bunch_move_kernel, dim3((n + BT - 1) / BT), st, p, s, bunch, n, cap, jb);
+  return hipGetLastError();
+}
+
+hipError_t launch_bunch_push(int storage, const Physics& p, long long s, int shift, const void* Ein,
+                             const void* Eout, double* bunch, int n, long long cap, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  BUNCH_DISPATCH(storage, bunch_push_kernel, dim3((n + BT - 1) / BT), st, p, s, shift, Ein, Eout, bunch, n, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_bunch_density(const Physics& p, long long s, double zoff, double t_ahead, const double* bunch,
+                                int n, long long cap, double* dens, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  bunch_density_kernel<<<dim3((n + BT - 1) / BT), BT, 0, st>>>(p, s, zoff, t_ahead, bunch, n, cap, dens);
+  return hipGetLastError();
+}
+
+hipError_t launch_bunch_gauss(int storage, const Physics& p, const double* dens, void* E, int comp, hipStream_t st) {
+  const dim3 grid((p.nz + 63) / 64);
+  if (storage == 0) bunch_gauss_kernel<0><<<grid, 64, 0, st>>>(p, dens, E, comp);
+  else if (storage == 1) bunch_gauss_kernel<1><<<grid, 64, 0, st>>>(p, dens, E, comp);
+  else bunch_gauss_kernel<2><<<grid, 64, 0, st>>>(p, dens, E, comp);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

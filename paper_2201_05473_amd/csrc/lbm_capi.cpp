@@ -81,6 +81,10 @@ int validate(const lbm_config* c, Physics* p) {
     return fail(LBM_EINVAL, "unknown collision operator %d", c->collision);
   if (c->collision == LBM_TRT && !(c->trt_magic > 0.0 && std::isfinite(c->trt_magic)))
     return fail(LBM_EINVAL, "trt_magic must be positive and finite (got %g)", c->trt_magic);
+  if (c->driver != LBM_DRIVER_RIGID && c->driver != LBM_DRIVER_PARTICLES)
+    return fail(LBM_EINVAL, "unknown driver %d", c->driver);
+  if (c->driver == LBM_DRIVER_PARTICLES && (c->max_particles < 0 || c->max_particles > INT32_MAX))
+    return fail(LBM_EINVAL, "max_particles must lie in [0, 2^31) (got %lld)", (long long)c->max_particles);
   if (p) {
     Physics& q = *p;
     std::memset(&q, 0, sizeof q);
@@ -111,14 +115,19 @@ int validate(const lbm_config* c, Physics* p) {
     q.fp64_math = c->fp64_math;
     q.coll = c->collision;
     q.tau_plus = c->collision == LBM_TRT ? 0.5 + c->trt_magic / (c->tau - 0.5) : c->tau;
+    q.driver = c->driver;
+    q.cap = c->driver == LBM_DRIVER_PARTICLES ? (long long)c->max_particles : 0;
   }
   return LBM_OK;
 }
 
 // Workspace layout: two population buffers, two moment buffers, two field buffers, and the
 // reduction scratch, each 256-byte aligned.
+// The particle driver adds the bunch (SoA [7][cap] doubles), two deposit buffers of J_bz, J_br
+// (auxiliary type, alternating between steps) and an FP64 density plane (initial field,
+// diagnostics); none of them for the rigid driver.
 struct Layout {
-  size_t g[2], M[2], E[2], partials, out, total;
+  size_t g[2], M[2], E[2], partials, out, bunch, jb[2], dens, total;
 };
 
 Layout layout(const Physics& p, int storage) {
@@ -134,6 +143,16 @@ Layout layout(const Physics& p, int storage) {
   off += round_up((size_t)lbm::diag_blocks(p) * 8 * sizeof(double), 256);
   L.out = off;
   off += 256;
+  L.bunch = L.jb[0] = L.jb[1] = L.dens = off;
+  if (p.driver == 1) {
+    off += round_up(7 * (size_t)p.cap * sizeof(double), 256);
+    for (int b = 0; b < 2; ++b) {
+      L.jb[b] = off;
+      off += round_up(2 * plane * aux_bytes(storage), 256);
+    }
+    L.dens = off;
+    off += round_up(plane * sizeof(double), 256);
+  }
   L.total = off;
   return L;
 }
@@ -153,6 +172,12 @@ struct lbm_ctx {
   // events; created on first use, default priority
   hipStream_t aux = nullptr;
   hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
+  // particle driver: particles in the bunch, and the deposit buffer the next step fills
+  long long nbunch = 0;
+  int jcur = 0;
+  double* bunch() { return (double*)(ws + L.bunch); }
+  void* jb(int b) { return ws + L.jb[b]; }
+  double* dens() { return (double*)(ws + L.dens); }
   void* g(int b) { return ws + L.g[b]; }
   void* M(int b) { return ws + L.M[b]; }
   void* E(int b) { return ws + L.E[b]; }
@@ -165,8 +190,23 @@ struct lbm_ctx {
 
 namespace {
 
+// Driver density at the nodes (z_i, r_j) and t_{k-1} for the Gauss residual: the particle bunch
+// deposited from its positions (which are at t_{k-1}) into the FP64 density plane, or nullptr for
+// the rigid driver's closed form.
+hipError_t driver_density_plane(lbm_ctx* c, const double** out) {
+  *out = nullptr;
+  if (c->p.driver != 1) return hipSuccess;
+  hipError_t e = hipMemsetAsync(c->dens(), 0, (size_t)c->p.plane * sizeof(double), c->stream);
+  if (e == hipSuccess)
+    e = lbm::launch_bunch_density(c->p, c->s, 0.0, 0.0, c->bunch(), (int)c->nbunch, c->p.cap, c->dens(), c->stream);
+  *out = c->dens();
+  return e;
+}
+
 int run_check(lbm_ctx* c) {
-  HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur),
+  const double* drv;
+  HIP_CHECK(driver_density_plane(c, &drv), "bunch density launch");
+  HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur), drv,
                                     c->partials(), c->red_out(), c->stream),
             "diagnostics launch");
   double out[8];
@@ -259,7 +299,23 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     a.E_in = c->E(c->cur);
     a.E_out = c->E(1 - c->cur);
     a.site_out = nullptr;
+    a.jb_in = nullptr;
+    a.jb_zero = nullptr;
+    if (c->p.driver == 1) {
+      // particles to t_k and their current J_b(t_{k-1/2}) into the buffer the previous step cleared
+      HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,
+                                       c->jb(c->jcur), c->stream),
+                "bunch launch");
+      a.jb_in = c->jb(c->jcur);
+      a.jb_zero = c->jb(1 - c->jcur);
+    }
     HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "step launch");
+    if (c->p.driver == 1) {
+      HIP_CHECK(lbm::launch_bunch_push(c->storage, c->p, c->s, a.shift, c->E(c->cur), c->E(1 - c->cur), c->bunch(),
+                                       (int)c->nbunch, c->p.cap, c->stream),
+                "bunch launch");
+      c->jcur ^= 1;
+    }
     c->cur ^= 1;
     c->k += 1;
     c->s += a.shift;
@@ -421,7 +477,9 @@ int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
 int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (!out) return fail(LBM_EINVAL, "out is NULL");
-  HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur),
+  const double* drv;
+  HIP_CHECK(driver_density_plane(c, &drv), "bunch density launch");
+  HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur), drv,
                                     c->partials(), c->red_out(), c->stream),
             "diagnostics launch");
   double r[8];
@@ -502,6 +560,7 @@ int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
   if ((c->p.per_z && c->p.nz < 5) || (c->p.per_r && c->p.nr < 5))
     return fail(LBM_EINVAL, "the adjoint needs at least 5 cells along periodic dimensions");
   if (c->p.coll != LBM_BGK) return fail(LBM_EINVAL, "the adjoint is implemented for the BGK collision only");
+  if (c->p.driver != LBM_DRIVER_RIGID) return fail(LBM_EINVAL, "the adjoint is implemented for the rigid driver only");
   return LBM_OK;
 }
 
@@ -546,6 +605,8 @@ hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const Sta
   a.M_in = x.M; a.M_out = y.M;
   a.E_in = x.E; a.E_out = y.E;
   a.site_out = c->p.fields_on ? site : nullptr;
+  a.jb_in = nullptr;
+  a.jb_zero = nullptr;
   return lbm::launch_step(c->storage, a, st);
 }
 
@@ -1049,3 +1110,51 @@ int lbm_destroy(lbm_ctx* c) {
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Particle driver: the bunch
+// ------------------------------------------------------------------------------------------
+int lbm_set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (c->p.driver != LBM_DRIVER_PARTICLES) return fail(LBM_EINVAL, "the bunch needs driver = LBM_DRIVER_PARTICLES");
+  if (n < 0 || n > c->p.cap) return fail(LBM_EINVAL, "n must lie in [0, max_particles] (got %lld)", (long long)n);
+  if (n > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
+  if (init_fields != 0 && init_fields != 1) return fail(LBM_EINVAL, "init_fields must be 0 or 1");
+  if (init_fields && c->k != 0) return fail(LBM_EINVAL, "the initial field can only be set at step 0");
+  for (int comp = 0; comp < 7; ++comp)
+    if (n > 0)
+      HIP_CHECK(hipMemcpyAsync(c->bunch() + comp * c->p.cap, bunch + comp * n, (size_t)n * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream),
+                "bunch upload");
+  c->nbunch = n;
+  if (init_fields && c->p.fields_on) {
+    // E_r^{-1} from the density at the positions (t = -dt) on the E_r columns; B^{-1/2} from the
+    // density at t = -dt/2 on the B columns
+    const size_t db = (size_t)c->p.plane * sizeof(double);
+    for (int comp = 1; comp <= 2; ++comp) {
+      HIP_CHECK(hipMemsetAsync(c->dens(), 0, db, c->stream), "clear");
+      HIP_CHECK(lbm::launch_bunch_density(c->p, 0, comp == 1 ? 0.0 : 0.5, comp == 1 ? 0.0 : 0.5 * c->p.dt,
+                                          c->bunch(), (int)n, c->p.cap, c->dens(), c->stream),
+                "bunch density launch");
+      HIP_CHECK(lbm::launch_bunch_gauss(c->storage, c->p, c->dens(), c->E(c->cur), comp, c->stream),
+                "bunch field launch");
+    }
+  }
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  return LBM_OK;
+}
+
+int lbm_get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (c->p.driver != LBM_DRIVER_PARTICLES) return fail(LBM_EINVAL, "the bunch needs driver = LBM_DRIVER_PARTICLES");
+  if (!n) return fail(LBM_EINVAL, "n is NULL");
+  if (n_max < c->nbunch) return fail(LBM_EINVAL, "n_max %lld < %lld particles", (long long)n_max, c->nbunch);
+  if (c->nbunch > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
+  for (int comp = 0; comp < 7 && c->nbunch > 0; ++comp)
+    HIP_CHECK(hipMemcpyAsync(bunch + comp * c->nbunch, c->bunch() + comp * c->p.cap,
+                             (size_t)c->nbunch * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+              "bunch download");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  *n = c->nbunch;
+  return LBM_OK;
+}

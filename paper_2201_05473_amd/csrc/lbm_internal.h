@@ -28,6 +28,8 @@ struct Physics {
   int fp64_math;            // FP64 arithmetic for FP32 / FP16 storage
   int coll;                 // collision operator: 0 BGK, 1 TRT, 2 regularised
   double tau_plus;          // TRT: relaxation time of the even part (tau otherwise)
+  int driver;               // 0 rigid bi-Gaussian, 1 macroparticles
+  long long cap;            // macroparticle capacity (driver 1)
 };
 
 // One launch of the fused step: physics + time counters + buffers.
@@ -44,6 +46,9 @@ struct StepArgs {
   void* E_out;
   void* site_out;    // optional (fields on): [3 planes] E_z, E_r, B_theta averaged to the sites as
                      // used by the fluid, at the output index; nullptr to skip
+  const void* jb_in; // particle driver: [2 planes] J_bz (E_z points), J_br (E_r points) at
+                     // t_{k-1/2}, logical columns of x^k (auxiliary type)
+  void* jb_zero;     // particle driver: [2 planes] cleared at the output index for the next step
 };
 
 // One reverse step of the adjoint at the state x^k (k, s, shift as for the forward step k).
@@ -86,6 +91,19 @@ struct AdjStep {
 // Launchers (defined in lbm_kernels.hip / lbm_adjoint.hip).  storage: 0 F64, 1 F32, 2 F16.
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st);
 // Bubble length count of one row (single block) into *out (device).
+// Particle driver (lbm_bunch.hip).  bunch: SoA [7][cap] doubles (x, y, z, p_x, p_y, p_z, w).
+// Move to t_k and deposit J_b(t_{k-1/2}) (atomics, auxiliary type) into jb (2 planes).
+hipError_t launch_bunch_move(int storage, const Physics& p, long long s, double* bunch, int n, long long cap,
+                             void* jb, hipStream_t st);
+// Boris push with E^k, B^{k+1/2} (Eout, frame s + shift) and B^{k-1/2} (Ein, frame s).
+hipError_t launch_bunch_push(int storage, const Physics& p, long long s, int shift, const void* Ein,
+                             const void* Eout, double* bunch, int n, long long cap, hipStream_t st);
+// Bunch density (FP64, atomics) on the nodes z = (s + i + zoff) dz, rows (j + 1/2) dr, positions moved
+// by t_ahead along the velocities; dens must be cleared first.
+hipError_t launch_bunch_density(const Physics& p, long long s, double zoff, double t_ahead, const double* bunch,
+                                int n, long long cap, double* dens, hipStream_t st);
+// Discrete Gauss field of the density dens into plane comp (1 = E_r, 2 = B_theta) of E.
+hipError_t launch_bunch_gauss(int storage, const Physics& p, const double* dens, void* E, int comp, hipStream_t st);
 hipError_t launch_bubble(int storage, const Physics& p, long long s, const void* M, int row, double n_star,
                          double z0, double z1, long long* out, hipStream_t st);
 hipError_t launch_init_fluid(int storage, const Physics& p, const double* n_pert,
@@ -103,8 +121,10 @@ hipError_t launch_state_set(int storage, const Physics& p, long long s, void* g,
                             void* E, int c, const double* src, hipStream_t st);
 // Diagnostics: partials[nblocks][8] then a single-block final pass into out[8].
 int diag_blocks(const Physics& p);
+// drv: FP64 driver density at the nodes (z_i, r_j) and t_{k-1} (pitched plane), or nullptr for the
+// rigid driver's closed form.
 hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
-                              const void* M, const void* E, double* partials, double* out,
+                              const void* M, const void* E, const double* drv, double* partials, double* out,
                               hipStream_t st);
 // Adjoint: per-block accumulators (2 * adjoint_partial_blocks of 4 doubles, zeroed by the caller),
 // one reverse step, the theta partials of the initial state (lam_next = lambda^0), and the final

@@ -25,7 +25,9 @@ namespace lbm {
 // LDS barriers (which only wait for LDS traffic).
 // ------------------------------------------------------------------------------------------
 // PER = false: the grid is known not to be periodic, and the wrap code is compiled out.
-template <int ST, bool FIELDS, bool M64, bool SITE, int COLL, bool PER>
+// DRV = 1: the driver current J_b comes from the particle bunch's deposit (a.jb_in, z and r
+// components) in place of the rigid driver's closed form.
+template <int ST, bool FIELDS, bool M64, bool SITE, int COLL, bool PER, int DRV>
 __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using S = typename Mode<ST, M64>::S;
   using C = typename Mode<ST, M64>::C;
@@ -53,6 +55,8 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   __shared__ CF sDz[EZZ];   // exp(-(z - z_d)^2 / 2 sigma_z^2) at the E_z columns
   __shared__ CF sDr[EZR];   // n_b exp(-r^2 / 2 sigma_r^2) at the fluid / E_z rows
   __shared__ CF sIr[EZR];   // 1 / r_j at the fluid / E_z rows
+  __shared__ CF sJbz[DRV ? EZR : 1][DRV ? EZZ : 1];   // particle driver: J_bz at the E_z points
+  __shared__ CF sJbr[DRV ? ERR : 1][DRV ? ERZ : 1];   // and J_br at the E_r points
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
@@ -85,6 +89,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   // --- 1. halo loads into registers --------------------------------------------------------
   A hm[SM][3];
   A hb[SB], hez[SEZ], her[SER];
+  A hjz[DRV ? SEZ : 1], hjr[DRV ? SER : 1];
 #pragma unroll
   for (int s = 0; s < SM; ++s) {
     const int t = min(tid + s * NTHREADS, NM - 1);
@@ -103,11 +108,13 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     for (int s = 0; s < SEZ; ++s) {
       const int t = min(tid + s * NTHREADS, NEZ - 1);
       hez[s] = Ezp[rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ)];
+      if (DRV) hjz[s] = ((const A*)a.jb_in)[rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ)];
     }
 #pragma unroll
     for (int s = 0; s < SER; ++s) {
       const int t = min(tid + s * NTHREADS, NER - 1);
       her[s] = Erp[rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ)];
+      if (DRV) hjr[s] = ((const A*)a.jb_in + plane)[rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ)];
     }
   }
 
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   }
   // the driver density factorises into a column and a row factor
   const double tb = ((double)a.k - 0.5) * dt;
-  if (FIELDS) {
+  if (FIELDS && !DRV) {
     for (int t = tid; t < EZZ; t += NTHREADS) {
       const int ii = i0 - 1 + t;
       const int ci = PER && p.per_z ? wrapi(ii, nz) : ii;
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   for (int t = tid; t < EZR; t += NTHREADS) {
     const double r = (j0 - 1 + t + 0.5) * h;
     const CF rr = (CF)r;
-    sDr[t] = (CF)p.nb * mexp(-(rr * rr) / (CF)(2.0 * p.sigma_r * p.sigma_r));
+    if (!DRV) sDr[t] = (CF)p.nb * mexp(-(rr * rr) / (CF)(2.0 * p.sigma_r * p.sigma_r));
     sIr[t] = CF(1) / rr;
   }
   __syncthreads();
@@ -196,11 +203,13 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     for (int s = 0; s < SEZ; ++s) {
       const int t = tid + s * NTHREADS;
       if (t < NEZ) sEz[t / EZZ][t % EZZ] = (CF)hez[s];
+      if (DRV && t < NEZ) sJbz[t / EZZ][t % EZZ] = (CF)hjz[s];
     }
 #pragma unroll
     for (int s = 0; s < SER; ++s) {
       const int t = tid + s * NTHREADS;
       if (t < NER) sEr[t / ERZ][t % ERZ] = (CF)her[s];
+      if (DRV && t < NER) sJbr[t / ERZ][t % ERZ] = (CF)hjr[s];
     }
     __syncthreads();
 
@@ -216,7 +225,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
         const CF bj = sBo[bb + 1][aa + 1];
         const CF curl = (bj + (CF)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
         const CF jf = CF(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
-        const CF jb = sDz[aa] * sDr[bb];
+        const CF jb = DRV ? sJbz[DRV ? bb : 0][DRV ? aa : 0] : sDz[aa] * sDr[bb];
         sEz[bb][aa] = sEz[bb][aa] + dtf * (curl + jf + jb);
       }
     }
@@ -226,7 +235,8 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
         const CF curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) * ih;   // -dB/dz
         const CF jf = CF(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
-        sEr[bb][aa] = sEr[bb][aa] + dtf * (curl + jf);
+        const CF jbr = DRV ? sJbr[DRV ? bb : 0][DRV ? aa : 0] : CF(0);
+        sEr[bb][aa] = sEr[bb][aa] + dtf * (curl + jf + jbr);
       }
     }
     __syncthreads();
@@ -274,6 +284,12 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   if (!site_ok) return;   // no barrier below this point
   const int oo32 = j * pitch + o;
   const long long oo = oo32;
+  if (DRV) {
+    // the next step's deposit buffer, cleared at this output cell
+    A* jz = (A*)a.jb_zero;
+    stv(jz + oo, C(0));
+    stv(jz + plane + oo, C(0));
+  }
   S* gout = (S*)a.g_out;
   A* Mout = (A*)a.M_out;
   A* Eout = (A*)a.E_out;
@@ -547,7 +563,7 @@ __global__ void init_fields_kernel(Physics p, void* Ev) {
   for (int j = 0; j < p.nr; ++j) {
     const long long oo = (long long)j * p.pitch + i;
     double er = 0.0, b = 0.0;
-    if (p.fields_on) {
+    if (p.fields_on && p.driver == 0) {   // a particle bunch sets its field with lbm_set_bunch
       const double r = (j + 0.5) * p.h;
       ce += (j + 0.5) * driver<double>(p, z, r, -p.dt);
       cb += (j + 0.5) * driver<double>(p, z + 0.5 * p.h, r, -0.5 * p.dt);
@@ -673,7 +689,7 @@ __device__ __forceinline__ void block_reduce5(double v[5], double* out) {
 template <int ST>
 __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, long long k,
                                                                   long long s, const void* Mv,
-                                                                  const void* Ev,
+                                                                  const void* Ev, const double* drv,
                                                                   double* partials) {
   using A = typename Mode<ST, false>::A;
   const long long n = (long long)p.nz * p.nr;
@@ -696,7 +712,9 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
       const double ezl = E[oo - 1];
       const double erb = j > 0 ? (double)E[p.plane + oo - p.pitch] : 0.0;
       const double div = (ez - ezl) / h + ((j + 1.0) * er - j * erb) / ((j + 0.5) * h);
-      const double rho = nb0 - m0 - driver<double>(p, z, r, ((double)k - 1.0) * p.dt);
+      // driver density at t_{k-1}: the closed form, or the bunch density deposited at the nodes
+      const double nd = drv ? drv[oo] : driver<double>(p, z, r, ((double)k - 1.0) * p.dt);
+      const double rho = nb0 - m0 - nd;
       v[2] = fabs(div - rho);
     }
     double bz, br;
@@ -767,10 +785,12 @@ static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr);
 template <int ST, bool M64, int COLL>
 static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
   const bool np = ST == 2 && !a.p.per_z && !a.p.per_r;
-  if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, ST != 2><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (np) step_kernel<ST, false, M64, false, COLL, ST != 2><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else step_kernel<ST, false, M64, false, COLL, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  const bool drv = a.p.driver == 1;
+  if (a.p.fields_on && drv) step_kernel<ST, true, M64, false, COLL, true, 1><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, ST != 2, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (np) step_kernel<ST, false, M64, false, COLL, ST != 2, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else step_kernel<ST, false, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
 // The site-field variant (used by the adjoint, which is BGK only) exists for BGK alone.
@@ -778,7 +798,7 @@ template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
   if (a.p.coll == 1) launch_step_c<ST, M64, 1>(a, grid, st);
   else if (a.p.coll == 2) launch_step_c<ST, M64, 2>(a, grid, st);
-  else if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else launch_step_c<ST, M64, 0>(a, grid, st);
 }
 
@@ -840,10 +860,10 @@ int diag_blocks(const Physics& p) {
 }
 
 hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
-                              const void* M, const void* E, double* partials, double* out,
+                              const void* M, const void* E, const double* drv, double* partials, double* out,
                               hipStream_t st) {
   const int nb = diag_blocks(p);
-  LBM_DISPATCH(storage, diag_partial_kernel, dim3(nb), dim3(RED_THREADS), st, p, k, s, M, E,
+  LBM_DISPATCH(storage, diag_partial_kernel, dim3(nb), dim3(RED_THREADS), st, p, k, s, M, E, drv,
                partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -68,6 +68,7 @@ def test_struct_layout_matches_c(lib, tmp_path):
     dict(storage=3), dict(nb=0.1, sigma_z=0.0), dict(n_floor=-1.0), dict(check_every=-1),
     dict(collision=3), dict(collision=-1), dict(collision=1, trt_magic=0.0),
     dict(collision=1, trt_magic=float("inf")),
+    dict(driver=2), dict(driver=1, max_particles=-1), dict(driver=1, max_particles=2 ** 31),
 ])
 def test_invalid_configs_rejected(lib, bad):
     with pytest.raises(lib.LbmError) as ei:

@@ -1,0 +1,145 @@
+"""GPU parity of the particle driver (reading R30: the bunch of Sec. II, Eq. (1), as macroparticles
+coupled through their projected current) against the FP64 oracle, through the C ABI.
+
+FP64: every state value to 1e-10 (max-norm per group, as for the rigid driver) and every particle
+coordinate to 1e-10 relative to its scale; lost particles (w = 0) identical.  The deposit uses
+atomic additions, so the GPU sums over particles in no fixed order: the agreement is to
+round-off, not bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import lbm_oracle as O
+from test_gpu_parity import TOL64, comp_errors, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2201_05473_amd import load_library
+    load_library()
+
+
+def lattice(cfg, bunch, n_pert=None):
+    from paper_2201_05473_amd import Lattice
+    lat = Lattice(cfg, n_pert)
+    lat.set_bunch(bunch, True)
+    return lat
+
+
+def bunch_errors(b, ref):
+    """Max relative error of positions (scale: max |position|), momenta (max |p|) and weights."""
+    ref = ref.numpy() if hasattr(ref, "numpy") else ref
+    out = []
+    for rows in ((0, 1, 2), (3, 4, 5), (6,)):
+        den = max(np.abs(ref[list(rows)]).max(), 1e-300)
+        out.append(np.abs(b[list(rows)] - ref[list(rows)]).max() / den)
+    return out
+
+
+CASES = {
+    # gamma = 5000, the paper's bunch shape: nearly rigid, moving window
+    "relativistic_window": dict(cfg=dict(moving_window=1), gamma=5000.0, emittance=0.05, spread=1e-4, steps=40),
+    # gamma = 3 with a transverse spread: the push deflects the particles, some leave radially and
+    # through the rear of the window (lost), and the deposit carries a radial current
+    "slow_deflected": dict(cfg=dict(moving_window=1), gamma=3.0, emittance=0.4, spread=0.05, steps=60),
+    # fixed window, TRT collision
+    "fixed_trt": dict(cfg=dict(collision=wl.TRT, trt_magic=0.25), gamma=20.0, emittance=0.1, spread=0.01,
+                      steps=30),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_parity(name):
+    c = CASES[name]
+    cfg = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=4.0,
+                    driver=wl.PARTICLES, max_particles=6000, storage=wl.F64, noise_amp=1e-3, seed=4,
+                    tau=0.7, **c["cfg"])
+    b = wl.bunch(cfg, 5000, gamma=c["gamma"], emittance=c["emittance"], energy_spread=c["spread"], seed=8)
+    pert = wl.density_perturbation(cfg)
+    print(f"[bunch fp64 parity] {name} 130x21, {c['steps']} steps, 5000 particles", flush=True)
+    lat = lattice(cfg, b, pert)
+    lat.step(c["steps"])
+    st, k, s = lat.state()
+    bg = lat.bunch()
+    S, P = O.run(cfg, c["steps"], pert, bunch=b)
+    assert (k, s) == (S.k, S.s)
+    errs = comp_errors(st, oracle_state(S, P))
+    assert errs.max() < TOL64, (errs.argmax(), errs.max())
+    ref = S.bunch.numpy()
+    assert np.array_equal(bg[6] == 0.0, ref[6] == 0.0)
+    be = bunch_errors(bg, ref)
+    print(name, "lost", int((ref[6] == 0.0).sum()), "bunch errors", be, flush=True)
+    assert max(be) < 1e-10, be
+    if name == "slow_deflected":
+        assert 0 < int((ref[6] == 0.0).sum()) < 5000     # the loss path ran
+    lat.close()
+
+
+def test_initial_gauss_law_from_the_bunch():
+    """Right after lbm_set_bunch the discrete Gauss residual (driver density from the deposited
+    bunch) vanishes, and the initial field matches the oracle's."""
+    cfg = wl.config("C2s", driver=wl.PARTICLES, max_particles=20000, storage=wl.F64)
+    b = wl.bunch(cfg, 20000, seed=3)
+    lat = lattice(cfg, b)
+    d = lat.diagnostics()
+    assert d["gauss_max"] < 1e-13, d
+    st, _, _ = lat.state()
+    S = O.initial_state(O.Params(cfg), None, None, b)
+    assert comp_errors(st, oracle_state(S, O.Params(cfg))).max() < 1e-12
+    lat.close()
+
+
+def test_full_size_c2_single_step_with_paper_sized_bunch():
+    """C2 at full size (2048 x 512) driven by a 200,000-particle bunch of the paper's shape
+    (gamma = 5000): one step, FP64 to 1e-10 with the oracle (state and bunch), FP32 moments to 1e-6."""
+    cfg = wl.config("C2", driver=wl.PARTICLES, max_particles=200000, storage=wl.F64)
+    b = wl.bunch(cfg, 200000, gamma=5000.0, emittance=0.05, energy_spread=1e-4, seed=6)
+    S, P = O.run(cfg, 1, bunch=b)
+    ref = oracle_state(S, P)
+    for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6)):
+        print(f"[bunch full size] C2 storage={storage}", flush=True)
+        lat = lattice(dict(cfg, storage=storage), b)
+        lat.step(1)
+        st, k, s = lat.state()
+        errs = comp_errors(st, ref)
+        if storage == wl.F64:
+            assert errs.max() < tol, (errs.argmax(), errs.max())
+            assert max(bunch_errors(lat.bunch(), S.bunch)) < 1e-10
+        else:
+            assert errs[27:].max() < tol, errs[27:]
+        lat.close()
+
+
+def test_bunch_interface_errors():
+    from paper_2201_05473_amd import LBM_EINVAL, LbmError, Lattice
+    rigid = Lattice(wl.config(None, nz=64, nr=8))
+    with pytest.raises(LbmError) as ei:
+        rigid.set_bunch(np.zeros((7, 1)))
+    assert ei.value.code == LBM_EINVAL
+    rigid.close()
+    cfg = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.2, driver=wl.PARTICLES,
+                    max_particles=10)
+    lat = Lattice(cfg)
+    with pytest.raises(LbmError) as ei:
+        lat.set_bunch(np.zeros((7, 11)))                 # over capacity
+    assert ei.value.code == LBM_EINVAL
+    b = wl.bunch(cfg, 10, seed=1)
+    lat.set_bunch(b)
+    assert np.array_equal(lat.bunch(), b)
+    lat.step(2)
+    with pytest.raises(LbmError) as ei:
+        lat.set_bunch(b, True)                           # initial field only at step 0
+    assert ei.value.code == LBM_EINVAL
+    lat.set_bunch(b, False)                              # resuming keeps the fields
+    lat.close()
+    fresh = Lattice(cfg)
+    with pytest.raises(LbmError) as ei:
+        fresh.adjoint(4, 2)                              # the adjoint covers the rigid driver
+    assert ei.value.code == LBM_EINVAL
+    fresh.close()
