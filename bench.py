@@ -212,6 +212,44 @@ def long_plasma_c5(budget_gb: float = 64.0, fd_params=("sigma_r", "nb")) -> dict
             "rel_err_vs_fd": {nm: abs(g[nm] - fd[nm]) / abs(fd[nm]) for nm in fd}}
 
 
+def particle_driver_c2(steps: int = 2000, n: int = 200000, timed_only: bool = False) -> dict:
+    """C2 (2048 x 512, FP32) driven by a macroparticle bunch of the paper's size and shape (Sec. IV:
+    2e5 particles, gamma = 5000, an rms divergence of 1.7 mrad, 0.01 % energy spread; here with
+    C2's sigma_z = 1 and sigma_r = 0.5) against the rigid driver of the same charge: time per step
+    (HIP events on the library's stream) and the max-norm difference of E_z after `steps` steps."""
+    import torch
+
+    import workloads as wl
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C2")
+    pcfg = dict(cfg, driver=wl.PARTICLES, max_particles=n)
+    bunch = wl.bunch(pcfg, n, gamma=5000.0, emittance=1.7e-3 * 5000.0 * cfg["sigma_r"], energy_spread=1e-4,
+                     seed=11)
+    res = {"workload": f"C2 FP32 with a {n}-particle bunch (gamma 5000, 1.7 mrad, 0.01 % spread), {steps} steps"}
+    fields = {}
+    for name, c in (("rigid", cfg), ("particles", pcfg)):
+        lat = Lattice(c)
+        if name == "particles":
+            lat.set_bunch(bunch)
+        lat.step(50)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        res[f"us_per_step_{name}"] = e0.elapsed_time(e1) * 1e3 / steps
+        if not timed_only:
+            fields[name] = lat.fields()[0].double()
+            if name == "particles":
+                res["particles_lost"] = int((lat.bunch()[6] == 0.0).sum())
+        lat.close()
+    res["overhead"] = res["us_per_step_particles"] / res["us_per_step_rigid"] - 1.0
+    if not timed_only:
+        res["Ez_rel_diff_vs_rigid"] = rel_err(fields["particles"], fields["rigid"])
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,13 +265,15 @@ def main():
     ap.add_argument("--c5", action="store_true",
                     help="the long-plasma case C5 instead of the headline: forward MLUPS, adjoint under "
                          "a 64 GB snapshot budget, gradient against FP64 finite differences (minutes)")
+    ap.add_argument("--profile-pic", action="store_true",
+                    help="for rocprofv3: C2 FP32 driven by the 200,000-particle bunch, timed steps only")
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="for rocprofv3: one C4 lbm_adjoint (2,000 steps, checkpoints every 45) after a "
                          "warm-up run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(the multi-GPU decomposition is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU decomposition is a design, not an implementation)"}))
         sys.exit(2)
 
     import torch
@@ -249,6 +289,10 @@ def main():
 
     if args.c5:
         print(json.dumps({"c5": long_plasma_c5()}))
+        return
+
+    if args.profile_pic:
+        print(json.dumps({"profile_pic": particle_driver_c2(steps=500, timed_only=True)}))
         return
 
     if args.profile_adjoint:
@@ -343,6 +387,7 @@ def main():
         adj = adjoint_c4()
         out["adjoint_forward_ratio"] = adj["ratio"]
         out["adjoint_C4"] = adj
+        out["particle_driver_C2"] = particle_driver_c2()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

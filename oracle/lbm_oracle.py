@@ -22,7 +22,7 @@ Normalised units: t omega_p, x k_p, n / n_0, p / (m_e c), e E / (m_e c omega_p),
 c = 1.  In these units the electron momentum equation reads dp/dt = -(E + beta x B), Ampere's law
 dE/dt = curl B + n_e beta_e + n_b beta_b and Faraday's law dB/dt = -curl E.
 
-Readings of the paper (where it is silent, garbled or inconsistent; each is listed in the design doc):
+Readings of the paper (where it is silent, garbled or inconsistent):
 
   R1  Eq. (9) is printed with coefficients 1/3, 1/18, 1/6; its zeroth and first moments then do
       not reproduce Eq. (8).  The standard D2Q9 form with c_s^2 = 1/3 is used:

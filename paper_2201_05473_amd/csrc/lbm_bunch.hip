@@ -5,7 +5,9 @@
 // w (electrons, n_0 / k_p^3).  After k steps the positions are at t_{k-1} and the momenta at
 // t_{k-1/2}.  Step k runs:
 //   bunch_move_kernel  positions to t_k, current w beta at the midpoints -> J_b(t_{k-1/2}) (z at the
-//                      E_z points, r at the E_r points), hardware float atomics;
+//                      E_z points, r at the E_r points): summed per block in LDS when the block's
+//                      particles span few columns (the bunch is stored in z order), then added
+//                      to the grid with hardware float atomics;
 //   (the step kernel reads J_b in Ampere's law)
 //   bunch_push_kernel  Boris push of the momenta to t_{k+1/2} with E^k and
 //                      B^k = (B^{k-1/2} + B^{k+1/2}) / 2 at the positions at t_k.
@@ -94,35 +96,106 @@ __device__ __forceinline__ double gather(const Physics& p, const Stencil& st, bo
   return out;
 }
 
+// LDS tile of the deposit privatisation: the J_z and J_r shares of a block's particles are summed
+// here first when they fall in TW consecutive columns and the first TRW rows (the bunch is kept in
+// z order, so a block's particles share a few columns), then added to the grid once per cell.
+constexpr int TW = 8, TRW = 192;
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T* a, double v) { atomicAdd(a, (T)v); }
+
+// Adds the shares of val over the stencil's nodes to the tile (columns from c0).
+template <typename T>
+__device__ __forceinline__ void deposit_tile(const Physics& p, const Stencil& st, bool edge, double val, T* tile,
+                                             int c0) {
+#pragma unroll
+  for (int di = 0; di < 2; ++di) {
+    const double wz = di ? st.fz : 1.0 - st.fz;
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      const double wr = dj ? st.fr : 1.0 - st.fr;
+      int j = st.j0 + dj;
+      if (j < 0) {
+        if (edge) continue;
+        j = 0;
+      }
+      const double rn = ((double)j + (edge ? 1.0 : 0.5)) * p.h;
+      lds_add(tile + j * TW + (st.i0 + di - c0), val * wz * wr / (TWO_PI * rn * p.h * p.h));
+    }
+  }
+}
+
 template <int ST>
 __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, double* b, int n, long long cap,
                                                         void* jbv) {
   using A = typename Mode<ST, false>::A;
+  __shared__ A tile[2][TRW * TW];
+  __shared__ int cmin, cmax, rmax;
   const int q = blockIdx.x * BT + threadIdx.x;
-  if (q >= n) return;
-  const double w = b[6 * cap + q];
-  if (w == 0.0) return;
-  const double x = b[q], y = b[cap + q], z = b[2 * cap + q];
-  const double px = b[3 * cap + q], py = b[4 * cap + q], pz = b[5 * cap + q];
-  const double g = sqrt(1.0 + (px * px + py * py + pz * pz));
-  const double bx = px / g, by = py / g, bz = pz / g;
-  const double xn = x + p.dt * bx, yn = y + p.dt * by, zn = z + p.dt * bz;
-  const double xm = 0.5 * (x + xn), ym = 0.5 * (y + yn), zm = 0.5 * (z + zn);
-  const double rm = sqrt(xm * xm + ym * ym), rn = sqrt(xn * xn + yn * yn);
-  const Stencil jz = stencil(p, zm, rm, s, 0.5, false), jr = stencil(p, zm, rm, s, 0.0, true);
-  const bool ok = inside(p, jz) && inside(p, jr) && inside(p, stencil(p, zn, rn, s, 0.5, false)) &&
-                  inside(p, stencil(p, zn, rn, s, 0.0, true)) && inside(p, stencil(p, zn, rn, s, 0.5, true));
-  if (!ok) {
-    b[6 * cap + q] = 0.0;   // lost
+  if (threadIdx.x == 0) {
+    cmin = INT32_MAX;
+    cmax = -1;
+    rmax = -1;
+  }
+  __syncthreads();
+  bool live = false;
+  Stencil jz{}, jr{};
+  double vz = 0.0, vr = 0.0;
+  if (q < n && b[6 * cap + q] != 0.0) {
+    const double w = b[6 * cap + q];
+    const double x = b[q], y = b[cap + q], z = b[2 * cap + q];
+    const double px = b[3 * cap + q], py = b[4 * cap + q], pz = b[5 * cap + q];
+    const double g = sqrt(1.0 + (px * px + py * py + pz * pz));
+    const double bx = px / g, by = py / g, bz = pz / g;
+    const double xn = x + p.dt * bx, yn = y + p.dt * by, zn = z + p.dt * bz;
+    const double xm = 0.5 * (x + xn), ym = 0.5 * (y + yn), zm = 0.5 * (z + zn);
+    const double rm = sqrt(xm * xm + ym * ym), rn = sqrt(xn * xn + yn * yn);
+    jz = stencil(p, zm, rm, s, 0.5, false);
+    jr = stencil(p, zm, rm, s, 0.0, true);
+    const bool ok = inside(p, jz) && inside(p, jr) && inside(p, stencil(p, zn, rn, s, 0.5, false)) &&
+                    inside(p, stencil(p, zn, rn, s, 0.0, true)) && inside(p, stencil(p, zn, rn, s, 0.5, true));
+    if (!ok) {
+      b[6 * cap + q] = 0.0;   // lost
+    } else {
+      b[q] = xn;
+      b[cap + q] = yn;
+      b[2 * cap + q] = zn;
+      vz = w * bz;
+      vr = w * (rm > 0.0 ? (xm * bx + ym * by) / rm : 0.0);
+      live = true;
+      atomicMin(&cmin, min(jz.i0, jr.i0));
+      atomicMax(&cmax, max(jz.i0, jr.i0) + 1);
+      atomicMax(&rmax, max(jz.j0, jr.j0) + 1);
+    }
+  }
+  __syncthreads();
+  A* J = (A*)jbv;
+  const int c0 = cmin, nc = cmax - cmin + 1, nrow = rmax + 1;
+  if (cmax < 0) return;                          // no live particle in the block (uniform)
+  if (nc > TW || nrow > TRW) {                   // too spread for the tile: straight to the grid
+    if (live) {
+      deposit(p, jz, false, vz, J);
+      deposit(p, jr, true, vr, J + p.plane);
+    }
     return;
   }
-  b[q] = xn;
-  b[cap + q] = yn;
-  b[2 * cap + q] = zn;
-  const double br = rm > 0.0 ? (xm * bx + ym * by) / rm : 0.0;
-  A* J = (A*)jbv;
-  deposit(p, jz, false, w * bz, J);
-  deposit(p, jr, true, w * br, J + p.plane);
+  for (int t = threadIdx.x; t < nrow * TW; t += BT) {
+    tile[0][t] = A(0);
+    tile[1][t] = A(0);
+  }
+  __syncthreads();
+  if (live) {
+    deposit_tile(p, jz, false, vz, tile[0], c0);
+    deposit_tile(p, jr, true, vr, tile[1], c0);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nrow * TW; t += BT) {
+    const int j = t / TW, c = t % TW;
+    if (c >= nc) continue;
+    const long long o = (long long)j * p.pitch + c0 + c;
+    if (tile[0][t] != A(0)) atomic_add(J + o, (double)tile[0][t]);
+    if (tile[1][t] != A(0)) atomic_add(J + p.plane + o, (double)tile[1][t]);
+  }
 }
 
 template <int ST>

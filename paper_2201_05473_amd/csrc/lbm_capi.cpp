@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
+#include <vector>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -172,9 +174,11 @@ struct lbm_ctx {
   // events; created on first use, default priority
   hipStream_t aux = nullptr;
   hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
-  // particle driver: particles in the bunch, and the deposit buffer the next step fills
+  // particle driver: particles in the bunch, the deposit buffer the next step fills, and the
+  // caller's index of each stored particle (the bunch is stored in z order)
   long long nbunch = 0;
   int jcur = 0;
+  std::vector<int64_t> order;
   double* bunch() { return (double*)(ws + L.bunch); }
   void* jb(int b) { return ws + L.jb[b]; }
   double* dens() { return (double*)(ws + L.dens); }
@@ -1114,18 +1118,50 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 // ------------------------------------------------------------------------------------------
 // Particle driver: the bunch
 // ------------------------------------------------------------------------------------------
+namespace {
+int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields);
+int get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n);
+}  // namespace
+
 int lbm_set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
+  try {
+    return set_bunch(c, n, bunch, init_fields);
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_ENOMEM, "host allocation failed");
+  }
+}
+
+int lbm_get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
+  try {
+    return get_bunch(c, bunch, n_max, n);
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_ENOMEM, "host allocation failed");
+  }
+}
+
+namespace {
+
+int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (c->p.driver != LBM_DRIVER_PARTICLES) return fail(LBM_EINVAL, "the bunch needs driver = LBM_DRIVER_PARTICLES");
   if (n < 0 || n > c->p.cap) return fail(LBM_EINVAL, "n must lie in [0, max_particles] (got %lld)", (long long)n);
   if (n > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
   if (init_fields != 0 && init_fields != 1) return fail(LBM_EINVAL, "init_fields must be 0 or 1");
   if (init_fields && c->k != 0) return fail(LBM_EINVAL, "the initial field can only be set at step 0");
+  // stored in z order, so that the particles of a thread block deposit into a few columns
+  c->order.resize((size_t)n);
+  std::iota(c->order.begin(), c->order.end(), (int64_t)0);
+  std::stable_sort(c->order.begin(), c->order.end(),
+                   [&](int64_t a, int64_t b) { return bunch[2 * n + a] < bunch[2 * n + b]; });
+  std::vector<double> sorted((size_t)(7 * n));
+  for (int comp = 0; comp < 7; ++comp)
+    for (int64_t i = 0; i < n; ++i) sorted[(size_t)(comp * n + i)] = bunch[comp * n + c->order[(size_t)i]];
   for (int comp = 0; comp < 7; ++comp)
     if (n > 0)
-      HIP_CHECK(hipMemcpyAsync(c->bunch() + comp * c->p.cap, bunch + comp * n, (size_t)n * sizeof(double),
+      HIP_CHECK(hipMemcpyAsync(c->bunch() + comp * c->p.cap, sorted.data() + comp * n, (size_t)n * sizeof(double),
                                hipMemcpyHostToDevice, c->stream),
                 "bunch upload");
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");   // before the host buffer goes
   c->nbunch = n;
   if (init_fields && c->p.fields_on) {
     // E_r^{-1} from the density at the positions (t = -dt) on the E_r columns; B^{-1/2} from the
@@ -1144,17 +1180,23 @@ int lbm_set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_field
   return LBM_OK;
 }
 
-int lbm_get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
+int get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (c->p.driver != LBM_DRIVER_PARTICLES) return fail(LBM_EINVAL, "the bunch needs driver = LBM_DRIVER_PARTICLES");
   if (!n) return fail(LBM_EINVAL, "n is NULL");
   if (n_max < c->nbunch) return fail(LBM_EINVAL, "n_max %lld < %lld particles", (long long)n_max, c->nbunch);
   if (c->nbunch > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
-  for (int comp = 0; comp < 7 && c->nbunch > 0; ++comp)
-    HIP_CHECK(hipMemcpyAsync(bunch + comp * c->nbunch, c->bunch() + comp * c->p.cap,
-                             (size_t)c->nbunch * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+  const long long nb = c->nbunch;
+  std::vector<double> stored((size_t)(7 * nb));
+  for (int comp = 0; comp < 7 && nb > 0; ++comp)
+    HIP_CHECK(hipMemcpyAsync(stored.data() + comp * nb, c->bunch() + comp * c->p.cap, (size_t)nb * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream),
               "bunch download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
-  *n = c->nbunch;
+  for (int comp = 0; comp < 7; ++comp)   // back to the caller's order
+    for (long long i = 0; i < nb; ++i) bunch[comp * nb + c->order[(size_t)i]] = stored[(size_t)(comp * nb + i)];
+  *n = nb;
   return LBM_OK;
 }
+
+}  // namespace
