@@ -12,6 +12,7 @@ import torch
 
 import workloads as wl
 from oracle import lbm_oracle as O
+from strips import group_errors, strip_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -31,26 +32,7 @@ def oracle_state(S, P):
                            np.stack([S.Ez.numpy(), S.Er.numpy(), S.B.numpy()])])
 
 
-# Components that share a physical scale: density populations, momentum populations (n p_z and
-# n p_r lattices), density moment, momentum moments, and the three fields.  Errors are taken
-# relative to the largest reference value of the group, so that a component that is exactly zero
-# up to round-off in the reference (e.g. E_z right after the Gauss-consistent initial state,
-# where the discrete curl of B cancels the driver current) does not make the norm ill-posed.
-GROUPS = [range(0, 9), range(9, 27), range(27, 28), range(28, 30), range(30, 33)]
-
-
-def comp_errors(st, ref):
-    errs = np.zeros(ref.shape[0])
-    if ref.shape[0] != 33:
-        groups = [range(ref.shape[0])]
-    else:
-        groups = GROUPS
-    for g in groups:
-        den = max(np.abs(ref[c]).max() for c in g)
-        for c in g:
-            num = np.abs(st[c] - ref[c]).max()
-            errs[c] = num / den if den > 0 else num
-    return errs
+comp_errors = group_errors
 
 
 def run_gpu(cfg, nsteps, n_pert=None, p_init=None):
@@ -248,6 +230,48 @@ def test_full_size_c2_single_steps():
             else:
                 assert errs[27:].max() < tol, errs[27:]
             lat.close()
+
+
+STRIP_W = 320      # columns of the front strip: inflow column, ramp, plasma edge and the driver
+STRIP_REAR = 64    # columns of the rear strip
+
+
+@pytest.mark.parametrize("name", ["C3", "C5"])
+def test_full_size_strips(name):
+    """C3 (4096 x 1024) and C5 (8192 x 2048) at full size: one step from the initial state and
+    one window-shift step (step counter set to 4), compared with the oracle on full-height
+    strips (axis to outer edge): the front strip holds the inflow column, the ramp, the plasma
+    edge and the driver (everything that is not vacuum at t = 0), the rear strip the rear
+    boundary.  The oracle steps each strip as a problem of its own (tests/strips.py); columns
+    near a cut edge are left out.  FP64 to 1e-10, FP32 moments and fields to 1e-6."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config(name, storage=wl.F64)
+    nz = cfg["nz"]
+    strips = ((nz - STRIP_W, STRIP_W), (0, STRIP_REAR))
+    refs = {(k0, c0): strip_reference(cfg, c0, w, k0) for k0 in (0, 4) for c0, w in strips}
+    for k0 in (0, 4):
+        front = refs[(k0, nz - STRIP_W)][0]
+        assert front[27].max() > 0.1 and np.abs(front[31:33]).max() > 1e-3   # plasma and driver field
+    for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6)):
+        for k0 in (0, 4):
+            print(f"[full size strips] {name} k0={k0} storage={storage}", flush=True)
+            lat = Lattice(dict(cfg, storage=storage))
+            if k0:
+                st0, _, _ = lat.state()
+                lat.set_state(st0, k0, 0)
+                del st0
+            lat.step(1)
+            st, k, s = lat.state()
+            lat.close()
+            assert (k, s) == (k0 + 1, 1 if k0 == 4 else 0)
+            for c0, _ in strips:
+                ref, a, b = refs[(k0, c0)]
+                errs = comp_errors(st[:, :, a:b], ref)
+                if storage == wl.F64:
+                    assert errs.max() < tol, (c0, errs.argmax(), errs.max())
+                else:
+                    assert errs[27:].max() < tol, (c0, errs[27:])
+            del st
 
 
 def test_periodic_conservation_at_full_size():
