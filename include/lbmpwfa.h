@@ -268,8 +268,10 @@ int lbm_bubble_length(lbm_ctx* ctx, int32_t row, double n_star, double z_from, d
  * init_fields = 1 (only at step 0) also sets the initial field from the bunch: E_z = 0, E_r and
  * B_theta from the discrete Gauss law of the bunch density deposited at t = -dt (E_r) and at
  * t = -dt/2 (B_theta, with B_theta = E_r as for a bunch at c); the fluid is not touched.
- * init_fields = 0 keeps the fields (to resume a run).  Synchronising.  LBM_EINVAL for another
- * driver, n out of range, or init_fields at a step other than 0. */
+ * init_fields = 0 keeps the fields (to resume a run).  The library keeps its own copy, stored in
+ * an order of its choosing (lbm_get_bunch returns the caller's order).  Synchronising.
+ * LBM_EINVAL for another driver, n out of range, a non-finite value, a negative weight, or
+ * init_fields at a step other than 0. */
 int lbm_set_bunch(lbm_ctx* ctx, int64_t n, const double* bunch, int32_t init_fields);
 
 /* Current bunch, [7][n] in the layout of lbm_set_bunch, into host memory of at least 7 * n_max

@@ -175,7 +175,7 @@ struct lbm_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   // particle driver: particles in the bunch, the deposit buffer the next step fills, and the
-  // caller's index of each stored particle (the bunch is stored in z order)
+  // caller's index of each stored particle (the bunch is stored by column of z, then radius)
   long long nbunch = 0;
   int jcur = 0;
   std::vector<int64_t> order;
@@ -290,6 +290,10 @@ int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init, 
 int lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  // particle driver: the push of a step and the move of the next run as one launch between two
+  // steps of this call (not across a diagnostic check, which reads the bunch at t_{k-1}); moved:
+  // the bunch is already at t_k with J_b(t_{k-1/2}) in jb(jcur)
+  bool moved = false;
   for (int64_t n = 0; n < nsteps; ++n) {
     lbm::StepArgs a;
     a.p = c->p;
@@ -307,17 +311,25 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     a.jb_zero = nullptr;
     if (c->p.driver == 1) {
       // particles to t_k and their current J_b(t_{k-1/2}) into the buffer the previous step cleared
-      HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,
-                                       c->jb(c->jcur), c->stream),
-                "bunch launch");
+      if (!moved)
+        HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,
+                                         c->jb(c->jcur), c->stream),
+                  "bunch launch");
       a.jb_in = c->jb(c->jcur);
       a.jb_zero = c->jb(1 - c->jcur);
     }
     HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "step launch");
     if (c->p.driver == 1) {
-      HIP_CHECK(lbm::launch_bunch_push(c->storage, c->p, c->s, a.shift, c->E(c->cur), c->E(1 - c->cur), c->bunch(),
-                                       (int)c->nbunch, c->p.cap, c->stream),
-                "bunch launch");
+      const bool check_next = c->cfg.check_every > 0 && (c->k + 1) % c->cfg.check_every == 0;
+      moved = n + 1 < nsteps && !check_next;
+      if (moved)
+        HIP_CHECK(lbm::launch_bunch_push_move(c->storage, c->p, c->s, a.shift, c->E(c->cur), c->E(1 - c->cur),
+                                              c->bunch(), (int)c->nbunch, c->p.cap, c->jb(1 - c->jcur), c->stream),
+                  "bunch launch");
+      else
+        HIP_CHECK(lbm::launch_bunch_push(c->storage, c->p, c->s, a.shift, c->E(c->cur), c->E(1 - c->cur),
+                                         c->bunch(), (int)c->nbunch, c->p.cap, c->stream),
+                  "bunch launch");
       c->jcur ^= 1;
     }
     c->cur ^= 1;
@@ -1148,11 +1160,23 @@ int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
   if (n > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
   if (init_fields != 0 && init_fields != 1) return fail(LBM_EINVAL, "init_fields must be 0 or 1");
   if (init_fields && c->k != 0) return fail(LBM_EINVAL, "the initial field can only be set at step 0");
-  // stored in z order, so that the particles of a thread block deposit into a few columns
+  for (int64_t i = 0; i < 7 * n; ++i)
+    if (!std::isfinite(bunch[i])) return fail(LBM_EINVAL, "bunch value %lld is not finite", (long long)i);
+  for (int64_t i = 0; i < n; ++i)
+    if (bunch[6 * n + i] < 0.0) return fail(LBM_EINVAL, "particle %lld has a negative weight", (long long)i);
+  // stored by grid column of z and, within a column, by radius: the 64 particles of a wavefront
+  // then share a few rows and columns, so that their field gathers and current deposits touch
+  // few cache lines, and a thread block's deposit fits its LDS tile
+  std::vector<double> col((size_t)n), rad((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    col[(size_t)i] = std::floor(bunch[2 * n + i] / c->p.h);
+    rad[(size_t)i] = bunch[i] * bunch[i] + bunch[n + i] * bunch[n + i];
+  }
   c->order.resize((size_t)n);
   std::iota(c->order.begin(), c->order.end(), (int64_t)0);
-  std::stable_sort(c->order.begin(), c->order.end(),
-                   [&](int64_t a, int64_t b) { return bunch[2 * n + a] < bunch[2 * n + b]; });
+  std::stable_sort(c->order.begin(), c->order.end(), [&](int64_t a, int64_t b) {
+    return col[(size_t)a] < col[(size_t)b] || (col[(size_t)a] == col[(size_t)b] && rad[(size_t)a] < rad[(size_t)b]);
+  });
   std::vector<double> sorted((size_t)(7 * n));
   for (int comp = 0; comp < 7; ++comp)
     for (int64_t i = 0; i < n; ++i) sorted[(size_t)(comp * n + i)] = bunch[comp * n + c->order[(size_t)i]];

@@ -98,6 +98,10 @@ hipError_t launch_bunch_move(int storage, const Physics& p, long long s, double*
 // Boris push with E^k, B^{k+1/2} (Eout, frame s + shift) and B^{k-1/2} (Ein, frame s).
 hipError_t launch_bunch_push(int storage, const Physics& p, long long s, int shift, const void* Ein,
                              const void* Eout, double* bunch, int n, long long cap, hipStream_t st);
+// The push of step k (arguments as above) and the move of step k + 1 (frame s + shift, deposit into
+// jb) in one launch.
+hipError_t launch_bunch_push_move(int storage, const Physics& p, long long s, int shift, const void* Ein,
+                                  const void* Eout, double* bunch, int n, long long cap, void* jb, hipStream_t st);
 // Bunch density (FP64, atomics) on the nodes z = (s + i + zoff) dz, rows (j + 1/2) dr, positions moved
 // by t_ahead along the velocities; dens must be cleared first.
 hipError_t launch_bunch_density(const Physics& p, long long s, double zoff, double t_ahead, const double* bunch,

@@ -81,6 +81,34 @@ def test_fp64_parity(name):
     lat.close()
 
 
+def test_call_splits_and_checks_agree():
+    """Within one lbm_step call the push of a step and the move of the next run as one launch; a
+    call boundary or a diagnostic check splits them.  One call of 45 steps, 45 calls of one step,
+    and calls of 13 + 32 steps with a check every 7 steps all give the oracle's state and bunch
+    (FP64, 1e-10), with the deflected slow bunch (losses included)."""
+    c = CASES["slow_deflected"]
+    base = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=4.0,
+                     driver=wl.PARTICLES, max_particles=6000, storage=wl.F64, noise_amp=1e-3, seed=4,
+                     tau=0.7, **c["cfg"])
+    b = wl.bunch(base, 5000, gamma=c["gamma"], emittance=c["emittance"], energy_spread=c["spread"], seed=8)
+    pert = wl.density_perturbation(base)
+    S, P = O.run(base, 45, pert, bunch=b)
+    ref_state, ref_b = oracle_state(S, P), S.bunch.numpy()
+    for label, cfg, calls in (("one call", base, [45]), ("single steps", base, [1] * 45),
+                              ("checks", dict(base, check_every=7), [13, 32])):
+        print(f"[bunch calls] {label}", flush=True)
+        lat = lattice(cfg, b, pert)
+        for n in calls:
+            lat.step(n)
+        st, k, s = lat.state()
+        assert (k, s) == (S.k, S.s)
+        assert comp_errors(st, ref_state).max() < TOL64, label
+        bg = lat.bunch()
+        assert np.array_equal(bg[6] == 0.0, ref_b[6] == 0.0), label
+        assert max(bunch_errors(bg, ref_b)) < 1e-10, label
+        lat.close()
+
+
 def test_initial_gauss_law_from_the_bunch():
     """Right after lbm_set_bunch the discrete Gauss residual (driver density from the deposited
     bunch) vanishes, and the initial field matches the oracle's."""
@@ -130,6 +158,17 @@ def test_bunch_interface_errors():
         lat.set_bunch(np.zeros((7, 11)))                 # over capacity
     assert ei.value.code == LBM_EINVAL
     b = wl.bunch(cfg, 10, seed=1)
+    for bad in (np.nan, np.inf):
+        nb = b.copy()
+        nb[2, 3] = bad
+        with pytest.raises(LbmError) as ei:
+            lat.set_bunch(nb)                            # non-finite coordinate
+        assert ei.value.code == LBM_EINVAL
+    nb = b.copy()
+    nb[6, 0] = -1.0
+    with pytest.raises(LbmError) as ei:
+        lat.set_bunch(nb)                                # negative weight
+    assert ei.value.code == LBM_EINVAL
     lat.set_bunch(b)
     assert np.array_equal(lat.bunch(), b)
     lat.step(2)
