@@ -81,7 +81,7 @@ enum { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2 };
 enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
 
 /* Run configuration.  Physical meaning (normalised units):
- *   nz, nr        grid size (both >= 3)
+ *   nz, nr        grid size: both >= 3, nr <= 65535, nz nr <= 2^26 sites
  *   dz, dr        cell size; must be equal (the D2Q9 lattice is square)
  *   c_dt_over_dz  c dt / dz, in (0, 1/sqrt(3)); keeps the lattice velocity below c_s and the
  *                 Yee scheme stable.  With moving_window it must be 1/m for an integer m

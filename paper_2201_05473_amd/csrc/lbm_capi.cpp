@@ -51,6 +51,7 @@ int validate(const lbm_config* c, Physics* p) {
   if (c->nz < 3 || c->nr < 3) return fail(LBM_EINVAL, "nz and nr must be >= 3 (got %d, %d)", c->nz, c->nr);
   if ((long long)c->nz * c->nr > (1LL << 31) / 32)
     return fail(LBM_EINVAL, "grid too large (%d x %d)", c->nz, c->nr);
+  if (c->nr > 65535) return fail(LBM_EINVAL, "nr must be <= 65535 (got %d)", c->nr);   // rows on grid y
   if (!(c->dz > 0.0) || !std::isfinite(c->dz)) return fail(LBM_EINVAL, "dz must be positive");
   if (std::fabs(c->dr - c->dz) > 1e-12 * c->dz) return fail(LBM_EINVAL, "dz and dr must be equal");
   const double lam = c->c_dt_over_dz;

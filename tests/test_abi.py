@@ -69,12 +69,20 @@ def test_struct_layout_matches_c(lib, tmp_path):
     dict(collision=3), dict(collision=-1), dict(collision=1, trt_magic=0.0),
     dict(collision=1, trt_magic=float("inf")),
     dict(driver=2), dict(driver=1, max_particles=-1), dict(driver=1, max_particles=2 ** 31),
+    dict(nz=8192, nr=8193), dict(nz=64, nr=65536), dict(tau=float("nan")), dict(dz=-0.05, dr=-0.05),
 ])
 def test_invalid_configs_rejected(lib, bad):
     with pytest.raises(lib.LbmError) as ei:
         lib.lbm_workspace_bytes(wl.config(None, **bad))
     assert ei.value.code == lib.LBM_EINVAL
     assert lib.lbm_last_error() != ""
+
+
+def test_largest_grid_accepted(lib):
+    """2^26 sites is the largest grid (every in-plane offset stays below 2^31 elements), and 65535
+    rows the most (rows are a launch dimension of some kernels)."""
+    assert lib.lbm_workspace_bytes(wl.config(None, nz=8192, nr=8192, storage=wl.F64)) > 2 * 27 * 8 * 2 ** 26
+    assert lib.lbm_workspace_bytes(wl.config(None, nz=64, nr=65535)) > 0
 
 
 def test_trt_magic_ignored_by_other_operators(lib):

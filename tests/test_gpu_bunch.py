@@ -109,6 +109,29 @@ def test_call_splits_and_checks_agree():
         lat.close()
 
 
+def test_empty_bunch():
+    """A particle-driven context with no particles (and one whose bunch was never set) evolves as
+    the plasma with no driver: the oracle's state for an empty bunch, FP64 to 1e-10, over 12
+    steps with two window shifts."""
+    cfg = wl.config(None, nz=70, nr=9, dz=0.05, dr=0.05, driver=wl.PARTICLES, max_particles=10,
+                    storage=wl.F64, noise_amp=1e-3, seed=3, moving_window=1, tau=0.7)
+    pert = wl.density_perturbation(cfg)
+    S, P = O.run(cfg, 12, pert, bunch=np.zeros((7, 0)))
+    ref = oracle_state(S, P)
+    from paper_2201_05473_amd import Lattice
+    for set_empty in (True, False):
+        print(f"[empty bunch] set_bunch(empty)={set_empty}", flush=True)
+        lat = Lattice(cfg, pert)
+        if set_empty:
+            lat.set_bunch(np.zeros((7, 0)), True)
+        lat.step(12)
+        st, k, s = lat.state()
+        assert (k, s) == (S.k, S.s)
+        assert comp_errors(st, ref).max() < TOL64
+        assert lat.bunch().shape == (7, 0)
+        lat.close()
+
+
 def test_initial_gauss_law_from_the_bunch():
     """Right after lbm_set_bunch the discrete Gauss residual (driver density from the deposited
     bunch) vanishes, and the initial field matches the oracle's."""

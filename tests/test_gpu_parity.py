@@ -274,6 +274,34 @@ def test_full_size_strips(name):
             del st
 
 
+def test_maximum_grid_uniform_oscillation():
+    """The largest grid the library accepts, 8192 x 8192 = 2^26 sites, FP32 storage, z-periodic
+    and cylindrical: a uniform plasma with p_z = eps oscillates by the exact discrete map of the
+    symplectic coupling (the closed form of the CPU pin, which a uniform current keeps valid in
+    cylindrical geometry: B stays zero), E^{k-1} = eps sin(k theta) / sqrt(1 - h^2 / 4), at every
+    site after 40 steps; the density stays uniform and E_r, B_theta, J_r stay zero.  A tile that
+    is skipped or mis-indexed anywhere in the grid breaks it."""
+    from paper_2201_05473_amd import Lattice
+    eps = 1e-6
+    cfg = wl.config(None, nz=8192, nr=8192, dz=0.02, dr=0.02, periodic=1, nb=0.0, tau=0.8,
+                    storage=wl.F32)
+    print("[maximum grid] 8192 x 8192 FP32, 40 steps", flush=True)
+    lat = Lattice(cfg, None, wl.uniform_momentum(cfg, pz=eps))
+    lat.step(40)
+    f = lat.fields()
+    m = lat.moments()
+    h = cfg["c_dt_over_dz"] * cfg["dz"]
+    ref = eps * math.sin(40 * 2 * math.asin(h / 2)) / math.sqrt(1 - h * h / 4)
+    assert abs(ref) > 0.1 * eps
+    assert float((f[0] - ref).abs().max()) < 1e-4 * abs(ref)
+    assert float(f[1].abs().max()) < 1e-6 * eps and float(f[2].abs().max()) < 1e-6 * eps
+    assert float((m[0] - 1.0).abs().max()) < 1e-6
+    assert float((m[1] - m[1][0, 0]).abs().max()) < 1e-4 * float(m[1][0, 0].abs())
+    assert float(m[2].abs().max()) < 1e-6 * eps
+    del f, m
+    lat.close()
+
+
 def test_periodic_conservation_at_full_size():
     """Property at any size: with periodic z and r, Cartesian and no fields, the global charge
     is conserved by the step (streaming is a permutation), here at 2048 x 512 in FP64."""
