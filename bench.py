@@ -28,7 +28,7 @@ KERNEL_SOURCES = ("paper_2201_05473_amd/csrc/lbm_kernels.hip", "paper_2201_05473
 def bytes_per_site(storage: int) -> int:
     """Algorithmic HBM bytes per site and step of the fused kernel: 27 populations read and
     written, and the auxiliary planes (3 moments, E_z, E_r, B_theta) read and written once."""
-    s_pop = {0: 8, 1: 4, 2: 2}[storage]
+    s_pop = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
     s_aux = 8 if storage == 0 else 4
     return 2 * 27 * s_pop + 2 * 6 * s_aux
 
@@ -260,7 +260,7 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3: the headline FP32 run only, then a plain 1 GiB device copy "
                          "(the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--storage", choices=("f64", "f32", "f16"), default="f32",
+    ap.add_argument("--storage", choices=("f64", "f32", "f16", "f16n"), default="f32",
                     help="population storage of the --profile run")
     ap.add_argument("--c5", action="store_true",
                     help="the long-plasma case C5 instead of the headline: forward MLUPS, adjoint under "
@@ -310,7 +310,7 @@ def main():
         return
 
     if args.profile:
-        storage = {"f64": wl.F64, "f32": wl.F32, "f16": wl.F16}[args.storage]
+        storage = {"f64": wl.F64, "f32": wl.F32, "f16": wl.F16, "f16n": wl.F16N}[args.storage]
         wall, ev_s, lat = time_run(dict(cfg, storage=storage), steps, warmup)
         lat.close()
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
@@ -352,7 +352,7 @@ def main():
         lat32.close()
         runs = {"f32": (wl.F32, 0, wall, ev_s, ref_f, ref_m)}
         for name, storage, m64 in (("f64", wl.F64, 0), ("f32_fp64math", wl.F32, 1),
-                                   ("f16", wl.F16, 0)):
+                                   ("f16", wl.F16, 0), ("f16n", wl.F16N, 0)):
             w, e, lat = time_run(dict(cfg, storage=storage, fp64_math=m64), steps, warmup)
             runs[name] = (storage, m64, w, e, lat.fields(), lat.moments())
             lat.close()
@@ -361,7 +361,7 @@ def main():
         for name, (storage, m64, w, e, fl, mo) in runs.items():
             b = bytes_per_site(storage)
             modes[name] = {
-                "storage": {0: "f64", 1: "f32", 2: "f16"}[storage],
+                "storage": {0: "f64", 1: "f32", 2: "f16", 3: "f16n"}[storage],
                 "arithmetic": "f64" if (storage == 0 or m64) else "f32",
                 "MLUPS": sites * steps / w / 1e6,
                 "alg_GBps": b * sites / (e / steps) / 1e9,
@@ -375,7 +375,7 @@ def main():
         # HBM-scale lattice (C3, 4096 x 1024, working set well above the 256 MB Infinity Cache)
         c3 = {}
         for name, storage, m64 in (("f32", wl.F32, 0), ("f32_fp64math", wl.F32, 1),
-                                   ("f64", wl.F64, 0), ("f16", wl.F16, 0)):
+                                   ("f64", wl.F64, 0), ("f16", wl.F16, 0), ("f16n", wl.F16N, 0)):
             ccfg = wl.config("C3", storage=storage, fp64_math=m64)
             n3 = ccfg["nz"] * ccfg["nr"]
             w, e, lat = time_run(ccfg, 1000, 50)

@@ -46,8 +46,11 @@ enum {
 /* Storage precision of the populations.  F64: populations, fields and arithmetic in FP64.
  * F32: populations and fields in FP32, FP32 arithmetic.  F16: populations in FP16, fields and
  * arithmetic in FP32.  The density lattice is stored as the deviation from the rest equilibrium
- * w_i n_bg(z); diagnostics are always accumulated in FP64. */
-enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+ * w_i n_bg(z); diagnostics are always accumulated in FP64.  F16N: as F16, but each population
+ * is stored as its part off the equilibrium (Eq. (9)) of the moments stored at its own site,
+ * which are FP32: the same bytes as F16 with about a tenth of its error, for more arithmetic per
+ * step.  The adjoint (lbm_adjoint, lbm_vjp_*) takes F64, F32 and F16. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_F16N = 3 };
 
 /* Collision operator of the three lattices.  The paper uses BGK (Eq. (7)) and notes (Sec. IV)
  * that BGK is the simplest choice and that other collision operators may stabilise the
@@ -86,7 +89,7 @@ enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
  *   c_dt_over_dz  c dt / dz, in (0, 1/sqrt(3)); keeps the lattice velocity below c_s and the
  *                 Yee scheme stable.  With moving_window it must be 1/m for an integer m
  *   tau           BGK relaxation time in lattice units, > 1/2; D = (tau - 1/2)/3 dz^2/dt (Eq. (12))
- *   storage       LBM_F64, LBM_F32 or LBM_F16
+ *   storage       LBM_F64, LBM_F32, LBM_F16 or LBM_F16N
  *   moving_window 1: shift the window one cell every m = 1/(c dt/dz) steps
  *   periodic      bit 0: periodic in z (excludes moving_window); bit 1: periodic in r
  *                 (requires fields_on = 0 and cyl_on = 0)

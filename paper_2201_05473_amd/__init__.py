@@ -5,6 +5,7 @@ The compute path is the HIP library liblbmpwfa.so (built by ``build.py``) behind
 device memory and streams.
 """
 from .binding import (LBM_EHIP, LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EUNSTABLE, LBM_F16,
+                      LBM_F16N,
                       LBM_F32, LBM_F64, LBM_OK, Lattice, LbmError, lbm_checkpoint_bytes, lbm_counters, lbm_destroy,
                       lbm_diagnostics, lbm_fields, lbm_get_state, lbm_init, lbm_last_error,
                       lbm_load, lbm_moments, lbm_save, lbm_set_state, lbm_step, lbm_workspace_bytes, load_library,
@@ -14,7 +15,7 @@ from .binding import (LBM_EHIP, LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EUNSTABL
 from .autograd import LbmWake, wake_objective
 
 __all__ = [
-    "LBM_OK", "LBM_EINVAL", "LBM_ENOMEM", "LBM_EHIP", "LBM_EUNSTABLE", "LBM_ESTATE", "LBM_F16", "LBM_F32", "LBM_F64", "Lattice", "LbmError", "load_library",
+    "LBM_OK", "LBM_EINVAL", "LBM_ENOMEM", "LBM_EHIP", "LBM_EUNSTABLE", "LBM_ESTATE", "LBM_F16", "LBM_F16N", "LBM_F32", "LBM_F64", "Lattice", "LbmError", "load_library",
     "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_fields", "lbm_get_state",
     "lbm_set_state", "lbm_diagnostics", "lbm_checkpoint_bytes", "lbm_save", "lbm_load", "lbm_adjoint", "lbm_adjoint_workspace_bytes",
     "lbm_adjoint_revolve", "lbm_adjoint_revolve_workspace_bytes", "lbm_bubble_length", "lbm_set_bunch",

@@ -14,8 +14,8 @@ import os
 import numpy as np
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-LBM_F64, LBM_F32, LBM_F16 = 0, 1, 2
-_STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
+LBM_F64, LBM_F32, LBM_F16, LBM_F16N = 0, 1, 2, 3
+_STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "f16n": LBM_F16N}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "liblbmpwfa.so")

@@ -58,7 +58,7 @@ int validate(const lbm_config* c, Physics* p) {
   if (!(lam > 0.0) || !(lam < 1.0 / std::sqrt(3.0)))
     return fail(LBM_EINVAL, "c_dt_over_dz must lie in (0, 1/sqrt(3)) (got %g)", lam);
   if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_EINVAL, "tau must exceed 1/2 (got %g)", c->tau);
-  if (c->storage != LBM_F64 && c->storage != LBM_F32 && c->storage != LBM_F16)
+  if (c->storage != LBM_F64 && c->storage != LBM_F32 && c->storage != LBM_F16 && c->storage != LBM_F16N)
     return fail(LBM_EINVAL, "unknown storage %d", c->storage);
   if (c->periodic < 0 || c->periodic > 3) return fail(LBM_EINVAL, "periodic must be in [0, 3]");
   const int per_z = c->periodic & 1, per_r = (c->periodic >> 1) & 1;
@@ -395,7 +395,9 @@ int lbm_set_state(lbm_ctx* c, const double* src, int64_t step, int64_t shifts) {
   if (step < 0 || shifts < 0) return fail(LBM_EINVAL, "counters must be >= 0");
   const size_t pl = (size_t)c->p.nr * c->p.nz;
   double* stage = (double*)c->staging();
-  for (int comp = 0; comp < 33; ++comp) {
+  // moments and fields first: LBM_F16N stores each population relative to its site's moments
+  for (int n = 0; n < 33; ++n) {
+    const int comp = (n + 27) % 33;
     HIP_CHECK(hipMemcpyAsync(stage, src + comp * pl, pl * sizeof(double), hipMemcpyHostToDevice,
                              c->stream),
               "upload");
@@ -577,6 +579,7 @@ int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
   if ((c->p.per_z && c->p.nz < 5) || (c->p.per_r && c->p.nr < 5))
     return fail(LBM_EINVAL, "the adjoint needs at least 5 cells along periodic dimensions");
   if (c->p.coll != LBM_BGK) return fail(LBM_EINVAL, "the adjoint is implemented for the BGK collision only");
+  if (c->storage == LBM_F16N) return fail(LBM_EINVAL, "the adjoint is implemented for LBM_F64, LBM_F32 and LBM_F16 storage");
   if (c->p.driver != LBM_DRIVER_RIGID) return fail(LBM_EINVAL, "the adjoint is implemented for the rigid driver only");
   return LBM_OK;
 }

@@ -21,6 +21,15 @@ template <> struct Mode<1, false> { using S = float;  using C = float;  using A 
 template <> struct Mode<1, true>  { using S = float;  using C = double; using A = float;  using CF = double; };
 template <> struct Mode<2, false> { using S = __half; using C = float;  using A = float;  using CF = float; };
 template <> struct Mode<2, true>  { using S = __half; using C = double; using A = float;  using CF = double; };
+// FP16 storage of the populations' part off the equilibrium of their site's stored moments
+template <> struct Mode<3, false> { using S = __half; using C = float;  using A = float;  using CF = float; };
+template <> struct Mode<3, true>  { using S = __half; using C = double; using A = float;  using CF = double; };
+
+// Storage mode 3 keeps, for each population g_q(x), only g_q(x) - f_eq_q(M(x)): its part off the
+// equilibrium of the moments M(x) stored at the same site (FP32), in FP16.  That part is small
+// next to g_q wherever the flow is near equilibrium, so its 11-bit significand loses far less
+// than storing g_q (or its deviation from rest) does.
+__host__ __device__ constexpr bool neq_storage(int ST) { return ST == 3; }
 
 __device__ __forceinline__ double ldv(double x) { return x; }
 __device__ __forceinline__ float ldv(float x) { return x; }
@@ -46,6 +55,19 @@ __host__ __device__ constexpr int XR(int q) {
 }
 template <typename C> __host__ __device__ constexpr C WQ(int q) {
   return q == 0 ? C(4) / C(9) : (q < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+// Equilibrium of direction q (Eq. (9), standard D2Q9 coefficients) for the three lattices at
+// moments with density deviation d0 from n_bg (density m0 = n_bg + d0), momenta a1, a2 and lattice
+// velocity (uz, ur); lattice 0 as the deviation from w_q n_bg.
+template <typename C>
+__device__ __forceinline__ void eq_dir(int q, C d0, C m0, C a1, C a2, C uz, C ur, C& e0, C& e1, C& e2) {
+  const C w = WQ<C>(q);
+  const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+  const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * (uz * uz + ur * ur);
+  e0 = w * (d0 + m0 * Q);
+  e1 = w * a1 * (C(1) + Q);
+  e2 = w * a2 * (C(1) + Q);
 }
 
 // Background (ion) density n_bg(z): uniform, linear ramp or tanh ramp (always FP64).

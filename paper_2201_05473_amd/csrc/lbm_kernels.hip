@@ -35,7 +35,8 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   using CF = typename Mode<ST, M64>::CF;
   // sums of the eight moving equilibria: FP64, except for FP16 storage, whose error is set by its
   // storage and whose step is instruction-bound (FP64 sums cost it 6 %)
-  using SE = typename std::conditional<ST == 2, C, double>::type;
+  using SE = typename std::conditional<ST >= 2, C, double>::type;
+  constexpr bool NEQ = neq_storage(ST);   // populations stored off their site's equilibrium
   const Physics& p = a.p;
   constexpr int MZ = TZ + 2, MR = TR + 2;    // moments:  cols i0-1..i0+TZ,   rows j0-1..j0+TR
   constexpr int BZ = TZ + 3, BR = TR + 3;    // B^{k-1/2}: cols i0-2..i0+TZ,  rows j0-2..j0+TR
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
   __shared__ CF sIr[EZR];   // 1 / r_j at the fluid / E_z rows
   __shared__ CF sJbz[DRV ? EZR : 1][DRV ? EZZ : 1];   // particle driver: J_bz at the E_z points
   __shared__ CF sJbr[DRV ? ERR : 1][DRV ? ERZ : 1];   // and J_br at the E_r points
+  __shared__ CF sU[NEQ ? 2 : 1][NEQ ? MR : 1][NEQ ? MZ : 1];   // NEQ: lattice velocity u* of the moments
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
@@ -182,12 +184,18 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       sM[0][bb][aa] = d0;
       sM[1][bb][aa] = m1;
       sM[2][bb][aa] = m2;
-      if (FIELDS) {
+      if (FIELDS || NEQ) {
         const CF m0 = (CF)sN[aa] + d0;
         CF bz, br;
         velocity<CF>(m0, m1, m2, (CF)p.n_floor, bz, br);
-        sJ[0][bb][aa] = m0 * bz;
-        sJ[1][bb][aa] = m0 * br;
+        if (FIELDS) {
+          sJ[0][bb][aa] = m0 * bz;
+          sJ[1][bb][aa] = m0 * br;
+        }
+        if (NEQ) {
+          sU[0][bb][aa] = (CF)p.lam * bz;
+          sU[1][bb][aa] = (CF)p.lam * br;
+        }
       }
     }
   }
@@ -335,6 +343,17 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       f0[q] = ldv(r0[q]) + w * dn;
       f1[q] = ldv(r1[q]);
       f2[q] = ldv(r2[q]);
+      if (NEQ) {
+        // add back the equilibrium of the source site's stored moments (from the LDS halo)
+        const int ga = tx + 1 - XZ(q), gb = ty + 1 - XR(q);
+        const C d0s = (C)sM[0][gb][ga];
+        C e0, e1, e2;
+        eq_dir<C>(q, d0s, (C)sN[ga] + d0s, (C)sM[1][gb][ga], (C)sM[2][gb][ga], (C)sU[0][gb][ga],
+                  (C)sU[1][gb][ga], e0, e1, e2);
+        f0[q] += e0;
+        f1[q] += e1;
+        f2[q] += e2;
+      }
     }
   }
 
@@ -382,6 +401,30 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
     F2 += (-A2 * br + Dc * (C)(sM[2][ty + 2][tx + 1] - sM[2][ty][tx + 1])) * ir;
   }
 
+  // Moments stored for the next step, A* = A + dt F (the zeroth moments of the populations
+  // written below).  NEQ: as rounded to the auxiliary type, with their lattice velocity, so that
+  // the equilibrium subtracted here is the one the next step adds back from the stored values.
+  C mo0 = dA0 + dtc * F0, mo1 = A1 + dtc * F1, mo2 = A2 + dtc * F2;
+  C uoz = C(0), uor = C(0);
+  if (NEQ) {
+    mo0 = (C)(A)mo0;
+    mo1 = (C)(A)mo1;
+    mo2 = (C)(A)mo2;
+    C boz, bor;
+    velocity<C>(nref + mo0, mo1, mo2, (C)p.n_floor, boz, bor);
+    uoz = (C)p.lam * boz;
+    uor = (C)p.lam * bor;
+  }
+  // population 9 k + q of the output site (NEQ: less the equilibrium of the stored moments)
+  auto put = [&](int kq, C v) {
+    if (NEQ) {
+      C e0, e1, e2;
+      eq_dir<C>(kq % 9, mo0, nref + mo0, mo1, mo2, uoz, uor, e0, e1, e2);
+      v -= kq < 9 ? e0 : (kq < 18 ? e1 : e2);
+    }
+    stv(gout + kq * plane + oo32, v);
+  };
+
   // Eqs. (7), (9), (10): relaxation toward the equilibrium (standard D2Q9 coefficients) plus
   // w_q dt F.  The equilibrium of direction q splits into a part even under xi -> -xi,
   // w (A (1 + 4.5 cu^2 - 1.5 u^2)), and an odd part, w A 3 cu (lattice 0 as the deviation).
@@ -405,14 +448,14 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       se1 += e1;
       se2 += e2;
       const C wdt = w * dtc;
-      stv(gout + q * plane + oo32, f0[q] - (f0[q] - e0) * itau + wdt * F0);
-      stv(gout + (9 + q) * plane + oo32, f1[q] - (f1[q] - e1) * itau + wdt * F1);
-      stv(gout + (18 + q) * plane + oo32, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+      put(q, f0[q] - (f0[q] - e0) * itau + wdt * F0);
+      put(9 + q, f1[q] - (f1[q] - e1) * itau + wdt * F1);
+      put(18 + q, f2[q] - (f2[q] - e2) * itau + wdt * F2);
     }
     const C wdt = WQ<C>(0) * dtc;
-    stv(gout + oo32, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itau + wdt * F0);
-    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itau + wdt * F1);
-    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itau + wdt * F2);
+    put(0, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itau + wdt * F0);
+    put(9, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itau + wdt * F1);
+    put(18, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itau + wdt * F2);
   } else if (COLL == 1) {
     // two relaxation times: the even part of f - f_eq relaxes with 1/tau_plus, the odd part
     // (which carries the flux and so sets D) with 1/tau.  The rest population is even.
@@ -432,27 +475,27 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       {
         const C re = (C(0.5) * (f0[q] + f0[b]) - w * (dA0 + A0 * ev)) * itp;
         const C ro = (C(0.5) * (f0[q] - f0[b]) - w * A0 * od) * itau;
-        stv(gout + q * plane + oo32, f0[q] - re - ro + wdt * F0);
-        stv(gout + b * plane + oo32, f0[b] - re + ro + wdt * F0);
+        put(q, f0[q] - re - ro + wdt * F0);
+        put(b, f0[b] - re + ro + wdt * F0);
       }
       {
         const C re = (C(0.5) * (f1[q] + f1[b]) - w * A1 * (C(1) + ev)) * itp;
         const C ro = (C(0.5) * (f1[q] - f1[b]) - w * A1 * od) * itau;
-        stv(gout + (9 + q) * plane + oo32, f1[q] - re - ro + wdt * F1);
-        stv(gout + (9 + b) * plane + oo32, f1[b] - re + ro + wdt * F1);
+        put(9 + q, f1[q] - re - ro + wdt * F1);
+        put(9 + b, f1[b] - re + ro + wdt * F1);
       }
       {
         const C re = (C(0.5) * (f2[q] + f2[b]) - w * A2 * (C(1) + ev)) * itp;
         const C ro = (C(0.5) * (f2[q] - f2[b]) - w * A2 * od) * itau;
-        stv(gout + (18 + q) * plane + oo32, f2[q] - re - ro + wdt * F2);
-        stv(gout + (18 + b) * plane + oo32, f2[b] - re + ro + wdt * F2);
+        put(18 + q, f2[q] - re - ro + wdt * F2);
+        put(18 + b, f2[b] - re + ro + wdt * F2);
       }
     }
     // the rest population (even): its equilibrium is the moment minus the other eight, as for BGK
     const C wdt = WQ<C>(0) * dtc;
-    stv(gout + oo32, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itp + wdt * F0);
-    stv(gout + 9 * plane + oo32, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itp + wdt * F1);
-    stv(gout + 18 * plane + oo32, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itp + wdt * F2);
+    put(0, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itp + wdt * F0);
+    put(9, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itp + wdt * F1);
+    put(18, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itp + wdt * F2);
   } else {
     // regularised: f - f_eq is replaced by its first-order Hermite projection
     // w xi . j_neq / c_s^2, j_neq = sum xi f - A u (the first moment of f_eq is A u), then
@@ -489,19 +532,19 @@ __global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
       se0 += e0;
       se1 += e1;
       se2 += e2;
-      stv(gout + q * plane + oo32, e0 + w * (xz * jz0 + xr * jr0) + wdt * F0);
-      stv(gout + (9 + q) * plane + oo32, e1 + w * (xz * jz1 + xr * jr1) + wdt * F1);
-      stv(gout + (18 + q) * plane + oo32, e2 + w * (xz * jz2 + xr * jr2) + wdt * F2);
+      put(q, e0 + w * (xz * jz0 + xr * jr0) + wdt * F0);
+      put(9 + q, e1 + w * (xz * jz1 + xr * jr1) + wdt * F1);
+      put(18 + q, e2 + w * (xz * jz2 + xr * jr2) + wdt * F2);
     }
     // the rest population (no first-order part): the moment minus the other eight, as for BGK
     const C wdt = WQ<C>(0) * dtc;
-    stv(gout + oo32, (C)((SE)dA0 - se0) + wdt * F0);
-    stv(gout + 9 * plane + oo32, (C)((SE)A1 - se1) + wdt * F1);
-    stv(gout + 18 * plane + oo32, (C)((SE)A2 - se2) + wdt * F2);
+    put(0, (C)((SE)dA0 - se0) + wdt * F0);
+    put(9, (C)((SE)A1 - se1) + wdt * F1);
+    put(18, (C)((SE)A2 - se2) + wdt * F2);
   }
-  stv(Mout + oo, dA0 + dtc * F0);   // density moment stored as the deviation from n_bg
-  stv(Mout + plane + oo, A1 + dtc * F1);
-  stv(Mout + 2 * plane + oo, A2 + dtc * F2);
+  stv(Mout + oo, mo0);   // density moment stored as the deviation from n_bg
+  stv(Mout + plane + oo, mo1);
+  stv(Mout + 2 * plane + oo, mo2);
 
   if (FIELDS) {
     stv(Eout + oo, (A)sEz[ty + 1][tx + 1]);
@@ -541,9 +584,11 @@ __global__ void init_fluid_kernel(Physics p, const double* n_pert, const double*
     const double w = WQ<double>(q);
     const double cu = XZ(q) * uz + XR(q) * ur;
     const double Q = 3.0 * cu + 4.5 * cu * cu - 1.5 * (uz * uz + ur * ur);
-    stv(g + q * p.plane + oo, w * ((n - nb) + n * Q));
-    stv(g + (9 + q) * p.plane + oo, w * a1 * (1.0 + Q));
-    stv(g + (18 + q) * p.plane + oo, w * a2 * (1.0 + Q));
+    // storage 3 keeps the part off the equilibrium, zero here
+    const bool z = neq_storage(ST);
+    stv(g + q * p.plane + oo, z ? 0.0 : w * ((n - nb) + n * Q));
+    stv(g + (9 + q) * p.plane + oo, z ? 0.0 : w * a1 * (1.0 + Q));
+    stv(g + (18 + q) * p.plane + oo, z ? 0.0 : w * a2 * (1.0 + Q));
   }
   stv(M + oo, n - nb);
   stv(M + p.plane + oo, a1);
@@ -615,6 +660,19 @@ __global__ void fields_out_kernel(Physics p, const void* Ev, void* dst, int dst_
   }
 }
 
+// Storage 3: the equilibrium part of population c at a site, from the moments stored there
+// (FP64 arithmetic; lattice 0 as the deviation from w n_bg).
+template <typename A>
+__device__ double neq_equilibrium(const Physics& p, long long s, int i, const A* M, long long oo, int c) {
+  const double d0 = (double)M[oo], a1 = (double)M[p.plane + oo], a2 = (double)M[2 * p.plane + oo];
+  const double m0 = nbg(p, (double)(s + i) * p.h) + d0;
+  double bz, br;
+  velocity<double>(m0, a1, a2, p.n_floor, bz, br);
+  double e0, e1, e2;
+  eq_dir<double>(c % 9, d0, m0, a1, a2, p.lam * bz, p.lam * br, e0, e1, e2);
+  return c < 9 ? e0 : (c < 18 ? e1 : e2);
+}
+
 template <int ST>
 __global__ void state_get_kernel(Physics p, long long s, const void* gv, const void* Mv,
                                  const void* Ev, int c, double* dst) {
@@ -627,6 +685,7 @@ __global__ void state_get_kernel(Physics p, long long s, const void* gv, const v
   double v;
   if (c < 27) {
     v = (double)ldv(((const S*)gv)[c * p.plane + oo]);
+    if (neq_storage(ST)) v += neq_equilibrium<A>(p, s, i, (const A*)Mv, oo, c);
     if (c < 9) v += WQ<double>(c) * nbg(p, (double)(s + i) * p.h);
   } else if (c < 30) {
     v = (double)((const A*)Mv)[(c - 27) * p.plane + oo];
@@ -649,6 +708,8 @@ __global__ void state_set_kernel(Physics p, long long s, void* gv, void* Mv, voi
   double v = src[(long long)j * p.nz + i];
   if (c < 27) {
     if (c < 9) v -= WQ<double>(c) * nbg(p, (double)(s + i) * p.h);
+    // storage 3: the moments are set first (the caller's order), the part off their equilibrium here
+    if (neq_storage(ST)) v -= neq_equilibrium<A>(p, s, i, (const A*)Mv, oo, c);
     stv(((S*)gv) + c * p.plane + oo, v);
   } else if (c < 30) {
     if (c == 27) v -= nbg(p, (double)(s + i) * p.h);
@@ -774,7 +835,8 @@ __global__ __launch_bounds__(RED_THREADS) void bubble_kernel(Physics p, long lon
   do {                                                                               \
     if ((storage) == 0) KERNEL<0><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);    \
     else if ((storage) == 1) KERNEL<1><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__); \
-    else KERNEL<2><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);                   \
+    else if ((storage) == 2) KERNEL<2><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__); \
+    else KERNEL<3><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);                   \
   } while (0)
 
 static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
@@ -784,22 +846,28 @@ static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr);
 // FP64 are bandwidth-bound and measure the same either way, so they keep one variant.
 template <int ST, bool M64, int COLL>
 static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
-  const bool np = ST == 2 && !a.p.per_z && !a.p.per_r;
+  constexpr bool half = ST >= 2;
+  const bool np = half && !a.p.per_z && !a.p.per_r;
   const bool drv = a.p.driver == 1;
   if (a.p.fields_on && drv) step_kernel<ST, true, M64, false, COLL, true, 1><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, ST != 2, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, !half, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (np) step_kernel<ST, false, M64, false, COLL, ST != 2, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (np) step_kernel<ST, false, M64, false, COLL, !half, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else step_kernel<ST, false, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
-// The site-field variant (used by the adjoint, which is BGK only) exists for BGK alone.
+// The site-field variant (used by the adjoint, which is BGK only and does not take storage 3)
+// exists for BGK alone.
 template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
   if (a.p.coll == 1) launch_step_c<ST, M64, 1>(a, grid, st);
   else if (a.p.coll == 2) launch_step_c<ST, M64, 2>(a, grid, st);
-  else if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else launch_step_c<ST, M64, 0>(a, grid, st);
+  else if constexpr (!neq_storage(ST)) {
+    if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+    else launch_step_c<ST, M64, 0>(a, grid, st);
+  } else {
+    launch_step_c<ST, M64, 0>(a, grid, st);
+  }
 }
 
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
@@ -808,8 +876,10 @@ hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {
   if (storage == 0) launch_step_t<0, false>(a, grid, st);
   else if (storage == 1 && a.p.fp64_math) launch_step_t<1, true>(a, grid, st);
   else if (storage == 1) launch_step_t<1, false>(a, grid, st);
-  else if (a.p.fp64_math) launch_step_t<2, true>(a, grid, st);
-  else launch_step_t<2, false>(a, grid, st);
+  else if (storage == 2 && a.p.fp64_math) launch_step_t<2, true>(a, grid, st);
+  else if (storage == 2) launch_step_t<2, false>(a, grid, st);
+  else if (a.p.fp64_math) launch_step_t<3, true>(a, grid, st);
+  else launch_step_t<3, false>(a, grid, st);
   return hipGetLastError();
 }
 

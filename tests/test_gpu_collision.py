@@ -70,13 +70,13 @@ def test_reduced_precision_parity_c2_copy(coll):
     storage, where the arithmetic adds nothing: BGK 9.9e-6, TRT 1.1e-5, regularised 1.7e-5).  So
     the test takes that storage floor from the FP64-arithmetic run, bounds it by 3e-5, and bounds
     the FP32-arithmetic field error by twice it (FP32 arithmetic may add at most the floor again;
-    measured: 1.0-1.45 times).  FP16: 5e-3 as for BGK."""
+    measured: 1.0-1.45 times).  FP16: 5e-3, FP16N: 5e-4 (fields) and 5e-5 (density), as for BGK."""
     cfg64 = wl.config("C2s", **COLLISIONS[coll])
     cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
     S, P = O.run(cfg64, 400)
     ref = {"n": S.M[0].numpy(), "Ez": S.Ez.numpy(), "Er": S.Er.numpy()}
     errs = {}
-    for (storage, m64) in ((wl.F32, 0), (wl.F32, 1), (wl.F16, 0)):
+    for (storage, m64) in ((wl.F32, 0), (wl.F32, 1), (wl.F16, 0), (wl.F16N, 0)):
         print(f"[collision reduced precision] {coll} C2s storage={storage} fp64_math={m64}", flush=True)
         lat = run_gpu(dict(cfg64, storage=storage, fp64_math=m64), 400)
         st, _, _ = lat.state()
@@ -90,6 +90,8 @@ def test_reduced_precision_parity_c2_copy(coll):
         assert floor[q] < 3e-5, errs
         assert f32[q] < 2.0 * floor[q], (q, errs)
     assert max(f16.values()) < 5e-3, errs
+    f16n = errs[(wl.F16N, 0)]
+    assert f16n["n"] < 5e-5 and f16n["Ez"] < 5e-4 and f16n["Er"] < 5e-4, errs
 
 
 @pytest.mark.parametrize("coll", ["trt_quarter", "regularised"])

@@ -180,13 +180,15 @@ def test_fp32_fp16_parity_c2_copy():
     field error by twice the floor (measured 7.9e-6 for E_z, 3.8e-6 for E_r).  The equilibrium's
     zeroth moments are exact, so the FP32-arithmetic error stays at the floor over long runs too
     (C2, 10,000 steps: E_z 5.9e-6).  FP16 storage: 5e-3 (11-bit significand of the stored
-    deviations)."""
+    deviations).  FP16N storage (the part off each site's equilibrium in FP16): fields 5e-4 and
+    density 5e-5 (measured 1.4e-4 / 2.2e-4 / 1.4e-5), and at most a quarter of FP16's field error
+    (measured a tenth)."""
     cfg64 = wl.config("C2s")
     cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
     S, P = O.run(cfg64, 400)
     ref = {"n": S.M[0].numpy(), "Ez": S.Ez.numpy(), "Er": S.Er.numpy()}
     errs = {}
-    for (storage, m64) in ((wl.F32, 0), (wl.F32, 1), (wl.F16, 0), (wl.F16, 1)):
+    for (storage, m64) in ((wl.F32, 0), (wl.F32, 1), (wl.F16, 0), (wl.F16, 1), (wl.F16N, 0), (wl.F16N, 1)):
         cfg = dict(cfg64, storage=storage, fp64_math=m64)
         print(f"[reduced precision] C2s storage={storage} fp64_math={m64} 400 steps", flush=True)
         lat = run_gpu(cfg, 400)
@@ -202,6 +204,43 @@ def test_fp32_fp16_parity_c2_copy():
         assert f32[q] < 2.0 * floor[q], (q, errs)
     for key in ((wl.F16, 0), (wl.F16, 1)):
         assert max(errs[key].values()) < 5e-3, errs
+    for m64 in (0, 1):
+        e16, e16n = errs[(wl.F16, m64)], errs[(wl.F16N, m64)]
+        assert e16n["n"] < 5e-5 and e16n["Ez"] < 5e-4 and e16n["Er"] < 5e-4, errs
+        assert e16n["Ez"] < 0.25 * e16["Ez"] and e16n["Er"] < 0.25 * e16["Er"], errs
+
+
+def test_f16n_state_view_checkpoint_and_adjoint():
+    """FP16N: lbm_get_state / lbm_set_state round-trip (the moments are written before the
+    populations, which are stored relative to them), lbm_save / lbm_load resume bit for bit, an
+    equilibrium initial state stores zero off-equilibrium parts (the state view then holds the
+    equilibrium of the stored moments), and the adjoint rejects the mode."""
+    from paper_2201_05473_amd import LBM_EINVAL, LbmError, Lattice
+    cfg = wl.config(None, nz=100, nr=10, nb=0.2, sigma_z=0.3, sigma_r=0.3, zd0=3.0, moving_window=1,
+                    storage=wl.F16N, noise_amp=1e-3, seed=2)
+    pert = wl.density_perturbation(cfg)
+    lat = Lattice(cfg, pert)
+    st0, _, _ = lat.state()
+    S = O.initial_state(O.Params(dict(cfg, storage=wl.F64)), pert)
+    assert comp_errors(st0, oracle_state(S, O.Params(cfg))).max() < 1e-6
+    lat.step(20)
+    s1, k, sh = lat.state()
+    b = Lattice(cfg)
+    b.set_state(s1, k, sh)
+    s2, _, _ = b.state()
+    assert comp_errors(s2, s1).max() < 1e-12
+    c = Lattice(cfg, pert)
+    c.step(10)
+    d = Lattice(cfg)
+    d.load(c.save())
+    d.step(10)
+    s3, _, _ = d.state()
+    assert np.array_equal(s3, s1)
+    with pytest.raises(LbmError) as ei:
+        Lattice(cfg).adjoint(4, 2)
+    assert ei.value.code == LBM_EINVAL
+    for x in (lat, b, c, d):
+        x.close()
 
 
 def test_full_size_c2_single_steps():
@@ -216,7 +255,7 @@ def test_full_size_c2_single_steps():
         S.k = k0
         S = O.step(S, P)
         ref = oracle_state(S, P)
-        for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6)):
+        for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6), (wl.F16N, 1e-6)):
             print(f"[full size] C2 k0={k0} storage={storage}", flush=True)
             lat = Lattice(dict(cfg, storage=storage))
             st0, _, _ = lat.state()

@@ -9,6 +9,8 @@ test_gpu_parity.py).  Max-norm errors relative to the FP64 maxima of n, E_z and 
   little because the equilibrium's zeroth moments are exact (measured 1e-6..5e-6 with FP32
   arithmetic, 7e-8..6e-6 with FP64 arithmetic).
 * FP16 storage: the bound is 5e-2 (10-bit mantissa); measured 1e-3..2e-2.
+* FP16N storage (the part of each population off its site's equilibrium in FP16, the moments in
+  FP32): the bound is 2e-3; measured 5e-5..6.5e-4.
 """
 import pytest
 import torch
@@ -18,7 +20,7 @@ import workloads as wl
 pytestmark = pytest.mark.gpu
 
 NSTEPS = 5000
-BOUND = {"f32_fp64math": 1e-5, "f32": 1e-5, "f16": 5e-2}
+BOUND = {"f32_fp64math": 1e-5, "f32": 1e-5, "f16": 5e-2, "f16n": 2e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -47,7 +49,8 @@ def test_c3_precision_sweep(tau):
     print(f"[precision] C3 tau={tau}", flush=True)
     m64, f64, d64 = run(wl.config("C3", storage=wl.F64, tau=tau))
     assert d64["nonfinite"] == 0
-    for name, storage, m in (("f32_fp64math", wl.F32, 1), ("f32", wl.F32, 0), ("f16", wl.F16, 0)):
+    for name, storage, m in (("f32_fp64math", wl.F32, 1), ("f32", wl.F32, 0), ("f16", wl.F16, 0),
+                             ("f16n", wl.F16N, 0)):
         mo, fo, d = run(wl.config("C3", storage=storage, fp64_math=m, tau=tau))
         assert d["nonfinite"] == 0, name
         errs = {"n": rel(mo[0], m64[0]), "Ez": rel(fo[0], f64[0]), "Er": rel(fo[1], f64[1])}

@@ -27,7 +27,7 @@ import copy
 
 import numpy as np
 
-F64, F32, F16 = 0, 1, 2
+F64, F32, F16, F16N = 0, 1, 2, 3   # F16N: FP16 populations stored off their site's equilibrium
 BGK, TRT, REG = 0, 1, 2
 RIGID, PARTICLES = 0, 1
 
