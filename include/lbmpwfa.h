@@ -185,7 +185,7 @@ int lbm_get_state(lbm_ctx* ctx, double* dst, int64_t* step, int64_t* shifts);
 int lbm_set_state(lbm_ctx* ctx, const double* src, int64_t step, int64_t shifts);
 
 /* Checkpoint in the native storage format, for bit-exact resume:
- * a 64-byte header (magic, storage, nz, nr, step, shift count) followed by the active
+ * a 64-byte header (magic, storage, nz, nr, row pitch, step, shift count, plane stride) followed by the active
  * population, moment and field buffers as stored.  lbm_checkpoint_bytes gives its size.
  * dst/src may be host or device memory (flag); both calls synchronise the stream.  lbm_load
  * returns LBM_EINVAL if the checkpoint was written for another grid or storage precision.  The

@@ -134,7 +134,8 @@ def test_revolve_workspace_scales_with_snapshots(lib):
     cfg = wl.config("C4")
     b1 = lbm_adjoint_revolve_workspace_bytes(cfg, 1)
     b5 = lbm_adjoint_revolve_workspace_bytes(cfg, 5)
-    state = 1024 * 256 * (27 * 4 + 6 * 4)
+    plane = 1024 * 256 + 64   # pitched rows, plus the 256-byte plane pad of FP32 storage
+    state = plane * (27 * 4 + 6 * 4)
     assert b5 - b1 == 4 * state
     with pytest.raises(Exception):
         lbm_adjoint_revolve_workspace_bytes(cfg, 0)
