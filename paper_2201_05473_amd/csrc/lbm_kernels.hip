@@ -27,8 +27,12 @@ namespace lbm {
 // PER = false: the grid is known not to be periodic, and the wrap code is compiled out.
 // DRV = 1: the driver current J_b comes from the particle bunch's deposit (a.jb_in, z and r
 // components) in place of the rigid driver's closed form.
+// FP16 storage (2, 3) with FP32 arithmetic is instruction-bound: 7 blocks per CU (7 waves per
+// SIMD, at most 72 VGPRs, 2 to 7 of them spilled) measured 3 % (FP16) and 8 % (FP16N) faster on
+// 2048 x 512 than the 6 that its 78 / 82 VGPRs allow.  FP32 and FP64 gain nothing from it, and
+// FP64 arithmetic needs twice the registers.
 template <int ST, bool FIELDS, bool M64, bool SITE, int COLL, bool PER, int DRV>
-__global__ __launch_bounds__(NTHREADS) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kernel(StepArgs a) {
   using S = typename Mode<ST, M64>::S;
   using C = typename Mode<ST, M64>::C;
   using A = typename Mode<ST, M64>::A;
