@@ -36,11 +36,11 @@ struct Stencil {
   double fz, fr;  // weight of the upper node in z and in r
 };
 
-// Nodes z = (s + i + zoff) dz and rows (j + 1/2) dr (edge = false) or (j + 1) dr (edge = true).
-__device__ __forceinline__ Stencil stencil(const Physics& p, double z, double r, long long s, double zoff,
-                                           bool edge) {
-  const double u = z / p.h - (double)s - zoff;
-  const double v = r / p.h - (edge ? 1.0 : 0.5);
+// Nodes z = (s + i + zoff) dz and rows (j + 1/2) dr (edge = false) or (j + 1) dr (edge = true);
+// ih = 1 / dz, computed once per thread by the caller.
+__device__ __forceinline__ Stencil stencil(double ih, double z, double r, long long s, double zoff, bool edge) {
+  const double u = z * ih - (double)s - zoff;
+  const double v = r * ih - (edge ? 1.0 : 0.5);
   const double fi = floor(u), fj = floor(v);
   Stencil st;
   st.i0 = (int)fi;
@@ -62,19 +62,17 @@ __device__ __forceinline__ void atomic_add(double* a, double v) { unsafeAtomicAd
 template <typename T>
 __device__ __forceinline__ void deposit(const Physics& p, const Stencil& st, bool edge, double val, T* F) {
 #pragma unroll
-  for (int di = 0; di < 2; ++di) {
-    const double wz = di ? st.fz : 1.0 - st.fz;
-#pragma unroll
-    for (int dj = 0; dj < 2; ++dj) {
-      const double wr = dj ? st.fr : 1.0 - st.fr;
-      int j = st.j0 + dj;
-      if (j < 0) {
-        if (edge) continue;   // the axis node of E_r / J_r carries nothing
-        j = 0;                // the row below the axis folds onto row 0
-      }
-      const double rn = ((double)j + (edge ? 1.0 : 0.5)) * p.h;
-      atomic_add(F + (long long)j * p.pitch + (st.i0 + di), val * wz * wr / (TWO_PI * rn * p.h * p.h));
+  for (int dj = 0; dj < 2; ++dj) {
+    int j = st.j0 + dj;
+    if (j < 0) {
+      if (edge) continue;   // the axis node of E_r / J_r carries nothing
+      j = 0;                // the row below the axis folds onto row 0
     }
+    const double rn = ((double)j + (edge ? 1.0 : 0.5)) * p.h;
+    const double vr = val * (dj ? st.fr : 1.0 - st.fr) / (TWO_PI * rn * p.h * p.h);
+#pragma unroll
+    for (int di = 0; di < 2; ++di)
+      atomic_add(F + (long long)j * p.pitch + (st.i0 + di), vr * (di ? st.fz : 1.0 - st.fz));
   }
 }
 
@@ -116,19 +114,16 @@ template <typename T>
 __device__ __forceinline__ void deposit_tile(const Physics& p, const Stencil& st, bool edge, double val, T* tile,
                                              int c0) {
 #pragma unroll
-  for (int di = 0; di < 2; ++di) {
-    const double wz = di ? st.fz : 1.0 - st.fz;
-#pragma unroll
-    for (int dj = 0; dj < 2; ++dj) {
-      const double wr = dj ? st.fr : 1.0 - st.fr;
-      int j = st.j0 + dj;
-      if (j < 0) {
-        if (edge) continue;
-        j = 0;
-      }
-      const double rn = ((double)j + (edge ? 1.0 : 0.5)) * p.h;
-      lds_add(tile + j * TW + (st.i0 + di - c0), val * wz * wr / (TWO_PI * rn * p.h * p.h));
+  for (int dj = 0; dj < 2; ++dj) {
+    int j = st.j0 + dj;
+    if (j < 0) {
+      if (edge) continue;
+      j = 0;
     }
+    const double rn = ((double)j + (edge ? 1.0 : 0.5)) * p.h;
+    const double vr = val * (dj ? st.fr : 1.0 - st.fr) / (TWO_PI * rn * p.h * p.h);
+#pragma unroll
+    for (int di = 0; di < 2; ++di) lds_add(tile + j * TW + (st.i0 + di - c0), vr * (di ? st.fz : 1.0 - st.fz));
   }
 }
 
@@ -138,24 +133,27 @@ __device__ __forceinline__ void deposit_tile(const Physics& p, const Stencil& st
 template <typename A>
 __device__ __forceinline__ void boris_push(const Physics& p, long long s, int shift, const A* Ein, const A* Eout,
                                            double x, double y, double z, double& px, double& py, double& pz) {
+  const double ih = 1.0 / p.h;
   const double r = sqrt(x * x + y * y);
-  const Stencil sc = stencil(p, z, r, s, 0.5, false);   // E_z points
-  const Stencil se = stencil(p, z, r, s, 0.0, true);    // E_r points
-  const Stencil sb = stencil(p, z, r, s, 0.5, true);    // B_theta points
+  const Stencil sc = stencil(ih, z, r, s, 0.5, false);   // E_z points
+  const Stencil se = stencil(ih, z, r, s, 0.0, true);    // E_r points
+  const Stencil sb = stencil(ih, z, r, s, 0.5, true);    // B_theta points
   const double ez = gather(p, sc, false, Eout, shift);
   const double er = gather(p, se, true, Eout + p.plane, shift);
   const double bt = 0.5 * (gather(p, sb, true, Ein + 2 * p.plane, 0) + gather(p, sb, true, Eout + 2 * p.plane, shift));
-  const double cx = r > 0.0 ? x / r : 0.0, cy = r > 0.0 ? y / r : 0.0;
+  const double ir = r > 0.0 ? 1.0 / r : 0.0;
+  const double cx = x * ir, cy = y * ir;
   const double Ex = er * cx, Ey = er * cy, Ez = ez;
   const double Bx = -bt * cy, By = bt * cx, Bz = 0.0;
   // half kick, rotation, half kick
   const double dt = p.dt;
   const double mx = px - 0.5 * dt * Ex, my = py - 0.5 * dt * Ey, mz = pz - 0.5 * dt * Ez;
-  const double g = sqrt(1.0 + (mx * mx + my * my + mz * mz));
-  const double tx = -0.5 * dt * Bx / g, ty = -0.5 * dt * By / g, tz = -0.5 * dt * Bz / g;
+  const double h2g = -0.5 * dt / sqrt(1.0 + (mx * mx + my * my + mz * mz));
+  const double tx = h2g * Bx, ty = h2g * By, tz = h2g * Bz;
   const double ux = mx + (my * tz - mz * ty), uy = my + (mz * tx - mx * tz), uz = mz + (mx * ty - my * tx);
   const double t2 = 1.0 + (tx * tx + ty * ty + tz * tz);
-  const double sx = 2.0 * tx / t2, sy = 2.0 * ty / t2, sz = 2.0 * tz / t2;
+  const double i2 = 2.0 / t2;
+  const double sx = tx * i2, sy = ty * i2, sz = tz * i2;
   px = mx + (uy * sz - uz * sy) - 0.5 * dt * Ex;
   py = my + (uz * sx - ux * sz) - 0.5 * dt * Ey;
   pz = mz + (ux * sy - uy * sx) - 0.5 * dt * Ez;
@@ -169,6 +167,7 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
                                                         const void* Eoutv, double* b, int n, long long cap,
                                                         void* jbv) {
   using A = typename Mode<ST, false>::A;
+  const double ih = 1.0 / p.h;
   __shared__ A tile[2][TRW * TW];
   __shared__ int cmin, cmax, rmax;
   if (threadIdx.x == 0) {
@@ -201,15 +200,15 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
       b[5 * cap + q] = pz;
     }
     const long long sm = PUSH ? s + shift : s;   // frame of the move
-    const double g = sqrt(1.0 + (px * px + py * py + pz * pz));
-    const double bx = px / g, by = py / g, bz = pz / g;
+    const double ig = 1.0 / sqrt(1.0 + (px * px + py * py + pz * pz));
+    const double bx = px * ig, by = py * ig, bz = pz * ig;
     const double xn = x + p.dt * bx, yn = y + p.dt * by, zn = z + p.dt * bz;
     const double xm = 0.5 * (x + xn), ym = 0.5 * (y + yn), zm = 0.5 * (z + zn);
     const double rm = sqrt(xm * xm + ym * ym), rn = sqrt(xn * xn + yn * yn);
-    jz[u] = stencil(p, zm, rm, sm, 0.5, false);
-    jr[u] = stencil(p, zm, rm, sm, 0.0, true);
-    const bool ok = inside(p, jz[u]) && inside(p, jr[u]) && inside(p, stencil(p, zn, rn, sm, 0.5, false)) &&
-                    inside(p, stencil(p, zn, rn, sm, 0.0, true)) && inside(p, stencil(p, zn, rn, sm, 0.5, true));
+    jz[u] = stencil(ih, zm, rm, sm, 0.5, false);
+    jr[u] = stencil(ih, zm, rm, sm, 0.0, true);
+    const bool ok = inside(p, jz[u]) && inside(p, jr[u]) && inside(p, stencil(ih, zn, rn, sm, 0.5, false)) &&
+                    inside(p, stencil(ih, zn, rn, sm, 0.0, true)) && inside(p, stencil(ih, zn, rn, sm, 0.5, true));
     if (!ok) {
       b[6 * cap + q] = 0.0;   // lost
       continue;
@@ -286,7 +285,8 @@ __global__ __launch_bounds__(BT) void bunch_density_kernel(Physics p, long long 
   const double x = b[q] + t_ahead * (px / g), y = b[cap + q] + t_ahead * (py / g);
   const double z = b[2 * cap + q] + t_ahead * (pz / g);
   const double r = sqrt(x * x + y * y);
-  const Stencil st = stencil(p, z, r, s, zoff, false);
+  const double ih = 1.0 / p.h;
+  const Stencil st = stencil(ih, z, r, s, zoff, false);
   if (!inside(p, st)) return;
   deposit(p, st, false, b[6 * cap + q], dens);
 }
