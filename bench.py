@@ -21,8 +21,9 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & HBM GB/s FP32 vs FP64 at stated Ez error; adjoint/forward time ratio"
 PEAK_HBM_GBS = 8000.0
+# the step kernel and the host code that sets its memory layout (pitch, plane stride)
 KERNEL_SOURCES = ("paper_2201_05473_amd/csrc/lbm_kernels.hip", "paper_2201_05473_amd/csrc/lbm_device.h",
-                  "paper_2201_05473_amd/csrc/lbm_internal.h")
+                  "paper_2201_05473_amd/csrc/lbm_internal.h", "paper_2201_05473_amd/csrc/lbm_capi.cpp")
 
 
 def bytes_per_site(storage: int) -> int:
