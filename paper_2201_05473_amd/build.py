@@ -30,5 +30,25 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+C_CLIENT = os.path.join(LIB_DIR, "lbm_c_run")
+
+
+def build_c_client() -> str:
+    """Compile the plain-C client of the ABI (tests/c_api/lbm_c_run.c, host code only, linked to
+    the library next to it); returns its path."""
+    root = os.path.dirname(HERE)
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = [os.environ.get("CC", "gcc"), "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I" + os.path.join(rocm, "include"), "-I" + os.path.join(root, "include"),
+           "-o", C_CLIENT, os.path.join(root, "tests", "c_api", "lbm_c_run.c"),
+           "-L" + LIB_DIR, "-llbmpwfa", "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise subprocess.CalledProcessError(res.returncode, cmd, res.stdout, res.stderr)
+    return C_CLIENT
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_client())
