@@ -54,16 +54,22 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_F16N = 3 };
 
 /* Collision operator of the three lattices.  The paper uses BGK (Eq. (7)) and notes (Sec. IV)
  * that BGK is the simplest choice and that other collision operators may stabilise the
- * non-linear regime.  Two are offered, each relaxing toward the equilibrium of Eq. (9), with the
- * source of Eq. (10) added unchanged:
+ * non-linear regime.  Three are offered, each relaxing toward the equilibrium of Eq. (9), with
+ * the source of Eq. (10) added unchanged:
  *   LBM_BGK  Eq. (7): one relaxation time tau for every population.
  *   LBM_TRT  two relaxation times: the part of f - f_eq that is even under xi -> -xi (pairs of
  *            opposite directions) relaxes with tau_plus, the odd part with tau.
  *   LBM_REG  regularised BGK: before relaxing with tau, f - f_eq is replaced by its projection
  *            on the first-order Hermite polynomials, w_i xi_i . j_neq / c_s^2 with
  *            j_neq = sum_i xi_i (f_i - f_eq_i); every non-equilibrium moment above the first is
- *            dropped. */
-enum { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2 };
+ *            dropped.
+ *   LBM_MRT  multiple relaxation times: f - f_eq is expanded in the nine orthogonal moments of
+ *            D2Q9 (the polynomials 1, 3|xi|^2 - 4, (9|xi|^4 - 21|xi|^2 + 8)/2, xi_z,
+ *            (3|xi|^2 - 5) xi_z, xi_r, (3|xi|^2 - 5) xi_r, xi_z^2 - xi_r^2, xi_z xi_r of the
+ *            velocities) and each relaxes with its own rate: the fluxes xi_z, xi_r with 1/tau,
+ *            the energy, energy square, heat fluxes and stresses with mrt_se, mrt_seps,
+ *            mrt_sq, mrt_spi. */
+enum { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2, LBM_MRT = 3 };
 
 /* Driver of the wake.  The paper drives the plasma with the electron bunch of its hybrid code:
  * macroparticles moved by the Lorentz force (Sec. II, Eq. (1)) whose current, projected on the
@@ -105,15 +111,20 @@ enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
  *                 values (LBM_EUNSTABLE); 0: no checks
  *   fp64_math     1: FP64 arithmetic in the step for FP32 / FP16 storage (storage unchanged);
  *                 0: arithmetic in FP32.  Ignored for LBM_F64 (always FP64).
- *   collision     LBM_BGK, LBM_TRT or LBM_REG (below).  All three conserve A + dt F and relax
- *                 the first moment with 1/tau, so D of Eq. (12) is the same for all three
+ *   collision     LBM_BGK, LBM_TRT, LBM_REG or LBM_MRT (above).  All four conserve A + dt F and
+ *                 relax the first moment with 1/tau, so D of Eq. (12) is the same for all four
  *   trt_magic     LBM_TRT only: Lambda = (tau_plus - 1/2)(tau - 1/2) > 0, which fixes the
  *                 relaxation time tau_plus of the symmetric part; Lambda = (tau - 1/2)^2 is BGK.
  *                 Ignored otherwise.
  *   driver        LBM_DRIVER_RIGID (nb, sigma_z, sigma_r, zd0 above) or LBM_DRIVER_PARTICLES
  *                 (a macroparticle bunch set with lbm_set_bunch; nb .. zd0 are then unused)
  *   max_particles LBM_DRIVER_PARTICLES: capacity of the bunch, in [0, 2^31); the workspace holds
- *                 7 doubles per particle.  Ignored otherwise. */
+ *                 7 doubles per particle.  Ignored otherwise.
+ *   mrt_se, mrt_seps, mrt_sq, mrt_spi
+ *                 LBM_MRT only: relaxation rates (1 / relaxation time) of the energy, energy
+ *                 square, heat-flux and stress moments, each in (0, 2); all four 1/tau is BGK,
+ *                 mrt_se = mrt_seps = mrt_spi = 1/tau_plus with mrt_sq = 1/tau is TRT.  Ignored
+ *                 otherwise. */
 typedef struct {
   int32_t nz, nr;
   double dz, dr, c_dt_over_dz, tau;
@@ -130,6 +141,7 @@ typedef struct {
   double trt_magic;
   int32_t driver;
   int64_t max_particles;
+  double mrt_se, mrt_seps, mrt_sq, mrt_spi;
 } lbm_config;
 
 /* FP64 diagnostics of the current state (all sums over the window):

@@ -62,8 +62,16 @@ Readings of the paper (where it is silent, garbled or inconsistent):
              Lambda (Lambda = (tau - 1/2)^2 gives BGK back);
         REG  regularised BGK for an advected scalar: f - f_eq is replaced by its first-order
              Hermite projection w_i xi_i . j_neq / c_s^2, j_neq = sum_i xi_i (f_i - f_eq_i),
-             before relaxing with tau (every non-equilibrium moment above the first is dropped).
-      Both relax the first moment exactly as BGK does, so D of Eq. (12) is unchanged.
+             before relaxing with tau (every non-equilibrium moment above the first is dropped);
+        MRT  multiple relaxation times: f - f_eq is expanded in the nine moments of D2Q9 given by
+             the polynomials 1, 3|xi|^2 - 4, (9|xi|^4 - 21|xi|^2 + 8)/2, xi_z, (3|xi|^2 - 5) xi_z,
+             xi_r, (3|xi|^2 - 5) xi_r, xi_z^2 - xi_r^2, xi_z xi_r (density, energy, energy
+             square, flux and heat flux in z and r, two stresses; orthogonal on the nine
+             velocities), and each moment relaxes with its own rate: the flux moments with 1/tau,
+             energy, energy square, heat flux and stresses with given rates s_e, s_eps, s_q,
+             s_pi in (0, 2) (the density moment of f - f_eq is zero).  s_e = s_eps = s_pi =
+             1/tau_plus with s_q = 1/tau is TRT; all four equal to 1/tau is BGK.
+      All three relax the first moment exactly as BGK does, so D of Eq. (12) is unchanged.
   R30 Particle driver (Sec. II: the bunch as macroparticles obeying Eq. (1), coupled through the
       currents projected on the grid).  Macroparticles in 3D Cartesian (x, y, z, p_x, p_y, p_z)
       with weights w (electrons, in units of n_0 / k_p^3).  State after k steps: positions at
@@ -112,7 +120,25 @@ W = (4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
 # Index of the opposite direction, xi_{OPP[q]} = -xi_q.
 OPP = tuple(XI.index((-xz, -xr)) for (xz, xr) in XI)
 # Collision operators (R29).
-BGK, TRT, REG = 0, 1, 2
+BGK, TRT, REG, MRT = 0, 1, 2, 3
+
+
+def mrt_basis():
+    """[9][9] rows of the D2Q9 moment basis of R29 (MRT), each row a polynomial in xi evaluated on
+    the nine velocities: density, energy, energy square, flux z, heat flux z, flux r, heat flux r,
+    normal stress, shear stress."""
+    rows = []
+    for poly in (lambda z, r, q2: 1.0,
+                 lambda z, r, q2: 3.0 * q2 - 4.0,
+                 lambda z, r, q2: (9.0 * q2 * q2 - 21.0 * q2 + 8.0) / 2.0,
+                 lambda z, r, q2: z,
+                 lambda z, r, q2: (3.0 * q2 - 5.0) * z,
+                 lambda z, r, q2: r,
+                 lambda z, r, q2: (3.0 * q2 - 5.0) * r,
+                 lambda z, r, q2: z * z - r * r,
+                 lambda z, r, q2: z * r):
+        rows.append([poly(z, r, z * z + r * r) for (z, r) in XI])
+    return torch.tensor(rows, dtype=DT)
 # Mirror parity of (n, n p_z, n p_r) across the axis r = 0 (R11).
 PARITY = (1.0, 1.0, -1.0)
 
@@ -141,8 +167,14 @@ class Params:
         # Eq. (12) in lattice units, converted to normalised units: D = (tau - 1/2)/3 dz^2/dt.
         self.D = (self.tau - 0.5) / 3.0 * self.h * self.h / self.dt
         self.collision = int(cfg.get("collision", BGK))
-        if self.collision not in (BGK, TRT, REG):
+        if self.collision not in (BGK, TRT, REG, MRT):
             raise ValueError("unknown collision operator")
+        # MRT rates of the nine moments (R29): density (any; its non-equilibrium part is zero),
+        # energy, energy square, flux z, heat flux z, flux r, heat flux r, two stresses
+        s_e, s_eps, s_q, s_pi = (float(cfg.get(k, 1.0)) for k in ("mrt_se", "mrt_seps", "mrt_sq", "mrt_spi"))
+        if self.collision == MRT and not all(0.0 < v < 2.0 for v in (s_e, s_eps, s_q, s_pi)):
+            raise ValueError("MRT rates must lie in (0, 2)")
+        self.mrt_rates = (0.0, s_e, s_eps, 1.0 / self.tau, s_q, 1.0 / self.tau, s_q, s_pi, s_pi)
         self.tau_plus = self.tau
         if self.collision == TRT:
             magic = float(cfg.get("trt_magic", 0.25))
@@ -373,6 +405,14 @@ def collide(f, feq, P: Params):
         even = 0.5 * (neq + mirrored)
         odd = 0.5 * (neq - mirrored)
         return f - even / P.tau_plus - odd / P.tau
+    if P.collision == MRT:
+        # expand neq in the orthogonal basis, relax each moment with its rate, transform back
+        B = mrt_basis()                                        # [moment][q]
+        norm2 = (B * B).sum(dim=1)
+        shape = (9,) + (1,) * (f.dim() - 1)
+        moments = torch.tensordot(B, neq, dims=([1], [0]))     # [moment][...]
+        rates = torch.tensor(P.mrt_rates, dtype=DT).reshape(shape)
+        return f - torch.tensordot(B.t(), rates * moments / norm2.reshape(shape), dims=([1], [0]))
     # REG: keep only the first-order Hermite part of neq, w_i xi_i . j_neq / c_s^2 (c_s^2 = 1/3)
     shape = (9,) + (1,) * (f.dim() - 1)
     xz = torch.tensor([x[0] for x in XI], dtype=DT).reshape(shape)

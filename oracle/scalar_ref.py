@@ -22,10 +22,12 @@ class Grid:
         self.dt = self.lam * self.h
         self.tau = float(cfg["tau"])
         self.D = (self.tau - 0.5) / 3 * self.h ** 2 / self.dt
-        self.coll = int(cfg.get("collision", 0))          # 0 BGK, 1 TRT, 2 regularised (R29)
+        self.coll = int(cfg.get("collision", 0))          # 0 BGK, 1 TRT, 2 regularised, 3 MRT (R29)
         self.tau_p = self.tau
         if self.coll == 1:
             self.tau_p = 0.5 + float(cfg.get("trt_magic", 0.25)) / (self.tau - 0.5)
+        s_e, s_eps, s_q, s_pi = (float(cfg.get(k, 1.0)) for k in ("mrt_se", "mrt_seps", "mrt_sq", "mrt_spi"))
+        self.mrt = (0.0, s_e, s_eps, 1.0 / self.tau, s_q, 1.0 / self.tau, s_q, s_pi, s_pi)
         self.window = bool(cfg.get("moving_window", 0))
         per = int(cfg.get("periodic", 0))
         self.pz, self.pr = bool(per & 1), bool(per & 2)
@@ -53,6 +55,13 @@ class Grid:
     def driver(self, z, r, t):
         return self.nb * math.exp(-(z - self.zd0 - t) ** 2 / (2 * self.sz ** 2)
                                   - r ** 2 / (2 * self.sr ** 2))
+
+
+def moment_poly(m, z, r):
+    """Value of the m-th D2Q9 moment polynomial of R29 (MRT) at the velocity (z, r)."""
+    q2 = z * z + r * r
+    return (1.0, 3 * q2 - 4, (9 * q2 * q2 - 21 * q2 + 8) / 2, z, (3 * q2 - 5) * z, r, (3 * q2 - 5) * r,
+            z * z - r * r, z * r)[m]
 
 
 def feq(q, A, uz, ur):
@@ -190,6 +199,12 @@ def step(G, st):
                         even = 0.5 * (neq[q] + neq[back])
                         odd = 0.5 * (neq[q] - neq[back])
                         post = f[kk][q] - even / G.tau_p - odd / G.tau
+                    elif G.coll == 3:
+                        post = f[kk][q]
+                        for m in range(9):
+                            row = [moment_poly(m, XI[p][0], XI[p][1]) for p in range(9)]
+                            nm = sum(row[p] * neq[p] for p in range(9))
+                            post -= G.mrt[m] * nm / sum(v * v for v in row) * row[q]
                     else:
                         post = fe[q] + (1 - 1 / G.tau) * 3 * W[q] * (XI[q][0] * jz + XI[q][1] * jr)
                     gn[kk][q][j][i] = post + W[q] * dt * F[kk]

@@ -41,6 +41,7 @@ class LbmConfig(ctypes.Structure):
         ("trt_magic", c_double),
         ("driver", c_int32),
         ("max_particles", c_int64),
+        ("mrt_se", c_double), ("mrt_seps", c_double), ("mrt_sq", c_double), ("mrt_spi", c_double),
     ]
 
 

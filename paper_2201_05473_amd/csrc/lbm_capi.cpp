@@ -80,8 +80,11 @@ int validate(const lbm_config* c, Physics* p) {
   if (!(c->n_floor >= 0.0)) return fail(LBM_EINVAL, "n_floor must be >= 0");
   if (c->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
   if (c->fp64_math != 0 && c->fp64_math != 1) return fail(LBM_EINVAL, "fp64_math must be 0 or 1");
-  if (c->collision != LBM_BGK && c->collision != LBM_TRT && c->collision != LBM_REG)
+  if (c->collision != LBM_BGK && c->collision != LBM_TRT && c->collision != LBM_REG && c->collision != LBM_MRT)
     return fail(LBM_EINVAL, "unknown collision operator %d", c->collision);
+  if (c->collision == LBM_MRT)
+    for (double v : {c->mrt_se, c->mrt_seps, c->mrt_sq, c->mrt_spi})
+      if (!(v > 0.0 && v < 2.0)) return fail(LBM_EINVAL, "MRT rates must lie in (0, 2) (got %g)", v);
   if (c->collision == LBM_TRT && !(c->trt_magic > 0.0 && std::isfinite(c->trt_magic)))
     return fail(LBM_EINVAL, "trt_magic must be positive and finite (got %g)", c->trt_magic);
   if (c->driver != LBM_DRIVER_RIGID && c->driver != LBM_DRIVER_PARTICLES)
@@ -124,6 +127,10 @@ int validate(const lbm_config* c, Physics* p) {
     q.tau_plus = c->collision == LBM_TRT ? 0.5 + c->trt_magic / (c->tau - 0.5) : c->tau;
     q.driver = c->driver;
     q.cap = c->driver == LBM_DRIVER_PARTICLES ? (long long)c->max_particles : 0;
+    q.mrt_se = c->mrt_se;
+    q.mrt_seps = c->mrt_seps;
+    q.mrt_sq = c->mrt_sq;
+    q.mrt_spi = c->mrt_spi;
   }
   return LBM_OK;
 }

@@ -57,6 +57,21 @@ template <typename C> __host__ __device__ constexpr C WQ(int q) {
   return q == 0 ? C(4) / C(9) : (q < 5 ? C(1) / C(9) : C(1) / C(36));
 }
 
+// Moment basis of the multiple-relaxation-time operator: value at velocity q of the m-th of the
+// nine D2Q9 moment polynomials 1, 3|xi|^2 - 4, (9|xi|^4 - 21|xi|^2 + 8)/2, xi_z, (3|xi|^2 - 5) xi_z,
+// xi_r, (3|xi|^2 - 5) xi_r, xi_z^2 - xi_r^2, xi_z xi_r (density, energy, energy square, flux and
+// heat flux in z and r, two stresses; orthogonal on the nine velocities), and its squared norm.
+__host__ __device__ constexpr int MB(int m, int q) {
+  const int z = XZ(q), r = XR(q), q2 = z * z + r * r;
+  return m == 0 ? 1 : m == 1 ? 3 * q2 - 4 : m == 2 ? (9 * q2 * q2 - 21 * q2 + 8) / 2 : m == 3 ? z
+       : m == 4 ? (3 * q2 - 5) * z : m == 5 ? r : m == 6 ? (3 * q2 - 5) * r : m == 7 ? z * z - r * r : z * r;
+}
+__host__ __device__ constexpr int MB_NORM2(int m) {
+  int sum = 0;
+  for (int q = 0; q < 9; ++q) sum += MB(m, q) * MB(m, q);
+  return sum;
+}
+
 // Equilibrium of direction q (Eq. (9), standard D2Q9 coefficients) for the three lattices at
 // moments with density deviation d0 from n_bg (density m0 = n_bg + d0), momenta a1, a2 and lattice
 // velocity (uz, ur); lattice 0 as the deviation from w_q n_bg.

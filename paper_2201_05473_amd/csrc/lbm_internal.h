@@ -26,10 +26,11 @@ struct Physics {
   double nb, sigma_z, sigma_r, zd0;
   int window, m, per_z, per_r, fields_on, cyl_on;
   int fp64_math;            // FP64 arithmetic for FP32 / FP16 storage
-  int coll;                 // collision operator: 0 BGK, 1 TRT, 2 regularised
+  int coll;                 // collision operator: 0 BGK, 1 TRT, 2 regularised, 3 MRT
   double tau_plus;          // TRT: relaxation time of the even part (tau otherwise)
   int driver;               // 0 rigid bi-Gaussian, 1 macroparticles
   long long cap;            // macroparticle capacity (driver 1)
+  double mrt_se, mrt_seps, mrt_sq, mrt_spi;   // MRT rates of energy, energy square, heat flux, stress
 };
 
 // One launch of the fused step: physics + time counters + buffers.

@@ -500,6 +500,51 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     put(0, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itp + wdt * F0);
     put(9, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itp + wdt * F1);
     put(18, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itp + wdt * F2);
+  } else if (COLL == 3) {
+    // multiple relaxation times: f - f_eq expanded in the orthogonal moments MB, each relaxed with
+    // its rate (the fluxes with 1/tau, so D is that of BGK; the density moment of f - f_eq is
+    // zero), then transformed back.  The equilibrium is BGK's, its rest population the moment
+    // minus the other eight.
+    const C rate[9] = {C(0), (C)p.mrt_se, (C)p.mrt_seps, itau, (C)p.mrt_sq, itau, (C)p.mrt_sq, (C)p.mrt_spi,
+                       (C)p.mrt_spi};
+    C Qq[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
+      Qq[q] = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
+    }
+    // lattice k: f its populations, mom its moment (for lattice 0 the deviation dA0, whose
+    // equilibrium is w (dA0 + A0 Q)), F its source
+    auto relax = [&](int k, const C (&f)[9], C mom, C F) {
+      C e[9];
+      SE sum = 0;
+#pragma unroll
+      for (int q = 1; q < 9; ++q) {
+        e[q] = k == 0 ? WQ<C>(q) * (dA0 + A0 * Qq[q]) : WQ<C>(q) * mom * (C(1) + Qq[q]);
+        sum += e[q];
+      }
+      e[0] = (C)((SE)mom - sum);
+      C c[9];
+#pragma unroll
+      for (int m = 1; m < 9; ++m) {
+        C nm = C(0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+          if (MB(m, q) != 0) nm += (C)MB(m, q) * (f[q] - e[q]);
+        c[m] = rate[m] * nm / (C)MB_NORM2(m);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        C v = f[q];
+#pragma unroll
+        for (int m = 1; m < 9; ++m)
+          if (MB(m, q) != 0) v -= (C)MB(m, q) * c[m];
+        put(9 * k + q, v + WQ<C>(q) * dtc * F);
+      }
+    };
+    relax(0, f0, dA0, F0);
+    relax(1, f1, A1, F1);
+    relax(2, f2, A2, F2);
   } else {
     // regularised: f - f_eq is replaced by its first-order Hermite projection
     // w xi . j_neq / c_s^2, j_neq = sum xi f - A u (the first moment of f_eq is A u), then
@@ -866,6 +911,7 @@ template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
   if (a.p.coll == 1) launch_step_c<ST, M64, 1>(a, grid, st);
   else if (a.p.coll == 2) launch_step_c<ST, M64, 2>(a, grid, st);
+  else if (a.p.coll == 3) launch_step_c<ST, M64, 3>(a, grid, st);
   else if constexpr (!neq_storage(ST)) {
     if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
     else launch_step_c<ST, M64, 0>(a, grid, st);

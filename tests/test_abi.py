@@ -66,8 +66,9 @@ def test_struct_layout_matches_c(lib, tmp_path):
     dict(nz=2), dict(nr=2), dict(ramp_kind=1, ramp_len=0.0), dict(ramp_kind=3),
     dict(periodic=1, moving_window=1), dict(periodic=2), dict(moving_window=1, c_dt_over_dz=0.3),
     dict(storage=4), dict(nb=0.1, sigma_z=0.0), dict(n_floor=-1.0), dict(check_every=-1),
-    dict(collision=3), dict(collision=-1), dict(collision=1, trt_magic=0.0),
+    dict(collision=4), dict(collision=-1), dict(collision=1, trt_magic=0.0),
     dict(collision=1, trt_magic=float("inf")),
+    dict(collision=3, mrt_sq=0.0), dict(collision=3, mrt_se=2.0), dict(collision=3, mrt_spi=float("nan")),
     dict(driver=2), dict(driver=1, max_particles=-1), dict(driver=1, max_particles=2 ** 31),
     dict(nz=8192, nr=8193), dict(nz=64, nr=65536), dict(tau=float("nan")), dict(dz=-0.05, dr=-0.05),
 ])

@@ -1,6 +1,6 @@
-"""GPU parity of the collision operators other than BGK (reading R29: two relaxation times, and
-the regularised operator) against the FP64 oracle, through the C ABI, and their rejection by the
-adjoint, which is implemented for BGK only.
+"""GPU parity of the collision operators other than BGK (reading R29: two relaxation times, the
+regularised operator and multiple relaxation times) against the FP64 oracle, through the C ABI,
+and their rejection by the adjoint, which is implemented for BGK only.
 
 FP64 storage matches to 1e-10 (max-norm per state group, as for BGK); FP32 and FP16 storage use
 the bounds stated at the test.  tau = 0.7 so that the TRT even rate differs from the odd one
@@ -29,6 +29,8 @@ COLLISIONS = {
     "trt_quarter": dict(collision=wl.TRT, trt_magic=0.25),
     "trt_twelfth": dict(collision=wl.TRT, trt_magic=1.0 / 12.0),
     "regularised": dict(collision=wl.REG),
+    # rates of energy, energy square, heat flux and stress all away from 1/tau and from each other
+    "mrt": dict(collision=wl.MRT, mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7, mrt_spi=1.2),
 }
 VARIANTS = {
     "window": dict(moving_window=1),
@@ -59,7 +61,7 @@ def test_fp64_parity(coll, var):
     lat.close()
 
 
-@pytest.mark.parametrize("coll", ["trt_quarter", "regularised"])
+@pytest.mark.parametrize("coll", ["trt_quarter", "regularised", "mrt"])
 def test_reduced_precision_parity_c2_copy(coll):
     """C2's 512 x 128 copy with the plasma already around the driver, 400 steps: FP32 and FP16
     storage against the FP64 oracle (max-norm relative error of n, E_z, E_r).
@@ -94,7 +96,7 @@ def test_reduced_precision_parity_c2_copy(coll):
     assert f16n["n"] < 5e-5 and f16n["Ez"] < 5e-4 and f16n["Er"] < 5e-4, errs
 
 
-@pytest.mark.parametrize("coll", ["trt_quarter", "regularised"])
+@pytest.mark.parametrize("coll", ["trt_quarter", "regularised", "mrt"])
 def test_full_size_c2_single_step(coll):
     """C2 at full size (2048 x 512, the benchmark's launch configuration), one step from the
     initial state with a seeded density perturbation and momentum, so that the populations leave

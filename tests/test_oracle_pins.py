@@ -72,6 +72,7 @@ def test_printed_equilibrium_coefficients_violate_moments():
     dict(ramp_kind=1, ramp_start=0.3, ramp_len=0.3, n_floor=1e-3),
     dict(collision=1, trt_magic=0.1, moving_window=1),
     dict(collision=2, ramp_kind=2, ramp_start=0.1, ramp_len=0.2),
+    dict(collision=3, mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7, mrt_spi=1.2, moving_window=1),
 ])
 def test_brute_force_agreement(variant):
     cfg = wl.config(None, nz=8, nr=4, dz=0.1, dr=0.1, nb=0.3, sigma_z=0.2, sigma_r=0.15, zd0=0.4,
@@ -92,9 +93,10 @@ def test_brute_force_agreement(variant):
 # P_rest: a uniform plasma at rest with no driver is a fixed point (ghosts, axis, window)
 # ---------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("collision", [0, 1, 2])
+@pytest.mark.parametrize("collision", [0, 1, 2, 3])
 def test_rest_is_fixed_point(collision):
-    cfg = wl.config(None, nz=32, nr=12, moving_window=1, n0=1.0, nb=0.0, collision=collision)
+    cfg = wl.config(None, nz=32, nr=12, moving_window=1, n0=1.0, nb=0.0, collision=collision,
+                    mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7, mrt_spi=1.2)
     P = O.Params(cfg)
     S0 = O.initial_state(P)
     S = S0
@@ -178,14 +180,17 @@ def test_momentum_diffusion_wave(tau):
 # ---------------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("tau,collision,magic", [(0.6, 0, 0.25), (0.8, 0, 0.25), (0.6, 1, 0.25),
-                                                 (0.8, 1, 1.0 / 12.0), (0.6, 2, 0.25)])
+                                                 (0.8, 1, 1.0 / 12.0), (0.6, 2, 0.25), (0.6, 3, 0.0),
+                                                 (0.8, 3, 0.0)])
 def test_diffusivity(tau, collision, magic):
-    """For TRT and the regularised operator (R29) D depends on tau alone: with tau = 0.6 and
+    """For TRT, the regularised operator and MRT (R29) D depends on tau alone: with tau = 0.6 and
     Lambda = 1/4 the even rate is tau_plus = 3, which would give a five times larger D if the two
-    rates were swapped."""
+    rates were swapped; MRT runs with energy, energy-square, heat-flux and stress rates
+    1.3, 0.6, 1.7, 1.2, none of them 1/tau."""
     n = 96
     cfg = wl.config(None, nz=n, nr=n, dz=0.05, dr=0.05, periodic=3, fields_on=0, cyl_on=0,
-                    nb=0.0, tau=tau, collision=collision, trt_magic=magic)
+                    nb=0.0, tau=tau, collision=collision, trt_magic=magic,
+                    mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7, mrt_spi=1.2)
     P = O.Params(cfg)
     zc, rc = 48 * 0.05, 48.5 * 0.05
     S = O.initial_state(P, wl.gaussian_bump(cfg, 0.1, 0.2, 0.2, zc=zc, rc=rc))
@@ -489,17 +494,23 @@ def _moments9(f):
     return torch.stack(out)
 
 
-@pytest.mark.parametrize("collision", [0, 1, 2])
+@pytest.mark.parametrize("collision", [0, 1, 2, 3])
 def test_collision_relaxes_each_moment_at_its_rate(collision):
     """Spatially uniform random populations on a doubly periodic lattice with fields and sources
     off: streaming is the identity, so one step is one collision.  The moment-space statement of
     each operator: BGK relaxes all eight non-conserved moments with 1/tau; TRT relaxes the odd
     ones (j, q) with 1/tau and the even ones (Pi, m4) with 1/tau_plus; the regularised operator
     relaxes j with 1/tau, sets Pi and m4 to equilibrium and sets q to q_eq + (1 - 1/tau) j_neq / 3
-    (the q-moment of the first-order Hermite term, since sum w xi_z^2 xi_r^2 = 1/9)."""
+    (the q-moment of the first-order Hermite term, since sum w xi_z^2 xi_r^2 = 1/9).  MRT, stated
+    in these raw moments through identities on the nine velocities (|xi|^4 = |xi|^2 + 2 xi_z^2
+    xi_r^2 and xi_z^3 = xi_z): j relaxes with 1/tau; Pi_zz + Pi_rr (= (e + 4 rho)/3) with s_e;
+    Pi_zz - Pi_rr and Pi_zr with s_pi; q_z = (q_z^MRT + 2 j_z)/3 and m4 = (eps + 2 e + 4 rho)/9
+    each with the mix of rates that gives."""
     tau, magic = 0.7, 0.09
+    s_e, s_eps, s_q, s_pi = 1.3, 0.6, 1.7, 1.2
     cfg = wl.config(None, nz=3, nr=3, periodic=3, fields_on=0, cyl_on=0, tau=tau,
-                    collision=collision, trt_magic=magic)
+                    collision=collision, trt_magic=magic, mrt_se=s_e, mrt_seps=s_eps, mrt_sq=s_q,
+                    mrt_spi=s_pi)
     P = O.Params(cfg)
     S = O.initial_state(P)
     gen = torch.Generator().manual_seed(11)
@@ -521,6 +532,20 @@ def test_collision_relaxes_each_moment_at_its_rate(collision):
             expect[1:3] = m0[1:3] - (m0[1:3] - meq[1:3]) / tau
             expect[even] = meq[even]
             expect[6:8] = meq[6:8] + (1 - 1 / tau) * (m0[1:3] - meq[1:3]) / 3
+        elif collision == 3:
+            d = m0 - meq
+            jn = (1 - 1 / tau) * d[1:3]                              # flux
+            tr = (1 - s_e) * (d[3] + d[4])                          # Pi_zz + Pi_rr
+            df = (1 - s_pi) * (d[3] - d[4])                         # Pi_zz - Pi_rr
+            expect[1:3] = meq[1:3] + jn
+            expect[3] = meq[3] + 0.5 * (tr + df)
+            expect[4] = meq[4] + 0.5 * (tr - df)
+            expect[5] = meq[5] + (1 - s_pi) * d[5]
+            qm = (1 - s_q) * (3 * d[6:8] - 2 * d[1:3])              # the MRT heat fluxes
+            expect[6:8] = meq[6:8] + (qm + 2 * jn) / 3
+            e_n = 3 * (d[3] + d[4])
+            eps_n = 9 * d[8] - 2 * e_n
+            expect[8] = meq[8] + ((1 - s_eps) * eps_n + 2 * (1 - s_e) * e_n) / 9
         else:
             expect[odd] = m0[odd] - (m0[odd] - meq[odd]) / tau
             expect[even] = m0[even] - (m0[even] - meq[even]) / tau_p
@@ -546,10 +571,34 @@ def test_trt_with_lambda_of_bgk_is_bgk():
     assert float((Sb.g - So.g).abs().max()) > 1e-6
 
 
+def test_mrt_reduces_to_bgk_and_trt():
+    """MRT with every rate 1/tau is BGK, and with s_e = s_eps = s_pi = 1/tau_plus, s_q = 1/tau it
+    is TRT (R29), over a coupled, driven, windowed run; rates off those values differ from both."""
+    tau, magic = 0.7, 0.09
+    tau_p = 0.5 + magic / (tau - 0.5)
+    base = dict(nz=40, nr=10, dz=0.05, dr=0.05, nb=0.8, sigma_z=0.3, sigma_r=0.3, zd0=1.5, tau=tau,
+                moving_window=1, noise_amp=0.02, seed=5)
+    runs = {}
+    for name, extra in (("bgk", dict()), ("trt", dict(collision=1, trt_magic=magic)),
+                        ("mrt_bgk", dict(collision=3, mrt_se=1 / tau, mrt_seps=1 / tau, mrt_sq=1 / tau,
+                                         mrt_spi=1 / tau)),
+                        ("mrt_trt", dict(collision=3, mrt_se=1 / tau_p, mrt_seps=1 / tau_p, mrt_sq=1 / tau,
+                                         mrt_spi=1 / tau_p)),
+                        ("mrt", dict(collision=3, mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7, mrt_spi=1.2))):
+        cfg = wl.config(None, **base, **extra)
+        runs[name], _ = _run(cfg, 30, wl.density_perturbation(cfg))
+    for a, b in (("bgk", "mrt_bgk"), ("trt", "mrt_trt")):
+        for x, y in ((runs[a].g, runs[b].g), (runs[a].M, runs[b].M), (runs[a].Ez, runs[b].Ez)):
+            assert float((x - y).abs().max()) < 1e-13 * max(1.0, float(x.abs().max())), (a, b)
+    for a in ("bgk", "trt"):
+        assert float((runs[a].g - runs["mrt"].g).abs().max()) > 1e-6
+
+
 def test_collision_operators_conserve_per_site():
-    for collision in (1, 2):
+    for collision in (1, 2, 3):
         cfg = wl.config(None, nz=24, nr=10, nb=0.4, sigma_z=0.3, sigma_r=0.3, zd0=0.6, noise_amp=0.01,
-                        seed=4, moving_window=1, collision=collision)
+                        seed=4, moving_window=1, collision=collision,
+                        mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7, mrt_spi=1.2)
         S, _ = _run(cfg, 9, wl.density_perturbation(cfg), wl.random_momentum(cfg, 0.1))
         assert float((S.g.sum(1) - S.M).abs().max()) < 1e-14
 
