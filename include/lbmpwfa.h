@@ -49,7 +49,8 @@ enum {
  * w_i n_bg(z); diagnostics are always accumulated in FP64.  F16N: as F16, but each population
  * is stored as its part off the equilibrium (Eq. (9)) of the moments stored at its own site,
  * which are FP32: the same bytes as F16 with about a tenth of its error, for more arithmetic per
- * step.  The adjoint (lbm_adjoint, lbm_vjp_*) takes F64, F32 and F16. */
+ * step.  The adjoint (lbm_adjoint, lbm_vjp_*) takes F64, F32 and F16 (with fp64_math = 1 on
+ * F32 and F16 for the BGK collision only). */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_F16N = 3 };
 
 /* Collision operator of the three lattices.  The paper uses BGK (Eq. (7)) and notes (Sec. IV)
@@ -173,7 +174,7 @@ int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init,
 
 /* Advance nsteps >= 0 steps.  One step (Eqs. (5)-(10), (13), (14)): Ampere with the previous
  * step's post-kick current and the driver current, Faraday, pull-stream of the 27 populations,
- * moments, Lorentz and axisymmetric sources, BGK collision, window shift when due.  Stream-
+ * moments, Lorentz and axisymmetric sources, collision (cfg.collision), window shift when due.  Stream-
  * ordered and asynchronous unless cfg.check_every > 0. */
 int lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
@@ -212,11 +213,14 @@ int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);
  *
  * theta = (ramp_len, n0, sigma_r, nb).  The objective J is the witness field: E_z of the state
  * on row obj->row, linearly interpolated in z at z_d(t_{N-1}) - obj->z_behind after N steps
- * (the time level of E in the state).  Adjoint arithmetic is FP64; on the device the adjoint
- * variables are stored in the precision of the auxiliary planes (FP64 for LBM_F64, FP32 for
- * LBM_F32 and LBM_F16), and the forward states are used in their storage precision.  Host-side
+ * (the time level of E in the state).  On the device the adjoint computes and stores its
+ * variables in the precision of the auxiliary planes (FP64 for LBM_F64, FP32 for LBM_F32 and
+ * LBM_F16), reads the forward states in their storage precision, and sums the theta partials in
+ * FP64; J and grad are FP64.  Host-side
  * adjoint arrays are FP64 in the layout of lbm_get_state: [27][nr][nz] populations,
- * [3][nr][nz] moments, [3][nr][nz] E_z, E_r, B_theta.
+ * [3][nr][nz] moments, [3][nr][nz] E_z, E_r, B_theta.  Every collision operator is covered:
+ * each writes the post-collision populations as P f + (I - P) f_eq + w_i dt F with a fixed linear
+ * map P of the pulled populations f (BGK: (1 - 1/tau) I), and the adjoint applies P^T.
  * ------------------------------------------------------------------------------------------- */
 typedef struct { double z_behind; int32_t row; } lbm_objective;
 

@@ -117,7 +117,7 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const T M[3], T jz
 // Site part of a reverse step for the tile whose first site is (i0, j0) (logical columns of x^k).
 // mreg: M_bar^{k+1} of the thread's site output, when the caller has it in registers (else read
 // from lam_next).  theta partials are added to part.  Every thread of the block must call it.
-template <int ST>
+template <int ST, int COLL>
 __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const typename Mode<ST, false>::C* mreg, double part[4]) {
   using S = typename Mode<ST, false>::S;
   using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
@@ -260,36 +260,107 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
       const T Ebz = (T)sfield[0], Ebr = (T)sfield[1], Bb = (T)sfield[2];
       const T ir = (T)(1.0 / ((j + 0.5) * h));
 
-      // g' = (1 - 1/tau) f + e/tau + w dt F,  M' = A + dt F,  e = w A (1 + Q(u))
+      // g' = P f + (I - P) e + w dt F,  M' = A + dt F,  e = w A (1 + Q(u)), with P the collision's
+      // action on the pulled populations (BGK: P = (1 - 1/tau) I).  So the pulled populations get
+      // P^T g_bar, and the equilibrium gets e_bar = g_bar - P^T g_bar (BGK: g_bar / tau).
       T Fb[3], Ab[3];
       T ubz = T(0.0), ubr = T(0.0);
       T sw[3] = {T(0.0), T(0.0), T(0.0)}, s0[3] = {T(0.0), T(0.0), T(0.0)};
       const T itau = T(1.0) / (T)p.tau, usq = uz * uz + ur * ur;
+      // P^T g_bar for lattice kk (operators other than BGK)
+      auto ptrans = [&](int kk, T (&pt)[9]) {
+        T g[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const T w = WQ<T>(q);
-        const T cu = XZ(q) * uz + XR(q) * ur;
-        const T e1 = w * (T(1.0) + T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * usq);   // e_q / A
-        const T fz = w * (T(3.0) * XZ(q) + T(9.0) * cu * XZ(q) - T(3.0) * uz);    // w dQ/du_z
-        const T fr = w * (T(3.0) * XR(q) + T(9.0) * cu * XR(q) - T(3.0) * ur);
-        T az = T(0.0);
+        for (int q = 0; q < 9; ++q) g[q] = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
+        if (COLL == 1) {
+          // two relaxation times: P = I - (even part / tau_plus + odd part / tau), symmetric
+          const T itp = T(1.0) / (T)p.tau_plus;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            const T gq = g[q], gb = g[OPPQ(q)];
+            pt[q] = gq - T(0.5) * (gq + gb) * itp - T(0.5) * (gq - gb) * itau;
+          }
+        } else if (COLL == 3) {
+          // multiple relaxation times: P = I - sum_m s_m b_m b_m^T / |b_m|^2, symmetric
+          const T rate[9] = {T(0.0), (T)p.mrt_se, (T)p.mrt_seps, itau, (T)p.mrt_sq, itau, (T)p.mrt_sq,
+                             (T)p.mrt_spi, (T)p.mrt_spi};
+          T c[9];
+#pragma unroll
+          for (int m = 1; m < 9; ++m) {
+            T nm = T(0.0);
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+              if (MB(m, q) != 0) nm += (T)MB(m, q) * g[q];
+            c[m] = rate[m] * nm / (T)MB_NORM2(m);
+          }
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            T v = g[q];
+#pragma unroll
+            for (int m = 1; m < 9; ++m)
+              if (MB(m, q) != 0) v -= (T)MB(m, q) * c[m];
+            pt[q] = v;
+          }
+        } else {
+          // regularised: P = (1 - 1/tau) H with H_qp = 3 w_q xi_q . xi_p
+          T jz = T(0.0), jr = T(0.0);
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            jz += WQ<T>(q) * XZ(q) * g[q];
+            jr += WQ<T>(q) * XR(q) * g[q];
+          }
+          const T k3 = T(3.0) * (T(1.0) - itau);
+#pragma unroll
+          for (int q = 0; q < 9; ++q) pt[q] = k3 * (XZ(q) * jz + XR(q) * jr);
+        }
+      };
+      if (COLL == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const T w = WQ<T>(q);
+          const T cu = XZ(q) * uz + XR(q) * ur;
+          const T e1 = w * (T(1.0) + T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * usq);   // e_q / A
+          const T fz = w * (T(3.0) * XZ(q) + T(9.0) * cu * XZ(q) - T(3.0) * uz);    // w dQ/du_z
+          const T fr = w * (T(3.0) * XR(q) + T(9.0) * cu * XR(q) - T(3.0) * ur);
+          T az = T(0.0);
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) {
+            const T gbq = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
+            sw[kk] += w * gbq;
+            s0[kk] += gbq * e1;
+            az += gbq * Am[kk];
+          }
+          ubz += az * fz;
+          ubr += az * fr;
+        }
+        ubz *= itau;
+        ubr *= itau;
+      } else {
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
-          const T gbq = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
-          sw[kk] += w * gbq;
-          s0[kk] += gbq * e1;
-          az += gbq * Am[kk];
+          T pt[9];
+          ptrans(kk, pt);
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            const T w = WQ<T>(q);
+            const T cu = XZ(q) * uz + XR(q) * ur;
+            const T e1 = w * (T(1.0) + T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+            const T fz = w * (T(3.0) * XZ(q) + T(9.0) * cu * XZ(q) - T(3.0) * uz);
+            const T fr = w * (T(3.0) * XR(q) + T(9.0) * cu * XR(q) - T(3.0) * ur);
+            const T gbq = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
+            const T eb = gbq - pt[q];
+            sw[kk] += w * gbq;
+            s0[kk] += eb * e1;
+            ubz += eb * Am[kk] * fz;
+            ubr += eb * Am[kk] * fr;
+          }
         }
-        ubz += az * fz;
-        ubr += az * fr;
       }
-      ubz *= itau;
-      ubr *= itau;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
         const T Mb = mreg ? mreg[kk] : (T)mbar[kk];
         Fb[kk] = dt * (sw[kk] + Mb);
-        Ab[kk] = Mb + s0[kk] * itau;
+        Ab[kk] = COLL == 0 ? Mb + s0[kk] * itau : Mb + s0[kk];
       }
       T bbz = lam * ubz, bbr = lam * ubr;
       T Ebz_b = T(0.0), Ebr_b = T(0.0), Bb_b = T(0.0);
@@ -318,15 +389,20 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
         Ab[2] += pbr * in;
         Ab[0] -= (pbz * pz + pbr * pr) * in;
       }
-      // adjoint of the pulled populations: (1 - 1/tau) g_bar' + A_bar
+      // adjoint of the pulled populations: P^T g_bar' + A_bar (BGK: (1 - 1/tau) g_bar' + A_bar)
       const T c1 = T(1.0) - itau;
+      T fb0[9];   // the adjoint of lattice 0's pulled populations, kept for the window-front term
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
+      for (int kk = 0; kk < 3; ++kk) {
+        T pt[9];
+        if (COLL != 0) ptrans(kk, pt);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          const T gbq = gok[q] ? (T)gbar[9 * kk + q] : T(0.0);
-          stv(&(Lo + (9 * kk + q) * plane)[cell], c1 * gbq + Ab[kk]);
+          const T v = COLL == 0 ? c1 * (gok[q] ? (T)gbar[9 * kk + q] : T(0.0)) + Ab[kk] : pt[q] + Ab[kk];
+          stv(&(Lo + (9 * kk + q) * plane)[cell], v);
+          if (kk == 0) fb0[q] = v;
         }
+      }
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) stv(&(W + (W_F + kk) * plane)[cell], Fb[kk]);
       stv(&(W + W_EZ * plane)[cell], Ebz_b);
@@ -340,7 +416,7 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
         double sum = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-          if (XZ(q) == -1) sum += WQ<double>(q) * (double)(c1 * (gok[q] ? (T)gbar[q] : T(0)) + Ab[0]);
+          if (XZ(q) == -1) sum += WQ<double>(q) * (double)fb0[q];
         part[0] += sum * dl;
         part[1] += sum * dn;
         if (a.shift) {
@@ -368,12 +444,12 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
   }
 }
 
-template <int ST>
+template <int ST, int COLL>
 __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   double part[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(ramp_len, n0, sigma_r, n_b)
-  site_body<ST>(a, (tile % gx) * TZ, (tile / gx) * TR, nullptr, part);
+  site_body<ST, COLL>(a, (tile % gx) * TZ, (tile / gx) * TR, nullptr, part);
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
 }
 
@@ -701,7 +777,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
 // part reads; the two steps use different work buffers.
 // The site step's arguments arrive without their physics (the same as ac.p), which keeps the
 // kernel's uniform values to one copy of the physics.
-template <int ST>
+template <int ST, int COLL>
 __device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss) {
   AdjArgs as;
   as.p = ac.p;
@@ -732,21 +808,21 @@ __device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss)
     part[0] += mb[0] * dl;
     part[1] += mb[0] * dn;
   }
-  site_body<ST>(as, o0 + as.shift, j0, mb, part);
+  site_body<ST, COLL>(as, o0 + as.shift, j0, mb, part);
   block_sum4(part, as.partials + (long long)blockIdx.x * 4);
 }
 
-template <int ST>
+template <int ST, int COLL>
 __global__ __launch_bounds__(NTHREADS) void adj_fused_kernel(AdjArgs ac, AdjStep ss) {
-  fused_body<ST>(ac, ss);
+  fused_body<ST, COLL>(ac, ss);
 }
 
 // FP32 and FP16 storage: held to 128 VGPRs (4 waves per SIMD), where the kernel fits without
 // spills; one register more would drop it to 3 waves per SIMD.
-template <int ST>
+template <int ST, int COLL>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(4))) void adj_fused4_kernel(AdjArgs ac,
                                                                                                      AdjStep ss) {
-  fused_body<ST>(ac, ss);
+  fused_body<ST, COLL>(ac, ss);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -920,9 +996,29 @@ int adjoint_partial_blocks(const Physics& p) { return step_blocks(p); }
 
 // a.partials holds 2 * adjoint_partial_blocks(p) accumulators of 4 doubles (site kernel, then
 // cell kernel); they must be zero before the first step and are summed by adjoint_reduce.
+// The site part with the run's collision operator.
+template <int COLL>
+static void site_launch_c(int storage, dim3 grid, hipStream_t st, const AdjArgs& a) {
+  if (storage == 0) adj_site_kernel<0, COLL><<<grid, NTHREADS, 0, st>>>(a);
+  else if (storage == 1) adj_site_kernel<1, COLL><<<grid, NTHREADS, 0, st>>>(a);
+  else adj_site_kernel<2, COLL><<<grid, NTHREADS, 0, st>>>(a);
+}
+static void site_launch(int storage, dim3 grid, hipStream_t st, const AdjArgs& a) {
+  if (a.p.coll == 1) site_launch_c<1>(storage, grid, st, a);
+  else if (a.p.coll == 2) site_launch_c<2>(storage, grid, st, a);
+  else if (a.p.coll == 3) site_launch_c<3>(storage, grid, st, a);
+  else site_launch_c<0>(storage, grid, st, a);
+}
+template <int COLL>
+static void fused_launch_c(int storage, dim3 grid, hipStream_t st, const AdjArgs& cell, const AdjStep& ss) {
+  if (storage == 0) adj_fused_kernel<0, COLL><<<grid, NTHREADS, 0, st>>>(cell, ss);
+  else if (storage == 1) adj_fused4_kernel<1, COLL><<<grid, NTHREADS, 0, st>>>(cell, ss);
+  else adj_fused4_kernel<2, COLL><<<grid, NTHREADS, 0, st>>>(cell, ss);
+}
+
 hipError_t launch_adjoint_step(int storage, const AdjArgs& a, hipStream_t st) {
   const int nb = step_blocks(a.p);
-  ADJ_DISPATCH(storage, adj_site_kernel, dim3(nb), NTHREADS, st, a);
+  site_launch(storage, dim3(nb), st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   AdjArgs b = a;
@@ -932,7 +1028,7 @@ hipError_t launch_adjoint_step(int storage, const AdjArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_adjoint_site(int storage, const AdjArgs& a, hipStream_t st) {
-  ADJ_DISPATCH(storage, adj_site_kernel, dim3(step_blocks(a.p)), NTHREADS, st, a);
+  site_launch(storage, dim3(step_blocks(a.p)), st, a);
   return hipGetLastError();
 }
 
@@ -947,9 +1043,10 @@ hipError_t launch_adjoint_fused(int storage, const AdjArgs& cell, const AdjArgs&
   const AdjStep ss{site.k, site.s, site.shift, site.pull_in, site.g, site.M, site.E,
                    site.lam_next, site.lam, site.work, site.site, site.partials};
   const dim3 grid(step_blocks(cell.p));
-  if (storage == 0) adj_fused_kernel<0><<<grid, NTHREADS, 0, st>>>(cell, ss);
-  else if (storage == 1) adj_fused4_kernel<1><<<grid, NTHREADS, 0, st>>>(cell, ss);
-  else adj_fused4_kernel<2><<<grid, NTHREADS, 0, st>>>(cell, ss);
+  if (cell.p.coll == 1) fused_launch_c<1>(storage, grid, st, cell, ss);
+  else if (cell.p.coll == 2) fused_launch_c<2>(storage, grid, st, cell, ss);
+  else if (cell.p.coll == 3) fused_launch_c<3>(storage, grid, st, cell, ss);
+  else fused_launch_c<0>(storage, grid, st, cell, ss);
   return hipGetLastError();
 }
 

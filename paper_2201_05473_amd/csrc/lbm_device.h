@@ -53,6 +53,8 @@ __host__ __device__ constexpr int XZ(int q) {
 __host__ __device__ constexpr int XR(int q) {
   return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
 }
+// Index of the direction opposite to q.
+__host__ __device__ constexpr int OPPQ(int q) { return q == 0 ? 0 : (q < 5 ? (q + 1) % 4 + 1 : (q - 3) % 4 + 5); }
 template <typename C> __host__ __device__ constexpr C WQ(int q) {
   return q == 0 ? C(4) / C(9) : (q < 5 ? C(1) / C(9) : C(1) / C(36));
 }

@@ -905,19 +905,25 @@ static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
   else step_kernel<ST, false, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
-// The site-field variant (used by the adjoint, which is BGK only and does not take storage 3)
-// exists for BGK alone.
+// The site-field variant is the adjoint's forward recompute (no storage 3, no particle driver;
+// FP64 arithmetic on FP32 / FP16 storage for BGK only).
+template <int ST, bool M64, int COLL>
+static void launch_step_s(const StepArgs& a, dim3 grid, hipStream_t st) {
+  if constexpr (!neq_storage(ST) && (!M64 || COLL == 0)) {
+    if (a.p.fields_on && a.site_out) {
+      step_kernel<ST, true, M64, true, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+      return;
+    }
+  }
+  launch_step_c<ST, M64, COLL>(a, grid, st);
+}
+
 template <int ST, bool M64>
 static void launch_step_t(const StepArgs& a, dim3 grid, hipStream_t st) {
-  if (a.p.coll == 1) launch_step_c<ST, M64, 1>(a, grid, st);
-  else if (a.p.coll == 2) launch_step_c<ST, M64, 2>(a, grid, st);
-  else if (a.p.coll == 3) launch_step_c<ST, M64, 3>(a, grid, st);
-  else if constexpr (!neq_storage(ST)) {
-    if (a.p.fields_on && a.site_out) step_kernel<ST, true, M64, true, 0, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
-    else launch_step_c<ST, M64, 0>(a, grid, st);
-  } else {
-    launch_step_c<ST, M64, 0>(a, grid, st);
-  }
+  if (a.p.coll == 1) launch_step_s<ST, M64, 1>(a, grid, st);
+  else if (a.p.coll == 2) launch_step_s<ST, M64, 2>(a, grid, st);
+  else if (a.p.coll == 3) launch_step_s<ST, M64, 3>(a, grid, st);
+  else launch_step_s<ST, M64, 0>(a, grid, st);
 }
 
 hipError_t launch_step(int storage, const StepArgs& a, hipStream_t st) {

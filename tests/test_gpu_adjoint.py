@@ -136,7 +136,7 @@ def test_adjoint_gradient_matches_oracle_autograd():
     Jref = O.objective(S, P, cfg["z_behind"])
     Jref.backward()
     gref = np.array([float(th[nm].grad) for nm in NAMES])
-    print("J", J, float(Jref), "grad", grad, gref, flush=True)
+    print("J", J, float(Jref.detach()), "grad", grad, gref, flush=True)
     assert abs(J - float(Jref)) < 1e-12 * abs(float(Jref))
     assert np.abs(grad - gref).max() < 1e-9 * np.abs(gref).max(), (grad, gref)
     assert (lat.counters()[0]) == n
@@ -161,7 +161,7 @@ def test_adjoint_front_column_across_tiles():
     Jref = O.objective(S, P, cfg["z_behind"])
     Jref.backward()
     gref = np.array([float(th[nm].grad) for nm in NAMES])
-    print("J", J, float(Jref), "grad", grad, gref, flush=True)
+    print("J", J, float(Jref.detach()), "grad", grad, gref, flush=True)
     assert abs(J - float(Jref)) < 1e-12 * abs(float(Jref))
     assert np.abs(grad - gref).max() < 1e-9 * np.abs(gref).max(), (grad, gref)
 

@@ -1,6 +1,7 @@
 """GPU parity of the collision operators other than BGK (reading R29: two relaxation times, the
 regularised operator and multiple relaxation times) against the FP64 oracle, through the C ABI,
-and their rejection by the adjoint, which is implemented for BGK only.
+for the step and for the hand-written adjoint (against autograd through the oracle, and against
+finite differences of the GPU forward at C4's full size).
 
 FP64 storage matches to 1e-10 (max-norm per state group, as for BGK); FP32 and FP16 storage use
 the bounds stated at the test.  tau = 0.7 so that the TRT even rate differs from the odd one
@@ -121,16 +122,109 @@ def test_full_size_c2_single_step(coll):
         lat.close()
 
 
-def test_adjoint_rejects_other_collisions():
+@pytest.mark.parametrize("var", ["window", "periodic_zr_cartesian", "tanh_window", "linear_vacuum_floor"])
+@pytest.mark.parametrize("coll", list(COLLISIONS))
+def test_vjp_step_matches_oracle_autograd(coll, var):
+    """One reverse step (the window-shift step k = 4 where the window is on) on 150 x 13 at a
+    state with noise and random momentum: lambda^k and the theta partials match the FP64 CPU
+    adjoint to 1e-10."""
+    from paper_2201_05473_amd import Lattice
+    from test_gpu_adjoint import group_errors, oracle_vjp_step
+    cfg = wl.config(None, nz=150, nr=13, dz=0.05, dr=0.05, nb=0.3, sigma_z=0.4, sigma_r=0.3,
+                    zd0=5.0, noise_amp=1e-3, seed=11, storage=wl.F64, tau=0.7,
+                    **COLLISIONS[coll], **VARIANTS[var])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=3)
+    lam_next = np.random.default_rng(104).standard_normal((33, cfg["nr"], cfg["nz"]))
+    print(f"[collision vjp step] {coll} {var} k=4", flush=True)
+    lat = Lattice(cfg, pert, pinit)
+    lat.step(4)
+    lam, grad = lat.vjp_step(lam_next)
+    lam_ref, grad_ref = oracle_vjp_step(cfg, 4, lam_next, pert, pinit)
+    errs = group_errors(lam, lam_ref)
+    assert errs.max() < 1e-10, (errs.argmax(), errs.max())
+    scale = max(np.abs(grad_ref).max(), 1e-300)
+    assert np.abs(grad - grad_ref).max() < 1e-10 * scale, (grad, grad_ref)
+    lat.close()
+
+
+def adjoint_wake_cfg(coll, storage=wl.F64):
+    from test_gpu_adjoint import wake_cfg
+    return dict(wake_cfg(storage), tau=0.7, **COLLISIONS[coll])
+
+
+@pytest.mark.parametrize("coll", list(COLLISIONS))
+def test_adjoint_gradient_matches_oracle_autograd(coll):
+    """lbm_adjoint on C4's 128 x 32 copy (witness in the wake, window shifts), 60 steps with a
+    checkpoint every 7 and a ragged last segment, against autograd through the FP64 oracle;
+    and the FP32-storage adjoint against it (FP32 arithmetic: bound 1e-4 of the largest
+    partial)."""
+    from paper_2201_05473_amd import Lattice
+    from test_gpu_adjoint import NAMES, theta_of
+    cfg = adjoint_wake_cfg(coll)
+    n, ck = 60, 7
+    print(f"[collision adjoint] {coll} 128x32 {n} steps", flush=True)
+    J, grad = Lattice(cfg).adjoint(n, ck, z_behind=cfg["z_behind"], row=0)
+    th = theta_of(cfg)
+    P = O.Params(cfg, th)
+    S = O.initial_state(P)
+    for _ in range(n):
+        S = O.step(S, P)
+    Jref = O.objective(S, P, cfg["z_behind"])
+    Jref.backward()
+    gref = np.array([float(th[nm].grad) for nm in NAMES])
+    J32, g32 = Lattice(dict(cfg, storage=wl.F32)).adjoint(n, ck, z_behind=cfg["z_behind"], row=0)
+    print(coll, "J", J, float(Jref.detach()), "grad", grad, gref, "fp32", g32, flush=True)
+    assert abs(J - float(Jref)) < 1e-12 * abs(float(Jref))
+    assert np.abs(grad - gref).max() < 1e-9 * np.abs(gref).max(), (grad, gref)
+    assert np.abs(g32 - gref).max() < 1e-4 * np.abs(gref).max(), (g32, gref)
+
+
+@pytest.mark.parametrize("coll", list(COLLISIONS))
+def test_adjoint_fd_c4(coll):
+    """C4 at full size (1024 x 256, 2,000 steps, FP32 storage, checkpoints every 45 steps) with
+    each operator at tau = 0.7: the adjoint gradient against central finite differences
+    (h = 1e-4) of FP64 forward runs, to 1e-4 (the BGK bound)."""
+    from paper_2201_05473_amd import Lattice
+    from test_gpu_adjoint import NAMES, gpu_objective
+    cfg = wl.config("C4", tau=0.7, **COLLISIONS[coll])
+    n, ck, zb = cfg["nsteps"], 45, cfg["z_behind"]
+    print(f"[collision adjoint fd] {coll} C4", flush=True)
+    J, grad = Lattice(cfg).adjoint(n, ck, z_behind=zb)
+    cfg64 = dict(cfg, storage=wl.F64)
+    J64 = gpu_objective(cfg64, n, zb)
+    fd = np.zeros(4)
+    hstep = 1e-4
+    for a, nm in enumerate(NAMES):
+        cp, cm = dict(cfg64), dict(cfg64)
+        cp[nm] += hstep
+        cm[nm] -= hstep
+        fd[a] = (gpu_objective(cp, n, zb) - gpu_objective(cm, n, zb)) / (2 * hstep)
+    rel = np.abs(grad - fd) / np.abs(fd)
+    print(coll, "C4 J32", J, "J64", J64, "adjoint", grad, "fd", fd, "rel", rel, flush=True)
+    assert abs(J - J64) < 1e-4 * abs(J64)
+    assert rel.max() < 1e-4, rel
+
+
+def test_adjoint_rejections():
+    """The adjoint refuses FP64 arithmetic on FP32 storage for operators other than BGK (the
+    forward recompute it needs exists for BGK only there) and FP16N storage."""
     from paper_2201_05473_amd import LBM_EINVAL, LbmError, Lattice
-    cfg = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.3, collision=wl.TRT)
-    lat = Lattice(cfg)
-    with pytest.raises(LbmError) as ei:
-        lat.adjoint(4, 2)
-    assert ei.value.code == LBM_EINVAL
-    with pytest.raises(LbmError) as ei:
-        lat.vjp_step(np.zeros((33, 8, 64)))
-    assert ei.value.code == LBM_EINVAL
+    base = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.3, tau=0.7)
+    for extra, why in ((dict(collision=wl.TRT, storage=wl.F32, fp64_math=1), "fp64_math"),
+                       (dict(collision=wl.MRT, storage=wl.F16, fp64_math=1), "fp64_math"),
+                       (dict(collision=wl.REG, storage=wl.F16N), "storage")):
+        lat = Lattice(dict(base, **extra))
+        with pytest.raises(LbmError) as ei:
+            lat.adjoint(4, 2, z_behind=1.0)
+        assert ei.value.code == LBM_EINVAL and why in str(ei.value), str(ei.value)
+        with pytest.raises(LbmError) as ei:
+            lat.vjp_step(np.zeros((33, 8, 64)))
+        assert ei.value.code == LBM_EINVAL and why in str(ei.value), str(ei.value)
+        lat.close()
+    lat = Lattice(dict(base, collision=wl.BGK, storage=wl.F32, fp64_math=1))
+    J, g = lat.adjoint(4, 2, z_behind=1.0)
+    assert np.isfinite(J) and np.all(np.isfinite(g))
     lat.close()
 
 
