@@ -290,7 +290,8 @@ int lbm_bubble_length(lbm_ctx* ctx, int32_t row, double n_star, double z_from, d
  * init_fields = 0 keeps the fields (to resume a run).  The library keeps its own copy, stored in
  * an order of its choosing (lbm_get_bunch returns the caller's order).  Synchronising.
  * LBM_EINVAL for another driver, n out of range, a non-finite value, a negative weight, or
- * init_fields at a step other than 0. */
+ * init_fields at a step other than 0 (the previous bunch is kept); LBM_ENOMEM if host memory
+ * runs out; LBM_EHIP if the upload fails, which leaves the context with no particles. */
 int lbm_set_bunch(lbm_ctx* ctx, int64_t n, const double* bunch, int32_t init_fields);
 
 /* Current bunch, [7][n] in the layout of lbm_set_bunch, into host memory of at least 7 * n_max

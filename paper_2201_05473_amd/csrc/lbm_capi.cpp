@@ -1200,20 +1200,25 @@ int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
     col[(size_t)i] = std::floor(bunch[2 * n + i] / c->p.h);
     rad[(size_t)i] = bunch[i] * bunch[i] + bunch[n + i] * bunch[n + i];
   }
-  c->order.resize((size_t)n);
-  std::iota(c->order.begin(), c->order.end(), (int64_t)0);
-  std::stable_sort(c->order.begin(), c->order.end(), [&](int64_t a, int64_t b) {
+  std::vector<int64_t> order((size_t)n);
+  std::iota(order.begin(), order.end(), (int64_t)0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return col[(size_t)a] < col[(size_t)b] || (col[(size_t)a] == col[(size_t)b] && rad[(size_t)a] < rad[(size_t)b]);
   });
   std::vector<double> sorted((size_t)(7 * n));
   for (int comp = 0; comp < 7; ++comp)
-    for (int64_t i = 0; i < n; ++i) sorted[(size_t)(comp * n + i)] = bunch[comp * n + c->order[(size_t)i]];
-  for (int comp = 0; comp < 7; ++comp)
-    if (n > 0)
-      HIP_CHECK(hipMemcpyAsync(c->bunch() + comp * c->p.cap, sorted.data() + comp * n, (size_t)n * sizeof(double),
-                               hipMemcpyHostToDevice, c->stream),
-                "bunch upload");
+    for (int64_t i = 0; i < n; ++i) sorted[(size_t)(comp * n + i)] = bunch[comp * n + order[(size_t)i]];
+  for (int comp = 0; comp < 7 && n > 0; ++comp) {
+    const hipError_t e = hipMemcpyAsync(c->bunch() + comp * c->p.cap, sorted.data() + comp * n,
+                                        (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(c->stream);   // copies already queued read `sorted`
+      c->nbunch = 0;                           // the device bunch is now partly overwritten
+      return hip_fail(e, "bunch upload");
+    }
+  }
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");   // before the host buffer goes
+  c->order.swap(order);
   c->nbunch = n;
   if (init_fields && c->p.fields_on) {
     // E_r^{-1} from the density at the positions (t = -dt) on the E_r columns; B^{-1/2} from the
@@ -1240,10 +1245,14 @@ int get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
   if (c->nbunch > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
   const long long nb = c->nbunch;
   std::vector<double> stored((size_t)(7 * nb));
-  for (int comp = 0; comp < 7 && nb > 0; ++comp)
-    HIP_CHECK(hipMemcpyAsync(stored.data() + comp * nb, c->bunch() + comp * c->p.cap, (size_t)nb * sizeof(double),
-                             hipMemcpyDeviceToHost, c->stream),
-              "bunch download");
+  for (int comp = 0; comp < 7 && nb > 0; ++comp) {
+    const hipError_t e = hipMemcpyAsync(stored.data() + comp * nb, c->bunch() + comp * c->p.cap,
+                                        (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(c->stream);   // copies already queued write `stored`
+      return hip_fail(e, "bunch download");
+    }
+  }
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   for (int comp = 0; comp < 7; ++comp)   // back to the caller's order
     for (long long i = 0; i < nb; ++i) bunch[comp * nb + c->order[(size_t)i]] = stored[(size_t)(comp * nb + i)];
