@@ -469,7 +469,11 @@ int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
   const void* src[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
   for (int r = 0; r < 3; ++r) {
     const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
-    HIP_CHECK(hipMemcpyAsync(d + off, src[r], nb, kind, c->stream), "save copy");
+    const hipError_t e = hipMemcpyAsync(d + off, src[r], nb, kind, c->stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(c->stream);   // the queued header copy reads h
+      return hip_fail(e, "save copy");
+    }
     off += nb;
   }
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
