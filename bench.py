@@ -251,6 +251,32 @@ def particle_driver_c2(steps: int = 2000, n: int = 200000, timed_only: bool = Fa
     return res
 
 
+def paper_grid_2mm() -> dict:
+    """The paper's finest grid of Table 1 (preset P: 2400 x 400 cells of 0.25 um, 48,000 steps of
+    c dt = dz/6 = 2 mm of propagation), FP32, rigid driver at the three charges alpha = 0.678,
+    3.39, 6.78: time
+    of the whole run (fluid and fields; HIP events on the library's stream), next to the time the
+    paper gives for its fluid routine alone on the same grid and distance (one Intel Xeon
+    E5-2695, Table 1).  Context only: another machine, and less work per step there.  The FP32
+    working set (about 2 x 110 MB) fits the 256 MB Infinity Cache, so this is not an HBM figure."""
+    import workloads as wl
+    res = {"workload": "P: 2400x400, dz=dr=0.0047/k_p (0.25 um at 1e16 cm^-3), c dt/dz=1/6, "
+                       "48000 steps (2 mm), FP32, uniform plasma, moving window, rigid driver "
+                       "sigma_z=0.333 sigma_r=0.1675",
+           "paper_fluid_routine_s": 28.88e3, "paper_hardware": "Intel Xeon E5-2695 @ 2.40 GHz"}
+    for alpha in (0.678, 3.39, 6.78):
+        cfg = wl.config("P", nb=alpha)
+        n = cfg["nsteps"]
+        wall, ev, lat = time_run(cfg, n, 0)
+        d = lat.diagnostics()
+        nmin = float(lat.moments()[0].min())
+        lat.close()
+        res[f"alpha_{alpha}"] = {"seconds": ev, "wall_s": wall, "MLUPS": cfg["nz"] * cfg["nr"] * n / ev / 1e6,
+                                 "nonfinite": int(d["nonfinite"]), "n_min": nmin}
+        print(f"[P] alpha={alpha}: {ev:.2f} s for {n} steps", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,6 +415,7 @@ def main():
         out["adjoint_forward_ratio"] = adj["ratio"]
         out["adjoint_C4"] = adj
         out["particle_driver_C2"] = particle_driver_c2()
+        out["paper_grid_2mm"] = paper_grid_2mm()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -20,6 +20,14 @@ Presets (sizes and physics follow the paper's set-up of Sec. IV, scaled to the G
   C4   1024 x 256,  dz=0.05, FP32, tanh ramp, 2,000 steps, witness 4 behind the driver.
   C4s  the 128 x 32 copy of C4 used for the CPU adjoint.
   C5   8192 x 2048, dz=0.02, FP32, tanh ramp of seed-drawn length in [5, 20], 20,000 steps.
+  P    the paper's finest grid (Sec. IV, Table 1): 600 x 100 um in cells of 0.25 um at
+       n0 = 1e16 cm^-3 (1/k_p = 53.14 um), so 2400 x 400 with dz = 0.0047.  The paper's
+       dt_c = 0.147 fs gives c dt/dz = 0.1763; the moving window here shifts one column every
+       1/(c dt/dz) steps, which must be an integer, so c dt/dz = 1/6 (dt = 0.139 fs), and 2 mm of
+       propagation is 48,000 steps (45,383 at the paper's dt).  Driver sigma_z = 17.7 um
+       (0.333), sigma_r = 8.9 um (0.1675), n_b = 0.678 (Q~ = 0.1; 3.39 and 6.78 for Q~ = 0.5
+       and 1), uniform plasma, moving window, FP32, tau = 0.8 (the paper takes the smallest
+       stable D and does not give it).  The driver sits 200 um behind the window's front edge.
 """
 from __future__ import annotations
 
@@ -92,12 +100,16 @@ def _preset(name):
                  n0=1.0, ramp_kind=2, ramp_start=zd0 + 2.0, ramp_len=float(rng.uniform(5.0, 20.0)),
                  nb=0.5, sigma_z=0.5, sigma_r=0.25, zd0=zd0, n_floor=1e-6, nsteps=20000,
                  seed=5)
+    elif name == "P":
+        b.update(nz=2400, nr=400, dz=0.0047, dr=0.0047, c_dt_over_dz=1.0 / 6.0, tau=0.8, storage=F32,
+                 moving_window=1, n0=1.0, ramp_kind=0, nb=0.678, sigma_z=0.333, sigma_r=0.1675,
+                 zd0=_window_driver(2400, 0.0047, 0.333, ahead=3.764), n_floor=1e-6, nsteps=48000)
     else:
         raise KeyError(f"unknown workload preset {name!r}")
     return b
 
 
-PRESET_NAMES = ("C1", "C2", "C2s", "C3", "C4", "C4s", "C5")
+PRESET_NAMES = ("C1", "C2", "C2s", "C3", "C4", "C4s", "C5", "P")
 
 
 def config(name: str | None = None, **overrides) -> dict:
