@@ -82,3 +82,27 @@ def test_bubble_length_grows_as_diffusivity_falls(nb):
     assert first[0] > first[-1], first
     if nb == 2.0:
         assert all(a > b for a, b in zip(whole, whole[1:])), whole
+
+
+@pytest.mark.parametrize("alpha", [0.678, 3.39, 6.78])
+def test_bubble_length_on_the_paper_grid(alpha):
+    """The paper's own grid and charges (preset P: 2400 x 400, dz = 0.25 um, 2 mm of propagation,
+    Q~ = 0.1, 0.5, 1), FP32, tau = 0.6, 0.8, 1.0 (D = 0.00094 .. 0.0047): the first bubble
+    lengthens strictly as D falls, the GPU count equals the oracle's count on the same density,
+    and no density is negative or non-finite."""
+    from paper_2201_05473_amd import Lattice
+    first = []
+    for tau in (0.6, 0.8, 1.0):
+        cfg = wl.config("P", nb=alpha, tau=tau)
+        lat = Lattice(cfg)
+        lat.step(cfg["nsteps"])
+        k, s = lat.counters()
+        zd = cfg["zd0"] + (k - 1) * cfg["dz"] * cfg["c_dt_over_dz"]
+        c, L = lat.bubble_length(0, 0.95, zd - 2 * math.pi, zd)
+        n = lat.moments()[0].double().cpu()
+        assert (c, L) == O.bubble_length(n, s, O.Params(cfg), 0, 0.95, zd - 2 * math.pi, zd)
+        assert lat.diagnostics()["nonfinite"] == 0 and float(n.min()) >= 0.0
+        first.append(L)
+        lat.close()
+        print(f"[bubble, paper grid] alpha={alpha} tau={tau} first={L:.4f} ({L * 53.14:.1f} um)", flush=True)
+    assert first[0] > first[1] > first[2], first
