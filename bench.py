@@ -253,17 +253,20 @@ def particle_driver_c2(steps: int = 2000, n: int = 200000, timed_only: bool = Fa
 
 def paper_grid_2mm() -> dict:
     """The paper's finest grid of Table 1 (preset P: 2400 x 400 cells of 0.25 um, 48,000 steps of
-    c dt = dz/6 = 2 mm of propagation), FP32, rigid driver at the three charges alpha = 0.678,
-    3.39, 6.78: time
-    of the whole run (fluid and fields; HIP events on the library's stream), next to the time the
-    paper gives for its fluid routine alone on the same grid and distance (one Intel Xeon
-    E5-2695, Table 1).  Context only: another machine, and less work per step there.  The FP32
-    working set (about 2 x 110 MB) fits the 256 MB Infinity Cache, so this is not an HBM figure."""
+    c dt = dz/6 = 2 mm of propagation), FP32, at the three charges alpha = 0.678, 3.39, 6.78: time
+    of the whole run (fluid and fields; HIP events on the library's stream), with the rigid driver
+    and with the paper's 2e5-macroparticle bunch, next to the time the paper gives for its fluid
+    routine alone on the same grid and distance (one Intel Xeon E5-2695, Table 1).  Context only:
+    another machine, and less work per step there.  The FP32 working set (about 2 x 110 MB) fits
+    the 256 MB Infinity Cache, so this is not an HBM figure."""
     import workloads as wl
     res = {"workload": "P: 2400x400, dz=dr=0.0047/k_p (0.25 um at 1e16 cm^-3), c dt/dz=1/6, "
                        "48000 steps (2 mm), FP32, uniform plasma, moving window, rigid driver "
                        "sigma_z=0.333 sigma_r=0.1675",
            "paper_fluid_routine_s": 28.88e3, "paper_hardware": "Intel Xeon E5-2695 @ 2.40 GHz"}
+    import torch
+
+    from paper_2201_05473_amd import Lattice
     for alpha in (0.678, 3.39, 6.78):
         cfg = wl.config("P", nb=alpha)
         n = cfg["nsteps"]
@@ -271,9 +274,27 @@ def paper_grid_2mm() -> dict:
         d = lat.diagnostics()
         nmin = float(lat.moments()[0].min())
         lat.close()
-        res[f"alpha_{alpha}"] = {"seconds": ev, "wall_s": wall, "MLUPS": cfg["nz"] * cfg["nr"] * n / ev / 1e6,
-                                 "nonfinite": int(d["nonfinite"]), "n_min": nmin}
-        print(f"[P] alpha={alpha}: {ev:.2f} s for {n} steps", file=sys.stderr, flush=True)
+        r = {"seconds": ev, "wall_s": wall, "MLUPS": cfg["nz"] * cfg["nr"] * n / ev / 1e6,
+             "nonfinite": int(d["nonfinite"]), "n_min": nmin}
+        # the paper's driver: 2e5 macroparticles, gamma = 5000, 74 mm mrad (1.7 mrad), 0.01 % spread
+        npart = 200000
+        pcfg = dict(cfg, driver=wl.PARTICLES, max_particles=npart)
+        lat = Lattice(pcfg)
+        lat.set_bunch(wl.bunch(pcfg, npart, gamma=5000.0, emittance=1.7e-3 * 5000.0 * cfg["sigma_r"],
+                               energy_spread=1e-4, seed=11))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(n)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        r["seconds_particle_driver"] = e0.elapsed_time(e1) / 1e3
+        r["particles_lost"] = int((lat.bunch()[6] == 0.0).sum())
+        r["nonfinite_particle_driver"] = int(lat.diagnostics()["nonfinite"])
+        lat.close()
+        res[f"alpha_{alpha}"] = r
+        print(f"[P] alpha={alpha}: {ev:.2f} s rigid, {r['seconds_particle_driver']:.2f} s with {npart} "
+              f"particles, for {n} steps", file=sys.stderr, flush=True)
     return res
 
 
