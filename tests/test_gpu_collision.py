@@ -180,6 +180,22 @@ def test_adjoint_gradient_matches_oracle_autograd(coll):
     assert np.abs(g32 - gref).max() < 1e-4 * np.abs(gref).max(), (g32, gref)
 
 
+@pytest.mark.parametrize("coll", ["trt_quarter", "regularised", "mrt"])
+def test_revolve_matches_uniform_checkpointing(coll):
+    """Binomial checkpointing with 3 snapshots gives the gradient of the uniform schedule (37
+    steps on the 128 x 32 copy, window shifts included) and leaves the lattice at step 0."""
+    from paper_2201_05473_amd import Lattice
+    cfg = adjoint_wake_cfg(coll)
+    n = 37
+    J0, g0 = Lattice(cfg).adjoint(n, 6, z_behind=cfg["z_behind"])
+    lat = Lattice(cfg)
+    J, g, adv = lat.adjoint_revolve(n, 3, z_behind=cfg["z_behind"])
+    print(f"[collision revolve] {coll} forward steps {adv}", flush=True)
+    assert lat.counters() == (0, 0)
+    assert abs(J - J0) <= 1e-13 * abs(J0)
+    assert np.abs(g - g0).max() <= 1e-11 * np.abs(g0).max(), (g, g0)
+
+
 @pytest.mark.parametrize("coll", list(COLLISIONS))
 def test_adjoint_fd_c4(coll):
     """C4 at full size (1024 x 256, 2,000 steps, FP32 storage, checkpoints every 45 steps) with
