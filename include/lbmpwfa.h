@@ -3,9 +3,10 @@
  *
  * The library advances the plasma-electron fluid of G. Parise et al., "Lattice Boltzmann
  * simulations of Plasma Wakefield Acceleration" (arXiv:2201.05473) on an axisymmetric (z, r)
- * grid: three D2Q9 BGK lattices for A = (n, n p_z, n p_r) (Sec. III, Eqs. (6)-(14)) coupled to
- * Maxwell's equations on a Yee grid (Sec. II, Eq. (5)), driven by a rigid bi-Gaussian electron
- * bunch moving at c, on a window that moves with the driver (Sec. II, last paragraph).
+ * grid: three D2Q9 lattices for A = (n, n p_z, n p_r) (Sec. III, Eqs. (6)-(14); BGK collision, or
+ * one of the operators of lbm_config.collision) coupled to Maxwell's equations on a Yee grid
+ * (Sec. II, Eq. (5)), driven by a rigid bi-Gaussian electron bunch moving at c or by a
+ * macroparticle bunch, on a window that moves with the driver (Sec. II, last paragraph).
  *
  * Units are normalised plasma units: t omega_p, x k_p, n / n_0, p / (m_e c),
  * e E / (m_e c omega_p), e B / (m_e omega_p), c = 1.

@@ -12,9 +12,11 @@
 // identity map for the adjoint).
 //
 // Population adjoints are carried in "pulled" form: f_bar^k(y, q) is the adjoint of the population
-// that site y pulls in step k (the collision input).  The collision's VJP has rank-3 structure,
-// f_bar^k(y, q) = (1 - 1/tau) g_bar^{k+1}(y, q) + A_bar_kk(y) (kk = lattice of q), and the adjoint of
-// the stored population is its transposed pull, g_bar^k(x, q) = f_bar^k(x + xi_q, q).  So each
+// that site y pulls in step k (the collision input).  Every collision operator is linear in the
+// pulled populations apart from the equilibrium, g' = P f + (I - P) f_eq + w dt F, so its VJP is
+// f_bar^k(y, .) = P^T g_bar^{k+1}(y, .) + A_bar_kk(y) (kk = lattice of q; BGK: P = (1 - 1/tau) I,
+// which gives rank-3 structure), and the adjoint of the stored population is its transposed
+// pull, g_bar^k(x, q) = f_bar^k(x + xi_q, q).  So each
 // reverse step reads and writes the 27 population planes once, exactly like the forward step.
 // Gather form throughout: every output has a single writer, no atomics, fixed summation order.
 //
