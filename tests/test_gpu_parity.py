@@ -69,6 +69,36 @@ def test_fp64_parity_variants(name):
     assert errs.max() < TOL64, (errs.argmax(), errs.max())
 
 
+SMALL_GRIDS = {
+    "3x3_window": dict(nz=3, nr=3, moving_window=1),
+    "3x3_periodic_zr_cartesian": dict(nz=3, nr=3, periodic=3, fields_on=0, cyl_on=0),
+    "64x4_one_tile": dict(nz=64, nr=4),
+    "65x5_window": dict(nz=65, nr=5, moving_window=1),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL_GRIDS))
+def test_small_grids(name):
+    """The smallest grids the library takes (3 x 3), exactly one 64 x 4 tile, and one site past a
+    tile in both directions, 10 steps (two window shifts where the window is on), with noise and
+    random momentum: FP64 to 1e-10; FP32 and FP16 storage on the moments and fields (max-norm per
+    group) to 1e-5 and 5e-2."""
+    cfg = wl.config(None, dz=0.05, dr=0.05, nb=0.05, sigma_z=0.3, sigma_r=0.3, zd0=0.1,
+                    noise_amp=1e-3, seed=11, storage=wl.F64, **SMALL_GRIDS[name])
+    pert = wl.density_perturbation(cfg)
+    pinit = wl.random_momentum(cfg, 0.05, seed=3)
+    S, P = O.run(cfg, 10, pert, pinit)
+    ref = oracle_state(S, P)
+    for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-5), (wl.F16, 5e-2)):
+        print(f"[small grid] {name} storage={storage} 10 steps", flush=True)
+        lat = run_gpu(dict(cfg, storage=storage), 10, pert, pinit)
+        st, k, s = lat.state()
+        assert (k, s) == (S.k, S.s)
+        errs = comp_errors(st, ref)
+        assert (errs if storage == wl.F64 else errs[27:]).max() < tol, (storage, errs.argmax(), errs.max())
+        lat.close()
+
+
 def test_fp64_parity_c1_full_run():
     """C1 (256 x 64, tau 0.8, weak driver, +-1e-6 noise), all 500 steps, every state value."""
     cfg = wl.config("C1")
