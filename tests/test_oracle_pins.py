@@ -789,3 +789,114 @@ def test_free_particle_moves_exactly_and_is_lost_at_the_window_edge():
     assert float(S.bunch[6, 1]) == 0.0        # the backward particle left through the rear edge
     z1 = float(S.bunch[2, 1])
     assert 0.15 <= z1 < 0.15 + 0.02           # frozen where its midpoint stencil still fit column 1
+
+
+# ---------------------------------------------------------------------------------------------
+# FP64 diagnostics (charge of Sec. IV's set-up, field energy of Eq. (5)'s fields on the Yee grid
+# of reading R12, Gauss residual of reading R18) against closed forms.  Each sum is checked on a
+# state where only one term is non-zero, so a missing 2 pi, a power of dz, or r_edge in place of
+# r (or the reverse) changes one of the results by a factor.
+# ---------------------------------------------------------------------------------------------
+
+def _diag_state(nz=13, nr=7, h=0.05, **cfg_extra):
+    cfg = wl.config(None, nz=nz, nr=nr, dz=h, dr=h, nb=0.0, **cfg_extra)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    return S, P
+
+
+@pytest.mark.parametrize("n0", [1.0, 0.37])
+def test_diagnostic_charge_of_uniform_plasma(n0):
+    """Uniform density n0 on nr x nz cells: sum_j 2 pi (j + 1/2) dr dr dz nz n0 and
+    sum_j (2 j + 1) = nr^2 give pi (nr dr)^2 (nz dz) n0, the volume of the cylinder."""
+    nz, nr, h = 13, 7, 0.05
+    S, P = _diag_state(nz, nr, h, n0=n0)
+    d = O.diagnostics(S, P)
+    exact = math.pi * (nr * h) ** 2 * (nz * h) * n0
+    assert abs(d["charge"] - exact) <= 1e-13 * exact
+    assert d["field_energy"] == 0.0 and d["umax"] == 0.0 and d["nonfinite"] == 0
+
+
+def test_diagnostic_energy_of_uniform_axial_field():
+    """E_z = e everywhere (E_z lives on the fluid rows r_j = (j + 1/2) dr): the energy is
+    1/2 e^2 times the cylinder's volume pi (nr dr)^2 (nz dz)."""
+    nz, nr, h, e = 11, 6, 0.04, 0.3
+    S, P = _diag_state(nz, nr, h)
+    S.Ez = torch.full((nr, nz), e, dtype=F64)
+    d = O.diagnostics(S, P)
+    exact = 0.5 * e * e * math.pi * (nr * h) ** 2 * (nz * h)
+    assert abs(d["field_energy"] - exact) <= 1e-13 * exact
+
+
+@pytest.mark.parametrize("which", ["Er", "B"])
+def test_diagnostic_energy_of_uniform_edge_field(which):
+    """E_r = b (or B_theta = b) everywhere: both live on the edges r = (j + 1) dr, so the energy is
+    1/2 b^2 sum_j 2 pi (j + 1) dr^3 nz = 1/2 b^2 pi dr^3 nz nr (nr + 1), not the cylinder's
+    volume (which E_z on the rows (j + 1/2) dr would give)."""
+    nz, nr, h, b = 9, 5, 0.07, -0.8
+    S, P = _diag_state(nz, nr, h)
+    S.Er = torch.zeros(nr, nz, dtype=F64)
+    S.B = torch.zeros(nr, nz, dtype=F64)
+    setattr(S, which, torch.full((nr, nz), b, dtype=F64))
+    d = O.diagnostics(S, P)
+    exact = 0.5 * b * b * math.pi * h ** 3 * nz * nr * (nr + 1)
+    assert abs(d["field_energy"] - exact) <= 1e-13 * exact
+    cyl = 0.5 * b * b * math.pi * (nr * h) ** 2 * (nz * h)
+    assert abs(d["field_energy"] - cyl) > 0.1 * exact
+
+
+@pytest.mark.parametrize("pz,pr", [(0.3, 0.0), (2.0, -1.5), (0.0, 0.05)])
+def test_diagnostic_umax_of_uniform_momentum(pz, pr):
+    """Uniform momentum p: beta = |p| / sqrt(1 + |p|^2) (Eq. (2)), lattice speed
+    (c dt / dz) |beta| (reading R6)."""
+    nz, nr = 10, 4
+    cfg = wl.config(None, nz=nz, nr=nr, dz=0.05, dr=0.05, nb=0.0)
+    P = O.Params(cfg)
+    p_init = np.stack([np.full((nr, nz), pz), np.full((nr, nz), pr)])
+    S = O.initial_state(P, None, p_init)
+    d = O.diagnostics(S, P)
+    p2 = pz * pz + pr * pr
+    exact = cfg["c_dt_over_dz"] * math.sqrt(p2 / (1.0 + p2))
+    assert abs(d["umax"] - exact) <= 1e-14
+
+
+def test_diagnostic_gauss_residual_of_linear_fields():
+    """Reading R18 defines the residual as div_h E - (n_bg - n - n_b) with the finite-volume
+    divergence of the Yee grid.  E_r = a r_edge / 2 on the edges has discrete divergence exactly a
+    on every row, the axis row included (((j + 1)^2 - j^2) a dr / 2 over (j + 1/2) dr), and
+    E_z = b (i + 1/2) dz has d/dz exactly b.  With n = n_bg the residual is a + b everywhere it
+    is defined (columns i >= 1); with n = n_bg - a - b it vanishes."""
+    nz, nr, h, a, b = 12, 6, 0.05, 0.7, -0.25
+    S, P = _diag_state(nz, nr, h)
+    S.Er = (a * 0.5 * P.r_edge).expand(nr, nz).clone()
+    S.Ez = (b * (P.ii + 0.5) * h).expand(nr, nz).clone()
+    S.B = torch.zeros(nr, nz, dtype=F64)
+    G = O.gauss_residual(S, P)
+    assert G.shape == (nr, nz - 1)
+    assert torch.allclose(G, torch.full_like(G, a + b), rtol=0, atol=1e-13)
+    assert abs(O.diagnostics(S, P)["gauss_max"] - abs(a + b)) <= 1e-13
+    S.M = S.M.clone()
+    S.M[0] = S.M[0] - (a + b)
+    assert float(O.gauss_residual(S, P).abs().max()) <= 1e-13
+
+
+def test_diagnostic_gauss_residual_counts_the_driver():
+    """The driver's density enters the residual with the electrons' sign (both are electrons):
+    a state with no field, n = n_bg and a driver gives residual n_b at each site (i >= 1)."""
+    nz, nr, h = 12, 6, 0.05
+    cfg = wl.config(None, nz=nz, nr=nr, dz=h, dr=h, nb=0.4, sigma_z=0.1, sigma_r=0.1, zd0=0.3)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    S.Ez = torch.zeros(nr, nz, dtype=F64)
+    S.Er = torch.zeros(nr, nz, dtype=F64)
+    G = O.gauss_residual(S, P)
+    nb = O.driver_density(P.ii * h, P.r, -P.dt, P)
+    assert torch.allclose(G, nb[:, 1:], rtol=0, atol=1e-14)
+
+
+def test_diagnostic_counts_nonfinite_values():
+    S, P = _diag_state()
+    assert O.diagnostics(S, P)["nonfinite"] == 0
+    S.Ez = S.Ez.clone()
+    S.Ez[2, 3] = float("nan")
+    assert O.diagnostics(S, P)["nonfinite"] == 1
