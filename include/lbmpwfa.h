@@ -180,12 +180,17 @@ int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init,
 int lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Moments of the last step's post-collision state, [3][nr][nz]: n, J_z = n beta_z,
- * J_r = n beta_r.  dtype LBM_F64 or LBM_F32.  dst on the device (stream-ordered) or on the host
- * (synchronising). */
+ * J_r = n beta_r.  n is the zeroth moment of the density lattice (Eq. (8)) after the source of the
+ * step (A* = A + dt F); J = n beta is the electron current density J_e of Eq. (5), with
+ * beta = p / gamma from the zeroth moments of the momentum lattices (Eq. (2); zero at or below
+ * n_floor).  dtype LBM_F64 or LBM_F32.  dst on the device (stream-ordered) or on the host
+ * (synchronising).  LBM_EINVAL for a NULL dst or another dtype. */
 int lbm_moments(lbm_ctx* ctx, void* dst, int32_t dtype, int32_t dst_on_device);
 
-/* Fields of the state, [3][nr][nz]: E_z at t_{k-1}, E_r at t_{k-1}, B_theta at t_{k-1/2} after k
- * steps, on their staggered positions.  dtype and placement as lbm_moments. */
+/* Fields of the state, [3][nr][nz]: the E_z, E_r, B_theta of Maxwell's equations (Eq. (5)) on
+ * the radially half-shifted Yee grid (the paper names an FDTD/Yee scheme without its layout):
+ * E_z at (z_i + dz/2, r_j), E_r at (z_i, (j + 1) dr), B_theta at (z_i + dz/2, (j + 1) dr); E at
+ * t_{k-1} and B_theta at t_{k-1/2} after k steps.  dtype and placement as lbm_moments. */
 int lbm_fields(lbm_ctx* ctx, void* dst, int32_t dtype, int32_t dst_on_device);
 
 /* Full state in FP64 on the host: [27][nr][nz] populations (lattice-major, raw values, not
@@ -270,7 +275,20 @@ int lbm_adjoint_revolve(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, 
                         void* adj_ws, size_t adj_bytes, double* J, double grad[4],
                         int64_t* steps_advanced);
 
-/* FP64 diagnostics of the current state (deterministic two-pass reduction).  Synchronising. */
+/* The objective J of lbm_adjoint for the current state, without its gradient: E_z of row obj->row
+ * linearly interpolated in z at z_d(t_{k-1}) - obj->z_behind after k >= 1 steps (the time level of
+ * E in the state), z_d the driver centre.  Equals the J that lbm_adjoint returns after the same
+ * steps.  LBM_EINVAL for a row outside [0, nr) or a position outside the window, LBM_ESTATE before
+ * the first step.  Synchronising. */
+int lbm_witness(lbm_ctx* ctx, const lbm_objective* obj, double* J);
+
+/* FP64 diagnostics of the current state (the sums of lbm_diag above; deterministic two-pass
+ * reduction).  The charge is the electron number of the window, the quantity the moving-window
+ * set-up of Sec. IV conserves apart from inflow and outflow; the field energy is that of the
+ * fields of Eq. (5) on the Yee points; the Gauss residual checks Gauss's law, which the paper does
+ * not state and the scheme keeps only at t = 0 (the initial field is the driver's discrete Gauss
+ * field), since J_e = n beta of Eq. (5) leaves out the lattice's diffusive flux.  LBM_ESTATE for a
+ * NULL context, LBM_EINVAL for a NULL out.  Synchronising. */
 int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 
 /* Bubble length (Sec. IV, Fig. 4): the number of sites of row `row` at lab positions z in

@@ -12,8 +12,10 @@ THETA_NAMES = ("ramp_len", "n0", "sigma_r", "nb")
 class LbmWake(torch.autograd.Function):
     """forward(theta, cfg, nsteps, ckpt_every, n_pert, z_behind, row) -> J (FP64 scalar).
 
-    The forward pass runs lbm_adjoint (forward with checkpoints, reverse sweep), so backward only
-    scales the stored gradient: dL/dtheta = dL/dJ * dJ/dtheta."""
+    When theta needs a gradient, the forward pass runs lbm_adjoint (forward with checkpoints,
+    reverse sweep), so backward only scales the stored gradient: dL/dtheta = dL/dJ * dJ/dtheta.
+    Otherwise (no_grad, or theta without requires_grad) it runs the plain forward steps and
+    evaluates the same objective with lbm_witness, at the cost of a forward run."""
 
     @staticmethod
     def forward(ctx, theta, cfg, nsteps, ckpt_every, n_pert, z_behind, row):
@@ -22,7 +24,11 @@ class LbmWake(torch.autograd.Function):
         for name, v in zip(THETA_NAMES, th.tolist()):
             c[name] = v
         lat = Lattice(c, n_pert)
-        J, grad = lat.adjoint(int(nsteps), ckpt_every, float(z_behind), int(row))
+        if ctx.needs_input_grad[0]:
+            J, grad = lat.adjoint(int(nsteps), ckpt_every, float(z_behind), int(row))
+        else:
+            lat.step(int(nsteps))
+            J, grad = lat.witness(float(z_behind), int(row)), [float("nan")] * 4
         lat.close()
         ctx.save_for_backward(torch.as_tensor(grad, dtype=torch.float64))
         ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device

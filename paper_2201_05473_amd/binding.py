@@ -100,6 +100,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "lbm_adjoint_revolve_workspace_bytes": (c_int32, [P(LbmConfig), c_int32, P(c_size_t)]),
         "lbm_adjoint_revolve": (c_int32, [c_void_p, P(LbmObjective), c_int64, c_int32, c_void_p, c_size_t,
                                           P(c_double), c_void_p, P(c_int64)]),
+        "lbm_witness": (c_int32, [c_void_p, P(LbmObjective), P(c_double)]),
         "lbm_bubble_length": (c_int32, [c_void_p, c_int32, c_double, c_double, c_double, P(c_int64),
                                         P(c_double)]),
         "lbm_set_bunch": (c_int32, [c_void_p, c_int64, c_void_p, c_int32]),
@@ -254,6 +255,13 @@ def lbm_adjoint(ctx: int, z_behind: float, row: int, nsteps: int, ckpt_every: in
                                       c_void_p(ws_ptr), c_size_t(ws_bytes), ctypes.byref(J),
                                       grad.ctypes.data_as(c_void_p)))
     return J.value, grad
+
+
+def lbm_witness(ctx: int, z_behind: float, row: int) -> float:
+    obj = LbmObjective(float(z_behind), int(row))
+    J = c_double(0.0)
+    _check(load_library().lbm_witness(c_void_p(ctx), ctypes.byref(obj), ctypes.byref(J)))
+    return J.value
 
 
 def lbm_adjoint_revolve_workspace_bytes(cfg: dict | LbmConfig, snapshots: int) -> int:
@@ -412,6 +420,10 @@ class Lattice:
         nbytes = lbm_adjoint_revolve_workspace_bytes(self.cfg, snapshots)
         buf, ptr = self._scratch(nbytes)
         return lbm_adjoint_revolve(self.ctx, z_behind, row, nsteps, snapshots, ptr, nbytes)
+
+    def witness(self, z_behind: float = 4.0, row: int = 0) -> float:
+        """The adjoint's objective J for the current state (no gradient)."""
+        return lbm_witness(self.ctx, z_behind, row)
 
     def bubble_length(self, row: int = 0, n_star: float = 0.95, z_from: float = -math.inf,
                       z_to: float = math.inf):

@@ -190,6 +190,9 @@ struct lbm_ctx {
   // caller's index of each stored particle (the bunch is stored by column of z, then radius)
   long long nbunch = 0;
   int jcur = 0;
+  // set when a failed lbm_adjoint_revolve could not put the initial state back into the context's
+  // buffers (which it uses as scratch); cleared by lbm_set_state / lbm_load
+  bool broken = false;
   std::vector<int64_t> order;
   double* bunch() { return (double*)(ws + L.bunch); }
   void* jb(int b) { return ws + L.jb[b]; }
@@ -205,6 +208,15 @@ struct lbm_ctx {
 };
 
 namespace {
+
+// LBM_ESTATE for a NULL context or one whose state was lost (see lbm_ctx::broken).
+int live(const lbm_ctx* c) {
+  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (c->broken)
+    return fail(LBM_ESTATE, "the context's state was lost by a failed lbm_adjoint_revolve; "
+                            "restore a state with lbm_set_state or lbm_load");
+  return LBM_OK;
+}
 
 // Driver density at the nodes (z_i, r_j) and t_{k-1} for the Gauss residual: the particle bunch
 // deposited from its positions (which are at t_{k-1}) into the FP64 density plane, or nullptr for
@@ -300,7 +312,7 @@ int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init, 
 }
 
 int lbm_step(lbm_ctx* c, int64_t nsteps) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   // particle driver: the push of a step and the move of the next run as one launch between two
   // steps of this call (not across a diagnostic check, which reads the bunch at t_{k-1}); moved:
@@ -356,7 +368,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
 }
 
 static int output3(lbm_ctx* c, void* dst, int32_t dtype, int32_t on_device, bool moments) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!dst) return fail(LBM_EINVAL, "dst is NULL");
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
   const int f64 = dtype == LBM_F64;
@@ -382,7 +394,7 @@ int lbm_fields(lbm_ctx* c, void* dst, int32_t dtype, int32_t dst_on_device) {
 }
 
 int lbm_get_state(lbm_ctx* c, double* dst, int64_t* step, int64_t* shifts) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!dst) return fail(LBM_EINVAL, "dst is NULL");
   const size_t pl = (size_t)c->p.nr * c->p.nz;
   double* stage = (double*)c->staging();
@@ -419,6 +431,7 @@ int lbm_set_state(lbm_ctx* c, const double* src, int64_t step, int64_t shifts) {
   }
   c->k = step;
   c->s = shifts;
+  c->broken = false;
   return LBM_OK;
 }
 
@@ -439,14 +452,14 @@ size_t region_bytes(const lbm_ctx* c, int which) {
 }  // namespace
 
 int lbm_checkpoint_bytes(lbm_ctx* c, size_t* bytes) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
   *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + 2 * region_bytes(c, 1);
   return LBM_OK;
 }
 
 int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!dst) return fail(LBM_EINVAL, "dst is NULL");
   CkptHeader h;
   std::memset(&h, 0, sizeof h);
@@ -507,11 +520,12 @@ int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   c->k = h.step;
   c->s = h.shifts;
+  c->broken = false;
   return LBM_OK;
 }
 
 int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   const double* drv;
   HIP_CHECK(driver_density_plane(c, &drv), "bunch density launch");
@@ -589,7 +603,7 @@ StateView state_at(char* base, const Physics& p, int storage) {
 }
 
 int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!ws) return fail(LBM_EINVAL, "adjoint workspace is NULL");
   if ((uintptr_t)ws % 256 != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
   if (bytes < need) return fail(LBM_ENOMEM, "adjoint workspace too small: %zu < %zu bytes", bytes, need);
@@ -670,7 +684,7 @@ int lbm_vjp_workspace_bytes(const lbm_config* cfg, size_t* bytes) {
 }
 
 int lbm_vjp_step(lbm_ctx* c, void* ws, size_t bytes, const double* lam_next, double* lam_out, double grad[4]) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   const AdjLayout L = adj_layout(c->p, c->storage);
   int rc = adj_check(c, ws, bytes, L.vjp_total);
   if (rc) return rc;
@@ -696,7 +710,7 @@ int lbm_vjp_step(lbm_ctx* c, void* ws, size_t bytes, const double* lam_next, dou
 }
 
 int lbm_vjp_init(lbm_ctx* c, void* ws, size_t bytes, const double* lam0, double grad[4]) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   const AdjLayout L = adj_layout(c->p, c->storage);
   int rc = adj_check(c, ws, bytes, L.vjp_total);
   if (rc) return rc;
@@ -732,9 +746,8 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
   return LBM_OK;
 }
 
-int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every, void* ws,
-                size_t bytes, double* J, double grad[4]) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+static int adjoint_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every, void* ws,
+                       size_t bytes, double* J, double grad[4]) {
   if (!obj || !J || !grad) return fail(LBM_EINVAL, "NULL argument");
   if (nsteps < 1 || ckpt_every < 1) return fail(LBM_EINVAL, "nsteps and ckpt_every must be >= 1");
   if (c->k != 0) return fail(LBM_ESTATE, "lbm_adjoint needs the context at its initial state (step 0)");
@@ -909,6 +922,22 @@ int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ck
   return LBM_OK;
 }
 
+int lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t ckpt_every, void* ws,
+                size_t bytes, double* J, double grad[4]) {
+  if (int rc_ = live(c)) return rc_;
+  const int rc = adjoint_run(c, obj, nsteps, ckpt_every, ws, bytes, J, grad);
+  if (rc != LBM_OK) {
+    // work queued before the failure may still be running on either stream and writing into the
+    // caller's workspace: wait for it, so the caller can free the workspace on return (the
+    // context's own state, x^0, is only read by this call)
+    const std::string msg = g_err;
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamSynchronize(c->stream);
+    g_err = msg;
+  }
+  return rc;
+}
+
 // ------------------------------------------------------------------------------------------
 // Adjoint with a snapshot budget: binomial (revolve-type) checkpointing.
 // ------------------------------------------------------------------------------------------
@@ -1046,9 +1075,10 @@ int lbm_adjoint_revolve_workspace_bytes(const lbm_config* cfg, int32_t snapshots
   return LBM_OK;
 }
 
-int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t snapshots, void* ws,
-                        size_t bytes, double* J, double grad[4], int64_t* steps_advanced) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+// *snap0 is set once snapshot 0 (a copy of the context's state) is queued: from then on the
+// context's buffers are scratch and must be restored from it.
+static int revolve_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t snapshots, void* ws,
+                       size_t bytes, double* J, double grad[4], int64_t* steps_advanced, bool* snap0) {
   if (!obj || !J || !grad) return fail(LBM_EINVAL, "NULL argument");
   if (nsteps < 1 || snapshots < 1) return fail(LBM_EINVAL, "nsteps and snapshots must be >= 1");
   if (c->k != 0) return fail(LBM_ESTATE, "lbm_adjoint_revolve needs the context at its initial state (step 0)");
@@ -1089,6 +1119,7 @@ int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, in
   HIP_CHECK(hipMemcpyAsync(x0.g, ctx0.g, gbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
   HIP_CHECK(hipMemcpyAsync(x0.M, ctx0.M, mbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
   HIP_CHECK(hipMemcpyAsync(x0.E, ctx0.E, mbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
+  *snap0 = true;
   HIP_CHECK(hipMemsetAsync(r.w, 0, L.core_total, c->stream), "clear");
   {
     const size_t ab = aux_bytes(c->storage);
@@ -1118,9 +1149,65 @@ int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, in
   return LBM_OK;
 }
 
+int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int32_t snapshots, void* ws,
+                        size_t bytes, double* J, double grad[4], int64_t* steps_advanced) {
+  if (int rc_ = live(c)) return rc_;
+  bool snap0 = false;
+  const int rc = revolve_run(c, obj, nsteps, snapshots, ws, bytes, J, grad, steps_advanced, &snap0);
+  if (rc != LBM_OK) {
+    // drain what was queued, then put the initial state back from snapshot 0; if that fails too,
+    // the context refuses further use until a state is set or loaded
+    const std::string msg = g_err;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (snap0) {
+      const Physics& p = c->p;
+      const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
+      const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
+      const StateView x0 = state_at((char*)ws + adj_layout(p, c->storage).core_total, p, c->storage);
+      if (e == hipSuccess) e = hipMemcpyAsync(c->g(c->cur), x0.g, gbytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(c->M(c->cur), x0.M, mbytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(c->E(c->cur), x0.E, mbytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) c->broken = true;
+    }
+    g_err = msg;
+  }
+  return rc;
+}
+
+int lbm_witness(lbm_ctx* c, const lbm_objective* obj, double* J) {
+  if (int rc_ = live(c)) return rc_;
+  if (!obj || !J) return fail(LBM_EINVAL, "NULL argument");
+  const Physics& p = c->p;
+  if (c->k < 1) return fail(LBM_ESTATE, "the witness needs at least one step (E at t_{k-1})");
+  if (obj->row < 0 || obj->row >= p.nr) return fail(LBM_EINVAL, "objective row out of range");
+  // E^{k-1} at z_d(t_{k-1}) - z_behind, in the window's frame after s shifts
+  const double zstar = p.zd0 + (double)(c->k - 1) * p.dt - obj->z_behind;
+  const double xw = zstar / p.h - (double)c->s - 0.5;
+  const double fl = std::floor(xw);
+  if (!(fl >= 0.0 && fl < (double)(p.nz - 1))) return fail(LBM_EINVAL, "witness position outside the window");
+  const long long iw = (long long)fl;
+  const double ww = xw - fl;
+  const size_t ab = aux_bytes(c->storage);
+  const char* ez = (const char*)c->E(c->cur) + ((size_t)obj->row * p.pitch + (size_t)iw) * ab;
+  double e[2];
+  if (ab == 8) {
+    HIP_CHECK(hipMemcpyAsync(e, ez, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+  } else {
+    float f[2];
+    HIP_CHECK(hipMemcpyAsync(f, ez, 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream), "download");
+    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+    e[0] = f[0];
+    e[1] = f[1];
+  }
+  *J = (1.0 - ww) * e[0] + ww * e[1];
+  return LBM_OK;
+}
+
 int lbm_bubble_length(lbm_ctx* c, int32_t row, double n_star, double z_from, double z_to, int64_t* count,
                       double* length) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (!count) return fail(LBM_EINVAL, "count is NULL");
   if (row < 0 || row >= c->p.nr) return fail(LBM_EINVAL, "row out of range");
   if (!(n_star > 0.0) || !std::isfinite(n_star)) return fail(LBM_EINVAL, "n_star must be positive");
@@ -1186,7 +1273,7 @@ int lbm_get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
 namespace {
 
 int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (c->p.driver != LBM_DRIVER_PARTICLES) return fail(LBM_EINVAL, "the bunch needs driver = LBM_DRIVER_PARTICLES");
   if (n < 0 || n > c->p.cap) return fail(LBM_EINVAL, "n must lie in [0, max_particles] (got %lld)", (long long)n);
   if (n > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
@@ -1242,7 +1329,7 @@ int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
 }
 
 int get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
-  if (!c) return fail(LBM_ESTATE, "context is NULL");
+  if (int rc_ = live(c)) return rc_;
   if (c->p.driver != LBM_DRIVER_PARTICLES) return fail(LBM_EINVAL, "the bunch needs driver = LBM_DRIVER_PARTICLES");
   if (!n) return fail(LBM_EINVAL, "n is NULL");
   if (n_max < c->nbunch) return fail(LBM_EINVAL, "n_max %lld < %lld particles", (long long)n_max, c->nbunch);

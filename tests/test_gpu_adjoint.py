@@ -121,11 +121,13 @@ def wake_cfg(storage=wl.F64):
 
 
 def test_adjoint_gradient_matches_oracle_autograd():
-    """lbm_adjoint (forward with checkpoints every 7 steps, ragged last segment, reverse sweep,
-    initial state) on 128 x 32 for 60 steps against autograd through the FP64 oracle."""
+    """lbm_adjoint (forward with checkpoints every 14 steps, ragged last segment of 4, reverse
+    sweep, initial state) on the 128 x 32 copy of C4 for its whole run, 200 steps (40 window
+    shifts), against autograd through the FP64 oracle."""
     from paper_2201_05473_amd import Lattice
     cfg = wake_cfg()
-    n, ck = 60, 7
+    n, ck = cfg["nsteps"], 14
+    assert n == 200 and n % ck != 0
     lat = Lattice(cfg)
     J, grad = lat.adjoint(n, ck, z_behind=cfg["z_behind"], row=0)
     th = theta_of(cfg)
@@ -177,20 +179,34 @@ def test_autograd_function_backward():
     J2, g2 = lat.adjoint(40, 9, z_behind=cfg["z_behind"])
     assert abs(float(J) - J2) <= 1e-15 * abs(J2)
     assert np.allclose(theta.grad.numpy(), 3.0 * g2, rtol=1e-14, atol=0)
+    # without a gradient the objective comes from plain forward steps and lbm_witness
+    with torch.no_grad():
+        J3 = wake_objective(theta, cfg, 40, 9, z_behind=cfg["z_behind"])
+    assert not J3.requires_grad
+    assert abs(float(J3) - J2) <= 1e-12 * abs(J2), (float(J3), J2)
+    J4 = wake_objective(theta.detach(), cfg, 40, 9, z_behind=cfg["z_behind"])
+    assert abs(float(J4) - float(J3)) == 0.0
+    # lbm_witness after plain steps equals the witness of the oracle after the same steps
+    lat = Lattice(cfg)
+    lat.step(40)
+    P = O.Params(cfg)
+    S = O.initial_state(P)
+    for _ in range(40):
+        S = O.step(S, P)
+    Jref = float(O.objective(S, P, cfg["z_behind"]))
+    assert abs(lat.witness(cfg["z_behind"]) - Jref) <= 1e-12 * abs(Jref)
+    lat.close()
 
 
 def gpu_objective(cfg, nsteps, z_behind, row=0):
-    """J from a forward run: E_z on the row, linearly interpolated at z_d(t_{N-1}) - z_behind."""
+    """J from a forward run (lbm_witness): E_z on the row, linearly interpolated at
+    z_d(t_{N-1}) - z_behind."""
     from paper_2201_05473_amd import Lattice
     lat = Lattice(cfg)
     lat.step(nsteps)
-    ez = lat.fields()[0, row].cpu().numpy()
-    k, s = lat.counters()
-    h, dt = cfg["dz"], cfg["dz"] * cfg["c_dt_over_dz"]
-    x = (cfg["zd0"] + (k - 1) * dt - z_behind) / h - s - 0.5
-    i0 = int(np.floor(x))
-    w = x - i0
-    return (1 - w) * ez[i0] + w * ez[i0 + 1]
+    J = lat.witness(z_behind, row)
+    lat.close()
+    return J
 
 
 def test_adjoint_fd_c4():
@@ -275,3 +291,38 @@ def test_reduced_storage_adjoint_matches_oracle(coll, storage, m64):
     err = np.abs(grad - gref).max() / np.abs(gref).max()
     print(f"  grad {grad} oracle {gref} rel {err:.2e}", flush=True)
     assert err < (1e-5 if storage == wl.F32 else 1e-2), (grad, gref)
+
+
+def test_revolve_fd_c5_full_grid():
+    """C5's full grid and driver (8192 x 2048, dz = 0.02, FP32 storage, tanh ramp of the
+    seed-drawn length), shortened to 1,500 steps with the ramp started 8/k_p behind the driver so
+    that the witness sits in a wake that depends on all four parameters.  Binomial checkpointing
+    with 4 snapshots (the recursion nests 3 levels deep: beta(3, t) < 1,500 for t <= 18) against
+    central finite differences (h = 1e-4) of FP64 forward runs, for all four parameters."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config("C5")
+    n, zb = 1500, cfg["z_behind"]
+    cfg.update(ramp_start=cfg["zd0"] - 8.0)
+    lat = Lattice(cfg)
+    print(f"[C5] revolve, {n} steps, 4 snapshots, ramp_len {cfg['ramp_len']:.3f}", flush=True)
+    J, grad, adv = lat.adjoint_revolve(n, 4, z_behind=zb)
+    assert lat.counters() == (0, 0)
+    lat.close()
+    print(f"[C5] J {J:.9e}, forward steps taken {adv}", flush=True)
+    # more forward steps than three snapshots allow with fewer advances per step
+    assert adv > 2 * n
+    cfg64 = dict(cfg, storage=wl.F64)
+    J64 = gpu_objective(cfg64, n, zb)
+    fd = np.zeros(4)
+    hstep = 1e-4
+    for a, nm in enumerate(NAMES):
+        cp, cm = dict(cfg64), dict(cfg64)
+        cp[nm] += hstep
+        cm[nm] -= hstep
+        fd[a] = (gpu_objective(cp, n, zb) - gpu_objective(cm, n, zb)) / (2 * hstep)
+        print(f"[C5] fd {nm} {fd[a]:.9e} adjoint {grad[a]:.9e}", flush=True)
+    rel = np.abs(grad - fd) / np.abs(fd)
+    print("C5 J32", J, "J64", J64, "adjoint", grad, "fd", fd, "rel", rel, flush=True)
+    assert abs(J - J64) < 1e-4 * abs(J64)
+    assert np.all(np.abs(fd) > 1e-6), fd
+    assert rel.max() < 1e-4, rel
