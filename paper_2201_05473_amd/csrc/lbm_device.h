@@ -12,9 +12,8 @@ namespace lbm {
 // Precision modes: population storage S, arithmetic C, auxiliary (moments, fields) storage A.
 // ------------------------------------------------------------------------------------------
 // C: arithmetic of the fluid phase; CF: arithmetic of the field phase and of the moment halo
-// (LDS tiles).  M64 selects FP64 arithmetic for FP32 / FP16 storage: FP64 vector FMAs issue at
-// the FP32 rate here (packed FP32 is not used), so exact-in-FP64 collision sums cost little in
-// this memory-bound kernel, while FP32 collision sums leak ~1e-8 of mass per site and step.
+// (LDS tiles).  M64 selects FP64 arithmetic for FP32 / FP16 storage (FP64 vector FMAs issue at
+// the FP32 rate here, since packed FP32 is not used).
 template <int ST, bool M64> struct Mode;
 template <bool M64> struct Mode<0, M64> { using S = double; using C = double; using A = double; using CF = double; };
 template <> struct Mode<1, false> { using S = float;  using C = float;  using A = float;  using CF = float; };
@@ -73,6 +72,30 @@ __host__ __device__ constexpr int MB_NORM2(int m) {
   for (int q = 0; q < 9; ++q) sum += MB(m, q) * MB(m, q);
   return sum;
 }
+
+// Sum of the eight moving equilibria of a lattice, from which the rest population's equilibrium
+// is taken as the moment minus the sum (equal to Eq. (9) in exact arithmetic).  COMP: Kahan's
+// compensated sum in the arithmetic type T, so that the difference is as close to the exact one as
+// a sum in twice the precision would give (the running compensation c is the part of the sum lost
+// to rounding so far, and the true sum is s - c).  The FP32 step uses it: a plain FP32 sum rounds
+// with errors that are correlated between neighbouring sites and steps, and the drift of the
+// density and momentum moments they cause grows over a run.
+template <typename T, bool COMP>
+struct EqSum {
+  T s = T(0), c = T(0);
+  __device__ __forceinline__ void add(T x) {
+    if (COMP) {
+      const T y = x - c;
+      const T t = s + y;
+      c = (t - s) - y;
+      s = t;
+    } else {
+      s += x;
+    }
+  }
+  // m minus the sum
+  __device__ __forceinline__ T rest(T m) const { return COMP ? (m - s) + c : m - s; }
+};
 
 // Equilibrium of direction q (Eq. (9), standard D2Q9 coefficients) for the three lattices at
 // moments with density deviation d0 from n_bg (density m0 = n_bg + d0), momenta a1, a2 and lattice

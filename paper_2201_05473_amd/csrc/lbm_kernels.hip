@@ -1,8 +1,8 @@
 // HIP kernels (gfx950) of the lattice-Boltzmann plasma-wakefield step.
 //
 // One launch per time step: the fused kernel first advances the Yee fields of its tile (plus a
-// one-cell halo, recomputed from LDS) and then performs the pull-stream / collision (BGK, or TRT or regularised) of the
-// three D2Q9 lattices of its sites.  Notation and step order follow the paper (Parise et al.,
+// one-cell halo, recomputed from LDS) and then performs the pull-stream / collision (BGK, TRT,
+// regularised or MRT) of the three D2Q9 lattices of its sites.  Notation and step order follow the paper (Parise et al.,
 // arXiv:2201.05473): Eq. (5) for the fields, Eqs. (6)-(10), (13), (14) for the lattices; the
 // readings where the paper is silent are stated at each use.
 #include <hip/hip_fp16.h>
@@ -37,9 +37,10 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
   using C = typename Mode<ST, M64>::C;
   using A = typename Mode<ST, M64>::A;
   using CF = typename Mode<ST, M64>::CF;
-  // sums of the eight moving equilibria: FP64, except for FP16 storage, whose error is set by its
-  // storage and whose step is instruction-bound (FP64 sums cost it 6 %)
-  using SE = typename std::conditional<ST >= 2, C, double>::type;
+  // sums of the eight moving equilibria: compensated for FP32 storage with FP32 arithmetic; plain
+  // in FP64, and for FP16 storage, whose error is set by its storage and whose step is
+  // instruction-bound
+  using SE = EqSum<C, ST == 1 && !M64>;
   constexpr bool NEQ = neq_storage(ST);   // populations stored off their site's equilibrium
   const Physics& p = a.p;
   constexpr int MZ = TZ + 2, MR = TR + 2;    // moments:  cols i0-1..i0+TZ,   rows j0-1..j0+TR
@@ -435,11 +436,11 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
   const C itau = (C)(1.0 / p.tau);
   if (COLL == 0) {
     // BGK, Eq. (7).  The rest population's equilibrium is taken as the moment minus the other
-    // eight (equal to Eq. (9) in exact arithmetic), their sum accumulated in FP64 (type SE) and
-    // the difference rounded once, so that the equilibrium's zeroth moments are the moments
-    // themselves to half an ulp.  In FP32 the rounding of the equilibria would
-    // otherwise drift the density and momentum moments over many steps.
-    SE se0 = 0, se1 = 0, se2 = 0;
+    // eight (equal to Eq. (9) in exact arithmetic; EqSum), so that the equilibrium's zeroth
+    // moments are the moments themselves to about an ulp.  Otherwise the rounding of the
+    // equilibria (and of the weights 1/9, 1/36 in FP32) would drift the density and momentum
+    // moments over many steps.
+    SE se0, se1, se2;
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q);
@@ -448,23 +449,23 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
       const C e0 = w * (dA0 + A0 * Q);
       const C e1 = w * A1 * (C(1) + Q);
       const C e2 = w * A2 * (C(1) + Q);
-      se0 += e0;
-      se1 += e1;
-      se2 += e2;
+      se0.add(e0);
+      se1.add(e1);
+      se2.add(e2);
       const C wdt = w * dtc;
       put(q, f0[q] - (f0[q] - e0) * itau + wdt * F0);
       put(9 + q, f1[q] - (f1[q] - e1) * itau + wdt * F1);
       put(18 + q, f2[q] - (f2[q] - e2) * itau + wdt * F2);
     }
     const C wdt = WQ<C>(0) * dtc;
-    put(0, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itau + wdt * F0);
-    put(9, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itau + wdt * F1);
-    put(18, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itau + wdt * F2);
+    put(0, f0[0] - (f0[0] - se0.rest(dA0)) * itau + wdt * F0);
+    put(9, f1[0] - (f1[0] - se1.rest(A1)) * itau + wdt * F1);
+    put(18, f2[0] - (f2[0] - se2.rest(A2)) * itau + wdt * F2);
   } else if (COLL == 1) {
     // two relaxation times: the even part of f - f_eq relaxes with 1/tau_plus, the odd part
     // (which carries the flux and so sets D) with 1/tau.  The rest population is even.
     const C itp = (C)(1.0 / p.tau_plus);
-    SE se0 = 0, se1 = 0, se2 = 0;   // equilibria of the eight moving directions
+    SE se0, se1, se2;   // equilibria of the eight moving directions
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int q = t < 2 ? 1 + t : 5 + (t - 2);   // 1, 2, 5, 6
@@ -473,9 +474,9 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
       const C cu = (C)XZ(q) * uz + (C)XR(q) * ur;
       const C ev = C(4.5) * cu * cu - C(1.5) * usq;
       const C od = C(3) * cu;
-      se0 += C(2) * w * (dA0 + A0 * ev);
-      se1 += C(2) * w * A1 * (C(1) + ev);
-      se2 += C(2) * w * A2 * (C(1) + ev);
+      se0.add(C(2) * w * (dA0 + A0 * ev));
+      se1.add(C(2) * w * A1 * (C(1) + ev));
+      se2.add(C(2) * w * A2 * (C(1) + ev));
       {
         const C re = (C(0.5) * (f0[q] + f0[b]) - w * (dA0 + A0 * ev)) * itp;
         const C ro = (C(0.5) * (f0[q] - f0[b]) - w * A0 * od) * itau;
@@ -497,9 +498,9 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     }
     // the rest population (even): its equilibrium is the moment minus the other eight, as for BGK
     const C wdt = WQ<C>(0) * dtc;
-    put(0, f0[0] - (f0[0] - (C)((SE)dA0 - se0)) * itp + wdt * F0);
-    put(9, f1[0] - (f1[0] - (C)((SE)A1 - se1)) * itp + wdt * F1);
-    put(18, f2[0] - (f2[0] - (C)((SE)A2 - se2)) * itp + wdt * F2);
+    put(0, f0[0] - (f0[0] - se0.rest(dA0)) * itp + wdt * F0);
+    put(9, f1[0] - (f1[0] - se1.rest(A1)) * itp + wdt * F1);
+    put(18, f2[0] - (f2[0] - se2.rest(A2)) * itp + wdt * F2);
   } else if (COLL == 3) {
     // multiple relaxation times: f - f_eq expanded in the orthogonal moments MB, each relaxed with
     // its rate (the fluxes with 1/tau, so D is that of BGK; the density moment of f - f_eq is
@@ -517,13 +518,13 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     // equilibrium is w (dA0 + A0 Q)), F its source
     auto relax = [&](int k, const C (&f)[9], C mom, C F) {
       C e[9];
-      SE sum = 0;
+      SE sum;
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
         e[q] = k == 0 ? WQ<C>(q) * (dA0 + A0 * Qq[q]) : WQ<C>(q) * mom * (C(1) + Qq[q]);
-        sum += e[q];
+        sum.add(e[q]);
       }
-      e[0] = (C)((SE)mom - sum);
+      e[0] = sum.rest(mom);
       C c[9];
 #pragma unroll
       for (int m = 1; m < 9; ++m) {
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     jr1 = k3 * (jr1 - A1 * ur);
     jz2 = k3 * (jz2 - A2 * uz);
     jr2 = k3 * (jr2 - A2 * ur);
-    SE se0 = 0, se1 = 0, se2 = 0;   // equilibria of the eight moving directions
+    SE se0, se1, se2;   // equilibria of the eight moving directions
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q), wdt = w * dtc;
@@ -578,18 +579,18 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
       const C Q = C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
       const C xz = (C)XZ(q), xr = (C)XR(q);
       const C e0 = w * (dA0 + A0 * Q), e1 = w * A1 * (C(1) + Q), e2 = w * A2 * (C(1) + Q);
-      se0 += e0;
-      se1 += e1;
-      se2 += e2;
+      se0.add(e0);
+      se1.add(e1);
+      se2.add(e2);
       put(q, e0 + w * (xz * jz0 + xr * jr0) + wdt * F0);
       put(9 + q, e1 + w * (xz * jz1 + xr * jr1) + wdt * F1);
       put(18 + q, e2 + w * (xz * jz2 + xr * jr2) + wdt * F2);
     }
     // the rest population (no first-order part): the moment minus the other eight, as for BGK
     const C wdt = WQ<C>(0) * dtc;
-    put(0, (C)((SE)dA0 - se0) + wdt * F0);
-    put(9, (C)((SE)A1 - se1) + wdt * F1);
-    put(18, (C)((SE)A2 - se2) + wdt * F2);
+    put(0, se0.rest(dA0) + wdt * F0);
+    put(9, se1.rest(A1) + wdt * F1);
+    put(18, se2.rest(A2) + wdt * F2);
   }
   stv(Mout + oo, mo0);   // density moment stored as the deviation from n_bg
   stv(Mout + plane + oo, mo1);

@@ -222,13 +222,14 @@ def test_fp32_fp16_parity_c2_copy():
     E_z is not a near-cancellation residual), FP32 and FP16 storage against the FP64 oracle
     after 400 steps: max-norm relative error of n, E_z, E_r.
 
-    Bounds.  Density: 1e-5 with FP32 arithmetic (measured 5e-8), 1e-7 with FP64 arithmetic (the
-    collision then conserves mass to FP64 round-off).  Fields: the FP32 storage of populations and
-    fields alone puts E_z near 1e-5 on this short case (FP64 arithmetic on FP32 storage, where the
-    arithmetic adds nothing: 9.9e-6); that storage floor is bounded by 2e-5, and the FP32-arithmetic
-    field error by twice the floor (measured 7.9e-6 for E_z, 3.8e-6 for E_r).  The equilibrium's
-    zeroth moments are exact, so the FP32-arithmetic error stays at the floor over long runs too
-    (C2, 10,000 steps: E_z 5.9e-6).  FP16 storage: 5e-3 (11-bit significand of the stored
+    Bounds.  Density with FP32 arithmetic: 1e-5 (measured 4e-8); with FP64 arithmetic on FP32
+    storage 1e-7 (the collision then conserves mass to FP64 round-off).  Fields: on this young wake
+    the FP32 storage of E_r and B_theta sets a floor near 1e-5 for E_z.  Rounding only those two
+    fields to FP32 after every step of the oracle gives E_z 1.0e-5, rounding only the populations
+    and moments 3e-8, rounding E_z alone 6e-7; FP64 arithmetic on FP32 storage measures 9.9e-6 on
+    the GPU.  So the FP32-arithmetic fields are held to 1.5e-5 and to 1.5 times that floor
+    (measured 1.27e-5 for E_z with compensated FP32 equilibrium sums; a plain FP32 sum gave
+    2.0e-5).  FP16 storage: 5e-3 (11-bit significand of the stored
     deviations).  FP16N storage (the part off each site's equilibrium in FP16): fields 5e-4 and
     density 5e-5 (measured 1.4e-4 / 2.2e-4 / 1.4e-5), and at most a quarter of FP16's field error
     (measured a tenth)."""
@@ -249,8 +250,8 @@ def test_fp32_fp16_parity_c2_copy():
     f32, floor = errs[(wl.F32, 0)], errs[(wl.F32, 1)]
     assert f32["n"] < 1e-5 and floor["n"] < 1e-7, errs
     for q in ("Ez", "Er"):
-        assert floor[q] < 2e-5, errs
-        assert f32[q] < 2.0 * floor[q], (q, errs)
+        assert floor[q] < 1.5e-5, (q, errs)
+        assert f32[q] < 1.5e-5 and f32[q] < 1.5 * floor[q], (q, errs)
     for key in ((wl.F16, 0), (wl.F16, 1)):
         assert max(errs[key].values()) < 5e-3, errs
     for m64 in (0, 1):
