@@ -83,39 +83,84 @@ def rel_err(a, b) -> float:
     return float((a - b).abs().max()) / den if den > 0 else float((a - b).abs().max())
 
 
-def cpu_baseline(sample_steps: int = 60) -> dict:
+def c2_copy_with_wake() -> dict:
+    """C2's 1/16 copy (512 x 128, same dz, driver and tau) with the plasma ramp moved onto the
+    driver, so that a wake exists after a few hundred steps."""
+    import workloads as wl
+    cfg = wl.config("C2s", storage=wl.F64)
+    cfg.update(ramp_start=cfg["zd0"] - 3.0, ramp_len=1.0)
+    return cfg
+
+
+def cpu_baseline(sample_steps: int = 60, copy_steps: int = 400) -> dict:
     """The FP64 oracle, as it stands, on the host cores: C2 at full size for sample_steps steps
-    (about 10 s on 16 cores)."""
+    (about 10 s on 16 cores).  Then the oracle on C2's 1/16 copy with a wake (c2_copy_with_wake,
+    copy_steps steps), against which the GPU's FP32 and FP64 runs of the same copy are compared
+    (max-norm error of n, E_z, E_r relative to the oracle's max-norm)."""
     import torch
 
     import workloads as wl
     from oracle import lbm_oracle as O
+    from paper_2201_05473_amd import Lattice
     cfg = wl.config("C2", storage=0)
     P = O.Params(cfg)
-    S = O.initial_state(P)
-    S = O.step(S, P)   # untimed first step (allocator warm-up)
+    S = O.step(O.initial_state(P), P)   # untimed first step (allocator warm-up)
     t0 = time.perf_counter()
     for _ in range(sample_steps):
         S = O.step(S, P)
     dt = time.perf_counter() - t0
-    return {"value": P.nz * P.nr * sample_steps / dt / 1e6, "unit": "MLUPS",
-            "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"C2 2048x512 FP64 oracle (torch CPU), {sample_steps} step(s) after one untimed step"}
+    threads = torch.get_num_threads()
+    out = {"value": P.nz * P.nr * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+           "threads": threads, "host_cpus": os.cpu_count(), "kind": "oracle",
+           "sample": f"C2 2048x512 FP64 oracle (torch CPU, {threads} threads), {sample_steps} step(s) "
+                     "after one untimed step"}
+    ccfg = c2_copy_with_wake()
+    S, P = O.run(ccfg, copy_steps)
+    ref = {"n": S.M[0], "Ez": S.Ez, "Er": S.Er}
+    errs = {"workload": "C2's 1/16 copy, 512x128, ramp moved onto the driver", "steps": copy_steps}
+    for name, storage in (("f32", wl.F32), ("f64", wl.F64)):
+        lat = Lattice(dict(ccfg, storage=storage))
+        lat.step(copy_steps)
+        st, _, _ = lat.state()
+        lat.close()
+        errs[name] = {"n": O.rel_err(st[27], ref["n"]), "Ez": O.rel_err(st[30], ref["Ez"]),
+                      "Er": O.rel_err(st[31], ref["Er"])}
+    out["err_vs_oracle_C2_copy"] = errs
+    return out
+
+
+def mode_errors(cfg: dict, steps: int, modes) -> dict:
+    """Max-norm error of E_z, E_r and n of each (name, storage, fp64_math) mode against the FP64
+    run of the same workload after `steps` untimed steps (relative to the FP64 run's max-norm)."""
+    import workloads as wl
+    from paper_2201_05473_amd import Lattice
+
+    def run(storage, m64):
+        lat = Lattice(dict(cfg, storage=storage, fp64_math=m64))
+        lat.step(steps)
+        f, m = lat.fields(), lat.moments()
+        lat.close()
+        return f, m
+
+    f64_f, f64_m = run(wl.F64, 0)
+    out = {}
+    for name, storage, m64 in modes:
+        if storage == wl.F64:
+            continue
+        fl, mo = run(storage, m64)
+        out[name] = {"Ez": rel_err(fl[0], f64_f[0]), "Er": rel_err(fl[1], f64_f[1]), "n": rel_err(mo[0], f64_m[0])}
+    return out
 
 
 def objective_f64(cfg: dict, nsteps: int, z_behind: float, row: int = 0) -> float:
-    """J from a plain forward run: E_z on the row, linearly interpolated at z_d(t_{N-1}) - z_behind."""
+    """J from a plain forward run (lbm_witness): E_z on the row, linearly interpolated at
+    z_d(t_{N-1}) - z_behind."""
     from paper_2201_05473_amd import Lattice
     lat = Lattice(cfg)
     lat.step(nsteps)
-    ez = lat.fields()[0, row].double().cpu().numpy()
-    k, s = lat.counters()
+    J = lat.witness(z_behind, row)
     lat.close()
-    h, dt = cfg["dz"], cfg["dz"] * cfg["c_dt_over_dz"]
-    x = (cfg["zd0"] + (k - 1) * dt - z_behind) / h - s - 0.5
-    i0 = int(x // 1)
-    w = x - i0
-    return (1 - w) * ez[i0] + w * ez[i0 + 1]
+    return J
 
 
 def adjoint_c4(ckpt_every: int = 45) -> dict:
@@ -372,11 +417,17 @@ def main():
 
     # headline: FP32 storage
     wall, ev_s, lat32 = time_run(cfg, steps, warmup)
+    lat32.close()
     mlups = sites * steps / wall / 1e6
     kern_s = ev_s / steps
     bps = bytes_per_site(wl.F32)
     achieved = bps * sites / kern_s / 1e9
     traffic = measured_traffic("C2", wl.F32)
+    # the error clause of the metric: C2's own length (10,000 steps), untimed, whatever --steps is
+    err_steps = cfg["nsteps"]
+    modes_list = (("f32", wl.F32, 0), ("f64", wl.F64, 0), ("f32_fp64math", wl.F32, 1),
+                  ("f16", wl.F16, 0), ("f16n", wl.F16N, 0))
+    errs = mode_errors(cfg, err_steps, modes_list if not args.no_extra else modes_list[:2])
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
@@ -385,6 +436,9 @@ def main():
                                "populations, linear entrance ramp 10/k_p, driver n_b/n0=0.1 "
                                "sigma_z=1 sigma_r=0.5, moving window",
                    "sites": sites, "lattice_LUPS_factor": 3},
+        "err_vs_f64": dict(errs["f32"], steps=err_steps,
+                           note="FP32 storage and arithmetic against the FP64 run of the same workload, "
+                                "max-norm relative to the FP64 max-norm, after C2's full run (untimed)"),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "traffic_unit": "bytes/launch",
@@ -393,20 +447,15 @@ def main():
     }
 
     if not args.no_extra:
-        # the other storage / arithmetic modes at the same workload and step count, with the
-        # max-norm error of E_z, E_r and n against the FP64 run
-        ref_f = lat32.fields()
-        ref_m = lat32.moments()
-        lat32.close()
-        runs = {"f32": (wl.F32, 0, wall, ev_s, ref_f, ref_m)}
-        for name, storage, m64 in (("f64", wl.F64, 0), ("f32_fp64math", wl.F32, 1),
-                                   ("f16", wl.F16, 0), ("f16n", wl.F16N, 0)):
+        # the other storage / arithmetic modes: throughput over --steps timed steps, and the
+        # max-norm error of E_z, E_r and n against the FP64 run after C2's full run (untimed)
+        runs = {"f32": (wl.F32, 0, wall, ev_s)}
+        for name, storage, m64 in modes_list[1:]:
             w, e, lat = time_run(dict(cfg, storage=storage, fp64_math=m64), steps, warmup)
-            runs[name] = (storage, m64, w, e, lat.fields(), lat.moments())
+            runs[name] = (storage, m64, w, e)
             lat.close()
-        f64_f, f64_m = runs["f64"][4], runs["f64"][5]
         modes = {}
-        for name, (storage, m64, w, e, fl, mo) in runs.items():
+        for name, (storage, m64, w, e) in runs.items():
             b = bytes_per_site(storage)
             modes[name] = {
                 "storage": {0: "f64", 1: "f32", 2: "f16", 3: "f16n"}[storage],
@@ -415,9 +464,7 @@ def main():
                 "alg_GBps": b * sites / (e / steps) / 1e9,
                 "frac_of_peak": b * sites / (e / steps) / 1e9 / PEAK_HBM_GBS,
                 "bytes_per_site": b,
-                "err_vs_f64": None if name == "f64" else {
-                    "Ez": rel_err(fl[0], f64_f[0]), "Er": rel_err(fl[1], f64_f[1]),
-                    "n": rel_err(mo[0], f64_m[0])},
+                "err_vs_f64": None if name == "f64" else dict(errs[name], steps=err_steps),
             }
         out["modes_C2"] = modes
         # HBM-scale lattice (C3, 4096 x 1024, working set well above the 256 MB Infinity Cache)

@@ -15,17 +15,34 @@ HIPCC_FLAGS = (
 )
 
 
+OBJ_DIR = os.path.join(os.path.dirname(HERE), "_build")
+
+
 def build(verbose: bool = False) -> str:
-    """Compile the library; returns its path.  Raises CalledProcessError on failure."""
+    """Compile the library (one object per source, compiled in parallel, then linked); returns its
+    path.  Raises CalledProcessError on failure."""
     os.makedirs(LIB_DIR, exist_ok=True)
+    os.makedirs(OBJ_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+        cmd = [hipcc, *flags, "-c", "-o", obj, os.path.join(HERE, src)]
+        jobs.append((cmd, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    objs = []
+    for cmd, obj, proc in jobs:
+        out, err = proc.communicate()
+        if proc.returncode != 0:
+            raise subprocess.CalledProcessError(proc.returncode, cmd, out, err)
+        if verbose and err:
+            print(err)
+        objs.append(obj)
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *[os.path.join(HERE, s) for s in SOURCES]]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise subprocess.CalledProcessError(res.returncode, cmd, res.stdout, res.stderr)
-    if verbose and res.stderr:
-        print(res.stderr)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
