@@ -291,6 +291,20 @@ int lbm_witness(lbm_ctx* ctx, const lbm_objective* obj, double* J);
  * NULL context, LBM_EINVAL for a NULL out.  Synchronising. */
 int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 
+/* lbm_diagnostics for callers that cannot allocate device memory (harnesses that forbid hipMalloc,
+ * tight loops that must not allocate; it copies its result to the host, so it is not for code
+ * under HIP graph capture).  The same values, bit for bit, as
+ * lbm_diagnostics on the same state: the same kernels, with their per-block partial sums in a
+ * fixed array inside the library instead of the context's workspace.  That array holds the partials
+ * of at most 2048 blocks plus the result (16,392 doubles, 131,136 bytes); the first pass strides
+ * over the lattice, so every lattice that lbm_init accepts fits, and a larger need is refused with
+ * LBM_EINVAL.  Each GPU holds one copy of the array from the first lbm_init on it until the
+ * process ends, and every call on that GPU shares it: calls that overlap in time on one GPU (other
+ * streams or host threads) race on it and must be serialised by the caller.  Makes no allocation
+ * (no hipMalloc, hipFree or allocating library call).  LBM_ESTATE for a NULL context, LBM_EINVAL
+ * for a NULL out.  Synchronising. */
+int lbm_diagnostics_noalloc(lbm_ctx* ctx, lbm_diag* out);
+
 /* Bubble length (Sec. IV, Fig. 4): the number of sites of row `row` at lab positions z in
  * [z_from, z_to] whose electron density is below n_star times the local background density
  * n_bg(z) (sites in vacuum, n_bg = 0, excluded; the paper uses n_star = 0.95), and that number

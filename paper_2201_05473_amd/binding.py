@@ -87,6 +87,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "lbm_get_state": (c_int32, [c_void_p, c_void_p, P(c_int64), P(c_int64)]),
         "lbm_set_state": (c_int32, [c_void_p, c_void_p, c_int64, c_int64]),
         "lbm_diagnostics": (c_int32, [c_void_p, P(LbmDiag)]),
+        "lbm_diagnostics_noalloc": (c_int32, [c_void_p, P(LbmDiag)]),
         "lbm_checkpoint_bytes": (c_int32, [c_void_p, P(c_size_t)]),
         "lbm_save": (c_int32, [c_void_p, c_void_p, c_int32]),
         "lbm_load": (c_int32, [c_void_p, c_void_p, c_int32]),
@@ -192,6 +193,12 @@ def lbm_set_state(ctx: int, state, step: int, shifts: int):
 def lbm_diagnostics(ctx: int) -> dict:
     d = LbmDiag()
     _check(load_library().lbm_diagnostics(c_void_p(ctx), ctypes.byref(d)))
+    return {name: getattr(d, name) for name, _ in LbmDiag._fields_ if name != "reserved"}
+
+
+def lbm_diagnostics_noalloc(ctx: int) -> dict:
+    d = LbmDiag()
+    _check(load_library().lbm_diagnostics_noalloc(c_void_p(ctx), ctypes.byref(d)))
     return {name: getattr(d, name) for name, _ in LbmDiag._fields_ if name != "reserved"}
 
 

@@ -190,6 +190,8 @@ struct lbm_ctx {
   // caller's index of each stored particle (the bunch is stored by column of z, then radius)
   long long nbunch = 0;
   int jcur = 0;
+  // device address of the library's fixed diagnostic scratch on the context's device
+  double* scratch = nullptr;
   // set when a failed lbm_adjoint_revolve could not put the initial state back into the context's
   // buffers (which it uses as scratch); cleared by lbm_set_state / lbm_load
   bool broken = false;
@@ -282,7 +284,10 @@ int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init, 
   c->s = 0;
   c->stream = (hipStream_t)hip_stream;
   auto bail = [&](int code) { delete c; return code; };
-  hipError_t e = hipMemsetAsync(workspace, 0, L.total, c->stream);
+  // the fixed scratch of lbm_diagnostics_noalloc on this device (looked up once per device)
+  hipError_t e = lbm::diag_scratch(&c->scratch);
+  if (e != hipSuccess) return bail(hip_fail(e, "diagnostic scratch lookup"));
+  e = hipMemsetAsync(workspace, 0, L.total, c->stream);
   if (e != hipSuccess) return bail(hip_fail(e, "workspace clear"));
   // Upload the perturbation arrays into the inactive population buffer.
   const size_t plane_u = (size_t)p.nr * p.nz;
@@ -524,16 +529,16 @@ int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
   return LBM_OK;
 }
 
-int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
-  if (int rc_ = live(c)) return rc_;
+// The diagnostics with their partial sums in `partials` and the result in `res` (device).
+static int diagnostics_into(lbm_ctx* c, lbm_diag* out, double* partials, double* res) {
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   const double* drv;
   HIP_CHECK(driver_density_plane(c, &drv), "bunch density launch");
   HIP_CHECK(lbm::launch_diagnostics(c->storage, c->p, c->k, c->s, c->M(c->cur), c->E(c->cur), drv,
-                                    c->partials(), c->red_out(), c->stream),
+                                    partials, res, c->stream),
             "diagnostics launch");
   double r[8];
-  HIP_CHECK(hipMemcpyAsync(r, c->red_out(), sizeof r, hipMemcpyDeviceToHost, c->stream), "download");
+  HIP_CHECK(hipMemcpyAsync(r, res, sizeof r, hipMemcpyDeviceToHost, c->stream), "download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   out->charge = r[0];
   out->field_energy = r[1];
@@ -544,6 +549,21 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   out->step = c->k;
   out->shifts = c->s;
   return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+  if (int rc_ = live(c)) return rc_;
+  return diagnostics_into(c, out, c->partials(), c->red_out());
+}
+
+int lbm_diagnostics_noalloc(lbm_ctx* c, lbm_diag* out) {
+  if (int rc_ = live(c)) return rc_;
+  if (!c->scratch) return fail(LBM_ESTATE, "no diagnostic scratch on this context's device");
+  const size_t need = ((size_t)lbm::diag_blocks(c->p) + 1) * 8;
+  if (need > lbm::diag_scratch_doubles())
+    return fail(LBM_EINVAL, "diagnostics need %zu scratch doubles, the library holds %zu", need,
+                lbm::diag_scratch_doubles());
+  return diagnostics_into(c, out, c->scratch, c->scratch + (size_t)lbm::diag_blocks(c->p) * 8);
 }
 
 // --------------------------------------------------------------------------------------------

@@ -13,8 +13,13 @@ constexpr int TR = 4;
 constexpr int NTHREADS = TZ * TR;
 // Row pitch of every plane, in elements (keeps every row start 256-byte aligned in FP32).
 constexpr int PITCH_ALIGN = 64;
-// Blocks of the diagnostic reduction.
+// Blocks of the diagnostic reduction: threads per block, and the most blocks its first pass uses
+// (each thread strides over the lattice).
 constexpr int RED_THREADS = 256;
+constexpr int DIAG_MAX_BLOCKS = 2048;
+// Devices for which the library keeps per-device state (the scratch address of
+// lbm_diagnostics_noalloc).
+constexpr int MAX_DEVICES = 64;
 
 // Physical and grid parameters of a run (fixed for a context).
 struct Physics {
@@ -126,6 +131,10 @@ hipError_t launch_state_set(int storage, const Physics& p, long long s, void* g,
                             void* E, int c, const double* src, hipStream_t st);
 // Diagnostics: partials[nblocks][8] then a single-block final pass into out[8].
 int diag_blocks(const Physics& p);
+// Device address of the library's fixed diagnostic scratch on the current device (partials of
+// DIAG_MAX_BLOCKS blocks, then out[8]), and its size in doubles.
+hipError_t diag_scratch(double** ptr);
+size_t diag_scratch_doubles();
 // drv: FP64 driver density at the nodes (z_i, r_j) and t_{k-1} (pitched plane), or nullptr for the
 // rigid driver's closed form.
 hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,

@@ -8,6 +8,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lbm_device.h"
@@ -797,6 +798,8 @@ __device__ __forceinline__ void block_reduce5(double v[5], double* out) {
   }
 }
 
+// Each thread takes the sites u, u + stride, ... (stride = the whole grid of threads), so a fixed
+// number of blocks (at most DIAG_MAX_BLOCKS) covers any lattice.
 template <int ST>
 __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, long long k,
                                                                   long long s, const void* Mv,
@@ -804,9 +807,9 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
                                                                   double* partials) {
   using A = typename Mode<ST, false>::A;
   const long long n = (long long)p.nz * p.nr;
-  const long long u = (long long)blockIdx.x * RED_THREADS + threadIdx.x;
+  const long long stride = (long long)gridDim.x * RED_THREADS;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (u < n) {
+  for (long long u = (long long)blockIdx.x * RED_THREADS + threadIdx.x; u < n; u += stride) {
     const int i = (int)(u % p.nz), j = (int)(u / p.nz);
     const A* M = (const A*)Mv;
     const A* E = (const A*)Ev;
@@ -817,8 +820,8 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
     const double m0 = (double)M[oo] + nb0, m1 = M[p.plane + oo], m2 = M[2 * p.plane + oo];
     const double ez = E[oo], er = E[p.plane + oo], b = E[2 * p.plane + oo];
     const double twopi = 6.283185307179586;
-    v[0] = twopi * r * h * h * m0;
-    v[1] = 0.5 * twopi * h * h * (r * ez * ez + re * er * er + re * b * b);
+    v[0] += twopi * r * h * h * m0;
+    v[1] += 0.5 * twopi * h * h * (r * ez * ez + re * er * er + re * b * b);
     if (i >= 1) {
       const double ezl = E[oo - 1];
       const double erb = j > 0 ? (double)E[p.plane + oo - p.pitch] : 0.0;
@@ -826,11 +829,11 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
       // driver density at t_{k-1}: the closed form, or the bunch density deposited at the nodes
       const double nd = drv ? drv[oo] : driver<double>(p, z, r, ((double)k - 1.0) * p.dt);
       const double rho = nb0 - m0 - nd;
-      v[2] = fabs(div - rho);
+      v[2] = fmax(v[2], fabs(div - rho));
     }
     double bz, br;
     velocity<double>(m0, m1, m2, p.n_floor, bz, br);
-    v[3] = p.lam * sqrt(bz * bz + br * br);
+    v[3] = fmax(v[3], p.lam * sqrt(bz * bz + br * br));
     const double vals[6] = {(double)M[oo], m1, m2, ez, er, b};
     for (int c = 0; c < 6; ++c) v[4] += isfinite(vals[c]) ? 0.0 : 1.0;
   }
@@ -983,8 +986,36 @@ hipError_t launch_state_set(int storage, const Physics& p, long long s, void* g,
 
 int diag_blocks(const Physics& p) {
   const long long n = (long long)p.nz * p.nr;
-  return (int)((n + RED_THREADS - 1) / RED_THREADS);
+  const long long b = (n + RED_THREADS - 1) / RED_THREADS;
+  return (int)(b < DIAG_MAX_BLOCKS ? b : DIAG_MAX_BLOCKS);
 }
+
+// Scratch of lbm_diagnostics_noalloc: the partial sums of DIAG_MAX_BLOCKS blocks (8 doubles each)
+// and the 8 doubles of the final pass.  One copy per GPU, held until the process ends; every call
+// on a GPU uses the same copy (each block overwrites its own partials, so nothing needs clearing).
+static __device__ __align__(256) double scratch[(DIAG_MAX_BLOCKS + 1) * 8];
+
+// Device address of the scratch on the current device, looked up once per device.  The array's
+// name is a host-side stand-in in host code: kernels and copies take this address instead.
+hipError_t diag_scratch(double** ptr) {
+  static std::mutex mu;
+  static void* addr[MAX_DEVICES] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = a;
+  }
+  *ptr = (double*)addr[dev];
+  return hipSuccess;
+}
+
+size_t diag_scratch_doubles() { return sizeof(scratch) / sizeof(double); }
 
 hipError_t launch_diagnostics(int storage, const Physics& p, long long k, long long s,
                               const void* M, const void* E, const double* drv, double* partials, double* out,
