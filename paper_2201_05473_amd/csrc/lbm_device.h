@@ -141,6 +141,60 @@ __device__ __forceinline__ bool velocity(C n, C a1, C a2, C floor_, C& bz, C& br
   br = pr * ig;
   return true;
 }
+// FP32: beta = p / sqrt(1 + p^2) with p = a / n is a / sqrt(n^2 + a^2) for n > 0, which needs one
+// hardware reciprocal square root (1 ulp) and no division.  n > n_floor > 0 keeps n^2 normal for any
+// floor above 1e-19.
+template <>
+__device__ __forceinline__ bool velocity<float>(float n, float a1, float a2, float floor_, float& bz, float& br) {
+  if (!(n > floor_)) { bz = 0.f; br = 0.f; return false; }
+  const float ig = __builtin_amdgcn_rsqf(n * n + a1 * a1 + a2 * a2);
+  bz = a1 * ig;
+  br = a2 * ig;
+  return true;
+}
+
+// Buffer accesses.  A plane (or any array) is addressed through a buffer resource in scalar
+// registers (its base and size, uniform) and a 32-bit byte offset per lane, so no lane computes a
+// 64-bit address; an access past the resource's size reads zero and writes nothing.  Word 3 of
+// the resource is the raw-buffer format of the gfx9 family.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc brsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+// cache policy of a load: 0 default, 2 non-temporal
+template <int POL = 0> __device__ __forceinline__ float bld(float*, Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL));
+}
+template <int POL = 0> __device__ __forceinline__ double bld(double*, Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, POL));
+}
+template <int POL = 0> __device__ __forceinline__ __half bld(__half*, Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, POL));
+}
+// load of element `idx` of an array of T through resource r
+template <typename T, int POL = 0> __device__ __forceinline__ T bload(Rsrc r, uint32_t idx) {
+  return bld<POL>((T*)nullptr, r, idx * (uint32_t)sizeof(T));
+}
+// store of v, rounded to the storage type T (round to nearest even), to element idx
+__device__ __forceinline__ void bput(double*, Rsrc r, uint32_t idx, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                        (int)(idx * 8u), 0, 0);
+}
+__device__ __forceinline__ void bput(float*, Rsrc r, uint32_t idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(idx * 4u), 0, 0);
+}
+__device__ __forceinline__ void bput(float*, Rsrc r, uint32_t idx, double v) { bput((float*)nullptr, r, idx, (float)v); }
+__device__ __forceinline__ void bput(__half*, Rsrc r, uint32_t idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, (int)(idx * 2u), 0, 0);
+}
+__device__ __forceinline__ void bput(__half*, Rsrc r, uint32_t idx, double v) { bput((__half*)nullptr, r, idx, (float)v); }
+template <typename T, typename V> __device__ __forceinline__ void bstore(Rsrc r, uint32_t idx, V v) {
+  bput((T*)nullptr, r, idx, v);
+}
+// resource over plane c of a group of planes of `plane` elements of T starting at base
+template <typename T> __device__ __forceinline__ Rsrc plane_rsrc(const void* base, long long plane, int c) {
+  return brsrc((const T*)base + (long long)c * plane, (uint32_t)(plane * (long long)sizeof(T)));
+}
 
 // Population loads of the step: FP64 populations are read with non-temporal loads (measured on
 // MI355X: FP64 step 110 -> 96.5 us on 2048 x 512; the same for FP32 loads is 25 % slower, so

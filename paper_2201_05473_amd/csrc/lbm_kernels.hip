@@ -28,12 +28,13 @@ namespace lbm {
 // PER = false: the grid is known not to be periodic, and the wrap code is compiled out.
 // DRV = 1: the driver current J_b comes from the particle bunch's deposit (a.jb_in, z and r
 // components) in place of the rigid driver's closed form.
-// FP16 storage (2, 3) with FP32 arithmetic is instruction-bound: 7 blocks per CU (7 waves per
-// SIMD, at most 72 VGPRs, 2 to 7 of them spilled) measured 3 % (FP16) and 8 % (FP16N) faster on
-// 2048 x 512 than the 6 that its 78 / 82 VGPRs allow.  FP32 and FP64 gain nothing from it, and
-// FP64 arithmetic needs twice the registers.
+// Occupancy.  With FP32 arithmetic the halo goes straight to LDS, so a thread holds little more
+// than its 27 populations: FP32 storage fits 64 VGPRs without spills (8 waves per SIMD), except
+// MRT, whose moment transform needs more (6 blocks).  FP16 storage keeps its bound of 7 blocks
+// (FP16N with MRT spills a few registers under it and still runs faster than at 6).  FP64
+// arithmetic needs about twice the registers and takes the compiler's choice.
 template <int ST, bool FIELDS, bool M64, bool SITE, int COLL, bool PER, int DRV>
-__global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (COLL == 3 ? 6 : 8))) void step_kernel(StepArgs a) {
   using S = typename Mode<ST, M64>::S;
   using C = typename Mode<ST, M64>::C;
   using A = typename Mode<ST, M64>::A;
@@ -52,18 +53,31 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
   constexpr int NM = MR * MZ, NB = BR * BZ, NEZ = EZR * EZZ, NER = ERR * ERZ;
   constexpr int SM = (NM + NTHREADS - 1) / NTHREADS, SB = (NB + NTHREADS - 1) / NTHREADS;
   constexpr int SEZ = (NEZ + NTHREADS - 1) / NTHREADS, SER = (NER + NTHREADS - 1) / NTHREADS;
-  __shared__ CF sM[3][MR][MZ];
+  // Halo tiles in LDS, row-major, each padded to a whole number of block-wide passes: element t of
+  // a tile is the t-th load of the tile's flattened halo, so the 64 loads of a wavefront fill 64
+  // consecutive words.  With FP32 auxiliary planes and FP32 field arithmetic the halo loads go
+  // straight from memory to LDS (no registers held while the population loads are in flight);
+  // otherwise they pass through registers (conversion to FP64).
+  constexpr bool HDMA = std::is_same<A, float>::value && std::is_same<CF, float>::value;
+  __shared__ CF sMst[3][SM * NTHREADS];
+  __shared__ CF sBost[SB * NTHREADS];
+  __shared__ CF sEzst[SEZ * NTHREADS];
+  __shared__ CF sErst[SER * NTHREADS];
+  CF(*const sM[3])[MZ] = {reinterpret_cast<CF(*)[MZ]>(sMst[0]), reinterpret_cast<CF(*)[MZ]>(sMst[1]),
+                          reinterpret_cast<CF(*)[MZ]>(sMst[2])};
+  CF(*const sBo)[BZ] = reinterpret_cast<CF(*)[BZ]>(sBost);
+  CF(*const sEz)[EZZ] = reinterpret_cast<CF(*)[EZZ]>(sEzst);
+  CF(*const sEr)[ERZ] = reinterpret_cast<CF(*)[ERZ]>(sErst);
   __shared__ CF sJ[2][MR][MZ];
-  __shared__ CF sBo[BR][BZ];
-  __shared__ CF sEz[EZR][EZZ];
-  __shared__ CF sEr[ERR][ERZ];
   __shared__ CF sBn[BNR][BNZ];
   __shared__ double sN[MZ];
   __shared__ CF sDz[EZZ];   // exp(-(z - z_d)^2 / 2 sigma_z^2) at the E_z columns
   __shared__ CF sDr[EZR];   // n_b exp(-r^2 / 2 sigma_r^2) at the fluid / E_z rows
   __shared__ CF sIr[EZR];   // 1 / r_j at the fluid / E_z rows
-  __shared__ CF sJbz[DRV ? EZR : 1][DRV ? EZZ : 1];   // particle driver: J_bz at the E_z points
-  __shared__ CF sJbr[DRV ? ERR : 1][DRV ? ERZ : 1];   // and J_br at the E_r points
+  __shared__ CF sJbzst[DRV ? SEZ * NTHREADS : 1];   // particle driver: J_bz at the E_z points
+  __shared__ CF sJbrst[DRV ? SER * NTHREADS : 1];   // and J_br at the E_r points
+  CF(*const sJbz)[EZZ] = reinterpret_cast<CF(*)[EZZ]>(sJbzst);
+  CF(*const sJbr)[ERZ] = reinterpret_cast<CF(*)[ERZ]>(sJbrst);
   __shared__ CF sU[NEQ ? 2 : 1][NEQ ? MR : 1][NEQ ? MZ : 1];   // NEQ: lattice velocity u* of the moments
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
@@ -86,47 +100,94 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
   // row after the r rule (axis mirror row 0, outer copy, wrap); always in range.
   auto zcol = [&](int i) { return PER && p.per_z ? wrapi(i, nz) : (i < 0 ? 0 : (i < nz ? i : nz - 1)); };
   auto rrow = [&](int j) { return PER && p.per_r ? wrapi(j, nr) : (j < 0 ? 0 : (j < nr ? j : nr - 1)); };
-  // plane bases (uniform) + 32-bit in-plane offsets (a plane holds fewer than 2^31 elements)
-  const A* M0p = Min;
-  const A* M1p = Min + plane;
-  const A* M2p = Min + 2 * plane;
-  const A* Ezp = Ein;
-  const A* Erp = Ein + plane;
-  const A* Bp = Ein + 2 * plane;
+  // one buffer resource per plane (uniform) + 32-bit in-plane offsets (a plane holds fewer than
+  // 2^31 elements and fewer than 2^32 bytes)
+  const Rsrc M0p = plane_rsrc<A>(Min, plane, 0);
+  const Rsrc M1p = plane_rsrc<A>(Min, plane, 1);
+  const Rsrc M2p = plane_rsrc<A>(Min, plane, 2);
+  const Rsrc Ezp = plane_rsrc<A>(Ein, plane, 0);
+  const Rsrc Erp = plane_rsrc<A>(Ein, plane, 1);
+  const Rsrc Bp = plane_rsrc<A>(Ein, plane, 2);
 
-  // --- 1. halo loads into registers --------------------------------------------------------
-  A hm[SM][3];
-  A hb[SB], hez[SEZ], her[SER];
-  A hjz[DRV ? SEZ : 1], hjr[DRV ? SER : 1];
+  // --- 1. halo loads: into LDS (HDMA), or into registers ------------------------------------
+  // Every lane loads from a clamped, in-range address; with HDMA a wave's 64 words land at its
+  // 64 consecutive slots of the padded tile (slots past the tile are padding).
+  const int wv = __builtin_amdgcn_readfirstlane(tid / 64);   // wavefront of the block (uniform)
+  auto hload = [&](Rsrc r, uint32_t off, CF* tile, int s, A& reg) {
+    if constexpr (HDMA)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)(tile + s * NTHREADS + wv * 64),
+                                               4, (int)(off * 4u), 0, 0, 0);
+    else
+      reg = bload<A>(r, off);
+  };
+  A hm[HDMA ? 1 : SM][3];
+  A hb[HDMA ? 1 : SB], hez[HDMA ? 1 : SEZ], her[HDMA ? 1 : SER];
+  A hjz[DRV && !HDMA ? SEZ : 1], hjr[DRV && !HDMA ? SER : 1];
 #pragma unroll
   for (int s = 0; s < SM; ++s) {
     const int t = min(tid + s * NTHREADS, NM - 1);
-    const int off = rrow(j0 - 1 + t / MZ) * pitch + zcol(i0 - 1 + t % MZ);
-    hm[s][0] = M0p[off];
-    hm[s][1] = M1p[off];
-    hm[s][2] = M2p[off];
+    const uint32_t off = rrow(j0 - 1 + t / MZ) * pitch + zcol(i0 - 1 + t % MZ);
+    hload(M0p, off, sMst[0], s, hm[HDMA ? 0 : s][0]);
+    hload(M1p, off, sMst[1], s, hm[HDMA ? 0 : s][1]);
+    hload(M2p, off, sMst[2], s, hm[HDMA ? 0 : s][2]);
   }
   if (FIELDS) {
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       const int t = min(tid + s * NTHREADS, NB - 1);
-      hb[s] = Bp[rrow(j0 - 2 + t / BZ) * pitch + zcol(i0 - 2 + t % BZ)];
+      hload(Bp, rrow(j0 - 2 + t / BZ) * pitch + zcol(i0 - 2 + t % BZ), sBost, s, hb[HDMA ? 0 : s]);
     }
 #pragma unroll
     for (int s = 0; s < SEZ; ++s) {
       const int t = min(tid + s * NTHREADS, NEZ - 1);
-      hez[s] = Ezp[rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ)];
-      if (DRV) hjz[s] = ((const A*)a.jb_in)[rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ)];
+      const uint32_t off = rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ);
+      hload(Ezp, off, sEzst, s, hez[HDMA ? 0 : s]);
+      if (DRV) hload(plane_rsrc<A>(a.jb_in, plane, 0), off, sJbzst, s, hjz[HDMA ? 0 : s]);
     }
 #pragma unroll
     for (int s = 0; s < SER; ++s) {
       const int t = min(tid + s * NTHREADS, NER - 1);
-      her[s] = Erp[rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ)];
-      if (DRV) hjr[s] = ((const A*)a.jb_in + plane)[rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ)];
+      const uint32_t off = rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ);
+      hload(Erp, off, sErst, s, her[HDMA ? 0 : s]);
+      if (DRV) hload(plane_rsrc<A>(a.jb_in, plane, 1), off, sJbrst, s, hjr[HDMA ? 0 : s]);
     }
   }
+  // the population loads below must be issued after every halo load (the wait before the first
+  // barrier counts on it)
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::: "memory");
 
-  // --- 2. population loads (Eq. (6), pull form f_q(x) = g_q(x - xi_q)) ----------------------
+  // --- 2. per-column and per-row factors of the tile.  With the halo in LDS they are computed
+  // before the population loads are issued (the FP64 ramp profile needs many registers for a
+  // moment, which the in-flight populations would otherwise have to give up); with the halo in
+  // registers, after them. -------------------------------------------------------------------
+  const double tb = ((double)a.k - 0.5) * dt;
+  auto factors = [&]() {
+    // background density at the lab position of the physical column
+    for (int t = tid; t < MZ; t += NTHREADS) {
+      const int ii = i0 - 1 + t;
+      sN[t] = nbg(p, (double)(a.s + (PER && p.per_z ? wrapi(ii, nz) : ii)) * h);
+    }
+    // the driver density factorises into a column and a row factor
+    if (FIELDS && !DRV) {
+      for (int t = tid; t < EZZ; t += NTHREADS) {
+        const int ii = i0 - 1 + t;
+        const int ci = PER && p.per_z ? wrapi(ii, nz) : ii;
+        const CF dz = (CF)(((double)(a.s + ci) + 0.5) * h - (p.zd0 + tb));
+        sDz[t] = mexp(-(dz * dz) / (CF)(2.0 * p.sigma_z * p.sigma_z));
+      }
+    }
+    for (int t = tid; t < EZR; t += NTHREADS) {
+      const double r = (j0 - 1 + t + 0.5) * h;
+      const CF rr = (CF)r;
+      if (!DRV) sDr[t] = (CF)p.nb * mexp(-(rr * rr) / (CF)(2.0 * p.sigma_r * p.sigma_r));
+      sIr[t] = CF(1) / rr;
+    }
+  };
+  if constexpr (HDMA) factors();
+  __builtin_amdgcn_sched_barrier(0);
+
+  // --- 3. population loads (Eq. (6), pull form f_q(x) = g_q(x - xi_q)) ----------------------
   const int o = o0 + tx;       // output column (post-shift)
   const int i = i0 + tx;       // logical column (pre-shift)
   const int j = j0 + ty;
@@ -136,34 +197,22 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
   S r0[9], r1[9], r2[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    // ghost sources are replaced below; their (in-range) load is discarded
-    const int off = rrow(j - XR(q)) * pitch + zcol(i - XZ(q));
-    r0[q] = ldpop(&(gin + q * plane)[off]);
-    r1[q] = ldpop(&(gin + (9 + q) * plane)[off]);
-    r2[q] = ldpop(&(gin + (18 + q) * plane)[off]);
+    // ghost sources are replaced below; their (in-range) load is discarded.  FP64 populations are
+    // read non-temporally (measured: FP64 step 110 -> 96.5 us on 2048 x 512; FP32 loses 25 %)
+    constexpr int POL = ST == 0 ? 2 : 0;
+    const uint32_t off = rrow(j - XR(q)) * pitch + zcol(i - XZ(q));
+    r0[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, q), off);
+    r1[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, 9 + q), off);
+    r2[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, 18 + q), off);
   }
+  if constexpr (!HDMA) factors();
 
-  // --- 3. per-column and per-row factors of the tile --------------------------------------
-  // background density at the lab position of the physical column
-  for (int t = tid; t < MZ; t += NTHREADS) {
-    const int ii = i0 - 1 + t;
-    sN[t] = nbg(p, (double)(a.s + (PER && p.per_z ? wrapi(ii, nz) : ii)) * h);
-  }
-  // the driver density factorises into a column and a row factor
-  const double tb = ((double)a.k - 0.5) * dt;
-  if (FIELDS && !DRV) {
-    for (int t = tid; t < EZZ; t += NTHREADS) {
-      const int ii = i0 - 1 + t;
-      const int ci = PER && p.per_z ? wrapi(ii, nz) : ii;
-      const CF dz = (CF)(((double)(a.s + ci) + 0.5) * h - (p.zd0 + tb));
-      sDz[t] = mexp(-(dz * dz) / (CF)(2.0 * p.sigma_z * p.sigma_z));
-    }
-  }
-  for (int t = tid; t < EZR; t += NTHREADS) {
-    const double r = (j0 - 1 + t + 0.5) * h;
-    const CF rr = (CF)r;
-    if (!DRV) sDr[t] = (CF)p.nb * mexp(-(rr * rr) / (CF)(2.0 * p.sigma_r * p.sigma_r));
-    sIr[t] = CF(1) / rr;
+  if constexpr (HDMA) {
+    // the halo's loads to LDS were issued before the 27 population loads, and vector-memory
+    // counters retire in order: waiting until at most 27 are outstanding leaves the populations in
+    // flight (gfx9 encoding: vmcnt 27, expcnt and lgkmcnt not waited for)
+    static_assert(27 < 64, "vmcnt holds 6 bits");
+    __builtin_amdgcn_s_waitcnt((1 << 14) | (0xF << 8) | (0x7 << 4) | (27 & 0xF));
   }
   __syncthreads();
 
@@ -177,7 +226,16 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
       const int bb = t / MZ, aa = t % MZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
       const bool fresh = !p.per_z && p.window && ii == nz;   // window front: plasma at rest
-      CF d0 = (CF)hm[s][0], m1 = (CF)hm[s][1], m2 = (CF)hm[s][2];
+      CF d0, m1, m2;
+      if constexpr (HDMA) {
+        d0 = sM[0][bb][aa];
+        m1 = sM[1][bb][aa];
+        m2 = sM[2][bb][aa];
+      } else {
+        d0 = (CF)hm[s][0];
+        m1 = (CF)hm[s][1];
+        m2 = (CF)hm[s][2];
+      }
       if (fresh) {
         d0 = CF(0);
         m1 = CF(0);
@@ -208,22 +266,33 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
 
   if (FIELDS) {
     // --- 5. B^{k-1/2}, E^{k-1} into LDS (ghosts: B = 0 on the axis, zero-gradient elsewhere) --
+    if constexpr (HDMA) {
+      // the tiles are in LDS already; only B's rows below the axis are replaced (by zero)
+      if (j0 == 0) {
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      const int t = tid + s * NTHREADS;
-      if (t < NB) sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? CF(0) : (CF)hb[s];
-    }
+        for (int s = 0; s < SB; ++s) {
+          const int t = tid + s * NTHREADS;
+          if (t < 2 * BZ) sBo[t / BZ][t % BZ] = CF(0);
+        }
+      }
+    } else {
 #pragma unroll
-    for (int s = 0; s < SEZ; ++s) {
-      const int t = tid + s * NTHREADS;
-      if (t < NEZ) sEz[t / EZZ][t % EZZ] = (CF)hez[s];
-      if (DRV && t < NEZ) sJbz[t / EZZ][t % EZZ] = (CF)hjz[s];
-    }
+      for (int s = 0; s < SB; ++s) {
+        const int t = tid + s * NTHREADS;
+        if (t < NB) sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? CF(0) : (CF)hb[s];
+      }
 #pragma unroll
-    for (int s = 0; s < SER; ++s) {
-      const int t = tid + s * NTHREADS;
-      if (t < NER) sEr[t / ERZ][t % ERZ] = (CF)her[s];
-      if (DRV && t < NER) sJbr[t / ERZ][t % ERZ] = (CF)hjr[s];
+      for (int s = 0; s < SEZ; ++s) {
+        const int t = tid + s * NTHREADS;
+        if (t < NEZ) sEz[t / EZZ][t % EZZ] = (CF)hez[s];
+        if (DRV && t < NEZ) sJbz[t / EZZ][t % EZZ] = (CF)hjz[s];
+      }
+#pragma unroll
+      for (int s = 0; s < SER; ++s) {
+        const int t = tid + s * NTHREADS;
+        if (t < NER) sEr[t / ERZ][t % ERZ] = (CF)her[s];
+        if (DRV && t < NER) sJbr[t / ERZ][t % ERZ] = (CF)hjr[s];
+      }
     }
     __syncthreads();
 
@@ -296,27 +365,23 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
 
   // --- 8. fluid phase: one site per thread ------------------------------------------------
   if (!site_ok) return;   // no barrier below this point
-  const int oo32 = j * pitch + o;
-  const long long oo = oo32;
+  const uint32_t oo = j * pitch + o;
   if (DRV) {
     // the next step's deposit buffer, cleared at this output cell
-    A* jz = (A*)a.jb_zero;
-    stv(jz + oo, C(0));
-    stv(jz + plane + oo, C(0));
+    bstore<A>(plane_rsrc<A>(a.jb_zero, plane, 0), oo, C(0));
+    bstore<A>(plane_rsrc<A>(a.jb_zero, plane, 1), oo, C(0));
   }
-  S* gout = (S*)a.g_out;
-  A* Mout = (A*)a.M_out;
-  A* Eout = (A*)a.E_out;
+  const void* gout = a.g_out;
+  const void* Mout = a.M_out;
+  const void* Eout = a.E_out;
 
   if (fresh_site) {
     // new front column of the moved window: plasma at rest at n_bg, no fields
-    for (int c = 0; c < 27; ++c) stv(gout + c * plane + oo, C(0));
-    stv(Mout + oo, C(0));
-    stv(Mout + plane + oo, C(0));
-    stv(Mout + 2 * plane + oo, C(0));
-    stv(Eout + oo, C(0));
-    stv(Eout + plane + oo, C(0));
-    stv(Eout + 2 * plane + oo, C(0));
+    for (int c = 0; c < 27; ++c) bstore<S>(plane_rsrc<S>(gout, plane, c), oo, C(0));
+    for (int c = 0; c < 3; ++c) {
+      bstore<A>(plane_rsrc<A>(Mout, plane, c), oo, C(0));
+      bstore<A>(plane_rsrc<A>(Eout, plane, c), oo, C(0));
+    }
     return;
   }
 
@@ -385,10 +450,9 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     Bb = (C)((sBo[ty + 2][tx + 2] + sBo[ty + 2][tx + 1] + sBo[ty + 1][tx + 2] + sBo[ty + 1][tx + 1] +
               sBn[ty + 1][tx + 1] + sBn[ty + 1][tx] + sBn[ty][tx + 1] + sBn[ty][tx]) * CF(0.125));
     if (SITE) {
-      A* So = (A*)a.site_out;
-      stv(So + oo, Ebz);
-      stv(So + plane + oo, Ebr);
-      stv(So + 2 * plane + oo, Bb);
+      bstore<A>(plane_rsrc<A>(a.site_out, plane, 0), oo, Ebz);
+      bstore<A>(plane_rsrc<A>(a.site_out, plane, 1), oo, Ebr);
+      bstore<A>(plane_rsrc<A>(a.site_out, plane, 2), oo, Bb);
     }
   }
 
@@ -428,7 +492,7 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
       eq_dir<C>(kq % 9, mo0, nref + mo0, mo1, mo2, uoz, uor, e0, e1, e2);
       v -= kq < 9 ? e0 : (kq < 18 ? e1 : e2);
     }
-    stv(gout + kq * plane + oo32, v);
+    bstore<S>(plane_rsrc<S>(gout, plane, kq), oo, v);
   };
 
   // Eqs. (7), (9), (10): relaxation toward the equilibrium (standard D2Q9 coefficients) plus
@@ -441,7 +505,9 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     // moments are the moments themselves to about an ulp.  Otherwise the rounding of the
     // equilibria (and of the weights 1/9, 1/36 in FP32) would drift the density and momentum
     // moments over many steps.
+    // g' = f (1 - 1/tau) + (f_eq / tau + w dt F): two FMAs per population
     SE se0, se1, se2;
+    const C omt = C(1) - itau;
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       const C w = WQ<C>(q);
@@ -454,14 +520,14 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
       se1.add(e1);
       se2.add(e2);
       const C wdt = w * dtc;
-      put(q, f0[q] - (f0[q] - e0) * itau + wdt * F0);
-      put(9 + q, f1[q] - (f1[q] - e1) * itau + wdt * F1);
-      put(18 + q, f2[q] - (f2[q] - e2) * itau + wdt * F2);
+      put(q, f0[q] * omt + (e0 * itau + wdt * F0));
+      put(9 + q, f1[q] * omt + (e1 * itau + wdt * F1));
+      put(18 + q, f2[q] * omt + (e2 * itau + wdt * F2));
     }
     const C wdt = WQ<C>(0) * dtc;
-    put(0, f0[0] - (f0[0] - se0.rest(dA0)) * itau + wdt * F0);
-    put(9, f1[0] - (f1[0] - se1.rest(A1)) * itau + wdt * F1);
-    put(18, f2[0] - (f2[0] - se2.rest(A2)) * itau + wdt * F2);
+    put(0, f0[0] * omt + (se0.rest(dA0) * itau + wdt * F0));
+    put(9, f1[0] * omt + (se1.rest(A1) * itau + wdt * F1));
+    put(18, f2[0] * omt + (se2.rest(A2) * itau + wdt * F2));
   } else if (COLL == 1) {
     // two relaxation times: the even part of f - f_eq relaxes with 1/tau_plus, the odd part
     // (which carries the flux and so sets D) with 1/tau.  The rest population is even.
@@ -593,19 +659,17 @@ __global__ __launch_bounds__(NTHREADS, (ST >= 2 && !M64) ? 7 : 1) void step_kern
     put(9, se1.rest(A1) + wdt * F1);
     put(18, se2.rest(A2) + wdt * F2);
   }
-  stv(Mout + oo, mo0);   // density moment stored as the deviation from n_bg
-  stv(Mout + plane + oo, mo1);
-  stv(Mout + 2 * plane + oo, mo2);
+  bstore<A>(plane_rsrc<A>(Mout, plane, 0), oo, mo0);   // density moment stored as the deviation from n_bg
+  bstore<A>(plane_rsrc<A>(Mout, plane, 1), oo, mo1);
+  bstore<A>(plane_rsrc<A>(Mout, plane, 2), oo, mo2);
 
   if (FIELDS) {
-    stv(Eout + oo, (A)sEz[ty + 1][tx + 1]);
-    stv(Eout + plane + oo, (A)sEr[ty + 1][tx + 1]);
-    stv(Eout + 2 * plane + oo, (A)sBn[ty + 1][tx + 1]);
+    bstore<A>(plane_rsrc<A>(Eout, plane, 0), oo, (A)sEz[ty + 1][tx + 1]);
+    bstore<A>(plane_rsrc<A>(Eout, plane, 1), oo, (A)sEr[ty + 1][tx + 1]);
+    bstore<A>(plane_rsrc<A>(Eout, plane, 2), oo, (A)sBn[ty + 1][tx + 1]);
   } else {
-    const long long io = (long long)j * pitch + i;
-    stv(Eout + oo, (C)Ein[io]);
-    stv(Eout + plane + oo, (C)Ein[plane + io]);
-    stv(Eout + 2 * plane + oo, (C)Ein[2 * plane + io]);
+    const uint32_t io = j * pitch + i;
+    for (int c = 0; c < 3; ++c) bstore<A>(plane_rsrc<A>(Eout, plane, c), oo, bload<A>(plane_rsrc<A>(Ein, plane, c), io));
   }
 }
 
@@ -894,18 +958,16 @@ __global__ __launch_bounds__(RED_THREADS) void bubble_kernel(Physics p, long lon
 
 static dim3 site_grid(const Physics& p) { return dim3((p.nz + 255) / 256, p.nr); }
 
-// FP16 storage moves half the bytes of FP32 and is instruction-bound: it takes the variant with
-// the wrap code compiled out when the grid is not periodic (8 % faster on 2048 x 512).  FP32 and
-// FP64 are bandwidth-bound and measure the same either way, so they keep one variant.
+// A grid that is not periodic takes the variant with the wrap code (an integer modulo by the grid
+// size per index) compiled out.
 template <int ST, bool M64, int COLL>
 static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
-  constexpr bool half = ST >= 2;
-  const bool np = half && !a.p.per_z && !a.p.per_r;
+  const bool np = !a.p.per_z && !a.p.per_r;
   const bool drv = a.p.driver == 1;
   if (a.p.fields_on && drv) step_kernel<ST, true, M64, false, COLL, true, 1><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, !half, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
-  else if (np) step_kernel<ST, false, M64, false, COLL, !half, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (np) step_kernel<ST, false, M64, false, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else step_kernel<ST, false, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
