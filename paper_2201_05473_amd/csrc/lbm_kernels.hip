@@ -977,7 +977,8 @@ template <int ST, bool M64, int COLL>
 static void launch_step_s(const StepArgs& a, dim3 grid, hipStream_t st) {
   if constexpr (!neq_storage(ST) && (!M64 || COLL == 0)) {
     if (a.p.fields_on && a.site_out) {
-      step_kernel<ST, true, M64, true, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+      if (!a.p.per_z && !a.p.per_r) step_kernel<ST, true, M64, true, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+      else step_kernel<ST, true, M64, true, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
       return;
     }
   }
