@@ -251,8 +251,10 @@ int lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t nsteps, int32_t c
 /* Objective and its gradient dJ/d(ramp_len, n0, sigma_r, nb) over nsteps steps from the
  * initial state.  The context must be at step 0.  Forward pass with a stored checkpoint every
  * ckpt_every steps, then segment by segment in reverse: recompute the segment's states (and the
- * site-averaged fields of each of its steps) from its checkpoint, and run the reverse steps.
- * The last segment is kept from the forward pass (its states and site fields go straight to a
+ * site record of each of its steps: the site-averaged fields and the moments of the pulled
+ * populations, which is all the reverse step needs of the collision's input) from its
+ * checkpoint, and run the reverse steps.
+ * The last segment is kept from the forward pass (its states and site records go straight to a
  * segment buffer), so it is not recomputed.  The recompute of the next segment runs on a second
  * stream, created by the library on first use (default priority, released by lbm_destroy),
  * while the reverse steps run on the caller's stream; with more than one segment the workspace
@@ -266,7 +268,7 @@ int lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int64_t nsteps, int32_t 
  * a checkpoint interval: binomial (revolve-type) checkpointing.  With s snapshots and every step
  * advanced at most t times, C(s + t, s) steps can be reversed; the recursion places each next
  * snapshot so that the later part of a range fits one snapshot fewer.  The workspace holds the
- * snapshots and the site fields of one step.  The context's two state buffers serve as scratch;
+ * snapshots and the site record of one step.  The context's two state buffers serve as scratch;
  * on return the context holds its initial state (step 0) again.  steps_advanced (may be NULL)
  * receives the number of forward steps taken, including the one each reverse step recomputes.
  * Synchronising.  Periodic dimensions need at least 5 cells. */

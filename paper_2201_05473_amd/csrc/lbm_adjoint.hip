@@ -20,8 +20,9 @@
 // reverse step reads and writes the 27 population planes once, exactly like the forward step.
 // Gather form throughout: every output has a single writer, no atomics, fixed summation order.
 //
-//   adj_site_kernel   per fluid site: gather g_bar^{k+1} (pull of f_bar^{k+1}), recompute the field
-//                     tile (Ampere, Faraday) and the site's forward collision, then the VJP of the
+//   adj_site_kernel   per fluid site: gather g_bar^{k+1} (pull of f_bar^{k+1}); the site fields and
+//                     the moments A of the pulled populations come from the site record that the
+//                     forward step wrote (the populations of x^k are not read); then the VJP of the
 //                     collision: f_bar^k (27), and the site adjoints F_bar (3, source terms),
 //                     E_bar_z, E_bar_r, B_bar; theta partials of the window-front ghost and of
 //                     the new front column.
@@ -112,28 +113,24 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const T M[3], T jz
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
-// adj_site_kernel: one thread per logical fluid site (i, j) of x^k.  The site fields of step k
-// (E_z, E_r, B_theta averaged to the site as the fluid used them) come from a.site, written by
-// the forward step's recompute at the output index.
+// adj_site_kernel: one thread per logical fluid site (i, j) of x^k.  The site record of step k
+// (E_z, E_r, B_theta averaged to the site as the fluid used them, and the moments of the pulled
+// populations) comes from a.site, written by the forward step's recompute at the output index.
 // ------------------------------------------------------------------------------------------
 // Site part of a reverse step for the tile whose first site is (i0, j0) (logical columns of x^k).
 // mreg: M_bar^{k+1} of the thread's site output, when the caller has it in registers (else read
 // from lam_next).  theta partials are added to part.  Every thread of the block must call it.
 template <int ST, int COLL>
 __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const typename Mode<ST, false>::C* mreg, double part[4]) {
-  using S = typename Mode<ST, false>::S;
   using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
   using T = typename Mode<ST, false>::C;   // arithmetic (FP64 for FP64 storage, else FP32)
   const Physics& p = a.p;
-  __shared__ double sN[TZ + 2];   // n_bg at the columns i0-1 .. i0+TZ
 
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
   const double h = p.h;
   const T dt = (T)p.dt, lam = (T)p.lam, floor_ = (T)p.n_floor;
-  const A* __restrict__ Min = (const A*)a.M;
-  const S* __restrict__ gin = (const S*)a.g;
   const A* __restrict__ L = (const A*)a.lam_next;
   const A* __restrict__ Sf = (const A*)a.site;
 
@@ -143,23 +140,18 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
   const int ic = i < nz ? i : nz - 1, jc = j < nr ? j : nr - 1;
   const int ib = (ic - a.shift) < 0 ? 0 : ic - a.shift;   // output index in x^{k+1}
 
-  // loads: the populations pulled from inside the domain, g_bar^{k+1} at the site's output
-  // position (the transposed pull of f_bar^{k+1}, or read directly), M_bar^{k+1}, site fields
-  S graw[27];
+  // loads: g_bar^{k+1} at the site's output position (the transposed pull of f_bar^{k+1}, or
+  // read directly), M_bar^{k+1}, and the site record the forward step wrote at the output
+  // index: the site fields and the moments A of the pulled populations (ghosts included).  The
+  // collision's Jacobian depends on the pulled populations only through A, so the populations of
+  // x^k are not read.
   A gbar[27];
   A mbar[3];
   A sfield[3] = {A(0), A(0), A(0)};
+  A amom[3];
   bool gok[9];
-  bool ghost[9];   // the pull in direction q reads an equilibrium ghost of a non-periodic edge
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const int ui = ic - XZ(q), uj = jc - XR(q);
-    const int si = p.per_z ? wrap1(ui, nz) : (ui < 0 ? 0 : (ui < nz ? ui : nz - 1));
-    const int sj = p.per_r ? wrap1(uj, nr) : (uj < 0 ? 0 : (uj < nr ? uj : nr - 1));
-    const int off = sj * pitch + si;
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk) graw[9 * kk + q] = (gin + (9 * kk + q) * plane)[off];
-    ghost[q] = (!p.per_z && (ui < 0 || ui >= nz)) || (!p.per_r && (uj < 0 || uj >= nr));
     int yi = ib, yj = jc;
     bool ok = true;
     if (a.pull_in) {
@@ -175,24 +167,14 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
   }
+  const int so = jc * pitch + ib;
 #pragma unroll
-  for (int kk = 0; kk < 3; ++kk) mbar[kk] = mreg ? A(0) : (L + (27 + kk) * plane)[jc * pitch + ib];
+  for (int kk = 0; kk < 3; ++kk) mbar[kk] = mreg ? A(0) : (L + (27 + kk) * plane)[so];
   if (p.fields_on)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[jc * pitch + ib];
-  // zeroth moments of the populations pulled from inside the domain (deviation form for lattice 0)
-  T Am[3] = {T(0.0), T(0.0), T(0.0)};
+    for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[so];
 #pragma unroll
-  for (int q = 0; q < 9; ++q)
-    if (!ghost[q])
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) Am[kk] += (T)ldv(graw[9 * kk + q]);
-
-  for (int t = tid; t < TZ + 2; t += NTHREADS) {
-    const int ii = i0 - 1 + t;
-    sN[t] = nbg(p, (double)(a.s + (p.per_z ? wrapi(ii, nz) : ii)) * h);
-  }
-  __syncthreads();
+  for (int c = 0; c < 3; ++c) amom[c] = (Sf + (3 + c) * plane)[so];
 
   if (a.shift && i == nz && j < nr) {
     // the column dropped in this step (column 0) has no site: zero adjoint sources.  Written
@@ -215,39 +197,7 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
 #pragma unroll
       for (int c = 0; c < 6; ++c) (W + c * plane)[cell] = A(0);
     } else {
-      // forward recompute of the site's moments (raw values): background of the pulled lattice-0
-      // deviations, and the equilibrium ghosts (moments of the source cell after the z rule then
-      // the r rule; the window front is plasma at rest)
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        if (ghost[q]) {
-          int si = i - XZ(q), sj = j - XR(q);
-          T Mg[3];
-          if (!p.per_z && si >= nz && p.window) {
-            Mg[0] = (T)sN[tx + 1 - XZ(q)];
-            Mg[1] = T(0.0);
-            Mg[2] = T(0.0);
-          } else {
-            si = p.per_z ? wrap1(si, nz) : (si < 0 ? 0 : (si < nz ? si : nz - 1));
-            const int rj = p.per_r ? wrap1(sj, nr) : (sj < 0 ? 0 : (sj < nr ? sj : nr - 1));
-            const int off = rj * pitch + si;
-            const int sa = si - (i0 - 1);
-            Mg[0] = (T)((double)Min[off] + ((sa >= 0 && sa < TZ + 2) ? sN[sa] : nbg(p, (double)(a.s + si) * h)));
-            Mg[1] = (T)Min[plane + off];
-            Mg[2] = (T)(Min + 2 * plane)[off];
-          }
-          if (!p.per_r && sj < 0) Mg[2] = -Mg[2];   // axis mirror
-          T bz, br;
-          velocity<T>(Mg[0], Mg[1], Mg[2], floor_, bz, br);
-          const T uz = lam * bz, ur = lam * br;
-          const T cu = XZ(q) * uz + XR(q) * ur;
-          const T Q = T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * (uz * uz + ur * ur);
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) Am[kk] += WQ<T>(q) * Mg[kk] * (T(1.0) + Q);
-        } else {
-          Am[0] += WQ<T>(q) * (T)sN[tx + 1 - XZ(q)];
-        }
-      }
+      const T Am[3] = {(T)amom[0], (T)amom[1], (T)amom[2]};
       const T n = Am[0];
       T bz, br;
       const bool live = velocity<T>(Am[0], Am[1], Am[2], floor_, bz, br);

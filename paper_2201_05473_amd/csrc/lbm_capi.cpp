@@ -573,9 +573,10 @@ namespace {
 
 size_t state_bytes(const Physics& p, int storage);
 
-// the site fields of one step (E_z, E_r, B_theta averaged to the sites), auxiliary type
+// the site record of one step for its reverse (E_z, E_r, B_theta averaged to the sites, and the
+// moments of the pulled populations), auxiliary type
 size_t site_bytes(const Physics& p, int storage) {
-  return round_up(3 * (size_t)p.plane * aux_bytes(storage), 256);
+  return round_up(6 * (size_t)p.plane * aux_bytes(storage), 256);
 }
 
 // Adjoint workspace: two lambda buffers and the work planes in the adjoint precision (the
@@ -675,7 +676,7 @@ lbm::AdjArgs adj_args(lbm_ctx* c, const StateView& x, const void* site, long lon
   return a;
 }
 
-// forward step k from x into y, saving the site fields of the step
+// forward step k from x into y, saving the step's site record (site may be nullptr: a plain step)
 hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const StateView& y, void* site,
                           hipStream_t st) {
   lbm::StepArgs a;
@@ -686,7 +687,7 @@ hipError_t step_with_site(lbm_ctx* c, long long k, const StateView& x, const Sta
   a.g_in = x.g; a.g_out = y.g;
   a.M_in = x.M; a.M_out = y.M;
   a.E_in = x.E; a.E_out = y.E;
-  a.site_out = c->p.fields_on ? site : nullptr;
+  a.site_out = site;
   a.jb_in = nullptr;
   a.jb_zero = nullptr;
   return lbm::launch_step(c->storage, a, st);
@@ -805,7 +806,7 @@ static int adjoint_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int
 
   // Forward pass.  x^0 stays in the context's current buffer and is checkpoint 0; each later
   // checkpoint is written by the step that makes it (no copies).  The last segment runs with its
-  // site fields straight into its segment buffer, so the reverse sweep needs no recompute of it;
+  // site records straight into its segment buffer, so the reverse sweep needs no recompute of it;
   // x^N goes to the context's other buffer, which becomes current when the call ends.
   const int c0 = c->cur;
   const StateView x0{c->g(c0), c->M(c0), c->E(c0)};
@@ -865,7 +866,7 @@ static int adjoint_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int
   }
   int cur = 0;
   // Reverse sweep, segment by segment.  The recompute of segment sgi - 1 (states from its
-  // checkpoint, and the site fields of each step) runs on the second stream while the reverse
+  // checkpoint, and the site record of each step) runs on the second stream while the reverse
   // sweep of segment sgi runs on the caller's stream; segments alternate between two buffers.
   // Segments other than the last are full length; their first state is read from the checkpoint,
   // slots 1 .. len - 1 of the buffer hold the later states (slot len is scratch).
@@ -885,7 +886,7 @@ static int adjoint_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int
   HIP_CHECK(hipStreamWaitEvent(c->aux, c->ev_fwd, 0), "stream wait");
   // Within the sweep, the cell part of step k and the site part of step k - 1 run as one fused
   // launch; the site part of the last step and the cell part of step 0 run alone.  At a segment
-  // boundary the fused launch reads the last state (and site fields) of the previous segment,
+  // boundary the fused launch reads the last state (and site record) of the previous segment,
   // so the caller's stream waits for that segment's recompute first; a segment buffer is
   // released once the cell part of its first step has run.
   auto xs = [&](int64_t k) -> StateView {
@@ -979,7 +980,7 @@ struct Revolve {
   const AdjLayout* L;
   char* w;
   char* snaps;     // snapshot slots, one state each
-  char* sites;     // site fields of the step being reversed
+  char* sites;     // site record of the step being reversed
   size_t sb;
   char* lam[2];
   int cur;
@@ -1023,12 +1024,11 @@ struct Revolve {
     return LBM_OK;
   }
 
-  // reverse step k from x^k (in x): the step again with its site fields saved (its output, x^{k+1},
+  // reverse step k from x^k (in x): the step again with its site record saved (its output, x^{k+1},
   // gives J when k = N - 1), then the reverse kernels
   int reverse_step(int64_t k, const StateView& x) {
     const StateView y = (x.g == c->g(0)) ? ctxbuf(1) : ctxbuf(0);   // not x itself
-    HIP_CHECK(lbm::launch_step(c->storage, step_args(k, x, y, c->p.fields_on ? sites : nullptr), c->stream),
-              "step launch");
+    HIP_CHECK(lbm::launch_step(c->storage, step_args(k, x, y, sites), c->stream), "step launch");
     ++advanced;
     if (k == nsteps - 1) {
       const size_t ab = aux_bytes(c->storage);

@@ -50,8 +50,10 @@ struct StepArgs {
   void* M_out;
   const void* E_in;  // [3 planes] E_z, E_r, B_theta
   void* E_out;
-  void* site_out;    // optional (fields on): [3 planes] E_z, E_r, B_theta averaged to the sites as
-                     // used by the fluid, at the output index; nullptr to skip
+  void* site_out;    // optional, for the reverse sweep: [6 planes] at the output index, E_z, E_r,
+                     // B_theta averaged to the sites as used by the fluid (fields on; else left
+                     // alone), then the moments n, n p_z, n p_r of the pulled populations (Eq. (8),
+                     // ghosts included, before the forcing); nullptr to skip
   const void* jb_in; // particle driver: [2 planes] J_bz (E_z points), J_br (E_r points) at
                      // t_{k-1/2}, logical columns of x^k (auxiliary type)
   void* jb_zero;     // particle driver: [2 planes] cleared at the output index for the next step
@@ -74,7 +76,7 @@ struct AdjArgs {
   const void* lam_next;
   void* lam;
   void* work;
-  const void* site;   // site fields of step k (3 planes, auxiliary type, output index), fields on
+  const void* site;   // site record of step k (6 planes, auxiliary type, output index, as site_out)
   double* partials;
 };
 

@@ -437,6 +437,12 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
     A2 += f2[q];
   }
   const C A0 = nref + dA0;
+  if (SITE) {
+    // the pulled moments for the reverse sweep, which then needs none of the populations
+    bstore<A>(plane_rsrc<A>(a.site_out, plane, 3), oo, A0);
+    bstore<A>(plane_rsrc<A>(a.site_out, plane, 4), oo, A1);
+    bstore<A>(plane_rsrc<A>(a.site_out, plane, 5), oo, A2);
+  }
   C bz, br;
   const bool live = velocity<C>(A0, A1, A2, (C)p.n_floor, bz, br);
   const C uz = (C)p.lam * bz, ur = (C)p.lam * br;   // lattice velocity u* = beta c dt/dz
@@ -971,13 +977,15 @@ static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
   else step_kernel<ST, false, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
-// The site-field variant is the adjoint's forward recompute (no storage 3, no particle driver;
-// FP64 arithmetic on FP32 / FP16 storage for BGK only).
+// The site-record variant is the adjoint's forward recompute (no storage 3, no particle driver;
+// FP64 arithmetic on FP32 / FP16 storage for BGK only).  Without fields it takes the general
+// (wrap) variant: that case is not on any timed path.
 template <int ST, bool M64, int COLL>
 static void launch_step_s(const StepArgs& a, dim3 grid, hipStream_t st) {
   if constexpr (!neq_storage(ST) && (!M64 || COLL == 0)) {
-    if (a.p.fields_on && a.site_out) {
-      if (!a.p.per_z && !a.p.per_r) step_kernel<ST, true, M64, true, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+    if (a.site_out) {
+      if (!a.p.fields_on) step_kernel<ST, false, M64, true, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
+      else if (!a.p.per_z && !a.p.per_r) step_kernel<ST, true, M64, true, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
       else step_kernel<ST, true, M64, true, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
       return;
     }
