@@ -28,10 +28,11 @@ KERNEL_SOURCES = ("paper_2201_05473_amd/csrc/lbm_kernels.hip", "paper_2201_05473
 
 def bytes_per_site(storage: int) -> int:
     """Algorithmic HBM bytes per site and step of the fused kernel: 27 populations read and
-    written, and the auxiliary planes (3 moments, E_z, E_r, B_theta) read and written once."""
+    written, and the auxiliary planes (3 moments, E_z, E_r, B_theta) read and written once; FP32
+    storage adds the word of bfloat16 residuals of E_r and B_theta (read and written)."""
     s_pop = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
     s_aux = 8 if storage == 0 else 4
-    return 2 * 27 * s_pop + 2 * 6 * s_aux
+    return 2 * 27 * s_pop + 2 * 6 * s_aux + (2 * 4 if storage == 1 else 0)
 
 
 def kernel_hash() -> str:

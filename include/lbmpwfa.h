@@ -45,7 +45,10 @@ enum {
 };
 
 /* Storage precision of the populations.  F64: populations, fields and arithmetic in FP64.
- * F32: populations and fields in FP32, FP32 arithmetic.  F16: populations in FP16, fields and
+ * F32: populations and fields in FP32, FP32 arithmetic; E_r and B_theta carry a bfloat16
+ * residual each (one more 32-bit plane), so that the field update accumulates without an FP32
+ * rounding per step (compensated fields: the FP32 rounding of the large driver fields would
+ * otherwise set the E_z error near 1e-5).  F16: populations in FP16, fields and
  * arithmetic in FP32.  The density lattice is stored as the deviation from the rest equilibrium
  * w_i n_bg(z); diagnostics are always accumulated in FP64.  F16N: as F16, but each population
  * is stored as its part off the equilibrium (Eq. (9)) of the moments stored at its own site,
@@ -190,7 +193,8 @@ int lbm_moments(lbm_ctx* ctx, void* dst, int32_t dtype, int32_t dst_on_device);
 /* Fields of the state, [3][nr][nz]: the E_z, E_r, B_theta of Maxwell's equations (Eq. (5)) on
  * the radially half-shifted Yee grid (the paper names an FDTD/Yee scheme without its layout):
  * E_z at (z_i + dz/2, r_j), E_r at (z_i, (j + 1) dr), B_theta at (z_i + dz/2, (j + 1) dr); E at
- * t_{k-1} and B_theta at t_{k-1/2} after k steps.  dtype and placement as lbm_moments. */
+ * t_{k-1} and B_theta at t_{k-1/2} after k steps (LBM_F32 storage: each with its residual
+ * added, in FP64).  dtype and placement as lbm_moments. */
 int lbm_fields(lbm_ctx* ctx, void* dst, int32_t dtype, int32_t dst_on_device);
 
 /* Full state in FP64 on the host: [27][nr][nz] populations (lattice-major, raw values, not
@@ -205,7 +209,8 @@ int lbm_set_state(lbm_ctx* ctx, const double* src, int64_t step, int64_t shifts)
 
 /* Checkpoint in the native storage format, for bit-exact resume:
  * a 64-byte header (magic, storage, nz, nr, row pitch, step, shift count, plane stride) followed by the active
- * population, moment and field buffers as stored.  lbm_checkpoint_bytes gives its size.
+ * population, moment and field buffers as stored (with LBM_F32 the field buffer includes the
+ * plane of residuals).  lbm_checkpoint_bytes gives its size.
  * dst/src may be host or device memory (flag); both calls synchronise the stream.  lbm_load
  * returns LBM_EINVAL if the checkpoint was written for another grid or storage precision.  The
  * bunch of LBM_DRIVER_PARTICLES is not part of it: keep it with lbm_get_bunch and restore it with

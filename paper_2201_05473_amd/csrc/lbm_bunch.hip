@@ -303,7 +303,9 @@ __global__ void bunch_gauss_kernel(Physics p, const double* dens, void* Ev, int 
   for (int j = 0; j < p.nr; ++j) {
     const long long oo = (long long)j * p.pitch + i;
     cum += (j + 0.5) * dens[oo];
-    stv(E + oo, -p.h * cum / (j + 1.0));
+    const double v = -p.h * cum / (j + 1.0);
+    stv(E + oo, v);
+    set_field_lo<ST>(Ev, p.plane, oo, comp, v);
   }
 }
 

@@ -44,6 +44,8 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t pop_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
 size_t aux_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+// bytes of one group of field planes (E_z, E_r, B_theta, and the residual plane of FP32 storage)
+size_t field_bytes(size_t plane, int storage) { return (size_t)lbm::field_planes(storage) * plane * aux_bytes(storage); }
 
 // Validate a configuration; on success fill the derived physics.
 int validate(const lbm_config* c, Physics* p) {
@@ -149,10 +151,11 @@ Layout layout(const Physics& p, int storage) {
   const size_t plane = (size_t)p.plane;
   const size_t gb = round_up(27 * plane * pop_bytes(storage), 256);
   const size_t mb = round_up(3 * plane * aux_bytes(storage), 256);
+  const size_t eb = round_up(field_bytes(plane, storage), 256);
   size_t off = 0;
   for (int b = 0; b < 2; ++b) { L.g[b] = off; off += gb; }
   for (int b = 0; b < 2; ++b) { L.M[b] = off; off += mb; }
-  for (int b = 0; b < 2; ++b) { L.E[b] = off; off += mb; }
+  for (int b = 0; b < 2; ++b) { L.E[b] = off; off += eb; }
   L.partials = off;
   off += round_up((size_t)lbm::diag_blocks(p) * 8 * sizeof(double), 256);
   L.out = off;
@@ -448,18 +451,19 @@ struct CkptHeader {
   char pad[16];
 };
 static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
-const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '1'};
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '2'};
 
 size_t region_bytes(const lbm_ctx* c, int which) {
   const size_t plane = (size_t)c->p.plane;
-  return which == 0 ? 27 * plane * pop_bytes(c->storage) : 3 * plane * aux_bytes(c->storage);
+  return which == 0 ? 27 * plane * pop_bytes(c->storage)
+                    : (which == 1 ? 3 * plane * aux_bytes(c->storage) : field_bytes(plane, c->storage));
 }
 }  // namespace
 
 int lbm_checkpoint_bytes(lbm_ctx* c, size_t* bytes) {
   if (int rc_ = live(c)) return rc_;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + 2 * region_bytes(c, 1);
+  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + region_bytes(c, 1) + region_bytes(c, 2);
   return LBM_OK;
 }
 
@@ -486,7 +490,7 @@ int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
   size_t off = sizeof h;
   const void* src[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
   for (int r = 0; r < 3; ++r) {
-    const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
+    const size_t nb = region_bytes(c, r);
     const hipError_t e = hipMemcpyAsync(d + off, src[r], nb, kind, c->stream);
     if (e != hipSuccess) {
       (void)hipStreamSynchronize(c->stream);   // the queued header copy reads h
@@ -518,7 +522,7 @@ int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
   size_t off = sizeof h;
   void* dstp[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
   for (int r = 0; r < 3; ++r) {
-    const size_t nb = region_bytes(c, r == 0 ? 0 : 1);
+    const size_t nb = region_bytes(c, r);
     HIP_CHECK(hipMemcpyAsync(dstp[r], s + off, nb, kind, c->stream), "load copy");
     off += nb;
   }
@@ -607,7 +611,8 @@ AdjLayout adj_layout(const Physics& p, int storage) {
 // bytes of one stored state in the native layout (populations, moments, fields)
 size_t state_bytes(const Physics& p, int storage) {
   const size_t plane = (size_t)p.plane;
-  return round_up(27 * plane * pop_bytes(storage), 256) + 2 * round_up(3 * plane * aux_bytes(storage), 256);
+  return round_up(27 * plane * pop_bytes(storage), 256) + round_up(3 * plane * aux_bytes(storage), 256) +
+         round_up(field_bytes(plane, storage), 256);
 }
 
 struct StateView {
@@ -620,7 +625,7 @@ StateView state_at(char* base, const Physics& p, int storage) {
   const size_t plane = (size_t)p.plane;
   const size_t gb = round_up(27 * plane * pop_bytes(storage), 256);
   const size_t mb = round_up(3 * plane * aux_bytes(storage), 256);
-  return StateView{base, base + gb, base + gb + mb};
+  return StateView{base, base + gb, base + gb + mb};   // fields after the moments
 }
 
 int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
@@ -1135,10 +1140,11 @@ static int revolve_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int
   // snapshot 0 = x^0 (the context's state); lambda^N = dJ/dx^N
   const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
   const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
+  const size_t ebytes = round_up(field_bytes((size_t)p.plane, c->storage), 256);
   const StateView x0 = r.slot(0), ctx0{c->g(c->cur), c->M(c->cur), c->E(c->cur)};
   HIP_CHECK(hipMemcpyAsync(x0.g, ctx0.g, gbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
   HIP_CHECK(hipMemcpyAsync(x0.M, ctx0.M, mbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
-  HIP_CHECK(hipMemcpyAsync(x0.E, ctx0.E, mbytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
+  HIP_CHECK(hipMemcpyAsync(x0.E, ctx0.E, ebytes, hipMemcpyDeviceToDevice, c->stream), "snapshot");
   *snap0 = true;
   HIP_CHECK(hipMemsetAsync(r.w, 0, L.core_total, c->stream), "clear");
   {
@@ -1161,7 +1167,7 @@ static int revolve_run(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, int
   // the context's buffers served as scratch: restore the initial state
   HIP_CHECK(hipMemcpyAsync(ctx0.g, x0.g, gbytes, hipMemcpyDeviceToDevice, c->stream), "restore");
   HIP_CHECK(hipMemcpyAsync(ctx0.M, x0.M, mbytes, hipMemcpyDeviceToDevice, c->stream), "restore");
-  HIP_CHECK(hipMemcpyAsync(ctx0.E, x0.E, mbytes, hipMemcpyDeviceToDevice, c->stream), "restore");
+  HIP_CHECK(hipMemcpyAsync(ctx0.E, x0.E, ebytes, hipMemcpyDeviceToDevice, c->stream), "restore");
   HIP_CHECK(hipMemcpyAsync(grad, r.w + L.grad, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "download");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   *J = r.J;
@@ -1183,10 +1189,11 @@ int lbm_adjoint_revolve(lbm_ctx* c, const lbm_objective* obj, int64_t nsteps, in
       const Physics& p = c->p;
       const size_t gbytes = round_up(27 * (size_t)p.plane * pop_bytes(c->storage), 256);
       const size_t mbytes = round_up(3 * (size_t)p.plane * aux_bytes(c->storage), 256);
+      const size_t ebytes = round_up(field_bytes((size_t)p.plane, c->storage), 256);
       const StateView x0 = state_at((char*)ws + adj_layout(p, c->storage).core_total, p, c->storage);
       if (e == hipSuccess) e = hipMemcpyAsync(c->g(c->cur), x0.g, gbytes, hipMemcpyDeviceToDevice, c->stream);
       if (e == hipSuccess) e = hipMemcpyAsync(c->M(c->cur), x0.M, mbytes, hipMemcpyDeviceToDevice, c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(c->E(c->cur), x0.E, mbytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(c->E(c->cur), x0.E, ebytes, hipMemcpyDeviceToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) c->broken = true;
     }

@@ -171,6 +171,9 @@ template <int POL = 0> __device__ __forceinline__ double bld(double*, Rsrc r, ui
 template <int POL = 0> __device__ __forceinline__ __half bld(__half*, Rsrc r, uint32_t off) {
   return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, POL));
 }
+template <int POL = 0> __device__ __forceinline__ uint32_t bld(uint32_t*, Rsrc r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL);
+}
 // load of element `idx` of an array of T through resource r
 template <typename T, int POL = 0> __device__ __forceinline__ T bload(Rsrc r, uint32_t idx) {
   return bld<POL>((T*)nullptr, r, idx * (uint32_t)sizeof(T));
@@ -188,12 +191,74 @@ __device__ __forceinline__ void bput(__half*, Rsrc r, uint32_t idx, float v) {
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, (int)(idx * 2u), 0, 0);
 }
 __device__ __forceinline__ void bput(__half*, Rsrc r, uint32_t idx, double v) { bput((__half*)nullptr, r, idx, (float)v); }
+__device__ __forceinline__ void bput(uint32_t*, Rsrc r, uint32_t idx, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)(idx * 4u), 0, 0);
+}
 template <typename T, typename V> __device__ __forceinline__ void bstore(Rsrc r, uint32_t idx, V v) {
   bput((T*)nullptr, r, idx, v);
 }
 // resource over plane c of a group of planes of `plane` elements of T starting at base
 template <typename T> __device__ __forceinline__ Rsrc plane_rsrc(const void* base, long long plane, int c) {
   return brsrc((const T*)base + (long long)c * plane, (uint32_t)(plane * (long long)sizeof(T)));
+}
+
+// Compensated fields of FP32 storage.  E_r and B_theta are kept as an FP32 value plus the part
+// that value misses, rounded to bfloat16 (8 more significand bits: 2^-32 relative together), so
+// that the field update accumulates its increments without an FP32 rounding per step.  The two
+// residuals of a cell share one 32-bit word of a fourth field plane: E_r's in the low half,
+// B_theta's in the high half.  Without them, the FP32 rounding of the large driver fields E_r and
+// B_theta, stored step after step, sets the E_z error of a young wake near 1e-5 (CPU emulation in
+// the oracle: 1.0e-5 after 400 steps of C2's 512 x 128 copy; with the residuals, 6e-7).
+// bfloat16 of x, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ __forceinline__ float lo_er(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ __forceinline__ float lo_b(uint32_t w) { return __builtin_bit_cast(float, w & 0xFFFF0000u); }
+__device__ __forceinline__ uint32_t lo_pack(float er_lo, float b_lo) {
+  return bf16_rne(er_lo) | (bf16_rne(b_lo) << 16);
+}
+// FP32 value and residual of a double
+__device__ __forceinline__ void split_lo(double v, float& hi, float& lo) {
+  hi = (float)v;
+  lo = (float)(v - (double)hi);
+}
+// (hi + lo) + d in FP32 without losing d's low bits: hi becomes the rounded sum, lo the part it
+// misses (Knuth's two-sum of hi and d, the error added to lo, then renormalised).  No contraction
+// into FMAs, which would change the error terms.
+__device__ __forceinline__ void acc_comp(float& hi, float& lo, float d) {
+#pragma clang fp contract(off)
+  const float s = hi + d;
+  const float bp = s - hi;
+  const float err = (hi - (s - bp)) + (d - bp);
+  const float l = lo + err;
+  const float h2 = s + l;
+  lo = l - (h2 - s);
+  hi = h2;
+}
+
+// Residual of field component c (0 E_z, 1 E_r, 2 B_theta) of cell oo, in a field group of planes
+// of `plane` elements (zero where the storage keeps none)
+template <int ST>
+__device__ __forceinline__ double field_lo(const void* E, long long plane, long long oo, int c) {
+  if constexpr (fields_lo(ST)) {
+    if (c == 0) return 0.0;
+    const uint32_t w = ((const uint32_t*)E)[3 * plane + oo];
+    return (double)(c == 1 ? lo_er(w) : lo_b(w));
+  } else {
+    return 0.0;
+  }
+}
+// Store the residual of v (whose FP32 value the caller stores) for field component c of cell oo
+template <int ST>
+__device__ __forceinline__ void set_field_lo(void* E, long long plane, long long oo, int c, double v) {
+  if constexpr (fields_lo(ST)) {
+    if (c == 0) return;
+    float hi, lo;
+    split_lo(v, hi, lo);
+    uint32_t* w = (uint32_t*)E + 3 * plane + oo;
+    *w = c == 1 ? ((*w & 0xFFFF0000u) | bf16_rne(lo)) : ((*w & 0xFFFFu) | (bf16_rne(lo) << 16));
+  }
 }
 
 // Population loads of the step: FP64 populations are read with non-temporal loads (measured on

@@ -21,6 +21,11 @@ constexpr int DIAG_MAX_BLOCKS = 2048;
 // lbm_diagnostics_noalloc).
 constexpr int MAX_DEVICES = 64;
 
+// FP32 storage (1) keeps bfloat16 residuals of E_r and B_theta in a fourth field plane
+// (compensated fields); the other storages have three field planes.
+__host__ __device__ constexpr bool fields_lo(int storage) { return storage == 1; }
+__host__ __device__ constexpr int field_planes(int storage) { return fields_lo(storage) ? 4 : 3; }
+
 // Physical and grid parameters of a run (fixed for a context).
 struct Physics {
   int nz, nr, pitch;
@@ -48,7 +53,8 @@ struct StepArgs {
   void* g_out;
   const void* M_in;
   void* M_out;
-  const void* E_in;  // [3 planes] E_z, E_r, B_theta
+  const void* E_in;  // [3 planes] E_z, E_r, B_theta; FP32 storage: a fourth plane with the
+                     // bfloat16 residuals of E_r (low half) and B_theta (high half) of each cell
   void* E_out;
   void* site_out;    // optional, for the reverse sweep: [6 planes] at the output index, E_z, E_r,
                      // B_theta averaged to the sites as used by the fluid (fields on; else left

@@ -59,15 +59,29 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
   // straight from memory to LDS (no registers held while the population loads are in flight);
   // otherwise they pass through registers (conversion to FP64).
   constexpr bool HDMA = std::is_same<A, float>::value && std::is_same<CF, float>::value;
+  // FP32 storage: compensated E_r and B_theta (their bfloat16 residuals in a fourth field plane).
+  // With FP32 field arithmetic the residual words are a fifth LDS tile over B's halo (E_r's
+  // residual of the cell whose B is at a slot shares its word) and the updates accumulate with
+  // acc_comp; with FP64 field arithmetic the residuals are folded into the FP64 tiles at load and
+  // split off again at the store.
+  constexpr bool XLO = fields_lo(ST) && FIELDS;
+  constexpr bool COMP = XLO && HDMA;
   __shared__ CF sMst[3][SM * NTHREADS];
   __shared__ CF sBost[SB * NTHREADS];
   __shared__ CF sEzst[SEZ * NTHREADS];
   __shared__ CF sErst[SER * NTHREADS];
+  __shared__ uint32_t sXst[COMP ? SB * NTHREADS : 1];
   CF(*const sM[3])[MZ] = {reinterpret_cast<CF(*)[MZ]>(sMst[0]), reinterpret_cast<CF(*)[MZ]>(sMst[1]),
                           reinterpret_cast<CF(*)[MZ]>(sMst[2])};
   CF(*const sBo)[BZ] = reinterpret_cast<CF(*)[BZ]>(sBost);
   CF(*const sEz)[EZZ] = reinterpret_cast<CF(*)[EZZ]>(sEzst);
   CF(*const sEr)[ERZ] = reinterpret_cast<CF(*)[ERZ]>(sErst);
+  // residual words: slot (b, a) of the B tile; E_r slot (b, a) is word (b + 1, a + 1).  Halves are
+  // written with 16-bit stores (little endian: E_r's residual at the even halfword)
+  uint32_t(*const sX)[BZ] = reinterpret_cast<uint32_t(*)[BZ]>(sXst);
+  uint16_t* const sX16 = reinterpret_cast<uint16_t*>(sXst);
+  auto xer16 = [&](int b, int a) -> uint16_t& { return sX16[2 * (b * BZ + a)]; };
+  auto xb16 = [&](int b, int a) -> uint16_t& { return sX16[2 * (b * BZ + a) + 1]; };
   __shared__ CF sJ[2][MR][MZ];
   __shared__ CF sBn[BNR][BNZ];
   __shared__ double sN[MZ];
@@ -108,6 +122,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
   const Rsrc Ezp = plane_rsrc<A>(Ein, plane, 0);
   const Rsrc Erp = plane_rsrc<A>(Ein, plane, 1);
   const Rsrc Bp = plane_rsrc<A>(Ein, plane, 2);
+  const Rsrc Xp = plane_rsrc<uint32_t>(Ein, plane, 3);   // residual words (fields_lo storage)
 
   // --- 1. halo loads: into LDS (HDMA), or into registers ------------------------------------
   // Every lane loads from a clamped, in-range address; with HDMA a wave's 64 words land at its
@@ -122,6 +137,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
   };
   A hm[HDMA ? 1 : SM][3];
   A hb[HDMA ? 1 : SB], hez[HDMA ? 1 : SEZ], her[HDMA ? 1 : SER];
+  uint32_t hxb[XLO && !HDMA ? SB : 1], hxr[XLO && !HDMA ? SER : 1];
   A hjz[DRV && !HDMA ? SEZ : 1], hjr[DRV && !HDMA ? SER : 1];
 #pragma unroll
   for (int s = 0; s < SM; ++s) {
@@ -135,7 +151,13 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       const int t = min(tid + s * NTHREADS, NB - 1);
-      hload(Bp, rrow(j0 - 2 + t / BZ) * pitch + zcol(i0 - 2 + t % BZ), sBost, s, hb[HDMA ? 0 : s]);
+      const uint32_t off = rrow(j0 - 2 + t / BZ) * pitch + zcol(i0 - 2 + t % BZ);
+      hload(Bp, off, sBost, s, hb[HDMA ? 0 : s]);
+      if constexpr (COMP)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            Xp, (__attribute__((address_space(3))) void*)(sXst + s * NTHREADS + wv * 64), 4, (int)(off * 4u), 0, 0, 0);
+      else if constexpr (XLO)
+        hxb[s] = bload<uint32_t>(Xp, off);
     }
 #pragma unroll
     for (int s = 0; s < SEZ; ++s) {
@@ -149,6 +171,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       const int t = min(tid + s * NTHREADS, NER - 1);
       const uint32_t off = rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ);
       hload(Erp, off, sErst, s, her[HDMA ? 0 : s]);
+      if constexpr (XLO && !HDMA) hxr[s] = bload<uint32_t>(Xp, off);
       if (DRV) hload(plane_rsrc<A>(a.jb_in, plane, 1), off, sJbrst, s, hjr[HDMA ? 0 : s]);
     }
   }
@@ -272,14 +295,21 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
           const int t = tid + s * NTHREADS;
-          if (t < 2 * BZ) sBo[t / BZ][t % BZ] = CF(0);
+          if (t < 2 * BZ) {
+            sBo[t / BZ][t % BZ] = CF(0);
+            if constexpr (COMP) sX[t / BZ][t % BZ] = 0u;   // B's residual, and E_r's of row -1
+          }
         }
       }
     } else {
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         const int t = tid + s * NTHREADS;
-        if (t < NB) sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? CF(0) : (CF)hb[s];
+        if (t < NB) {
+          CF v = (CF)hb[s];
+          if constexpr (XLO) v += (CF)lo_b(hxb[s]);
+          sBo[t / BZ][t % BZ] = (j0 - 2 + t / BZ) < 0 ? CF(0) : v;
+        }
       }
 #pragma unroll
       for (int s = 0; s < SEZ; ++s) {
@@ -290,7 +320,11 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
 #pragma unroll
       for (int s = 0; s < SER; ++s) {
         const int t = tid + s * NTHREADS;
-        if (t < NER) sEr[t / ERZ][t % ERZ] = (CF)her[s];
+        if (t < NER) {
+          CF v = (CF)her[s];
+          if constexpr (XLO) v += (CF)lo_er(hxr[s]);
+          sEr[t / ERZ][t % ERZ] = v;
+        }
         if (DRV && t < NER) sJbr[t / ERZ][t % ERZ] = (CF)hjr[s];
       }
     }
@@ -306,7 +340,15 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
         // (B_j + j (B_j - B_{j-1})) / r_j: same value, no large cancellation at large j in
         // reduced precision; the axis flux (j = 0) vanishes
         const CF bj = sBo[bb + 1][aa + 1];
-        const CF curl = (bj + (CF)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
+        CF curl;
+        if constexpr (COMP) {
+          // B_theta's residuals enter the difference and the axis term
+          const CF lj = lo_b(sX[bb + 1][aa + 1]), lm = lo_b(sX[bb][aa + 1]);
+          const CF d = (bj - sBo[bb][aa + 1]) + (lj - lm);
+          curl = (bj + (lj + (CF)jj * d)) * sIr[bb];
+        } else {
+          curl = (bj + (CF)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
+        }
         const CF jf = CF(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
         const CF jb = DRV ? sJbz[DRV ? bb : 0][DRV ? aa : 0] : sDz[aa] * sDr[bb];
         sEz[bb][aa] = sEz[bb][aa] + dtf * (curl + jf + jb);
@@ -316,10 +358,19 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       const int bb = t / ERZ, aa = t % ERZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
       if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
-        const CF curl = -(sBo[bb + 1][aa + 1] - sBo[bb + 1][aa]) * ih;   // -dB/dz
+        CF dB = sBo[bb + 1][aa + 1] - sBo[bb + 1][aa];
+        if constexpr (COMP) dB += lo_b(sX[bb + 1][aa + 1]) - lo_b(sX[bb + 1][aa]);
+        const CF curl = -dB * ih;   // -dB/dz
         const CF jf = CF(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
         const CF jbr = DRV ? sJbr[DRV ? bb : 0][DRV ? aa : 0] : CF(0);
-        sEr[bb][aa] = sEr[bb][aa] + dtf * (curl + jf + jbr);
+        if constexpr (COMP) {
+          float hi = sEr[bb][aa], lo = lo_er(sX[bb + 1][aa + 1]);
+          acc_comp(hi, lo, dtf * (curl + jf + jbr));
+          sEr[bb][aa] = hi;
+          xer16(bb + 1, aa + 1) = (uint16_t)bf16_rne(lo);
+        } else {
+          sEr[bb][aa] = sEr[bb][aa] + dtf * (curl + jf + jbr);
+        }
       }
     }
     __syncthreads();
@@ -330,7 +381,10 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
         for (int bb = tid; bb < EZR; bb += NTHREADS) sEz[bb][0] = sEz[bb][1];
       const int af = nz - (i0 - 1);   // LDS column of i = nz
       if (af >= 1 && af < ERZ)
-        for (int bb = tid; bb < ERR; bb += NTHREADS) sEr[bb][af] = sEr[bb][af - 1];
+        for (int bb = tid; bb < ERR; bb += NTHREADS) {
+          sEr[bb][af] = sEr[bb][af - 1];
+          if constexpr (COMP) xer16(bb + 1, af + 1) = xer16(bb + 1, af);
+        }
     }
     __syncthreads();
     // ... then the r rule: outer E_z copy, E_r = 0 on the axis
@@ -348,16 +402,31 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       const int bb = t / BNZ, aa = t % BNZ;
       const int ii = i0 - 1 + aa, jj = j0 - 1 + bb;
       CF v = CF(0);
+      float vlo = 0.f;
       if ((p.per_z || (ii >= 0 && ii < nz)) && jj >= 0 && jj < nr) {
         const CF dez = (sEz[bb + 1][aa] - sEz[bb][aa]) * ih;
-        const CF der = (sEr[bb][aa + 1] - sEr[bb][aa]) * ih;
-        v = sBo[bb + 1][aa + 1] + dtf * (dez - der);
+        CF dEr = sEr[bb][aa + 1] - sEr[bb][aa];
+        if constexpr (COMP) dEr += lo_er(sX[bb + 1][aa + 2]) - lo_er(sX[bb + 1][aa + 1]);
+        const CF der = dEr * ih;
+        if constexpr (COMP) {
+          float hi = sBo[bb + 1][aa + 1];
+          vlo = lo_b(sX[bb + 1][aa + 1]);
+          acc_comp(hi, vlo, dtf * (dez - der));
+          v = hi;
+        } else {
+          v = sBo[bb + 1][aa + 1] + dtf * (dez - der);
+        }
       }
       sBn[bb][aa] = v;
+      // B^{k+1/2}'s residual replaces B^{k-1/2}'s in the same word (read above by this thread only)
+      if constexpr (COMP) xb16(bb + 1, aa + 1) = (uint16_t)bf16_rne(vlo);
     }
     __syncthreads();
     if (!p.per_z && i0 == 0)
-      for (int bb = tid; bb < BNR; bb += NTHREADS) sBn[bb][0] = sBn[bb][1];   // rear copy
+      for (int bb = tid; bb < BNR; bb += NTHREADS) {   // rear copy
+        sBn[bb][0] = sBn[bb][1];
+        if constexpr (COMP) xb16(bb + 1, 1) = xb16(bb + 1, 2);
+      }
     __syncthreads();
   } else {
     __syncthreads();
@@ -382,6 +451,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       bstore<A>(plane_rsrc<A>(Mout, plane, c), oo, C(0));
       bstore<A>(plane_rsrc<A>(Eout, plane, c), oo, C(0));
     }
+    if constexpr (fields_lo(ST)) bstore<uint32_t>(plane_rsrc<uint32_t>(Eout, plane, 3), oo, 0u);
     return;
   }
 
@@ -673,9 +743,19 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
     bstore<A>(plane_rsrc<A>(Eout, plane, 0), oo, (A)sEz[ty + 1][tx + 1]);
     bstore<A>(plane_rsrc<A>(Eout, plane, 1), oo, (A)sEr[ty + 1][tx + 1]);
     bstore<A>(plane_rsrc<A>(Eout, plane, 2), oo, (A)sBn[ty + 1][tx + 1]);
+    if constexpr (COMP) {
+      bstore<uint32_t>(plane_rsrc<uint32_t>(Eout, plane, 3), oo, sX[ty + 2][tx + 2]);
+    } else if constexpr (XLO) {
+      float eh, el, bh, bl;
+      split_lo((double)sEr[ty + 1][tx + 1], eh, el);
+      split_lo((double)sBn[ty + 1][tx + 1], bh, bl);
+      bstore<uint32_t>(plane_rsrc<uint32_t>(Eout, plane, 3), oo, lo_pack(el, bl));
+    }
   } else {
     const uint32_t io = j * pitch + i;
     for (int c = 0; c < 3; ++c) bstore<A>(plane_rsrc<A>(Eout, plane, c), oo, bload<A>(plane_rsrc<A>(Ein, plane, c), io));
+    if constexpr (fields_lo(ST))
+      bstore<uint32_t>(plane_rsrc<uint32_t>(Eout, plane, 3), oo, bload<uint32_t>(plane_rsrc<uint32_t>(Ein, plane, 3), io));
   }
 }
 
@@ -739,6 +819,12 @@ __global__ void init_fields_kernel(Physics p, void* Ev) {
     stv(E + oo, 0.0);
     stv(E + p.plane + oo, er);
     stv(E + 2 * p.plane + oo, b);
+    if constexpr (fields_lo(ST)) {
+      float eh, el, bh, bl;
+      split_lo(er, eh, el);
+      split_lo(b, bh, bl);
+      ((uint32_t*)Ev)[3 * p.plane + oo] = lo_pack(el, bl);
+    }
   }
 }
 
@@ -775,7 +861,7 @@ __global__ void fields_out_kernel(Physics p, const void* Ev, void* dst, int dst_
   const long long oo = (long long)j * p.pitch + i;
   const long long u = (long long)j * p.nz + i, pl = (long long)p.nr * p.nz;
   for (int c = 0; c < 3; ++c) {
-    const double v = (double)E[c * p.plane + oo];
+    const double v = (double)E[c * p.plane + oo] + field_lo<ST>(Ev, p.plane, oo, c);
     if (dst_f64) ((double*)dst)[c * pl + u] = v;
     else ((float*)dst)[c * pl + u] = (float)v;
   }
@@ -812,7 +898,7 @@ __global__ void state_get_kernel(Physics p, long long s, const void* gv, const v
     v = (double)((const A*)Mv)[(c - 27) * p.plane + oo];
     if (c == 27) v += nbg(p, (double)(s + i) * p.h);
   } else {
-    v = (double)((const A*)Ev)[(c - 30) * p.plane + oo];
+    v = (double)((const A*)Ev)[(c - 30) * p.plane + oo] + field_lo<ST>(Ev, p.plane, oo, c - 30);
   }
   dst[(long long)j * p.nz + i] = v;
 }
@@ -837,6 +923,7 @@ __global__ void state_set_kernel(Physics p, long long s, void* gv, void* Mv, voi
     stv(((A*)Mv) + (c - 27) * p.plane + oo, v);
   } else {
     stv(((A*)Ev) + (c - 30) * p.plane + oo, v);
+    set_field_lo<ST>(Ev, p.plane, oo, c - 30, v);
   }
 }
 
@@ -888,13 +975,14 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Physics p, lo
     const double z = (double)(s + i) * h;
     const double nb0 = nbg(p, z);
     const double m0 = (double)M[oo] + nb0, m1 = M[p.plane + oo], m2 = M[2 * p.plane + oo];
-    const double ez = E[oo], er = E[p.plane + oo], b = E[2 * p.plane + oo];
+    const double ez = E[oo], er = (double)E[p.plane + oo] + field_lo<ST>(Ev, p.plane, oo, 1),
+                 b = (double)E[2 * p.plane + oo] + field_lo<ST>(Ev, p.plane, oo, 2);
     const double twopi = 6.283185307179586;
     v[0] += twopi * r * h * h * m0;
     v[1] += 0.5 * twopi * h * h * (r * ez * ez + re * er * er + re * b * b);
     if (i >= 1) {
       const double ezl = E[oo - 1];
-      const double erb = j > 0 ? (double)E[p.plane + oo - p.pitch] : 0.0;
+      const double erb = j > 0 ? (double)E[p.plane + oo - p.pitch] + field_lo<ST>(Ev, p.plane, oo - p.pitch, 1) : 0.0;
       const double div = (ez - ezl) / h + ((j + 1.0) * er - j * erb) / ((j + 0.5) * h);
       // driver density at t_{k-1}: the closed form, or the bunch density deposited at the nodes
       const double nd = drv ? drv[oo] : driver<double>(p, z, r, ((double)k - 1.0) * p.dt);

@@ -136,7 +136,8 @@ def test_revolve_workspace_scales_with_snapshots(lib):
     b1 = lbm_adjoint_revolve_workspace_bytes(cfg, 1)
     b5 = lbm_adjoint_revolve_workspace_bytes(cfg, 5)
     plane = 1024 * 256 + 64   # pitched rows, plus the 256-byte plane pad of FP32 storage
-    state = plane * (27 * 4 + 6 * 4)
+    # 27 populations, 3 moments, 3 fields and the residual word of E_r and B_theta (FP32 storage)
+    state = plane * (27 * 4 + 3 * 4 + 4 * 4)
     assert b5 - b1 == 4 * state
     with pytest.raises(Exception):
         lbm_adjoint_revolve_workspace_bytes(cfg, 0)

@@ -247,8 +247,11 @@ def test_adjoint_rejections():
 def test_regularised_operator_tames_the_nonlinear_wake():
     """The paper attributes the rise of the smallest usable D in the nonlinear regime to BGK.
     Nonlinear wake (n_b = 2, Q~ = 3.9; 2048 x 256, dz = 0.02, FP32, 6,000 steps) at tau = 0.55
-    (D = 0.0017, below BGK's usable range): BGK's most negative density is about -0.04, the
-    regularised operator's about -5e-5.  The test asks for a hundredfold smaller excursion."""
+    (D = 0.0017, below BGK's usable range): BGK's most negative density is about -1e-2, the
+    regularised operator's about -5e-5.  The test asks for a hundredfold smaller excursion.  BGK's
+    excursion grows from rounding noise, so its size depends on the field precision: -0.04 with
+    plain FP32 fields, -0.0099 with the compensated E_r and B_theta; the bound on BGK only asks that
+    it is clearly negative."""
     import math
 
     from paper_2201_05473_amd import Lattice
@@ -266,5 +269,5 @@ def test_regularised_operator_tames_the_nonlinear_wake():
         nmin[coll] = float(n.min())
         print(f"[nonlinear wake] collision={coll} tau=0.55 n_min={nmin[coll]:.3e}", flush=True)
         lat.close()
-    assert nmin[wl.BGK] < -1e-2, nmin
+    assert nmin[wl.BGK] < -5e-3, nmin
     assert math.isfinite(nmin[wl.REG]) and abs(min(nmin[wl.REG], 0.0)) < 1e-2 * abs(nmin[wl.BGK]), nmin

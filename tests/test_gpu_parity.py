@@ -222,14 +222,15 @@ def test_fp32_fp16_parity_c2_copy():
     E_z is not a near-cancellation residual), FP32 and FP16 storage against the FP64 oracle
     after 400 steps: max-norm relative error of n, E_z, E_r.
 
-    Bounds.  Density with FP32 arithmetic: 1e-5 (measured 4e-8); with FP64 arithmetic on FP32
-    storage 1e-7 (the collision then conserves mass to FP64 round-off).  Fields: on this young wake
-    the FP32 storage of E_r and B_theta sets a floor near 1e-5 for E_z.  Rounding only those two
-    fields to FP32 after every step of the oracle gives E_z 1.0e-5, rounding only the populations
-    and moments 3e-8, rounding E_z alone 6e-7; FP64 arithmetic on FP32 storage measures 9.9e-6 on
-    the GPU.  So the FP32-arithmetic fields are held to 1.5e-5 and to 1.5 times that floor
-    (measured 1.27e-5 for E_z with compensated FP32 equilibrium sums; a plain FP32 sum gave
-    2.0e-5).  FP16 storage: 5e-3 (11-bit significand of the stored
+    Bounds.  FP32 storage keeps E_r and B_theta with bfloat16 residuals (compensated fields).
+    Without them the FP32 rounding of those two stored fields set a floor near 1e-5 for E_z on this
+    young wake (CPU emulation in the oracle, rounding only E_r and B_theta to FP32 after every
+    step: 1.0e-5; the GPU measured 9.9e-6 with FP64 arithmetic and 1.27e-5 with FP32); with the
+    residuals the emulation gives 6e-7.  Measured now: FP32 arithmetic n 6.7e-8, E_z 1.0e-6,
+    E_r 4.0e-7; FP64 arithmetic on FP32 storage n 7.8e-9, E_z 6.8e-7, E_r 2.2e-7.  Held to: the
+    1e-5 of the target for every quantity with FP32 arithmetic, and 3e-6 for its fields (a
+    third of the uncompensated floor, so a return of that floor fails); FP64 arithmetic: n 1e-7,
+    fields 2e-6.  FP16 storage: 5e-3 (11-bit significand of the stored
     deviations).  FP16N storage (the part off each site's equilibrium in FP16): fields 5e-4 and
     density 5e-5 (measured 1.4e-4 / 2.2e-4 / 1.4e-5), and at most a quarter of FP16's field error
     (measured a tenth)."""
@@ -248,10 +249,9 @@ def test_fp32_fp16_parity_c2_copy():
         print(storage, m64, errs[(storage, m64)], flush=True)
         lat.close()
     f32, floor = errs[(wl.F32, 0)], errs[(wl.F32, 1)]
-    assert f32["n"] < 1e-5 and floor["n"] < 1e-7, errs
+    assert max(f32.values()) < 1e-5 and floor["n"] < 1e-7, errs
     for q in ("Ez", "Er"):
-        assert floor[q] < 1.5e-5, (q, errs)
-        assert f32[q] < 1.5e-5 and f32[q] < 1.5 * floor[q], (q, errs)
+        assert f32[q] < 3e-6 and floor[q] < 2e-6, (q, errs)
     for key in ((wl.F16, 0), (wl.F16, 1)):
         assert max(errs[key].values()) < 5e-3, errs
     for m64 in (0, 1):
