@@ -1058,7 +1058,8 @@ template <int ST, bool M64, int COLL>
 static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
   const bool np = !a.p.per_z && !a.p.per_r;
   const bool drv = a.p.driver == 1;
-  if (a.p.fields_on && drv) step_kernel<ST, true, M64, false, COLL, true, 1><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  if (a.p.fields_on && drv && np) step_kernel<ST, true, M64, false, COLL, false, 1><<<grid, dim3(NTHREADS), 0, st>>>(a);
+  else if (a.p.fields_on && drv) step_kernel<ST, true, M64, false, COLL, true, 1><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else if (a.p.fields_on && np) step_kernel<ST, true, M64, false, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else if (a.p.fields_on) step_kernel<ST, true, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
   else if (np) step_kernel<ST, false, M64, false, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);

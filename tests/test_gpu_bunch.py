@@ -51,6 +51,8 @@ CASES = {
     # fixed window, TRT collision
     "fixed_trt": dict(cfg=dict(collision=wl.TRT, trt_magic=0.25), gamma=20.0, emittance=0.1, spread=0.01,
                       steps=30),
+    # periodic z (the step variant with the wrap code; non-periodic grids take the one without)
+    "periodic_z": dict(cfg=dict(periodic=1), gamma=20.0, emittance=0.1, spread=0.01, steps=30),
 }
 
 
