@@ -117,39 +117,30 @@ __device__ __forceinline__ void current_vjp(const Physics& p, const T M[3], T jz
 // (E_z, E_r, B_theta averaged to the site as the fluid used them, and the moments of the pulled
 // populations) comes from a.site, written by the forward step's recompute at the output index.
 // ------------------------------------------------------------------------------------------
-// Site part of a reverse step for the tile whose first site is (i0, j0) (logical columns of x^k).
-// mreg: M_bar^{k+1} of the thread's site output, when the caller has it in registers (else read
-// from lam_next).  theta partials are added to part.  Every thread of the block must call it.
-template <int ST, int COLL>
-__device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const typename Mode<ST, false>::C* mreg, double part[4]) {
-  using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
-  using T = typename Mode<ST, false>::C;   // arithmetic (FP64 for FP64 storage, else FP32)
-  const Physics& p = a.p;
+// The site part's loads (see site_body), issued by the caller ahead of other work.
+template <int ST> struct SiteIn {
+  typename Mode<ST, false>::A gbar[27], mbar[3], sfield[3], amom[3];
+  bool gok[9];
+};
 
+// Loads of the site part for the tile whose first site is (i0, j0): g_bar^{k+1} at the site's
+// output position (the transposed pull of f_bar^{k+1}, or read directly), M_bar^{k+1} unless the
+// caller has it in registers (with_mbar false), and the site record the forward step wrote at the
+// output index: the site fields and the moments A of the pulled populations (ghosts included).
+// The collision's Jacobian depends on the pulled populations only through A, so the populations
+// of x^k are not read.  Every read is of data written before the launch.
+template <int ST>
+__device__ __forceinline__ void site_load(const AdjArgs& a, int i0, int j0, bool with_mbar, SiteIn<ST>& in) {
+  using A = typename Mode<ST, false>::A;
+  const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
   const long long plane = p.plane;
   const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
-  const double h = p.h;
-  const T dt = (T)p.dt, lam = (T)p.lam, floor_ = (T)p.n_floor;
   const A* __restrict__ L = (const A*)a.lam_next;
   const A* __restrict__ Sf = (const A*)a.site;
-
   const int i = i0 + tx, j = j0 + ty;
-  const bool mine = i < nz && j < nr;
-  const bool dropped = a.shift && i == 0;   // this column leaves the window in step k
   const int ic = i < nz ? i : nz - 1, jc = j < nr ? j : nr - 1;
   const int ib = (ic - a.shift) < 0 ? 0 : ic - a.shift;   // output index in x^{k+1}
-
-  // loads: g_bar^{k+1} at the site's output position (the transposed pull of f_bar^{k+1}, or
-  // read directly), M_bar^{k+1}, and the site record the forward step wrote at the output
-  // index: the site fields and the moments A of the pulled populations (ghosts included).  The
-  // collision's Jacobian depends on the pulled populations only through A, so the populations of
-  // x^k are not read.
-  A gbar[27];
-  A mbar[3];
-  A sfield[3] = {A(0), A(0), A(0)};
-  A amom[3];
-  bool gok[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     int yi = ib, yj = jc;
@@ -162,19 +153,45 @@ __device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, cons
       if (p.per_r) yj = wrap1(yj, nr);
       else if (yj < 0 || yj >= nr) { ok = false; yj = yj < 0 ? 0 : nr - 1; }
     }
-    gok[q] = ok;
+    in.gok[q] = ok;
     const int yo = yj * pitch + yi;
 #pragma unroll
-    for (int kk = 0; kk < 3; ++kk) gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
+    for (int kk = 0; kk < 3; ++kk) in.gbar[9 * kk + q] = (L + (9 * kk + q) * plane)[yo];
   }
   const int so = jc * pitch + ib;
 #pragma unroll
-  for (int kk = 0; kk < 3; ++kk) mbar[kk] = mreg ? A(0) : (L + (27 + kk) * plane)[so];
-  if (p.fields_on)
+  for (int kk = 0; kk < 3; ++kk) in.mbar[kk] = with_mbar ? (L + (27 + kk) * plane)[so] : A(0);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sfield[c] = (Sf + c * plane)[so];
+  for (int c = 0; c < 3; ++c) in.sfield[c] = p.fields_on ? (Sf + c * plane)[so] : A(0);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) amom[c] = (Sf + (3 + c) * plane)[so];
+  for (int c = 0; c < 3; ++c) in.amom[c] = (Sf + (3 + c) * plane)[so];
+}
+
+// Site part of a reverse step for the tile whose first site is (i0, j0) (logical columns of x^k),
+// from its loads (site_load).  mreg: M_bar^{k+1} of the thread's site output, when the caller has
+// it in registers (else in.mbar).  theta partials are added to part.
+template <int ST, int COLL>
+__device__ __forceinline__ void site_body(const AdjArgs& a, int i0, int j0, const typename Mode<ST, false>::C* mreg,
+                                          double part[4], const SiteIn<ST>& in) {
+  using A = typename Mode<ST, false>::A;   // auxiliary planes and adjoint variables
+  using T = typename Mode<ST, false>::C;   // arithmetic (FP64 for FP64 storage, else FP32)
+  const Physics& p = a.p;
+
+  const int nz = p.nz, nr = p.nr, pitch = p.pitch;
+  const long long plane = p.plane;
+  const int tid = threadIdx.x, tx = tid % TZ, ty = tid / TZ;
+  const double h = p.h;
+  const T dt = (T)p.dt, lam = (T)p.lam, floor_ = (T)p.n_floor;
+  const A* __restrict__ L = (const A*)a.lam_next;
+
+  const int i = i0 + tx, j = j0 + ty;
+  const bool mine = i < nz && j < nr;
+  const bool dropped = a.shift && i == 0;   // this column leaves the window in step k
+  const A (&gbar)[27] = in.gbar;
+  const A (&mbar)[3] = in.mbar;
+  const A (&sfield)[3] = in.sfield;
+  const A (&amom)[3] = in.amom;
+  const bool (&gok)[9] = in.gok;
 
   if (a.shift && i == nz && j < nr) {
     // the column dropped in this step (column 0) has no site: zero adjoint sources.  Written
@@ -401,7 +418,10 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
   const int gx = (a.p.nz + TZ - 1) / TZ, gy = (a.p.nr + TR - 1) / TR;
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   double part[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(ramp_len, n0, sigma_r, n_b)
-  site_body<ST, COLL>(a, (tile % gx) * TZ, (tile / gx) * TR, nullptr, part);
+  const int i0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
+  SiteIn<ST> in;
+  site_load<ST>(a, i0, j0, true, in);
+  site_body<ST, COLL>(a, i0, j0, nullptr, part, in);
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
 }
 
@@ -411,10 +431,12 @@ __global__ __launch_bounds__(NTHREADS) void adj_site_kernel(AdjArgs a) {
 // ------------------------------------------------------------------------------------------
 // Cell part of a reverse step for the tile whose first cell is (i0, j0) of x^k.  The moment
 // adjoint of the thread's cell (zero for a thread outside the grid) is returned in mb_out as well
-// as stored.  theta partials are added to part.  Every thread of the block must call it.
-template <int ST>
+// as stored.  theta partials are added to part.  Every thread of the block must call it.  pre()
+// runs once the cell part's own loads are issued: a fused caller issues the site part's loads
+// there, so that they are in flight during the cell part (the compiler's waits count them out).
+template <int ST, typename Pre>
 __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, double part[4],
-                                          typename Mode<ST, false>::C mb_out[3]) {
+                                          typename Mode<ST, false>::C mb_out[3], Pre&& pre) {
   using A = typename Mode<ST, false>::A;
   const Physics& p = a.p;
   const int nz = p.nz, nr = p.nr, pitch = p.pitch;
@@ -509,6 +531,7 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
       t = min(tid + sl * NTHREADS, NLR - 1);
       rLR[sl] = (L + 31 * plane)[noff(i0 + t % LRZ, j0 - 1 + t / LRZ, oLR[sl])];
     }
+    pre();
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       int t = tid + sl * NTHREADS;
@@ -590,13 +613,16 @@ __device__ __forceinline__ void cell_body(const AdjArgs& a, int i0, int j0, doub
       part[2] += dt * lez * dsr;
       part[3] += dt * lez * dnb;
     }
-  } else if (mine) {
-    // fields are carried unchanged and unused
+  } else {
+    pre();
+    if (mine) {
+      // fields are carried unchanged and unused
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      bool ok;
-      const int o = noff(i, j, ok);
-      stv(&(Lo + (30 + c) * plane)[cell], ok ? (double)(L + (30 + c) * plane)[o] : 0.0);
+      for (int c = 0; c < 3; ++c) {
+        bool ok;
+        const int o = noff(i, j, ok);
+        stv(&(Lo + (30 + c) * plane)[cell], ok ? (double)(L + (30 + c) * plane)[o] : 0.0);
+      }
     }
   }
   mb_out[0] = mb_out[1] = mb_out[2] = 0;
@@ -716,7 +742,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_cell_kernel(AdjArgs a) {
   const int tile = xcd_tile(blockIdx.x, gx * gy);
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   typename Mode<ST, false>::C mb[3];
-  cell_body<ST>(a, (tile % gx) * TZ, (tile / gx) * TR, part, mb);
+  cell_body<ST>(a, (tile % gx) * TZ, (tile / gx) * TR, part, mb, [] {});
   block_sum4(part, a.partials + (long long)blockIdx.x * 4);
 }
 
@@ -750,7 +776,8 @@ __device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss)
   const int o0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   typename Mode<ST, false>::C mb[3];
-  cell_body<ST>(ac, o0, j0, part, mb);
+  SiteIn<ST> in;
+  cell_body<ST>(ac, o0, j0, part, mb, [&] { site_load<ST>(as, o0 + as.shift, j0, false, in); });
   const Physics& p = ac.p;
   if (p.window && as.shift && o0 + (int)threadIdx.x % TZ == p.nz - 1 && j0 + (int)threadIdx.x / TZ < p.nr) {
     // this cell is the front column that step k - 1's window shift created (density n_bg):
@@ -760,7 +787,7 @@ __device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss)
     part[0] += mb[0] * dl;
     part[1] += mb[0] * dn;
   }
-  site_body<ST, COLL>(as, o0 + as.shift, j0, mb, part);
+  site_body<ST, COLL>(as, o0 + as.shift, j0, mb, part, in);
   block_sum4(part, as.partials + (long long)blockIdx.x * 4);
 }
 

@@ -68,12 +68,12 @@ def test_reduced_precision_parity_c2_copy(coll):
     storage against the FP64 oracle (max-norm relative error of n, E_z, E_r).
 
     Bounds.  Density: those of the BGK test (1e-5 with FP32 arithmetic, 1e-7 with FP64
-    arithmetic).  Fields: on this case the FP32 storage of populations and fields alone puts the
-    E_z error near 1e-5, and where it lies depends on the operator (with FP64 arithmetic on FP32
-    storage, where the arithmetic adds nothing: BGK 9.9e-6, TRT 1.1e-5, regularised 1.7e-5).  So
-    the test takes that storage floor from the FP64-arithmetic run, bounds it by 3e-5, and bounds
-    the FP32-arithmetic field error by twice it (FP32 arithmetic may add at most the floor again;
-    measured: 1.0-1.45 times).  FP16: 5e-3, FP16N: 5e-4 (fields) and 5e-5 (density), as for BGK."""
+    arithmetic).  Fields: with plain FP32 storage of E_r and B_theta the E_z error sat near 1e-5
+    here (FP64 arithmetic on FP32 storage: BGK 9.9e-6, TRT 1.1e-5, regularised 1.7e-5); with the
+    compensated fields it is below 1e-6 (TRT: FP32 arithmetic E_z 8.5e-7, E_r 4.0e-7; FP64
+    arithmetic 5.8e-7, 1.8e-7).  So, as for BGK: every FP32 quantity within the target's 1e-5, the
+    fields within 3e-6 (a third of the uncompensated level), and with FP64 arithmetic within
+    2e-6.  FP16: 5e-3, FP16N: 5e-4 (fields) and 5e-5 (density), as for BGK."""
     cfg64 = wl.config("C2s", **COLLISIONS[coll])
     cfg64.update(ramp_start=cfg64["zd0"] - 3.0, ramp_len=1.0)
     S, P = O.run(cfg64, 400)
@@ -88,10 +88,9 @@ def test_reduced_precision_parity_c2_copy(coll):
         print(coll, storage, m64, errs[(storage, m64)], flush=True)
         lat.close()
     f32, floor, f16 = errs[(wl.F32, 0)], errs[(wl.F32, 1)], errs[(wl.F16, 0)]
-    assert f32["n"] < 1e-5 and floor["n"] < 1e-7, errs
+    assert max(f32.values()) < 1e-5 and floor["n"] < 1e-7, errs
     for q in ("Ez", "Er"):
-        assert floor[q] < 3e-5, errs
-        assert f32[q] < 2.0 * floor[q], (q, errs)
+        assert f32[q] < 3e-6 and floor[q] < 2e-6, (q, errs)
     assert max(f16.values()) < 5e-3, errs
     f16n = errs[(wl.F16N, 0)]
     assert f16n["n"] < 5e-5 and f16n["Ez"] < 5e-4 and f16n["Er"] < 5e-4, errs
