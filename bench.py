@@ -209,7 +209,7 @@ def adjoint_c4(ckpt_every: int = 45) -> dict:
             "rel_err_vs_fd": {nm: float(r) for nm, r in zip(names, rel)}}
 
 
-def long_plasma_c5(budget_gb: float = 64.0, fd_params=("sigma_r", "nb")) -> dict:
+def long_plasma_c5(budget_gb: float = 64.0, fd_params=("ramp_len", "n0", "sigma_r", "nb")) -> dict:
     """C5 (8192 x 2048, 20,000 steps, FP32, tanh ramp of seed-drawn length): forward MLUPS, the
     binomial-checkpointed adjoint under a snapshot budget of budget_gb, its time over the
     forward's, and the gradient against central differences (h = 1e-4) of FP64 forward runs for
@@ -223,7 +223,9 @@ def long_plasma_c5(budget_gb: float = 64.0, fd_params=("sigma_r", "nb")) -> dict
     n, zb = cfg["nsteps"], cfg["z_behind"]
     sites = cfg["nz"] * cfg["nr"]
     names = ("ramp_len", "n0", "sigma_r", "nb")
-    state_bytes = sites * (27 * 4 + 6 * 4)
+    # bytes of one snapshot (one stored state), from the library's own workspace sizes
+    from paper_2201_05473_amd import lbm_adjoint_revolve_workspace_bytes
+    state_bytes = (lbm_adjoint_revolve_workspace_bytes(cfg, 5) - lbm_adjoint_revolve_workspace_bytes(cfg, 1)) // 4
     snapshots = int(budget_gb * 1e9 // state_bytes)
     lat = Lattice(cfg)
     torch.cuda.synchronize()

@@ -776,8 +776,16 @@ __device__ __forceinline__ void fused_body(const AdjArgs& ac, const AdjStep& ss)
   const int o0 = (tile % gx) * TZ, j0 = (tile / gx) * TR;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   typename Mode<ST, false>::C mb[3];
+  // The site part's loads go in flight during the cell part (FP32 and FP16 storage: 121 VGPRs, the
+  // four wavefronts per SIMD that a C4-sized grid holds anyway; C4 adjoint/forward 3.49 -> 3.28).
+  // FP64 would need 54 more registers for them, so it loads after the cell part.
   SiteIn<ST> in;
-  cell_body<ST>(ac, o0, j0, part, mb, [&] { site_load<ST>(as, o0 + as.shift, j0, false, in); });
+  if constexpr (ST == 0) {
+    cell_body<ST>(ac, o0, j0, part, mb, [] {});
+    site_load<ST>(as, o0 + as.shift, j0, false, in);
+  } else {
+    cell_body<ST>(ac, o0, j0, part, mb, [&] { site_load<ST>(as, o0 + as.shift, j0, false, in); });
+  }
   const Physics& p = ac.p;
   if (p.window && as.shift && o0 + (int)threadIdx.x % TZ == p.nz - 1 && j0 + (int)threadIdx.x / TZ < p.nr) {
     // this cell is the front column that step k - 1's window shift created (density n_bg):
