@@ -299,6 +299,22 @@ def particle_driver_c2(steps: int = 2000, n: int = 200000, timed_only: bool = Fa
     return res
 
 
+def shard_c5_rank0(steps: int = 1000, warmup: int = 50) -> dict:
+    """One GPU's share of C5 under the r-slab decomposition over 8 GPUs: rank 0's slab, 8192 x 256
+    rows with the axis, the same physics (FP32), the step kernel alone (no halo exchange, which
+    this one-GPU build does not have)."""
+    import workloads as wl
+    cfg = wl.config("C5")
+    cfg.update(nr=cfg["nr"] // 8)
+    n = cfg["nz"] * cfg["nr"]
+    wall, ev_s, lat = time_run(cfg, steps, warmup)
+    lat.close()
+    b = bytes_per_site(wl.F32)
+    return {"workload": "C5's rank-0 r-slab for 8 GPUs: 8192x256, FP32, %d timed steps" % steps,
+            "MLUPS": n * steps / wall / 1e6, "kernel_avg_us": ev_s / steps * 1e6,
+            "alg_GBps": b * n / (ev_s / steps) / 1e9, "frac_of_peak": b * n / (ev_s / steps) / 1e9 / PEAK_HBM_GBS}
+
+
 def paper_grid_2mm() -> dict:
     """The paper's finest grid of Table 1 (preset P: 2400 x 400 cells of 0.25 um, 48,000 steps of
     c dt = dz/6 = 2 mm of propagation), FP32, at the three charges alpha = 0.678, 3.39, 6.78: time
@@ -501,6 +517,7 @@ def main():
         out["adjoint_C4"] = adj
         out["particle_driver_C2"] = particle_driver_c2()
         out["paper_grid_2mm"] = paper_grid_2mm()
+        out["shard_C5_rank0"] = shard_c5_rank0()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

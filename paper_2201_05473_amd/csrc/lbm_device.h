@@ -178,6 +178,34 @@ template <int POL = 0> __device__ __forceinline__ uint32_t bld(uint32_t*, Rsrc r
 template <typename T, int POL = 0> __device__ __forceinline__ T bload(Rsrc r, uint32_t idx) {
   return bld<POL>((T*)nullptr, r, idx * (uint32_t)sizeof(T));
 }
+// Groups of planes under one resource: element idx of the plane that starts soff bytes into the
+// group (soff uniform, a scalar operand of the instruction), so the planes of a group need no
+// resource each.  FP32 and FP16 only (a group must stay under 4 GiB).
+template <int POL = 0> __device__ __forceinline__ float bldg(float*, Rsrc r, uint32_t off, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, POL));
+}
+template <int POL = 0> __device__ __forceinline__ __half bldg(__half*, Rsrc r, uint32_t off, uint32_t soff) {
+  return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, POL));
+}
+template <typename T, int POL = 0> __device__ __forceinline__ T bload_g(Rsrc r, uint32_t idx, uint32_t soff) {
+  return bldg<POL>((T*)nullptr, r, idx * (uint32_t)sizeof(T), soff);
+}
+__device__ __forceinline__ void bputg(float*, Rsrc r, uint32_t idx, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(idx * 4u), (int)soff, 0);
+}
+__device__ __forceinline__ void bputg(float*, Rsrc r, uint32_t idx, uint32_t soff, double v) {
+  bputg((float*)nullptr, r, idx, soff, (float)v);
+}
+__device__ __forceinline__ void bputg(__half*, Rsrc r, uint32_t idx, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, (int)(idx * 2u),
+                                        (int)soff, 0);
+}
+__device__ __forceinline__ void bputg(__half*, Rsrc r, uint32_t idx, uint32_t soff, double v) {
+  bputg((__half*)nullptr, r, idx, soff, (float)v);
+}
+template <typename T, typename V> __device__ __forceinline__ void bstore_g(Rsrc r, uint32_t idx, uint32_t soff, V v) {
+  bputg((T*)nullptr, r, idx, soff, v);
+}
 // store of v, rounded to the storage type T (round to nearest even), to element idx
 __device__ __forceinline__ void bput(double*, Rsrc r, uint32_t idx, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,

@@ -218,15 +218,28 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
   const bool fresh_site = site_ok && a.shift && i == nz;
   const bool active = site_ok && !fresh_site;
   S r0[9], r1[9], r2[9];
+  // FP32 and FP16: one resource per lattice (nine planes, under 4 GiB at the largest grid), the
+  // plane selected by the instruction's scalar offset; FP64: one resource per plane
+  constexpr bool GRP = sizeof(S) <= 4;
+  const uint32_t pbytes = (uint32_t)(plane * (long long)sizeof(S));
+  const Rsrc lat_in[3] = {brsrc((const S*)gin, GRP ? 9u * pbytes : 0u),
+                          brsrc((const S*)gin + 9 * plane, GRP ? 9u * pbytes : 0u),
+                          brsrc((const S*)gin + 18 * plane, GRP ? 9u * pbytes : 0u)};
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     // ghost sources are replaced below; their (in-range) load is discarded.  FP64 populations are
     // read non-temporally (measured: FP64 step 110 -> 96.5 us on 2048 x 512; FP32 loses 25 %)
     constexpr int POL = ST == 0 ? 2 : 0;
     const uint32_t off = rrow(j - XR(q)) * pitch + zcol(i - XZ(q));
-    r0[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, q), off);
-    r1[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, 9 + q), off);
-    r2[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, 18 + q), off);
+    if constexpr (GRP) {
+      r0[q] = bload_g<S, POL>(lat_in[0], off, (uint32_t)q * pbytes);
+      r1[q] = bload_g<S, POL>(lat_in[1], off, (uint32_t)q * pbytes);
+      r2[q] = bload_g<S, POL>(lat_in[2], off, (uint32_t)q * pbytes);
+    } else {
+      r0[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, q), off);
+      r1[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, 9 + q), off);
+      r2[q] = bload<S, POL>(plane_rsrc<S>(gin, plane, 18 + q), off);
+    }
   }
   if constexpr (!HDMA) factors();
 
@@ -568,7 +581,12 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       eq_dir<C>(kq % 9, mo0, nref + mo0, mo1, mo2, uoz, uor, e0, e1, e2);
       v -= kq < 9 ? e0 : (kq < 18 ? e1 : e2);
     }
-    bstore<S>(plane_rsrc<S>(gout, plane, kq), oo, v);
+    if constexpr (sizeof(S) <= 4) {
+      const uint32_t pb = (uint32_t)(plane * (long long)sizeof(S));
+      bstore_g<S>(brsrc((const S*)gout + (kq / 9) * 9 * plane, 9u * pb), oo, (uint32_t)(kq % 9) * pb, v);
+    } else {
+      bstore<S>(plane_rsrc<S>(gout, plane, kq), oo, v);
+    }
   };
 
   // Eqs. (7), (9), (10): relaxation toward the equilibrium (standard D2Q9 coefficients) plus
