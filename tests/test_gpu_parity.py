@@ -202,6 +202,49 @@ def test_checkpoint_resume_is_exact():
     assert ei.value.code == LBM_EINVAL
 
 
+def test_fp32_compensated_fields_state_and_checkpoint():
+    """FP32 storage keeps E_r and B_theta as an FP32 value plus a bfloat16 residual.  Through the
+    FP64 state view they hold 32 significand bits: lbm_set_state then lbm_get_state returns E_r
+    and B_theta within 2^-32 of their magnitude (E_z, without a residual, within FP32 rounding),
+    lbm_fields gives the same values as the state view, and a save / load of the native format
+    (which carries the residual plane) resumes bit for bit."""
+    from paper_2201_05473_amd import Lattice
+    cfg = wl.config(None, nz=100, nr=10, nb=0.2, sigma_z=0.3, sigma_r=0.3, zd0=3.0,
+                    moving_window=1, storage=wl.F32, noise_amp=1e-4, seed=2)
+    pert = wl.density_perturbation(cfg)
+    lat = run_gpu(cfg, 7, pert)
+    st, k, s = lat.state()
+    rng = np.random.default_rng(3)
+    st = st.copy()
+    for c in (30, 31, 32):
+        st[c] = rng.uniform(-0.1, 0.1, size=st[c].shape)
+    lat.set_state(st, k, s)
+    got, k2, s2 = lat.state()
+    assert (k2, s2) == (k, s)
+    scale = 0.1
+    assert np.abs(got[30] - st[30]).max() <= 2.0 ** -24 * scale
+    for c in (31, 32):
+        err = np.abs(got[c] - st[c]).max()
+        assert err <= 2.0 ** -32 * scale, (c, err)
+    f = lat.fields(torch.float64)
+    torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    for c in range(3):
+        assert np.array_equal(f[c], got[30 + c]), c
+    lat.close()
+    a = run_gpu(cfg, 20, pert)
+    sa, ka, sa_s = a.state()
+    b = run_gpu(cfg, 10, pert)
+    c = Lattice(cfg)
+    c.load(b.save(True))
+    c.step(10)
+    sc, kc, sc_s = c.state()
+    assert (ka, sa_s) == (kc, sc_s)
+    assert np.array_equal(sa, sc)
+    for x in (a, b, c):
+        x.close()
+
+
 def test_nonfinite_state_is_reported():
     """Failure detection forced from the host: a NaN planted in one population is caught by the
     periodic check and lbm_step returns LBM_EUNSTABLE."""
