@@ -54,7 +54,7 @@ Readings of the paper (where it is silent, garbled or inconsistent):
   R28 Bubble length (Sec. IV, Fig. 4): sites of one row, in a given lab z-range, whose density is
       below n* = 0.95 times the local background (vacuum sites excluded), times dz.
   R29 Collision operators other than BGK (Sec. IV names BGK as the simplest choice and leaves
-      others to future work without naming one).  Two are offered; both keep the equilibrium of
+      others to future work without naming one).  Three are offered; all keep the equilibrium of
       Eq. (9) and add the source of Eq. (10) unchanged after relaxing:
         TRT  two relaxation times: the non-equilibrium part f - f_eq is split into its even and
              odd parts under xi -> -xi; the odd part (which carries the flux, hence D) relaxes
@@ -90,6 +90,12 @@ Readings of the paper (where it is silent, garbled or inconsistent):
       to zero and it no longer moves.  The initial field is the discrete Gauss field of the
       deposited bunch density (positions at t = -dt for E_r, at t = -dt/2 for B_theta, with
       B_theta = E_r as for the rigid driver).
+
+Pins.  tests/test_oracle_pins.py checks this module against closed forms, invariants and brute
+force.  Three readings have no closed form to check them against and are pinned only through
+invariants (a plasma at rest stays at rest, axis mirror symmetry, conservation): the exact lag
+and stencil of the axisymmetric source (R10), the time level of the ghost moments (R11), and the
+equilibrium ghosts at the axis row.  For those the module is the definition: parity unpinned.
 
 State after k completed steps (k = 0 is the initial state):
     g  [3][9][nr][nz]   post-collision populations of step k-1 (raw values, not deviations)
