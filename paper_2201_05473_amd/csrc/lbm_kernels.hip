@@ -28,6 +28,10 @@ namespace lbm {
 // PER = false: the grid is known not to be periodic, and the wrap code is compiled out.
 // DRV = 1: the driver current J_b comes from the particle bunch's deposit (a.jb_in, z and r
 // components) in place of the rigid driver's closed form.
+// SITE = true: the adjoint's forward recompute; the step also writes its site record (the
+// site-averaged fields and the moments of the pulled populations, a.site_out).
+// FP32 storage keeps E_r and B_theta compensated: an FP32 value plus a bfloat16 residual in a
+// fourth field plane, updated with a two-sum (lbm_device.h, "Compensated fields").
 // Occupancy.  With FP32 arithmetic the halo goes straight to LDS, so a thread holds little more
 // than its 27 populations: FP32 storage fits 64 VGPRs without spills (8 waves per SIMD), except
 // MRT, whose moment transform needs more (6 blocks).  FP16 storage keeps its bound of 7 blocks
