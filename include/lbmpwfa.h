@@ -129,6 +129,11 @@ enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
  *                 LBM_MRT only: relaxation rates (1 / relaxation time) of the energy, energy
  *                 square, heat-flux and stress moments, each in (0, 2); all four 1/tau is BGK,
  *                 mrt_se = mrt_seps = mrt_spi = 1/tau_plus with mrt_sq = 1/tau is TRT.  Ignored
+ *                 otherwise.
+ *   resort_every  LBM_DRIVER_PARTICLES: every that many steps lbm_step re-sorts the stored bunch
+ *                 on the device by grid cell (column, then row), so that the particles of a
+ *                 wavefront stay close together as the bunch disperses; 0 is 1000, negative
+ *                 values are rejected.  The caller's order is kept (lbm_get_bunch).  Ignored
  *                 otherwise. */
 typedef struct {
   int32_t nz, nr;
@@ -147,6 +152,7 @@ typedef struct {
   int32_t driver;
   int64_t max_particles;
   double mrt_se, mrt_seps, mrt_sq, mrt_spi;
+  int32_t resort_every;
 } lbm_config;
 
 /* FP64 diagnostics of the current state (all sums over the window):

@@ -7,7 +7,9 @@
 //   bunch_move_kernel  positions to t_k, current w beta at the midpoints -> J_b(t_{k-1/2}) (z at the
 //                      E_z points, r at the E_r points): summed per block in LDS when the block's
 //                      particles span few columns (the bunch is stored by column of z, then by
-//                      radius), then added to the grid with hardware float atomics;
+//                      radius: sorted on upload, and again on the device every few hundred or
+//                      thousand steps as the particles drift apart), then added to the grid with
+//                      hardware float atomics;
 //   (the step kernel reads J_b in Ampere's law)
 //   bunch_push_kernel  Boris push of the momenta to t_{k+1/2} with E^k and
 //                      B^k = (B^{k-1/2} + B^{k+1/2}) / 2 at the positions at t_k.
@@ -354,7 +356,166 @@ __global__ void bunch_gauss_kernel(Physics p, const double* dens, void* Ev, int 
   }
 }
 
+// Re-sort of the bunch: a counting sort by cell.  The key of a particle at its position (t_{k-1},
+// frame s) is its cell, column-major: the column of z in the window, then the row of r >> rshift,
+// both clamped to the grid; lost particles (w = 0) take the last key.  A pass counts the particles
+// per key (an atomic increment, whose return value is the particle's rank within its key), an
+// exclusive scan turns the counts into offsets, and a scatter moves each particle to offset + rank.
+// The order within a key is the order of the atomics: arbitrary, which only the order of the
+// float additions of the deposit can tell.
+constexpr int SCAN_T = 1024;            // threads of the scan kernels
+constexpr int SCAN_ITEMS = 4;           // keys per thread
+constexpr int SCAN_CHUNK = SCAN_T * SCAN_ITEMS;
+constexpr long long MAX_KEYS = 1 << 22; // rows are coarsened (rshift) to stay within this many keys
+
+__global__ __launch_bounds__(256) void sort_clear_kernel(uint32_t* counts, long long nkeys) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t < nkeys) counts[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void sort_count_kernel(Physics p, long long s, int rshift, const double* b, int n,
+                                                         long long cap, uint32_t* counts, uint32_t* key,
+                                                         uint32_t* rank) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const uint32_t nrk = (uint32_t)((p.nr - 1) >> rshift) + 1u;
+  uint32_t k = (uint32_t)p.nz * nrk;
+  if (b[6 * cap + q] != 0.0) {
+    const double ih = 1.0 / p.h;
+    const double x = b[q], y = b[cap + q];
+    const double u = floor(b[2 * cap + q] * ih) - (double)s;
+    const double v = floor(sqrt(x * x + y * y) * ih);
+    const int i = (int)fmin(fmax(u, 0.0), (double)(p.nz - 1));
+    const int j = (int)fmin(fmax(v, 0.0), (double)(p.nr - 1));
+    k = (uint32_t)i * nrk + (uint32_t)(j >> rshift);
+  }
+  key[q] = k;
+  rank[q] = atomicAdd(counts + k, 1u);
+}
+
+// Exclusive scan of v over the SCAN_T threads of the block; *total gets the block's sum.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d *= 2) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < SCAN_T / 64; ++w) {
+    const uint32_t t = wsum[w];
+    before += w < wv ? t : 0u;
+    all += t;
+  }
+  __syncthreads();   // wsum is free again for the caller's next scan
+  *total = all;
+  return before + x - v;
+}
+
+// Sum of each chunk of SCAN_CHUNK counts into bsum[chunk].
+__global__ __launch_bounds__(SCAN_T) void sort_chunk_sum_kernel(const uint32_t* counts, long long nkeys,
+                                                                 uint32_t* bsum) {
+  __shared__ uint32_t wsum[SCAN_T / 64];
+  const long long base = (long long)blockIdx.x * SCAN_CHUNK + (long long)threadIdx.x * SCAN_ITEMS;
+  uint32_t v = 0;
+#pragma unroll
+  for (int e = 0; e < SCAN_ITEMS; ++e) v += base + e < nkeys ? counts[base + e] : 0u;
+  uint32_t total;
+  (void)block_scan(v, wsum, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk sums in place (one block, chunks of SCAN_T with a carry).
+__global__ __launch_bounds__(SCAN_T) void sort_top_scan_kernel(uint32_t* bsum, int nchunks) {
+  __shared__ uint32_t wsum[SCAN_T / 64];
+  uint32_t carry = 0;
+  for (int base = 0; base < nchunks; base += SCAN_T) {
+    const int t = base + threadIdx.x;
+    const uint32_t v = t < nchunks ? bsum[t] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_scan(v, wsum, &total);
+    if (t < nchunks) bsum[t] = carry + ex;
+    carry += total;
+  }
+}
+
+// Counts to exclusive offsets in place: the chunk's offset plus the scan within the chunk.
+__global__ __launch_bounds__(SCAN_T) void sort_offsets_kernel(uint32_t* counts, long long nkeys,
+                                                               const uint32_t* bsum) {
+  __shared__ uint32_t wsum[SCAN_T / 64];
+  const long long base = (long long)blockIdx.x * SCAN_CHUNK + (long long)threadIdx.x * SCAN_ITEMS;
+  uint32_t c[SCAN_ITEMS], v = 0;
+#pragma unroll
+  for (int e = 0; e < SCAN_ITEMS; ++e) {
+    c[e] = base + e < nkeys ? counts[base + e] : 0u;
+    v += c[e];
+  }
+  uint32_t total;
+  uint32_t off = bsum[blockIdx.x] + block_scan(v, wsum, &total);
+#pragma unroll
+  for (int e = 0; e < SCAN_ITEMS; ++e) {
+    if (base + e < nkeys) counts[base + e] = off;
+    off += c[e];
+  }
+}
+
+// out[:, offsets[key[q]] + rank[q]] = in[:, q] for the 7 components, and the same for pid.
+__global__ __launch_bounds__(256) void sort_scatter_kernel(const double* in, const int32_t* pid_in,
+                                                           const uint32_t* offsets, const uint32_t* key,
+                                                           const uint32_t* rank, int n, long long cap, double* out,
+                                                           int32_t* pid_out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const long long d = (long long)offsets[key[q]] + rank[q];
+#pragma unroll
+  for (int c = 0; c < 7; ++c) out[c * cap + d] = in[c * cap + q];
+  pid_out[d] = pid_in[q];
+}
+
 }  // namespace
+
+void bunch_sort_shape(const Physics& p, int* rshift, long long* nkeys) {
+  int r = 0;
+  while ((long long)p.nz * (((p.nr - 1) >> r) + 1) + 1 > MAX_KEYS && ((p.nr - 1) >> r) > 0) ++r;
+  *rshift = r;
+  *nkeys = (long long)p.nz * (((p.nr - 1) >> r) + 1) + 1;
+}
+
+size_t bunch_sort_bytes(const Physics& p) {
+  int r;
+  long long nkeys;
+  bunch_sort_shape(p, &r, &nkeys);
+  const long long nchunks = (nkeys + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  return up((size_t)nkeys * 4) + up((size_t)nchunks * 4) + 2 * up((size_t)p.cap * 4);
+}
+
+hipError_t launch_bunch_resort(const Physics& p, long long s, const double* in, const int32_t* pid_in, int n,
+                               void* scratch, double* out, int32_t* pid_out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int rshift;
+  long long nkeys;
+  bunch_sort_shape(p, &rshift, &nkeys);
+  const long long nchunks = (nkeys + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  char* w = (char*)scratch;
+  uint32_t* counts = (uint32_t*)w;
+  uint32_t* bsum = (uint32_t*)(w + up((size_t)nkeys * 4));
+  uint32_t* key = (uint32_t*)(w + up((size_t)nkeys * 4) + up((size_t)nchunks * 4));
+  uint32_t* rank = (uint32_t*)((char*)key + up((size_t)p.cap * 4));
+  const dim3 gp((n + 255) / 256);
+  sort_clear_kernel<<<dim3((unsigned)((nkeys + 255) / 256)), 256, 0, st>>>(counts, nkeys);
+  sort_count_kernel<<<gp, 256, 0, st>>>(p, s, rshift, in, n, p.cap, counts, key, rank);
+  sort_chunk_sum_kernel<<<dim3((unsigned)nchunks), SCAN_T, 0, st>>>(counts, nkeys, bsum);
+  sort_top_scan_kernel<<<1, SCAN_T, 0, st>>>(bsum, (int)nchunks);
+  sort_offsets_kernel<<<dim3((unsigned)nchunks), SCAN_T, 0, st>>>(counts, nkeys, bsum);
+  sort_scatter_kernel<<<gp, 256, 0, st>>>(in, pid_in, counts, key, rank, n, p.cap, out, pid_out);
+  return hipGetLastError();
+}
 
 #define BUNCH_DISPATCH(storage, KERNEL, GRID, STREAM, ...)                         \
   do {                                                                             \

@@ -93,6 +93,8 @@ int validate(const lbm_config* c, Physics* p) {
     return fail(LBM_EINVAL, "unknown driver %d", c->driver);
   if (c->driver == LBM_DRIVER_PARTICLES && (c->max_particles < 0 || c->max_particles > INT32_MAX))
     return fail(LBM_EINVAL, "max_particles must lie in [0, 2^31) (got %lld)", (long long)c->max_particles);
+  if (c->driver == LBM_DRIVER_PARTICLES && c->resort_every < 0)
+    return fail(LBM_EINVAL, "resort_every must be >= 0 (got %d)", c->resort_every);
   if (p) {
     Physics& q = *p;
     std::memset(&q, 0, sizeof q);
@@ -139,11 +141,12 @@ int validate(const lbm_config* c, Physics* p) {
 
 // Workspace layout: two population buffers, two moment buffers, two field buffers, and the
 // reduction scratch, each 256-byte aligned.
-// The particle driver adds the bunch (SoA [7][cap] doubles), two deposit buffers of J_bz, J_br
-// (auxiliary type, alternating between steps) and an FP64 density plane (initial field,
-// diagnostics); none of them for the rigid driver.
+// The particle driver adds two bunch buffers (SoA [7][cap] doubles; a re-sort moves the bunch from
+// one to the other) with the caller's index of each stored particle (int32 [cap] each), the
+// scratch of the re-sort, two deposit buffers of J_bz, J_br (auxiliary type, alternating between
+// steps) and an FP64 density plane (initial field, diagnostics); none of them for the rigid driver.
 struct Layout {
-  size_t g[2], M[2], E[2], partials, out, bunch, jb[2], dens, total;
+  size_t g[2], M[2], E[2], partials, out, bunch[2], pid[2], sort, jb[2], dens, total;
 };
 
 Layout layout(const Physics& p, int storage) {
@@ -160,9 +163,16 @@ Layout layout(const Physics& p, int storage) {
   off += round_up((size_t)lbm::diag_blocks(p) * 8 * sizeof(double), 256);
   L.out = off;
   off += 256;
-  L.bunch = L.jb[0] = L.jb[1] = L.dens = off;
+  L.bunch[0] = L.bunch[1] = L.pid[0] = L.pid[1] = L.sort = L.jb[0] = L.jb[1] = L.dens = off;
   if (p.driver == 1) {
-    off += round_up(7 * (size_t)p.cap * sizeof(double), 256);
+    for (int b = 0; b < 2; ++b) {
+      L.bunch[b] = off;
+      off += round_up(7 * (size_t)p.cap * sizeof(double), 256);
+      L.pid[b] = off;
+      off += round_up((size_t)p.cap * sizeof(int32_t), 256);
+    }
+    L.sort = off;
+    off += round_up(lbm::bunch_sort_bytes(p), 256);
     for (int b = 0; b < 2; ++b) {
       L.jb[b] = off;
       off += round_up(2 * plane * aux_bytes(storage), 256);
@@ -189,17 +199,21 @@ struct lbm_ctx {
   // events; created on first use, default priority
   hipStream_t aux = nullptr;
   hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
-  // particle driver: particles in the bunch, the deposit buffer the next step fills, and the
-  // caller's index of each stored particle (the bunch is stored by column of z, then radius)
+  // particle driver: particles in the bunch, the deposit buffer the next step fills, and the bunch
+  // buffer in use (with the caller's index of each stored particle; the bunch is stored by cell:
+  // column of z, then radius)
   long long nbunch = 0;
   int jcur = 0;
+  int bcur = 0;
   // device address of the library's fixed diagnostic scratch on the context's device
   double* scratch = nullptr;
   // set when a failed lbm_adjoint_revolve could not put the initial state back into the context's
   // buffers (which it uses as scratch); cleared by lbm_set_state / lbm_load
   bool broken = false;
-  std::vector<int64_t> order;
-  double* bunch() { return (double*)(ws + L.bunch); }
+  double* bunch(int b) { return (double*)(ws + L.bunch[b]); }
+  double* bunch() { return bunch(bcur); }
+  int32_t* pid(int b) { return (int32_t*)(ws + L.pid[b]); }
+  void* sort_scratch() { return ws + L.sort; }
   void* jb(int b) { return ws + L.jb[b]; }
   double* dens() { return (double*)(ws + L.dens); }
   void* g(int b) { return ws + L.g[b]; }
@@ -323,8 +337,10 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (int rc_ = live(c)) return rc_;
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   // particle driver: the push of a step and the move of the next run as one launch between two
-  // steps of this call (not across a diagnostic check, which reads the bunch at t_{k-1}); moved:
-  // the bunch is already at t_k with J_b(t_{k-1/2}) in jb(jcur)
+  // steps of this call (not across a diagnostic check, which reads the bunch at t_{k-1}, nor across
+  // a re-sort, which sorts the positions at t_{k-1}); moved: the bunch is already at t_k with
+  // J_b(t_{k-1/2}) in jb(jcur)
+  const long long resort = c->cfg.resort_every > 0 ? c->cfg.resort_every : 1000;
   bool moved = false;
   for (int64_t n = 0; n < nsteps; ++n) {
     lbm::StepArgs a;
@@ -343,17 +359,25 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     a.jb_zero = nullptr;
     if (c->p.driver == 1) {
       // particles to t_k and their current J_b(t_{k-1/2}) into the buffer the previous step cleared
-      if (!moved)
+      if (!moved) {
+        if (c->k > 0 && c->k % resort == 0 && c->nbunch > 0) {
+          HIP_CHECK(lbm::launch_bunch_resort(c->p, c->s, c->bunch(c->bcur), c->pid(c->bcur), (int)c->nbunch,
+                                             c->sort_scratch(), c->bunch(1 - c->bcur), c->pid(1 - c->bcur),
+                                             c->stream),
+                    "bunch sort launch");
+          c->bcur ^= 1;
+        }
         HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,
                                          c->jb(c->jcur), c->stream),
                   "bunch launch");
+      }
       a.jb_in = c->jb(c->jcur);
       a.jb_zero = c->jb(1 - c->jcur);
     }
     HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "step launch");
     if (c->p.driver == 1) {
       const bool check_next = c->cfg.check_every > 0 && (c->k + 1) % c->cfg.check_every == 0;
-      moved = n + 1 < nsteps && !check_next;
+      moved = n + 1 < nsteps && !check_next && (c->k + 1) % resort != 0;
       if (moved)
         HIP_CHECK(lbm::launch_bunch_push_move(c->storage, c->p, c->s, a.shift, c->E(c->cur), c->E(1 - c->cur),
                                               c->bunch(), (int)c->nbunch, c->p.cap, c->jb(1 - c->jcur), c->stream),
@@ -1326,17 +1350,21 @@ int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
   std::vector<double> sorted((size_t)(7 * n));
   for (int comp = 0; comp < 7; ++comp)
     for (int64_t i = 0; i < n; ++i) sorted[(size_t)(comp * n + i)] = bunch[comp * n + order[(size_t)i]];
-  for (int comp = 0; comp < 7 && n > 0; ++comp) {
-    const hipError_t e = hipMemcpyAsync(c->bunch() + comp * c->p.cap, sorted.data() + comp * n,
-                                        (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  std::vector<int32_t> pid((size_t)n);
+  for (int64_t i = 0; i < n; ++i) pid[(size_t)i] = (int32_t)order[(size_t)i];
+  for (int comp = 0; comp < 8 && n > 0; ++comp) {
+    const hipError_t e =
+        comp < 7 ? hipMemcpyAsync(c->bunch() + comp * c->p.cap, sorted.data() + comp * n,
+                                  (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream)
+                 : hipMemcpyAsync(c->pid(c->bcur), pid.data(), (size_t)n * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) {
-      (void)hipStreamSynchronize(c->stream);   // copies already queued read `sorted`
+      (void)hipStreamSynchronize(c->stream);   // copies already queued read `sorted` and `pid`
       c->nbunch = 0;                           // the device bunch is now partly overwritten
       return hip_fail(e, "bunch upload");
     }
   }
-  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");   // before the host buffer goes
-  c->order.swap(order);
+  HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");   // before the host buffers go
   c->nbunch = n;
   if (init_fields && c->p.fields_on) {
     // E_r^{-1} from the density at the positions (t = -dt) on the E_r columns; B^{-1/2} from the
@@ -1363,17 +1391,29 @@ int get_bunch(lbm_ctx* c, double* bunch, int64_t n_max, int64_t* n) {
   if (c->nbunch > 0 && !bunch) return fail(LBM_EINVAL, "bunch is NULL");
   const long long nb = c->nbunch;
   std::vector<double> stored((size_t)(7 * nb));
-  for (int comp = 0; comp < 7 && nb > 0; ++comp) {
-    const hipError_t e = hipMemcpyAsync(stored.data() + comp * nb, c->bunch() + comp * c->p.cap,
-                                        (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  std::vector<int32_t> pid((size_t)nb);
+  for (int comp = 0; comp < 8 && nb > 0; ++comp) {
+    const hipError_t e =
+        comp < 7 ? hipMemcpyAsync(stored.data() + comp * nb, c->bunch() + comp * c->p.cap,
+                                  (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, c->stream)
+                 : hipMemcpyAsync(pid.data(), c->pid(c->bcur), (size_t)nb * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) {
-      (void)hipStreamSynchronize(c->stream);   // copies already queued write `stored`
+      (void)hipStreamSynchronize(c->stream);   // copies already queued write `stored` and `pid`
       return hip_fail(e, "bunch download");
     }
   }
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
-  for (int comp = 0; comp < 7; ++comp)   // back to the caller's order
-    for (long long i = 0; i < nb; ++i) bunch[comp * nb + c->order[(size_t)i]] = stored[(size_t)(comp * nb + i)];
+  // back to the caller's order; the indices are a permutation of [0, nb) (checked, so that a
+  // damaged index array is reported rather than followed)
+  std::vector<char> seen((size_t)nb, 0);
+  for (long long i = 0; i < nb; ++i) {
+    const int32_t o = pid[(size_t)i];
+    if (o < 0 || o >= nb || seen[(size_t)o]) return fail(LBM_ESTATE, "bunch index %lld is not a permutation", i);
+    seen[(size_t)o] = 1;
+  }
+  for (int comp = 0; comp < 7; ++comp)
+    for (long long i = 0; i < nb; ++i) bunch[comp * nb + pid[(size_t)i]] = stored[(size_t)(comp * nb + i)];
   *n = nb;
   return LBM_OK;
 }

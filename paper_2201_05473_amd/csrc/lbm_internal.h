@@ -116,6 +116,14 @@ hipError_t launch_bunch_push(int storage, const Physics& p, long long s, int shi
 // jb) in one launch.
 hipError_t launch_bunch_push_move(int storage, const Physics& p, long long s, int shift, const void* Ein,
                                   const void* Eout, double* bunch, int n, long long cap, void* jb, hipStream_t st);
+// Re-sort of the bunch by cell (column of z in frame s, then row; lost particles last): in -> out
+// (SoA [7][cap] each, not overlapping) with the caller's indices pid_in -> pid_out; scratch holds
+// bunch_sort_bytes(p) bytes (256-byte aligned), whose contents need not be kept between calls.
+// rshift: rows are merged in groups of 2^rshift so that the nkeys keys stay within a bound.
+void bunch_sort_shape(const Physics& p, int* rshift, long long* nkeys);
+size_t bunch_sort_bytes(const Physics& p);
+hipError_t launch_bunch_resort(const Physics& p, long long s, const double* in, const int32_t* pid_in, int n,
+                               void* scratch, double* out, int32_t* pid_out, hipStream_t st);
 // Bunch density (FP64, atomics) on the nodes z = (s + i + zoff) dz, rows (j + 1/2) dr, positions moved
 // by t_ahead along the velocities; dens must be cleared first.
 hipError_t launch_bunch_density(const Physics& p, long long s, double zoff, double t_ahead, const double* bunch,

@@ -85,9 +85,10 @@ def test_fp64_parity(name):
 
 def test_call_splits_and_checks_agree():
     """Within one lbm_step call the push of a step and the move of the next run as one launch; a
-    call boundary or a diagnostic check splits them.  One call of 45 steps, 45 calls of one step,
-    and calls of 13 + 32 steps with a check every 7 steps all give the oracle's state and bunch
-    (FP64, 1e-10), with the deflected slow bunch (losses included)."""
+    call boundary, a diagnostic check or a re-sort of the bunch splits them.  One call of 45 steps,
+    45 calls of one step, calls of 13 + 32 steps with a check every 7 steps, and re-sorts every 4
+    steps (with and without checks every 7) all give the oracle's state and bunch (FP64, 1e-10,
+    bunch in the caller's order), with the deflected slow bunch (losses included)."""
     c = CASES["slow_deflected"]
     base = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=4.0,
                      driver=wl.PARTICLES, max_particles=6000, storage=wl.F64, noise_amp=1e-3, seed=4,
@@ -97,7 +98,9 @@ def test_call_splits_and_checks_agree():
     S, P = O.run(base, 45, pert, bunch=b)
     ref_state, ref_b = oracle_state(S, P), S.bunch.numpy()
     for label, cfg, calls in (("one call", base, [45]), ("single steps", base, [1] * 45),
-                              ("checks", dict(base, check_every=7), [13, 32])):
+                              ("checks", dict(base, check_every=7), [13, 32]),
+                              ("re-sorts", dict(base, resort_every=4), [45]),
+                              ("re-sorts and checks", dict(base, resort_every=4, check_every=7), [13, 1, 31])):
         print(f"[bunch calls] {label}", flush=True)
         lat = lattice(cfg, b, pert)
         for n in calls:
