@@ -115,48 +115,114 @@ constexpr int TW = 8, TRW = 192;
 // on C2 with 200,000 particles: 1 is best (2: +1.5 %, 4: +12 %); with 10^6 particles 2 gains 2 %.
 constexpr int PPT = 1;
 
-template <typename T>
-__device__ __forceinline__ void lds_add(T* a, double v) { atomicAdd(a, (T)v); }
+// Lane shifts of the data-parallel primitives (DPP) for the segmented sums below; lanes whose source
+// lies outside the pattern read zero.  ROW_SHR(k): lane l reads lane l - k of its row of 16;
+// BCAST15: rows 1 and 3 read the last lane of the row before; BCAST31: rows 2 and 3 read lane 31.
+constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
+constexpr int BCAST15 = 0x142, BCAST31 = 0x143;
 
-// Adds the shares of val over the stencil's nodes to the packed tile.  The E_r points' row below
-// the axis carries nothing; the E_z points' folds onto row 0.
-// FP64 tiles (FP64 storage) take the shares in FP64, as the oracle; FP32 tiles in FP32 with the
-// hardware reciprocal (1 ulp), below the FP32 rounding of the stored current.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Inclusive sum of v over the lanes of the run of equal keys that ends at this lane (pos: this
+// lane's distance from the start of its run).  Every lane of the wavefront must take part, and
+// every shift runs on all of them: a lane shift reads nothing from a lane switched off, so the
+// shifted value is taken unconditionally and weighted by 0 or 1 (a select would let the compiler
+// move the shift under a branch).  The values are finite.
+template <typename V>
+__device__ __forceinline__ V run_sum(V v, int pos, int lane) {
+  V y = dpp<ROW_SHR1, 0xf>(v);
+  v += y * (V)(pos >= 1);
+  y = dpp<ROW_SHR2, 0xf>(v);
+  v += y * (V)(pos >= 2);
+  y = dpp<ROW_SHR4, 0xf>(v);
+  v += y * (V)(pos >= 4);
+  y = dpp<ROW_SHR8, 0xf>(v);
+  v += y * (V)(pos >= 8);
+  y = dpp<BCAST15, 0xa>(v);
+  v += y * (V)(pos > (lane & 15) && (lane & 16));
+  y = dpp<BCAST31, 0xc>(v);
+  v += y * (V)(pos > lane - 32 && lane >= 32);
+  return v;
+}
+
+// Adds the shares of val over the stencil's nodes to the packed tile (row-major, nc columns from
+// column c0 and row r0).  The E_r points' row below the axis carries nothing; the E_z points' folds
+// onto row 0.  Lanes whose stencils start at the same node and are neighbours in the wavefront
+// (the bunch is stored by cell, so runs are long) first sum their four node shares; the last lane
+// of each run adds the sums, so one LDS atomic serves the run.  Every lane of the wavefront takes
+// part (live = false: no particle).
+// FP64 tiles (FP64 storage) take the shares in FP64, as the oracle (the run's sum is divided by
+// the node volume once); FP32 tiles in FP32 with the hardware reciprocal (1 ulp), below the FP32
+// rounding of the stored current.
 template <typename T>
-__device__ __forceinline__ void deposit_tile(const Physics& p, const Stencil& st, bool edge, double val, T* tile,
-                                             int c0, int r0, int nc) {
+__device__ __forceinline__ void deposit_tile(const Physics& p, const Stencil& st, bool edge, double val, bool live,
+                                             T* tile, int c0, int r0, int nc) {
+  const int lane = threadIdx.x % 64;
+  const int key = live ? (st.j0 - r0 + 1) * TW + (st.i0 - c0) : -1;
+  const int prev = __shfl_up(key, 1, 64);
+  const unsigned long long heads = __ballot(lane == 0 || prev != key);
+  const int pos = lane - (63 - __clzll(heads & (~0ull >> (63 - lane))));
+  const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+  const T v = live ? (T)val : T(0), fr = (T)st.fr, fz = (T)st.fz;
+  const T a0 = v * (T(1) - fr), a1 = v * fr;
+  const T s00 = run_sum(a0 * (T(1) - fz), pos, lane), s01 = run_sum(a0 * fz, pos, lane);
+  const T s10 = run_sum(a1 * (T(1) - fz), pos, lane), s11 = run_sum(a1 * fz, pos, lane);
+  if (!tail || key < 0) return;
 #pragma unroll
   for (int dj = 0; dj < 2; ++dj) {
     const int j = st.j0 + dj;
     if (edge && j < 0) continue;
     const int jj = j < 0 ? 0 : j;
     T* row = tile + (jj - r0) * nc + (st.i0 - c0);
+    const T lo = dj ? s10 : s00, hi = dj ? s11 : s01;
     if constexpr (std::is_same<T, double>::value) {
-      const double rn = ((double)jj + (edge ? 1.0 : 0.5)) * p.h;
-      const double vr = val * (dj ? st.fr : 1.0 - st.fr) / (TWO_PI * rn * p.h * p.h);
-      lds_add(row, vr * (1.0 - st.fz));
-      lds_add(row + 1, vr * st.fz);
-    } else {
       // val / (2 pi r_node dz dr) with r_node = (jj + 1 or 1/2) dr
-      const float k = (float)val * (float)(1.0 / (TWO_PI * p.h * p.h * p.h));
-      const float fr = (float)st.fr, fz = (float)st.fz;
-      const float vr = k * (dj ? fr : 1.f - fr) * __builtin_amdgcn_rcpf((float)jj + (edge ? 1.f : 0.5f));
-      atomicAdd(row, vr * (1.f - fz));
-      atomicAdd(row + 1, vr * fz);
+      const double vol = TWO_PI * (((double)jj + (edge ? 1.0 : 0.5)) * p.h) * p.h * p.h;
+      atomicAdd(row, lo / vol);
+      atomicAdd(row + 1, hi / vol);
+    } else {
+      const float k = (float)(1.0 / (TWO_PI * p.h * p.h * p.h)) *
+                      __builtin_amdgcn_rcpf((float)jj + (edge ? 1.f : 0.5f));
+      atomicAdd(row, lo * k);
+      atomicAdd(row + 1, hi * k);
     }
   }
 }
 
-// Wavefront minimum / maximum (all 64 lanes take part)
+// Wavefront minimum / maximum, the same in every lane (all 64 lanes take part): a scan with the
+// lane shifts above (lanes outside a shift's pattern read the identity), whose last lane holds the
+// result.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dppi(int identity, int v) {
+  return __builtin_amdgcn_update_dpp(identity, v, CTRL, ROWS, 0xf, false);
+}
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+  v = min(v, dppi<ROW_SHR1, 0xf>(INT32_MAX, v));
+  v = min(v, dppi<ROW_SHR2, 0xf>(INT32_MAX, v));
+  v = min(v, dppi<ROW_SHR4, 0xf>(INT32_MAX, v));
+  v = min(v, dppi<ROW_SHR8, 0xf>(INT32_MAX, v));
+  v = min(v, dppi<BCAST15, 0xa>(INT32_MAX, v));
+  v = min(v, dppi<BCAST31, 0xc>(INT32_MAX, v));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  v = max(v, dppi<ROW_SHR1, 0xf>(INT32_MIN, v));
+  v = max(v, dppi<ROW_SHR2, 0xf>(INT32_MIN, v));
+  v = max(v, dppi<ROW_SHR4, 0xf>(INT32_MIN, v));
+  v = max(v, dppi<ROW_SHR8, 0xf>(INT32_MIN, v));
+  v = max(v, dppi<BCAST15, 0xa>(INT32_MIN, v));
+  v = max(v, dppi<BCAST31, 0xc>(INT32_MIN, v));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Boris push for dp/dt = -(E + beta x B) of one particle at (x, y, z) (positions at t_k, frame s):
@@ -254,26 +320,24 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
     lrmin = min(lrmin, max(0, min(jz[u].j0, jr[u].j0)));
     lrmax = max(lrmax, max(jz[u].j0, jr[u].j0) + 1);
   }
-  // the block's extent: wavefront reductions, one slot per wavefront
-  const int wv = threadIdx.x / 64;
-  lcmin = wave_min(lcmin);
-  lcmax = wave_max(lcmax);
-  lrmin = wave_min(lrmin);
-  lrmax = wave_max(lrmax);
-  if (threadIdx.x % 64 == 0) {
-    ext[wv][0] = lcmin;
-    ext[wv][1] = lcmax;
-    ext[wv][2] = lrmin;
-    ext[wv][3] = lrmax;
-  }
-  __syncthreads();
-  int c0 = INT32_MAX, c1 = -1, r0 = INT32_MAX, r1 = -1;
+  // the block's extent: wavefront reductions, then (several wavefronts) one slot per wavefront
+  int c0 = wave_min(lcmin), c1 = wave_max(lcmax), r0 = wave_min(lrmin), r1 = wave_max(lrmax);
+  if constexpr (BT > 64) {
+    const int wv = threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0) {
+      ext[wv][0] = c0;
+      ext[wv][1] = c1;
+      ext[wv][2] = r0;
+      ext[wv][3] = r1;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < BT / 64; ++k) {
-    c0 = min(c0, ext[k][0]);
-    c1 = max(c1, ext[k][1]);
-    r0 = min(r0, ext[k][2]);
-    r1 = max(r1, ext[k][3]);
+    for (int k = 0; k < BT / 64; ++k) {
+      c0 = min(c0, ext[k][0]);
+      c1 = max(c1, ext[k][1]);
+      r0 = min(r0, ext[k][2]);
+      r1 = max(r1, ext[k][3]);
+    }
   }
   A* J = (A*)jbv;
   if (c1 < 0) return;                            // no live particle in the block (uniform)
@@ -294,10 +358,9 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
   }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PPT; ++u) {
-    if (!live[u]) continue;
-    deposit_tile(p, jz[u], false, vz[u], tile[0], c0, r0, nc);
-    deposit_tile(p, jr[u], true, vr[u], tile[1], c0, r0, nc);
+  for (int u = 0; u < PPT; ++u) {   // every lane, live or not (wavefront-wide sums)
+    deposit_tile(p, jz[u], false, vz[u], live[u], tile[0], c0, r0, nc);
+    deposit_tile(p, jr[u], true, vr[u], live[u], tile[1], c0, r0, nc);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < cells; t += BT) {
