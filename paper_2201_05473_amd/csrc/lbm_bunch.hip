@@ -580,6 +580,54 @@ hipError_t launch_bunch_resort(const Physics& p, long long s, const double* in, 
   return hipGetLastError();
 }
 
+namespace {
+
+// Extent of the live particles (one block of EXT_T threads striding over the bunch): lowest and
+// highest column floor(z / dz) and highest row floor(r / dr), in the lab frame.
+constexpr int EXT_T = 1024;
+__global__ __launch_bounds__(EXT_T) void bunch_extent_kernel(Physics p, const double* b, int n, long long cap,
+                                                             int* out) {
+  __shared__ int part[EXT_T / 64][3];
+  const double ih = 1.0 / p.h;
+  int zlo = INT32_MAX, zhi = INT32_MIN, rhi = INT32_MIN;
+  for (int q = threadIdx.x; q < n; q += EXT_T) {
+    if (b[6 * cap + q] == 0.0) continue;
+    const double x = b[q], y = b[cap + q];
+    const double u = fmin(fmax(floor(b[2 * cap + q] * ih), -1e9), 1e9);
+    const double v = fmin(floor(sqrt(x * x + y * y) * ih), 1e9);
+    zlo = min(zlo, (int)u);
+    zhi = max(zhi, (int)u);
+    rhi = max(rhi, (int)v);
+  }
+  zlo = wave_min(zlo);
+  zhi = wave_max(zhi);
+  rhi = wave_max(rhi);
+  if (threadIdx.x % 64 == 0) {
+    part[threadIdx.x / 64][0] = zlo;
+    part[threadIdx.x / 64][1] = zhi;
+    part[threadIdx.x / 64][2] = rhi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < EXT_T / 64; ++w) {
+      zlo = min(zlo, part[w][0]);
+      zhi = max(zhi, part[w][1]);
+      rhi = max(rhi, part[w][2]);
+    }
+    out[0] = zlo;
+    out[1] = zhi;
+    out[2] = rhi;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_bunch_extent(const Physics& p, const double* bunch, int n, long long cap, int* out,
+                               hipStream_t st) {
+  bunch_extent_kernel<<<1, EXT_T, 0, st>>>(p, bunch, n, cap, out);
+  return hipGetLastError();
+}
+
 #define BUNCH_DISPATCH(storage, KERNEL, GRID, STREAM, ...)                         \
   do {                                                                             \
     if ((storage) == 0) KERNEL<0><<<(GRID), BT, 0, (STREAM)>>>(__VA_ARGS__);       \

@@ -143,10 +143,10 @@ int validate(const lbm_config* c, Physics* p) {
 // reduction scratch, each 256-byte aligned.
 // The particle driver adds two bunch buffers (SoA [7][cap] doubles; a re-sort moves the bunch from
 // one to the other) with the caller's index of each stored particle (int32 [cap] each), the
-// scratch of the re-sort, two deposit buffers of J_bz, J_br (auxiliary type, alternating between
+// scratch of the re-sort, a slot for the bunch's extent, two deposit buffers of J_bz, J_br (auxiliary type, alternating between
 // steps) and an FP64 density plane (initial field, diagnostics); none of them for the rigid driver.
 struct Layout {
-  size_t g[2], M[2], E[2], partials, out, bunch[2], pid[2], sort, jb[2], dens, total;
+  size_t g[2], M[2], E[2], partials, out, bunch[2], pid[2], sort, ext, jb[2], dens, total;
 };
 
 Layout layout(const Physics& p, int storage) {
@@ -163,7 +163,7 @@ Layout layout(const Physics& p, int storage) {
   off += round_up((size_t)lbm::diag_blocks(p) * 8 * sizeof(double), 256);
   L.out = off;
   off += 256;
-  L.bunch[0] = L.bunch[1] = L.pid[0] = L.pid[1] = L.sort = L.jb[0] = L.jb[1] = L.dens = off;
+  L.bunch[0] = L.bunch[1] = L.pid[0] = L.pid[1] = L.sort = L.ext = L.jb[0] = L.jb[1] = L.dens = off;
   if (p.driver == 1) {
     for (int b = 0; b < 2; ++b) {
       L.bunch[b] = off;
@@ -173,6 +173,8 @@ Layout layout(const Physics& p, int storage) {
     }
     L.sort = off;
     off += round_up(lbm::bunch_sort_bytes(p), 256);
+    L.ext = off;
+    off += 256;
     for (int b = 0; b < 2; ++b) {
       L.jb[b] = off;
       off += round_up(2 * plane * aux_bytes(storage), 256);
@@ -205,6 +207,11 @@ struct lbm_ctx {
   long long nbunch = 0;
   int jcur = 0;
   int bcur = 0;
+  // extent of the live particles when the bunch was last set or re-sorted (positions at
+  // t_{ext_k - 1}; lab-frame cells: lowest and highest column of z, highest row of r; empty when
+  // ext[0] > ext[1]): it bounds where the deposits of the following steps can fall
+  int ext[3] = {INT32_MAX, INT32_MIN, INT32_MIN};
+  long long ext_k = 0;
   // device address of the library's fixed diagnostic scratch on the context's device
   double* scratch = nullptr;
   // set when a failed lbm_adjoint_revolve could not put the initial state back into the context's
@@ -214,6 +221,7 @@ struct lbm_ctx {
   double* bunch() { return bunch(bcur); }
   int32_t* pid(int b) { return (int32_t*)(ws + L.pid[b]); }
   void* sort_scratch() { return ws + L.sort; }
+  int* ext_dev() { return (int*)(ws + L.ext); }
   void* jb(int b) { return ws + L.jb[b]; }
   double* dens() { return (double*)(ws + L.dens); }
   void* g(int b) { return ws + L.g[b]; }
@@ -248,6 +256,26 @@ hipError_t driver_density_plane(lbm_ctx* c, const double** out) {
     e = lbm::launch_bunch_density(c->p, c->s, 0.0, 0.0, c->bunch(), (int)c->nbunch, c->p.cap, c->dens(), c->stream);
   *out = c->dens();
   return e;
+}
+
+// Where J_b can be non-zero at step k (the deposit the step reads, the previous one its clear
+// removes, the next one the cleared buffer receives): the extent of the live particles at
+// t_{ext_k - 1}, widened by the distance a particle can travel (|v| < c: dt per step in z and in r)
+// between then and the midpoints of those deposits, by the stencils' reach and by one cell of
+// rounding.  Columns in the window frame of step k.
+void jb_bound(const lbm_ctx* c, lbm::StepArgs& a) {
+  if (c->ext[0] > c->ext[1]) {   // no live particle: no deposit
+    a.jb_c0 = 1 << 30;
+    a.jb_c1 = -(1 << 30);
+    a.jb_r1 = -(1 << 30);
+    return;
+  }
+  const long long n = c->k > c->ext_k ? c->k - c->ext_k : c->ext_k - c->k;
+  const long long m = (long long)std::ceil(((double)n + 2.0) * c->p.dt / c->p.h) + 3;
+  const auto clampi = [](long long v) { return (int)std::min<long long>(std::max<long long>(v, -(1LL << 30)), 1LL << 30); };
+  a.jb_c0 = clampi((long long)c->ext[0] - m - c->s);
+  a.jb_c1 = clampi((long long)c->ext[1] + 1 + m - c->s);
+  a.jb_r1 = clampi((long long)c->ext[2] + 1 + m);
 }
 
 int run_check(lbm_ctx* c) {
@@ -366,6 +394,14 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
                                              c->stream),
                     "bunch sort launch");
           c->bcur ^= 1;
+          // a fresh extent tightens the J_b bound (one synchronisation per re-sort)
+          HIP_CHECK(lbm::launch_bunch_extent(c->p, c->bunch(), (int)c->nbunch, c->p.cap, c->ext_dev(), c->stream),
+                    "bunch extent launch");
+          int ext[3];
+          HIP_CHECK(hipMemcpyAsync(ext, c->ext_dev(), sizeof ext, hipMemcpyDeviceToHost, c->stream), "copy");
+          HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
+          std::memcpy(c->ext, ext, sizeof ext);
+          c->ext_k = c->k;
         }
         HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,
                                          c->jb(c->jcur), c->stream),
@@ -373,6 +409,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
       }
       a.jb_in = c->jb(c->jcur);
       a.jb_zero = c->jb(1 - c->jcur);
+      jb_bound(c, a);
     }
     HIP_CHECK(lbm::launch_step(c->storage, a, c->stream), "step launch");
     if (c->p.driver == 1) {
@@ -1364,8 +1401,22 @@ int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
       return hip_fail(e, "bunch upload");
     }
   }
+  // the deposit buffers may hold the previous bunch's current, outside the new bunch's bound
+  for (int b = 0; b < 2; ++b)
+    HIP_CHECK(hipMemsetAsync(c->jb(b), 0, 2 * (size_t)c->p.plane * aux_bytes(c->storage), c->stream), "clear");
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");   // before the host buffers go
   c->nbunch = n;
+  c->ext[0] = INT32_MAX;
+  c->ext[1] = c->ext[2] = INT32_MIN;
+  for (int64_t i = 0; i < n; ++i) {
+    if (bunch[6 * n + i] == 0.0) continue;
+    const double u = std::min(std::max(std::floor(bunch[2 * n + i] / c->p.h), -1e9), 1e9);
+    const double v = std::min(std::floor(std::sqrt(bunch[i] * bunch[i] + bunch[n + i] * bunch[n + i]) / c->p.h), 1e9);
+    c->ext[0] = std::min(c->ext[0], (int)u);
+    c->ext[1] = std::max(c->ext[1], (int)u);
+    c->ext[2] = std::max(c->ext[2], (int)v);
+  }
+  c->ext_k = c->k;
   if (init_fields && c->p.fields_on) {
     // E_r^{-1} from the density at the positions (t = -dt) on the E_r columns; B^{-1/2} from the
     // density at t = -dt/2 on the B columns

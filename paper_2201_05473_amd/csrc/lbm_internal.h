@@ -63,6 +63,9 @@ struct StepArgs {
   const void* jb_in; // particle driver: [2 planes] J_bz (E_z points), J_br (E_r points) at
                      // t_{k-1/2}, logical columns of x^k (auxiliary type)
   void* jb_zero;     // particle driver: [2 planes] cleared at the output index for the next step
+  int jb_c0 = 0;     // particle driver: columns [jb_c0, jb_c1] (logical, frame s) and rows
+  int jb_c1 = -1;    // [0, jb_r1] outside which J_b is zero in both buffers: blocks whose tile
+  int jb_r1 = -1;    // misses them skip J_b (loads and clears)
 };
 
 // One reverse step of the adjoint at the state x^k (k, s, shift as for the forward step k).
@@ -124,6 +127,10 @@ void bunch_sort_shape(const Physics& p, int* rshift, long long* nkeys);
 size_t bunch_sort_bytes(const Physics& p);
 hipError_t launch_bunch_resort(const Physics& p, long long s, const double* in, const int32_t* pid_in, int n,
                                void* scratch, double* out, int32_t* pid_out, hipStream_t st);
+// Extent of the live particles (lab frame, cells of dz): out[0] = min floor(z / dz), out[1] = max
+// floor(z / dz), out[2] = max floor(r / dr); out[0] > out[1] when no particle is live.  One block.
+hipError_t launch_bunch_extent(const Physics& p, const double* bunch, int n, long long cap, int* out,
+                               hipStream_t st);
 // Bunch density (FP64, atomics) on the nodes z = (s + i + zoff) dz, rows (j + 1/2) dr, positions moved
 // by t_ahead along the velocities; dens must be cleared first.
 hipError_t launch_bunch_density(const Physics& p, long long s, double zoff, double t_ahead, const double* bunch,

@@ -107,6 +107,9 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
   const int j0 = (tile / gx) * TR;
   const int tid = threadIdx.x;
   const int tx = tid % TZ, ty = tid / TZ;
+  // particle driver: J_b is zero outside the bunch's bound, so a tile (halo included) that misses it
+  // neither reads J_b nor clears the next step's buffer (uniform)
+  const bool jb_on = DRV && i0 + TZ + 1 >= a.jb_c0 && i0 - 2 <= a.jb_c1 && j0 - 2 <= a.jb_r1;
   const double h = p.h, dt = p.dt;
   const C hc = (C)h, dtc = (C)dt;
   const CF hf = (CF)h, dtf = (CF)dt;
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       const int t = min(tid + s * NTHREADS, NEZ - 1);
       const uint32_t off = rrow(j0 - 1 + t / EZZ) * pitch + zcol(i0 - 1 + t % EZZ);
       hload(Ezp, off, sEzst, s, hez[HDMA ? 0 : s]);
-      if (DRV) hload(plane_rsrc<A>(a.jb_in, plane, 0), off, sJbzst, s, hjz[HDMA ? 0 : s]);
+      if (jb_on) hload(plane_rsrc<A>(a.jb_in, plane, 0), off, sJbzst, s, hjz[HDMA ? 0 : s]);
     }
 #pragma unroll
     for (int s = 0; s < SER; ++s) {
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       const uint32_t off = rrow(j0 - 1 + t / ERZ) * pitch + zcol(i0 - 1 + t % ERZ);
       hload(Erp, off, sErst, s, her[HDMA ? 0 : s]);
       if constexpr (XLO && !HDMA) hxr[s] = bload<uint32_t>(Xp, off);
-      if (DRV) hload(plane_rsrc<A>(a.jb_in, plane, 1), off, sJbrst, s, hjr[HDMA ? 0 : s]);
+      if (jb_on) hload(plane_rsrc<A>(a.jb_in, plane, 1), off, sJbrst, s, hjr[HDMA ? 0 : s]);
     }
   }
   // the population loads below must be issued after every halo load (the wait before the first
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
       for (int s = 0; s < SEZ; ++s) {
         const int t = tid + s * NTHREADS;
         if (t < NEZ) sEz[t / EZZ][t % EZZ] = (CF)hez[s];
-        if (DRV && t < NEZ) sJbz[t / EZZ][t % EZZ] = (CF)hjz[s];
+        if (jb_on && t < NEZ) sJbz[t / EZZ][t % EZZ] = (CF)hjz[s];
       }
 #pragma unroll
       for (int s = 0; s < SER; ++s) {
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
           if constexpr (XLO) v += (CF)lo_er(hxr[s]);
           sEr[t / ERZ][t % ERZ] = v;
         }
-        if (DRV && t < NER) sJbr[t / ERZ][t % ERZ] = (CF)hjr[s];
+        if (jb_on && t < NER) sJbr[t / ERZ][t % ERZ] = (CF)hjr[s];
       }
     }
     __syncthreads();
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
           curl = (bj + (CF)jj * (bj - sBo[bb][aa + 1])) * sIr[bb];
         }
         const CF jf = CF(0.5) * (sJ[0][bb][aa] + sJ[0][bb][aa + 1]);
-        const CF jb = DRV ? sJbz[DRV ? bb : 0][DRV ? aa : 0] : sDz[aa] * sDr[bb];
+        const CF jb = DRV ? (jb_on ? sJbz[DRV ? bb : 0][DRV ? aa : 0] : CF(0)) : sDz[aa] * sDr[bb];
         sEz[bb][aa] = sEz[bb][aa] + dtf * (curl + jf + jb);
       }
     }
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
         if constexpr (COMP) dB += lo_b(sX[bb + 1][aa + 1]) - lo_b(sX[bb + 1][aa]);
         const CF curl = -dB * ih;   // -dB/dz
         const CF jf = CF(0.5) * (sJ[1][bb][aa] + sJ[1][bb + 1][aa]);
-        const CF jbr = DRV ? sJbr[DRV ? bb : 0][DRV ? aa : 0] : CF(0);
+        const CF jbr = jb_on ? sJbr[DRV ? bb : 0][DRV ? aa : 0] : CF(0);
         if constexpr (COMP) {
           float hi = sEr[bb][aa], lo = lo_er(sX[bb + 1][aa + 1]);
           acc_comp(hi, lo, dtf * (curl + jf + jbr));
@@ -452,7 +455,7 @@ __global__ __launch_bounds__(NTHREADS, (ST == 0 || M64) ? 1 : (ST >= 2 ? 7 : (CO
   // --- 8. fluid phase: one site per thread ------------------------------------------------
   if (!site_ok) return;   // no barrier below this point
   const uint32_t oo = j * pitch + o;
-  if (DRV) {
+  if (jb_on) {
     // the next step's deposit buffer, cleared at this output cell
     bstore<A>(plane_rsrc<A>(a.jb_zero, plane, 0), oo, C(0));
     bstore<A>(plane_rsrc<A>(a.jb_zero, plane, 1), oo, C(0));

@@ -100,6 +100,7 @@ def test_call_splits_and_checks_agree():
     for label, cfg, calls in (("one call", base, [45]), ("single steps", base, [1] * 45),
                               ("checks", dict(base, check_every=7), [13, 32]),
                               ("re-sorts", dict(base, resort_every=4), [45]),
+                              ("re-sorts every step", dict(base, resort_every=1), [45]),
                               ("re-sorts and checks", dict(base, resort_every=4, check_every=7), [13, 1, 31])):
         print(f"[bunch calls] {label}", flush=True)
         lat = lattice(cfg, b, pert)
@@ -112,6 +113,38 @@ def test_call_splits_and_checks_agree():
         assert np.array_equal(bg[6] == 0.0, ref_b[6] == 0.0), label
         assert max(bunch_errors(bg, ref_b)) < 1e-10, label
         lat.close()
+
+
+def test_bunch_replaced_mid_run():
+    """lbm_set_bunch(init_fields = 0) after 20 steps replaces a bunch near the window's front with
+    one centred 3 k_p^-1 (60 cells) further back; 100 more steps match the oracle with the same swap
+    (FP64, 1e-10).  The step reads and clears J_b only near the current bunch (its extent widened by
+    c dt per step since it was taken), and that region grows over about 20 cells of the first
+    bunch's last deposit within those steps: that current must not survive there."""
+    cfg = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=5.0,
+                    driver=wl.PARTICLES, max_particles=6000, storage=wl.F64, noise_amp=1e-3, seed=4,
+                    tau=0.7, moving_window=1)
+    a = wl.bunch(cfg, 5000, gamma=5000.0, emittance=0.05, energy_spread=1e-4, seed=8)
+    b = wl.bunch(dict(cfg, zd0=2.0), 3000, gamma=5000.0, emittance=0.05, energy_spread=1e-4, seed=9)
+    pert = wl.density_perturbation(cfg)
+    S, P = O.run(cfg, 20, pert, bunch=a)
+    b[2] += S.k * P.dt                                   # the second bunch's positions at t_19
+    S.bunch = torch.as_tensor(b.copy(), dtype=torch.float64)
+    for _ in range(100):
+        S = O.step(S, P)
+    print("[bunch swap] 20 + 100 steps", flush=True)
+    lat = lattice(cfg, a, pert)
+    lat.step(20)
+    lat.set_bunch(b, False)
+    lat.step(100)
+    st, k, s = lat.state()
+    assert (k, s) == (S.k, S.s)
+    assert comp_errors(st, oracle_state(S, P)).max() < TOL64
+    ref = S.bunch.numpy()
+    bg = lat.bunch()
+    assert np.array_equal(bg[6] == 0.0, ref[6] == 0.0)
+    assert max(bunch_errors(bg, ref)) < 1e-10
+    lat.close()
 
 
 def test_empty_bunch():
