@@ -147,6 +147,36 @@ def test_bunch_replaced_mid_run():
     lat.close()
 
 
+@pytest.mark.parametrize("resort", [0, 3])
+def test_fp32_particle_run(resort):
+    """FP32 storage with the particle driver over 60 steps of the deflected slow bunch (losses
+    included), with the default re-sort interval and with a re-sort every 3 steps: the FP32 tile
+    deposit (shares summed within runs of lanes in FP32) and the J_b bound against the FP64
+    oracle.  Moments and fields within 1e-5 of their group's scale, particle coordinates within
+    1e-6 of theirs, and the same particles lost."""
+    c = CASES["slow_deflected"]
+    cfg = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=4.0,
+                    driver=wl.PARTICLES, max_particles=6000, storage=wl.F32, noise_amp=1e-3, seed=4,
+                    tau=0.7, resort_every=resort, **c["cfg"])
+    b = wl.bunch(cfg, 5000, gamma=c["gamma"], emittance=c["emittance"], energy_spread=c["spread"], seed=8)
+    pert = wl.density_perturbation(cfg)
+    S, P = O.run(dict(cfg, storage=wl.F64), 60, pert, bunch=b)
+    print(f"[bunch fp32] resort_every={resort}", flush=True)
+    lat = lattice(cfg, b, pert)
+    lat.step(60)
+    st, k, s = lat.state()
+    assert (k, s) == (S.k, S.s)
+    errs = comp_errors(st, oracle_state(S, P))
+    ref = S.bunch.numpy()
+    bg = lat.bunch()
+    be = bunch_errors(bg, ref)
+    print("moments/fields", errs[27:].max(), "bunch", be, flush=True)
+    assert errs[27:].max() < 1e-5, errs[27:]
+    assert np.array_equal(bg[6] == 0.0, ref[6] == 0.0)
+    assert max(be) < 1e-6, be
+    lat.close()
+
+
 def test_empty_bunch():
     """A particle-driven context with no particles (and one whose bunch was never set) evolves as
     the plasma with no driver: the oracle's state for an empty bunch, FP64 to 1e-10, over 12
