@@ -382,6 +382,9 @@ def main():
                          "a 64 GB snapshot budget, gradient against FP64 finite differences (minutes)")
     ap.add_argument("--profile-pic", action="store_true",
                     help="for rocprofv3: C2 FP32 driven by the 200,000-particle bunch, timed steps only")
+    ap.add_argument("--pattern-ceiling", action="store_true",
+                    help="run the memory-pattern ceiling program (the FP32 step's access pattern with no "
+                         "arithmetic, and a float4 copy of the same bytes, on the C2 and C3 grids)")
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="for rocprofv3: one C4 lbm_adjoint (2,000 steps, checkpoints every 45) after a "
                          "warm-up run")
@@ -404,6 +407,19 @@ def main():
 
     if args.c5:
         print(json.dumps({"c5": long_plasma_c5()}))
+        return
+
+    if args.pattern_ceiling:
+        import subprocess
+        from paper_2201_05473_amd.build import PATTERN_CEILING
+        if not os.path.exists(PATTERN_CEILING):
+            print(json.dumps({"error": "pattern_ceiling is not built (__graft_entry__.build())"}))
+            sys.exit(1)
+        res = subprocess.run([PATTERN_CEILING], capture_output=True, text=True)
+        if res.returncode != 0:
+            print(res.stderr, file=sys.stderr)
+            sys.exit(res.returncode)
+        print(json.dumps({"pattern_ceiling": [json.loads(l) for l in res.stdout.splitlines() if l.startswith("{")]}))
         return
 
     if args.profile_pic:

@@ -66,6 +66,24 @@ def build_c_client() -> str:
     return C_CLIENT
 
 
+PATTERN_CEILING = os.path.join(LIB_DIR, "pattern_ceiling")
+
+
+def build_pattern_ceiling() -> str:
+    """Compile the standalone memory-pattern ceiling program (csrc/pattern_ceiling.hip: the FP32
+    step's access pattern with no arithmetic, and a float4 copy of the same bytes); returns its
+    path."""
+    os.makedirs(LIB_DIR, exist_ok=True)
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    cmd = [hipcc, *flags, "-o", PATTERN_CEILING, os.path.join(HERE, "csrc", "pattern_ceiling.hip")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise subprocess.CalledProcessError(res.returncode, cmd, res.stdout, res.stderr)
+    return PATTERN_CEILING
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_c_client())
+    print(build_pattern_ceiling())
