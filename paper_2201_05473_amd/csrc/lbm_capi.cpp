@@ -207,11 +207,12 @@ struct lbm_ctx {
   long long nbunch = 0;
   int jcur = 0;
   int bcur = 0;
-  // extent of the live particles when the bunch was last set or re-sorted (positions at
-  // t_{ext_k - 1}; lab-frame cells: lowest and highest column of z, highest row of r; empty when
-  // ext[0] > ext[1]): it bounds where the deposits of the following steps can fall
+  // extent of the live particles when the bunch was last set or re-sorted (lab-frame cells: lowest
+  // and highest column of z, highest row of r; empty when ext[0] > ext[1]) and the number of steps
+  // taken since (a state loaded in between changes k, not the distance the particles have moved):
+  // it bounds where the deposits of the following steps can fall
   int ext[3] = {INT32_MAX, INT32_MIN, INT32_MIN};
-  long long ext_k = 0;
+  long long ext_age = 0;
   // device address of the library's fixed diagnostic scratch on the context's device
   double* scratch = nullptr;
   // set when a failed lbm_adjoint_revolve could not put the initial state back into the context's
@@ -258,11 +259,11 @@ hipError_t driver_density_plane(lbm_ctx* c, const double** out) {
   return e;
 }
 
-// Where J_b can be non-zero at step k (the deposit the step reads, the previous one its clear
-// removes, the next one the cleared buffer receives): the extent of the live particles at
-// t_{ext_k - 1}, widened by the distance a particle can travel (|v| < c: dt per step in z and in r)
-// between then and the midpoints of those deposits, by the stencils' reach and by one cell of
-// rounding.  Columns in the window frame of step k.
+// Where J_b can be non-zero at the step about to be taken (the deposit the step reads, the
+// previous one its clear removes, the next one the cleared buffer receives): the extent of the live
+// particles ext_age steps ago, widened by the distance a particle can travel (|v| < c: dt per step
+// in z and in r) between then and the midpoints of those deposits, by the stencils' reach and by
+// one cell of rounding.  Columns in the window frame of the step.
 void jb_bound(const lbm_ctx* c, lbm::StepArgs& a) {
   if (c->ext[0] > c->ext[1]) {   // no live particle: no deposit
     a.jb_c0 = 1 << 30;
@@ -270,8 +271,7 @@ void jb_bound(const lbm_ctx* c, lbm::StepArgs& a) {
     a.jb_r1 = -(1 << 30);
     return;
   }
-  const long long n = c->k > c->ext_k ? c->k - c->ext_k : c->ext_k - c->k;
-  const long long m = (long long)std::ceil(((double)n + 2.0) * c->p.dt / c->p.h) + 3;
+  const long long m = (long long)std::ceil(((double)c->ext_age + 2.0) * c->p.dt / c->p.h) + 3;
   const auto clampi = [](long long v) { return (int)std::min<long long>(std::max<long long>(v, -(1LL << 30)), 1LL << 30); };
   a.jb_c0 = clampi((long long)c->ext[0] - m - c->s);
   a.jb_c1 = clampi((long long)c->ext[1] + 1 + m - c->s);
@@ -401,7 +401,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
           HIP_CHECK(hipMemcpyAsync(ext, c->ext_dev(), sizeof ext, hipMemcpyDeviceToHost, c->stream), "copy");
           HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
           std::memcpy(c->ext, ext, sizeof ext);
-          c->ext_k = c->k;
+          c->ext_age = 0;
         }
         HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,
                                          c->jb(c->jcur), c->stream),
@@ -428,6 +428,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     c->cur ^= 1;
     c->k += 1;
     c->s += a.shift;
+    c->ext_age += 1;
     if (c->cfg.check_every > 0 && c->k % c->cfg.check_every == 0) {
       int rc = run_check(c);
       if (rc) return rc;
@@ -1416,7 +1417,7 @@ int set_bunch(lbm_ctx* c, int64_t n, const double* bunch, int32_t init_fields) {
     c->ext[1] = std::max(c->ext[1], (int)u);
     c->ext[2] = std::max(c->ext[2], (int)v);
   }
-  c->ext_k = c->k;
+  c->ext_age = 0;
   if (init_fields && c->p.fields_on) {
     // E_r^{-1} from the density at the positions (t = -dt) on the E_r columns; B^{-1/2} from the
     // density at t = -dt/2 on the B columns
