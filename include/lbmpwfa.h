@@ -185,7 +185,9 @@ int lbm_init(const lbm_config* cfg, const double* n_pert, const double* p_init,
 /* Advance nsteps >= 0 steps.  One step (Eqs. (5)-(10), (13), (14)): Ampere with the previous
  * step's post-kick current and the driver current, Faraday, pull-stream of the 27 populations,
  * moments, Lorentz and axisymmetric sources, collision (cfg.collision), window shift when due.  Stream-
- * ordered and asynchronous unless cfg.check_every > 0. */
+ * ordered and asynchronous, except that it synchronises the stream at each diagnostic check
+ * (cfg.check_every > 0) and, with LBM_DRIVER_PARTICLES and particles in the bunch, at each re-sort
+ * (every cfg.resort_every steps), which reads back the bunch's extent. */
 int lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Moments of the last step's post-collision state, [3][nr][nz]: n, J_z = n beta_z,
