@@ -132,7 +132,7 @@ enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
  *                 otherwise.
  *   resort_every  LBM_DRIVER_PARTICLES: every that many steps lbm_step re-sorts the stored bunch
  *                 on the device by grid cell (column, then row), so that the particles of a
- *                 wavefront stay close together as the bunch disperses; 0 is 1000, negative
+ *                 wavefront stay close together as the bunch disperses; 0 is 500, negative
  *                 values are rejected.  The caller's order is kept (lbm_get_bunch).  Ignored
  *                 otherwise. */
 typedef struct {

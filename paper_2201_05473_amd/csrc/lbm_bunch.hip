@@ -582,15 +582,16 @@ hipError_t launch_bunch_resort(const Physics& p, long long s, const double* in, 
 
 namespace {
 
-// Extent of the live particles (one block of EXT_T threads striding over the bunch): lowest and
-// highest column floor(z / dz) and highest row floor(r / dr), in the lab frame.
+// Extent of the live particles, per block of EXT_T threads striding over the bunch: lowest and
+// highest column floor(z / dz) and highest row floor(r / dr), in the lab frame, into
+// out[3 * blockIdx.x ..].
 constexpr int EXT_T = 1024;
 __global__ __launch_bounds__(EXT_T) void bunch_extent_kernel(Physics p, const double* b, int n, long long cap,
                                                              int* out) {
   __shared__ int part[EXT_T / 64][3];
   const double ih = 1.0 / p.h;
   int zlo = INT32_MAX, zhi = INT32_MIN, rhi = INT32_MIN;
-  for (int q = threadIdx.x; q < n; q += EXT_T) {
+  for (int q = blockIdx.x * EXT_T + threadIdx.x; q < n; q += gridDim.x * EXT_T) {
     if (b[6 * cap + q] == 0.0) continue;
     const double x = b[q], y = b[cap + q];
     const double u = fmin(fmax(floor(b[2 * cap + q] * ih), -1e9), 1e9);
@@ -614,17 +615,19 @@ __global__ __launch_bounds__(EXT_T) void bunch_extent_kernel(Physics p, const do
       zhi = max(zhi, part[w][1]);
       rhi = max(rhi, part[w][2]);
     }
-    out[0] = zlo;
-    out[1] = zhi;
-    out[2] = rhi;
+    out[3 * blockIdx.x + 0] = zlo;
+    out[3 * blockIdx.x + 1] = zhi;
+    out[3 * blockIdx.x + 2] = rhi;
   }
 }
 
 }  // namespace
 
+int bunch_extent_blocks(int n) { return n <= 0 ? 1 : (n + EXT_T - 1) / EXT_T < EXTENT_BLOCKS ? (n + EXT_T - 1) / EXT_T : EXTENT_BLOCKS; }
+
 hipError_t launch_bunch_extent(const Physics& p, const double* bunch, int n, long long cap, int* out,
                                hipStream_t st) {
-  bunch_extent_kernel<<<1, EXT_T, 0, st>>>(p, bunch, n, cap, out);
+  bunch_extent_kernel<<<bunch_extent_blocks(n), EXT_T, 0, st>>>(p, bunch, n, cap, out);
   return hipGetLastError();
 }
 

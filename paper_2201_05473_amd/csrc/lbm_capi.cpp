@@ -174,7 +174,7 @@ Layout layout(const Physics& p, int storage) {
     L.sort = off;
     off += round_up(lbm::bunch_sort_bytes(p), 256);
     L.ext = off;
-    off += 256;
+    off += round_up(3 * lbm::EXTENT_BLOCKS * sizeof(int), 256);
     for (int b = 0; b < 2; ++b) {
       L.jb[b] = off;
       off += round_up(2 * plane * aux_bytes(storage), 256);
@@ -368,7 +368,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
   // steps of this call (not across a diagnostic check, which reads the bunch at t_{k-1}, nor across
   // a re-sort, which sorts the positions at t_{k-1}); moved: the bunch is already at t_k with
   // J_b(t_{k-1/2}) in jb(jcur)
-  const long long resort = c->cfg.resort_every > 0 ? c->cfg.resort_every : 1000;
+  const long long resort = c->cfg.resort_every > 0 ? c->cfg.resort_every : 500;
   bool moved = false;
   for (int64_t n = 0; n < nsteps; ++n) {
     lbm::StepArgs a;
@@ -397,10 +397,18 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
           // a fresh extent tightens the J_b bound (one synchronisation per re-sort)
           HIP_CHECK(lbm::launch_bunch_extent(c->p, c->bunch(), (int)c->nbunch, c->p.cap, c->ext_dev(), c->stream),
                     "bunch extent launch");
-          int ext[3];
-          HIP_CHECK(hipMemcpyAsync(ext, c->ext_dev(), sizeof ext, hipMemcpyDeviceToHost, c->stream), "copy");
+          const int nb = lbm::bunch_extent_blocks((int)c->nbunch);
+          int part[3 * lbm::EXTENT_BLOCKS];
+          HIP_CHECK(hipMemcpyAsync(part, c->ext_dev(), 3 * nb * sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                    "copy");
           HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
-          std::memcpy(c->ext, ext, sizeof ext);
+          c->ext[0] = INT32_MAX;
+          c->ext[1] = c->ext[2] = INT32_MIN;
+          for (int b = 0; b < nb; ++b) {
+            c->ext[0] = std::min(c->ext[0], part[3 * b]);
+            c->ext[1] = std::max(c->ext[1], part[3 * b + 1]);
+            c->ext[2] = std::max(c->ext[2], part[3 * b + 2]);
+          }
           c->ext_age = 0;
         }
         HIP_CHECK(lbm::launch_bunch_move(c->storage, c->p, c->s, c->bunch(), (int)c->nbunch, c->p.cap,

@@ -127,8 +127,12 @@ void bunch_sort_shape(const Physics& p, int* rshift, long long* nkeys);
 size_t bunch_sort_bytes(const Physics& p);
 hipError_t launch_bunch_resort(const Physics& p, long long s, const double* in, const int32_t* pid_in, int n,
                                void* scratch, double* out, int32_t* pid_out, hipStream_t st);
-// Extent of the live particles (lab frame, cells of dz): out[0] = min floor(z / dz), out[1] = max
-// floor(z / dz), out[2] = max floor(r / dr); out[0] > out[1] when no particle is live.  One block.
+// Extent of the live particles (lab frame, cells of dz), as partial extents of
+// bunch_extent_blocks(n) <= EXTENT_BLOCKS blocks: out[3 b] = min floor(z / dz), out[3 b + 1] = max
+// floor(z / dz), out[3 b + 2] = max floor(r / dr) over block b's particles (min > max when it has no
+// live particle); the caller reduces them.
+constexpr int EXTENT_BLOCKS = 128;
+int bunch_extent_blocks(int n);
 hipError_t launch_bunch_extent(const Physics& p, const double* bunch, int n, long long cap, int* out,
                                hipStream_t st);
 // Bunch density (FP64, atomics) on the nodes z = (s + i + zoff) dz, rows (j + 1/2) dr, positions moved
