@@ -53,6 +53,11 @@ CASES = {
                       steps=30),
     # periodic z (the step variant with the wrap code; non-periodic grids take the one without)
     "periodic_z": dict(cfg=dict(periodic=1), gamma=20.0, emittance=0.1, spread=0.01, steps=30),
+    # moving window with the regularised and the MRT collision operators
+    "window_regularised": dict(cfg=dict(moving_window=1, collision=wl.REG), gamma=20.0, emittance=0.1,
+                               spread=0.01, steps=30),
+    "window_mrt": dict(cfg=dict(moving_window=1, collision=wl.MRT, mrt_se=1.3, mrt_seps=0.6, mrt_sq=1.7,
+                                mrt_spi=1.2), gamma=20.0, emittance=0.1, spread=0.01, steps=30),
 }
 
 
