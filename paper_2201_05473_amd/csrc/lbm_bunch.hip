@@ -5,10 +5,11 @@
 // w (electrons, n_0 / k_p^3).  After k steps the positions are at t_{k-1} and the momenta at
 // t_{k-1/2}.  Step k runs:
 //   bunch_move_kernel  positions to t_k, current w beta at the midpoints -> J_b(t_{k-1/2}) (z at the
-//                      E_z points, r at the E_r points): summed per block in LDS when the block's
-//                      particles span few columns (the bunch is stored by column of z, then by
-//                      radius: sorted on upload, and again on the device every few hundred or
-//                      thousand steps as the particles drift apart), then added to the grid with
+//                      E_z points, r at the E_r points): the shares of neighbouring lanes that
+//                      start at the same node summed within the wavefront, then per block in LDS
+//                      when the block's particles span few columns (the bunch is stored by column
+//                      of z, then by radius: sorted on upload, and again on the device every few
+//                      hundred steps as the particles drift apart), then added to the grid with
 //                      hardware float atomics;
 //   (the step kernel reads J_b in Ampere's law)
 //   bunch_push_kernel  Boris push of the momenta to t_{k+1/2} with E^k and
