@@ -92,9 +92,12 @@ Readings of the paper (where it is silent, garbled or inconsistent):
       B_theta = E_r as for the rigid driver).
 
 Pins.  tests/test_oracle_pins.py checks this module against closed forms, invariants and brute
-force.  Three readings have no closed form to check them against and are pinned only through
-invariants (a plasma at rest stays at rest, axis mirror symmetry, conservation): the exact lag
-and stencil of the axisymmetric source (R10), the time level of the ghost moments (R11), and the
+force.  The stencil of the axisymmetric source (R10) is pinned by the exact radial heat kernel
+and by second-order convergence to it under refinement (a source dividing by another radius
+converges at first order).  Three readings have no closed form to check them against and are
+pinned only through invariants (a plasma at rest stays at rest, axis mirror symmetry,
+conservation): the exact time lag of that source (the previous step's moments; the current ones
+would converge at the same order), the time level of the ghost moments (R11), and the
 equilibrium ghosts at the axis row.  For those the module is the definition: parity unpinned.
 
 State after k completed steps (k = 0 is the initial state):
