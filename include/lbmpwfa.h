@@ -233,9 +233,10 @@ int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);
  * theta = (ramp_len, n0, sigma_r, nb).  The objective J is the witness field: E_z of the state
  * on row obj->row, linearly interpolated in z at z_d(t_{N-1}) - obj->z_behind after N steps
  * (the time level of E in the state).  On the device the adjoint computes and stores its
- * variables in the precision of the auxiliary planes (FP64 for LBM_F64, FP32 for LBM_F32 and
- * LBM_F16), reads the forward states in their storage precision, and sums the theta partials in
- * FP64; J and grad are FP64.  Host-side
+ * variables in the precision of the auxiliary planes (FP64 for LBM_F64, FP32 for LBM_F32,
+ * LBM_F16 and LBM_F16N), reads the forward states in their storage precision, and sums the theta
+ * partials in FP64; J and grad are FP64.  With LBM_F16N the state it differentiates is the state
+ * view of lbm_get_state (the populations, not their stored parts off the equilibrium).  Host-side
  * adjoint arrays are FP64 in the layout of lbm_get_state: [27][nr][nz] populations,
  * [3][nr][nz] moments, [3][nr][nz] E_z, E_r, B_theta.  Every collision operator is covered:
  * each writes the post-collision populations as P f + (I - P) f_eq + w_i dt F with a fixed linear

@@ -705,7 +705,6 @@ int adj_check(lbm_ctx* c, void* ws, size_t bytes, size_t need) {
   if (bytes < need) return fail(LBM_ENOMEM, "adjoint workspace too small: %zu < %zu bytes", bytes, need);
   if ((c->p.per_z && c->p.nz < 5) || (c->p.per_r && c->p.nr < 5))
     return fail(LBM_EINVAL, "the adjoint needs at least 5 cells along periodic dimensions");
-  if (c->storage == LBM_F16N) return fail(LBM_EINVAL, "the adjoint is implemented for LBM_F64, LBM_F32 and LBM_F16 storage");
   if (c->storage != LBM_F64 && c->p.fp64_math && c->p.coll != LBM_BGK)
     return fail(LBM_EINVAL, "the adjoint takes fp64_math = 1 with the BGK collision only");
   if (c->p.driver != LBM_DRIVER_RIGID) return fail(LBM_EINVAL, "the adjoint is implemented for the rigid driver only");

@@ -1091,12 +1091,12 @@ static void launch_step_c(const StepArgs& a, dim3 grid, hipStream_t st) {
   else step_kernel<ST, false, M64, false, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
 }
 
-// The site-record variant is the adjoint's forward recompute (no storage 3, no particle driver;
-// FP64 arithmetic on FP32 / FP16 storage for BGK only).  Without fields it takes the general
-// (wrap) variant: that case is not on any timed path.
+// The site-record variant is the adjoint's forward recompute (no particle driver; FP64
+// arithmetic on reduced storage for BGK only).  Without fields it takes the general (wrap)
+// variant: that case is not on any timed path.
 template <int ST, bool M64, int COLL>
 static void launch_step_s(const StepArgs& a, dim3 grid, hipStream_t st) {
-  if constexpr (!neq_storage(ST) && (!M64 || COLL == 0)) {
+  if constexpr (!M64 || COLL == 0) {
     if (a.site_out) {
       if (!a.p.fields_on) step_kernel<ST, false, M64, true, COLL, true, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);
       else if (!a.p.per_z && !a.p.per_r) step_kernel<ST, true, M64, true, COLL, false, 0><<<grid, dim3(NTHREADS), 0, st>>>(a);

@@ -272,14 +272,16 @@ def oracle_wake_gradient(cfg, n):
 
 
 @pytest.mark.parametrize("coll,storage,m64", [
-    (wl.BGK, wl.F32, 1), (wl.BGK, wl.F16, 0), (wl.BGK, wl.F16, 1), (wl.MRT, wl.F16, 0)])
+    (wl.BGK, wl.F32, 1), (wl.BGK, wl.F16, 0), (wl.BGK, wl.F16, 1), (wl.MRT, wl.F16, 0),
+    (wl.BGK, wl.F16N, 0), (wl.BGK, wl.F16N, 1), (wl.MRT, wl.F16N, 0)])
 def test_reduced_storage_adjoint_matches_oracle(coll, storage, m64):
-    """lbm_adjoint with the forward states stored in FP32 or FP16 (and FP32 or FP64 arithmetic in
-    the forward) on the 128 x 32 copy of C4, 60 steps, against the FP64 oracle's gradient
-    (max-norm error over the four partials, relative to the largest).  Bounds: 1e-5 for FP32
-    storage (measured 2.4e-7) and 1e-2 for FP16 storage (measured 2.5e-3 to 2.6e-3, with either
-    arithmetic: the FP16 rounding of the stored states sets it; the two small partials, ramp
-    length and n0, are off by 3-6 % of their own size)."""
+    """lbm_adjoint with the forward states stored in FP32, FP16 or FP16N (and FP32 or FP64
+    arithmetic in the forward) on the 128 x 32 copy of C4, 60 steps, against the FP64 oracle's
+    gradient (max-norm error over the four partials, relative to the largest).  Bounds: 1e-5 for
+    FP32 storage (measured 2.4e-7 to 5.3e-7), 1e-2 for FP16 storage (measured 2.5e-3 to 2.6e-3,
+    with either arithmetic: the FP16 rounding of the stored states sets it; the two small
+    partials, ramp length and n0, are off by 3-6 % of their own size) and 3e-3 for FP16N (measured
+    8.8e-4 to 1.0e-3: its states are closer to the FP64 ones)."""
     from paper_2201_05473_amd import Lattice
     cfg = dict(wake_cfg(storage), collision=coll, fp64_math=m64)
     if coll == wl.MRT:
@@ -290,7 +292,7 @@ def test_reduced_storage_adjoint_matches_oracle(coll, storage, m64):
     J, grad = Lattice(cfg).adjoint(n, ck, z_behind=cfg["z_behind"], row=0)
     err = np.abs(grad - gref).max() / np.abs(gref).max()
     print(f"  grad {grad} oracle {gref} rel {err:.2e}", flush=True)
-    assert err < (1e-5 if storage == wl.F32 else 1e-2), (grad, gref)
+    assert err < {wl.F32: 1e-5, wl.F16: 1e-2, wl.F16N: 3e-3}[storage], (grad, gref)
 
 
 def test_revolve_fd_c5_full_grid():

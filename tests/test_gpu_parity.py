@@ -303,12 +303,12 @@ def test_fp32_fp16_parity_c2_copy():
         assert e16n["Ez"] < 0.25 * e16["Ez"] and e16n["Er"] < 0.25 * e16["Er"], errs
 
 
-def test_f16n_state_view_checkpoint_and_adjoint():
+def test_f16n_state_view_and_checkpoint():
     """FP16N: lbm_get_state / lbm_set_state round-trip (the moments are written before the
-    populations, which are stored relative to them), lbm_save / lbm_load resume bit for bit, an
-    equilibrium initial state stores zero off-equilibrium parts (the state view then holds the
-    equilibrium of the stored moments), and the adjoint rejects the mode."""
-    from paper_2201_05473_amd import LBM_EINVAL, LbmError, Lattice
+    populations, which are stored relative to them), lbm_save / lbm_load resume bit for bit, and
+    an equilibrium initial state stores zero off-equilibrium parts (the state view then holds the
+    equilibrium of the stored moments)."""
+    from paper_2201_05473_amd import Lattice
     cfg = wl.config(None, nz=100, nr=10, nb=0.2, sigma_z=0.3, sigma_r=0.3, zd0=3.0, moving_window=1,
                     storage=wl.F16N, noise_amp=1e-3, seed=2)
     pert = wl.density_perturbation(cfg)
@@ -329,9 +329,6 @@ def test_f16n_state_view_checkpoint_and_adjoint():
     d.step(10)
     s3, _, _ = d.state()
     assert np.array_equal(s3, s1)
-    with pytest.raises(LbmError) as ei:
-        Lattice(cfg).adjoint(4, 2)
-    assert ei.value.code == LBM_EINVAL
     for x in (lat, b, c, d):
         x.close()
 
