@@ -222,13 +222,13 @@ def test_adjoint_fd_c4(coll):
 
 
 def test_adjoint_rejections():
-    """The adjoint refuses FP64 arithmetic on FP32 storage for operators other than BGK (the
-    forward recompute it needs exists for BGK only there) and FP16N storage."""
+    """The adjoint refuses FP64 arithmetic on reduced storage (FP32, FP16, FP16N) for operators
+    other than BGK: the forward recompute it needs exists for BGK only there."""
     from paper_2201_05473_amd import LBM_EINVAL, LbmError, Lattice
     base = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.3, tau=0.7)
     for extra, why in ((dict(collision=wl.TRT, storage=wl.F32, fp64_math=1), "fp64_math"),
                        (dict(collision=wl.MRT, storage=wl.F16, fp64_math=1), "fp64_math"),
-                       (dict(collision=wl.REG, storage=wl.F16N), "storage")):
+                       (dict(collision=wl.REG, storage=wl.F16N, fp64_math=1), "fp64_math")):
         lat = Lattice(dict(base, **extra))
         with pytest.raises(LbmError) as ei:
             lat.adjoint(4, 2, z_behind=1.0)
