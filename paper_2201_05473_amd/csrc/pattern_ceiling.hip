@@ -12,12 +12,18 @@
 // same kernel on unpadded planes in plain block order, and copy_kernel moving the same number of
 // bytes as one contiguous float4 stream, are measured beside it.
 //
+// With --arith the FP32 pattern is measured again on both grids with 27 w dependent-free
+// multiply-adds per site added between the loads and the stores (w = 0 .. 48; the step issues about
+// 1,400 vector instructions per site): how much arithmetic the pattern's rate absorbs on a grid the
+// MALL partly serves (C2) and on one it cannot (C3).
+//
 // Standalone program (not part of the library): prints one JSON line per measurement.  Every index
 // is clamped into the arrays, and the grids are whole multiples of the tile.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #define CK(x)                                                                              \
   do {                                                                                     \
@@ -50,7 +56,8 @@ __device__ __forceinline__ int cz(int q) { return (q == 1 || q == 5 || q == 8) ?
 __device__ __forceinline__ int cr(int q) { return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0); }
 __device__ __forceinline__ int clampi(int x, int n) { return x < 0 ? 0 : (x >= n ? n - 1 : x); }
 
-template <typename P, typename X, int NAUX, bool XCD>
+// WORK: rounds of 27 multiply-adds per site between the loads and the stores (0: the pure pattern)
+template <typename P, typename X, int NAUX, bool XCD, int WORK>
 __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __restrict__ pin, P* __restrict__ pout,
                                                           const X* __restrict__ ain, X* __restrict__ aout) {
   const int gx = g.nz / TZ;
@@ -71,6 +78,11 @@ __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __res
   X s = X(0);
 #pragma unroll
   for (int c = 0; c < NPOP; ++c) s += f[c];
+#pragma unroll 1
+  for (int w = 0; w < WORK; ++w) {
+#pragma unroll
+    for (int c = 0; c < NPOP; ++c) f[c] = f[c] * X(0.999999) + X(1e-9) * s;
+  }
 #pragma unroll
   for (int c = 0; c < NPOP; ++c) pout[c * g.plane + o] = (P)(f[c] + X(1e-7) * s);
 #pragma unroll
@@ -91,7 +103,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ in
 
 // One measurement: the pattern (step layout and order, then unpadded and in plain order) and the
 // float4 copy of the same bytes, for population type P and NAUX auxiliary words of type X.
-template <typename P, typename X, int NAUX>
+template <typename P, typename X, int NAUX, int WORK = 0>
 void measure(const char* name, int nz, int nr, int iters, bool variants) {
   Grid g;
   g.nz = nz;
@@ -122,9 +134,9 @@ void measure(const char* name, int nz, int nr, int iters, bool variants) {
     if (k == 1 && !variants) continue;
     auto launch = [&] {
       if (k == 0) {
-        pattern_kernel<P, X, NAUX, true><<<tiles, TZ * TR>>>(g, pin, pout, ain, aout);
+        pattern_kernel<P, X, NAUX, true, WORK><<<tiles, TZ * TR>>>(g, pin, pout, ain, aout);
       } else if (k == 1) {
-        pattern_kernel<P, X, NAUX, false><<<tiles, TZ * TR>>>(gu, pin, pout, ain, aout);
+        pattern_kernel<P, X, NAUX, false, WORK><<<tiles, TZ * TR>>>(gu, pin, pout, ain, aout);
       } else {
         copy_kernel<<<(unsigned)((n4p + 255) / 256), 256>>>((const float4*)pin, (float4*)pout, n4p);
         copy_kernel<<<(unsigned)((n4a + 255) / 256), 256>>>((const float4*)ain, (float4*)aout, n4a);
@@ -140,9 +152,9 @@ void measure(const char* name, int nz, int nr, int iters, bool variants) {
     float ms;
     CK(hipEventElapsedTime(&ms, e0, e1));
     const double us = ms * 1e3 / iters;
-    printf("{\"workload\": \"%s %dx%d\", \"kernel\": \"%s\", \"bytes_per_site\": %d, \"us\": %.2f, "
-           "\"GBps\": %.1f, \"frac_of_8TBps\": %.4f}\n",
-           name, nz, nr, kname[k], bps, us, bytes / us / 1e3, bytes / us / 1e3 / 8000.0);
+    printf("{\"workload\": \"%s %dx%d\", \"kernel\": \"%s\", \"fma_per_site\": %d, \"bytes_per_site\": %d, "
+           "\"us\": %.2f, \"GBps\": %.1f, \"frac_of_8TBps\": %.4f}\n",
+           name, nz, nr, kname[k], k == 2 ? 0 : NPOP * WORK, bps, us, bytes / us / 1e3, bytes / us / 1e3 / 8000.0);
     fflush(stdout);
   }
   CK(hipEventDestroy(e0));
@@ -153,8 +165,23 @@ void measure(const char* name, int nz, int nr, int iters, bool variants) {
   CK(hipFree(aout));
 }
 
-int main() {
+int main(int argc, char** argv) {
   CK(hipSetDevice(0));
+  if (argc > 1 && std::strcmp(argv[1], "--arith") == 0) {
+    measure<float, float, 7, 0>("C2 FP32", 2048, 512, 400, false);
+    measure<float, float, 7, 0>("C3 FP32", 4096, 1024, 100, false);
+    measure<float, float, 7, 8>("C2 FP32", 2048, 512, 400, false);
+    measure<float, float, 7, 8>("C3 FP32", 4096, 1024, 100, false);
+    measure<float, float, 7, 16>("C2 FP32", 2048, 512, 400, false);
+    measure<float, float, 7, 16>("C3 FP32", 4096, 1024, 100, false);
+    measure<float, float, 7, 24>("C2 FP32", 2048, 512, 400, false);
+    measure<float, float, 7, 24>("C3 FP32", 4096, 1024, 100, false);
+    measure<float, float, 7, 32>("C2 FP32", 2048, 512, 400, false);
+    measure<float, float, 7, 32>("C3 FP32", 4096, 1024, 100, false);
+    measure<float, float, 7, 48>("C2 FP32", 2048, 512, 400, false);
+    measure<float, float, 7, 48>("C3 FP32", 4096, 1024, 100, false);
+    return 0;
+  }
   measure<float, float, 7>("C2 FP32", 2048, 512, 400, true);
   measure<float, float, 7>("C3 FP32", 4096, 1024, 100, true);
   measure<_Float16, float, 6>("C3 FP16", 4096, 1024, 100, false);
