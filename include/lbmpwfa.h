@@ -124,7 +124,10 @@ enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
  *   driver        LBM_DRIVER_RIGID (nb, sigma_z, sigma_r, zd0 above) or LBM_DRIVER_PARTICLES
  *                 (a macroparticle bunch set with lbm_set_bunch; nb .. zd0 are then unused)
  *   max_particles LBM_DRIVER_PARTICLES: capacity of the bunch, in [0, 2^31); the workspace holds
- *                 7 doubles per particle.  Ignored otherwise.
+ *                 128 bytes per particle (the 7 doubles twice, since a re-sort moves the bunch to
+ *                 a second buffer, the caller's index of each stored particle twice, and the
+ *                 re-sort's key and rank) besides the per-grid buffers of the driver (two J_b plane
+ *                 pairs, a density plane, the re-sort's count per cell).  Ignored otherwise.
  *   mrt_se, mrt_seps, mrt_sq, mrt_spi
  *                 LBM_MRT only: relaxation rates (1 / relaxation time) of the energy, energy
  *                 square, heat-flux and stress moments, each in (0, 2); all four 1/tau is BGK,
