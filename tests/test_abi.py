@@ -61,6 +61,17 @@ def test_struct_layout_matches_c(lib, tmp_path):
     assert vals == expect
 
 
+def test_particle_workspace_growth(lib):
+    """The particle driver's workspace grows by 128 bytes per particle of capacity (two copies of
+    the 7 doubles, two int32 caller indices, the re-sort's uint32 key and rank), up to the 256-byte
+    rounding of its six per-particle regions."""
+    base = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.2, driver=wl.PARTICLES)
+    w0 = lib.lbm_workspace_bytes(dict(base, max_particles=0))
+    for n in (1000, 100000):
+        grow = lib.lbm_workspace_bytes(dict(base, max_particles=n)) - w0
+        assert 128 * n <= grow <= 128 * n + 6 * 256, (n, grow)
+
+
 @pytest.mark.parametrize("bad", [
     dict(tau=0.5), dict(tau=0.3), dict(dr=0.06), dict(c_dt_over_dz=0.6), dict(c_dt_over_dz=0.0),
     dict(nz=2), dict(nr=2), dict(ramp_kind=1, ramp_len=0.0), dict(ramp_kind=3),
@@ -73,17 +84,6 @@ def test_struct_layout_matches_c(lib, tmp_path):
     dict(driver=1, max_particles=4, resort_every=-1),
     dict(nz=8192, nr=8193), dict(nz=64, nr=65536), dict(tau=float("nan")), dict(dz=-0.05, dr=-0.05),
 ])
-def test_particle_workspace_growth(lib):
-    """The particle driver's workspace grows by 128 bytes per particle of capacity (two copies of
-    the 7 doubles, two int32 caller indices, the re-sort's uint32 key and rank), up to the 256-byte
-    rounding of its six per-particle regions."""
-    base = wl.config(None, nz=64, nr=8, nb=0.3, zd0=2.0, sigma_z=0.3, sigma_r=0.2, driver=wl.PARTICLES)
-    w0 = lib.lbm_workspace_bytes(dict(base, max_particles=0))
-    for n in (1000, 100000):
-        grow = lib.lbm_workspace_bytes(dict(base, max_particles=n)) - w0
-        assert 128 * n <= grow <= 128 * n + 6 * 256, (n, grow)
-
-
 def test_invalid_configs_rejected(lib, bad):
     with pytest.raises(lib.LbmError) as ei:
         lib.lbm_workspace_bytes(wl.config(None, **bad))
