@@ -346,9 +346,11 @@ int lbm_bubble_length(lbm_ctx* ctx, int32_t row, double n_star, double z_from, d
  * runs out; LBM_EHIP if the upload fails, which leaves the context with no particles. */
 int lbm_set_bunch(lbm_ctx* ctx, int64_t n, const double* bunch, int32_t init_fields);
 
-/* Current bunch, [7][n] in the layout of lbm_set_bunch, into host memory of at least 7 * n_max
- * doubles; the number of particles goes to *n (lost particles included, with w = 0).  LBM_EINVAL
- * if n_max is smaller.  Synchronising. */
+/* Current bunch, [7][n] in the layout of lbm_set_bunch and in the caller's order (lbm_step
+ * re-sorts the stored bunch; a device index array maps it back), into host memory of at least
+ * 7 * n_max doubles; the number of particles goes to *n (lost particles included, with w = 0).
+ * LBM_EINVAL if n_max is smaller; LBM_ESTATE (bunch left unwritten) if the index array read back
+ * is not a permutation; LBM_EHIP if a download fails.  Synchronising. */
 int lbm_get_bunch(lbm_ctx* ctx, double* bunch, int64_t n_max, int64_t* n);
 
 /* Step and window-shift counters of the state. */
