@@ -53,8 +53,8 @@ enum {
  * w_i n_bg(z); diagnostics are always accumulated in FP64.  F16N: as F16, but each population
  * is stored as its part off the equilibrium (Eq. (9)) of the moments stored at its own site,
  * which are FP32: the same bytes as F16 with about a tenth of its error, for more arithmetic per
- * step.  The adjoint (lbm_adjoint, lbm_vjp_*) takes F64, F32 and F16 (with fp64_math = 1 on
- * F32 and F16 for the BGK collision only). */
+ * step.  The adjoint (lbm_adjoint, lbm_vjp_*) takes every storage (with fp64_math = 1 on F32,
+ * F16 and F16N for the BGK collision only). */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_F16N = 3 };
 
 /* Collision operator of the three lattices.  The paper uses BGK (Eq. (7)) and notes (Sec. IV)
