@@ -17,6 +17,10 @@
 // 1,400 vector instructions per site): how much arithmetic the pattern's rate absorbs on a grid the
 // MALL partly serves (C2) and on one it cannot (C3).
 //
+// With --zmarch the FP32 pattern is measured as a z-marching kernel instead: each block walks SEG
+// consecutive tiles of one row strip along z (blocks in the XCD-aware order), issuing the next
+// tile's loads before the current tile's stores.
+//
 // Standalone program (not part of the library): prints one JSON line per measurement.  Every index
 // is clamped into the arrays, and the grids are whole multiples of the tile.
 #include <hip/hip_runtime.h>
@@ -87,6 +91,49 @@ __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __res
   for (int c = 0; c < NPOP; ++c) pout[c * g.plane + o] = (P)(f[c] + X(1e-7) * s);
 #pragma unroll
   for (int c = 0; c < NAUX; ++c) aout[c * g.plane + o] = a[c] + X(1e-7) * s;
+}
+
+// z-marching: block b owns SEG consecutive tiles of one row strip and walks them along z, the next
+// tile's 34 loads issued before the current tile's 34 stores (FP32 only)
+template <int SEG>
+__global__ __launch_bounds__(TZ * TR) void zmarch_kernel(Grid g, const float* __restrict__ pin, float* __restrict__ pout,
+                                                         const float* __restrict__ ain, float* __restrict__ aout) {
+  const int gx = g.nz / TZ;
+  const int segs = gx / SEG;
+  const int bid = xcd_order(blockIdx.x, gridDim.x);
+  const int strip = bid / segs, seg = bid % segs;
+  const int j = strip * TR + threadIdx.x / TZ;
+  float f[NPOP], a[7], fn[NPOP], an[7];
+  auto load = [&](int tile, float* ff, float* aa) {
+    const int i = tile * TZ + threadIdx.x % TZ;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const long long off = (long long)clampi(j - cr(q), g.nr) * g.nz + clampi(i - cz(q), g.nz);
+#pragma unroll
+      for (int l = 0; l < 3; ++l) ff[9 * l + q] = pin[(9 * l + q) * g.plane + off];
+    }
+    const long long o = (long long)j * g.nz + i;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) aa[c] = ain[c * g.plane + o];
+  };
+  const int t0 = seg * SEG;
+  load(t0, f, a);
+  for (int t = 0; t < SEG; ++t) {
+    if (t + 1 < SEG) load(t0 + t + 1, fn, an);
+    const int i = (t0 + t) * TZ + threadIdx.x % TZ;
+    const long long o = (long long)j * g.nz + i;
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < NPOP; ++c) s += f[c];
+#pragma unroll
+    for (int c = 0; c < NPOP; ++c) pout[c * g.plane + o] = f[c] + 1e-7f * s;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) aout[c * g.plane + o] = a[c] + 1e-7f * s;
+#pragma unroll
+    for (int c = 0; c < NPOP; ++c) f[c] = fn[c];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) a[c] = an[c];
+  }
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
@@ -165,8 +212,55 @@ void measure(const char* name, int nz, int nr, int iters, bool variants) {
   CK(hipFree(aout));
 }
 
+template <int SEG>
+void measure_z(const char* name, int nz, int nr, int iters) {
+  Grid g;
+  g.nz = nz;
+  g.nr = nr;
+  g.plane = (long long)nz * nr + 64;
+  const double bytes = 272.0 * (double)nz * nr;
+  float *pin, *pout, *ain, *aout;
+  CK(hipMalloc(&pin, NPOP * g.plane * 4));
+  CK(hipMalloc(&pout, NPOP * g.plane * 4));
+  CK(hipMalloc(&ain, 7 * g.plane * 4));
+  CK(hipMalloc(&aout, 7 * g.plane * 4));
+  CK(hipMemset(pin, 0, NPOP * g.plane * 4));
+  CK(hipMemset(ain, 0, 7 * g.plane * 4));
+  const int blocks = (nr / TR) * (nz / TZ / SEG);
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  for (int it = 0; it < 20; ++it) zmarch_kernel<SEG><<<blocks, TZ * TR>>>(g, pin, pout, ain, aout);
+  CK(hipDeviceSynchronize());
+  CK(hipEventRecord(e0));
+  for (int it = 0; it < iters; ++it) zmarch_kernel<SEG><<<blocks, TZ * TR>>>(g, pin, pout, ain, aout);
+  CK(hipEventRecord(e1));
+  CK(hipEventSynchronize(e1));
+  CK(hipGetLastError());
+  float ms;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  const double us = ms * 1e3 / iters;
+  printf("{\"workload\": \"%s %dx%d\", \"kernel\": \"z-march, %d tiles per block\", \"us\": %.2f, \"frac_of_8TBps\": %.4f}\n",
+         name, nz, nr, SEG, us, bytes / us / 1e3 / 8000.0);
+  fflush(stdout);
+  CK(hipFree(pin));
+  CK(hipFree(pout));
+  CK(hipFree(ain));
+  CK(hipFree(aout));
+}
+
 int main(int argc, char** argv) {
   CK(hipSetDevice(0));
+  if (argc > 1 && std::strcmp(argv[1], "--zmarch") == 0) {
+    measure_z<2>("C2 FP32", 2048, 512, 400);
+    measure_z<4>("C2 FP32", 2048, 512, 400);
+    measure_z<8>("C2 FP32", 2048, 512, 400);
+    measure_z<2>("C3 FP32", 4096, 1024, 100);
+    measure_z<4>("C3 FP32", 4096, 1024, 100);
+    measure_z<8>("C3 FP32", 4096, 1024, 100);
+    measure_z<16>("C3 FP32", 4096, 1024, 100);
+    return 0;
+  }
   if (argc > 1 && std::strcmp(argv[1], "--arith") == 0) {
     measure<float, float, 7, 0>("C2 FP32", 2048, 512, 400, false);
     measure<float, float, 7, 0>("C3 FP32", 4096, 1024, 100, false);
