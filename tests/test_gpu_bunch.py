@@ -152,21 +152,21 @@ def test_bunch_replaced_mid_run():
     lat.close()
 
 
-@pytest.mark.parametrize("resort", [0, 3])
-def test_fp32_particle_run(resort):
+@pytest.mark.parametrize("resort,m64", [(0, 0), (3, 0), (3, 1)])
+def test_fp32_particle_run(resort, m64):
     """FP32 storage with the particle driver over 60 steps of the deflected slow bunch (losses
-    included), with the default re-sort interval and with a re-sort every 3 steps: the FP32 tile
-    deposit (shares summed within runs of lanes in FP32) and the J_b bound against the FP64
-    oracle.  Moments and fields within 1e-5 of their group's scale, particle coordinates within
-    1e-6 of theirs, and the same particles lost."""
+    included), with the default re-sort interval and with a re-sort every 3 steps, in FP32 and in
+    FP64 arithmetic (fp64_math): the FP32 tile deposit (shares summed within runs of lanes in
+    FP32) and the J_b bound against the FP64 oracle.  Moments and fields within 1e-5 of their
+    group's scale, particle coordinates within 1e-6 of theirs, and the same particles lost."""
     c = CASES["slow_deflected"]
     cfg = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=4.0,
                     driver=wl.PARTICLES, max_particles=6000, storage=wl.F32, noise_amp=1e-3, seed=4,
-                    tau=0.7, resort_every=resort, **c["cfg"])
+                    tau=0.7, resort_every=resort, fp64_math=m64, **c["cfg"])
     b = wl.bunch(cfg, 5000, gamma=c["gamma"], emittance=c["emittance"], energy_spread=c["spread"], seed=8)
     pert = wl.density_perturbation(cfg)
-    S, P = O.run(dict(cfg, storage=wl.F64), 60, pert, bunch=b)
-    print(f"[bunch fp32] resort_every={resort}", flush=True)
+    S, P = O.run(dict(cfg, storage=wl.F64, fp64_math=0), 60, pert, bunch=b)
+    print(f"[bunch fp32] resort_every={resort} fp64_math={m64}", flush=True)
     lat = lattice(cfg, b, pert)
     lat.step(60)
     st, k, s = lat.state()
