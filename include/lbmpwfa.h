@@ -218,14 +218,19 @@ int lbm_get_state(lbm_ctx* ctx, double* dst, int64_t* step, int64_t* shifts);
  * and shift counters.  Values are rounded to the storage precision.  Synchronising. */
 int lbm_set_state(lbm_ctx* ctx, const double* src, int64_t step, int64_t shifts);
 
-/* Checkpoint in the native storage format, for bit-exact resume:
- * a 64-byte header (magic, storage, nz, nr, row pitch, step, shift count, plane stride) followed by the active
- * population, moment and field buffers as stored (with LBM_F32 the field buffer includes the
- * plane of residuals).  lbm_checkpoint_bytes gives its size.
+/* Checkpoint in the native storage format, for exact resume:
+ * a 64-byte header (magic, storage, nz, nr, row pitch, step, shift count, plane stride, driver,
+ * particle count) followed by the active population, moment and field buffers as stored (with
+ * LBM_F32 the field buffer includes the plane of residuals).  With LBM_DRIVER_PARTICLES a bunch
+ * section follows: the extent that bounds the J_b region and its age in steps (24 bytes), the 7
+ * coordinate arrays of the bunch in its stored order (FP64) and each particle's index in the
+ * caller's order (int32).  lbm_checkpoint_bytes gives the size of the context's checkpoint, which
+ * depends on the number of particles (it changes only with lbm_set_bunch and lbm_load).
  * dst/src may be host or device memory (flag); both calls synchronise the stream.  lbm_load
- * returns LBM_EINVAL if the checkpoint was written for another grid or storage precision.  The
- * bunch of LBM_DRIVER_PARTICLES is not part of it: keep it with lbm_get_bunch and restore it with
- * lbm_set_bunch(init_fields = 0). */
+ * returns LBM_EINVAL, and leaves the context as it was, if the checkpoint was written for another
+ * grid, storage precision or driver, holds more than max_particles particles or an index array
+ * that is not a permutation.  It replaces the bunch and clears the J_b buffers.  A rigid-driver run
+ * resumes bit for bit; a particle-driven one to round-off (the deposit adds in no fixed order). */
 int lbm_checkpoint_bytes(lbm_ctx* ctx, size_t* bytes);
 int lbm_save(lbm_ctx* ctx, void* dst, int32_t dst_on_device);
 int lbm_load(lbm_ctx* ctx, const void* src, int32_t src_on_device);

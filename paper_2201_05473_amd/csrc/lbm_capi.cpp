@@ -518,26 +518,72 @@ struct CkptHeader {
   char magic[8];
   int32_t storage, nz, nr, pitch;
   int64_t step, shifts, plane;
-  char pad[16];
+  int32_t driver, reserved;
+  int64_t nbunch;   // particles in the bunch section (LBM_DRIVER_PARTICLES), else 0
 };
 static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
-const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '2'};
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'W', 'F', 'A', '3'};
+
+// Head of the bunch section: the extent the J_b bound starts from and its age in steps.
+struct CkptBunch {
+  int32_t ext[3], reserved;
+  int64_t ext_age;
+};
+static_assert(sizeof(CkptBunch) == 24, "bunch section head is 24 bytes");
 
 size_t region_bytes(const lbm_ctx* c, int which) {
   const size_t plane = (size_t)c->p.plane;
   return which == 0 ? 27 * plane * pop_bytes(c->storage)
                     : (which == 1 ? 3 * plane * aux_bytes(c->storage) : field_bytes(plane, c->storage));
 }
+
+// The bunch section of a checkpoint of n particles: head, 7 coordinates per particle (FP64,
+// component-major, in stored order) and each particle's index in the caller's order (int32).
+size_t bunch_section_bytes(const lbm_ctx* c, long long n) {
+  return c->p.driver == LBM_DRIVER_PARTICLES ? sizeof(CkptBunch) + (size_t)n * (7 * sizeof(double) + sizeof(int32_t))
+                                             : 0;
+}
+
+// One piece of a checkpoint: `bytes` at `ckpt_off` in the checkpoint and at `ctx_mem` in the
+// context (device memory, or host memory when `host` is set: the headers).
+struct Piece {
+  size_t ckpt_off;
+  void* ctx_mem;
+  size_t bytes;
+  bool host;
+};
+
+// The pieces of the context's checkpoint after the header, in order.
+void pieces(lbm_ctx* c, CkptBunch* bh, std::vector<Piece>& out) {
+  size_t off = sizeof(CkptHeader);
+  void* reg[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
+  for (int r = 0; r < 3; ++r) {
+    out.push_back({off, reg[r], region_bytes(c, r), false});
+    off += region_bytes(c, r);
+  }
+  if (c->p.driver == LBM_DRIVER_PARTICLES) {
+    const size_t n = (size_t)c->nbunch;
+    out.push_back({off, bh, sizeof(CkptBunch), true});
+    off += sizeof(CkptBunch);
+    for (int comp = 0; comp < 7; ++comp) {
+      out.push_back({off, c->bunch() + comp * c->p.cap, n * sizeof(double), false});
+      off += n * sizeof(double);
+    }
+    out.push_back({off, c->pid(c->bcur), n * sizeof(int32_t), false});
+  }
+}
 }  // namespace
 
 int lbm_checkpoint_bytes(lbm_ctx* c, size_t* bytes) {
   if (int rc_ = live(c)) return rc_;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + region_bytes(c, 1) + region_bytes(c, 2);
+  *bytes = sizeof(CkptHeader) + region_bytes(c, 0) + region_bytes(c, 1) + region_bytes(c, 2) +
+           bunch_section_bytes(c, c->nbunch);
   return LBM_OK;
 }
 
-int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
+namespace {
+int ckpt_save(lbm_ctx* c, void* dst, int32_t on_device) {
   if (int rc_ = live(c)) return rc_;
   if (!dst) return fail(LBM_EINVAL, "dst is NULL");
   CkptHeader h;
@@ -550,57 +596,122 @@ int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
   h.plane = c->p.plane;
   h.step = c->k;
   h.shifts = c->s;
+  h.driver = c->p.driver;
+  h.nbunch = c->p.driver == LBM_DRIVER_PARTICLES ? c->nbunch : 0;
+  CkptBunch bh;
+  std::memset(&bh, 0, sizeof bh);
+  std::memcpy(bh.ext, c->ext, sizeof bh.ext);
+  bh.ext_age = c->ext_age;
+  std::vector<Piece> ps{{0, &h, sizeof h, true}};
+  pieces(c, &bh, ps);
   char* d = (char*)dst;
-  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  if (on_device) {
-    HIP_CHECK(hipMemcpyAsync(d, &h, sizeof h, hipMemcpyHostToDevice, c->stream), "save header");
-  } else {
-    std::memcpy(d, &h, sizeof h);
-  }
-  size_t off = sizeof h;
-  const void* src[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
-  for (int r = 0; r < 3; ++r) {
-    const size_t nb = region_bytes(c, r);
-    const hipError_t e = hipMemcpyAsync(d + off, src[r], nb, kind, c->stream);
+  for (const Piece& q : ps) {
+    hipError_t e = hipSuccess;
+    if (!on_device && q.host)
+      std::memcpy(d + q.ckpt_off, q.ctx_mem, q.bytes);
+    else if (q.bytes > 0)
+      e = hipMemcpyAsync(d + q.ckpt_off, q.ctx_mem, q.bytes,
+                         q.host ? hipMemcpyHostToDevice : (on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost),
+                         c->stream);
     if (e != hipSuccess) {
-      (void)hipStreamSynchronize(c->stream);   // the queued header copy reads h
+      (void)hipStreamSynchronize(c->stream);   // queued copies read h and bh
       return hip_fail(e, "save copy");
     }
-    off += nb;
   }
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   return LBM_OK;
 }
 
-int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
+int ckpt_load(lbm_ctx* c, const void* src, int32_t on_device) {
   if (!c) return fail(LBM_ESTATE, "context is NULL");
   if (!src) return fail(LBM_EINVAL, "src is NULL");
-  CkptHeader h;
   const char* s = (const char*)src;
-  if (on_device) {
-    HIP_CHECK(hipMemcpyAsync(&h, s, sizeof h, hipMemcpyDeviceToHost, c->stream), "load header");
-    HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
-  } else {
-    std::memcpy(&h, s, sizeof h);
-  }
+  // reads `bytes` at `off` of the checkpoint into host memory
+  const auto read = [&](void* to, size_t off, size_t bytes) -> hipError_t {
+    if (!on_device) {
+      std::memcpy(to, s + off, bytes);
+      return hipSuccess;
+    }
+    hipError_t e = bytes > 0 ? hipMemcpyAsync(to, s + off, bytes, hipMemcpyDeviceToHost, c->stream) : hipSuccess;
+    const hipError_t e2 = hipStreamSynchronize(c->stream);
+    return e != hipSuccess ? e : e2;
+  };
+  CkptHeader h;
+  HIP_CHECK(read(&h, 0, sizeof h), "load header");
   if (std::memcmp(h.magic, kMagic, 8) != 0) return fail(LBM_EINVAL, "not an lbmpwfa checkpoint");
   if (h.storage != c->storage || h.nz != c->p.nz || h.nr != c->p.nr || h.pitch != c->p.pitch ||
       h.plane != c->p.plane)
     return fail(LBM_EINVAL, "checkpoint is for another grid or storage precision");
+  if (h.driver != c->p.driver) return fail(LBM_EINVAL, "checkpoint is for another driver");
   if (h.step < 0 || h.shifts < 0) return fail(LBM_EINVAL, "corrupt checkpoint counters");
-  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  size_t off = sizeof h;
-  void* dstp[3] = {c->g(c->cur), c->M(c->cur), c->E(c->cur)};
-  for (int r = 0; r < 3; ++r) {
-    const size_t nb = region_bytes(c, r);
-    HIP_CHECK(hipMemcpyAsync(dstp[r], s + off, nb, kind, c->stream), "load copy");
-    off += nb;
+  const bool particles = c->p.driver == LBM_DRIVER_PARTICLES;
+  if (particles ? (h.nbunch < 0 || h.nbunch > c->p.cap) : h.nbunch != 0)
+    return fail(LBM_EINVAL, "checkpoint holds %lld particles (max_particles %lld)", (long long)h.nbunch,
+                (long long)c->p.cap);
+  // the context's pieces with the checkpoint's particle count, into bunch buffer 0
+  const long long n = h.nbunch;
+  const int bcur_was = c->bcur;
+  const long long nbunch_was = c->nbunch;
+  c->bcur = 0;
+  c->nbunch = particles ? n : 0;
+  CkptBunch bh;
+  std::vector<Piece> ps;
+  pieces(c, &bh, ps);
+  c->bcur = bcur_was;
+  c->nbunch = nbunch_was;
+  if (particles) {
+    // the bunch head and the index array are checked before anything of the context changes
+    HIP_CHECK(read(&bh, ps[3].ckpt_off, sizeof bh), "load bunch head");
+    if (bh.ext_age < 0) return fail(LBM_EINVAL, "corrupt checkpoint bunch extent");
+    std::vector<int32_t> pid((size_t)n);
+    HIP_CHECK(read(pid.data(), ps.back().ckpt_off, (size_t)n * sizeof(int32_t)), "load bunch indices");
+    std::vector<char> seen((size_t)n, 0);
+    for (long long i = 0; i < n; ++i) {
+      const int32_t o = pid[(size_t)i];
+      if (o < 0 || o >= n || seen[(size_t)o]) return fail(LBM_EINVAL, "checkpoint bunch index %lld is not a permutation", i);
+      seen[(size_t)o] = 1;
+    }
+  }
+  for (const Piece& q : ps) {
+    if (q.host || q.bytes == 0) continue;
+    HIP_CHECK(hipMemcpyAsync(q.ctx_mem, s + q.ckpt_off, q.bytes,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
+              "load copy");
+  }
+  if (particles) {
+    // the next step deposits into a cleared buffer and clears the other only near the bunch
+    for (int b = 0; b < 2; ++b)
+      HIP_CHECK(hipMemsetAsync(c->jb(b), 0, 2 * (size_t)c->p.plane * aux_bytes(c->storage), c->stream), "clear");
   }
   HIP_CHECK(hipStreamSynchronize(c->stream), "synchronise");
   c->k = h.step;
   c->s = h.shifts;
+  if (particles) {
+    c->nbunch = n;
+    c->bcur = 0;
+    c->jcur = 0;
+    std::memcpy(c->ext, bh.ext, sizeof c->ext);
+    c->ext_age = bh.ext_age;
+  }
   c->broken = false;
   return LBM_OK;
+}
+}  // namespace
+
+int lbm_save(lbm_ctx* c, void* dst, int32_t on_device) {
+  try {
+    return ckpt_save(c, dst, on_device);
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_ENOMEM, "host allocation failed");
+  }
+}
+
+int lbm_load(lbm_ctx* c, const void* src, int32_t on_device) {
+  try {
+    return ckpt_load(c, src, on_device);
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_ENOMEM, "host allocation failed");
+  }
 }
 
 // The diagnostics with their partial sums in `partials` and the result in `res` (device).
