@@ -628,11 +628,12 @@ int ckpt_load(lbm_ctx* c, const void* src, int32_t on_device) {
   const char* s = (const char*)src;
   // reads `bytes` at `off` of the checkpoint into host memory
   const auto read = [&](void* to, size_t off, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;   // `to` may be NULL (an empty bunch)
     if (!on_device) {
       std::memcpy(to, s + off, bytes);
       return hipSuccess;
     }
-    hipError_t e = bytes > 0 ? hipMemcpyAsync(to, s + off, bytes, hipMemcpyDeviceToHost, c->stream) : hipSuccess;
+    const hipError_t e = hipMemcpyAsync(to, s + off, bytes, hipMemcpyDeviceToHost, c->stream);
     const hipError_t e2 = hipStreamSynchronize(c->stream);
     return e != hipSuccess ? e : e2;
   };

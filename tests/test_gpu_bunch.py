@@ -243,7 +243,8 @@ def test_fp32_particle_run(resort, m64):
 def test_empty_bunch():
     """A particle-driven context with no particles (and one whose bunch was never set) evolves as
     the plasma with no driver: the oracle's state for an empty bunch, FP64 to 1e-10, over 12
-    steps with two window shifts."""
+    steps with two window shifts, also when resumed from a checkpoint (host and device memory)
+    taken after 5 steps."""
     cfg = wl.config(None, nz=70, nr=9, dz=0.05, dr=0.05, driver=wl.PARTICLES, max_particles=10,
                     storage=wl.F64, noise_amp=1e-3, seed=3, moving_window=1, tau=0.7)
     pert = wl.density_perturbation(cfg)
@@ -255,12 +256,21 @@ def test_empty_bunch():
         lat = Lattice(cfg, pert)
         if set_empty:
             lat.set_bunch(np.zeros((7, 0)), True)
-        lat.step(12)
-        st, k, s = lat.state()
-        assert (k, s) == (S.k, S.s)
-        assert comp_errors(st, ref).max() < TOL64
-        assert lat.bunch().shape == (7, 0)
-        lat.close()
+        lat.step(5)
+        cks = [lat.save(False), lat.save(True)]
+        lat.step(7)
+        for x in [lat] + cks:
+            if x is not lat:
+                res = Lattice(cfg)
+                res.load(x)
+                res.step(7)
+            else:
+                res = lat
+            st, k, s = res.state()
+            assert (k, s) == (S.k, S.s)
+            assert comp_errors(st, ref).max() < TOL64
+            assert res.bunch().shape == (7, 0)
+            res.close()
 
 
 def test_initial_gauss_law_from_the_bunch():
