@@ -376,7 +376,8 @@ class Lattice:
         lbm_set_state(self.ctx, state, step, shifts)
 
     def save(self, on_device: bool = False):
-        """Native-format checkpoint: a uint8 numpy array (host) or torch tensor (device)."""
+        """Native-format checkpoint: a uint8 numpy array (host) or torch tensor (device); with the
+        particle driver it holds the bunch as well."""
         import torch
         n = lbm_checkpoint_bytes(self.ctx)
         if on_device:
