@@ -21,6 +21,13 @@
 // consecutive tiles of one row strip along z (blocks in the XCD-aware order), issuing the next
 // tile's loads before the current tile's stores.
 //
+// With --shift the FP32 pattern is measured with its pull offsets switched off (every load at the
+// site: rows start 256-byte aligned), with the row offsets only (still aligned), with the full pull
+// (the z offsets make 18 of the 27 loads start 4 bytes off a cache line), and with the z offsets
+// taken by aligned row loads realigned across lanes (a wavefront DPP shift by one lane, the column
+// past the wavefront's end from a single-lane load).  The realigned outputs are first checked
+// against the full pull's bit for bit.
+//
 // Standalone program (not part of the library): prints one JSON line per measurement.  Every index
 // is clamped into the arrays, and the grids are whole multiples of the tile.
 #include <hip/hip_runtime.h>
@@ -60,8 +67,10 @@ __device__ __forceinline__ int cz(int q) { return (q == 1 || q == 5 || q == 8) ?
 __device__ __forceinline__ int cr(int q) { return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0); }
 __device__ __forceinline__ int clampi(int x, int n) { return x < 0 ? 0 : (x >= n ? n - 1 : x); }
 
-// WORK: rounds of 27 multiply-adds per site between the loads and the stores (0: the pure pattern)
-template <typename P, typename X, int NAUX, bool XCD, int WORK>
+// WORK: rounds of 27 multiply-adds per site between the loads and the stores (0: the pure pattern).
+// SHIFT: 0 no pull offsets, 1 row offsets only, 2 the full pull, 3 the full pull with the z offsets
+// realigned across lanes (FP32; every lane active, as the DPP shift needs)
+template <typename P, typename X, int NAUX, bool XCD, int WORK, int SHIFT = 2>
 __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __restrict__ pin, P* __restrict__ pout,
                                                           const X* __restrict__ ain, X* __restrict__ aout) {
   const int gx = g.nz / TZ;
@@ -71,9 +80,33 @@ __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __res
   X f[NPOP], a[NAUX];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const long long off = (long long)clampi(j - cr(q), g.nr) * g.nz + clampi(i - cz(q), g.nz);
+    if constexpr (SHIFT == 3 && sizeof(P) == 4) {
+      // aligned row load, realigned across lanes with a wavefront DPP shift; the one column past the
+      // row's end comes from a single-lane load
+      const int lane = threadIdx.x % 64;
+      const int i0 = i - lane;
+      const long long rowb = (long long)clampi(j - cr(q), g.nr) * g.nz;
 #pragma unroll
-    for (int l = 0; l < 3; ++l) f[9 * l + q] = (X)pin[(9 * l + q) * g.plane + off];
+      for (int l = 0; l < 3; ++l) {
+        const P* src = pin + (9 * l + q) * g.plane + rowb;
+        const int v = __builtin_bit_cast(int, (float)src[i]);
+        if (cz(q) == 0) {
+          f[9 * l + q] = (X)__builtin_bit_cast(float, v);
+        } else {
+          int e = 0;
+          const int edge = cz(q) > 0 ? 0 : 63;
+          if (lane == edge) e = __builtin_bit_cast(int, (float)src[clampi(cz(q) > 0 ? i0 - 1 : i0 + 64, g.nz)]);
+          const int sh = cz(q) > 0 ? __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true)
+                                   : __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
+          f[9 * l + q] = (X)__builtin_bit_cast(float, sh | e);
+        }
+      }
+    } else {
+      const int dz = SHIFT == 2 ? cz(q) : 0, dr = SHIFT >= 1 ? cr(q) : 0;
+      const long long off = (long long)clampi(j - dr, g.nr) * g.nz + clampi(i - dz, g.nz);
+#pragma unroll
+      for (int l = 0; l < 3; ++l) f[9 * l + q] = (X)pin[(9 * l + q) * g.plane + off];
+    }
   }
   const long long o = (long long)j * g.nz + i;
 #pragma unroll
@@ -249,8 +282,103 @@ void measure_z(const char* name, int nz, int nr, int iters) {
   CK(hipFree(aout));
 }
 
+template <int SHIFT>
+void measure_s(const char* name, int nz, int nr, int iters) {
+  Grid g;
+  g.nz = nz;
+  g.nr = nr;
+  g.plane = (long long)nz * nr + 64;
+  const double bytes = 272.0 * (double)nz * nr;
+  float *pin, *pout, *ain, *aout;
+  CK(hipMalloc(&pin, NPOP * g.plane * 4));
+  CK(hipMalloc(&pout, NPOP * g.plane * 4));
+  CK(hipMalloc(&ain, 7 * g.plane * 4));
+  CK(hipMalloc(&aout, 7 * g.plane * 4));
+  CK(hipMemset(pin, 0, NPOP * g.plane * 4));
+  CK(hipMemset(ain, 0, 7 * g.plane * 4));
+  const int tiles = (nz / TZ) * (nr / TR);
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  for (int it = 0; it < 20; ++it) pattern_kernel<float, float, 7, true, 0, SHIFT><<<tiles, TZ * TR>>>(g, pin, pout, ain, aout);
+  CK(hipDeviceSynchronize());
+  CK(hipEventRecord(e0));
+  for (int it = 0; it < iters; ++it) pattern_kernel<float, float, 7, true, 0, SHIFT><<<tiles, TZ * TR>>>(g, pin, pout, ain, aout);
+  CK(hipEventRecord(e1));
+  CK(hipEventSynchronize(e1));
+  CK(hipGetLastError());
+  float ms;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  const double us = ms * 1e3 / iters;
+  printf("{\"workload\": \"%s %dx%d\", \"shift_mode\": %d, \"us\": %.2f, \"frac_of_8TBps\": %.4f}\n",
+         name, nz, nr, SHIFT, us, bytes / us / 1e3 / 8000.0);
+  fflush(stdout);
+  CK(hipFree(pin));
+  CK(hipFree(pout));
+  CK(hipFree(ain));
+  CK(hipFree(aout));
+}
+
+// The realigned pull (SHIFT 3) against the full pull (SHIFT 2) on the same input, C2's grid: the
+// outputs must agree bit for bit.
+bool realigned_pull_matches() {
+  Grid g;
+  g.nz = 2048;
+  g.nr = 512;
+  g.plane = (long long)g.nz * g.nr + 64;
+  const size_t np = NPOP * g.plane, na = 7 * g.plane;
+  float *pin, *o2, *o3, *ain, *aout;
+  CK(hipMalloc(&pin, np * 4));
+  CK(hipMalloc(&o2, np * 4));
+  CK(hipMalloc(&o3, np * 4));
+  CK(hipMalloc(&ain, na * 4));
+  CK(hipMalloc(&aout, na * 4));
+  float* h = (float*)malloc(np * 4);
+  float* h2 = (float*)malloc(np * 4);
+  if (!h || !h2) {
+    fprintf(stderr, "host allocation failed\n");
+    exit(1);
+  }
+  for (size_t t = 0; t < np; ++t) h[t] = (float)((t * 2654435761u) % 1000003u) * 1e-6f;
+  CK(hipMemcpy(pin, h, np * 4, hipMemcpyHostToDevice));
+  CK(hipMemset(ain, 0, na * 4));
+  const int tiles = (g.nz / TZ) * (g.nr / TR);
+  pattern_kernel<float, float, 7, true, 0, 2><<<tiles, TZ * TR>>>(g, pin, o2, ain, aout);
+  pattern_kernel<float, float, 7, true, 0, 3><<<tiles, TZ * TR>>>(g, pin, o3, ain, aout);
+  CK(hipDeviceSynchronize());
+  CK(hipGetLastError());
+  CK(hipMemcpy(h, o2, np * 4, hipMemcpyDeviceToHost));
+  CK(hipMemcpy(h2, o3, np * 4, hipMemcpyDeviceToHost));
+  long long bad = 0;
+  for (size_t t = 0; t < np; ++t) bad += std::memcmp(&h[t], &h2[t], 4) != 0;
+  printf("{\"check\": \"realigned pull against the full pull, C2 FP32\", \"mismatches\": %lld}\n", bad);
+  fflush(stdout);
+  free(h);
+  free(h2);
+  CK(hipFree(pin));
+  CK(hipFree(o2));
+  CK(hipFree(o3));
+  CK(hipFree(ain));
+  CK(hipFree(aout));
+  return bad == 0;
+}
+
 int main(int argc, char** argv) {
   CK(hipSetDevice(0));
+  if (argc > 1 && std::strcmp(argv[1], "--shift") == 0) {
+    if (!realigned_pull_matches()) return 1;
+    for (int rep = 0; rep < 2; ++rep) {
+      measure_s<0>("C2 FP32", 2048, 512, 400);
+      measure_s<1>("C2 FP32", 2048, 512, 400);
+      measure_s<2>("C2 FP32", 2048, 512, 400);
+      measure_s<3>("C2 FP32", 2048, 512, 400);
+      measure_s<0>("C3 FP32", 4096, 1024, 100);
+      measure_s<1>("C3 FP32", 4096, 1024, 100);
+      measure_s<2>("C3 FP32", 4096, 1024, 100);
+      measure_s<3>("C3 FP32", 4096, 1024, 100);
+    }
+    return 0;
+  }
   if (argc > 1 && std::strcmp(argv[1], "--zmarch") == 0) {
     measure_z<2>("C2 FP32", 2048, 512, 400);
     measure_z<4>("C2 FP32", 2048, 512, 400);
