@@ -25,7 +25,8 @@
 // site: rows start 256-byte aligned), with the row offsets only (still aligned), with the full pull
 // (the z offsets make 18 of the 27 loads start 4 bytes off a cache line), and with the z offsets
 // taken by aligned row loads realigned across lanes (a wavefront DPP shift by one lane, the column
-// past the wavefront's end from a single-lane load).  The realigned outputs are first checked
+// past the wavefront's end from a single-lane load), and with the z offsets moved to the stores (each
+// population plane stored shifted by its z velocity).  The realigned outputs are first checked
 // against the full pull's bit for bit.
 //
 // Standalone program (not part of the library): prints one JSON line per measurement.  Every index
@@ -69,7 +70,8 @@ __device__ __forceinline__ int clampi(int x, int n) { return x < 0 ? 0 : (x >= n
 
 // WORK: rounds of 27 multiply-adds per site between the loads and the stores (0: the pure pattern).
 // SHIFT: 0 no pull offsets, 1 row offsets only, 2 the full pull, 3 the full pull with the z offsets
-// realigned across lanes (FP32; every lane active, as the DPP shift needs)
+// realigned across lanes (FP32; every lane active, as the DPP shift needs), 4 the z offsets on the
+// stores instead
 template <typename P, typename X, int NAUX, bool XCD, int WORK, int SHIFT = 2>
 __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __restrict__ pin, P* __restrict__ pout,
                                                           const X* __restrict__ ain, X* __restrict__ aout) {
@@ -121,7 +123,12 @@ __global__ __launch_bounds__(TZ * TR) void pattern_kernel(Grid g, const P* __res
     for (int c = 0; c < NPOP; ++c) f[c] = f[c] * X(0.999999) + X(1e-9) * s;
   }
 #pragma unroll
-  for (int c = 0; c < NPOP; ++c) pout[c * g.plane + o] = (P)(f[c] + X(1e-7) * s);
+  for (int c = 0; c < NPOP; ++c) {
+    // SHIFT 4: each population plane stored shifted by its own z velocity, so that the pull's z
+    // offsets move from the loads to the stores (rows still pulled)
+    const long long oc = SHIFT == 4 ? (long long)j * g.nz + clampi(i + cz(c % 9), g.nz) : o;
+    pout[c * g.plane + oc] = (P)(f[c] + X(1e-7) * s);
+  }
 #pragma unroll
   for (int c = 0; c < NAUX; ++c) aout[c * g.plane + o] = a[c] + X(1e-7) * s;
 }
@@ -372,10 +379,12 @@ int main(int argc, char** argv) {
       measure_s<1>("C2 FP32", 2048, 512, 400);
       measure_s<2>("C2 FP32", 2048, 512, 400);
       measure_s<3>("C2 FP32", 2048, 512, 400);
+      measure_s<4>("C2 FP32", 2048, 512, 400);
       measure_s<0>("C3 FP32", 4096, 1024, 100);
       measure_s<1>("C3 FP32", 4096, 1024, 100);
       measure_s<2>("C3 FP32", 4096, 1024, 100);
       measure_s<3>("C3 FP32", 4096, 1024, 100);
+      measure_s<4>("C3 FP32", 4096, 1024, 100);
     }
     return 0;
   }
