@@ -29,6 +29,11 @@
 // population plane stored shifted by its z velocity).  The realigned outputs are first checked
 // against the full pull's bit for bit.
 //
+// With --layout the FP32 pattern (full pull) is measured beside two other arrangements of the same
+// 272 B per site, each with and without the pull's offsets: a chunked layout (the 3 lattices of a
+// direction in one plane as [row][64-column chunk][lattice][64], the 7 auxiliary words in one plane
+// likewise: 10 streams each way instead of 34) and four sites per lane with 16-byte accesses.
+//
 // Standalone program (not part of the library): prints one JSON line per measurement.  Every index
 // is clamped into the arrays, and the grids are whole multiples of the tile.
 #include <hip/hip_runtime.h>
@@ -326,6 +331,155 @@ void measure_s(const char* name, int nz, int nr, int iters) {
   CK(hipFree(aout));
 }
 
+// Chunked layout: the 3 lattices of one direction share a plane, [row][64-column chunk][lattice][64],
+// and the 7 auxiliary words of a site share one plane, [row][chunk][word][64]: 10 streams each way.
+template <int PULL>
+__global__ __launch_bounds__(TZ * TR) void chunk_kernel(Grid g, const float* __restrict__ pin, float* __restrict__ pout,
+                                                        const float* __restrict__ ain, float* __restrict__ aout) {
+  const int gx = g.nz / TZ;
+  const int tile = xcd_order(blockIdx.x, gridDim.x);
+  const int i = (tile % gx) * TZ + threadIdx.x % TZ;
+  const int j = (tile / gx) * TR + threadIdx.x / TZ;
+  const long long qplane = 3LL * g.nz * g.nr + 64;
+  float f[NPOP], a[7];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int jj = PULL ? clampi(j - cr(q), g.nr) : j, ii = PULL ? clampi(i - cz(q), g.nz) : i;
+    const long long base = q * qplane + (long long)jj * 3 * g.nz + (ii / 64) * 192 + ii % 64;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) f[9 * l + q] = pin[base + 64 * l];
+  }
+  const long long ob = (long long)j * 7 * g.nz + (i / 64) * 448 + i % 64;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) a[c] = ain[ob + 64 * c];
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < NPOP; ++c) s += f[c];
+  const long long pb = (long long)j * 3 * g.nz + (i / 64) * 192 + i % 64;
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) pout[q * qplane + pb + 64 * l] = f[9 * l + q] + 1e-7f * s;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) aout[ob + 64 * c] = a[c] + 1e-7f * s;
+}
+
+template <int PULL>
+void measure_c(const char* name, int nz, int nr, int iters) {
+  Grid g;
+  g.nz = nz;
+  g.nr = nr;
+  g.plane = 0;   // unused: the chunked planes have their own strides
+  const long long qplane = 3LL * nz * nr + 64;
+  const double bytes = 272.0 * (double)nz * nr;
+  float *pin, *pout, *ain, *aout;
+  CK(hipMalloc(&pin, 9 * qplane * 4));
+  CK(hipMalloc(&pout, 9 * qplane * 4));
+  CK(hipMalloc(&ain, 7LL * nz * nr * 4));
+  CK(hipMalloc(&aout, 7LL * nz * nr * 4));
+  CK(hipMemset(pin, 0, 9 * qplane * 4));
+  CK(hipMemset(ain, 0, 7LL * nz * nr * 4));
+  const int tiles = (nz / TZ) * (nr / TR);
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  for (int it = 0; it < 20; ++it) chunk_kernel<PULL><<<tiles, TZ * TR>>>(g, pin, pout, ain, aout);
+  CK(hipDeviceSynchronize());
+  CK(hipEventRecord(e0));
+  for (int it = 0; it < iters; ++it) chunk_kernel<PULL><<<tiles, TZ * TR>>>(g, pin, pout, ain, aout);
+  CK(hipEventRecord(e1));
+  CK(hipEventSynchronize(e1));
+  CK(hipGetLastError());
+  float ms;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  const double us = ms * 1e3 / iters;
+  printf("{\"workload\": \"%s %dx%d\", \"kernel\": \"chunked layout, pull %d\", \"us\": %.2f, \"frac_of_8TBps\": %.4f}\n",
+         name, nz, nr, PULL, us, bytes / us / 1e3 / 8000.0);
+  fflush(stdout);
+  CK(hipFree(pin));
+  CK(hipFree(pout));
+  CK(hipFree(ain));
+  CK(hipFree(aout));
+}
+
+// Four sites per lane: 16-byte loads and stores (a block: 256 columns x 4 rows), the planar layout
+// of the step; the pulled loads start 4 bytes off 16 (the hardware takes dword-aligned 16-byte
+// accesses), clamped so that all four columns lie in the row.
+struct __attribute__((aligned(4))) F4 { float x, y, z, w; };
+template <int PULL>
+__global__ __launch_bounds__(256) void vec4_kernel(Grid g, const float* __restrict__ pin, float* __restrict__ pout,
+                                                   const float* __restrict__ ain, float* __restrict__ aout) {
+  const int gx = g.nz / 256;
+  const int tile = xcd_order(blockIdx.x, gridDim.x);
+  const int i = (tile % gx) * 256 + 4 * (threadIdx.x % 64);
+  const int j = (tile / gx) * 4 + threadIdx.x / 64;
+  F4 f[NPOP], a[7];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int jj = PULL ? clampi(j - cr(q), g.nr) : j;
+    int ii = PULL ? i - cz(q) : i;
+    ii = ii < 0 ? 0 : (ii > g.nz - 4 ? g.nz - 4 : ii);
+    const long long off = (long long)jj * g.nz + ii;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) f[9 * l + q] = *(const F4*)(pin + (9 * l + q) * g.plane + off);
+  }
+  const long long o = (long long)j * g.nz + i;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) a[c] = *(const F4*)(ain + c * g.plane + o);
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < NPOP; ++c) s += f[c].x + f[c].y + f[c].z + f[c].w;
+#pragma unroll
+  for (int c = 0; c < NPOP; ++c) {
+    F4 v = f[c];
+    v.x += 1e-7f * s; v.y += 1e-7f * s; v.z += 1e-7f * s; v.w += 1e-7f * s;
+    *(F4*)(pout + c * g.plane + o) = v;
+  }
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    F4 v = a[c];
+    v.x += 1e-7f * s; v.y += 1e-7f * s; v.z += 1e-7f * s; v.w += 1e-7f * s;
+    *(F4*)(aout + c * g.plane + o) = v;
+  }
+}
+
+template <int PULL>
+void measure_v(const char* name, int nz, int nr, int iters) {
+  Grid g;
+  g.nz = nz;
+  g.nr = nr;
+  g.plane = (long long)nz * nr + 64;
+  const double bytes = 272.0 * (double)nz * nr;
+  float *pin, *pout, *ain, *aout;
+  CK(hipMalloc(&pin, NPOP * g.plane * 4));
+  CK(hipMalloc(&pout, NPOP * g.plane * 4));
+  CK(hipMalloc(&ain, 7 * g.plane * 4));
+  CK(hipMalloc(&aout, 7 * g.plane * 4));
+  CK(hipMemset(pin, 0, NPOP * g.plane * 4));
+  CK(hipMemset(ain, 0, 7 * g.plane * 4));
+  const int tiles = (nz / 256) * (nr / 4);
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  for (int it = 0; it < 20; ++it) vec4_kernel<PULL><<<tiles, 256>>>(g, pin, pout, ain, aout);
+  CK(hipDeviceSynchronize());
+  CK(hipEventRecord(e0));
+  for (int it = 0; it < iters; ++it) vec4_kernel<PULL><<<tiles, 256>>>(g, pin, pout, ain, aout);
+  CK(hipEventRecord(e1));
+  CK(hipEventSynchronize(e1));
+  CK(hipGetLastError());
+  float ms;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  const double us = ms * 1e3 / iters;
+  printf("{\"workload\": \"%s %dx%d\", \"kernel\": \"4 sites per lane, pull %d\", \"us\": %.2f, \"frac_of_8TBps\": %.4f}\n",
+         name, nz, nr, PULL, us, bytes / us / 1e3 / 8000.0);
+  fflush(stdout);
+  CK(hipFree(pin));
+  CK(hipFree(pout));
+  CK(hipFree(ain));
+  CK(hipFree(aout));
+}
+
 // The realigned pull (SHIFT 3) against the full pull (SHIFT 2) on the same input, C2's grid: the
 // outputs must agree bit for bit.
 bool realigned_pull_matches() {
@@ -372,6 +526,21 @@ bool realigned_pull_matches() {
 
 int main(int argc, char** argv) {
   CK(hipSetDevice(0));
+  if (argc > 1 && std::strcmp(argv[1], "--layout") == 0) {
+    for (int rep = 0; rep < 2; ++rep) {
+      measure_s<2>("C2 FP32", 2048, 512, 400);
+      measure_c<1>("C2 FP32", 2048, 512, 400);
+      measure_c<0>("C2 FP32", 2048, 512, 400);
+      measure_v<1>("C2 FP32", 2048, 512, 400);
+      measure_v<0>("C2 FP32", 2048, 512, 400);
+      measure_s<2>("C3 FP32", 4096, 1024, 100);
+      measure_c<1>("C3 FP32", 4096, 1024, 100);
+      measure_c<0>("C3 FP32", 4096, 1024, 100);
+      measure_v<1>("C3 FP32", 4096, 1024, 100);
+      measure_v<0>("C3 FP32", 4096, 1024, 100);
+    }
+    return 0;
+  }
   if (argc > 1 && std::strcmp(argv[1], "--shift") == 0) {
     if (!realigned_pull_matches()) return 1;
     for (int rep = 0; rep < 2; ++rep) {
