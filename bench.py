@@ -319,7 +319,7 @@ def paper_grid_2mm() -> dict:
     """The paper's finest grid of Table 1 (preset P: 2400 x 400 cells of 0.25 um, 48,000 steps of
     c dt = dz/6 = 2 mm of propagation), FP32, at the three charges alpha = 0.678, 3.39, 6.78: time
     of the whole run (fluid and fields; HIP events on the library's stream), with the rigid driver
-    and with the paper's 2e5-macroparticle bunch, next to the time the paper gives for its fluid
+    and with the paper's 2e5-macroparticle bunch (bunch_streaming = 1), next to the time the paper gives for its fluid
     routine alone on the same grid and distance (one Intel Xeon E5-2695, Table 1).  Context only:
     another machine, and less work per step there.  The FP32 working set (about 2 x 110 MB) fits
     the 256 MB Infinity Cache, so this is not an HBM figure."""
@@ -340,9 +340,11 @@ def paper_grid_2mm() -> dict:
         lat.close()
         r = {"seconds": ev, "wall_s": wall, "MLUPS": cfg["nz"] * cfg["nr"] * n / ev / 1e6,
              "nonfinite": int(d["nonfinite"]), "n_min": nmin}
-        # the paper's driver: 2e5 macroparticles, gamma = 5000, 74 mm mrad (1.7 mrad), 0.01 % spread
+        # the paper's driver: 2e5 macroparticles, gamma = 5000, 74 mm mrad (1.7 mrad), 0.01 % spread;
+        # the step's traffic on this grid (261 MB) is about the MALL's size, so the push and move
+        # stream the bunch past the caches (bunch_streaming)
         npart = 200000
-        pcfg = dict(cfg, driver=wl.PARTICLES, max_particles=npart)
+        pcfg = dict(cfg, driver=wl.PARTICLES, max_particles=npart, bunch_streaming=1)
         lat = Lattice(pcfg)
         lat.set_bunch(wl.bunch(pcfg, npart, gamma=5000.0, emittance=1.7e-3 * 5000.0 * cfg["sigma_r"],
                                energy_spread=1e-4, seed=11))

@@ -43,6 +43,7 @@ class LbmConfig(ctypes.Structure):
         ("max_particles", c_int64),
         ("mrt_se", c_double), ("mrt_seps", c_double), ("mrt_sq", c_double), ("mrt_spi", c_double),
         ("resort_every", c_int32),
+        ("bunch_streaming", c_int32),
     ]
 
 

@@ -259,10 +259,22 @@ __device__ __forceinline__ void boris_push(const Physics& p, long long s, int sh
   pz = mz + (ux * sy - uy * sx) - 0.5 * dt * Ez;
 }
 
+// The bunch's coordinates: non-temporal (NT) accesses keep them out of the caches' way.
+template <bool NT>
+__device__ __forceinline__ double bunch_ld(const double* a) {
+  if constexpr (NT) return __builtin_nontemporal_load(a);
+  else return *a;
+}
+template <bool NT>
+__device__ __forceinline__ void bunch_st(double v, double* a) {
+  if constexpr (NT) __builtin_nontemporal_store(v, a);
+  else *a = v;
+}
+
 // Move to the next time level and deposit the midpoint current; PUSH: first the Boris push of the
 // step that has just run (s, shift, Ein, Eout as for bunch_push_kernel), then the move in the frame
-// s + shift of the next step.
-template <int ST, bool PUSH>
+// s + shift of the next step.  NT: non-temporal loads and stores of the coordinates.
+template <int ST, bool PUSH, bool NT>
 __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, int shift, const void* Einv,
                                                         const void* Eoutv, double* b, int n, long long cap,
                                                         void* jbv) {
@@ -280,9 +292,9 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
     // particle (a clamped one past the end) before any test, so the loads issue together
     const long long q = ((long long)blockIdx.x * PPT + u) * BT + threadIdx.x;
     const long long qc = q < n ? q : (long long)n - 1;
-    const double w = b[6 * cap + qc];
-    const double x = b[qc], y = b[cap + qc], z = b[2 * cap + qc];
-    double px = b[3 * cap + qc], py = b[4 * cap + qc], pz = b[5 * cap + qc];
+    const double w = bunch_ld<NT>(b + 6 * cap + qc);
+    const double x = bunch_ld<NT>(b + qc), y = bunch_ld<NT>(b + cap + qc), z = bunch_ld<NT>(b + 2 * cap + qc);
+    double px = bunch_ld<NT>(b + 3 * cap + qc), py = bunch_ld<NT>(b + 4 * cap + qc), pz = bunch_ld<NT>(b + 5 * cap + qc);
     live[u] = false;
     jz[u] = Stencil{};
     jr[u] = Stencil{};
@@ -291,9 +303,9 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
     if (q >= n || w == 0.0) continue;
     if (PUSH) {
       boris_push(p, s, shift, (const A*)Einv, (const A*)Eoutv, x, y, z, px, py, pz);
-      b[3 * cap + q] = px;
-      b[4 * cap + q] = py;
-      b[5 * cap + q] = pz;
+      bunch_st<NT>(px, b + 3 * cap + q);
+      bunch_st<NT>(py, b + 4 * cap + q);
+      bunch_st<NT>(pz, b + 5 * cap + q);
     }
     const long long sm = PUSH ? s + shift : s;   // frame of the move
     const double ig = 1.0 / sqrt(1.0 + (px * px + py * py + pz * pz));
@@ -309,9 +321,9 @@ __global__ __launch_bounds__(BT) void bunch_move_kernel(Physics p, long long s, 
       b[6 * cap + q] = 0.0;   // lost
       continue;
     }
-    b[q] = xn;
-    b[cap + q] = yn;
-    b[2 * cap + q] = zn;
+    bunch_st<NT>(xn, b + q);
+    bunch_st<NT>(yn, b + cap + q);
+    bunch_st<NT>(zn, b + 2 * cap + q);
     vz[u] = w * bz;
     vr[u] = w * (rm > 0.0 ? (xm * bx + ym * by) / rm : 0.0);
     live[u] = true;
@@ -644,9 +656,15 @@ hipError_t move_dispatch(int storage, const Physics& p, long long s, int shift, 
                          double* bunch, int n, long long cap, void* jb, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const dim3 grid((n + PPT * BT - 1) / (PPT * BT));
-  if (storage == 0) bunch_move_kernel<0, PUSH><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
-  else if (storage == 1) bunch_move_kernel<1, PUSH><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
-  else bunch_move_kernel<2, PUSH><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+  if (p.bunch_nt) {
+    if (storage == 0) bunch_move_kernel<0, PUSH, true><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+    else if (storage == 1) bunch_move_kernel<1, PUSH, true><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+    else bunch_move_kernel<2, PUSH, true><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+  } else {
+    if (storage == 0) bunch_move_kernel<0, PUSH, false><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+    else if (storage == 1) bunch_move_kernel<1, PUSH, false><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+    else bunch_move_kernel<2, PUSH, false><<<grid, BT, 0, st>>>(p, s, shift, Ein, Eout, bunch, n, cap, jb);
+  }
   return hipGetLastError();
 }
 

@@ -95,6 +95,8 @@ int validate(const lbm_config* c, Physics* p) {
     return fail(LBM_EINVAL, "max_particles must lie in [0, 2^31) (got %lld)", (long long)c->max_particles);
   if (c->driver == LBM_DRIVER_PARTICLES && c->resort_every < 0)
     return fail(LBM_EINVAL, "resort_every must be >= 0 (got %d)", c->resort_every);
+  if (c->driver == LBM_DRIVER_PARTICLES && c->bunch_streaming != 0 && c->bunch_streaming != 1)
+    return fail(LBM_EINVAL, "bunch_streaming must be 0 or 1 (got %d)", c->bunch_streaming);
   if (p) {
     Physics& q = *p;
     std::memset(&q, 0, sizeof q);
@@ -131,6 +133,7 @@ int validate(const lbm_config* c, Physics* p) {
     q.tau_plus = c->collision == LBM_TRT ? 0.5 + c->trt_magic / (c->tau - 0.5) : c->tau;
     q.driver = c->driver;
     q.cap = c->driver == LBM_DRIVER_PARTICLES ? (long long)c->max_particles : 0;
+    q.bunch_nt = c->driver == LBM_DRIVER_PARTICLES ? c->bunch_streaming : 0;
     q.mrt_se = c->mrt_se;
     q.mrt_seps = c->mrt_seps;
     q.mrt_sq = c->mrt_sq;

@@ -40,6 +40,7 @@ struct Physics {
   double tau_plus;          // TRT: relaxation time of the even part (tau otherwise)
   int driver;               // 0 rigid bi-Gaussian, 1 macroparticles
   long long cap;            // macroparticle capacity (driver 1)
+  int bunch_nt;             // driver 1: non-temporal bunch accesses in the push and move
   double mrt_se, mrt_seps, mrt_sq, mrt_spi;   // MRT rates of energy, energy square, heat flux, stress
 };
 

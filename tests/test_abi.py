@@ -82,6 +82,7 @@ def test_particle_workspace_growth(lib):
     dict(collision=3, mrt_sq=0.0), dict(collision=3, mrt_se=2.0), dict(collision=3, mrt_spi=float("nan")),
     dict(driver=2), dict(driver=1, max_particles=-1), dict(driver=1, max_particles=2 ** 31),
     dict(driver=1, max_particles=4, resort_every=-1),
+    dict(driver=1, max_particles=4, bunch_streaming=2),
     dict(nz=8192, nr=8193), dict(nz=64, nr=65536), dict(tau=float("nan")), dict(dz=-0.05, dr=-0.05),
 ])
 def test_invalid_configs_rejected(lib, bad):

@@ -46,7 +46,7 @@ CONFIG_FIELDS = (
     "n0", "ramp_kind", "ramp_start", "ramp_len",
     "nb", "sigma_z", "sigma_r", "zd0", "n_floor", "check_every", "fp64_math",
     "collision", "trt_magic", "driver", "max_particles",
-    "mrt_se", "mrt_seps", "mrt_sq", "mrt_spi", "resort_every",
+    "mrt_se", "mrt_seps", "mrt_sq", "mrt_spi", "resort_every", "bunch_streaming",
 )
 
 _BASE = dict(
@@ -55,7 +55,7 @@ _BASE = dict(
     n0=1.0, ramp_kind=0, ramp_start=0.0, ramp_len=1.0,
     nb=0.0, sigma_z=0.5, sigma_r=0.5, zd0=0.0, n_floor=1e-10, check_every=0, fp64_math=0,
     collision=0, trt_magic=0.25, driver=0, max_particles=0,
-    mrt_se=1.0, mrt_seps=1.0, mrt_sq=1.0, mrt_spi=1.0, resort_every=0,
+    mrt_se=1.0, mrt_seps=1.0, mrt_sq=1.0, mrt_spi=1.0, resort_every=0, bunch_streaming=0,
     # workload-level fields (not part of the C struct)
     noise_amp=0.0, seed=0, nsteps=1, z_behind=4.0,
 )
