@@ -29,6 +29,11 @@
 // population plane stored shifted by its z velocity).  The realigned outputs are first checked
 // against the full pull's bit for bit.
 //
+// With --pingpong the FP32 pattern runs as the step does, alternating between two buffer sets so
+// that each launch reads what the previous one wrote (the other measurements read one input set
+// every launch, which the MALL can keep), on C2, on a grid of the paper's size (2432 x 400, the
+// paper's 2400 columns rounded up to the tile) and on C3.
+//
 // With --layout the FP32 pattern (full pull) is measured beside two other arrangements of the same
 // 272 B per site, each with and without the pull's offsets: a chunked layout (the 3 lattices of a
 // direction in one plane as [row][64-column chunk][lattice][64], the 7 auxiliary words in one plane
@@ -480,6 +485,52 @@ void measure_v(const char* name, int nz, int nr, int iters) {
   CK(hipFree(aout));
 }
 
+// The FP32 pattern as the step runs it: two buffer sets, each launch reading the set the previous
+// one wrote (the other measurements read the same input every launch).
+void measure_pp(const char* name, int nz, int nr, int iters) {
+  Grid g;
+  g.nz = nz;
+  g.nr = nr;
+  g.plane = (long long)nz * nr + 64;
+  const double bytes = 272.0 * (double)nz * nr;
+  float *p0, *p1, *a0, *a1;
+  CK(hipMalloc(&p0, NPOP * g.plane * 4));
+  CK(hipMalloc(&p1, NPOP * g.plane * 4));
+  CK(hipMalloc(&a0, 7 * g.plane * 4));
+  CK(hipMalloc(&a1, 7 * g.plane * 4));
+  CK(hipMemset(p0, 0, NPOP * g.plane * 4));
+  CK(hipMemset(p1, 0, NPOP * g.plane * 4));
+  CK(hipMemset(a0, 0, 7 * g.plane * 4));
+  CK(hipMemset(a1, 0, 7 * g.plane * 4));
+  const int tiles = (nz / TZ) * (nr / TR);
+  auto launch = [&](int it) {
+    if (it & 1) pattern_kernel<float, float, 7, true, 0, 2><<<tiles, TZ * TR>>>(g, p1, p0, a1, a0);
+    else pattern_kernel<float, float, 7, true, 0, 2><<<tiles, TZ * TR>>>(g, p0, p1, a0, a1);
+  };
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  for (int it = 0; it < 20; ++it) launch(it);
+  CK(hipDeviceSynchronize());
+  CK(hipEventRecord(e0));
+  for (int it = 0; it < iters; ++it) launch(it);
+  CK(hipEventRecord(e1));
+  CK(hipEventSynchronize(e1));
+  CK(hipGetLastError());
+  float ms;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  const double us = ms * 1e3 / iters;
+  printf("{\"workload\": \"%s %dx%d\", \"kernel\": \"step access pattern, ping-pong buffers\", \"us\": %.2f, "
+         "\"frac_of_8TBps\": %.4f}\n", name, nz, nr, us, bytes / us / 1e3 / 8000.0);
+  fflush(stdout);
+  CK(hipEventDestroy(e0));
+  CK(hipEventDestroy(e1));
+  CK(hipFree(p0));
+  CK(hipFree(p1));
+  CK(hipFree(a0));
+  CK(hipFree(a1));
+}
+
 // The realigned pull (SHIFT 3) against the full pull (SHIFT 2) on the same input, C2's grid: the
 // outputs must agree bit for bit.
 bool realigned_pull_matches() {
@@ -526,6 +577,14 @@ bool realigned_pull_matches() {
 
 int main(int argc, char** argv) {
   CK(hipSetDevice(0));
+  if (argc > 1 && std::strcmp(argv[1], "--pingpong") == 0) {
+    for (int rep = 0; rep < 3; ++rep) {
+      measure_pp("C2 FP32", 2048, 512, 400);
+      measure_pp("P-size FP32", 2432, 400, 400);
+      measure_pp("C3 FP32", 4096, 1024, 100);
+    }
+    return 0;
+  }
   if (argc > 1 && std::strcmp(argv[1], "--layout") == 0) {
     for (int rep = 0; rep < 2; ++rep) {
       measure_s<2>("C2 FP32", 2048, 512, 400);
