@@ -142,9 +142,9 @@ enum { LBM_DRIVER_RIGID = 0, LBM_DRIVER_PARTICLES = 1 };
  *                 LBM_DRIVER_PARTICLES: 1 = the push and move read and write the bunch with
  *                 non-temporal accesses, which leave the GPU's caches to the step's own data.
  *                 That pays on a grid whose step traffic is about the size of the last-level
- *                 cache (256 MB): 2400 x 400 in FP32 (261 MB per step) goes from 68.7 to 62.6 us
+ *                 cache (256 MB): 2400 x 400 in FP32 (261 MB per step) goes from 68.7 to 62.8 us
  *                 per step with 200,000 particles; on a larger one it costs, since the bunch then
- *                 comes from HBM (2048 x 512: 70.7 against 73.3 us).  0 = cached accesses.  Only 0
+ *                 comes from HBM (2048 x 512: 70.6 against 73.2 us).  0 = cached accesses.  Only 0
  *                 and 1 are accepted.  Results are the same either way.  Ignored otherwise. */
 typedef struct {
   int32_t nz, nr;
