@@ -327,7 +327,8 @@ def paper_grid_2mm() -> dict:
     res = {"workload": "P: 2400x400, dz=dr=0.0047/k_p (0.25 um at 1e16 cm^-3), c dt/dz=1/6, "
                        "48000 steps (2 mm), FP32, uniform plasma, moving window, rigid driver "
                        "sigma_z=0.333 sigma_r=0.1675",
-           "paper_fluid_routine_s": 28.88e3, "paper_hardware": "Intel Xeon E5-2695 @ 2.40 GHz"}
+           "paper_fluid_routine_s": 28.88e3, "paper_hardware": "Intel Xeon E5-2695 @ 2.40 GHz",
+           "particle_driver": "2e5 macroparticles, gamma 5000, 1.7 mrad, 0.01 % spread, bunch_streaming=1"}
     import torch
 
     from paper_2201_05473_amd import Lattice
