@@ -213,21 +213,22 @@ def test_checkpoint_resumes_particle_run():
         x.close()
 
 
-@pytest.mark.parametrize("resort,m64", [(0, 0), (3, 0), (3, 1)])
-def test_fp32_particle_run(resort, m64):
+@pytest.mark.parametrize("resort,m64,nt", [(0, 0, 0), (3, 0, 0), (3, 1, 0), (3, 0, 1)])
+def test_fp32_particle_run(resort, m64, nt):
     """FP32 storage with the particle driver over 60 steps of the deflected slow bunch (losses
     included), with the default re-sort interval and with a re-sort every 3 steps, in FP32 and in
-    FP64 arithmetic (fp64_math): the FP32 tile deposit (shares summed within runs of lanes in
-    FP32) and the J_b bound against the FP64 oracle.  Moments and fields within 1e-5 of their
-    group's scale, particle coordinates within 1e-6 of theirs, and the same particles lost."""
+    FP64 arithmetic (fp64_math), and with non-temporal bunch accesses (bunch_streaming): the FP32
+    tile deposit (shares summed within runs of lanes in FP32) and the J_b bound against the FP64
+    oracle.  Moments and fields within 1e-5 of their group's scale, particle coordinates within
+    1e-6 of theirs, and the same particles lost."""
     c = CASES["slow_deflected"]
     cfg = wl.config(None, nz=130, nr=21, dz=0.05, dr=0.05, nb=0.4, sigma_z=0.35, sigma_r=0.25, zd0=4.0,
                     driver=wl.PARTICLES, max_particles=6000, storage=wl.F32, noise_amp=1e-3, seed=4,
-                    tau=0.7, resort_every=resort, fp64_math=m64, **c["cfg"])
+                    tau=0.7, resort_every=resort, fp64_math=m64, bunch_streaming=nt, **c["cfg"])
     b = wl.bunch(cfg, 5000, gamma=c["gamma"], emittance=c["emittance"], energy_spread=c["spread"], seed=8)
     pert = wl.density_perturbation(cfg)
     S, P = O.run(dict(cfg, storage=wl.F64, fp64_math=0), 60, pert, bunch=b)
-    print(f"[bunch fp32] resort_every={resort} fp64_math={m64}", flush=True)
+    print(f"[bunch fp32] resort_every={resort} fp64_math={m64} bunch_streaming={nt}", flush=True)
     lat = lattice(cfg, b, pert)
     lat.step(60)
     st, k, s = lat.state()
